@@ -1,0 +1,100 @@
+"""Test-side helpers: canonical cycle form, an independent brute-force
+enumerator, and small graph utilities.  Neither the oracle nor the HIP path
+imports this module."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def adjacency_sets(n, row_ptr, col_idx):
+    return [set(int(w) for w in col_idx[row_ptr[v]:row_ptr[v + 1]]) for v in range(n)]
+
+
+def canonical(cycle) -> tuple:
+    """Rotate a cycle (vertex sequence, first vertex not repeated) so that it
+    starts at its minimum vertex id and continues towards the smaller of that
+    vertex's two cycle neighbours."""
+    c = [int(x) for x in cycle]
+    k = len(c)
+    i = c.index(min(c))
+    fwd, bwd = c[(i + 1) % k], c[(i - 1) % k]
+    if fwd <= bwd:
+        return tuple(c[(i + j) % k] for j in range(k))
+    return tuple(c[(i - j) % k] for j in range(k))
+
+
+def canonical_sorted(cycles) -> list:
+    return sorted((canonical(c) for c in cycles), key=lambda t: (len(t), t))
+
+
+def is_chordless_cycle(cycle, adj) -> bool:
+    """Checks the definition directly: consecutive vertices adjacent
+    (cyclically), all distinct, and no other pair adjacent."""
+    c = [int(x) for x in cycle]
+    k = len(c)
+    if k < 3 or len(set(c)) != k:
+        return False
+    for i in range(k):
+        for j in range(i + 1, k):
+            consecutive = (j == i + 1) or (i == 0 and j == k - 1)
+            if (c[j] in adj[c[i]]) != consecutive:
+                return False
+    return True
+
+
+def brute_force_sets(n, row_ptr, col_idx):
+    """All vertex sets S (|S| >= 3) whose induced subgraph is connected and
+    2-regular, i.e. all chordless cycles as frozensets.  Exhaustive over the
+    2^n subsets; intended for n <= 16."""
+    assert n <= 20
+    adj = np.zeros(n, dtype=np.uint32)
+    for v in range(n):
+        for w in col_idx[row_ptr[v]:row_ptr[v + 1]]:
+            adj[v] |= np.uint32(1) << np.uint32(w)
+    if n == 0:
+        return []
+    S = np.arange(1 << n, dtype=np.uint32)
+    ok = np.bitwise_count(S) >= 3
+    for v in range(n):
+        inS = (S >> np.uint32(v)) & np.uint32(1)
+        d = np.bitwise_count(S & adj[v])
+        ok &= (inS == 0) | (d == 2)
+    out = []
+    for s in np.nonzero(ok)[0]:
+        s = int(s)
+        # connectivity of G[S] by flood fill
+        start = (s & -s).bit_length() - 1
+        seen = 1 << start
+        frontier = seen
+        while frontier:
+            nxt = 0
+            f = frontier
+            while f:
+                v = (f & -f).bit_length() - 1
+                f &= f - 1
+                nxt |= int(adj[v]) & s
+            nxt &= ~seen
+            seen |= nxt
+            frontier = nxt
+        if seen == s:
+            out.append(frozenset(v for v in range(n) if s >> v & 1))
+    return out
+
+
+def hist_of_sets(sets, n):
+    h = np.zeros(n + 1, np.int64)
+    for s in sets:
+        h[len(s)] += 1
+    return h
+
+
+def dense_adjacency(n, row_ptr, col_idx):
+    A = np.zeros((n, n), dtype=np.int64)
+    for v in range(n):
+        A[v, col_idx[row_ptr[v]:row_ptr[v + 1]]] = 1
+    return A
+
+
+def triangles_by_trace(n, row_ptr, col_idx) -> int:
+    A = dense_adjacency(n, row_ptr, col_idx)
+    return int(np.trace(A @ A @ A) // 6)

@@ -1,0 +1,312 @@
+"""Pins for the CPU oracle.  Nothing here recomputes the oracle's own
+formulas: each check comes from the definition of a chordless cycle, from a
+closed form, from a value the paper prints, or from brute force."""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from ccutil import (adjacency_sets, brute_force_sets, canonical, hist_of_sets,
+                    is_chordless_cycle, triangles_by_trace)
+from paper_1410_4876_amd import graphgen as gg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def run(g, cycles=True):
+    return oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=cycles)
+
+
+def oracle_sets(res):
+    return [frozenset(int(v) for v in c) for c in oracle.cycle_list(res)]
+
+
+def check_against_brute(g):
+    res = run(g)
+    got = oracle_sets(res)
+    assert len(got) == len(set(got)), "oracle emitted a cycle twice"
+    want = brute_force_sets(g.n, g.row_ptr, g.col_idx)
+    assert set(got) == set(want), g.name
+    assert np.array_equal(res.hist, hist_of_sets(want, g.n))
+    adj = adjacency_sets(g.n, g.row_ptr, g.col_idx)
+    for c in oracle.cycle_list(res):
+        assert is_chordless_cycle(c, adj)
+    return res
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5])
+def test_exhaustive_small(n):
+    """Every labelled graph on n <= 5 vertices."""
+    pairs = n * (n - 1) // 2
+    for bits in range(1 << pairs):
+        check_against_brute(gg.from_adjacency_bits(n, bits))
+
+
+def test_exhaustive_n6_sample():
+    """A deterministic third of the 32768 labelled graphs on 6 vertices."""
+    for bits in range(0, 1 << 15, 3):
+        check_against_brute(gg.from_adjacency_bits(6, bits))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_er_vs_brute(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(7, 15))
+    m = int(rng.integers(n - 1, min(3 * n, n * (n - 1) // 2) + 1))
+    check_against_brute(gg.er_gnm(n, m, rng))
+
+
+@pytest.mark.parametrize("p,q", [(2, 5), (3, 3), (3, 4), (3, 5), (2, 7), (4, 4)])
+def test_grids_vs_brute(p, q):
+    rng = np.random.default_rng(p * 31 + q)
+    check_against_brute(gg.permute_random(gg.grid(p, q), rng))
+
+
+def test_hypercube_and_misc_vs_brute():
+    for g in [gg.hypercube(3), gg.hypercube(4), gg.wheel(7), gg.complete_multipartite(2, 3, 3),
+              gg.cone(gg.cycle(8)), gg.disjoint_union(gg.cycle(5), gg.complete(4), gg.grid(2, 3))]:
+        check_against_brute(g)
+
+
+# --------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [3, 4, 5, 17, 64, 100, 200])
+def test_cycle_graph(n):
+    r = run(gg.permute_random(gg.cycle(n), np.random.default_rng(n)))
+    assert r.count == 1 and r.hist[n] == 1
+
+
+@pytest.mark.parametrize("n", [3, 4, 7, 12, 20])
+def test_complete_graph(n):
+    r = run(gg.complete(n), cycles=False)
+    assert r.hist[3] == math.comb(n, 3) and r.count == math.comb(n, 3)
+
+
+@pytest.mark.parametrize("a,b", [(2, 2), (2, 5), (3, 4), (8, 8), (11, 7)])
+def test_complete_bipartite(a, b):
+    r = run(gg.complete_bipartite(a, b), cycles=False)
+    assert r.hist[4] == math.comb(a, 2) * math.comb(b, 2) and r.count == r.hist[4]
+
+
+@pytest.mark.parametrize("a,b,c", [(1, 1, 1), (2, 2, 2), (2, 3, 4), (5, 1, 3)])
+def test_complete_tripartite(a, b, c):
+    # Triangles take one vertex per part; a chordless 4-cycle alternates
+    # between two parts; no longer chordless cycle exists (the complement is
+    # a union of cliques).
+    r = run(gg.complete_multipartite(a, b, c), cycles=False)
+    sq = math.comb(a, 2) * math.comb(b, 2) + math.comb(a, 2) * math.comb(c, 2) + \
+        math.comb(b, 2) * math.comb(c, 2)
+    h = np.append(r.hist, [0, 0])
+    assert h[3] == a * b * c and h[4] == sq and r.count == a * b * c + sq
+
+
+@pytest.mark.parametrize("rim", [4, 5, 9, 30, 100])
+def test_wheel(rim):
+    r = run(gg.permute_random(gg.wheel(rim), np.random.default_rng(rim)), cycles=False)
+    assert r.hist[3] == rim and r.hist[rim] == 1 and r.count == rim + 1
+
+
+@pytest.mark.parametrize("q", [2, 3, 8, 30])
+def test_ladder(q):
+    r = run(gg.ladder(q), cycles=False)
+    assert r.hist[4] == q - 1 and r.count == q - 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_trees_have_no_cycles_and_no_triplets(seed):
+    rng = np.random.default_rng(seed)
+    g = gg.random_tree(int(rng.integers(1, 90)), rng)
+    r = run(g, cycles=False)
+    assert r.count == 0
+    assert r.front[3] == 0  # T(G) is empty for a tree (Section 2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_unicyclic_has_one_triplet(seed):
+    # A tree plus one edge closing a cycle of length >= 4: |T(G)| = 1 for
+    # any degree labelling (Section 2).
+    rng = np.random.default_rng(100 + seed)
+    k = int(rng.integers(4, 12))
+    extra = int(rng.integers(0, 30))
+    e = [(i, (i + 1) % k) for i in range(k)]
+    for v in range(k, k + extra):
+        e.append((int(rng.integers(0, v)), v))
+    g = gg.permute_random(gg.csr_from_edges(k + extra, e), rng)
+    r = run(g, cycles=False)
+    assert r.front[3] == 1 and r.count == 1 and r.hist[k] == 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_chordal_graphs_have_only_triangles(seed):
+    rng = np.random.default_rng(200 + seed)
+    g = gg.permute_random(gg.random_k_tree(int(rng.integers(6, 40)), int(rng.integers(1, 5)), rng), rng)
+    r = run(g, cycles=False)
+    assert r.count == r.hist[3] == triangles_by_trace(g.n, g.row_ptr, g.col_idx)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_cone_adds_m_triangles(seed):
+    rng = np.random.default_rng(300 + seed)
+    g = gg.er_gnm(30, 60, rng)
+    base = run(g, cycles=False)
+    c = run(gg.cone(g), cycles=False)
+    want = base.hist.copy()
+    want = np.append(want, 0)
+    want[3] += g.m
+    assert np.array_equal(c.hist, want)
+
+
+def test_disjoint_union_adds_histograms():
+    rng = np.random.default_rng(7)
+    parts = [gg.er_gnm(20, 40, rng), gg.grid(4, 5), gg.wheel(6)]
+    u = run(gg.disjoint_union(*parts), cycles=False)
+    want = np.zeros(u.hist.shape[0], np.int64)
+    for p in parts:
+        h = run(p, cycles=False).hist
+        want[:h.shape[0]] += h
+    assert np.array_equal(u.hist, want)
+
+
+# ------------------------------------------------- values printed in Table 1
+def _table1_rows():
+    with open(os.path.join(GOLDEN, "table1.json")) as f:
+        return json.load(f)["rows"]
+
+
+def _build(row):
+    return getattr(gg, row["family"])(*row["args"])
+
+
+@pytest.mark.parametrize("row", [r for r in _table1_rows() if r["clc"] <= 60000],
+                         ids=lambda r: r["name"])
+def test_table1_small(row):
+    g = _build(row)
+    assert (g.n, g.m, g.max_degree) == (row["n"], row["m"], row["delta"])
+    r = run(g, cycles=False)
+    assert r.hist[3] == row["c3"]
+    assert r.count - r.hist[3] == row["clc"]
+
+
+@pytest.mark.parametrize("name", ["K_{50,50}", "Grid 6x10", "Grid 7x10"])
+def test_table1_large(name):
+    row = next(r for r in _table1_rows() if r["name"] == name)
+    g = _build(row)
+    assert (g.n, g.m, g.max_degree) == (row["n"], row["m"], row["delta"])
+    hist, _ = oracle.histogram_parallel(g.n, g.row_ptr, g.col_idx, procs=8)
+    assert hist[3] == row["c3"] and hist.sum() - hist[3] == row["clc"]
+
+
+@pytest.mark.skipif(os.environ.get("CC_SLOW") != "1", reason="about 2 min on 8 cores; CC_SLOW=1")
+def test_table1_grid_8x10():
+    row = next(r for r in _table1_rows() if r["name"] == "Grid 8x10")
+    g = _build(row)
+    hist, _ = oracle.histogram_parallel(g.n, g.row_ptr, g.col_idx, procs=8)
+    assert hist.sum() == row["clc"]
+
+
+def test_grid_transpose_symmetry():
+    for p, q in [(3, 7), (4, 6), (5, 7)]:
+        a = run(gg.grid(p, q), cycles=False).hist
+        b = run(gg.permute_random(gg.grid(q, p), np.random.default_rng(p + q)), cycles=False).hist
+        assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------- labelling, triplets
+def _check_degree_labelling(g, lab):
+    """l is a degree labelling iff each vertex, when removed in label order,
+    has minimum degree among the vertices not yet removed (Section 2).  The
+    tie rule (smallest id) is checked too."""
+    n = g.n
+    assert sorted(lab.tolist()) == list(range(n))
+    order = np.argsort(lab)
+    adj = adjacency_sets(n, g.row_ptr, g.col_idx)
+    alive = set(range(n))
+    for u in order:
+        u = int(u)
+        degs = {v: len(adj[v] & alive) for v in alive}
+        dmin = min(degs.values())
+        assert degs[u] == dmin
+        assert u == min(v for v in alive if degs[v] == dmin)
+        alive.remove(u)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_degree_labelling_definition(seed):
+    rng = np.random.default_rng(400 + seed)
+    n = int(rng.integers(1, 60))
+    g = gg.er_gnm(n, int(rng.integers(0, min(n * (n - 1) // 2, 3 * n) + 1)), rng)
+    _check_degree_labelling(g, oracle.degree_labelling(g.n, g.row_ptr, g.col_idx))
+    r = run(g, cycles=False)
+    assert np.array_equal(r.labels, oracle.degree_labelling(g.n, g.row_ptr, g.col_idx))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_triplet_counts(seed):
+    # Stage one splits the pairs of higher-labelled neighbours of every u
+    # into triangles and initial triplets; |T(G)| <= (Delta - 1) m / 2.
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(5, 60))
+    g = gg.er_gnm(n, int(rng.integers(n, min(n * (n - 1) // 2, 4 * n) + 1)), rng)
+    r = run(g, cycles=False)
+    lab = r.labels
+    adj = adjacency_sets(g.n, g.row_ptr, g.col_idx)
+    pairs = sum(math.comb(sum(1 for w in adj[u] if lab[w] > lab[u]), 2) for u in range(g.n))
+    assert r.front[3] + r.hist[3] == pairs
+    assert r.hist[3] == triangles_by_trace(g.n, g.row_ptr, g.col_idx)
+    assert 2 * r.front[3] <= (g.max_degree - 1) * g.m
+    assert oracle.count_roots(g.n, g.row_ptr, g.col_idx) == pairs
+
+
+# ------------------------------------------------------------- invariances
+@pytest.mark.parametrize("seed", range(5))
+def test_permutation_equivariance(seed):
+    rng = np.random.default_rng(600 + seed)
+    g = gg.er_gnm(24, 50, rng)
+    perm = rng.permutation(g.n)
+    a = {canonical(perm[c]) for c in oracle.cycle_list(run(g))}
+    b = {canonical(c) for c in oracle.cycle_list(run(gg.permute(g, perm)))}
+    assert a == b
+
+
+def test_root_ranges_partition_the_result():
+    g = gg.workload_er40()
+    full = run(g, cycles=False)
+    roots = oracle.count_roots(g.n, g.row_ptr, g.col_idx)
+    h = np.zeros_like(full.hist)
+    f = np.zeros_like(full.front)
+    for lo in range(0, roots, 7):
+        r = oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=False,
+                                    root_lo=lo, root_hi=min(lo + 7, roots))
+        h += r.hist
+        f += r.front
+    assert np.array_equal(h, full.hist) and np.array_equal(f, full.front)
+
+
+def test_rejects_non_simple():
+    ok = gg.cycle(5)
+    assert oracle.validate(ok.n, ok.row_ptr, ok.col_idx) == 0
+    # self-loop
+    assert oracle.validate(2, np.array([0, 2, 3]), np.array([0, 1, 0])) == oracle.ERR_NOT_SIMPLE
+    # duplicate neighbour
+    assert oracle.validate(2, np.array([0, 2, 4]), np.array([1, 1, 0, 0])) == oracle.ERR_NOT_SIMPLE
+    # asymmetric
+    assert oracle.validate(3, np.array([0, 1, 2, 2]), np.array([1, 2])) == oracle.ERR_NOT_SIMPLE
+    # out of range
+    assert oracle.validate(2, np.array([0, 1, 2]), np.array([5, 0])) == oracle.ERR_NOT_SIMPLE
+    with pytest.raises(ValueError):
+        oracle.enumerate_cycles(2, np.array([0, 2, 3]), np.array([0, 1, 0]))
+
+
+def test_workload_generators_shapes():
+    g1, g2, g3 = gg.workload_er40(), gg.workload_grid8x8(), gg.workload_grid7x12()
+    assert (g1.n, g1.m) == (40, 100)
+    assert (g2.n, g2.m, g2.max_degree) == (64, 112, 4)
+    assert (g3.n, g3.m, g3.max_degree) == (84, 149, 4)
+    # a permuted grid keeps the grid's histogram
+    a = run(gg.grid(5, 7), cycles=False).hist
+    b = run(gg.permute_random(gg.grid(5, 7), gg.rng_for(9)), cycles=False).hist
+    assert np.array_equal(a, b)
