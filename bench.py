@@ -1,0 +1,125 @@
+#!/usr/bin/env python3
+"""Benchmark: chordless cycles/s on one MI355X.
+
+Workload: the 8x8 grid (n=64, m=112, ids permuted with seed 14104876+2),
+full enumeration of every chordless cycle as int32 vertex lists into
+device buffers.  One step = one whole pass of the path on the resident CSR:
+ingest + validation + degree labelling (cc_prepare), stage one, the level
+loop and the output (cc_enumerate), and the handle release.
+
+Prints one JSON line with the throughput, the roofline of the dominant
+kernel (the breadth-first level kernel, timed with HIP events on the stream
+it runs on), and the CPU oracle timed on this host as a baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+
+
+def cpu_baseline(g, budget_s=30.0):
+    """The oracle (single thread, one counting+storing pass) on the same
+    graph.  The 8x8 grid takes about 15 s, inside the bounded budget."""
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.enumerate_single_pass(g.n, g.row_ptr, g.col_idx, verts_cap=64 << 20,
+                                     cyc_cap=4 << 20)
+    dt = time.perf_counter() - t0
+    return {"value": round(r.n_cycles / dt, 1), "unit": "chordless cycles/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"whole workload, one pass storing all cycles ({r.n_cycles} cycles, "
+                      f"{dt:.1f} s, single thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time steps without per-kernel HIP events (no roofline)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the path shards by triplet "
+                                   "or by graph across GPUs, which is not built here",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1410_4876_amd import cc
+    from paper_1410_4876_amd import graphgen as gg
+
+    torch.cuda.set_device(0)
+    g = gg.workload_grid8x8()
+    rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    profile = not args.no_profile
+
+    # exact output sizes (outside the timed region)
+    with cc.Graph(g.n, rp, ci, stream=stream) as h0:
+        hist = h0.histogram()
+    n_cycles = int(hist.sum())
+    n_verts = int((hist * np.arange(hist.size)).sum())
+    verts = torch.empty(n_verts, dtype=torch.int32, device="cuda")
+    offs = torch.empty(n_cycles + 1, dtype=torch.int64, device="cuda")
+
+    def step():
+        with cc.Graph(g.n, rp, ci, stream=stream, profile=profile) as h:
+            nc, nv = h.enumerate_into(verts, offs)
+            assert nc == n_cycles and nv == n_verts
+            return h.last_run()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+
+    out = {
+        "metric": "chordless cycles/s on 1 MI355X",
+        "value": round(n_cycles * args.steps / elapsed, 1),
+        "unit": "chordless cycles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "grid 8x8 (n=64, m=112), ids permuted, full enumeration to "
+                               "int32 vertex lists", "cycles": n_cycles, "vertices_out": n_verts,
+                   "paths_expanded": int(infos[-1]["paths"]), "parallelism": "single GPU"},
+        "paths_per_s": round(infos[-1]["paths"] * args.steps / elapsed, 1),
+        "gpu_ms_per_step": round(sum(i["gpu_ms"] for i in infos) / len(infos), 4),
+    }
+    if profile:
+        lvl_ms = sum(i["level_ms"] for i in infos)
+        lvl_bytes = sum(i["level_bytes"] for i in infos)
+        launches = sum(i["levels_launched"] for i in infos)
+        achieved = lvl_bytes / (lvl_ms * 1e-3) / 1e9 if lvl_ms > 0 else 0.0
+        out["roofline"] = {"bound": "hbm", "kernel": "k_level (breadth-first level, enumerate)",
+                           "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                           "bytes_per_launch": round(lvl_bytes / max(launches, 1), 1),
+                           "avg_launch_us": round(lvl_ms * 1e3 / max(launches, 1), 3)}
+        out["breakdown_ms"] = {
+            "stage1": round(sum(i["stage1_ms"] for i in infos) / len(infos), 4),
+            "levels": round(lvl_ms / len(infos), 4),
+            "dfs": round(sum(i["dfs_ms"] for i in infos) / len(infos), 4)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

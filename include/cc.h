@@ -1,0 +1,157 @@
+/*
+ * cc.h -- C ABI of libcc: enumeration of all chordless cycles of a finite
+ * undirected simple graph on an MI355X (gfx950) GPU.
+ *
+ * A chordless cycle is an induced subgraph that is a cycle (Section 1 of
+ * Jradi et al., "A GPU-based parallel algorithm for enumerating all
+ * chordless cycles in graphs").  The library finds every such cycle exactly
+ * once with the paper's method: a degree labelling of the vertices
+ * (Section 2), the initial triplets and the triangles (Section 4.3,
+ * Algorithm 2), then one-vertex extension of every open chordless path with
+ * a chord test (Section 4.4, Algorithm 3), level by level (Algorithm 4).
+ * When a level's frontier would exceed the caller's memory budget the
+ * remaining work continues depth-first on per-wavefront stacks.
+ *
+ * Conventions for every entry point:
+ *  - Graphs are int32 CSR: row_ptr[n+1] (row_ptr[0] = 0, non-decreasing),
+ *    col_idx[row_ptr[n]]; each undirected edge appears in both lists.  Lists
+ *    need not be sorted.  The graph must be simple: no self-loop, no
+ *    repeated neighbour, symmetric, ids in [0, n).  1 <= n <= CC_MAX_VERTICES
+ *    (n = 0 is accepted and has no cycles).
+ *  - The "length" of a cycle is its number of vertices k (3 <= k <= n).
+ *  - Cycles are reported in canonical form: starting at the vertex with the
+ *    smallest original id, continuing towards the smaller of that vertex's
+ *    two cycle neighbours.  Enumeration output is ordered by length; the
+ *    order among cycles of equal length is unspecified.
+ *  - Pointers are host pointers unless a CC_*_DEVICE flag says otherwise.
+ *    Device pointers must be device-accessible memory of the current HIP
+ *    device.  All GPU work is ordered on cc_options.stream; every call
+ *    returns only after its results are complete (the call synchronises
+ *    that stream).
+ *  - The caller owns every buffer it passes; the library owns a handle from
+ *    the call that creates it until the matching release call.  A handle
+ *    must not be used from two threads at once; separate handles may run
+ *    concurrently on separate streams.
+ *  - Errors are returned as cc_status; outputs are unspecified after an
+ *    error unless stated otherwise.
+ */
+#ifndef CC_H
+#define CC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CC_MAX_VERTICES 128
+#define CC_ABI_VERSION 1
+
+typedef enum cc_status {
+  CC_OK = 0,
+  CC_ERR_INVALID_ARG = -1,      /* null pointer, negative size, bad flags     */
+  CC_ERR_NOT_SIMPLE = -2,       /* self-loop, repeated or one-way edge, bad id */
+  CC_ERR_TOO_LARGE = -3,        /* n > CC_MAX_VERTICES                         */
+  CC_ERR_BUFFER_TOO_SMALL = -4, /* output buffer too small; sizes reported     */
+  CC_ERR_OUT_OF_MEMORY = -5,    /* device allocation failed / budget too small */
+  CC_ERR_DEVICE = -6,           /* HIP runtime error or device-side failure    */
+  CC_ERR_NO_DEVICE = -7         /* no usable gfx950 device                     */
+} cc_status;
+
+/* cc_options.flags */
+#define CC_INPUT_DEVICE  (1u << 0) /* row_ptr/col_idx (and batch offsets) are device pointers */
+#define CC_OUTPUT_DEVICE (1u << 1) /* cc_enumerate's verts/offsets are device pointers        */
+#define CC_FORCE_DFS     (1u << 2) /* take the depth-first path from level dfs_level on      */
+#define CC_PROFILE       (1u << 3) /* time each kernel of a run with HIP events (cc_run_info) */
+
+typedef struct cc_options {
+  void *stream;                  /* hipStream_t; NULL = the null stream                 */
+  int64_t frontier_budget_bytes; /* device memory for open paths; 0 = 4 GiB             */
+  uint32_t flags;                /* CC_* flags above                                     */
+  int32_t dfs_level;             /* with CC_FORCE_DFS: path length t >= 3 whose frontier
+                                    is handed to the depth-first kernel                  */
+  int32_t dfs_waves_per_cu;      /* depth-first kernel occupancy; 0 = default            */
+  int32_t bfs_blocks;            /* grid of the level kernel; 0 = default                */
+} cc_options;
+
+typedef struct cc_graph cc_graph;
+
+/* Statistics of the most recent count/histogram/enumerate call on a handle. */
+typedef struct cc_run_info {
+  int64_t cycles;            /* total chordless cycles                               */
+  int64_t paths;             /* open chordless paths expanded (sum over lengths)     */
+  int64_t peak_frontier;     /* largest level frontier held in breadth-first mode     */
+  int32_t switch_level;      /* path length handed to the depth-first kernel, 0=none */
+  int32_t levels_launched;   /* breadth-first level kernels launched                 */
+  double gpu_ms;             /* device time of the call, HIP events around its work  */
+  /* With CC_PROFILE only (else 0): device time of each part of the run.       */
+  double stage1_ms;          /* initial triplets and triangles                       */
+  double level_ms;           /* all breadth-first level kernels                      */
+  double dfs_ms;             /* depth-first kernels and their preparation            */
+  int64_t level_bytes;       /* frontier and output bytes the level kernels must move */
+} cc_run_info;
+
+/*
+ * cc_prepare -- validate a graph and compute its degree labelling
+ * (Section 2: repeatedly remove a vertex of minimum remaining degree; the
+ * i-th removed vertex gets label i, 0-based; ties go to the smallest id).
+ *   n        number of vertices, 0 <= n <= CC_MAX_VERTICES
+ *   row_ptr  n+1 offsets; col_idx row_ptr[n] neighbour ids (host, or device
+ *            with CC_INPUT_DEVICE).  With CC_INPUT_DEVICE, col_idx must hold
+ *            row_ptr[n] entries whenever row_ptr[n] <= n*(n-1).
+ *   opt      may be NULL (defaults).  The options are kept in the handle.
+ *   out      receives the handle; the inputs may be freed when this returns.
+ * Errors: INVALID_ARG, TOO_LARGE, NOT_SIMPLE (Section 2 assumes a simple
+ * graph), OUT_OF_MEMORY, DEVICE, NO_DEVICE.  *out is NULL on error.
+ */
+cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     const cc_options *opt, cc_graph **out);
+
+/* cc_count -- total number of chordless cycles, triangles included (the
+ * paper's C3 + #clc, Table 1).  Runs the count-only pipeline. */
+cc_status cc_count(cc_graph *g, int64_t *total);
+
+/* cc_histogram -- hist[k] = number of chordless cycles with k vertices for
+ * 0 <= k < hist_len (entries 0..2 are zero); hist_len >= n+1 (host array).
+ * Count-only: no cycle is stored (the paper's count-only mode, Table 1
+ * footnote on Grid 8x10). */
+cc_status cc_histogram(cc_graph *g, int64_t *hist, int32_t hist_len);
+
+/*
+ * cc_enumerate -- write every chordless cycle (Algorithm 1's output set C).
+ *   verts[verts_cap]        concatenated cycles, original vertex ids
+ *   offsets[cycles_cap + 1] cycle i is verts[offsets[i] .. offsets[i+1])
+ *   n_cycles, n_verts       receive the exact totals (host int64)
+ * Both buffers are host memory, or device memory with CC_OUTPUT_DEVICE.
+ * Sizing: the totals equal sum(hist) and sum(k * hist[k]) from
+ * cc_histogram.  If cycles_cap < total cycles or verts_cap < total
+ * vertices, returns CC_ERR_BUFFER_TOO_SMALL with *n_cycles / *n_verts set
+ * to the required sizes; buffer contents are then unspecified.
+ */
+cc_status cc_enumerate(cc_graph *g, int32_t *verts, int64_t verts_cap, int64_t *offsets,
+                       int64_t cycles_cap, int64_t *n_cycles, int64_t *n_verts);
+
+/* cc_labels -- labels[v] = degree label of vertex v (host array of n). */
+cc_status cc_labels(cc_graph *g, int32_t *labels);
+
+/* cc_frontier -- front[t] = number of open chordless paths with t vertices
+ * that the last run expanded (front[3] = |T(G)|, Section 2), for
+ * 0 <= t < len, len >= n+1 (host array). */
+cc_status cc_frontier(cc_graph *g, int64_t *front, int32_t len);
+
+/* cc_last_run -- statistics of the last count/histogram/enumerate call. */
+cc_status cc_last_run(cc_graph *g, cc_run_info *info);
+
+/* cc_release -- free a handle and its device memory (NULL is ignored). */
+void cc_release(cc_graph *g);
+
+/* cc_status_string -- static English description of a status code. */
+const char *cc_status_string(cc_status s);
+
+/* cc_abi_version -- CC_ABI_VERSION of the loaded library. */
+int32_t cc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CC_H */

@@ -151,6 +151,27 @@ def enumerate_cycles(n, row_ptr, col_idx, want_cycles=True, root_lo=0, root_hi=I
     return Result(hist, front, lab[:n], cycles, nc.value, nv.value)
 
 
+def enumerate_single_pass(n, row_ptr, col_idx, verts_cap, cyc_cap, root_lo=0,
+                          root_hi=INT64_MAX) -> Result:
+    """One oracle pass that counts and stores the cycles into buffers of the
+    given capacities (cycles beyond them are counted, not stored)."""
+    lib = _load()
+    rp, ci = _arrays(row_ptr, col_idx)
+    hist = np.zeros(n + 1, np.int64)
+    front = np.zeros(n + 1, np.int64)
+    lab = np.zeros(max(n, 1), np.int32)
+    verts = np.zeros(max(int(verts_cap), 1), np.int32)
+    offs = np.zeros(int(cyc_cap) + 1, np.int64)
+    nc = ctypes.c_int64(0)
+    nv = ctypes.c_int64(0)
+    st = lib.orc_enumerate(n, _p32(rp), _p32(ci), root_lo, root_hi, _p64(hist), _p64(front),
+                           _p32(lab), _p32(verts), int(verts_cap), _p64(offs), int(cyc_cap),
+                           ctypes.byref(nc), ctypes.byref(nv))
+    if st != OK:
+        raise ValueError(f"oracle: status {st}")
+    return Result(hist, front, lab[:n], (verts, offs), nc.value, nv.value)
+
+
 def cycle_list(res: Result):
     """The stored cycles as a list of int32 arrays (path order)."""
     verts, offs = res.cycles

@@ -1,0 +1,262 @@
+"""Python binding of libcc (argument marshalling only).
+
+Every computation runs in the HIP kernels behind the C ABI declared in
+include/cc.h; this module converts numpy arrays / torch tensors into
+pointers, sizes and a HIP stream, and raises on error statuses.  There is no
+CPU fallback: if libcc.so is missing or no gfx950 device is present, calls
+fail loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcc.so")
+
+CC_OK = 0
+CC_ERR_INVALID_ARG = -1
+CC_ERR_NOT_SIMPLE = -2
+CC_ERR_TOO_LARGE = -3
+CC_ERR_BUFFER_TOO_SMALL = -4
+CC_ERR_OUT_OF_MEMORY = -5
+CC_ERR_DEVICE = -6
+CC_ERR_NO_DEVICE = -7
+
+CC_INPUT_DEVICE = 1 << 0
+CC_OUTPUT_DEVICE = 1 << 1
+CC_FORCE_DFS = 1 << 2
+CC_PROFILE = 1 << 3
+CC_MAX_VERTICES = 128
+
+_lock = threading.Lock()
+_lib = None
+
+
+class CCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p),
+                ("frontier_budget_bytes", ctypes.c_int64),
+                ("flags", ctypes.c_uint32),
+                ("dfs_level", ctypes.c_int32),
+                ("dfs_waves_per_cu", ctypes.c_int32),
+                ("bfs_blocks", ctypes.c_int32)]
+
+
+class RunInfo(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int64),
+                ("paths", ctypes.c_int64),
+                ("peak_frontier", ctypes.c_int64),
+                ("switch_level", ctypes.c_int32),
+                ("levels_launched", ctypes.c_int32),
+                ("gpu_ms", ctypes.c_double),
+                ("stage1_ms", ctypes.c_double),
+                ("level_ms", ctypes.c_double),
+                ("dfs_ms", ctypes.c_double),
+                ("level_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def lib():
+    """Load libcc.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"libcc.so not built ({LIB_PATH}); run __graft_entry__.build()")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+            pp = ctypes.POINTER(ctypes.c_void_p)
+            L.cc_prepare.argtypes = [i32, vp, vp, ctypes.POINTER(Options), pp]
+            L.cc_prepare.restype = ctypes.c_int
+            L.cc_count.argtypes = [vp, ctypes.POINTER(i64)]
+            L.cc_count.restype = ctypes.c_int
+            L.cc_histogram.argtypes = [vp, vp, i32]
+            L.cc_histogram.restype = ctypes.c_int
+            L.cc_enumerate.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+            L.cc_enumerate.restype = ctypes.c_int
+            L.cc_labels.argtypes = [vp, vp]
+            L.cc_labels.restype = ctypes.c_int
+            L.cc_frontier.argtypes = [vp, vp, i32]
+            L.cc_frontier.restype = ctypes.c_int
+            L.cc_last_run.argtypes = [vp, ctypes.POINTER(RunInfo)]
+            L.cc_last_run.restype = ctypes.c_int
+            L.cc_release.argtypes = [vp]
+            L.cc_release.restype = None
+            L.cc_status_string.argtypes = [ctypes.c_int]
+            L.cc_status_string.restype = ctypes.c_char_p
+            L.cc_abi_version.argtypes = []
+            L.cc_abi_version.restype = i32
+            _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().cc_status_string(status).decode()
+
+
+def _check(st: int, where: str):
+    if st != CC_OK:
+        raise CCError(st, where)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    """(pointer, is_device, keepalive) for a numpy array or torch tensor."""
+    if x is None:
+        return None, False, None
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(x.data_ptr()), bool(x.is_cuda), x
+    a = np.ascontiguousarray(x)
+    return ctypes.c_void_p(a.ctypes.data), False, a
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Graph:
+    """A prepared graph (cc_prepare).  Use as a context manager or call
+    release()."""
+
+    def __init__(self, n, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
+                 force_dfs_level: int | None = None, dfs_waves_per_cu: int = 0,
+                 bfs_blocks: int = 0, output_device: bool = True, profile: bool = False):
+        L = lib()
+        rp, rp_dev, self._k1 = _ptr(_as_i32(row_ptr))
+        ci, ci_dev, self._k2 = _ptr(_as_i32(col_idx))
+        if rp_dev != ci_dev and n > 0:
+            raise ValueError("row_ptr and col_idx must both be host or both be device")
+        flags = 0
+        if rp_dev:
+            flags |= CC_INPUT_DEVICE
+        if output_device:
+            flags |= CC_OUTPUT_DEVICE
+        if force_dfs_level is not None:
+            flags |= CC_FORCE_DFS
+        if profile:
+            flags |= CC_PROFILE
+        self.opt = Options(_stream_handle(stream), int(budget_bytes), flags,
+                           int(force_dfs_level or 0), int(dfs_waves_per_cu), int(bfs_blocks))
+        self.n = int(n)
+        self.output_device = output_device
+        h = ctypes.c_void_p()
+        st = L.cc_prepare(self.n, rp, ci, ctypes.byref(self.opt), ctypes.byref(h))
+        self._k1 = self._k2 = None
+        _check(st, "cc_prepare")
+        self.h = h
+
+    # -- lifetime
+    def release(self):
+        if getattr(self, "h", None):
+            lib().cc_release(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.release()
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    # -- calls
+    def count(self) -> int:
+        total = ctypes.c_int64()
+        _check(lib().cc_count(self.h, ctypes.byref(total)), "cc_count")
+        return total.value
+
+    def histogram(self) -> np.ndarray:
+        h = np.zeros(self.n + 1, np.int64)
+        _check(lib().cc_histogram(self.h, ctypes.c_void_p(h.ctypes.data), h.size), "cc_histogram")
+        return h
+
+    def enumerate_into(self, verts, offsets):
+        """Fill caller buffers (torch device tensors when the graph was
+        prepared with output_device=True, else numpy arrays).  Returns
+        (n_cycles, n_verts); raises CCError(CC_ERR_BUFFER_TOO_SMALL) with
+        .required = (n_cycles, n_verts) if they do not fit."""
+        vp, _, _ = _ptr(verts)
+        op, _, _ = _ptr(offsets)
+        nc, nv = ctypes.c_int64(), ctypes.c_int64()
+        vcap = int(verts.numel() if _is_torch(verts) else np.asarray(verts).size)
+        ccap = int(offsets.numel() if _is_torch(offsets) else np.asarray(offsets).size) - 1
+        st = lib().cc_enumerate(self.h, vp, vcap, op, max(ccap, 0), ctypes.byref(nc), ctypes.byref(nv))
+        if st != CC_OK:
+            err = CCError(st, "cc_enumerate")
+            err.required = (nc.value, nv.value)
+            raise err
+        return nc.value, nv.value
+
+    def enumerate(self, device="cuda"):
+        """Size exactly (histogram), allocate, enumerate.  Returns
+        (verts, offsets) as torch tensors on `device` when prepared with
+        output_device=True, else numpy arrays."""
+        h = self.histogram()
+        nc = int(h.sum())
+        nv = int((h * np.arange(h.size)).sum())
+        if self.output_device:
+            import torch
+            verts = torch.empty(max(nv, 1), dtype=torch.int32, device=device)
+            offs = torch.empty(nc + 1, dtype=torch.int64, device=device)
+        else:
+            verts = np.empty(max(nv, 1), np.int32)
+            offs = np.empty(nc + 1, np.int64)
+        got_c, got_v = self.enumerate_into(verts, offs)
+        assert got_c == nc and got_v == nv
+        return verts[:nv], offs
+
+    def labels(self) -> np.ndarray:
+        lab = np.zeros(max(self.n, 1), np.int32)
+        _check(lib().cc_labels(self.h, ctypes.c_void_p(lab.ctypes.data)), "cc_labels")
+        return lab[:self.n]
+
+    def frontier(self) -> np.ndarray:
+        f = np.zeros(self.n + 1, np.int64)
+        _check(lib().cc_frontier(self.h, ctypes.c_void_p(f.ctypes.data), f.size), "cc_frontier")
+        return f
+
+    def last_run(self) -> dict:
+        info = RunInfo()
+        _check(lib().cc_last_run(self.h, ctypes.byref(info)), "cc_last_run")
+        return info.as_dict()
+
+
+def _as_i32(x):
+    if x is None:
+        return None
+    if _is_torch(x):
+        import torch
+        return x.to(torch.int32).contiguous()
+    a = np.asarray(x)
+    if a.size == 0:
+        a = np.zeros(1, np.int32)
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def prepare(g, **kw) -> Graph:
+    """cc_prepare on a graphgen.CSR-like object (n, row_ptr, col_idx)."""
+    return Graph(g.n, g.row_ptr, g.col_idx, **kw)

@@ -1,0 +1,601 @@
+// Host runtime behind the C ABI of include/cc.h: validation of arguments,
+// device memory, the level loop (Algorithm 4, without per-level readback),
+// the hand-over to the depth-first kernel, and result readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstddef>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "cc.h"
+#include "cc_internal.h"
+
+namespace {
+
+constexpr int64_t kDefaultBudget = 4ll << 30;
+constexpr double kIdleTimeoutSeconds = 30.0;
+
+struct DeviceInfo {
+  bool ok = false;
+  int cus = 0;
+  unsigned long long clock_hz = 0;
+};
+
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+// Per-device set-up: checks the architecture, reads the CU count and the
+// constant-rate clock, and keeps freed stream-ordered memory in the pool so
+// per-call workspaces are cheap after the first call.
+cc_status device_info(int dev, DeviceInfo *out) {
+  if (dev < 0 || dev >= 64) return CC_ERR_NO_DEVICE;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if (!g_dev[dev].ok) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return CC_ERR_NO_DEVICE;
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) return CC_ERR_NO_DEVICE;
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        rate_khz <= 0)
+      rate_khz = 100000;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    g_dev[dev].cus = p.multiProcessorCount;
+    g_dev[dev].clock_hz = (unsigned long long)rate_khz * 1000ull;
+    g_dev[dev].ok = true;
+  }
+  *out = g_dev[dev];
+  return CC_OK;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Per-handle device/pinned resources are recycled through a small free list
+// so that creating a handle per request (serving) costs no allocation after
+// warm-up.
+struct HandleRes {
+  int device;
+  void *d_blob;
+  void *h_ctl;
+  hipEvent_t ev0, ev1;
+};
+std::mutex g_pool_mu;
+HandleRes g_pool[64];
+int g_pool_n = 0;
+
+bool pool_take(int device, HandleRes *r) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (int i = g_pool_n - 1; i >= 0; --i) {
+    if (g_pool[i].device == device) {
+      *r = g_pool[i];
+      g_pool[i] = g_pool[--g_pool_n];
+      return true;
+    }
+  }
+  return false;
+}
+
+bool pool_give(const HandleRes &r) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool_n >= 64) return false;
+  g_pool[g_pool_n++] = r;
+  return true;
+}
+
+}  // namespace
+
+struct cc_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  cc_options opt{};
+  int32_t n = 0;
+  int W = 1;
+  int max_deg = 0;
+  DeviceInfo dev{};
+  void *d_blob = nullptr;  // adj | perm | label | status | ctl
+  unsigned long long *d_adj = nullptr;
+  int *d_perm = nullptr;
+  int *d_label = nullptr;
+  unsigned int *d_status = nullptr;
+  CcCtl *d_ctl = nullptr;
+  CcCtl *h_ctl = nullptr;  // pinned readback
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evp[2 * CC_MAXN + 8] = {};  // CC_PROFILE: around each kernel group
+  bool have_run = false;
+  int64_t hist[CC_HSLOTS]{};
+  int64_t front[CC_HSLOTS]{};
+  cc_run_info info{};
+};
+
+namespace {
+
+cc_status hip_err(hipError_t e) {
+  if (e == hipErrorOutOfMemory) return CC_ERR_OUT_OF_MEMORY;
+  return e == hipSuccess ? CC_OK : CC_ERR_DEVICE;
+}
+
+#define CC_TRY(expr)                          \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_err(e_); \
+  } while (0)
+
+// Address of a counter array inside the device-side control block.
+unsigned long long *dev_field(CcCtl *ctl, size_t offset) {
+  return (unsigned long long *)((char *)ctl + offset);
+}
+
+int64_t choose3(int64_t n) { return n < 3 ? 0 : n * (n - 1) * (n - 2) / 6; }
+
+// Carves one frontier buffer (SoA: X words, S words, vv) out of `base`.
+Frontier carve_frontier(char *base, unsigned long long cap, int W, bool en) {
+  Frontier f{};
+  size_t off = 0;
+  f.X = (unsigned long long *)(base + off);
+  off = align_up(off + cap * W * 8, 256);
+  if (en) {
+    f.S = (unsigned long long *)(base + off);
+    off = align_up(off + cap * W * 8, 256);
+  }
+  f.vv = (unsigned short *)(base + off);
+  f.cap = cap;
+  return f;
+}
+
+size_t frontier_bytes(unsigned long long cap, int W, bool en) {
+  size_t b = align_up(cap * W * 8, 256);
+  if (en) b += align_up(cap * W * 8, 256);
+  b += align_up(cap * 2, 256);
+  return b;
+}
+
+// Carves the depth-first workspace (queue + per-wavefront stacks) out of a
+// region of `bytes`.  Returns the number of wavefronts that fit (<= waves).
+int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_children,
+              DfsWork *wk) {
+  DfsWork d{};
+  const size_t item = (size_t)W * 8 * (en ? 2 : 1) + 4;
+  unsigned long long qcap = 4096;
+  while (qcap > 16 && qcap * (CC_CHUNK * item + 12) > bytes / 4) qcap >>= 1;
+  size_t off = 0;
+  d.qseq = (unsigned long long *)(base + off);
+  off = align_up(off + qcap * 8, 256);
+  d.qN = (unsigned int *)(base + off);
+  off = align_up(off + qcap * 4, 256);
+  d.qX = (unsigned long long *)(base + off);
+  off = align_up(off + qcap * W * CC_CHUNK * 8, 256);
+  if (en) {
+    d.qS = (unsigned long long *)(base + off);
+    off = align_up(off + qcap * W * CC_CHUNK * 8, 256);
+  }
+  d.qM = (unsigned int *)(base + off);
+  off = align_up(off + qcap * CC_CHUNK * 4, 256);
+  d.qcap = qcap;
+  const size_t rest = bytes > off + 4096 ? bytes - off - 4096 : 0;
+  const unsigned long long min_cap = (unsigned long long)CC_CHUNK * (max_children + 2);
+  int nw = waves;
+  while (nw > 4 && rest / ((size_t)nw * item) < min_cap) nw -= 4;
+  unsigned long long cap_w = rest / ((size_t)std::max(nw, 1) * item);
+  cap_w = std::min<unsigned long long>(cap_w, 1ull << 20);
+  cap_w &= ~63ull;
+  if (cap_w < min_cap) return 0;
+  d.cap_w = cap_w;
+  d.stackX = (unsigned long long *)(base + off);
+  off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
+  if (en) {
+    d.stackS = (unsigned long long *)(base + off);
+    off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
+  }
+  d.stackM = (unsigned int *)(base + off);
+  d.max_children = max_children;
+  d.donate_check = 4;
+  *wk = d;
+  return nw;
+}
+
+struct RunOut {
+  OutDev out{};
+  bool enumerate = false;
+};
+
+// One full device run: stage one, the level loop, and the depth-first
+// continuation if the budget (or CC_FORCE_DFS) requires it.
+cc_status run_device(cc_graph *g, const RunOut &ro) {
+  const int n = g->n;
+  const int W = g->W;
+  const bool en = ro.enumerate;
+  hipStream_t s = g->stream;
+  int64_t budget = g->opt.frontier_budget_bytes > 0 ? g->opt.frontier_budget_bytes : kDefaultBudget;
+  const size_t per_path = (size_t)W * 8 * (en ? 2 : 1) + 2;
+  unsigned long long cap = (unsigned long long)(budget / 2) / per_path;
+  const unsigned long long min_cap = (unsigned long long)choose3(n) + CC_CHUNK;
+  cap = std::max(cap, min_cap);
+  cap = align_up(cap, 64);
+  const size_t buf_bytes = align_up(frontier_bytes(cap, W, en), 1 << 16);
+  char *arena = nullptr;
+  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes, s));
+  Frontier f[2] = {carve_frontier(arena, cap, W, en), carve_frontier(arena + buf_bytes, cap, W, en)};
+
+  const int maxc = std::max(1, g->max_deg - 1);
+  int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 8;
+  waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
+  const int want_waves = std::max(4, (g->dev.cus * waves_per_cu) / 4 * 4);
+  DfsWork wc[2], we[2];
+  int nw_c = std::min(carve_dfs(arena, buf_bytes, W, false, want_waves, maxc, &wc[0]),
+                      carve_dfs(arena + buf_bytes, buf_bytes, W, false, want_waves, maxc, &wc[1]));
+  int nw_e = en ? std::min(carve_dfs(arena, buf_bytes, W, true, want_waves, maxc, &we[0]),
+                           carve_dfs(arena + buf_bytes, buf_bytes, W, true, want_waves, maxc, &we[1]))
+                : 4;
+  if (nw_c < 4 || nw_e < 4) {
+    (void)hipFreeAsync(arena, s);
+    return CC_ERR_OUT_OF_MEMORY;
+  }
+  const int dfs_blocks_c = nw_c / 4, dfs_blocks_e = nw_e / 4;
+  const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 8;
+  const int forced = (g->opt.flags & CC_FORCE_DFS) ? std::max(3, (int)g->opt.dfs_level) : -1;
+  const unsigned long long idle_timeout =
+      (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz);
+
+  GraphDev gd{g->d_adj, g->d_perm, n};
+  CcCtl *ctl = g->d_ctl;
+  hipError_t e = hipSuccess;
+  int levels = 0;
+  auto chk = [&](hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  };
+  const bool prof = (g->opt.flags & CC_PROFILE) != 0;
+  if (prof) {
+    for (int i = 0; i < 2 * n + 8; ++i)
+      if (!g->evp[i]) chk(hipEventCreate(&g->evp[i]));
+  }
+  // evp layout: [0,1] stage one, [2+2(t-3), 3+2(t-3)] level t, [2n, 2n+1] depth-first
+  auto mark = [&](int i) {
+    if (prof) chk(hipEventRecord(g->evp[i], s));
+  };
+  chk(hipEventRecord(g->ev0, s));
+  chk(cc_launch_zero(ctl, sizeof(CcCtl), s));
+  mark(0);
+  chk(cc_launch_triplets(W, en, gd, ctl, f[1], ro.out, s));
+  mark(1);
+  for (int t = 3; t <= n - 1 && e == hipSuccess; ++t, ++levels) {
+    mark(2 + 2 * (t - 3));
+    chk(cc_launch_level(W, en, gd, ctl, f[t & 1], f[(t + 1) & 1], ro.out, t, forced, bfs_blocks, s));
+    mark(3 + 2 * (t - 3));
+  }
+  // Depth-first continuation (each kernel returns at once if the levels
+  // finished within the budget).
+  mark(2 * n);
+  chk(cc_launch_dfs_prepare(ctl, wc[0], wc[1], n, false, s));
+  chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc[0], wc[1], ro.out,
+                    dev_field(ctl, en ? offsetof(CcCtl, dfs_hist) : offsetof(CcCtl, hist)), true,
+                    dfs_blocks_c, idle_timeout, s));
+  if (en) {
+    chk(cc_launch_dfs_prepare(ctl, we[0], we[1], n, true, s));
+    chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we[0], we[1], ro.out, nullptr, false,
+                      dfs_blocks_e, idle_timeout, s));
+    chk(cc_launch_finalize(ctl, ro.out, n, s));
+  }
+  mark(2 * n + 1);
+  chk(hipEventRecord(g->ev1, s));
+  chk(hipMemcpyAsync(g->h_ctl, ctl, sizeof(CcCtl), hipMemcpyDeviceToHost, s));
+  chk(hipFreeAsync(arena, s));
+  chk(hipStreamSynchronize(s));
+  if (e != hipSuccess) return hip_err(e);
+
+  const CcCtl &h = *g->h_ctl;
+  std::memset(g->hist, 0, sizeof(g->hist));
+  std::memset(g->front, 0, sizeof(g->front));
+  int64_t cycles = 0, paths = 0;
+  for (int k = 0; k <= n; ++k) {
+    g->hist[k] = (int64_t)h.hist[k];
+    g->front[k] = (int64_t)h.front[k];
+    cycles += g->hist[k];
+    paths += g->front[k];
+  }
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, g->ev0, g->ev1);
+  g->info.cycles = cycles;
+  g->info.paths = paths;
+  g->info.peak_frontier = (int64_t)h.peak;
+  g->info.switch_level = h.mode ? h.switch_level : 0;
+  g->info.levels_launched = levels;
+  g->info.gpu_ms = ms;
+  g->info.stage1_ms = g->info.level_ms = g->info.dfs_ms = 0.0;
+  g->info.level_bytes = 0;
+  if (prof) {
+    auto span = [&](int a, int b) {
+      float x = 0.f;
+      (void)hipEventElapsedTime(&x, g->evp[a], g->evp[b]);
+      return (double)x;
+    };
+    g->info.stage1_ms = span(0, 1);
+    for (int t = 3; t <= n - 1; ++t) g->info.level_ms += span(2 + 2 * (t - 3), 3 + 2 * (t - 3));
+    g->info.dfs_ms = span(2 * n, 2 * n + 1);
+    // Bytes the level kernels must move: each path they expand is read once,
+    // each extension they write is written once (X words, S words in
+    // enumerate mode, 2 bytes of end vertices), and each cycle they close is
+    // written as k int32 ids plus one int64 offset.
+    const int last = h.mode ? (h.skip_first ? h.switch_level : h.switch_level - 1) : n - 1;
+    const int64_t pp = (int64_t)per_path;
+    int64_t bytes = 0;
+    for (int t = 3; t <= last && t <= n - 1; ++t) {
+      bytes += (int64_t)std::min<unsigned long long>(h.count[t], cap) * pp;
+      bytes += (int64_t)std::min<unsigned long long>(h.count[t + 1], cap) * pp;
+      if (en) bytes += (int64_t)h.hist[t + 1] * (4 * (t + 1) + 8);
+    }
+    g->info.level_bytes = bytes;
+  }
+  g->have_run = true;
+  if (h.status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
+  return CC_OK;
+}
+
+cc_status check_handle(cc_graph *g) {
+  if (!g) return CC_ERR_INVALID_ARG;
+  if (hipSetDevice(g->device) != hipSuccess) return CC_ERR_DEVICE;
+  return CC_OK;
+}
+
+cc_status run_counts(cc_graph *g) {
+  if (g->n < 3) {
+    std::memset(g->hist, 0, sizeof(g->hist));
+    std::memset(g->front, 0, sizeof(g->front));
+    g->info = cc_run_info{};
+    g->have_run = true;
+    return CC_OK;
+  }
+  RunOut ro;
+  return run_device(g, ro);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t cc_abi_version(void) { return CC_ABI_VERSION; }
+
+const char *cc_status_string(cc_status s) {
+  switch (s) {
+    case CC_OK: return "ok";
+    case CC_ERR_INVALID_ARG: return "invalid argument";
+    case CC_ERR_NOT_SIMPLE: return "graph is not a simple undirected graph";
+    case CC_ERR_TOO_LARGE: return "graph has more vertices than supported";
+    case CC_ERR_BUFFER_TOO_SMALL: return "output buffer too small";
+    case CC_ERR_OUT_OF_MEMORY: return "out of device memory or frontier budget too small";
+    case CC_ERR_DEVICE: return "HIP runtime or device error";
+    case CC_ERR_NO_DEVICE: return "no usable gfx950 device";
+  }
+  return "unknown status";
+}
+
+cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     const cc_options *opt, cc_graph **out) {
+  if (!out) return CC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n < 0) return CC_ERR_INVALID_ARG;
+  if (n > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
+  if (n > 0 && !row_ptr) return CC_ERR_INVALID_ARG;
+  const uint32_t flags = opt ? opt->flags : 0u;
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE))
+    return CC_ERR_INVALID_ARG;
+  if (opt && opt->frontier_budget_bytes < 0) return CC_ERR_INVALID_ARG;
+  if ((flags & CC_FORCE_DFS) && opt->dfs_level < 3) return CC_ERR_INVALID_ARG;
+  int64_t nnz = 0;
+  if (n > 0 && !(flags & CC_INPUT_DEVICE)) {
+    nnz = row_ptr[n];
+    if (row_ptr[0] != 0 || nnz < 0 || nnz > (int64_t)n * (n - 1)) return CC_ERR_NOT_SIMPLE;
+    if (nnz > 0 && !col_idx) return CC_ERR_INVALID_ARG;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CC_ERR_NO_DEVICE;
+  DeviceInfo di;
+  cc_status st = device_info(dev, &di);
+  if (st != CC_OK) return st;
+
+  cc_graph *g = new cc_graph();
+  g->device = dev;
+  g->dev = di;
+  if (opt) g->opt = *opt;
+  g->stream = (hipStream_t)g->opt.stream;
+  g->n = n;
+  g->W = n <= 64 ? 1 : 2;
+  const size_t adj_b = align_up((size_t)CC_MAXN * 2 * 8, 256);
+  const size_t vec_b = align_up((size_t)CC_MAXN * 4, 256);
+  const size_t blob = adj_b + 2 * vec_b + 256 + align_up(sizeof(CcCtl), 256);
+  auto fail = [&](cc_status s) {
+    cc_release(g);
+    return s;
+  };
+  HandleRes res;
+  if (pool_take(dev, &res)) {
+    g->d_blob = res.d_blob;
+    g->h_ctl = (CcCtl *)res.h_ctl;
+    g->ev0 = res.ev0;
+    g->ev1 = res.ev1;
+  } else {
+    if (hipMalloc(&g->d_blob, blob) != hipSuccess) return fail(CC_ERR_OUT_OF_MEMORY);
+    if (hipHostMalloc((void **)&g->h_ctl, sizeof(CcCtl), hipHostMallocDefault) != hipSuccess)
+      return fail(CC_ERR_OUT_OF_MEMORY);
+    if (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess)
+      return fail(CC_ERR_DEVICE);
+  }
+  char *b = (char *)g->d_blob;
+  g->d_adj = (unsigned long long *)b;
+  g->d_perm = (int *)(b + adj_b);
+  g->d_label = (int *)(b + adj_b + vec_b);
+  g->d_status = (unsigned int *)(b + adj_b + 2 * vec_b);
+  g->d_ctl = (CcCtl *)(b + adj_b + 2 * vec_b + 256);
+  if (n == 0) {
+    *out = g;
+    return CC_OK;
+  }
+  const int *d_rp = row_ptr, *d_ci = col_idx;
+  void *tmp = nullptr;
+  hipStream_t s = g->stream;
+  if (!(flags & CC_INPUT_DEVICE)) {
+    const size_t rb = align_up((size_t)(n + 1) * 4, 256);
+    if (hipMallocAsync(&tmp, rb + (size_t)std::max<int64_t>(nnz, 1) * 4, s) != hipSuccess)
+      return fail(CC_ERR_OUT_OF_MEMORY);
+    if (hipMemcpyAsync(tmp, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync((char *)tmp + rb, col_idx, (size_t)nnz * 4,
+                                   hipMemcpyHostToDevice, s) != hipSuccess)) {
+      (void)hipFreeAsync(tmp, s);
+      (void)hipStreamSynchronize(s);
+      return fail(CC_ERR_DEVICE);
+    }
+    d_rp = (const int *)tmp;
+    d_ci = (const int *)((char *)tmp + rb);
+  }
+  hipError_t e = cc_launch_ingest(g->W, 1, nullptr, n, d_rp, d_ci, g->d_adj, 0, g->d_perm,
+                                  g->d_label, g->d_status, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&g->h_ctl->status, g->d_status, 4, hipMemcpyDeviceToHost, s);
+  if (tmp) (void)hipFreeAsync(tmp, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(hip_err(e));
+  const unsigned int stv = g->h_ctl->status;
+  if ((stv & 0xffu) != 0u || !(stv & 0x100u)) return fail(CC_ERR_NOT_SIMPLE);
+  g->max_deg = (int)(stv >> 16);
+  *out = g;
+  return CC_OK;
+}
+
+cc_status cc_histogram(cc_graph *g, int64_t *hist, int32_t hist_len) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!hist || hist_len < g->n + 1) return CC_ERR_INVALID_ARG;
+  st = run_counts(g);
+  if (st != CC_OK) return st;
+  for (int k = 0; k < hist_len; ++k) hist[k] = k <= g->n ? g->hist[k] : 0;
+  return CC_OK;
+}
+
+cc_status cc_count(cc_graph *g, int64_t *total) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!total) return CC_ERR_INVALID_ARG;
+  st = run_counts(g);
+  if (st != CC_OK) return st;
+  *total = g->info.cycles;
+  return CC_OK;
+}
+
+cc_status cc_enumerate(cc_graph *g, int32_t *verts, int64_t verts_cap, int64_t *offsets,
+                       int64_t cycles_cap, int64_t *n_cycles, int64_t *n_verts) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!n_cycles || !n_verts || verts_cap < 0 || cycles_cap < 0) return CC_ERR_INVALID_ARG;
+  if ((verts_cap > 0 && !verts) || !offsets) return CC_ERR_INVALID_ARG;
+  *n_cycles = 0;
+  *n_verts = 0;
+  const bool dev_out = (g->opt.flags & CC_OUTPUT_DEVICE) != 0;
+  if (g->n < 3) {
+    (void)run_counts(g);
+    if (dev_out) {
+      const int64_t zero = 0;
+      if (hipMemcpyAsync(offsets, &zero, 8, hipMemcpyHostToDevice, g->stream) != hipSuccess ||
+          hipStreamSynchronize(g->stream) != hipSuccess)
+        return CC_ERR_DEVICE;
+    } else {
+      offsets[0] = 0;
+    }
+    return CC_OK;
+  }
+  auto totals = [&](int64_t *c, int64_t *v) {
+    *c = 0;
+    *v = 0;
+    for (int k = 0; k <= g->n; ++k) {
+      *c += g->hist[k];
+      *v += g->hist[k] * k;
+    }
+  };
+  if (dev_out) {
+    RunOut ro;
+    ro.enumerate = true;
+    ro.out = OutDev{verts, (long long *)offsets, verts_cap, cycles_cap};
+    st = run_device(g, ro);
+    if (st != CC_OK) return st;
+    totals(n_cycles, n_verts);
+    if (*n_cycles > cycles_cap || *n_verts > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
+    return CC_OK;
+  }
+  // Host buffers: count first to size exact device buffers, then enumerate
+  // into them and copy back.
+  st = run_counts(g);
+  if (st != CC_OK) return st;
+  int64_t c = 0, v = 0;
+  totals(&c, &v);
+  *n_cycles = c;
+  *n_verts = v;
+  if (c > cycles_cap || v > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
+  void *dv = nullptr, *doff = nullptr;
+  hipStream_t s = g->stream;
+  if (hipMallocAsync(&dv, (size_t)std::max<int64_t>(v, 1) * 4, s) != hipSuccess)
+    return CC_ERR_OUT_OF_MEMORY;
+  if (hipMallocAsync(&doff, (size_t)(c + 1) * 8, s) != hipSuccess) {
+    (void)hipFreeAsync(dv, s);
+    (void)hipStreamSynchronize(s);
+    return CC_ERR_OUT_OF_MEMORY;
+  }
+  RunOut ro;
+  ro.enumerate = true;
+  ro.out = OutDev{(int *)dv, (long long *)doff, v, c};
+  st = run_device(g, ro);
+  if (st == CC_OK) {
+    if (hipMemcpyAsync(verts, dv, (size_t)v * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(offsets, doff, (size_t)(c + 1) * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+      st = CC_ERR_DEVICE;
+  }
+  (void)hipFreeAsync(dv, s);
+  (void)hipFreeAsync(doff, s);
+  if (hipStreamSynchronize(s) != hipSuccess && st == CC_OK) st = CC_ERR_DEVICE;
+  return st;
+}
+
+cc_status cc_labels(cc_graph *g, int32_t *labels) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!labels) return CC_ERR_INVALID_ARG;
+  if (g->n == 0) return CC_OK;
+  if (hipMemcpyAsync(labels, g->d_label, (size_t)g->n * 4, hipMemcpyDeviceToHost, g->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(g->stream) != hipSuccess)
+    return CC_ERR_DEVICE;
+  return CC_OK;
+}
+
+cc_status cc_frontier(cc_graph *g, int64_t *front, int32_t len) {
+  if (!g || !front || len < g->n + 1) return CC_ERR_INVALID_ARG;
+  for (int t = 0; t < len; ++t) front[t] = (t <= g->n && g->have_run) ? g->front[t] : 0;
+  return CC_OK;
+}
+
+cc_status cc_last_run(cc_graph *g, cc_run_info *info) {
+  if (!g || !info) return CC_ERR_INVALID_ARG;
+  *info = g->info;
+  return CC_OK;
+}
+
+void cc_release(cc_graph *g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->d_blob) (void)hipStreamSynchronize(g->stream);
+  for (hipEvent_t &ev : g->evp)
+    if (ev) (void)hipEventDestroy(ev);
+  const bool complete = g->d_blob && g->h_ctl && g->ev0 && g->ev1;
+  if (!(complete && pool_give(HandleRes{g->device, g->d_blob, g->h_ctl, g->ev0, g->ev1}))) {
+    if (g->d_blob) (void)hipFree(g->d_blob);
+    if (g->h_ctl) (void)hipHostFree(g->h_ctl);
+    if (g->ev0) (void)hipEventDestroy(g->ev0);
+    if (g->ev1) (void)hipEventDestroy(g->ev1);
+  }
+  delete g;
+}
+
+}  // extern "C"

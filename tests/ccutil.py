@@ -98,3 +98,53 @@ def dense_adjacency(n, row_ptr, col_idx):
 def triangles_by_trace(n, row_ptr, col_idx) -> int:
     A = dense_adjacency(n, row_ptr, col_idx)
     return int(np.trace(A @ A @ A) // 6)
+
+
+def canonical_groups(verts, offs):
+    """Canonicalise a CSR of cycles (any rotation/direction) and group by
+    length: returns {k: (N_k, k) int64 array, rows sorted lexicographically}.
+    Vectorised per length."""
+    verts = np.asarray(verts, dtype=np.int64)
+    offs = np.asarray(offs, dtype=np.int64)
+    lens = np.diff(offs)
+    out = {}
+    for k in np.unique(lens):
+        k = int(k)
+        starts = offs[:-1][lens == k]
+        a = verts[starts[:, None] + np.arange(k)[None, :]]
+        i = np.argmin(a, axis=1)
+        fwd = a[np.arange(a.shape[0]), (i + 1) % k]
+        bwd = a[np.arange(a.shape[0]), (i - 1) % k]
+        step = np.where(fwd <= bwd, 1, -1)
+        idx = (i[:, None] + step[:, None] * np.arange(k)[None, :]) % k
+        c = np.take_along_axis(a, idx, axis=1)
+        order = np.lexsort(c.T[::-1])
+        out[k] = c[order]
+    return out
+
+
+def is_canonical_array(verts, offs) -> bool:
+    """True if every cycle already starts at its minimum and continues towards
+    the smaller neighbour."""
+    verts = np.asarray(verts, dtype=np.int64)
+    offs = np.asarray(offs, dtype=np.int64)
+    lens = np.diff(offs)
+    for k in np.unique(lens):
+        k = int(k)
+        starts = offs[:-1][lens == k]
+        a = verts[starts[:, None] + np.arange(k)[None, :]]
+        if not np.all(a[:, 0] == a.min(axis=1)):
+            return False
+        if k >= 3 and not np.all(a[:, 1] <= a[:, -1]):
+            return False
+    return True
+
+
+def groups_digest(groups) -> str:
+    """sha256 over the canonical sorted cycles, lengths ascending."""
+    import hashlib
+    h = hashlib.sha256()
+    for k in sorted(groups):
+        h.update(np.int64(k).tobytes())
+        h.update(np.ascontiguousarray(groups[k], dtype=np.int64).tobytes())
+    return h.hexdigest()

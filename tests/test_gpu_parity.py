@@ -1,0 +1,224 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Results are exact: the sorted set of canonical cycles, the per-length
+histogram, the degree labels and the per-length counts of expanded paths
+must all be equal.  Large workloads compare against stored oracle outputs
+(tests/golden, written by tests/golden/make_golden.py)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from ccutil import canonical_groups, groups_digest, is_canonical_array
+from paper_1410_4876_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a gfx950 device"
+    from paper_1410_4876_amd import cc as mod
+    mod.lib()
+    return mod
+
+
+def oracle_run(g, cycles=True):
+    return oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=cycles)
+
+
+def gpu_enumerate(cc, g, **kw):
+    import torch
+    with cc.prepare(g, **kw) as h:
+        verts, offs = h.enumerate()
+        torch.cuda.synchronize()
+        return (verts.cpu().numpy(), offs.cpu().numpy(), h.histogram(), h.labels(),
+                h.frontier(), h.last_run())
+
+
+def assert_same_cycles(gpu_verts, gpu_offs, ores):
+    assert is_canonical_array(gpu_verts, gpu_offs)
+    assert np.all(np.diff(np.diff(gpu_offs)) >= 0), "output not ordered by length"
+    a = canonical_groups(gpu_verts, gpu_offs)
+    b = canonical_groups(*ores.cycles)
+    assert sorted(a) == sorted(b)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), f"cycles of length {k} differ"
+        if a[k].shape[0] > 1:
+            assert not np.any(np.all(a[k][1:] == a[k][:-1], axis=1)), "duplicate cycle"
+
+
+def full_parity(cc, g, **kw):
+    ores = oracle_run(g)
+    v, o, hist, lab, front, info = gpu_enumerate(cc, g, **kw)
+    assert np.array_equal(hist, ores.hist)
+    assert np.array_equal(lab, ores.labels)
+    assert np.array_equal(front, ores.front)
+    assert_same_cycles(v, o, ores)
+    with cc.prepare(g, **kw) as h:
+        assert np.array_equal(h.histogram(), ores.hist)
+        assert np.array_equal(h.frontier(), ores.front)
+        assert h.count() == ores.count
+    return info
+
+
+def small_suite():
+    rng = np.random.default_rng(4242)
+    out = [gg.cycle(3), gg.cycle(4), gg.cycle(64), gg.cycle(65), gg.cycle(128),
+           gg.complete(5), gg.complete(12), gg.complete_bipartite(8, 8), gg.wheel(9),
+           gg.wheel(64), gg.wheel(100), gg.ladder(20), gg.hypercube(4), gg.hypercube(5),
+           gg.complete_multipartite(3, 4, 5), gg.grid(5, 6), gg.grid(6, 6), gg.grid(4, 10),
+           gg.permute_random(gg.grid(5, 10), rng), gg.path_graph(30), gg.random_tree(60, rng),
+           gg.cone(gg.cycle(20)), gg.disjoint_union(gg.grid(4, 4), gg.wheel(5), gg.complete(4))]
+    # Sparse enough that the oracle finishes in seconds; n > 64 exercises
+    # two-word bitsets.
+    for n, m in [(10, 20), (14, 30), (30, 60), (40, 100), (63, 120), (64, 128), (65, 130),
+                 (90, 130), (100, 125), (110, 135), (128, 150)]:
+        out.append(gg.er_gnm(n, m, np.random.default_rng(4242)))
+    return out
+
+
+@pytest.mark.parametrize("g", small_suite(), ids=lambda g: f"{g.name}_n{g.n}_m{g.m}")
+def test_small_suite_parity(cc, g):
+    full_parity(cc, g)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_degenerate_sizes(cc, n):
+    g = gg.path_graph(n) if n else gg.csr_from_edges(0, [])
+    with cc.prepare(g) as h:
+        assert h.count() == 0
+        assert not h.histogram().any()
+        v, o = h.enumerate()
+        assert o.numel() == 1 and int(o[0]) == 0
+
+
+def test_no_edges(cc):
+    g = gg.csr_from_edges(50, [])
+    with cc.prepare(g) as h:
+        assert h.count() == 0 and h.labels().tolist() == list(range(50))
+
+
+@pytest.mark.parametrize("level", [3, 4, 6, 10])
+def test_forced_depth_first_matches(cc, level):
+    rng = np.random.default_rng(level)
+    for g in [gg.permute_random(gg.grid(5, 7), rng), gg.er_gnm(60, 110, rng),
+              gg.er_gnm(100, 125, rng)]:
+        info = full_parity(cc, g, force_dfs_level=level)
+        assert info["switch_level"] == level
+
+
+def test_budget_overflow_switches_to_depth_first(cc):
+    # 6x8 grid: the largest level holds 46482 paths; 512 KiB of frontier
+    # budget holds about 14600 (enumerate) or 26200 (count) per level, so the
+    # levels overflow and hand over to the stacks.
+    g = gg.permute_random(gg.grid(6, 8), np.random.default_rng(5))
+    info = full_parity(cc, g, budget_bytes=512 << 10)
+    assert info["switch_level"] > 3
+
+
+def test_device_pointer_input(cc):
+    import torch
+    g = gg.workload_er40()
+    rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
+    h = cc.Graph(g.n, rp, ci)
+    try:
+        assert np.array_equal(h.histogram(), oracle_run(g, cycles=False).hist)
+    finally:
+        h.release()
+
+
+def test_host_output_buffers(cc):
+    g = gg.grid(5, 6)
+    ores = oracle_run(g)
+    with cc.prepare(g, output_device=False) as h:
+        v, o = h.enumerate()
+        assert_same_cycles(v, o, ores)
+
+
+def test_buffer_too_small_reports_sizes(cc):
+    import torch
+    g = gg.grid(4, 5)
+    ores = oracle_run(g)
+    with cc.prepare(g) as h:
+        v = torch.empty(10, dtype=torch.int32, device="cuda")
+        o = torch.empty(3, dtype=torch.int64, device="cuda")
+        with pytest.raises(cc.CCError) as ei:
+            h.enumerate_into(v, o)
+        assert ei.value.status == cc.CC_ERR_BUFFER_TOO_SMALL
+        assert ei.value.required == (ores.n_cycles, ores.n_verts)
+
+
+@pytest.mark.parametrize("case", ["self_loop", "duplicate", "asymmetric", "out_of_range"])
+def test_rejects_non_simple(cc, case):
+    import torch
+    rp, ci = {
+        "self_loop": ([0, 2, 3, 4], [0, 1, 0, 0]),
+        "duplicate": ([0, 2, 4, 4], [1, 1, 0, 0]),
+        "asymmetric": ([0, 1, 1, 1], [1]),
+        "out_of_range": ([0, 1, 2, 2], [7, 0]),
+    }[case]
+    for dev in (False, True):
+        r = np.array(rp, np.int32)
+        c = np.array(ci, np.int32)
+        if dev:
+            r = torch.tensor(r, device="cuda")
+            c = torch.tensor(c, device="cuda")
+        with pytest.raises(cc.CCError) as ei:
+            cc.Graph(3, r, c)
+        assert ei.value.status == cc.CC_ERR_NOT_SIMPLE
+
+
+def test_repeated_runs_identical(cc):
+    g = gg.er_gnm(50, 120, np.random.default_rng(3))
+    with cc.prepare(g) as h:
+        a = [h.histogram() for _ in range(3)]
+        assert all(np.array_equal(a[0], x) for x in a)
+
+
+# ------------------------------------------------------------- workloads
+def test_workload_er40_full_enumeration(cc):
+    """ER G(40, 100): full enumeration, live oracle."""
+    full_parity(cc, gg.workload_er40())
+
+
+def test_workload_grid8x8_full_enumeration(cc):
+    """8x8 grid, ids permuted: full enumeration as int32 vertex lists,
+    compared with the stored oracle output."""
+    gold = json.load(open(os.path.join(GOLDEN, "grid8x8.json")))
+    g = gg.workload_grid8x8()
+    v, o, hist, lab, front, info = gpu_enumerate(cc, g)
+    assert hist.tolist() == gold["hist"]
+    assert lab.tolist() == gold["labels"]
+    assert front.tolist() == gold["front"]
+    assert int(o[-1]) == gold["total_verts"]
+    assert is_canonical_array(v, o)
+    assert groups_digest(canonical_groups(v, o)) == gold["canonical_sha256"]
+
+
+def test_workload_grid8x8_forced_depth_first(cc):
+    gold = json.load(open(os.path.join(GOLDEN, "grid8x8.json")))
+    g = gg.workload_grid8x8()
+    with cc.prepare(g, force_dfs_level=12) as h:
+        assert h.histogram().tolist() == gold["hist"]
+        assert h.frontier().tolist() == gold["front"]
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "grid7x12.json")),
+                    reason="stored oracle output for the 7x12 grid not generated")
+def test_workload_grid7x12_count_only_4gb(cc):
+    """7x12 grid, count-only, 4 GiB frontier budget (the depth-first switch
+    is expected to fire)."""
+    gold = json.load(open(os.path.join(GOLDEN, "grid7x12.json")))
+    g = gg.workload_grid7x12()
+    with cc.prepare(g, budget_bytes=4 << 30) as h:
+        assert h.histogram().tolist() == gold["hist"]
+        assert h.labels().tolist() == gold["labels"]
+        assert h.frontier().tolist() == gold["front"]
+        info = h.last_run()
+        print("grid7x12", info)
