@@ -6,55 +6,82 @@
 #include <stdint.h>
 
 #define CC_MAXN 128
-#define CC_HSLOTS (CC_MAXN + 2)   // histogram / per-length arrays: index 0..n+1
+#define CC_HSLOTS (CC_MAXN + 2)   // per-length arrays: index 0..n+1
 #define CC_WAVE 64
 #define CC_BLOCK 256              // threads per block for the expansion kernels
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk
+#define CC_LEVEL_IPT 4            // paths per lane per chunk in the level kernel
+#define CC_ROOT_CLAIM 1024        // handed-over paths a depth-first wavefront claims at once
+// Frontier and staged-cycle counters are split into CC_SHARDS shards, each
+// on its own cache lines: a block appends to shard blockIdx % CC_SHARDS, so
+// no counter sees more than 1/CC_SHARDS of the atomics (same-address
+// device-scope atomics serialise across the chip).
+#define CC_SHARDS 64
 
 // Device-side error bits (CcCtl::status).
 #define CC_DEV_NOT_SIMPLE 1u
-#define CC_DEV_STACK_FULL 2u      // depth-first stack and donation queue both full
+#define CC_DEV_STACK_FULL 2u      // a depth-first stack had no room (results incomplete)
 #define CC_DEV_IDLE_TIMEOUT 4u    // an idle wavefront gave up waiting (diagnostic only)
 
+// skip bits for the paths handed to the depth-first kernel
+#define CC_SKIP_FRONT 1           // their path count is already recorded
+#define CC_SKIP_CLOSE 2           // their closures are already recorded
+
 // Control block of one run in device memory.  Zeroed by a kernel at the start
-// of every run.  All counters are 64-bit.
+// of every run.  Per-shard arrays are shard-major, [s][k].
 struct CcCtl {
-  unsigned long long count[CC_HSLOTS];     // count[t]: open paths with t vertices written
-  unsigned long long hist[CC_HSLOTS];      // hist[k]: cycles with k vertices
-  unsigned long long front[CC_HSLOTS];     // front[t]: paths with t vertices expanded
-  unsigned long long dfs_hist[CC_HSLOTS];  // enumerate: depth-first part, counting pass
-  unsigned long long len_cursor[CC_HSLOTS];// enumerate: depth-first slot allocator per length
-  unsigned long long len_cbase[CC_HSLOTS]; // enumerate: first cycle index of each length
-  unsigned long long len_vbase[CC_HSLOTS]; // enumerate: first vertex offset of each length
-  unsigned long long peak;                 // largest breadth-first frontier
-  unsigned long long root_cursor;          // depth-first: next unclaimed root path
-  unsigned long long q_head, q_tail;       // depth-first donation queue positions
-  unsigned long long dfs_batches;          // depth-first batches processed (diagnostic)
-  unsigned long long donations;            // chunks donated (diagnostic)
-  int mode;                                // 0 = breadth-first, 1 = depth-first took over
-  int switch_level;                        // path length handed to the depth-first kernel
-  int skip_first;                          // 1: the roots' first expansion was already counted
-  int busy;                                // depth-first wavefronts holding or seeking work
-  int idle;                                // depth-first wavefronts waiting for work
-  unsigned int status;                     // CC_DEV_* bits
-  int bfs_max_len;                         // longest cycle written by the breadth-first part
+  unsigned long long count_sh[CC_SHARDS][CC_HSLOTS];  // open paths with t vertices, per shard
+  unsigned long long hist_sh[CC_SHARDS][CC_HSLOTS];   // cycles with k vertices, per shard
+  unsigned long long hist[CC_HSLOTS];       // final histogram (written by k_finalize)
+  unsigned long long front[CC_HSLOTS];      // paths with t vertices expanded
+  unsigned long long cum_c[CC_HSLOTS];      // enumerate: cycles of length <= t (breadth-first)
+  unsigned long long cum_v[CC_HSLOTS];      // enumerate: their vertex count
+  unsigned long long dfs_hist[CC_HSLOTS];   // enumerate: depth-first part, counting pass
+  unsigned long long len_cursor[CC_HSLOTS]; // enumerate: depth-first slot allocator per length
+  unsigned long long len_cbase[CC_HSLOTS];  // enumerate: first cycle index of each length
+  unsigned long long len_vbase[CC_HSLOTS];  // enumerate: first vertex offset of each length
+  unsigned long long peak;                  // largest breadth-first frontier
+  unsigned long long root_cursor;           // depth-first: next unclaimed handed-over path
+  unsigned long long q_head, q_tail;        // depth-first donation queue positions
+  unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
+  unsigned long long donations;             // chunks donated (diagnostic)
+  int mode;                                 // 0 = breadth-first, 1 = depth-first took over
+  int switch_level;                         // path length handed to the depth-first kernel
+  int skip;                                 // CC_SKIP_* bits for the handed-over paths
+  int busy;                                 // depth-first wavefronts holding or seeking work
+  int idle;                                 // depth-first wavefronts waiting for work
+  unsigned int status;                      // CC_DEV_* bits
+  int bfs_max_len;                          // longest cycle length final after the levels
   int pad;
 };
 
-// Frontier of open paths, structure of arrays, capacity `cap` paths.
-// Word w of path i's exclusion set X is X[w * cap + i]; likewise S (vertex
-// set, enumerate mode only); vv[i] = v1 | vt << 8 (ids are labels).
+// Frontier of open paths, structure of arrays, CC_SHARDS shards of cap_s
+// paths.  Path `off` of shard s is element i = s * cap_s + off; word w of its
+// exclusion set X (label space) is X[w * cap + i]; likewise its vertex set S
+// (original-id space, enumerate mode only); vv[i] = v1 | vt << 8 (labels).
 struct Frontier {
   unsigned long long *X;
   unsigned long long *S;
   unsigned short *vv;
+  unsigned long long cap;    // CC_SHARDS * cap_s
+  unsigned long long cap_s;
+};
+
+// Staged cycles of one level (enumerate mode): vertex-set bitsets in
+// original-id space, sharded like a frontier: word w of cycle `off` of shard
+// s is C[w * cap + s * cap_s + off].
+struct Stage {
+  unsigned long long *C;
   unsigned long long cap;
+  unsigned long long cap_s;
 };
 
 // Relabelled graph: adjacency bitsets in label space (row l = neighbours of
-// the vertex with label l, W words per row) and perm[l] = original id.
+// the vertex with label l), the same graph in original-id space, and
+// perm[l] = original id of label l.
 struct GraphDev {
   const unsigned long long *adj;
+  const unsigned long long *adj_orig;
   const int *perm;
   int n;
 };
@@ -86,21 +113,27 @@ struct DfsWork {
 // ------------------------------------------------------------------ launchers
 // All return hipSuccess or the launch error.  `W` is 1 (n <= 64) or 2.
 hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s);
+// adj (label space) and adj_orig (original ids) rows are at (v0 + row) * W.
 hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n_single,
                             const int *row_ptr, const int *col_idx, unsigned long long *adj,
-                            int adj_stride_words, int *perm, int *label, unsigned int *status,
-                            hipStream_t s);
+                            unsigned long long *adj_orig, int *perm, int *label,
+                            unsigned int *status, hipStream_t s);
 hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
-                              OutDev out, hipStream_t s);
+                              Stage st, hipStream_t s);
+// host_done (pinned host memory, may be NULL) receives the first level that
+// found nothing to do, so the host can stop launching levels early.
 hipError_t cc_launch_level(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier fin,
-                           Frontier fout, OutDev out, int t, int forced_level, int blocks,
+                           Frontier fout, Stage sprev, Stage scur, OutDev out, int t,
+                           int forced_level, int blocks, unsigned int *host_done,
                            hipStream_t s);
 // The depth-first workspace lives in the frontier buffer that does not hold
 // the handed-over paths: wk0 is carved from buffer 0, wk1 from buffer 1.
+// Cycle counts of block b go to hist_out[(b % CC_SHARDS) * hist_stride + k]
+// (hist_out NULL: not counted).
 hipError_t cc_launch_dfs(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f0,
                          Frontier f1, DfsWork wk0, DfsWork wk1, OutDev out,
-                         unsigned long long *hist_out, bool count_front, int blocks,
-                         unsigned long long idle_timeout, hipStream_t s);
+                         unsigned long long *hist_out, int hist_stride, bool count_front,
+                         int blocks, unsigned long long idle_timeout, hipStream_t s);
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, bool enum_bases,
                                  hipStream_t s);
-hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, hipStream_t s);
+hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool enumerate, hipStream_t s);

@@ -148,40 +148,69 @@ template <typename T>
 __device__ __forceinline__ T ld_acquire(T *p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Plain read of a value written by an earlier kernel on the same stream
+// (kernel boundaries already order it); no cache maintenance.
+template <typename T>
+__device__ __forceinline__ T ld_relaxed(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 template <typename T>
 __device__ __forceinline__ void st_release(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// -------------------------------------------------------------- decoding
-// Writes the k vertices of the chordless cycle C (label-space bitset) as
-// original ids, starting at the smallest original id and continuing towards
-// the smaller of its two cycle neighbours.  In an induced cycle every vertex
-// has exactly two neighbours inside C, so the walk is unique.
-template <int W>
-__device__ void write_cycle(const unsigned long long *sN, const int *sPerm, Bits<W> C, int k,
-                            int *dst) {
-  Bits<W> it = C;
-  int start = -1, best = 0x7fffffff;
-  while (bany(it)) {
-    int v = bpop_lowest(it);
-    int o = sPerm[v];
-    if (o < best) {
-      best = o;
-      start = v;
-    }
+__device__ __forceinline__ void st_system(unsigned int *p, unsigned int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// ------------------------------------------------------------ shards
+// Wavefront-wide inclusive scan of one value per lane (lane = shard); writes
+// pre[0] = 0 and pre[s + 1] = sum of shards 0..s.  Called by a whole
+// wavefront.
+__device__ __forceinline__ void shard_prefix(unsigned long long v, unsigned long long *pre) {
+  const int lane = lane_id();
+  unsigned long long x = v;
+#pragma unroll
+  for (int o = 1; o < CC_WAVE; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, CC_WAVE);
+    if (lane >= o) x += y;
   }
-  Bits<W> nb = band(row<W>(sN, start), C);
-  const int a = bany(nb) ? bpop_lowest(nb) : start;
-  const int b = bany(nb) ? bpop_lowest(nb) : a;
-  int cur = (sPerm[a] < sPerm[b]) ? a : b;
-  int prev = start;
-  dst[0] = best;
-  dst[1] = sPerm[cur];
+  pre[lane + 1] = x;
+  if (lane == 0) pre[0] = 0ull;
+}
+
+// Shard holding global element i (0 <= i < pre[CC_SHARDS]): the largest s
+// with pre[s] <= i, which is never an empty shard.
+__device__ __forceinline__ int shard_of(const unsigned long long *pre, unsigned long long i) {
+  int lo = 0, hi = CC_SHARDS;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// -------------------------------------------------------------- decoding
+// Writes the k vertices of a chordless cycle given as a bitset C over
+// original ids: it starts at the smallest id and continues towards the
+// smaller of that vertex's two cycle neighbours.  In an induced cycle every
+// vertex has exactly two neighbours inside C, so the walk is unique.
+// sNo holds the adjacency rows in original-id space.
+template <int W>
+__device__ void write_cycle(const unsigned long long *sNo, Bits<W> C, int k, int *dst) {
+  Bits<W> it = C;
+  const int start = bpop_lowest(it);
+  Bits<W> nb = band(row<W>(sNo, start), C);
+  const int first = bany(nb) ? bpop_lowest(nb) : start;  // C is always a cycle here
+  int prev = start, cur = first;
+  dst[0] = start;
+  dst[1] = first;
   for (int j = 2; j < k; ++j) {
-    Bits<W> nx = band(row<W>(sN, cur), bandnot(C, bsingle<W>(prev)));
-    const int nxt = bany(nx) ? bpop_lowest(nx) : start;  // C is always a cycle here
-    dst[j] = sPerm[nxt];
+    Bits<W> nx = band(row<W>(sNo, cur), bandnot(C, bsingle<W>(prev)));
+    const int nxt = bany(nx) ? bpop_lowest(nx) : start;
+    dst[j] = nxt;
     prev = cur;
     cur = nxt;
   }
@@ -199,12 +228,13 @@ __global__ void k_zero(unsigned int *p, size_t words) {
 // adjacency bitsets, computes the degree labelling (Section 2: repeatedly
 // take the remaining vertex of minimum remaining degree, smallest id on
 // ties; it gets the next label) with one wavefront holding two vertices per
-// lane, and writes the bitsets renumbered by label.
+// lane, and writes the bitsets renumbered by label plus the original ones.
 template <int W>
 __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vtx_off,
                                                 int n_single, const int *__restrict__ rp,
                                                 const int *__restrict__ ci,
                                                 unsigned long long *__restrict__ adj_out,
+                                                unsigned long long *__restrict__ adj_orig,
                                                 int *__restrict__ perm_out,
                                                 int *__restrict__ label_out,
                                                 unsigned int *__restrict__ status) {
@@ -306,6 +336,8 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
     perm_out[v0 + l] = v;
     label_out[v0 + v] = l;
     Bits<W> r = row<W>(sA, v);
+#pragma unroll
+    for (int k = 0; k < W; ++k) adj_orig[(size_t)(v0 + v) * W + k] = r.w[k];
     Bits<W> out = bzero<W>();
     while (bany(r)) out = bor(out, bsingle<W>(sLab[bpop_lowest(r)]));
 #pragma unroll
@@ -318,19 +350,24 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
 // Initial triplets and triangles (Algorithm 1's set T(G) and the triangles
 // of C; Algorithm 2 computes the same sets).  One block; each thread takes
 // (u, x) pairs with x a higher-labelled neighbour of u and scans the
-// neighbours y of u above x.
+// neighbours y of u above x.  Results are numbered with LDS counters and
+// dealt round-robin over the shards (item j -> shard j % CC_SHARDS, slot
+// j / CC_SHARDS), so every shard gets the same share.
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, Frontier f,
-                                                       OutDev out) {
+                                                       Stage st) {
   __shared__ unsigned long long sN[CC_MAXN * W];
   __shared__ int sPerm[CC_MAXN];
-  __shared__ unsigned long long sRed[CC_BLOCK / CC_WAVE];
+  __shared__ unsigned int sTrip, sTri;
   const int n = g.n;
   const int tid = threadIdx.x;
   for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
   for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
+  if (tid == 0) {
+    sTrip = 0u;
+    sTri = 0u;
+  }
   __syncthreads();
-  unsigned long long tri = 0;
   for (int idx = tid; idx < n * n; idx += CC_BLOCK) {
     const int u = idx / n, x = idx - u * n;
     const Bits<W> nu = row<W>(sN, u);
@@ -340,25 +377,26 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
     while (bany(ys)) {
       const int y = bpop_lowest(ys);
       if (btest(nx, y)) {
+        const unsigned j = atomicAdd(&sTri, 1u);
         if (ENUM) {
-          const unsigned long long slot = atomicAdd(&ctl->hist[3], 1ull);
-          const long long pos = (long long)slot * 3;
-          if ((long long)slot < out.cyc_cap && pos + 3 <= out.verts_cap) {
-            Bits<W> C = bor(bor(bsingle<W>(x), bsingle<W>(u)), bsingle<W>(y));
-            write_cycle<W>(sN, sPerm, C, 3, out.verts + pos);
-            out.offs[slot] = pos;
+          const unsigned long long slot = (j % CC_SHARDS) * st.cap_s + j / CC_SHARDS;
+          if (j / CC_SHARDS < st.cap_s) {
+            const Bits<W> C =
+                bor(bor(bsingle<W>(sPerm[x]), bsingle<W>(sPerm[u])), bsingle<W>(sPerm[y]));
+#pragma unroll
+            for (int k = 0; k < W; ++k) st.C[k * st.cap + slot] = C.w[k];
           }
-        } else {
-          ++tri;
         }
       } else {
-        const unsigned long long slot = atomicAdd(&ctl->count[3], 1ull);
-        if (slot < f.cap) {
+        const unsigned j = atomicAdd(&sTrip, 1u);
+        if (j / CC_SHARDS < f.cap_s) {
+          const unsigned long long slot = (j % CC_SHARDS) * f.cap_s + j / CC_SHARDS;
           const Bits<W> X = bor(nu, low_through<W>(u));
 #pragma unroll
           for (int k = 0; k < W; ++k) f.X[k * f.cap + slot] = X.w[k];
           if (ENUM) {
-            const Bits<W> S = bor(bor(bsingle<W>(x), bsingle<W>(u)), bsingle<W>(y));
+            const Bits<W> S =
+                bor(bor(bsingle<W>(sPerm[x]), bsingle<W>(sPerm[u])), bsingle<W>(sPerm[y]));
 #pragma unroll
             for (int k = 0; k < W; ++k) f.S[k * f.cap + slot] = S.w[k];
           }
@@ -367,173 +405,281 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
       }
     }
   }
-  if (!ENUM) {
-    tri = wave_sum_u64(tri);
-    if (lane_id() == 0) sRed[tid / CC_WAVE] = tri;
-    __syncthreads();
-    if (tid == 0) {
-      unsigned long long s = 0;
-      for (int i = 0; i < CC_BLOCK / CC_WAVE; ++i) s += sRed[i];
-      if (s) atomicAdd(&ctl->hist[3], s);
-    }
+  __syncthreads();
+  if (tid < CC_SHARDS) {
+    const unsigned s = tid;
+    ctl->count_sh[s][3] = sTrip > s ? (sTrip - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
+    ctl->hist_sh[s][3] = sTri > s ? (sTri - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
   }
 }
 
 // ------------------------------------------------------ breadth-first level
-// One level of Algorithm 3 over the frontier of paths with t vertices:
-// every path is expanded by one lane; closures are counted into hist[t+1]
-// (and written, enumerate mode); extensions are compacted into the next
-// frontier with one atomic per wavefront plus ballot/mbcnt ranks.  The
-// frontier size lives in device memory (count[t]), so the host launches the
-// level loop without reading anything back (Algorithm 4's fixed relaunches).
+// One level of Algorithm 3 over the frontier of paths with t vertices, plus
+// (enumerate mode) the decoding of the cycles with t vertices that the
+// previous level staged.
+//
+// Expansion: a block takes chunks of CC_BLOCK * CC_LEVEL_IPT consecutive
+// paths (one lane per path, CC_LEVEL_IPT rounds), counts the extensions and
+// closures of the chunk, and reserves room for all of them with one atomic
+// per chunk on its own shard's counters; each wavefront then owns a
+// contiguous sub-range and ranks its lanes inside it with ballot/mbcnt, so
+// the stores of a round land on consecutive slots.  Closures of paths with t
+// vertices are cycles with t+1 vertices: counted in hist_sh[.][t+1] and, when
+// enumerating, staged as vertex bitsets for the next level to decode.
+//
+// Decoding: cycle g of length t (global order: shards in turn) goes to
+// output index cum_c[t-1] + g, vertices at cum_v[t-1] + g * t, so the output
+// is ordered by length.  Every lane decodes one cycle.
+//
+// The frontier size lives in device memory, so the host launches the level
+// loop without reading anything back (Algorithm 4's fixed relaunches); if
+// `host_done` is given, the kernel also tells the host when the levels have
+// nothing left to do so that it can stop launching them.
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Frontier fin,
-                                                    Frontier fout, OutDev out, int t,
-                                                    int forced_level) {
+                                                    Frontier fout, Stage sprev, Stage scur,
+                                                    OutDev out, int t, int forced_level,
+                                                    unsigned int *host_done) {
+  constexpr int IPT = CC_LEVEL_IPT;
+  constexpr int NW = CC_BLOCK / CC_WAVE;
   __shared__ unsigned long long sN[CC_MAXN * W];
+  __shared__ unsigned long long sNo[ENUM ? CC_MAXN * W : 1];
   __shared__ int sPerm[ENUM ? CC_MAXN : 1];
-  __shared__ unsigned long long sRed[CC_BLOCK / CC_WAVE];
-  __shared__ long long sBase[2];
-  if (ld_acquire(&ctl->mode) != 0) return;
-  const unsigned long long cnt = ctl->count[t];
-  if (cnt > fin.cap) {
-    // The previous level produced more paths than fit: hand its (intact)
-    // input frontier to the depth-first kernel; that level's closures and
-    // path count are already recorded.
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ctl->skip_first = 1;
-      ctl->switch_level = t - 1;
-      ctl->bfs_max_len = t;
-      __threadfence();
-      st_release(&ctl->mode, 1);
-    }
-    return;
-  }
-  if (t == forced_level) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      ctl->skip_first = 0;
-      ctl->switch_level = t;
-      ctl->bfs_max_len = t;
-      __threadfence();
-      st_release(&ctl->mode, 1);
-    }
-    return;
-  }
-  if (cnt == 0) return;
-  const int n = g.n;
+  __shared__ unsigned long long sPre[CC_SHARDS + 1];
+  __shared__ unsigned long long sPreH[ENUM ? CC_SHARDS + 1 : 1];
+  __shared__ unsigned int sWaveExt[NW];
+  __shared__ unsigned int sWaveClos[NW];
+  __shared__ unsigned long long sExtBase, sClosBase;
+  __shared__ unsigned long long sRed[NW];
+  __shared__ unsigned long long sCum[2];
+  __shared__ int sFlags;
   const int tid = threadIdx.x;
-  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
-  if (ENUM) {
-    for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
-    if (tid == 0) {
-      long long cb = 0, vb = 0;
-      for (int j = 3; j <= t; ++j) {
-        cb += (long long)ctl->hist[j];
-        vb += (long long)ctl->hist[j] * j;
+  const int lane = lane_id();
+  const int wave = tid / CC_WAVE;
+  if (ld_relaxed(&ctl->mode) != 0) {
+    if (host_done && blockIdx.x == 0 && tid == 0) st_system(host_done, (unsigned)t);
+    return;
+  }
+  const int n = g.n;
+  if (wave == 0) {
+    const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][t]);
+    shard_prefix(c, sPre);
+    const bool ovf = c > fin.cap_s;
+    bool hovf = false;
+    if (ENUM) {
+      const unsigned long long h = ld_relaxed(&ctl->hist_sh[lane][t]);
+      shard_prefix(h, sPreH);
+      hovf = h > sprev.cap_s;
+    }
+    const unsigned long long mo = wave_ballot(ovf), mh = wave_ballot(hovf);
+    if (lane == 0) {
+      sFlags = (mo ? 1 : 0) | (mh ? 2 : 0);
+      if (ENUM) {
+        sCum[0] = ld_relaxed(&ctl->cum_c[t - 1]);
+        sCum[1] = ld_relaxed(&ctl->cum_v[t - 1]);
       }
-      sBase[0] = cb;
-      sBase[1] = vb;
     }
   }
+  if (ENUM) {
+    for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
+  }
+  __syncthreads();
+  const int flags = sFlags;
+  const unsigned long long cnt = sPre[CC_SHARDS];
+
+  // ---- decode the cycles with t vertices staged by the previous level
+  if (ENUM && !(flags & 2)) {
+    const unsigned long long htot = sPreH[CC_SHARDS];
+    const long long cb = (long long)sCum[0], vb = (long long)sCum[1];
+    for (unsigned long long gi = (unsigned long long)blockIdx.x * CC_BLOCK + tid; gi < htot;
+         gi += (unsigned long long)gridDim.x * CC_BLOCK) {
+      const int s = shard_of(sPreH, gi);
+      const unsigned long long e = (unsigned long long)s * sprev.cap_s + (gi - sPreH[s]);
+      Bits<W> C;
+#pragma unroll
+      for (int w = 0; w < W; ++w) C.w[w] = sprev.C[w * sprev.cap + e];
+      const long long cyc = cb + (long long)gi;
+      const long long pos = vb + (long long)gi * t;
+      if (cyc < out.cyc_cap && pos + t <= out.verts_cap) {
+        write_cycle<W>(sNo, C, t, out.verts + pos);
+        out.offs[cyc] = pos;
+      }
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      ctl->cum_c[t] = (unsigned long long)cb + htot;
+      ctl->cum_v[t] = (unsigned long long)vb + htot * (unsigned long long)t;
+    }
+  }
+
+  // ---- hand over to the depth-first kernel when needed
+  int sw_level = 0, sw_skip = 0, sw_max = 0;
+  if (flags & 2) {
+    // The previous level staged more cycles than fit: its paths are handed
+    // over again and everything from them on is recounted.
+    sw_level = t - 1;
+    sw_skip = CC_SKIP_FRONT;
+    sw_max = t - 1;
+  } else if (flags & 1) {
+    // The previous level produced more paths than fit: hand its (intact)
+    // input frontier over; that level's closures and path count are
+    // already recorded.
+    sw_level = t - 1;
+    sw_skip = CC_SKIP_FRONT | CC_SKIP_CLOSE;
+    sw_max = t;
+  } else if (t == forced_level) {
+    sw_level = t;
+    sw_skip = 0;
+    sw_max = t;
+  }
+  if (sw_level) {
+    if (blockIdx.x == 0 && tid == 0) {
+      ctl->skip = sw_skip;
+      ctl->switch_level = sw_level;
+      ctl->bfs_max_len = sw_max;
+      __threadfence();
+      st_release(&ctl->mode, 1);
+      if (host_done) st_system(host_done, (unsigned)t);
+    }
+    return;
+  }
+  if (cnt == 0) {
+    if (host_done && blockIdx.x == 0 && tid == 0) st_system(host_done, (unsigned)t);
+    return;
+  }
+  const unsigned long long chunk = (unsigned long long)CC_BLOCK * IPT;
+  // Blocks without a chunk leave before staging anything more.
+  if ((unsigned long long)blockIdx.x * chunk >= cnt) return;
+  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+  if (ENUM)
+    for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
   __syncthreads();
   if (blockIdx.x == 0 && tid == 0) {
     ctl->front[t] = cnt;
     atomicMax(&ctl->peak, cnt);
   }
-  const int lane = lane_id();
-  const unsigned long long nwaves = (unsigned long long)gridDim.x * (CC_BLOCK / CC_WAVE);
-  const unsigned long long wv = (unsigned long long)blockIdx.x * (CC_BLOCK / CC_WAVE) + tid / CC_WAVE;
   const int k = t + 1;
+  const int osh = blockIdx.x % CC_SHARDS;  // this block's output shard
   unsigned long long acc = 0;
-  for (unsigned long long b0 = wv * CC_WAVE; b0 < cnt; b0 += nwaves * CC_WAVE) {
-    const unsigned long long i = b0 + lane;
-    const bool valid = i < cnt;
-    Bits<W> X = bzero<W>(), S = bzero<W>();
-    int v1 = 0, vt = 0;
-    if (valid) {
+  for (unsigned long long c0 = (unsigned long long)blockIdx.x * chunk; c0 < cnt;
+       c0 += (unsigned long long)gridDim.x * chunk) {
+    Bits<W> Xn[IPT], Sv[IPT], clos[IPT], ext[IPT];
+    int v1[IPT];
+    unsigned my_ext = 0, my_clos = 0;
 #pragma unroll
-      for (int w = 0; w < W; ++w) X.w[w] = fin.X[w * fin.cap + i];
-      if (ENUM) {
+    for (int j = 0; j < IPT; ++j) {
+      const unsigned long long i = c0 + (unsigned long long)j * CC_BLOCK + tid;
+      const bool valid = i < cnt;
+      Bits<W> X = bzero<W>();
+      Sv[j] = bzero<W>();
+      int a = 0, b = 0;
+      if (valid) {
+        const int s = shard_of(sPre, i);
+        const unsigned long long e = (unsigned long long)s * fin.cap_s + (i - sPre[s]);
 #pragma unroll
-        for (int w = 0; w < W; ++w) S.w[w] = fin.S[w * fin.cap + i];
+        for (int w = 0; w < W; ++w) X.w[w] = fin.X[w * fin.cap + e];
+        if (ENUM) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) Sv[j].w[w] = fin.S[w * fin.cap + e];
+        }
+        const unsigned vv = fin.vv[e];
+        a = vv & 0xffu;
+        b = vv >> 8;
       }
-      const unsigned vv = fin.vv[i];
-      v1 = vv & 0xffu;
-      vt = vv >> 8;
+      const Bits<W> nvt = row<W>(sN, b);
+      const Bits<W> nv1 = row<W>(sN, a);
+      const Bits<W> cand = bandnot(nvt, X);
+      clos[j] = valid ? band(cand, nv1) : bzero<W>();
+      ext[j] = valid ? bandnot(cand, nv1) : bzero<W>();
+      Xn[j] = bor(X, nvt);
+      v1[j] = a;
+      my_ext += (unsigned)bpop(ext[j]);
+      my_clos += (unsigned)bpop(clos[j]);
     }
-    const Bits<W> nvt = row<W>(sN, vt);
-    const Bits<W> nv1 = row<W>(sN, v1);
-    const Bits<W> cand = bandnot(nvt, X);
-    Bits<W> clos = band(cand, nv1);
-    Bits<W> ext = bandnot(cand, nv1);
-    if (!valid) {
-      clos = bzero<W>();
-      ext = bzero<W>();
+    if (!ENUM) acc += my_clos;
+    const unsigned we = wave_sum_u32(my_ext);
+    const unsigned wc = ENUM ? wave_sum_u32(my_clos) : 0u;
+    if (lane == 0) {
+      sWaveExt[wave] = we;
+      sWaveClos[wave] = wc;
     }
-    if (ENUM) {
-      const unsigned tot = wave_sum_u32((unsigned)bpop(clos));
-      if (tot) {
-        unsigned long long slot0 = 0;
-        if (lane == 0) slot0 = atomicAdd(&ctl->hist[k], (unsigned long long)tot);
-        slot0 = bcast_u64(slot0);
-        unsigned long long off = 0;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned te = 0, tc = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        te += sWaveExt[w];
+        tc += sWaveClos[w];
+      }
+      sExtBase = te ? atomicAdd(&ctl->count_sh[osh][k], (unsigned long long)te) : 0ull;
+      sClosBase = (ENUM && tc) ? atomicAdd(&ctl->hist_sh[osh][k], (unsigned long long)tc) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long ebase = sExtBase, cbase = sClosBase;
+    for (int w = 0; w < wave; ++w) {
+      ebase += sWaveExt[w];
+      cbase += sWaveClos[w];
+    }
+    if (we) {
+      unsigned long long off = 0;
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        Bits<W> e = ext[j];
         while (true) {
-          const bool has = bany(clos);
+          const bool has = bany(e);
           const unsigned long long mask = wave_ballot(has);
           if (!mask) break;
           if (has) {
-            const int v = bpop_lowest(clos);
-            const unsigned long long slot = slot0 + off + lanes_below(mask);
-            const long long cyc = sBase[0] + (long long)slot;
-            const long long pos = sBase[1] + (long long)slot * k;
-            if (cyc < out.cyc_cap && pos + k <= out.verts_cap) {
-              write_cycle<W>(sN, sPerm, bor(S, bsingle<W>(v)), k, out.verts + pos);
-              out.offs[cyc] = pos;
+            const int v = bpop_lowest(e);
+            const unsigned long long slot = ebase + off + lanes_below(mask);
+            if (slot < fout.cap_s) {
+              const unsigned long long o = (unsigned long long)osh * fout.cap_s + slot;
+#pragma unroll
+              for (int w = 0; w < W; ++w) fout.X[w * fout.cap + o] = Xn[j].w[w];
+              if (ENUM) {
+                const Bits<W> Sn = bor(Sv[j], bsingle<W>(sPerm[v]));
+#pragma unroll
+                for (int w = 0; w < W; ++w) fout.S[w * fout.cap + o] = Sn.w[w];
+              }
+              fout.vv[o] = (unsigned short)(v1[j] | (v << 8));
             }
           }
           off += __popcll(mask);
         }
       }
-    } else {
-      acc += (unsigned long long)bpop(clos);
     }
-    const unsigned tot = wave_sum_u32((unsigned)bpop(ext));
-    if (tot) {
-      unsigned long long slot0 = 0;
-      if (lane == 0) slot0 = atomicAdd(&ctl->count[k], (unsigned long long)tot);
-      slot0 = bcast_u64(slot0);
-      const Bits<W> Xn = bor(X, nvt);
+    if (ENUM && wc) {
       unsigned long long off = 0;
-      while (true) {
-        const bool has = bany(ext);
-        const unsigned long long mask = wave_ballot(has);
-        if (!mask) break;
-        if (has) {
-          const int v = bpop_lowest(ext);
-          const unsigned long long slot = slot0 + off + lanes_below(mask);
-          if (slot < fout.cap) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) fout.X[w * fout.cap + slot] = Xn.w[w];
-            if (ENUM) {
-              const Bits<W> Sn = bor(S, bsingle<W>(v));
+      for (int j = 0; j < IPT; ++j) {
+        Bits<W> c = clos[j];
+        while (true) {
+          const bool has = bany(c);
+          const unsigned long long mask = wave_ballot(has);
+          if (!mask) break;
+          if (has) {
+            const int v = bpop_lowest(c);
+            const unsigned long long slot = cbase + off + lanes_below(mask);
+            if (slot < scur.cap_s) {
+              const unsigned long long o = (unsigned long long)osh * scur.cap_s + slot;
+              const Bits<W> C = bor(Sv[j], bsingle<W>(sPerm[v]));
 #pragma unroll
-              for (int w = 0; w < W; ++w) fout.S[w * fout.cap + slot] = Sn.w[w];
+              for (int w = 0; w < W; ++w) scur.C[w * scur.cap + o] = C.w[w];
             }
-            fout.vv[slot] = (unsigned short)(v1 | (v << 8));
           }
+          off += __popcll(mask);
         }
-        off += __popcll(mask);
       }
     }
+    __syncthreads();  // the per-wavefront totals are rewritten by the next chunk
   }
   if (!ENUM) {
     acc = wave_sum_u64(acc);
-    if (lane == 0) sRed[tid / CC_WAVE] = acc;
+    if (lane == 0) sRed[wave] = acc;
     __syncthreads();
     if (tid == 0) {
-      unsigned long long s = 0;
-      for (int i = 0; i < CC_BLOCK / CC_WAVE; ++i) s += sRed[i];
-      if (s) atomicAdd(&ctl->hist[k], s);
+      unsigned long long sum = 0;
+      for (int i = 0; i < NW; ++i) sum += sRed[i];
+      if (sum) atomicAdd(&ctl->hist_sh[osh][k], sum);
     }
   }
 }
@@ -543,100 +689,113 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
 // (each up to CC_CHUNK paths) with one sequence number per cell.  Only lane
 // 0 of a wavefront touches the cursors; the whole wavefront moves the data.
 __device__ long long q_reserve_push(CcCtl *ctl, const DfsWork &wk) {
-  unsigned long long pos = ld_acquire(&ctl->q_tail);
+  unsigned long long pos = ld_relaxed(&ctl->q_tail);
   for (int attempt = 0; attempt < 32; ++attempt) {
     const unsigned long long cell = pos & (wk.qcap - 1);
     const unsigned long long seq = ld_acquire(&wk.qseq[cell]);
     const long long diff = (long long)(seq - pos);
     if (diff == 0) {
       if (atomicCAS(&ctl->q_tail, pos, pos + 1) == pos) return (long long)pos;
-      pos = ld_acquire(&ctl->q_tail);
+      pos = ld_relaxed(&ctl->q_tail);
     } else if (diff < 0) {
       return -1;  // full
     } else {
-      pos = ld_acquire(&ctl->q_tail);
+      pos = ld_relaxed(&ctl->q_tail);
     }
   }
   return -1;
 }
 
 __device__ long long q_reserve_pop(CcCtl *ctl, const DfsWork &wk) {
-  unsigned long long pos = ld_acquire(&ctl->q_head);
+  unsigned long long pos = ld_relaxed(&ctl->q_head);
   for (int attempt = 0; attempt < 32; ++attempt) {
     const unsigned long long cell = pos & (wk.qcap - 1);
     const unsigned long long seq = ld_acquire(&wk.qseq[cell]);
     const long long diff = (long long)(seq - (pos + 1));
     if (diff == 0) {
       if (atomicCAS(&ctl->q_head, pos, pos + 1) == pos) return (long long)pos;
-      pos = ld_acquire(&ctl->q_head);
+      pos = ld_relaxed(&ctl->q_head);
     } else if (diff < 0) {
       return -1;  // empty
     } else {
-      pos = ld_acquire(&ctl->q_head);
+      pos = ld_relaxed(&ctl->q_head);
     }
   }
   return -1;
 }
 
 __device__ __forceinline__ bool work_visible(CcCtl *ctl, unsigned long long nroots) {
-  if (ld_acquire(&ctl->root_cursor) < nroots) return true;
-  const unsigned long long h = ld_acquire(&ctl->q_head);
-  const unsigned long long tl = ld_acquire(&ctl->q_tail);
+  if (ld_relaxed(&ctl->root_cursor) < nroots) return true;
+  const unsigned long long h = ld_relaxed(&ctl->q_head);
+  const unsigned long long tl = ld_relaxed(&ctl->q_tail);
   return tl > h;
 }
 
-// Depth-first continuation (north of the memory budget).  Each wavefront
-// owns a LIFO stack of open paths in device memory; a step pops up to 64
-// paths (one per lane), expands them exactly like a breadth-first level and
-// pushes the extensions back, so memory grows with depth, not with the
-// frontier.  Work enters from the handed-over frontier (claimed in chunks of
-// 64 with an atomic cursor) and from chunks that busy wavefronts donate from
-// the bottom of their stacks when others are idle.  Termination: a
-// wavefront leaves only after it saw no busy wavefront and then no visible
-// work; a wavefront holding paths is always counted busy.
+// Depth-first continuation (beyond the memory budget).  Each wavefront owns
+// a LIFO stack of open paths in device memory; a step pops up to 64 paths
+// (one per lane), expands them exactly like a breadth-first level and pushes
+// the extensions back, so memory grows with depth, not with the frontier.
+// Work enters from the handed-over frontier, which wavefronts claim in
+// private ranges of CC_ROOT_CLAIM paths (one atomic per range) and consume 64
+// at a time whenever their stack is empty, and from chunks that busy
+// wavefronts donate (from the end of their range, else from the bottom of
+// their stack) when others are idle.  Termination: a wavefront leaves only
+// after it saw no busy wavefront and then no visible work; a wavefront that
+// holds paths is always counted busy.  Idle wavefronts back off
+// exponentially so that their polling does not load the memory system.
+// Cycle counts go to hist_out[(block % CC_SHARDS) * hist_stride + k].
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Frontier f0,
                                                   Frontier f1, DfsWork wk0, DfsWork wk1,
                                                   OutDev out, unsigned long long *hist_out,
-                                                  int count_front,
+                                                  int hist_stride, int count_front,
                                                   unsigned long long idle_timeout) {
   __shared__ unsigned long long sN[CC_MAXN * W];
-  __shared__ int sPerm[ENUM ? CC_MAXN : 1];
+  __shared__ unsigned long long sNo[ENUM ? CC_MAXN * W : 1];
+  __shared__ int sPerm[CC_MAXN];
   __shared__ unsigned long long sHist[CC_HSLOTS];
   __shared__ unsigned long long sFront[CC_HSLOTS];
   __shared__ long long sCb[ENUM ? CC_HSLOTS : 1];
   __shared__ long long sVb[ENUM ? CC_HSLOTS : 1];
-  if (ld_acquire(&ctl->mode) == 0) return;
+  __shared__ unsigned long long sPre[CC_SHARDS + 1];
+  if (ld_relaxed(&ctl->mode) == 0) return;
   const int L = ctl->switch_level;
-  const bool skip = ctl->skip_first != 0;
+  const int skipbits = ctl->skip;
   const Frontier roots = (L & 1) ? f1 : f0;
   const DfsWork wk = (L & 1) ? wk0 : wk1;  // the buffer not holding the roots
-  const unsigned long long nroots = min(ctl->count[L], roots.cap);
   const int n = g.n;
   const int tid = threadIdx.x;
+  const int lane = lane_id();
+  if (tid < CC_WAVE) {
+    const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][L]);
+    shard_prefix(c <= roots.cap_s ? c : roots.cap_s, sPre);
+  }
   for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+  for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
   for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
     sHist[i] = 0ull;
     sFront[i] = 0ull;
   }
   if (ENUM) {
-    for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
+    for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
     for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
       sCb[i] = (long long)ctl->len_cbase[i];
       sVb[i] = (long long)ctl->len_vbase[i];
     }
   }
   __syncthreads();
+  const unsigned long long nroots = sPre[CC_SHARDS];
 
-  const int lane = lane_id();
   const unsigned long long wid = (unsigned long long)blockIdx.x * (CC_BLOCK / CC_WAVE) + tid / CC_WAVE;
   const unsigned long long cap = wk.cap_w;
   unsigned long long *stX = wk.stackX + wid * W * cap;
   unsigned long long *stS = ENUM ? wk.stackS + wid * W * cap : nullptr;
   unsigned int *stM = wk.stackM + wid * cap;
   const unsigned long long maxc = (unsigned long long)max(wk.max_children, 1);
+  const unsigned int root_meta = ((unsigned)L << 16) | (1u << 24);
 
-  unsigned long long bot = 0, top = 0;
+  unsigned long long bot = 0, top = 0;     // live stack entries [bot, top)
+  unsigned long long r_lo = 0, r_hi = 0;   // private range of handed-over paths
   unsigned long long steps = 0, batches = 0, donated = 0;
   if (lane == 0) atomicAdd(&ctl->busy, 1);
 
@@ -644,6 +803,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     Bits<W> X = bzero<W>(), S = bzero<W>();
     unsigned int m = 0;
     bool valid = false;
+    bool have = false;
     if (top > bot) {
       // Pop up to 64 paths from the top, keeping room for their extensions.
       unsigned long long kk = min(top - bot, (unsigned long long)CC_CHUNK);
@@ -662,95 +822,102 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       }
       top = start;
       if (top == bot) top = bot = 0;
+      have = true;
     } else {
-      bool got = false;
-      // 1. the handed-over frontier
-      if (ld_acquire(&ctl->root_cursor) < nroots) {
-        unsigned long long c = 0;
-        if (lane == 0) c = atomicAdd(&ctl->root_cursor, (unsigned long long)CC_CHUNK);
+      if (r_lo >= r_hi) {
+        unsigned long long c = ~0ull;
+        if (lane == 0 && ld_relaxed(&ctl->root_cursor) < nroots)
+          c = atomicAdd(&ctl->root_cursor, (unsigned long long)CC_ROOT_CLAIM);
         c = bcast_u64(c);
         if (c < nroots) {
-          const unsigned long long kk = min(nroots - c, (unsigned long long)CC_CHUNK);
-          valid = (unsigned long long)lane < kk;
-          if (valid) {
-            const unsigned long long i = c + lane;
-#pragma unroll
-            for (int w = 0; w < W; ++w) X.w[w] = roots.X[w * roots.cap + i];
-            if (ENUM) {
-#pragma unroll
-              for (int w = 0; w < W; ++w) S.w[w] = roots.S[w * roots.cap + i];
-            }
-            const unsigned vv = roots.vv[i];
-            m = (vv & 0xffu) | ((vv >> 8) << 8) | ((unsigned)L << 16) | (1u << 24);
-          }
-          got = true;
+          r_lo = c;
+          r_hi = min(c + (unsigned long long)CC_ROOT_CLAIM, nroots);
         }
       }
-      // 2. a donated chunk
-      if (!got) {
-        long long pos = -1;
-        if (lane == 0) pos = q_reserve_pop(ctl, wk);
-        pos = bcast_i64(pos);
-        if (pos >= 0) {
-          const unsigned long long cell = (unsigned long long)pos & (wk.qcap - 1);
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          const unsigned kk = wk.qN[cell];
-          valid = (unsigned)lane < kk;
-          if (valid) {
-            const unsigned long long base = cell * CC_CHUNK + lane;
+      if (r_lo < r_hi) {
+        const unsigned long long kk = min(r_hi - r_lo, (unsigned long long)CC_CHUNK);
+        valid = (unsigned long long)lane < kk;
+        if (valid) {
+          const unsigned long long i = r_lo + lane;
+          const int s = shard_of(sPre, i);
+          const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
 #pragma unroll
-            for (int w = 0; w < W; ++w) X.w[w] = wk.qX[(cell * W + w) * CC_CHUNK + lane];
-            if (ENUM) {
+          for (int w = 0; w < W; ++w) X.w[w] = roots.X[w * roots.cap + e];
+          if (ENUM) {
 #pragma unroll
-              for (int w = 0; w < W; ++w) S.w[w] = wk.qS[(cell * W + w) * CC_CHUNK + lane];
-            }
-            m = wk.qM[base];
+            for (int w = 0; w < W; ++w) S.w[w] = roots.S[w * roots.cap + e];
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          if (lane == 0) st_release(&wk.qseq[cell], (unsigned long long)pos + wk.qcap);
-          got = true;
+          m = (unsigned)roots.vv[e] | root_meta;
         }
+        r_lo += kk;
+        have = true;
       }
-      // 3. nothing anywhere: wait as idle, or leave
-      if (!got) {
+    }
+    if (!have) {
+      // a donated chunk
+      long long pos = -1;
+      if (lane == 0) pos = q_reserve_pop(ctl, wk);
+      pos = bcast_i64(pos);
+      if (pos >= 0) {
+        const unsigned long long cell = (unsigned long long)pos & (wk.qcap - 1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const unsigned kk = wk.qN[cell];
+        valid = (unsigned)lane < kk;
+        if (valid) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) X.w[w] = wk.qX[(cell * W + w) * CC_CHUNK + lane];
+          if (ENUM) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) S.w[w] = wk.qS[(cell * W + w) * CC_CHUNK + lane];
+          }
+          m = wk.qM[cell * CC_CHUNK + lane];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (lane == 0) st_release(&wk.qseq[cell], (unsigned long long)pos + wk.qcap);
+        have = true;
+      }
+    }
+    if (!have) {
+      // nothing anywhere: wait as idle, or leave
+      if (lane == 0) {
+        atomicSub(&ctl->busy, 1);
+        atomicAdd(&ctl->idle, 1);
+      }
+      bool leave = false;
+      const unsigned long long t0 = wall_clock64();
+      int backoff = 1;
+      while (true) {
+        for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(64);
+        backoff = min(backoff * 2, 64);
+        int flag = 0;  // 1: work seen, 2: leave, 3: gave up waiting
         if (lane == 0) {
-          atomicSub(&ctl->busy, 1);
-          atomicAdd(&ctl->idle, 1);
+          if (work_visible(ctl, nroots)) {
+            flag = 1;
+          } else if (ld_acquire(&ctl->busy) == 0) {
+            flag = work_visible(ctl, nroots) ? 1 : 2;
+          } else if (wall_clock64() - t0 > idle_timeout) {
+            flag = 3;
+          }
         }
-        bool leave = false;
-        const unsigned long long t0 = wall_clock64();
-        while (true) {
-          __builtin_amdgcn_s_sleep(8);
-          int flag = 0;  // 1: work seen, 2: leave
+        flag = __shfl(flag, 0, CC_WAVE);
+        if (flag == 1) {
           if (lane == 0) {
-            if (work_visible(ctl, nroots)) {
-              flag = 1;
-            } else if (ld_acquire(&ctl->busy) == 0) {
-              flag = work_visible(ctl, nroots) ? 1 : 2;
-            } else if (wall_clock64() - t0 > idle_timeout) {
-              flag = 3;
-            }
+            atomicAdd(&ctl->busy, 1);
+            atomicSub(&ctl->idle, 1);
           }
-          flag = __shfl(flag, 0, CC_WAVE);
-          if (flag == 1) {
-            if (lane == 0) {
-              atomicAdd(&ctl->busy, 1);
-              atomicSub(&ctl->idle, 1);
-            }
-            break;
-          }
-          if (flag >= 2) {
-            if (lane == 0) {
-              atomicSub(&ctl->idle, 1);
-              if (flag == 3) atomicOr(&ctl->status, CC_DEV_IDLE_TIMEOUT);
-            }
-            leave = true;
-            break;
-          }
+          break;
         }
-        if (leave) break;
-        continue;
+        if (flag >= 2) {
+          if (lane == 0) {
+            atomicSub(&ctl->idle, 1);
+            if (flag == 3) atomicOr(&ctl->status, CC_DEV_IDLE_TIMEOUT);
+          }
+          leave = true;
+          break;
+        }
       }
+      if (leave) break;
+      continue;
     }
 
     // ---- expand the batch (one path per lane)
@@ -758,7 +925,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     const int v1 = m & 0xffu;
     const int vt = (m >> 8) & 0xffu;
     const int t = (m >> 16) & 0xffu;
-    const bool first = valid && (m >> 24) && skip;
+    const bool root = (m >> 24) != 0;
+    const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
+    const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
     const Bits<W> nvt = row<W>(sN, vt);
     const Bits<W> nv1 = row<W>(sN, v1);
     const Bits<W> cand = bandnot(nvt, X);
@@ -768,8 +937,17 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       clos = bzero<W>();
       ext = bzero<W>();
     }
-    if (valid && !first) {
-      if (count_front) atomicAdd(&sFront[t], 1ull);
+    if (count_front) {
+      // paths expanded, per length: one LDS add per distinct length
+      unsigned long long act = wave_ballot(count_path);
+      while (act) {
+        const int t0 = __shfl(t, (int)(__ffsll((long long)act) - 1), CC_WAVE);
+        const unsigned long long same = act & wave_ballot(t == t0);
+        if (lane == 0) atomicAdd(&sFront[t0], (unsigned long long)__popcll(same));
+        act &= ~same;
+      }
+    }
+    if (count_close) {
       const int c = bpop(clos);
       if (c) {
         if (hist_out) atomicAdd(&sHist[t + 1], (unsigned long long)c);
@@ -782,7 +960,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
             const long long cyc = sCb[k] + (long long)(slot0 + j);
             const long long pos = sVb[k] + (long long)(slot0 + j) * k;
             if (cyc < out.cyc_cap && pos + k <= out.verts_cap) {
-              write_cycle<W>(sN, sPerm, bor(S, bsingle<W>(v)), k, out.verts + pos);
+              write_cycle<W>(sNo, bor(S, bsingle<W>(sPerm[v])), k, out.verts + pos);
               out.offs[cyc] = pos;
             }
           }
@@ -833,7 +1011,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
 #pragma unroll
             for (int w = 0; w < W; ++w) stX[w * cap + i] = Xn.w[w];
             if (ENUM) {
-              const Bits<W> Sn = bor(S, bsingle<W>(v));
+              const Bits<W> Sn = bor(S, bsingle<W>(sPerm[v]));
 #pragma unroll
               for (int w = 0; w < W; ++w) stS[w * cap + i] = Sn.w[w];
             }
@@ -845,11 +1023,14 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       }
     }
 
-    // ---- donate the oldest chunk when other wavefronts are idle
+    // ---- donate a chunk when other wavefronts are idle: the end of the
+    // private range first, else the oldest (shallowest) stack entries
     ++steps;
-    if ((steps % (unsigned long long)wk.donate_check) == 0 && top - bot >= 2 * CC_CHUNK) {
+    const bool range_big = r_hi - r_lo >= 2 * CC_CHUNK;
+    if ((steps % (unsigned long long)wk.donate_check) == 0 &&
+        (range_big || top - bot >= 2 * CC_CHUNK)) {
       int idle = 0;
-      if (lane == 0) idle = ld_acquire(&ctl->idle);
+      if (lane == 0) idle = ld_relaxed(&ctl->idle);
       idle = __shfl(idle, 0, CC_WAVE);
       if (idle > 0) {
         long long pos = -1;
@@ -857,18 +1038,41 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         pos = bcast_i64(pos);
         if (pos >= 0) {
           const unsigned long long cell = (unsigned long long)pos & (wk.qcap - 1);
-          const unsigned long long i = bot + lane;
+          Bits<W> dX, dS = bzero<W>();
+          unsigned int dm;
+          if (range_big) {
+            const unsigned long long i = r_hi - CC_CHUNK + lane;
+            const int s = shard_of(sPre, i);
+            const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
 #pragma unroll
-          for (int w = 0; w < W; ++w) wk.qX[(cell * W + w) * CC_CHUNK + lane] = stX[w * cap + i];
+            for (int w = 0; w < W; ++w) dX.w[w] = roots.X[w * roots.cap + e];
+            if (ENUM) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) dS.w[w] = roots.S[w * roots.cap + e];
+            }
+            dm = (unsigned)roots.vv[e] | root_meta;
+            r_hi -= CC_CHUNK;
+          } else {
+            const unsigned long long i = bot + lane;
+#pragma unroll
+            for (int w = 0; w < W; ++w) dX.w[w] = stX[w * cap + i];
+            if (ENUM) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) dS.w[w] = stS[w * cap + i];
+            }
+            dm = stM[i];
+            bot += CC_CHUNK;
+          }
+#pragma unroll
+          for (int w = 0; w < W; ++w) wk.qX[(cell * W + w) * CC_CHUNK + lane] = dX.w[w];
           if (ENUM) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) wk.qS[(cell * W + w) * CC_CHUNK + lane] = stS[w * cap + i];
+            for (int w = 0; w < W; ++w) wk.qS[(cell * W + w) * CC_CHUNK + lane] = dS.w[w];
           }
-          wk.qM[cell * CC_CHUNK + lane] = stM[i];
+          wk.qM[cell * CC_CHUNK + lane] = dm;
           if (lane == 0) wk.qN[cell] = CC_CHUNK;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
           if (lane == 0) st_release(&wk.qseq[cell], (unsigned long long)pos + 1ull);
-          bot += CC_CHUNK;
           ++donated;
         }
       }
@@ -880,24 +1084,51 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     if (donated) atomicAdd(&ctl->donations, donated);
   }
   __syncthreads();
+  unsigned long long *hdst = hist_out ? hist_out + (size_t)(blockIdx.x % CC_SHARDS) * hist_stride
+                                      : nullptr;
   for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
-    if (hist_out && sHist[i]) atomicAdd(&hist_out[i], sHist[i]);
+    if (hdst && sHist[i]) atomicAdd(&hdst[i], sHist[i]);
     if (count_front && sFront[i]) atomicAdd(&ctl->front[i], sFront[i]);
   }
 }
 
+// Per-length cycle totals: lengths up to bfs_max_len come from the
+// breadth-first levels (summed over shards); longer ones, when the
+// depth-first kernel took over in enumerate mode, from its counting pass.
+// Count mode accumulates everything in the shards.  One block.
+__device__ void length_totals(CcCtl *ctl, bool enumerate, unsigned long long *sTot) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < CC_HSLOTS; k += blockDim.x) sTot[k] = 0ull;
+  __syncthreads();
+  const bool dfs = ld_relaxed(&ctl->mode) != 0;
+  const int kmax = (enumerate && dfs) ? ctl->bfs_max_len : CC_HSLOTS - 1;
+  for (int p = tid; p < CC_SHARDS * CC_HSLOTS; p += blockDim.x) {
+    const int s = p / CC_HSLOTS, k = p - s * CC_HSLOTS;
+    if (k <= kmax) {
+      const unsigned long long v = ld_relaxed(&ctl->hist_sh[s][k]);
+      if (v) atomicAdd(&sTot[k], v);
+    }
+  }
+  __syncthreads();
+  if (enumerate && dfs)
+    for (int k = tid; k < CC_HSLOTS; k += blockDim.x)
+      if (k > kmax) sTot[k] = ctl->dfs_hist[k];
+  __syncthreads();
+}
+
 // Resets the depth-first coordination state (and, for the writing pass of
-// enumerate mode, computes where each cycle length starts in the output:
-// lengths up to bfs_max_len were written by the breadth-first levels, longer
-// ones come from the depth-first counting pass).  Does nothing when the
-// breadth-first levels finished on their own.
+// enumerate mode, computes where each cycle length starts in the output).
+// Does nothing when the breadth-first levels finished on their own.
 __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, int enum_bases) {
-  if (ld_acquire(&ctl->mode) == 0) return;
+  __shared__ unsigned long long sTot[CC_HSLOTS];
+  if (ld_relaxed(&ctl->mode) == 0) return;
   const DfsWork wk = (ctl->switch_level & 1) ? wk0 : wk1;
   for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
        i < wk.qcap; i += (unsigned long long)gridDim.x * blockDim.x)
     wk.qseq[i] = i;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x != 0) return;
+  if (enum_bases) length_totals(ctl, true, sTot);
+  if (threadIdx.x == 0) {
     ctl->root_cursor = 0;
     ctl->q_head = 0;
     ctl->q_tail = 0;
@@ -905,33 +1136,31 @@ __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, int e
     ctl->idle = 0;
     if (enum_bases) {
       long long cb = 0, vb = 0;
-      for (int k = 0; k <= n + 1 && k < CC_HSLOTS; ++k) {
-        const long long c = (k <= ctl->bfs_max_len) ? (long long)ctl->hist[k]
-                                                     : (long long)ctl->dfs_hist[k];
+      for (int k = 0; k < CC_HSLOTS; ++k) {
         ctl->len_cbase[k] = (unsigned long long)cb;
         ctl->len_vbase[k] = (unsigned long long)vb;
         ctl->len_cursor[k] = 0;
-        cb += c;
-        vb += c * k;
+        cb += (long long)sTot[k];
+        vb += (long long)sTot[k] * k;
       }
     }
   }
 }
 
-// Enumerate mode: fold the depth-first counts into the histogram and close
-// the offsets array with the total vertex count.
-__global__ void k_finalize(CcCtl *ctl, OutDev out, int n) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  if (ld_acquire(&ctl->mode) != 0) {
-    for (int k = ctl->bfs_max_len + 1; k <= n + 1 && k < CC_HSLOTS; ++k)
-      ctl->hist[k] += ctl->dfs_hist[k];
+// Final histogram; in enumerate mode also closes the offsets array with the
+// total vertex count.  One block.
+__global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
+  __shared__ unsigned long long sTot[CC_HSLOTS];
+  length_totals(ctl, enumerate != 0, sTot);
+  for (int k = threadIdx.x; k < CC_HSLOTS; k += blockDim.x) ctl->hist[k] = sTot[k];
+  if (enumerate && threadIdx.x == 0) {
+    long long c = 0, v = 0;
+    for (int k = 0; k <= n && k < CC_HSLOTS; ++k) {
+      c += (long long)sTot[k];
+      v += (long long)sTot[k] * k;
+    }
+    if (c <= out.cyc_cap && v <= out.verts_cap && out.offs) out.offs[c] = v;
   }
-  long long c = 0, v = 0;
-  for (int k = 0; k <= n && k < CC_HSLOTS; ++k) {
-    c += (long long)ctl->hist[k];
-    v += (long long)ctl->hist[k] * k;
-  }
-  if (c <= out.cyc_cap && v <= out.verts_cap && out.offs) out.offs[c] = v;
 }
 
 }  // namespace
@@ -946,54 +1175,55 @@ hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s) {
 
 hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n_single,
                             const int *row_ptr, const int *col_idx, unsigned long long *adj,
-                            int /*adj_stride_words*/, int *perm, int *label,
+                            unsigned long long *adj_orig, int *perm, int *label,
                             unsigned int *status, hipStream_t s) {
   if (W == 1)
     hipLaunchKernelGGL(k_ingest<1>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
-                       row_ptr, col_idx, adj, perm, label, status);
+                       row_ptr, col_idx, adj, adj_orig, perm, label, status);
   else
     hipLaunchKernelGGL(k_ingest<2>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
-                       row_ptr, col_idx, adj, perm, label, status);
+                       row_ptr, col_idx, adj, adj_orig, perm, label, status);
   return hipGetLastError();
 }
 
-hipError_t cc_launch_triplets(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f3, OutDev out,
+hipError_t cc_launch_triplets(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f3, Stage st,
                               hipStream_t s) {
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_triplets<1, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, out);
-    else hipLaunchKernelGGL((k_triplets<1, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, out);
+    if (en) hipLaunchKernelGGL((k_triplets<1, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
+    else hipLaunchKernelGGL((k_triplets<1, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
   } else {
-    if (en) hipLaunchKernelGGL((k_triplets<2, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, out);
-    else hipLaunchKernelGGL((k_triplets<2, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, out);
+    if (en) hipLaunchKernelGGL((k_triplets<2, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
+    else hipLaunchKernelGGL((k_triplets<2, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
   }
   return hipGetLastError();
 }
 
 hipError_t cc_launch_level(int W, bool en, GraphDev g, CcCtl *ctl, Frontier fin, Frontier fout,
-                           OutDev out, int t, int forced_level, int blocks, hipStream_t s) {
+                           Stage sprev, Stage scur, OutDev out, int t, int forced_level,
+                           int blocks, unsigned int *host_done, hipStream_t s) {
   dim3 gr(blocks), bl(CC_BLOCK);
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_level<1, true>), gr, bl, 0, s, g, ctl, fin, fout, out, t, forced_level);
-    else hipLaunchKernelGGL((k_level<1, false>), gr, bl, 0, s, g, ctl, fin, fout, out, t, forced_level);
+    if (en) hipLaunchKernelGGL((k_level<1, true>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
+    else hipLaunchKernelGGL((k_level<1, false>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
   } else {
-    if (en) hipLaunchKernelGGL((k_level<2, true>), gr, bl, 0, s, g, ctl, fin, fout, out, t, forced_level);
-    else hipLaunchKernelGGL((k_level<2, false>), gr, bl, 0, s, g, ctl, fin, fout, out, t, forced_level);
+    if (en) hipLaunchKernelGGL((k_level<2, true>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
+    else hipLaunchKernelGGL((k_level<2, false>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
   }
   return hipGetLastError();
 }
 
 hipError_t cc_launch_dfs(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
                          DfsWork wk0, DfsWork wk1, OutDev out, unsigned long long *hist_out,
-                         bool count_front, int blocks, unsigned long long idle_timeout,
-                         hipStream_t s) {
+                         int hist_stride, bool count_front, int blocks,
+                         unsigned long long idle_timeout, hipStream_t s) {
   dim3 gr(blocks), bl(CC_BLOCK);
   const int cf = count_front ? 1 : 0;
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_dfs<1, true>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, cf, idle_timeout);
-    else hipLaunchKernelGGL((k_dfs<1, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, cf, idle_timeout);
+    if (en) hipLaunchKernelGGL((k_dfs<1, true>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
+    else hipLaunchKernelGGL((k_dfs<1, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
   } else {
-    if (en) hipLaunchKernelGGL((k_dfs<2, true>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, cf, idle_timeout);
-    else hipLaunchKernelGGL((k_dfs<2, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, cf, idle_timeout);
+    if (en) hipLaunchKernelGGL((k_dfs<2, true>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
+    else hipLaunchKernelGGL((k_dfs<2, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
   }
   return hipGetLastError();
 }
@@ -1005,7 +1235,7 @@ hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, bo
   return hipGetLastError();
 }
 
-hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, ctl, out, n);
+hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool en, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, ctl, out, n, en ? 1 : 0);
   return hipGetLastError();
 }

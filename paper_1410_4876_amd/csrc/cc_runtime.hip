@@ -63,6 +63,7 @@ struct HandleRes {
   int device;
   void *d_blob;
   void *h_ctl;
+  void *h_done;
   hipEvent_t ev0, ev1;
 };
 std::mutex g_pool_mu;
@@ -99,12 +100,15 @@ struct cc_graph {
   int max_deg = 0;
   DeviceInfo dev{};
   void *d_blob = nullptr;  // adj | perm | label | status | ctl
-  unsigned long long *d_adj = nullptr;
+  unsigned long long *d_adj = nullptr;       // label-space adjacency bitsets
+  unsigned long long *d_adj_orig = nullptr;  // original-id adjacency bitsets
   int *d_perm = nullptr;
   int *d_label = nullptr;
   unsigned int *d_status = nullptr;
   CcCtl *d_ctl = nullptr;
   CcCtl *h_ctl = nullptr;  // pinned readback
+  unsigned int *h_done = nullptr;  // pinned flag written by the level kernels
+  unsigned int *d_done = nullptr;  // its device-side address
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evp[2 * CC_MAXN + 8] = {};  // CC_PROFILE: around each kernel group
   bool have_run = false;
@@ -133,9 +137,11 @@ unsigned long long *dev_field(CcCtl *ctl, size_t offset) {
 
 int64_t choose3(int64_t n) { return n < 3 ? 0 : n * (n - 1) * (n - 2) / 6; }
 
-// Carves one frontier buffer (SoA: X words, S words, vv) out of `base`.
-Frontier carve_frontier(char *base, unsigned long long cap, int W, bool en) {
+// Carves one sharded frontier buffer (SoA: X words, S words, vv) of
+// CC_SHARDS * cap_s paths out of `base`.
+Frontier carve_frontier(char *base, unsigned long long cap_s, int W, bool en) {
   Frontier f{};
+  const unsigned long long cap = cap_s * CC_SHARDS;
   size_t off = 0;
   f.X = (unsigned long long *)(base + off);
   off = align_up(off + cap * W * 8, 256);
@@ -145,10 +151,12 @@ Frontier carve_frontier(char *base, unsigned long long cap, int W, bool en) {
   }
   f.vv = (unsigned short *)(base + off);
   f.cap = cap;
+  f.cap_s = cap_s;
   return f;
 }
 
-size_t frontier_bytes(unsigned long long cap, int W, bool en) {
+size_t frontier_bytes(unsigned long long cap_s, int W, bool en) {
+  const unsigned long long cap = cap_s * CC_SHARDS;
   size_t b = align_up(cap * W * 8, 256);
   if (en) b += align_up(cap * W * 8, 256);
   b += align_up(cap * 2, 256);
@@ -206,21 +214,41 @@ struct RunOut {
 
 // One full device run: stage one, the level loop, and the depth-first
 // continuation if the budget (or CC_FORCE_DFS) requires it.
+//
+// Device memory (one stream-ordered allocation, sized by the budget): two
+// sharded frontier buffers used alternately by the levels and, in enumerate
+// mode, two staging buffers for the cycles one level closes and the next
+// decodes.  The depth-first workspace reuses the frontier buffer that does
+// not hold the handed-over paths.
 cc_status run_device(cc_graph *g, const RunOut &ro) {
   const int n = g->n;
   const int W = g->W;
   const bool en = ro.enumerate;
   hipStream_t s = g->stream;
-  int64_t budget = g->opt.frontier_budget_bytes > 0 ? g->opt.frontier_budget_bytes : kDefaultBudget;
-  const size_t per_path = (size_t)W * 8 * (en ? 2 : 1) + 2;
-  unsigned long long cap = (unsigned long long)(budget / 2) / per_path;
-  const unsigned long long min_cap = (unsigned long long)choose3(n) + CC_CHUNK;
-  cap = std::max(cap, min_cap);
-  cap = align_up(cap, 64);
-  const size_t buf_bytes = align_up(frontier_bytes(cap, W, en), 1 << 16);
+  const int64_t budget =
+      g->opt.frontier_budget_bytes > 0 ? g->opt.frontier_budget_bytes : kDefaultBudget;
+  // bytes per unit of capacity: a path in each frontier buffer, plus a
+  // staged cycle in each staging buffer
+  const size_t per_unit = 2 * ((size_t)W * 8 * (en ? 2 : 1) + 2) + (en ? 2 * (size_t)W * 8 : 0);
+  unsigned long long cap_s = (unsigned long long)budget / per_unit / CC_SHARDS;
+  // stage one writes every initial triplet (at most C(n,3)) round-robin
+  const unsigned long long min_cap_s = (unsigned long long)choose3(n) / CC_SHARDS + CC_CHUNK;
+  cap_s = align_up(std::max(cap_s, min_cap_s), 64);
+  const unsigned long long cap = cap_s * CC_SHARDS;
+  const size_t buf_bytes = align_up(frontier_bytes(cap_s, W, en), 1 << 16);
+  const size_t stage_bytes = en ? align_up(cap * W * 8, 1 << 16) : 0;
   char *arena = nullptr;
-  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes, s));
-  Frontier f[2] = {carve_frontier(arena, cap, W, en), carve_frontier(arena + buf_bytes, cap, W, en)};
+  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes + 2 * stage_bytes, s));
+  Frontier f[2] = {carve_frontier(arena, cap_s, W, en),
+                   carve_frontier(arena + buf_bytes, cap_s, W, en)};
+  Stage st[2] = {};
+  if (en) {
+    for (int i = 0; i < 2; ++i) {
+      st[i].C = (unsigned long long *)(arena + 2 * buf_bytes + i * stage_bytes);
+      st[i].cap = cap;
+      st[i].cap_s = cap_s;
+    }
+  }
 
   const int maxc = std::max(1, g->max_deg - 1);
   int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 8;
@@ -242,7 +270,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   const unsigned long long idle_timeout =
       (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz);
 
-  GraphDev gd{g->d_adj, g->d_perm, n};
+  GraphDev gd{g->d_adj, g->d_adj_orig, g->d_perm, n};
   CcCtl *ctl = g->d_ctl;
   hipError_t e = hipSuccess;
   int levels = 0;
@@ -254,36 +282,53 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     for (int i = 0; i < 2 * n + 8; ++i)
       if (!g->evp[i]) chk(hipEventCreate(&g->evp[i]));
   }
-  // evp layout: [0,1] stage one, [2+2(t-3), 3+2(t-3)] level t, [2n, 2n+1] depth-first
+  // evp layout: [0,1] stage one, [2+2(t-3), 3+2(t-3)] level t, [2n+2, 2n+3] depth-first
   auto mark = [&](int i) {
     if (prof) chk(hipEventRecord(g->evp[i], s));
   };
   chk(hipEventRecord(g->ev0, s));
   chk(cc_launch_zero(ctl, sizeof(CcCtl), s));
   mark(0);
-  chk(cc_launch_triplets(W, en, gd, ctl, f[1], ro.out, s));
+  chk(cc_launch_triplets(W, en, gd, ctl, f[1], st[0], s));
   mark(1);
-  for (int t = 3; t <= n - 1 && e == hipSuccess; ++t, ++levels) {
+  // Level t expands the paths with t vertices and (enumerate mode) decodes
+  // the cycles with t vertices; level n only decodes.  The level kernels
+  // report the first level with nothing to do through a pinned host word and
+  // launching stops there (the remaining levels would all return at once).
+  // The flag may arrive late: extra launches are no-ops.
+  volatile unsigned int *done = g->h_done;
+  *done = 0u;
+  for (int t = 3; t <= n && e == hipSuccess; ++t, ++levels) {
+    if (*done != 0u) break;
     mark(2 + 2 * (t - 3));
-    chk(cc_launch_level(W, en, gd, ctl, f[t & 1], f[(t + 1) & 1], ro.out, t, forced, bfs_blocks, s));
+    chk(cc_launch_level(W, en, gd, ctl, f[t & 1], f[(t + 1) & 1], st[(t - 1) & 1], st[t & 1],
+                        ro.out, t, forced, bfs_blocks, g->d_done, s));
     mark(3 + 2 * (t - 3));
   }
   // Depth-first continuation (each kernel returns at once if the levels
   // finished within the budget).
-  mark(2 * n);
+  mark(2 * n + 2);
   chk(cc_launch_dfs_prepare(ctl, wc[0], wc[1], n, false, s));
-  chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc[0], wc[1], ro.out,
-                    dev_field(ctl, en ? offsetof(CcCtl, dfs_hist) : offsetof(CcCtl, hist)), true,
-                    dfs_blocks_c, idle_timeout, s));
   if (en) {
+    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc[0], wc[1], ro.out,
+                      dev_field(ctl, offsetof(CcCtl, dfs_hist)), 0, true, dfs_blocks_c,
+                      idle_timeout, s));
     chk(cc_launch_dfs_prepare(ctl, we[0], we[1], n, true, s));
-    chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we[0], we[1], ro.out, nullptr, false,
+    chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we[0], we[1], ro.out, nullptr, 0, false,
                       dfs_blocks_e, idle_timeout, s));
-    chk(cc_launch_finalize(ctl, ro.out, n, s));
+  } else {
+    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc[0], wc[1], ro.out,
+                      dev_field(ctl, offsetof(CcCtl, hist_sh)), CC_HSLOTS, true, dfs_blocks_c,
+                      idle_timeout, s));
   }
-  mark(2 * n + 1);
+  mark(2 * n + 3);
+  chk(cc_launch_finalize(ctl, ro.out, n, en, s));
   chk(hipEventRecord(g->ev1, s));
-  chk(hipMemcpyAsync(g->h_ctl, ctl, sizeof(CcCtl), hipMemcpyDeviceToHost, s));
+  // Read back the unsharded tail of the control block (everything for
+  // profiling runs, which also report per-level traffic).
+  const size_t tail = prof ? 0 : offsetof(CcCtl, hist);
+  chk(hipMemcpyAsync((char *)g->h_ctl + tail, (char *)ctl + tail, sizeof(CcCtl) - tail,
+                     hipMemcpyDeviceToHost, s));
   chk(hipFreeAsync(arena, s));
   chk(hipStreamSynchronize(s));
   if (e != hipSuccess) return hip_err(e);
@@ -315,19 +360,26 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       return (double)x;
     };
     g->info.stage1_ms = span(0, 1);
-    for (int t = 3; t <= n - 1; ++t) g->info.level_ms += span(2 + 2 * (t - 3), 3 + 2 * (t - 3));
-    g->info.dfs_ms = span(2 * n, 2 * n + 1);
-    // Bytes the level kernels must move: each path they expand is read once,
-    // each extension they write is written once (X words, S words in
-    // enumerate mode, 2 bytes of end vertices), and each cycle they close is
-    // written as k int32 ids plus one int64 offset.
-    const int last = h.mode ? (h.skip_first ? h.switch_level : h.switch_level - 1) : n - 1;
-    const int64_t pp = (int64_t)per_path;
+    for (int t = 3; t < 3 + levels; ++t) g->info.level_ms += span(2 + 2 * (t - 3), 3 + 2 * (t - 3));
+    g->info.dfs_ms = span(2 * n + 2, 2 * n + 3);
+    // Bytes the level kernels must move: each path they expand is read once
+    // and each extension they write is written once (X words, S words in
+    // enumerate mode, 2 bytes of end vertices); each cycle they close is
+    // staged (W words written, then read by the next level) and written as
+    // k int32 ids plus one int64 offset.
+    const int last = h.mode ? h.switch_level : n;
+    const int64_t pp = (int64_t)W * 8 * (en ? 2 : 1) + 2;
+    auto level_count = [&](int t) {
+      unsigned long long c = 0;
+      for (int sh = 0; sh < CC_SHARDS; ++sh) c += std::min(h.count_sh[sh][t], cap_s);
+      return (int64_t)c;
+    };
     int64_t bytes = 0;
-    for (int t = 3; t <= last && t <= n - 1; ++t) {
-      bytes += (int64_t)std::min<unsigned long long>(h.count[t], cap) * pp;
-      bytes += (int64_t)std::min<unsigned long long>(h.count[t + 1], cap) * pp;
-      if (en) bytes += (int64_t)h.hist[t + 1] * (4 * (t + 1) + 8);
+    for (int t = 3; t <= last && t < 3 + levels; ++t) {
+      bytes += level_count(t) * pp;
+      if (t + 1 <= n) bytes += level_count(t + 1) * pp;
+      if (en && t + 1 <= n && t + 1 <= (h.mode ? h.bfs_max_len : n))
+        bytes += (int64_t)h.hist[t + 1] * (16 * W + 4 * (t + 1) + 8);
     }
     g->info.level_bytes = bytes;
   }
@@ -407,7 +459,7 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   g->W = n <= 64 ? 1 : 2;
   const size_t adj_b = align_up((size_t)CC_MAXN * 2 * 8, 256);
   const size_t vec_b = align_up((size_t)CC_MAXN * 4, 256);
-  const size_t blob = adj_b + 2 * vec_b + 256 + align_up(sizeof(CcCtl), 256);
+  const size_t blob = 2 * adj_b + 2 * vec_b + 256 + align_up(sizeof(CcCtl), 256);
   auto fail = [&](cc_status s) {
     cc_release(g);
     return s;
@@ -416,21 +468,28 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   if (pool_take(dev, &res)) {
     g->d_blob = res.d_blob;
     g->h_ctl = (CcCtl *)res.h_ctl;
+    g->h_done = (unsigned int *)res.h_done;
     g->ev0 = res.ev0;
     g->ev1 = res.ev1;
   } else {
     if (hipMalloc(&g->d_blob, blob) != hipSuccess) return fail(CC_ERR_OUT_OF_MEMORY);
     if (hipHostMalloc((void **)&g->h_ctl, sizeof(CcCtl), hipHostMallocDefault) != hipSuccess)
       return fail(CC_ERR_OUT_OF_MEMORY);
+    if (hipHostMalloc((void **)&g->h_done, 64, hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
+      return fail(CC_ERR_OUT_OF_MEMORY);
     if (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess)
       return fail(CC_ERR_DEVICE);
   }
+  if (hipHostGetDevicePointer((void **)&g->d_done, g->h_done, 0) != hipSuccess)
+    return fail(CC_ERR_DEVICE);
   char *b = (char *)g->d_blob;
   g->d_adj = (unsigned long long *)b;
-  g->d_perm = (int *)(b + adj_b);
-  g->d_label = (int *)(b + adj_b + vec_b);
-  g->d_status = (unsigned int *)(b + adj_b + 2 * vec_b);
-  g->d_ctl = (CcCtl *)(b + adj_b + 2 * vec_b + 256);
+  g->d_adj_orig = (unsigned long long *)(b + adj_b);
+  g->d_perm = (int *)(b + 2 * adj_b);
+  g->d_label = (int *)(b + 2 * adj_b + vec_b);
+  g->d_status = (unsigned int *)(b + 2 * adj_b + 2 * vec_b);
+  g->d_ctl = (CcCtl *)(b + 2 * adj_b + 2 * vec_b + 256);
   if (n == 0) {
     *out = g;
     return CC_OK;
@@ -452,7 +511,7 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
     d_rp = (const int *)tmp;
     d_ci = (const int *)((char *)tmp + rb);
   }
-  hipError_t e = cc_launch_ingest(g->W, 1, nullptr, n, d_rp, d_ci, g->d_adj, 0, g->d_perm,
+  hipError_t e = cc_launch_ingest(g->W, 1, nullptr, n, d_rp, d_ci, g->d_adj, g->d_adj_orig, g->d_perm,
                                   g->d_label, g->d_status, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&g->h_ctl->status, g->d_status, 4, hipMemcpyDeviceToHost, s);
@@ -588,10 +647,12 @@ void cc_release(cc_graph *g) {
   if (g->d_blob) (void)hipStreamSynchronize(g->stream);
   for (hipEvent_t &ev : g->evp)
     if (ev) (void)hipEventDestroy(ev);
-  const bool complete = g->d_blob && g->h_ctl && g->ev0 && g->ev1;
-  if (!(complete && pool_give(HandleRes{g->device, g->d_blob, g->h_ctl, g->ev0, g->ev1}))) {
+  const bool complete = g->d_blob && g->h_ctl && g->h_done && g->ev0 && g->ev1;
+  if (!(complete &&
+        pool_give(HandleRes{g->device, g->d_blob, g->h_ctl, g->h_done, g->ev0, g->ev1}))) {
     if (g->d_blob) (void)hipFree(g->d_blob);
     if (g->h_ctl) (void)hipHostFree(g->h_ctl);
+    if (g->h_done) (void)hipHostFree(g->h_done);
     if (g->ev0) (void)hipEventDestroy(g->ev0);
     if (g->ev1) (void)hipEventDestroy(g->ev1);
   }
