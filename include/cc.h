@@ -72,6 +72,8 @@ typedef struct cc_options {
                                     is handed to the depth-first kernel                  */
   int32_t dfs_waves_per_cu;      /* depth-first kernel occupancy; 0 = default            */
   int32_t bfs_blocks;            /* grid of the level kernel; 0 = default                */
+  int32_t dfs_donate_min;        /* depth-first: a wavefront donates work to idle ones once
+                                    it holds at least this many paths; 0 = default      */
 } cc_options;
 
 typedef struct cc_graph cc_graph;

@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
                 ("flags", ctypes.c_uint32),
                 ("dfs_level", ctypes.c_int32),
                 ("dfs_waves_per_cu", ctypes.c_int32),
-                ("bfs_blocks", ctypes.c_int32)]
+                ("bfs_blocks", ctypes.c_int32),
+                ("dfs_donate_min", ctypes.c_int32)]
 
 
 class RunInfo(ctypes.Structure):
@@ -140,7 +141,8 @@ class Graph:
 
     def __init__(self, n, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
                  force_dfs_level: int | None = None, dfs_waves_per_cu: int = 0,
-                 bfs_blocks: int = 0, output_device: bool = True, profile: bool = False):
+                 bfs_blocks: int = 0, output_device: bool = True, profile: bool = False,
+                 dfs_donate_min: int = 0):
         L = lib()
         rp, rp_dev, self._k1 = _ptr(_as_i32(row_ptr))
         ci, ci_dev, self._k2 = _ptr(_as_i32(col_idx))
@@ -156,7 +158,8 @@ class Graph:
         if profile:
             flags |= CC_PROFILE
         self.opt = Options(_stream_handle(stream), int(budget_bytes), flags,
-                           int(force_dfs_level or 0), int(dfs_waves_per_cu), int(bfs_blocks))
+                           int(force_dfs_level or 0), int(dfs_waves_per_cu), int(bfs_blocks),
+                           int(dfs_donate_min))
         self.n = int(n)
         self.output_device = output_device
         h = ctypes.c_void_p()

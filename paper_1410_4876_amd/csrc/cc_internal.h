@@ -42,14 +42,13 @@ struct CcCtl {
   unsigned long long len_vbase[CC_HSLOTS];  // enumerate: first vertex offset of each length
   unsigned long long peak;                  // largest breadth-first frontier
   unsigned long long root_cursor;           // depth-first: next unclaimed handed-over path
-  unsigned long long q_head, q_tail;        // depth-first donation queue positions
   unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
-  unsigned long long donations;             // chunks donated (diagnostic)
+  unsigned long long donations;             // chunks given away on request (diagnostic)
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over
   int switch_level;                         // path length handed to the depth-first kernel
   int skip;                                 // CC_SKIP_* bits for the handed-over paths
   int busy;                                 // depth-first wavefronts holding or seeking work
-  int idle;                                 // depth-first wavefronts waiting for work
+  int unused;
   unsigned int status;                      // CC_DEV_* bits
   int bfs_max_len;                          // longest cycle length final after the levels
   int pad;
@@ -94,20 +93,27 @@ struct OutDev {
   long long cyc_cap;
 };
 
-// Depth-first workspace: per-wavefront stacks and the donation queue.
+// Depth-first workspace: per-wavefront stacks, mailboxes and inboxes.
+// Mailbox words of wavefront w (its own 128-byte line):
+//   mail[w * CC_MAIL + 0]  request: 0 none, r + 1 from wavefront r, CC_MAIL_CLOSED
+//   mail[w * CC_MAIL + 1]  response to w's own request: 0 none, 1 work, 2 declined
+//   mail[w * CC_MAIL + 2]  paths delivered into w's inbox
+//   mail[w * CC_MAIL + 3]  paths w could give away (hint for victim choice)
+#define CC_MAIL 32
+#define CC_MAIL_CLOSED 0xffffffffu
 struct DfsWork {
   unsigned long long *stackX;   // [nwaves][W][cap_w]
   unsigned long long *stackS;   // [nwaves][W][cap_w] (enumerate only)
   unsigned int *stackM;         // [nwaves][cap_w]: v1 | vt<<8 | t<<16 | root<<24
   unsigned long long cap_w;     // items per wavefront stack
-  unsigned long long *qseq;     // [qcap] cell sequence numbers
-  unsigned long long *qX;       // [qcap][W][CC_CHUNK]
-  unsigned long long *qS;       // [qcap][W][CC_CHUNK]
-  unsigned int *qM;             // [qcap][CC_CHUNK]
-  unsigned int *qN;             // [qcap] items in the cell
-  unsigned long long qcap;
+  unsigned int *mail;           // [nwaves][CC_MAIL]
+  unsigned long long *inX;      // [nwaves][W][CC_CHUNK] inbox
+  unsigned long long *inS;      // [nwaves][W][CC_CHUNK] (enumerate only)
+  unsigned int *inM;            // [nwaves][CC_CHUNK]
+  int nwaves;
   int max_children;             // upper bound on extensions of one path
-  int donate_check;             // batches between donation checks
+  int donate_check;             // batches between mailbox checks
+  int donate_min;               // paths a wavefront must hold before it gives some away
 };
 
 // ------------------------------------------------------------------ launchers

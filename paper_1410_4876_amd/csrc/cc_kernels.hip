@@ -142,7 +142,6 @@ __device__ __forceinline__ unsigned int wave_min_u32(unsigned int v) {
 __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v) {
   return __shfl(v, 0, CC_WAVE);
 }
-__device__ __forceinline__ long long bcast_i64(long long v) { return __shfl(v, 0, CC_WAVE); }
 
 template <typename T>
 __device__ __forceinline__ T ld_acquire(T *p) {
@@ -158,6 +157,22 @@ template <typename T>
 __device__ __forceinline__ void st_release(T *p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Coherent single accesses (relaxed, agent scope): each is one sc1 load or
+// store, visible across the XCDs, with no cache-wide maintenance.  The
+// depth-first donation queue moves its payload with these and orders it with
+// wait_mem() instead of agent-scope fences, which would write back or
+// invalidate the whole L2 of the XCD.
+template <typename T>
+__device__ __forceinline__ T ld_coh(T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until every memory access this wavefront issued has completed.
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
 
 __device__ __forceinline__ void st_system(unsigned int *p, unsigned int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -685,64 +700,27 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
 }
 
 // ---------------------------------------------------------- depth-first
-// Donation queue: a bounded multi-producer multi-consumer ring of chunks
-// (each up to CC_CHUNK paths) with one sequence number per cell.  Only lane
-// 0 of a wavefront touches the cursors; the whole wavefront moves the data.
-__device__ long long q_reserve_push(CcCtl *ctl, const DfsWork &wk) {
-  unsigned long long pos = ld_relaxed(&ctl->q_tail);
-  for (int attempt = 0; attempt < 32; ++attempt) {
-    const unsigned long long cell = pos & (wk.qcap - 1);
-    const unsigned long long seq = ld_acquire(&wk.qseq[cell]);
-    const long long diff = (long long)(seq - pos);
-    if (diff == 0) {
-      if (atomicCAS(&ctl->q_tail, pos, pos + 1) == pos) return (long long)pos;
-      pos = ld_relaxed(&ctl->q_tail);
-    } else if (diff < 0) {
-      return -1;  // full
-    } else {
-      pos = ld_relaxed(&ctl->q_tail);
-    }
-  }
-  return -1;
-}
-
-__device__ long long q_reserve_pop(CcCtl *ctl, const DfsWork &wk) {
-  unsigned long long pos = ld_relaxed(&ctl->q_head);
-  for (int attempt = 0; attempt < 32; ++attempt) {
-    const unsigned long long cell = pos & (wk.qcap - 1);
-    const unsigned long long seq = ld_acquire(&wk.qseq[cell]);
-    const long long diff = (long long)(seq - (pos + 1));
-    if (diff == 0) {
-      if (atomicCAS(&ctl->q_head, pos, pos + 1) == pos) return (long long)pos;
-      pos = ld_relaxed(&ctl->q_head);
-    } else if (diff < 0) {
-      return -1;  // empty
-    } else {
-      pos = ld_relaxed(&ctl->q_head);
-    }
-  }
-  return -1;
-}
-
-__device__ __forceinline__ bool work_visible(CcCtl *ctl, unsigned long long nroots) {
-  if (ld_relaxed(&ctl->root_cursor) < nroots) return true;
-  const unsigned long long h = ld_relaxed(&ctl->q_head);
-  const unsigned long long tl = ld_relaxed(&ctl->q_tail);
-  return tl > h;
-}
-
-// Depth-first continuation (beyond the memory budget).  Each wavefront owns
-// a LIFO stack of open paths in device memory; a step pops up to 64 paths
-// (one per lane), expands them exactly like a breadth-first level and pushes
-// the extensions back, so memory grows with depth, not with the frontier.
-// Work enters from the handed-over frontier, which wavefronts claim in
-// private ranges of CC_ROOT_CLAIM paths (one atomic per range) and consume 64
-// at a time whenever their stack is empty, and from chunks that busy
-// wavefronts donate (from the end of their range, else from the bottom of
-// their stack) when others are idle.  Termination: a wavefront leaves only
-// after it saw no busy wavefront and then no visible work; a wavefront that
-// holds paths is always counted busy.  Idle wavefronts back off
-// exponentially so that their polling does not load the memory system.
+// Depth-first continuation (beyond the memory budget, or on request).  Each
+// wavefront owns a LIFO stack of open paths in device memory; a step pops up
+// to 64 paths (one per lane), expands them exactly like a breadth-first level
+// and pushes the extensions back, so memory grows with depth, not with the
+// frontier.  Work enters from the handed-over frontier, which wavefronts
+// claim in private ranges (one atomic per range) and consume 64 at a time
+// whenever their stack is empty.
+//
+// Load balance is by work requests through per-wavefront mailboxes (each
+// wavefront polls only its own cache line, so no address is shared by the
+// polling): an idle wavefront reads the published "paths I could give" hints
+// of 64 others, asks the richest, and waits on its own line; a busy
+// wavefront looks at its mailbox every few batches and either ships up to
+// 64 paths (the end of its private range, else the oldest, shallowest stack
+// entries) into the requester's inbox or declines.  Payloads move with
+// coherent single accesses and are published after an s_waitcnt, never with
+// cache-wide fences.
+//
+// Termination: `busy` counts wavefronts that hold paths, including paths in
+// transit (the donor counts the recipient before answering), so busy == 0
+// with the handed-over frontier exhausted means no work is left anywhere.
 // Cycle counts go to hist_out[(block % CC_SHARDS) * hist_stride + k].
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Frontier f0,
@@ -786,17 +764,28 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   __syncthreads();
   const unsigned long long nroots = sPre[CC_SHARDS];
 
-  const unsigned long long wid = (unsigned long long)blockIdx.x * (CC_BLOCK / CC_WAVE) + tid / CC_WAVE;
+  const int wid = blockIdx.x * (CC_BLOCK / CC_WAVE) + tid / CC_WAVE;
+  const int nwaves = gridDim.x * (CC_BLOCK / CC_WAVE);
   const unsigned long long cap = wk.cap_w;
-  unsigned long long *stX = wk.stackX + wid * W * cap;
-  unsigned long long *stS = ENUM ? wk.stackS + wid * W * cap : nullptr;
-  unsigned int *stM = wk.stackM + wid * cap;
+  unsigned long long *stX = wk.stackX + (unsigned long long)wid * W * cap;
+  unsigned long long *stS = ENUM ? wk.stackS + (unsigned long long)wid * W * cap : nullptr;
+  unsigned int *stM = wk.stackM + (unsigned long long)wid * cap;
+  unsigned int *my_mail = wk.mail + (size_t)wid * CC_MAIL;
   const unsigned long long maxc = (unsigned long long)max(wk.max_children, 1);
+  const unsigned long long dmin = (unsigned long long)max(wk.donate_min, 2);
   const unsigned int root_meta = ((unsigned)L << 16) | (1u << 24);
+  // Claim size: up to CC_ROOT_CLAIM paths, but small enough that every
+  // wavefront gets several claims when the handed-over frontier is small.
+  const unsigned long long claim =
+      max((unsigned long long)CC_CHUNK,
+          min((unsigned long long)CC_ROOT_CLAIM,
+              nroots / ((unsigned long long)nwaves * 4) / CC_CHUNK * CC_CHUNK));
 
   unsigned long long bot = 0, top = 0;     // live stack entries [bot, top)
   unsigned long long r_lo = 0, r_hi = 0;   // private range of handed-over paths
   unsigned long long steps = 0, batches = 0, donated = 0;
+  unsigned long long rng = 0x9E3779B97F4A7C15ull * (unsigned long long)(wid + 1);
+  bool roots_done = false;
   if (lane == 0) atomicAdd(&ctl->busy, 1);
 
   while (true) {
@@ -824,14 +813,16 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       if (top == bot) top = bot = 0;
       have = true;
     } else {
-      if (r_lo >= r_hi) {
+      if (r_lo >= r_hi && !roots_done) {
         unsigned long long c = ~0ull;
         if (lane == 0 && ld_relaxed(&ctl->root_cursor) < nroots)
-          c = atomicAdd(&ctl->root_cursor, (unsigned long long)CC_ROOT_CLAIM);
+          c = atomicAdd(&ctl->root_cursor, claim);
         c = bcast_u64(c);
         if (c < nroots) {
           r_lo = c;
-          r_hi = min(c + (unsigned long long)CC_ROOT_CLAIM, nroots);
+          r_hi = min(c + claim, nroots);
+        } else {
+          roots_done = true;
         }
       }
       if (r_lo < r_hi) {
@@ -854,70 +845,107 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       }
     }
     if (!have) {
-      // a donated chunk
-      long long pos = -1;
-      if (lane == 0) pos = q_reserve_pop(ctl, wk);
-      pos = bcast_i64(pos);
-      if (pos >= 0) {
-        const unsigned long long cell = (unsigned long long)pos & (wk.qcap - 1);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const unsigned kk = wk.qN[cell];
-        valid = (unsigned)lane < kk;
-        if (valid) {
-#pragma unroll
-          for (int w = 0; w < W; ++w) X.w[w] = wk.qX[(cell * W + w) * CC_CHUNK + lane];
-          if (ENUM) {
-#pragma unroll
-            for (int w = 0; w < W; ++w) S.w[w] = wk.qS[(cell * W + w) * CC_CHUNK + lane];
-          }
-          m = wk.qM[cell * CC_CHUNK + lane];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0) st_release(&wk.qseq[cell], (unsigned long long)pos + wk.qcap);
-        have = true;
-      }
-    }
-    if (!have) {
-      // nothing anywhere: wait as idle, or leave
+      // ---- idle: ask a busy wavefront for work, or leave when none is left
       if (lane == 0) {
+        st_coh(&my_mail[3], 0u);
         atomicSub(&ctl->busy, 1);
-        atomicAdd(&ctl->idle, 1);
       }
-      bool leave = false;
+      int victim = -1;                 // wavefront our pending request went to
+      unsigned long long t_req = 0;
+      int outcome = 0;                 // 1: work delivered, 2: leave, 3: roots left, 4: gave up
       const unsigned long long t0 = wall_clock64();
       int backoff = 1;
       while (true) {
-        for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(64);
-        backoff = min(backoff * 2, 64);
-        int flag = 0;  // 1: work seen, 2: leave, 3: gave up waiting
+        int o = 0;
         if (lane == 0) {
-          if (work_visible(ctl, nroots)) {
-            flag = 1;
-          } else if (ld_acquire(&ctl->busy) == 0) {
-            flag = work_visible(ctl, nroots) ? 1 : 2;
-          } else if (wall_clock64() - t0 > idle_timeout) {
-            flag = 3;
+          // decline whatever is asked of us while we have nothing
+          const unsigned r = ld_coh(&my_mail[0]);
+          if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r)
+            st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
+          if (victim >= 0) {
+            const unsigned resp = ld_coh(&my_mail[1]);
+            if (resp == 1u) {
+              o = 1;
+            } else if (resp == 2u) {
+              st_coh(&my_mail[1], 0u);
+              victim = -1;
+            } else if (wall_clock64() - t_req > 20000ull || ld_coh(&ctl->busy) == 0) {
+              // withdraw; if the victim already took the request, keep waiting
+              if (atomicCAS(&wk.mail[(size_t)victim * CC_MAIL], (unsigned)wid + 1u, 0u) ==
+                  (unsigned)wid + 1u)
+                victim = -1;
+            }
+          }
+          if (o == 0 && victim < 0) {
+            if (!roots_done && ld_coh(&ctl->root_cursor) < nroots) o = 3;
+            else if (ld_coh(&ctl->busy) == 0) o = 2;
+            else if (wall_clock64() - t0 > idle_timeout) o = 4;
           }
         }
-        flag = __shfl(flag, 0, CC_WAVE);
-        if (flag == 1) {
-          if (lane == 0) {
-            atomicAdd(&ctl->busy, 1);
-            atomicSub(&ctl->idle, 1);
-          }
+        o = __shfl(o, 0, CC_WAVE);
+        victim = __shfl(victim, 0, CC_WAVE);
+        if (o != 0) {
+          outcome = o;
           break;
         }
-        if (flag >= 2) {
-          if (lane == 0) {
-            atomicSub(&ctl->idle, 1);
-            if (flag == 3) atomicOr(&ctl->status, CC_DEV_IDLE_TIMEOUT);
+        if (victim < 0) {
+          // pick the richest of 64 candidates by their published hints
+          rng ^= rng << 13;
+          rng ^= rng >> 7;
+          rng ^= rng << 17;
+          const int cand = (int)(((rng >> 16) + (unsigned long long)lane * 40503ull) %
+                                 (unsigned long long)nwaves);
+          unsigned hint = cand == wid ? 0u : ld_coh(&wk.mail[(size_t)cand * CC_MAIL + 3]);
+          if (hint < dmin) hint = 0u;
+          unsigned long long key = ((unsigned long long)hint << 32) | (unsigned)cand;
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long other = __shfl_xor(key, off, CC_WAVE);
+            key = other > key ? other : key;
           }
-          leave = true;
-          break;
+          if ((key >> 32) != 0ull) {
+            const int v = (int)(key & 0xffffffffull);
+            int ok = 0;
+            if (lane == 0)
+              ok = atomicCAS(&wk.mail[(size_t)v * CC_MAIL], 0u, (unsigned)wid + 1u) == 0u;
+            ok = __shfl(ok, 0, CC_WAVE);
+            if (ok) {
+              victim = v;
+              t_req = wall_clock64();
+              backoff = 1;
+              continue;
+            }
+          }
         }
+        for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(16);
+        backoff = min(backoff * 2, 32);
       }
-      if (leave) break;
-      continue;
+      if (outcome == 3) {
+        if (lane == 0) atomicAdd(&ctl->busy, 1);
+        continue;
+      }
+      if (outcome != 1) {
+        if (outcome == 4 && lane == 0) atomicOr(&ctl->status, CC_DEV_IDLE_TIMEOUT);
+        break;
+      }
+      // Work arrived in our inbox (the donor already counted us busy).
+      unsigned kk = 0;
+      if (lane == 0) kk = ld_coh(&my_mail[2]);
+      kk = __shfl(kk, 0, CC_WAVE);
+      valid = (unsigned)lane < kk;
+      if (valid) {
+        const size_t ib = (size_t)wid * W * CC_CHUNK;
+#pragma unroll
+        for (int w = 0; w < W; ++w) X.w[w] = ld_coh(&wk.inX[ib + w * CC_CHUNK + lane]);
+        if (ENUM) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) S.w[w] = ld_coh(&wk.inS[ib + w * CC_CHUNK + lane]);
+        }
+        m = ld_coh(&wk.inM[(size_t)wid * CC_CHUNK + lane]);
+      }
+      wait_mem();
+      if (lane == 0) st_coh(&my_mail[1], 0u);
+      have = true;
     }
 
     // ---- expand the batch (one path per lane)
@@ -977,8 +1005,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     const unsigned tot = wave_sum_u32((unsigned)bpop(ext));
     if (tot) {
       if (top + tot > cap && bot > 0) {
-        // Slide the live part of the stack down to index 0 (chunks of 64;
-        // bot is a multiple of 64, so a chunk never overlaps its source).
+        // Slide the live part of the stack down to index 0, 64 entries at a
+        // time: a chunk's loads all complete before its stores, and later
+        // chunks only read above what earlier chunks wrote.
         const unsigned long long live = top - bot;
         for (unsigned long long c0 = 0; c0 < live; c0 += CC_CHUNK) {
           const unsigned long long i = c0 + lane;
@@ -1023,63 +1052,84 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       }
     }
 
-    // ---- donate a chunk when other wavefronts are idle: the end of the
-    // private range first, else the oldest (shallowest) stack entries
+    // ---- every few batches: publish what we could give, answer a request
     ++steps;
-    const bool range_big = r_hi - r_lo >= 2 * CC_CHUNK;
-    if ((steps % (unsigned long long)wk.donate_check) == 0 &&
-        (range_big || top - bot >= 2 * CC_CHUNK)) {
-      int idle = 0;
-      if (lane == 0) idle = ld_relaxed(&ctl->idle);
-      idle = __shfl(idle, 0, CC_WAVE);
-      if (idle > 0) {
-        long long pos = -1;
-        if (lane == 0) pos = q_reserve_push(ctl, wk);
-        pos = bcast_i64(pos);
-        if (pos >= 0) {
-          const unsigned long long cell = (unsigned long long)pos & (wk.qcap - 1);
-          Bits<W> dX, dS = bzero<W>();
-          unsigned int dm;
-          if (range_big) {
-            const unsigned long long i = r_hi - CC_CHUNK + lane;
-            const int s = shard_of(sPre, i);
-            const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
+    if (((steps + (unsigned long long)wid) % (unsigned long long)wk.donate_check) == 0) {
+      const unsigned long long range_left = r_hi - r_lo, stack_left = top - bot;
+      const unsigned long long left = range_left + stack_left;
+      unsigned req = 0;
+      if (lane == 0) {
+        st_coh(&my_mail[3], (unsigned)min(left, 0x7fffffffull));
+        const unsigned r = ld_coh(&my_mail[0]);
+        if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r) req = r;
+      }
+      req = __shfl(req, 0, CC_WAVE);
+      if (req != 0u) {
+        const int q = (int)req - 1;
+        unsigned int *q_mail = wk.mail + (size_t)q * CC_MAIL;
+        const bool from_range = range_left >= dmin;
+        if (from_range || stack_left >= dmin) {
+          const unsigned long long give =
+              min((from_range ? range_left : stack_left) / 2, (unsigned long long)CC_CHUNK);
+          const bool mine = (unsigned long long)lane < give;
+          Bits<W> dX = bzero<W>(), dS = bzero<W>();
+          unsigned int dm = 0;
+          if (from_range) {
+            if (mine) {
+              const unsigned long long i = r_hi - give + lane;
+              const int s = shard_of(sPre, i);
+              const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
 #pragma unroll
-            for (int w = 0; w < W; ++w) dX.w[w] = roots.X[w * roots.cap + e];
-            if (ENUM) {
+              for (int w = 0; w < W; ++w) dX.w[w] = roots.X[w * roots.cap + e];
+              if (ENUM) {
 #pragma unroll
-              for (int w = 0; w < W; ++w) dS.w[w] = roots.S[w * roots.cap + e];
+                for (int w = 0; w < W; ++w) dS.w[w] = roots.S[w * roots.cap + e];
+              }
+              dm = (unsigned)roots.vv[e] | root_meta;
             }
-            dm = (unsigned)roots.vv[e] | root_meta;
-            r_hi -= CC_CHUNK;
+            r_hi -= give;
           } else {
-            const unsigned long long i = bot + lane;
+            if (mine) {
+              const unsigned long long i = bot + lane;
 #pragma unroll
-            for (int w = 0; w < W; ++w) dX.w[w] = stX[w * cap + i];
+              for (int w = 0; w < W; ++w) dX.w[w] = stX[w * cap + i];
+              if (ENUM) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) dS.w[w] = stS[w * cap + i];
+              }
+              dm = stM[i];
+            }
+            bot += give;
+            if (top == bot) top = bot = 0;
+          }
+          if (mine) {
+            const size_t ib = (size_t)q * W * CC_CHUNK;
+#pragma unroll
+            for (int w = 0; w < W; ++w) st_coh(&wk.inX[ib + w * CC_CHUNK + lane], dX.w[w]);
             if (ENUM) {
 #pragma unroll
-              for (int w = 0; w < W; ++w) dS.w[w] = stS[w * cap + i];
+              for (int w = 0; w < W; ++w) st_coh(&wk.inS[ib + w * CC_CHUNK + lane], dS.w[w]);
             }
-            dm = stM[i];
-            bot += CC_CHUNK;
+            st_coh(&wk.inM[(size_t)q * CC_CHUNK + lane], dm);
           }
-#pragma unroll
-          for (int w = 0; w < W; ++w) wk.qX[(cell * W + w) * CC_CHUNK + lane] = dX.w[w];
-          if (ENUM) {
-#pragma unroll
-            for (int w = 0; w < W; ++w) wk.qS[(cell * W + w) * CC_CHUNK + lane] = dS.w[w];
+          if (lane == 0) {
+            st_coh(&q_mail[2], (unsigned)give);
+            atomicAdd(&ctl->busy, 1);  // the recipient holds paths from now on
           }
-          wk.qM[cell * CC_CHUNK + lane] = dm;
-          if (lane == 0) wk.qN[cell] = CC_CHUNK;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          if (lane == 0) st_release(&wk.qseq[cell], (unsigned long long)pos + 1ull);
+          wait_mem();
+          if (lane == 0) st_coh(&q_mail[1], 1u);
           ++donated;
+        } else if (lane == 0) {
+          st_coh(&q_mail[1], 2u);
         }
       }
     }
   }
 
+  // Close the mailbox; decline a request that arrived meanwhile.
   if (lane == 0) {
+    const unsigned r = atomicExch(&my_mail[0], CC_MAIL_CLOSED);
+    if (r != 0u && r != CC_MAIL_CLOSED) st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
     atomicAdd(&ctl->dfs_batches, batches);
     if (donated) atomicAdd(&ctl->donations, donated);
   }
@@ -1123,17 +1173,15 @@ __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, int e
   __shared__ unsigned long long sTot[CC_HSLOTS];
   if (ld_relaxed(&ctl->mode) == 0) return;
   const DfsWork wk = (ctl->switch_level & 1) ? wk0 : wk1;
-  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
-       i < wk.qcap; i += (unsigned long long)gridDim.x * blockDim.x)
-    wk.qseq[i] = i;
+  const size_t words = (size_t)wk.nwaves * CC_MAIL;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
+       i += (size_t)gridDim.x * blockDim.x)
+    wk.mail[i] = 0u;
   if (blockIdx.x != 0) return;
   if (enum_bases) length_totals(ctl, true, sTot);
   if (threadIdx.x == 0) {
     ctl->root_cursor = 0;
-    ctl->q_head = 0;
-    ctl->q_tail = 0;
     ctl->busy = 0;
-    ctl->idle = 0;
     if (enum_bases) {
       long long cb = 0, vb = 0;
       for (int k = 0; k < CC_HSLOTS; ++k) {

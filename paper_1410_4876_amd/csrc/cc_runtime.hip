@@ -163,36 +163,34 @@ size_t frontier_bytes(unsigned long long cap_s, int W, bool en) {
   return b;
 }
 
-// Carves the depth-first workspace (queue + per-wavefront stacks) out of a
-// region of `bytes`.  Returns the number of wavefronts that fit (<= waves).
+// Carves the depth-first workspace (per-wavefront stacks, mailboxes and
+// inboxes) out of a region of `bytes`.  Returns the number of wavefronts
+// that fit (<= waves, a multiple of 4), 0 if not even 4 fit.
 int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_children,
               DfsWork *wk) {
   DfsWork d{};
   const size_t item = (size_t)W * 8 * (en ? 2 : 1) + 4;
-  unsigned long long qcap = 4096;
-  while (qcap > 16 && qcap * (CC_CHUNK * item + 12) > bytes / 4) qcap >>= 1;
-  size_t off = 0;
-  d.qseq = (unsigned long long *)(base + off);
-  off = align_up(off + qcap * 8, 256);
-  d.qN = (unsigned int *)(base + off);
-  off = align_up(off + qcap * 4, 256);
-  d.qX = (unsigned long long *)(base + off);
-  off = align_up(off + qcap * W * CC_CHUNK * 8, 256);
-  if (en) {
-    d.qS = (unsigned long long *)(base + off);
-    off = align_up(off + qcap * W * CC_CHUNK * 8, 256);
-  }
-  d.qM = (unsigned int *)(base + off);
-  off = align_up(off + qcap * CC_CHUNK * 4, 256);
-  d.qcap = qcap;
-  const size_t rest = bytes > off + 4096 ? bytes - off - 4096 : 0;
   const unsigned long long min_cap = (unsigned long long)CC_CHUNK * (max_children + 2);
+  auto need = [&](int nw, unsigned long long cap_w) {
+    return (size_t)nw * (CC_MAIL * 4 + CC_CHUNK * item + cap_w * item) + 16 * 256;
+  };
   int nw = waves;
-  while (nw > 4 && rest / ((size_t)nw * item) < min_cap) nw -= 4;
-  unsigned long long cap_w = rest / ((size_t)std::max(nw, 1) * item);
-  cap_w = std::min<unsigned long long>(cap_w, 1ull << 20);
-  cap_w &= ~63ull;
+  while (nw > 4 && need(nw, min_cap) > bytes) nw -= 4;
+  if (need(nw, min_cap) > bytes) return 0;
+  unsigned long long cap_w = (bytes - need(nw, 0)) / ((size_t)nw * item);
+  cap_w = std::min<unsigned long long>(cap_w, 1ull << 20) & ~63ull;
   if (cap_w < min_cap) return 0;
+  size_t off = 0;
+  d.mail = (unsigned int *)(base + off);
+  off = align_up(off + (size_t)nw * CC_MAIL * 4, 256);
+  d.inX = (unsigned long long *)(base + off);
+  off = align_up(off + (size_t)nw * W * CC_CHUNK * 8, 256);
+  if (en) {
+    d.inS = (unsigned long long *)(base + off);
+    off = align_up(off + (size_t)nw * W * CC_CHUNK * 8, 256);
+  }
+  d.inM = (unsigned int *)(base + off);
+  off = align_up(off + (size_t)nw * CC_CHUNK * 4, 256);
   d.cap_w = cap_w;
   d.stackX = (unsigned long long *)(base + off);
   off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
@@ -201,8 +199,10 @@ int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_child
     off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
   }
   d.stackM = (unsigned int *)(base + off);
+  d.nwaves = nw;
   d.max_children = max_children;
-  d.donate_check = 4;
+  d.donate_check = 16;
+  d.donate_min = 2 * CC_CHUNK;
   *wk = d;
   return nw;
 }
@@ -251,7 +251,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   }
 
   const int maxc = std::max(1, g->max_deg - 1);
-  int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 8;
+  int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 16;
   waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
   const int want_waves = std::max(4, (g->dev.cus * waves_per_cu) / 4 * 4);
   DfsWork wc[2], we[2];
@@ -264,6 +264,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     (void)hipFreeAsync(arena, s);
     return CC_ERR_OUT_OF_MEMORY;
   }
+  if (g->opt.dfs_donate_min > 0)
+    for (DfsWork *d : {&wc[0], &wc[1], &we[0], &we[1]}) d->donate_min = g->opt.dfs_donate_min;
   const int dfs_blocks_c = nw_c / 4, dfs_blocks_e = nw_e / 4;
   const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 8;
   const int forced = (g->opt.flags & CC_FORCE_DFS) ? std::max(3, (int)g->opt.dfs_level) : -1;
