@@ -147,6 +147,43 @@ cc_status cc_last_run(cc_graph *g, cc_run_info *info);
 /* cc_release -- free a handle and its device memory (NULL is ignored). */
 void cc_release(cc_graph *g);
 
+/* ------------------------------------------------------------- batches
+ * Many small graphs enumerated together (count-only).  The graphs are packed
+ * as one CSR: graph g owns vertices graph_vtx_off[g] .. graph_vtx_off[g+1]
+ * (global ids in row_ptr/col_idx), graph_vtx_off[0] = 0, every graph has at
+ * most CC_MAX_VERTICES vertices and no edge leaves its graph.
+ */
+typedef struct cc_batch cc_batch;
+
+#define CC_BATCH_PERSISTENT 0 /* stage one of all graphs in one launch, then one
+                                 persistent depth-first launch with work stealing */
+#define CC_BATCH_PER_GRAPH  1 /* the same kernels launched once per graph
+                                 (baseline for comparison)                       */
+
+/* cc_prepare_batch -- validate every graph and compute its degree labelling
+ * (one block per graph).  graph_vtx_off has n_graphs+1 entries; with
+ * CC_INPUT_DEVICE all three arrays are device pointers.  Errors as
+ * cc_prepare (NOT_SIMPLE if any graph is not simple). */
+cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const int32_t *row_ptr,
+                           const int32_t *col_idx, const cc_options *opt, cc_batch **out);
+
+/* cc_histogram_batch -- per-graph histograms: hists[g * hist_stride + k] =
+ * cycles with k vertices in graph g (host array, hist_stride >= largest
+ * graph + 1; entries past a graph's size are zero).  mode is
+ * CC_BATCH_PERSISTENT or CC_BATCH_PER_GRAPH; both give the same numbers. */
+cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, int32_t mode);
+
+/* cc_batch_labels -- degree label of every vertex (host array of the total
+ * vertex count, indexed by global id; labels are local to each graph). */
+cc_status cc_batch_labels(cc_batch *b, int32_t *labels);
+
+/* cc_batch_last_run -- statistics of the last cc_histogram_batch call
+ * (levels_launched counts kernel launches; paths is the batch total). */
+cc_status cc_batch_last_run(cc_batch *b, cc_run_info *info);
+
+/* cc_release_batch -- free a batch handle (NULL is ignored). */
+void cc_release_batch(cc_batch *b);
+
 /* cc_status_string -- static English description of a status code. */
 const char *cc_status_string(cc_status s);
 

@@ -31,6 +31,8 @@ CC_OUTPUT_DEVICE = 1 << 1
 CC_FORCE_DFS = 1 << 2
 CC_PROFILE = 1 << 3
 CC_MAX_VERTICES = 128
+CC_BATCH_PERSISTENT = 0
+CC_BATCH_PER_GRAPH = 1
 
 _lock = threading.Lock()
 _lib = None
@@ -98,6 +100,16 @@ def lib():
             L.cc_status_string.restype = ctypes.c_char_p
             L.cc_abi_version.argtypes = []
             L.cc_abi_version.restype = i32
+            L.cc_prepare_batch.argtypes = [i32, vp, vp, vp, ctypes.POINTER(Options), pp]
+            L.cc_prepare_batch.restype = ctypes.c_int
+            L.cc_histogram_batch.argtypes = [vp, vp, i32, i32]
+            L.cc_histogram_batch.restype = ctypes.c_int
+            L.cc_batch_labels.argtypes = [vp, vp]
+            L.cc_batch_labels.restype = ctypes.c_int
+            L.cc_batch_last_run.argtypes = [vp, ctypes.POINTER(RunInfo)]
+            L.cc_batch_last_run.restype = ctypes.c_int
+            L.cc_release_batch.argtypes = [vp]
+            L.cc_release_batch.restype = None
             _lib = L
     return _lib
 
@@ -263,3 +275,71 @@ def _as_i32(x):
 def prepare(g, **kw) -> Graph:
     """cc_prepare on a graphgen.CSR-like object (n, row_ptr, col_idx)."""
     return Graph(g.n, g.row_ptr, g.col_idx, **kw)
+
+
+class Batch:
+    """Many graphs packed as one CSR (cc_prepare_batch)."""
+
+    def __init__(self, graph_vtx_off, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
+                 dfs_waves_per_cu: int = 0, dfs_donate_min: int = 0):
+        L = lib()
+        off, off_dev, k0 = _ptr(_as_i32(graph_vtx_off))
+        rp, rp_dev, k1 = _ptr(_as_i32(row_ptr))
+        ci, ci_dev, k2 = _ptr(_as_i32(col_idx))
+        if not (off_dev == rp_dev == ci_dev):
+            raise ValueError("batch arrays must all be host or all be device")
+        self.n_graphs = int((graph_vtx_off.numel() if _is_torch(graph_vtx_off)
+                             else np.asarray(graph_vtx_off).size) - 1)
+        sizes = np.diff(np.asarray(graph_vtx_off.cpu() if _is_torch(graph_vtx_off)
+                                   else graph_vtx_off, dtype=np.int64))
+        self.sizes = sizes
+        self.n_vertices = int(sizes.sum())
+        self.max_n = int(sizes.max()) if sizes.size else 0
+        flags = CC_INPUT_DEVICE if off_dev else 0
+        self.opt = Options(_stream_handle(stream), int(budget_bytes), flags, 0,
+                           int(dfs_waves_per_cu), 0, int(dfs_donate_min))
+        h = ctypes.c_void_p()
+        st = L.cc_prepare_batch(self.n_graphs, off, rp, ci, ctypes.byref(self.opt), ctypes.byref(h))
+        _check(st, "cc_prepare_batch")
+        self.h = h
+
+    def release(self):
+        if getattr(self, "h", None):
+            lib().cc_release_batch(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.release()
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def histograms(self, per_graph_launch: bool = False) -> np.ndarray:
+        """[n_graphs, max_n + 1] int64: row g is graph g's histogram."""
+        stride = self.max_n + 1
+        out = np.zeros((self.n_graphs, stride), np.int64)
+        mode = CC_BATCH_PER_GRAPH if per_graph_launch else CC_BATCH_PERSISTENT
+        _check(lib().cc_histogram_batch(self.h, ctypes.c_void_p(out.ctypes.data), stride, mode),
+               "cc_histogram_batch")
+        return out
+
+    def labels(self) -> np.ndarray:
+        lab = np.zeros(max(self.n_vertices, 1), np.int32)
+        _check(lib().cc_batch_labels(self.h, ctypes.c_void_p(lab.ctypes.data)), "cc_batch_labels")
+        return lab[:self.n_vertices]
+
+    def last_run(self) -> dict:
+        info = RunInfo()
+        _check(lib().cc_batch_last_run(self.h, ctypes.byref(info)), "cc_batch_last_run")
+        return info.as_dict()
+
+
+def prepare_batch(batch, **kw) -> Batch:
+    """cc_prepare_batch on a graphgen.Batch-like object."""
+    return Batch(batch.graph_vtx_off, batch.row_ptr, batch.col_idx, **kw)

@@ -105,25 +105,51 @@ struct DfsWork {
   unsigned long long *stackX;   // [nwaves][W][cap_w]
   unsigned long long *stackS;   // [nwaves][W][cap_w] (enumerate only)
   unsigned int *stackM;         // [nwaves][cap_w]: v1 | vt<<8 | t<<16 | root<<24
+  unsigned int *stackG;         // [nwaves][cap_w] graph id (batches only)
   unsigned long long cap_w;     // items per wavefront stack
   unsigned int *mail;           // [nwaves][CC_MAIL]
   unsigned long long *inX;      // [nwaves][W][CC_CHUNK] inbox
   unsigned long long *inS;      // [nwaves][W][CC_CHUNK] (enumerate only)
   unsigned int *inM;            // [nwaves][CC_CHUNK]
+  unsigned int *inG;            // [nwaves][CC_CHUNK] (batches only)
   int nwaves;
   int max_children;             // upper bound on extensions of one path
   int donate_check;             // batches between mailbox checks
   int donate_min;               // paths a wavefront must hold before it gives some away
 };
 
+// A batch of graphs packed as one CSR (graph g owns vertices
+// vtx_off[g] .. vtx_off[g+1]).  Its initial triplets sit in one array of
+// root slots; graph g's slots are root_off[g] .. root_off[g+1] (an upper
+// bound on its triplets), unused slots carry gid CC_NO_GRAPH.
+#define CC_NO_GRAPH 0xffffffffu
+struct BatchDev {
+  const int *vtx_off;            // [G+1]
+  const unsigned long long *adj; // label-space rows at (vtx_off[g] + l) * W
+  const int *perm;               // perm[vtx_off[g] + l] = local id of label l
+  const long long *root_off;     // [G+1]
+  unsigned long long *rX;        // root slots: X words, word w at rX[w * rcap + i]
+  unsigned short *rvv;           // root slots: v1 | vt << 8
+  unsigned int *rgid;            // root slots: graph id or CC_NO_GRAPH
+  unsigned long long rcap;
+  unsigned long long r0, r1;     // slots handled by this launch
+  unsigned long long *hist;      // per-graph histograms, graph g at hist[g * hist_stride]
+  int hist_stride;
+  int g0;                        // first graph of this launch (stage one)
+};
+
 // ------------------------------------------------------------------ launchers
 // All return hipSuccess or the launch error.  `W` is 1 (n <= 64) or 2.
 hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s);
 // adj (label space) and adj_orig (original ids) rows are at (v0 + row) * W.
+// bound (may be NULL) receives, per graph, sum over vertices of C(deg, 2):
+// an upper bound on its initial triplets plus triangles.
 hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n_single,
                             const int *row_ptr, const int *col_idx, unsigned long long *adj,
                             unsigned long long *adj_orig, int *perm, int *label,
-                            unsigned int *status, hipStream_t s);
+                            unsigned int *status, long long *bound, hipStream_t s);
+// Stage one of graphs bt.g0 .. bt.g0 + n_graphs - 1 (one block each).
+hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s);
 hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
                               Stage st, hipStream_t s);
 // host_done (pinned host memory, may be NULL) receives the first level that
@@ -140,6 +166,10 @@ hipError_t cc_launch_dfs(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier
                          Frontier f1, DfsWork wk0, DfsWork wk1, OutDev out,
                          unsigned long long *hist_out, int hist_stride, bool count_front,
                          int blocks, unsigned long long idle_timeout, hipStream_t s);
+// Batched depth-first run over the root slots bt.r0 .. bt.r1 (workspace wk).
+hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt,
+                               int blocks, unsigned long long idle_timeout, hipStream_t s);
+// always: reset for a batched run (no breadth-first levels before it).
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, bool enum_bases,
-                                 hipStream_t s);
+                                 bool always, hipStream_t s);
 hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool enumerate, hipStream_t s);

@@ -252,11 +252,13 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
                                                 unsigned long long *__restrict__ adj_orig,
                                                 int *__restrict__ perm_out,
                                                 int *__restrict__ label_out,
-                                                unsigned int *__restrict__ status) {
+                                                unsigned int *__restrict__ status,
+                                                long long *__restrict__ bound) {
   __shared__ unsigned long long sA[CC_MAXN * W];
   __shared__ int sLab[CC_MAXN];
   __shared__ unsigned int sErr;
   __shared__ unsigned int sDeg;
+  __shared__ unsigned long long sPairs;
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
   int v0 = 0, n = n_single;
@@ -267,6 +269,7 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   if (tid == 0) {
     sErr = 0u;
     sDeg = 0u;
+    sPairs = 0ull;
   }
   for (int i = tid; i < CC_MAXN * W; i += blockDim.x) sA[i] = 0ull;
   __syncthreads();
@@ -308,6 +311,7 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
     sA[v * W] = r0;
     if (W == 2) sA[v * W + W - 1] = r1;
     atomicMax(&sDeg, (unsigned)(b - a));
+    atomicAdd(&sPairs, (unsigned long long)((b - a) * (b - a - 1) / 2));
   }
   __syncthreads();
   // symmetry: w in N(v) implies v in N(w)
@@ -358,7 +362,10 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
 #pragma unroll
     for (int k = 0; k < W; ++k) adj_out[(size_t)(v0 + l) * W + k] = out.w[k];
   }
-  if (tid == 0) status[g] = 0x100u | (sDeg << 16);  // bit 8: ok; bits 16..: max degree
+  if (tid == 0) {
+    status[g] = 0x100u | (sDeg << 16);  // bit 8: ok; bits 16..: max degree
+    if (bound) bound[g] = (long long)sPairs;
+  }
 }
 
 // ------------------------------------------------------------- stage one
@@ -426,6 +433,53 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
     ctl->count_sh[s][3] = sTrip > s ? (sTrip - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
     ctl->hist_sh[s][3] = sTri > s ? (sTri - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
   }
+}
+
+// Stage one for a batch: one block per graph, same pairs as k_triplets.
+// Graph g's triplets fill its root slots from root_off[g] in order; the
+// rest of its slots are marked unused; its triangles go to its histogram.
+template <int W>
+__global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
+  __shared__ unsigned long long sN[CC_MAXN * W];
+  __shared__ unsigned int sTrip, sTri;
+  const int g = bt.g0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const int vo = bt.vtx_off[g];
+  const int n = bt.vtx_off[g + 1] - vo;
+  const unsigned long long base = (unsigned long long)bt.root_off[g];
+  const unsigned long long slots = (unsigned long long)(bt.root_off[g + 1] - bt.root_off[g]);
+  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = bt.adj[(size_t)vo * W + i];
+  if (tid == 0) {
+    sTrip = 0u;
+    sTri = 0u;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n * n; idx += CC_BLOCK) {
+    const int u = idx / n, x = idx - u * n;
+    const Bits<W> nu = row<W>(sN, u);
+    if (x <= u || !btest(nu, x)) continue;
+    const Bits<W> nx = row<W>(sN, x);
+    Bits<W> ys = bandnot(nu, low_through<W>(x));
+    while (bany(ys)) {
+      const int y = bpop_lowest(ys);
+      if (btest(nx, y)) {
+        atomicAdd(&sTri, 1u);
+      } else {
+        const unsigned j = atomicAdd(&sTrip, 1u);
+        if (j < slots) {
+          const unsigned long long e = base + j;
+          const Bits<W> X = bor(nu, low_through<W>(u));
+#pragma unroll
+          for (int k = 0; k < W; ++k) bt.rX[k * bt.rcap + e] = X.w[k];
+          bt.rvv[e] = (unsigned short)(x | (y << 8));
+          bt.rgid[e] = (unsigned)g;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (unsigned long long j = sTrip + tid; j < slots; j += CC_BLOCK) bt.rgid[base + j] = CC_NO_GRAPH;
+  if (tid == 0 && sTri) atomicAdd(&bt.hist[(size_t)g * bt.hist_stride + 3], (unsigned long long)sTri);
 }
 
 // ------------------------------------------------------ breadth-first level
@@ -722,34 +776,43 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
 // transit (the donor counts the recipient before answering), so busy == 0
 // with the handed-over frontier exhausted means no work is left anywhere.
 // Cycle counts go to hist_out[(block % CC_SHARDS) * hist_stride + k].
-template <int W, bool ENUM>
+//
+// BATCH: many graphs at once.  Every path carries its graph id; adjacency
+// rows come from device memory (the graphs' rows stay cache-resident);
+// closures go straight to the per-graph histograms (one atomic per distinct
+// (graph, length) in a wavefront batch); the handed-over paths are the
+// batch's initial triplets in bt.r0..bt.r1, padding slots marked
+// CC_NO_GRAPH.  The mailboxes and stacks come from wk1.
+template <int W, bool ENUM, bool BATCH>
 __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Frontier f0,
                                                   Frontier f1, DfsWork wk0, DfsWork wk1,
                                                   OutDev out, unsigned long long *hist_out,
                                                   int hist_stride, int count_front,
-                                                  unsigned long long idle_timeout) {
-  __shared__ unsigned long long sN[CC_MAXN * W];
+                                                  unsigned long long idle_timeout, BatchDev bt) {
+  __shared__ unsigned long long sN[BATCH ? 1 : CC_MAXN * W];
   __shared__ unsigned long long sNo[ENUM ? CC_MAXN * W : 1];
-  __shared__ int sPerm[CC_MAXN];
+  __shared__ int sPerm[BATCH ? 1 : CC_MAXN];
   __shared__ unsigned long long sHist[CC_HSLOTS];
   __shared__ unsigned long long sFront[CC_HSLOTS];
   __shared__ long long sCb[ENUM ? CC_HSLOTS : 1];
   __shared__ long long sVb[ENUM ? CC_HSLOTS : 1];
   __shared__ unsigned long long sPre[CC_SHARDS + 1];
-  if (ld_relaxed(&ctl->mode) == 0) return;
-  const int L = ctl->switch_level;
-  const int skipbits = ctl->skip;
+  if (!BATCH && ld_relaxed(&ctl->mode) == 0) return;
+  const int L = BATCH ? 3 : ctl->switch_level;
+  const int skipbits = BATCH ? 0 : ctl->skip;
   const Frontier roots = (L & 1) ? f1 : f0;
-  const DfsWork wk = (L & 1) ? wk0 : wk1;  // the buffer not holding the roots
+  const DfsWork wk = (BATCH || !(L & 1)) ? wk1 : wk0;  // the buffer not holding the roots
   const int n = g.n;
   const int tid = threadIdx.x;
   const int lane = lane_id();
-  if (tid < CC_WAVE) {
+  if (!BATCH && tid < CC_WAVE) {
     const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][L]);
     shard_prefix(c <= roots.cap_s ? c : roots.cap_s, sPre);
   }
-  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
-  for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
+  if (!BATCH) {
+    for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+    for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
+  }
   for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
     sHist[i] = 0ull;
     sFront[i] = 0ull;
@@ -762,7 +825,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     }
   }
   __syncthreads();
-  const unsigned long long nroots = sPre[CC_SHARDS];
+  const unsigned long long nroots = BATCH ? bt.r1 - bt.r0 : sPre[CC_SHARDS];
 
   const int wid = blockIdx.x * (CC_BLOCK / CC_WAVE) + tid / CC_WAVE;
   const int nwaves = gridDim.x * (CC_BLOCK / CC_WAVE);
@@ -770,6 +833,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   unsigned long long *stX = wk.stackX + (unsigned long long)wid * W * cap;
   unsigned long long *stS = ENUM ? wk.stackS + (unsigned long long)wid * W * cap : nullptr;
   unsigned int *stM = wk.stackM + (unsigned long long)wid * cap;
+  unsigned int *stG = BATCH ? wk.stackG + (unsigned long long)wid * cap : nullptr;
   unsigned int *my_mail = wk.mail + (size_t)wid * CC_MAIL;
   const unsigned long long maxc = (unsigned long long)max(wk.max_children, 1);
   const unsigned long long dmin = (unsigned long long)max(wk.donate_min, 2);
@@ -790,7 +854,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
 
   while (true) {
     Bits<W> X = bzero<W>(), S = bzero<W>();
-    unsigned int m = 0;
+    unsigned int m = 0, gid = 0;
     bool valid = false;
     bool have = false;
     if (top > bot) {
@@ -808,6 +872,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
           for (int w = 0; w < W; ++w) S.w[w] = stS[w * cap + i];
         }
         m = stM[i];
+        if (BATCH) gid = stG[i];
       }
       top = start;
       if (top == bot) top = bot = 0;
@@ -830,15 +895,28 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         valid = (unsigned long long)lane < kk;
         if (valid) {
           const unsigned long long i = r_lo + lane;
-          const int s = shard_of(sPre, i);
-          const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
+          if (BATCH) {
+            const unsigned long long e = bt.r0 + i;
+            gid = bt.rgid[e];
+            valid = gid != CC_NO_GRAPH;
+            if (valid) {
 #pragma unroll
-          for (int w = 0; w < W; ++w) X.w[w] = roots.X[w * roots.cap + e];
-          if (ENUM) {
+              for (int w = 0; w < W; ++w) X.w[w] = bt.rX[w * bt.rcap + e];
+              m = (unsigned)bt.rvv[e] | root_meta;
+            } else {
+              gid = 0;
+            }
+          } else {
+            const int s = shard_of(sPre, i);
+            const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
 #pragma unroll
-            for (int w = 0; w < W; ++w) S.w[w] = roots.S[w * roots.cap + e];
+            for (int w = 0; w < W; ++w) X.w[w] = roots.X[w * roots.cap + e];
+            if (ENUM) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) S.w[w] = roots.S[w * roots.cap + e];
+            }
+            m = (unsigned)roots.vv[e] | root_meta;
           }
-          m = (unsigned)roots.vv[e] | root_meta;
         }
         r_lo += kk;
         have = true;
@@ -942,6 +1020,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
           for (int w = 0; w < W; ++w) S.w[w] = ld_coh(&wk.inS[ib + w * CC_CHUNK + lane]);
         }
         m = ld_coh(&wk.inM[(size_t)wid * CC_CHUNK + lane]);
+        if (BATCH) {
+          gid = ld_coh(&wk.inG[(size_t)wid * CC_CHUNK + lane]);
+          if (gid == CC_NO_GRAPH) {  // a padding slot of the initial triplets
+            valid = false;
+            gid = 0;
+          }
+        }
       }
       wait_mem();
       if (lane == 0) st_coh(&my_mail[1], 0u);
@@ -956,8 +1041,20 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     const bool root = (m >> 24) != 0;
     const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
     const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
-    const Bits<W> nvt = row<W>(sN, vt);
-    const Bits<W> nv1 = row<W>(sN, v1);
+    Bits<W> nvt, nv1;
+    int n_path = n;  // vertices of this path's graph
+    if (BATCH) {
+      const int vo = bt.vtx_off[gid];
+      n_path = bt.vtx_off[gid + 1] - vo;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        nvt.w[w] = bt.adj[(size_t)(vo + vt) * W + w];
+        nv1.w[w] = bt.adj[(size_t)(vo + v1) * W + w];
+      }
+    } else {
+      nvt = row<W>(sN, vt);
+      nv1 = row<W>(sN, v1);
+    }
     const Bits<W> cand = bandnot(nvt, X);
     Bits<W> clos = band(cand, nv1);
     Bits<W> ext = bandnot(cand, nv1);
@@ -975,7 +1072,21 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         act &= ~same;
       }
     }
-    if (count_close) {
+    if (BATCH) {
+      // one global add per distinct (graph, length) among the lanes
+      const unsigned c = count_close ? (unsigned)bpop(clos) : 0u;
+      const unsigned long long key = ((unsigned long long)gid << 8) | (unsigned)(t + 1);
+      unsigned long long act = wave_ballot(c != 0u);
+      while (act) {
+        const unsigned long long k0 = __shfl(key, (int)(__ffsll((long long)act) - 1), CC_WAVE);
+        const unsigned long long same = act & wave_ballot(key == k0);
+        const unsigned sum = wave_sum_u32((same >> lane) & 1ull ? c : 0u);
+        if (lane == 0)
+          atomicAdd(&bt.hist[(size_t)(k0 >> 8) * bt.hist_stride + (k0 & 0xffull)],
+                    (unsigned long long)sum);
+        act &= ~same;
+      }
+    } else if (count_close) {
       const int c = bpop(clos);
       if (c) {
         if (hist_out) atomicAdd(&sHist[t + 1], (unsigned long long)c);
@@ -998,7 +1109,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     // A path never has more than n vertices (each extension adds a vertex
     // outside S, and S is inside X); anything longer would mean corrupted
     // state, so it is dropped and reported instead of looping.
-    if (t >= n && bany(ext)) {
+    if (t >= n_path && bany(ext)) {
       atomicOr(&ctl->status, CC_DEV_STACK_FULL);
       ext = bzero<W>();
     }
@@ -1019,6 +1130,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
               for (int w = 0; w < W; ++w) stS[w * cap + i] = stS[w * cap + bot + i];
             }
             stM[i] = stM[bot + i];
+            if (BATCH) stG[i] = stG[bot + i];
           }
         }
         top = live;
@@ -1045,6 +1157,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
               for (int w = 0; w < W; ++w) stS[w * cap + i] = Sn.w[w];
             }
             stM[i] = mbase | ((unsigned)v << 8);
+            if (BATCH) stG[i] = gid;
           }
           off += __popcll(mask);
         }
@@ -1073,19 +1186,28 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
               min((from_range ? range_left : stack_left) / 2, (unsigned long long)CC_CHUNK);
           const bool mine = (unsigned long long)lane < give;
           Bits<W> dX = bzero<W>(), dS = bzero<W>();
-          unsigned int dm = 0;
+          unsigned int dm = 0, dg = 0;
           if (from_range) {
             if (mine) {
               const unsigned long long i = r_hi - give + lane;
-              const int s = shard_of(sPre, i);
-              const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
+              if (BATCH) {
+                // padding slots travel as paths with no extension
+                const unsigned long long e = bt.r0 + i;
+                dg = bt.rgid[e];
 #pragma unroll
-              for (int w = 0; w < W; ++w) dX.w[w] = roots.X[w * roots.cap + e];
-              if (ENUM) {
+                for (int w = 0; w < W; ++w) dX.w[w] = bt.rX[w * bt.rcap + e];
+                dm = (unsigned)bt.rvv[e] | root_meta;
+              } else {
+                const int s = shard_of(sPre, i);
+                const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
 #pragma unroll
-                for (int w = 0; w < W; ++w) dS.w[w] = roots.S[w * roots.cap + e];
+                for (int w = 0; w < W; ++w) dX.w[w] = roots.X[w * roots.cap + e];
+                if (ENUM) {
+#pragma unroll
+                  for (int w = 0; w < W; ++w) dS.w[w] = roots.S[w * roots.cap + e];
+                }
+                dm = (unsigned)roots.vv[e] | root_meta;
               }
-              dm = (unsigned)roots.vv[e] | root_meta;
             }
             r_hi -= give;
           } else {
@@ -1098,6 +1220,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
                 for (int w = 0; w < W; ++w) dS.w[w] = stS[w * cap + i];
               }
               dm = stM[i];
+              if (BATCH) dg = stG[i];
             }
             bot += give;
             if (top == bot) top = bot = 0;
@@ -1111,6 +1234,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
               for (int w = 0; w < W; ++w) st_coh(&wk.inS[ib + w * CC_CHUNK + lane], dS.w[w]);
             }
             st_coh(&wk.inM[(size_t)q * CC_CHUNK + lane], dm);
+            if (BATCH) st_coh(&wk.inG[(size_t)q * CC_CHUNK + lane], dg);
           }
           if (lane == 0) {
             st_coh(&q_mail[2], (unsigned)give);
@@ -1169,10 +1293,11 @@ __device__ void length_totals(CcCtl *ctl, bool enumerate, unsigned long long *sT
 // Resets the depth-first coordination state (and, for the writing pass of
 // enumerate mode, computes where each cycle length starts in the output).
 // Does nothing when the breadth-first levels finished on their own.
-__global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, int enum_bases) {
+__global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, int enum_bases,
+                              int always) {
   __shared__ unsigned long long sTot[CC_HSLOTS];
-  if (ld_relaxed(&ctl->mode) == 0) return;
-  const DfsWork wk = (ctl->switch_level & 1) ? wk0 : wk1;
+  if (!always && ld_relaxed(&ctl->mode) == 0) return;
+  const DfsWork wk = (!always && (ctl->switch_level & 1)) ? wk0 : wk1;
   const size_t words = (size_t)wk.nwaves * CC_MAIL;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
        i += (size_t)gridDim.x * blockDim.x)
@@ -1224,13 +1349,22 @@ hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s) {
 hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n_single,
                             const int *row_ptr, const int *col_idx, unsigned long long *adj,
                             unsigned long long *adj_orig, int *perm, int *label,
-                            unsigned int *status, hipStream_t s) {
+                            unsigned int *status, long long *bound, hipStream_t s) {
   if (W == 1)
     hipLaunchKernelGGL(k_ingest<1>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
-                       row_ptr, col_idx, adj, adj_orig, perm, label, status);
+                       row_ptr, col_idx, adj, adj_orig, perm, label, status, bound);
   else
     hipLaunchKernelGGL(k_ingest<2>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
-                       row_ptr, col_idx, adj, adj_orig, perm, label, status);
+                       row_ptr, col_idx, adj, adj_orig, perm, label, status, bound);
+  return hipGetLastError();
+}
+
+hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s) {
+  if (n_graphs <= 0) return hipSuccess;
+  if (W == 1)
+    hipLaunchKernelGGL(k_triplets_batch<1>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
+  else
+    hipLaunchKernelGGL(k_triplets_batch<2>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
   return hipGetLastError();
 }
 
@@ -1266,20 +1400,33 @@ hipError_t cc_launch_dfs(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Fr
                          unsigned long long idle_timeout, hipStream_t s) {
   dim3 gr(blocks), bl(CC_BLOCK);
   const int cf = count_front ? 1 : 0;
+  const BatchDev nb{};
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_dfs<1, true>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
-    else hipLaunchKernelGGL((k_dfs<1, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
+    if (en) hipLaunchKernelGGL((k_dfs<1, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
+    else hipLaunchKernelGGL((k_dfs<1, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
   } else {
-    if (en) hipLaunchKernelGGL((k_dfs<2, true>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
-    else hipLaunchKernelGGL((k_dfs<2, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout);
+    if (en) hipLaunchKernelGGL((k_dfs<2, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
+    else hipLaunchKernelGGL((k_dfs<2, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
   }
   return hipGetLastError();
 }
 
+hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,
+                               unsigned long long idle_timeout, hipStream_t s) {
+  dim3 gr(blocks), bl(CC_BLOCK);
+  const Frontier nf{};
+  const OutDev no{};
+  if (W == 1)
+    hipLaunchKernelGGL((k_dfs<1, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, wk, no, nullptr, 0, 1, idle_timeout, bt);
+  else
+    hipLaunchKernelGGL((k_dfs<2, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, wk, no, nullptr, 0, 1, idle_timeout, bt);
+  return hipGetLastError();
+}
+
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, bool enum_bases,
-                                 hipStream_t s) {
+                                 bool always, hipStream_t s) {
   hipLaunchKernelGGL(k_dfs_prepare, dim3(64), dim3(256), 0, s, ctl, wk0, wk1, n,
-                     enum_bases ? 1 : 0);
+                     enum_bases ? 1 : 0, always ? 1 : 0);
   return hipGetLastError();
 }
 

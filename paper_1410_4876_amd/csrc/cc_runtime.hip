@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "cc.h"
 #include "cc_internal.h"
@@ -167,9 +168,9 @@ size_t frontier_bytes(unsigned long long cap_s, int W, bool en) {
 // inboxes) out of a region of `bytes`.  Returns the number of wavefronts
 // that fit (<= waves, a multiple of 4), 0 if not even 4 fit.
 int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_children,
-              DfsWork *wk) {
+              DfsWork *wk, bool batch = false) {
   DfsWork d{};
-  const size_t item = (size_t)W * 8 * (en ? 2 : 1) + 4;
+  const size_t item = (size_t)W * 8 * (en ? 2 : 1) + 4 + (batch ? 4 : 0);
   const unsigned long long min_cap = (unsigned long long)CC_CHUNK * (max_children + 2);
   auto need = [&](int nw, unsigned long long cap_w) {
     return (size_t)nw * (CC_MAIL * 4 + CC_CHUNK * item + cap_w * item) + 16 * 256;
@@ -191,6 +192,10 @@ int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_child
   }
   d.inM = (unsigned int *)(base + off);
   off = align_up(off + (size_t)nw * CC_CHUNK * 4, 256);
+  if (batch) {
+    d.inG = (unsigned int *)(base + off);
+    off = align_up(off + (size_t)nw * CC_CHUNK * 4, 256);
+  }
   d.cap_w = cap_w;
   d.stackX = (unsigned long long *)(base + off);
   off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
@@ -199,6 +204,8 @@ int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_child
     off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
   }
   d.stackM = (unsigned int *)(base + off);
+  off = align_up(off + (size_t)nw * cap_w * 4, 256);
+  if (batch) d.stackG = (unsigned int *)(base + off);
   d.nwaves = nw;
   d.max_children = max_children;
   d.donate_check = 16;
@@ -310,12 +317,12 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   // Depth-first continuation (each kernel returns at once if the levels
   // finished within the budget).
   mark(2 * n + 2);
-  chk(cc_launch_dfs_prepare(ctl, wc[0], wc[1], n, false, s));
+  chk(cc_launch_dfs_prepare(ctl, wc[0], wc[1], n, false, false, s));
   if (en) {
     chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc[0], wc[1], ro.out,
                       dev_field(ctl, offsetof(CcCtl, dfs_hist)), 0, true, dfs_blocks_c,
                       idle_timeout, s));
-    chk(cc_launch_dfs_prepare(ctl, we[0], we[1], n, true, s));
+    chk(cc_launch_dfs_prepare(ctl, we[0], we[1], n, true, false, s));
     chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we[0], we[1], ro.out, nullptr, 0, false,
                       dfs_blocks_e, idle_timeout, s));
   } else {
@@ -514,7 +521,7 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
     d_ci = (const int *)((char *)tmp + rb);
   }
   hipError_t e = cc_launch_ingest(g->W, 1, nullptr, n, d_rp, d_ci, g->d_adj, g->d_adj_orig, g->d_perm,
-                                  g->d_label, g->d_status, s);
+                                  g->d_label, g->d_status, nullptr, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&g->h_ctl->status, g->d_status, 4, hipMemcpyDeviceToHost, s);
   if (tmp) (void)hipFreeAsync(tmp, s);
@@ -662,3 +669,302 @@ void cc_release(cc_graph *g) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct cc_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  cc_options opt{};
+  DeviceInfo dev{};
+  int32_t G = 0;
+  int32_t N = 0;
+  int W = 1;
+  int max_n = 0;
+  int max_deg = 0;
+  std::vector<int32_t> vtx_off;        // host copy
+  std::vector<long long> root_off;     // host copy, [G+1]
+  void *d_blob = nullptr;              // vtx_off | root_off | adj | adj_orig | perm | label | status | bound | ctl
+  int *d_vtx_off = nullptr;
+  long long *d_root_off = nullptr;
+  unsigned long long *d_adj = nullptr;
+  unsigned long long *d_adj_orig = nullptr;
+  int *d_perm = nullptr;
+  int *d_label = nullptr;
+  unsigned int *d_status = nullptr;
+  long long *d_bound = nullptr;
+  CcCtl *d_ctl = nullptr;
+  CcCtl *h_ctl = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  cc_run_info info{};
+};
+
+extern "C" {
+
+void cc_release_batch(cc_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  if (b->d_blob) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(b->d_blob);
+  }
+  if (b->h_ctl) (void)hipHostFree(b->h_ctl);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  delete b;
+}
+
+cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const int32_t *row_ptr,
+                           const int32_t *col_idx, const cc_options *opt, cc_batch **out) {
+  if (!out) return CC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n_graphs < 0 || !graph_vtx_off || (n_graphs > 0 && !row_ptr)) return CC_ERR_INVALID_ARG;
+  const uint32_t flags = opt ? opt->flags : 0u;
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE))
+    return CC_ERR_INVALID_ARG;
+  if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0)) return CC_ERR_INVALID_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CC_ERR_NO_DEVICE;
+  DeviceInfo di;
+  cc_status st = device_info(dev, &di);
+  if (st != CC_OK) return st;
+  // sizes and offsets are needed on the host
+  std::vector<int32_t> off((size_t)n_graphs + 1);
+  int32_t nnz = 0;
+  if (flags & CC_INPUT_DEVICE) {
+    if (hipMemcpy(off.data(), graph_vtx_off, off.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return CC_ERR_DEVICE;
+  } else {
+    std::memcpy(off.data(), graph_vtx_off, off.size() * 4);
+  }
+  if (off[0] != 0) return CC_ERR_INVALID_ARG;
+  int max_n = 0;
+  for (int g = 0; g < n_graphs; ++g) {
+    const int ng = off[g + 1] - off[g];
+    if (ng < 0) return CC_ERR_INVALID_ARG;
+    if (ng > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
+    max_n = std::max(max_n, ng);
+  }
+  const int32_t N = off[n_graphs];
+  if (n_graphs > 0) {
+    if (flags & CC_INPUT_DEVICE) {
+      if (hipMemcpy(&nnz, row_ptr + N, 4, hipMemcpyDeviceToHost) != hipSuccess) return CC_ERR_DEVICE;
+    } else {
+      nnz = row_ptr[N];
+      if (row_ptr[0] != 0) return CC_ERR_NOT_SIMPLE;
+    }
+    if (nnz < 0) return CC_ERR_NOT_SIMPLE;
+    if (nnz > 0 && !col_idx) return CC_ERR_INVALID_ARG;
+  }
+  cc_batch *b = new cc_batch();
+  auto fail = [&](cc_status s2) {
+    cc_release_batch(b);
+    return s2;
+  };
+  b->device = dev;
+  b->dev = di;
+  if (opt) b->opt = *opt;
+  b->stream = (hipStream_t)b->opt.stream;
+  b->G = n_graphs;
+  b->N = N;
+  b->W = max_n <= 64 ? 1 : 2;
+  b->max_n = max_n;
+  b->vtx_off = off;
+  const size_t Np = (size_t)std::max(N, 1);
+  const size_t Gp = (size_t)n_graphs + 1;
+  const size_t sz_off = align_up(Gp * 4, 256), sz_roff = align_up(Gp * 8, 256);
+  const size_t sz_adj = align_up(Np * b->W * 8, 256), sz_vec = align_up(Np * 4, 256);
+  const size_t sz_st = align_up(Gp * 4, 256), sz_bd = align_up(Gp * 8, 256);
+  const size_t blob = sz_off + sz_roff + 2 * sz_adj + 2 * sz_vec + sz_st + sz_bd +
+                      align_up(sizeof(CcCtl), 256);
+  if (hipMalloc(&b->d_blob, blob) != hipSuccess) return fail(CC_ERR_OUT_OF_MEMORY);
+  char *p = (char *)b->d_blob;
+  b->d_vtx_off = (int *)p; p += sz_off;
+  b->d_root_off = (long long *)p; p += sz_roff;
+  b->d_adj = (unsigned long long *)p; p += sz_adj;
+  b->d_adj_orig = (unsigned long long *)p; p += sz_adj;
+  b->d_perm = (int *)p; p += sz_vec;
+  b->d_label = (int *)p; p += sz_vec;
+  b->d_status = (unsigned int *)p; p += sz_st;
+  b->d_bound = (long long *)p; p += sz_bd;
+  b->d_ctl = (CcCtl *)p;
+  if (hipHostMalloc((void **)&b->h_ctl, sizeof(CcCtl), hipHostMallocDefault) != hipSuccess)
+    return fail(CC_ERR_OUT_OF_MEMORY);
+  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
+    return fail(CC_ERR_DEVICE);
+  b->root_off.assign(Gp, 0);
+  if (n_graphs == 0) {
+    *out = b;
+    return CC_OK;
+  }
+  hipStream_t s = b->stream;
+  const int *d_rp = row_ptr, *d_ci = col_idx;
+  void *tmp = nullptr;
+  if (hipMemcpyAsync(b->d_vtx_off, off.data(), Gp * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(CC_ERR_DEVICE);
+  if (!(flags & CC_INPUT_DEVICE)) {
+    const size_t rb = align_up(((size_t)N + 1) * 4, 256);
+    if (hipMallocAsync(&tmp, rb + (size_t)std::max(nnz, 1) * 4, s) != hipSuccess)
+      return fail(CC_ERR_OUT_OF_MEMORY);
+    if (hipMemcpyAsync(tmp, row_ptr, ((size_t)N + 1) * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync((char *)tmp + rb, col_idx, (size_t)nnz * 4,
+                                   hipMemcpyHostToDevice, s) != hipSuccess)) {
+      (void)hipFreeAsync(tmp, s);
+      (void)hipStreamSynchronize(s);
+      return fail(CC_ERR_DEVICE);
+    }
+    d_rp = (const int *)tmp;
+    d_ci = (const int *)((char *)tmp + rb);
+  }
+  std::vector<unsigned int> stat((size_t)n_graphs);
+  std::vector<long long> bound((size_t)n_graphs);
+  hipError_t e = cc_launch_ingest(b->W, n_graphs, b->d_vtx_off, 0, d_rp, d_ci, b->d_adj,
+                                  b->d_adj_orig, b->d_perm, b->d_label, b->d_status, b->d_bound, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stat.data(), b->d_status, (size_t)n_graphs * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bound.data(), b->d_bound, (size_t)n_graphs * 8, hipMemcpyDeviceToHost, s);
+  if (tmp) (void)hipFreeAsync(tmp, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(hip_err(e));
+  for (int g = 0; g < n_graphs; ++g) {
+    if ((stat[g] & 0xffu) != 0u || !(stat[g] & 0x100u)) return fail(CC_ERR_NOT_SIMPLE);
+    b->max_deg = std::max(b->max_deg, (int)(stat[g] >> 16));
+    b->root_off[g + 1] = b->root_off[g] + bound[g];
+  }
+  if (hipMemcpyAsync(b->d_root_off, b->root_off.data(), Gp * 8, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(CC_ERR_DEVICE);
+  *out = b;
+  return CC_OK;
+}
+
+cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, int32_t mode) {
+  if (!b || !hists || hist_stride < b->max_n + 1) return CC_ERR_INVALID_ARG;
+  if (mode != CC_BATCH_PERSISTENT && mode != CC_BATCH_PER_GRAPH) return CC_ERR_INVALID_ARG;
+  if (hipSetDevice(b->device) != hipSuccess) return CC_ERR_DEVICE;
+  const int G = b->G;
+  for (size_t i = 0; i < (size_t)G * hist_stride; ++i) hists[i] = 0;
+  b->info = cc_run_info{};
+  if (G == 0) return CC_OK;
+  hipStream_t s = b->stream;
+  const int W = b->W;
+  const int dstride = b->max_n + 2;
+  const unsigned long long rcap = std::max<long long>(b->root_off[G], 1);
+  const int maxc = std::max(1, b->max_deg - 1);
+  int waves_per_cu = b->opt.dfs_waves_per_cu > 0 ? b->opt.dfs_waves_per_cu : 16;
+  waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
+  const bool per_graph = mode == CC_BATCH_PER_GRAPH;
+  // per-graph launches use a small grid: at most 64 blocks per graph
+  const int want_waves = per_graph ? 256 : std::max(4, (b->dev.cus * waves_per_cu) / 4 * 4);
+  const int64_t budget = b->opt.frontier_budget_bytes > 0 ? b->opt.frontier_budget_bytes
+                                                          : kDefaultBudget;
+  // workspace: root slots (X words, end vertices, graph id), per-graph
+  // histograms, and the depth-first stacks in the rest of the budget
+  const size_t roots_b = align_up(rcap * W * 8, 256) + align_up(rcap * 2, 256) +
+                         align_up(rcap * 4, 256);
+  const size_t hist_b = align_up((size_t)G * dstride * 8, 256);
+  const size_t stack_b = (size_t)std::max<int64_t>(budget / 2, (int64_t)64 << 20);
+  char *arena = nullptr;
+  CC_TRY(hipMallocAsync((void **)&arena, roots_b + hist_b + stack_b, s));
+  BatchDev bt{};
+  bt.vtx_off = b->d_vtx_off;
+  bt.adj = b->d_adj;
+  bt.perm = b->d_perm;
+  bt.root_off = b->d_root_off;
+  bt.rX = (unsigned long long *)arena;
+  bt.rvv = (unsigned short *)(arena + align_up(rcap * W * 8, 256));
+  bt.rgid = (unsigned int *)(arena + align_up(rcap * W * 8, 256) + align_up(rcap * 2, 256));
+  bt.rcap = rcap;
+  bt.hist = (unsigned long long *)(arena + roots_b);
+  bt.hist_stride = dstride;
+  DfsWork wk{};
+  const int nw = carve_dfs(arena + roots_b + hist_b, stack_b, W, false, want_waves, maxc, &wk, true);
+  if (nw < 4) {
+    (void)hipFreeAsync(arena, s);
+    return CC_ERR_OUT_OF_MEMORY;
+  }
+  if (b->opt.dfs_donate_min > 0) wk.donate_min = b->opt.dfs_donate_min;
+  const unsigned long long idle_timeout =
+      (unsigned long long)(kIdleTimeoutSeconds * (double)b->dev.clock_hz);
+  GraphDev gd{b->d_adj, b->d_adj_orig, b->d_perm, b->max_n};
+  CcCtl *ctl = b->d_ctl;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  };
+  chk(hipEventRecord(b->ev0, s));
+  chk(cc_launch_zero(ctl, sizeof(CcCtl), s));
+  chk(cc_launch_zero(bt.hist, hist_b, s));
+  int launches = 0;
+  if (!per_graph) {
+    // one launch for stage one of every graph, one persistent depth-first
+    // launch over all their initial triplets
+    bt.g0 = 0;
+    chk(cc_launch_triplets_batch(W, bt, G, s));
+    bt.r0 = 0;
+    bt.r1 = (unsigned long long)b->root_off[G];
+    chk(cc_launch_dfs_prepare(ctl, wk, wk, b->max_n, false, true, s));
+    chk(cc_launch_dfs_batch(W, gd, ctl, wk, bt, nw / 4, idle_timeout, s));
+    launches = 3;
+  } else {
+    // the same kernels, one graph at a time
+    for (int g = 0; g < G && e == hipSuccess; ++g) {
+      bt.g0 = g;
+      chk(cc_launch_triplets_batch(W, bt, 1, s));
+      bt.r0 = (unsigned long long)b->root_off[g];
+      bt.r1 = (unsigned long long)b->root_off[g + 1];
+      const unsigned long long slots = bt.r1 - bt.r0;
+      const int blocks = (int)std::min<unsigned long long>(nw / 4, std::max(1ull, (slots + 255) / 256));
+      chk(cc_launch_dfs_prepare(ctl, wk, wk, b->max_n, false, true, s));
+      chk(cc_launch_dfs_batch(W, gd, ctl, wk, bt, blocks, idle_timeout, s));
+      launches += 3;
+    }
+  }
+  chk(hipEventRecord(b->ev1, s));
+  std::vector<unsigned long long> hh((size_t)G * dstride);
+  chk(hipMemcpyAsync(hh.data(), bt.hist, hh.size() * 8, hipMemcpyDeviceToHost, s));
+  const size_t tail = offsetof(CcCtl, hist);
+  chk(hipMemcpyAsync((char *)b->h_ctl + tail, (char *)ctl + tail, sizeof(CcCtl) - tail,
+                     hipMemcpyDeviceToHost, s));
+  chk(hipFreeAsync(arena, s));
+  chk(hipStreamSynchronize(s));
+  if (e != hipSuccess) return hip_err(e);
+  int64_t cycles = 0, paths = 0;
+  for (int g = 0; g < G; ++g) {
+    const int ng = b->vtx_off[g + 1] - b->vtx_off[g];
+    for (int k = 0; k <= ng; ++k) {
+      hists[(size_t)g * hist_stride + k] = (int64_t)hh[(size_t)g * dstride + k];
+      cycles += (int64_t)hh[(size_t)g * dstride + k];
+    }
+  }
+  for (int t = 0; t < CC_HSLOTS; ++t) paths += (int64_t)b->h_ctl->front[t];
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
+  b->info.cycles = cycles;
+  b->info.paths = paths;
+  b->info.levels_launched = launches;
+  b->info.gpu_ms = ms;
+  if (b->h_ctl->status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
+  return CC_OK;
+}
+
+cc_status cc_batch_last_run(cc_batch *b, cc_run_info *info) {
+  if (!b || !info) return CC_ERR_INVALID_ARG;
+  *info = b->info;
+  return CC_OK;
+}
+
+cc_status cc_batch_labels(cc_batch *b, int32_t *labels) {
+  if (!b || !labels) return CC_ERR_INVALID_ARG;
+  if (b->N == 0) return CC_OK;
+  if (hipSetDevice(b->device) != hipSuccess ||
+      hipMemcpyAsync(labels, b->d_label, (size_t)b->N * 4, hipMemcpyDeviceToHost, b->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return CC_ERR_DEVICE;
+  return CC_OK;
+}
+
+}  // extern "C"
+
