@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -37,12 +39,50 @@ def cpu_baseline(g, budget_s=30.0):
                       f"{dt:.1f} s, single thread)"}
 
 
+def batched_section(args):
+    """4096 ER graphs (n in [16, 64], d in [2.5, 5]): per-graph histograms
+    with one persistent launch (autotuned on a held-out calibration batch)
+    against the same kernels launched once per graph."""
+    import torch
+
+    from paper_1410_4876_amd import autotune, cc
+    from paper_1410_4876_amd import graphgen as gg
+
+    tuned = autotune.tune_batch()
+    b = gg.workload_batch4096()
+    with cc.prepare_batch(b, **tuned["options"]) as h:
+        h.histograms()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            hist = h.histograms()
+        dt = (time.perf_counter() - t0) / args.steps
+        cycles = int(hist.sum())
+        paths = h.last_run()["paths"]
+        t0 = time.perf_counter()
+        hist_pg = h.histograms(per_graph_launch=True)
+        dt_pg = time.perf_counter() - t0
+        launches_pg = h.last_run()["levels_launched"]
+    assert np.array_equal(hist, hist_pg)
+    return {"workload": "4096 ER graphs, n in [16,64], d in [2.5,5]", "cycles": cycles,
+            "paths_expanded": int(paths),
+            "persistent": {"ms": round(dt * 1e3, 3), "cycles_per_s": round(cycles / dt, 1),
+                           "launches": 3},
+            "per_graph_launch": {"ms": round(dt_pg * 1e3, 3),
+                                 "cycles_per_s": round(cycles / dt_pg, 1),
+                                 "launches": int(launches_pg)},
+            "speedup": round(dt_pg / dt, 2),
+            "autotuned": tuned["options"], "autotune_calibration_ms": tuned["ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 4096-graph batched vs per-graph-launch comparison")
     ap.add_argument("--no-profile", action="store_true",
                     help="time steps without per-kernel HIP events (no roofline)")
     args = ap.parse_args()
@@ -52,7 +92,6 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1410_4876_amd import cc
@@ -125,6 +164,8 @@ def main():
             "stage1": round(sum(i["stage1_ms"] for i in pinfos) / len(pinfos), 4),
             "levels": round(lvl_ms / len(pinfos), 4),
             "dfs": round(sum(i["dfs_ms"] for i in pinfos) / len(pinfos), 4)}
+    if not args.no_batch:
+        out["batched"] = batched_section(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g)
     print(json.dumps(out), flush=True)

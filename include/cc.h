@@ -74,6 +74,8 @@ typedef struct cc_options {
   int32_t bfs_blocks;            /* grid of the level kernel; 0 = default                */
   int32_t dfs_donate_min;        /* depth-first: a wavefront donates work to idle ones once
                                     it holds at least this many paths; 0 = default      */
+  int32_t dfs_claim;             /* depth-first: handed-over paths claimed per atomic
+                                    (multiple of 64); 0 = sized from the frontier       */
 } cc_options;
 
 typedef struct cc_graph cc_graph;

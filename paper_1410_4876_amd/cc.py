@@ -51,7 +51,8 @@ class Options(ctypes.Structure):
                 ("dfs_level", ctypes.c_int32),
                 ("dfs_waves_per_cu", ctypes.c_int32),
                 ("bfs_blocks", ctypes.c_int32),
-                ("dfs_donate_min", ctypes.c_int32)]
+                ("dfs_donate_min", ctypes.c_int32),
+                ("dfs_claim", ctypes.c_int32)]
 
 
 class RunInfo(ctypes.Structure):
@@ -154,7 +155,7 @@ class Graph:
     def __init__(self, n, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
                  force_dfs_level: int | None = None, dfs_waves_per_cu: int = 0,
                  bfs_blocks: int = 0, output_device: bool = True, profile: bool = False,
-                 dfs_donate_min: int = 0):
+                 dfs_donate_min: int = 0, dfs_claim: int = 0):
         L = lib()
         rp, rp_dev, self._k1 = _ptr(_as_i32(row_ptr))
         ci, ci_dev, self._k2 = _ptr(_as_i32(col_idx))
@@ -171,7 +172,7 @@ class Graph:
             flags |= CC_PROFILE
         self.opt = Options(_stream_handle(stream), int(budget_bytes), flags,
                            int(force_dfs_level or 0), int(dfs_waves_per_cu), int(bfs_blocks),
-                           int(dfs_donate_min))
+                           int(dfs_donate_min), int(dfs_claim))
         self.n = int(n)
         self.output_device = output_device
         h = ctypes.c_void_p()
@@ -281,7 +282,7 @@ class Batch:
     """Many graphs packed as one CSR (cc_prepare_batch)."""
 
     def __init__(self, graph_vtx_off, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
-                 dfs_waves_per_cu: int = 0, dfs_donate_min: int = 0):
+                 dfs_waves_per_cu: int = 0, dfs_donate_min: int = 0, dfs_claim: int = 0):
         L = lib()
         off, off_dev, k0 = _ptr(_as_i32(graph_vtx_off))
         rp, rp_dev, k1 = _ptr(_as_i32(row_ptr))
@@ -297,7 +298,7 @@ class Batch:
         self.max_n = int(sizes.max()) if sizes.size else 0
         flags = CC_INPUT_DEVICE if off_dev else 0
         self.opt = Options(_stream_handle(stream), int(budget_bytes), flags, 0,
-                           int(dfs_waves_per_cu), 0, int(dfs_donate_min))
+                           int(dfs_waves_per_cu), 0, int(dfs_donate_min), int(dfs_claim))
         h = ctypes.c_void_p()
         st = L.cc_prepare_batch(self.n_graphs, off, rp, ci, ctypes.byref(self.opt), ctypes.byref(h))
         _check(st, "cc_prepare_batch")

@@ -116,6 +116,7 @@ struct DfsWork {
   int max_children;             // upper bound on extensions of one path
   int donate_check;             // batches between mailbox checks
   int donate_min;               // paths a wavefront must hold before it gives some away
+  int claim;                    // handed-over paths per claim; 0 = sized from the frontier
 };
 
 // A batch of graphs packed as one CSR (graph g owns vertices

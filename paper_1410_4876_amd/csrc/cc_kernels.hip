@@ -841,9 +841,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   // Claim size: up to CC_ROOT_CLAIM paths, but small enough that every
   // wavefront gets several claims when the handed-over frontier is small.
   const unsigned long long claim =
-      max((unsigned long long)CC_CHUNK,
-          min((unsigned long long)CC_ROOT_CLAIM,
-              nroots / ((unsigned long long)nwaves * 4) / CC_CHUNK * CC_CHUNK));
+      wk.claim > 0 ? (unsigned long long)wk.claim
+                   : max((unsigned long long)CC_CHUNK,
+                         min((unsigned long long)CC_ROOT_CLAIM,
+                             nroots / ((unsigned long long)nwaves * 4) / CC_CHUNK * CC_CHUNK));
 
   unsigned long long bot = 0, top = 0;     // live stack entries [bot, top)
   unsigned long long r_lo = 0, r_hi = 0;   // private range of handed-over paths

@@ -271,8 +271,10 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     (void)hipFreeAsync(arena, s);
     return CC_ERR_OUT_OF_MEMORY;
   }
-  if (g->opt.dfs_donate_min > 0)
-    for (DfsWork *d : {&wc[0], &wc[1], &we[0], &we[1]}) d->donate_min = g->opt.dfs_donate_min;
+  for (DfsWork *d : {&wc[0], &wc[1], &we[0], &we[1]}) {
+    if (g->opt.dfs_donate_min > 0) d->donate_min = g->opt.dfs_donate_min;
+    d->claim = g->opt.dfs_claim > 0 ? (g->opt.dfs_claim + CC_CHUNK - 1) / CC_CHUNK * CC_CHUNK : 0;
+  }
   const int dfs_blocks_c = nw_c / 4, dfs_blocks_e = nw_e / 4;
   const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 8;
   const int forced = (g->opt.flags & CC_FORCE_DFS) ? std::max(3, (int)g->opt.dfs_level) : -1;
@@ -445,7 +447,9 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   const uint32_t flags = opt ? opt->flags : 0u;
   if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE))
     return CC_ERR_INVALID_ARG;
-  if (opt && opt->frontier_budget_bytes < 0) return CC_ERR_INVALID_ARG;
+  if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
+              opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))
+    return CC_ERR_INVALID_ARG;
   if ((flags & CC_FORCE_DFS) && opt->dfs_level < 3) return CC_ERR_INVALID_ARG;
   int64_t nnz = 0;
   if (n > 0 && !(flags & CC_INPUT_DEVICE)) {
@@ -721,7 +725,9 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   const uint32_t flags = opt ? opt->flags : 0u;
   if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE))
     return CC_ERR_INVALID_ARG;
-  if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0)) return CC_ERR_INVALID_ARG;
+  if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
+              opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))
+    return CC_ERR_INVALID_ARG;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return CC_ERR_NO_DEVICE;
   DeviceInfo di;
@@ -885,6 +891,7 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
     return CC_ERR_OUT_OF_MEMORY;
   }
   if (b->opt.dfs_donate_min > 0) wk.donate_min = b->opt.dfs_donate_min;
+  wk.claim = b->opt.dfs_claim > 0 ? (b->opt.dfs_claim + CC_CHUNK - 1) / CC_CHUNK * CC_CHUNK : 0;
   const unsigned long long idle_timeout =
       (unsigned long long)(kIdleTimeoutSeconds * (double)b->dev.clock_hz);
   GraphDev gd{b->d_adj, b->d_adj_orig, b->d_perm, b->max_n};

@@ -76,11 +76,13 @@ def test_argument_errors_before_any_device_call(L):
     assert L.cc_prepare(129, rp, ci, None, ctypes.byref(h)) == cc.CC_ERR_TOO_LARGE
     assert L.cc_prepare(2, rp, ci, None, None) == cc.CC_ERR_INVALID_ARG
     assert L.cc_prepare(2, None, ci, None, ctypes.byref(h)) == cc.CC_ERR_INVALID_ARG
-    bad = cc.Options(None, 0, 1 << 7, 0, 0, 0, 0)
+    bad = cc.Options(None, 0, 1 << 7, 0, 0, 0, 0, 0)
     assert L.cc_prepare(2, rp, ci, ctypes.byref(bad), ctypes.byref(h)) == cc.CC_ERR_INVALID_ARG
-    neg = cc.Options(None, -5, 0, 0, 0, 0, 0)
+    neg = cc.Options(None, -5, 0, 0, 0, 0, 0, 0)
     assert L.cc_prepare(2, rp, ci, ctypes.byref(neg), ctypes.byref(h)) == cc.CC_ERR_INVALID_ARG
-    forced = cc.Options(None, 0, cc.CC_FORCE_DFS, 2, 0, 0, 0)
+    neg_claim = cc.Options(None, 0, 0, 0, 0, 0, 0, -64)
+    assert L.cc_prepare(2, rp, ci, ctypes.byref(neg_claim), ctypes.byref(h)) == cc.CC_ERR_INVALID_ARG
+    forced = cc.Options(None, 0, cc.CC_FORCE_DFS, 2, 0, 0, 0, 0)
     assert L.cc_prepare(2, rp, ci, ctypes.byref(forced), ctypes.byref(h)) == cc.CC_ERR_INVALID_ARG
     # host CSR whose header cannot describe a simple graph
     rp_bad = (ctypes.c_int32 * 3)(1, 1, 2)
