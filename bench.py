@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only time a plain 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 4096-graph batched vs per-graph-launch comparison")
     ap.add_argument("--no-profile", action="store_true",
@@ -98,6 +100,23 @@ def main():
     from paper_1410_4876_amd import graphgen as gg
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # A plain copy of known size: what the HBM byte counters read for it
+        # scales the counters read for the level kernel.
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(args.steps, 1)
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": src.numel() * 4,
+                          "ms": round(dt * 1e3, 4),
+                          "GBps_read_plus_write": round(2 * src.numel() * 4 / dt / 1e9, 1)}))
+        return
     g = gg.workload_grid8x8()
     rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
     ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
