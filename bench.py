@@ -23,6 +23,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+PROFILE = os.path.join(ROOT, "profiles", "k_level_grid8x8_enumerate.md")
+KERNELS = os.path.join(ROOT, "paper_1410_4876_amd", "csrc", "cc_kernels.hip")
+
+
+def counted_traffic():
+    """HBM bytes per level launch from the committed rocprofv3 PMC summary,
+    or None when the kernel source has changed since the counters were
+    taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+        data = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = hashlib.sha256(open(KERNELS, "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    return data["traffic_bytes_per_launch"] if data.get("kernel_source_sha256") == src else None
 
 
 def cpu_baseline(g, budget_s=30.0):
@@ -174,7 +191,8 @@ def main():
         out["roofline"] = {"bound": "hbm",
                            "kernel": "k_level (breadth-first level with staged-cycle decode)",
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                           "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                           "traffic": counted_traffic(),
                            "bytes_per_launch": round(lvl_bytes / max(launches, 1), 1),
                            "avg_launch_us": round(lvl_ms * 1e3 / max(launches, 1), 3),
                            "launches_per_step": round(launches / len(pinfos), 1),
