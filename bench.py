@@ -92,6 +92,25 @@ def batched_section(args):
             "autotuned": tuned["options"], "autotune_calibration_ms": tuned["ms"]}
 
 
+def serving_section(args):
+    """Open-loop Poisson request stream (2000 requests/s; half p x q grids,
+    p, q in 3..7, half ER graphs, n in 20..80, d in [3, 5]) replayed against
+    the serving loop; p50/p99 latency beside throughput."""
+    from paper_1410_4876_amd import cc, loadgen
+    from paper_1410_4876_amd import graphgen as gg
+
+    reqs = gg.request_stream(rate_hz=2000.0, duration_s=args.serve_seconds, k=5)
+    with cc.Server() as sv:
+        # warm-up: a short stream of its own, not part of the figures
+        loadgen.run_stream(sv, gg.request_stream(rate_hz=2000.0, duration_s=0.2, k=1005))
+        r = loadgen.run_stream(sv, reqs)
+    out = {k: v for k, v in r.items() if k not in ("hists", "statuses")}
+    out["workload"] = (f"Poisson stream at 2000 requests/s for {args.serve_seconds:g} s: "
+                       "grids p x q (p, q in 3..7) and ER graphs (n in 20..80, d in [3,5]), "
+                       "ids permuted")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +121,9 @@ def main():
                     help="only time a plain 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 4096-graph batched vs per-graph-launch comparison")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the replayed request stream (the full stream is 60 s)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-profile", action="store_true",
                     help="time steps without per-kernel HIP events (no roofline)")
     args = ap.parse_args()
@@ -203,6 +225,8 @@ def main():
             "dfs": round(sum(i["dfs_ms"] for i in pinfos) / len(pinfos), 4)}
     if not args.no_batch:
         out["batched"] = batched_section(args)
+    if not args.no_serve:
+        out["serving"] = serving_section(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g)
     print(json.dumps(out), flush=True)

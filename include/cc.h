@@ -55,7 +55,11 @@ typedef enum cc_status {
   CC_ERR_BUFFER_TOO_SMALL = -4, /* output buffer too small; sizes reported     */
   CC_ERR_OUT_OF_MEMORY = -5,    /* device allocation failed / budget too small */
   CC_ERR_DEVICE = -6,           /* HIP runtime error or device-side failure    */
-  CC_ERR_NO_DEVICE = -7         /* no usable gfx950 device                     */
+  CC_ERR_NO_DEVICE = -7,        /* no usable gfx950 device                     */
+  CC_ERR_NOT_READY = -8,        /* serving: the request has not finished yet    */
+  CC_ERR_INTERNAL = -9          /* a device-side consistency check failed; the
+                                   results of the call are discarded (see
+                                   cc_run_info.device_diag)                     */
 } cc_status;
 
 /* cc_options.flags */
@@ -93,6 +97,8 @@ typedef struct cc_run_info {
   double level_ms;           /* all breadth-first level kernels                      */
   double dfs_ms;             /* depth-first kernels and their preparation            */
   int64_t level_bytes;       /* frontier and output bytes the level kernels must move */
+  int64_t device_diag;       /* after CC_ERR_INTERNAL: which check failed (kind << 24 |
+                                low 24 bits of the offending value), else 0          */
 } cc_run_info;
 
 /*
@@ -185,6 +191,54 @@ cc_status cc_batch_last_run(cc_batch *b, cc_run_info *info);
 
 /* cc_release_batch -- free a batch handle (NULL is ignored). */
 void cc_release_batch(cc_batch *b);
+
+/* ------------------------------------------------------------- serving
+ * A request loop for many independent graphs (count + histogram each).  A
+ * dispatcher thread admits pending requests, in arrival order, into a free
+ * device slot while the slot's capacities hold (graphs, vertices, adjacency
+ * entries, and root slots: a graph needs sum over vertices of C(deg, 2)),
+ * and runs each admitted group as one batch (stage one, then one persistent
+ * depth-first launch on the slot's share of the CUs).  Slots run
+ * concurrently, so requests that arrive while others are on the GPU start
+ * as soon as a slot frees up.  Results do not depend on how requests were
+ * grouped.
+ */
+typedef struct cc_server cc_server;
+
+typedef struct cc_server_options {
+  int32_t slots;             /* concurrent device slots; 0 = 4                       */
+  int32_t max_batch_graphs;  /* graphs per batch; 0 = 256                            */
+  int64_t slot_root_slots;   /* initial-triplet slots per batch; 0 = 4M               */
+  int64_t slot_work_bytes;   /* depth-first workspace per slot; 0 = 256 MiB           */
+  int32_t dfs_waves_per_cu;  /* wavefronts per CU shared by all slots; 0 = 16        */
+  int32_t reserved;
+} cc_server_options;
+
+/* cc_server_create -- allocate the slots (device and pinned memory) and start
+ * the dispatcher on the current HIP device. */
+cc_status cc_server_create(const cc_server_options *opt, cc_server **out);
+
+/* cc_server_submit -- queue one graph (host CSR, copied before returning);
+ * *request_id receives its id.  Argument errors as cc_prepare; a graph
+ * larger than a whole slot completes at once with CC_ERR_OUT_OF_MEMORY as
+ * its request status. */
+cc_status cc_server_submit(cc_server *sv, int32_t n, const int32_t *row_ptr,
+                           const int32_t *col_idx, int64_t *request_id);
+
+/* cc_server_result -- wait up to timeout_s for a request; on success write
+ * its histogram (hist_len >= n+1), its latency from submission to
+ * completion in ms, and its own status (CC_OK, CC_ERR_NOT_SIMPLE, ...), and
+ * forget the request.  Returns CC_ERR_NOT_READY on timeout (the request
+ * stays queryable). */
+cc_status cc_server_result(cc_server *sv, int64_t request_id, double timeout_s, int64_t *hist,
+                           int32_t hist_len, double *latency_ms, cc_status *request_status);
+
+/* cc_server_stats -- stats[0] completed, [1] batches launched, [2] pending,
+ * [3] rejected, [4] largest batch (len >= 5). */
+cc_status cc_server_stats(cc_server *sv, int64_t *stats, int32_t len);
+
+/* cc_server_destroy -- finish every queued request, stop, free (NULL ok). */
+void cc_server_destroy(cc_server *sv);
 
 /* cc_status_string -- static English description of a status code. */
 const char *cc_status_string(cc_status s);

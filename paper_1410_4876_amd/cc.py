@@ -25,6 +25,8 @@ CC_ERR_BUFFER_TOO_SMALL = -4
 CC_ERR_OUT_OF_MEMORY = -5
 CC_ERR_DEVICE = -6
 CC_ERR_NO_DEVICE = -7
+CC_ERR_NOT_READY = -8
+CC_ERR_INTERNAL = -9
 
 CC_INPUT_DEVICE = 1 << 0
 CC_OUTPUT_DEVICE = 1 << 1
@@ -65,10 +67,17 @@ class RunInfo(ctypes.Structure):
                 ("stage1_ms", ctypes.c_double),
                 ("level_ms", ctypes.c_double),
                 ("dfs_ms", ctypes.c_double),
-                ("level_bytes", ctypes.c_int64)]
+                ("level_bytes", ctypes.c_int64),
+                ("device_diag", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch_graphs", ctypes.c_int32),
+                ("slot_root_slots", ctypes.c_int64), ("slot_work_bytes", ctypes.c_int64),
+                ("dfs_waves_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def lib():
@@ -111,6 +120,18 @@ def lib():
             L.cc_batch_last_run.restype = ctypes.c_int
             L.cc_release_batch.argtypes = [vp]
             L.cc_release_batch.restype = None
+            L.cc_server_create.argtypes = [ctypes.POINTER(ServerOptions), pp]
+            L.cc_server_create.restype = ctypes.c_int
+            L.cc_server_submit.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i64)]
+            L.cc_server_submit.restype = ctypes.c_int
+            L.cc_server_result.argtypes = [vp, i64, ctypes.c_double, vp, i32,
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int)]
+            L.cc_server_result.restype = ctypes.c_int
+            L.cc_server_stats.argtypes = [vp, vp, i32]
+            L.cc_server_stats.restype = ctypes.c_int
+            L.cc_server_destroy.argtypes = [vp]
+            L.cc_server_destroy.restype = None
             _lib = L
     return _lib
 
@@ -119,9 +140,16 @@ def status_string(status: int) -> str:
     return lib().cc_status_string(status).decode()
 
 
-def _check(st: int, where: str):
+def _check(st: int, where: str, info_fn=None):
     if st != CC_OK:
-        raise CCError(st, where)
+        err = CCError(st, where)
+        if st == CC_ERR_INTERNAL and info_fn is not None:
+            # which device-side check failed: kind << 24 | low bits of the value
+            info = RunInfo()
+            if info_fn(ctypes.byref(info)) == CC_OK:
+                err.device_diag = int(info.device_diag)
+                err.args = (f"{err.args[0]} [device_diag 0x{err.device_diag:08x}]",)
+        raise err
 
 
 def _is_torch(x) -> bool:
@@ -199,15 +227,19 @@ class Graph:
         except Exception:
             pass
 
+    def _info_fn(self, p):
+        return lib().cc_last_run(self.h, p)
+
     # -- calls
     def count(self) -> int:
         total = ctypes.c_int64()
-        _check(lib().cc_count(self.h, ctypes.byref(total)), "cc_count")
+        _check(lib().cc_count(self.h, ctypes.byref(total)), "cc_count", self._info_fn)
         return total.value
 
     def histogram(self) -> np.ndarray:
         h = np.zeros(self.n + 1, np.int64)
-        _check(lib().cc_histogram(self.h, ctypes.c_void_p(h.ctypes.data), h.size), "cc_histogram")
+        _check(lib().cc_histogram(self.h, ctypes.c_void_p(h.ctypes.data), h.size), "cc_histogram",
+               self._info_fn)
         return h
 
     def enumerate_into(self, verts, offsets):
@@ -221,6 +253,8 @@ class Graph:
         vcap = int(verts.numel() if _is_torch(verts) else np.asarray(verts).size)
         ccap = int(offsets.numel() if _is_torch(offsets) else np.asarray(offsets).size) - 1
         st = lib().cc_enumerate(self.h, vp, vcap, op, max(ccap, 0), ctypes.byref(nc), ctypes.byref(nv))
+        if st == CC_ERR_INTERNAL:
+            _check(st, "cc_enumerate", self._info_fn)
         if st != CC_OK:
             err = CCError(st, "cc_enumerate")
             err.required = (nc.value, nv.value)
@@ -327,7 +361,7 @@ class Batch:
         out = np.zeros((self.n_graphs, stride), np.int64)
         mode = CC_BATCH_PER_GRAPH if per_graph_launch else CC_BATCH_PERSISTENT
         _check(lib().cc_histogram_batch(self.h, ctypes.c_void_p(out.ctypes.data), stride, mode),
-               "cc_histogram_batch")
+               "cc_histogram_batch", lambda p: lib().cc_batch_last_run(self.h, p))
         return out
 
     def labels(self) -> np.ndarray:
@@ -344,3 +378,70 @@ class Batch:
 def prepare_batch(batch, **kw) -> Batch:
     """cc_prepare_batch on a graphgen.Batch-like object."""
     return Batch(batch.graph_vtx_off, batch.row_ptr, batch.col_idx, **kw)
+
+
+class Server:
+    """Request loop over many independent graphs (cc_server_*).  submit()
+    copies the graph and returns a request id at once; result() waits for
+    that request and returns (histogram, latency_ms, status)."""
+
+    def __init__(self, slots: int = 0, max_batch_graphs: int = 0, slot_root_slots: int = 0,
+                 slot_work_bytes: int = 0, dfs_waves_per_cu: int = 0):
+        L = lib()
+        self.opt = ServerOptions(int(slots), int(max_batch_graphs), int(slot_root_slots),
+                                 int(slot_work_bytes), int(dfs_waves_per_cu), 0)
+        h = ctypes.c_void_p()
+        _check(L.cc_server_create(ctypes.byref(self.opt), ctypes.byref(h)), "cc_server_create")
+        self.h = h
+        self._n = {}
+
+    def submit(self, n, row_ptr, col_idx) -> int:
+        rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
+        ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
+        if ci.size == 0:
+            ci = np.zeros(1, np.int32)
+        rid = ctypes.c_int64()
+        _check(lib().cc_server_submit(self.h, int(n), ctypes.c_void_p(rp.ctypes.data),
+                                      ctypes.c_void_p(ci.ctypes.data), ctypes.byref(rid)),
+               "cc_server_submit")
+        self._n[rid.value] = int(n)
+        return rid.value
+
+    def submit_graph(self, g) -> int:
+        return self.submit(g.n, g.row_ptr, g.col_idx)
+
+    def result(self, request_id: int, timeout_s: float = 60.0):
+        """(hist int64[n+1], latency_ms, status).  Raises CCError(CC_ERR_NOT_READY)
+        on timeout; `status` is the request's own (0, or e.g. CC_ERR_NOT_SIMPLE)."""
+        n = self._n[request_id]
+        hist = np.zeros(n + 1, np.int64)
+        lat = ctypes.c_double()
+        rst = ctypes.c_int()
+        _check(lib().cc_server_result(self.h, int(request_id), float(timeout_s),
+                                      ctypes.c_void_p(hist.ctypes.data), n + 1,
+                                      ctypes.byref(lat), ctypes.byref(rst)), "cc_server_result")
+        del self._n[request_id]
+        return hist, lat.value, rst.value
+
+    def stats(self) -> dict:
+        a = np.zeros(5, np.int64)
+        _check(lib().cc_server_stats(self.h, ctypes.c_void_p(a.ctypes.data), 5), "cc_server_stats")
+        return {"completed": int(a[0]), "batches": int(a[1]), "pending": int(a[2]),
+                "rejected": int(a[3]), "max_batch": int(a[4])}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cc_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

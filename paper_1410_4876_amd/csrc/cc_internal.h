@@ -22,6 +22,13 @@
 #define CC_DEV_NOT_SIMPLE 1u
 #define CC_DEV_STACK_FULL 2u      // a depth-first stack had no room (results incomplete)
 #define CC_DEV_IDLE_TIMEOUT 4u    // an idle wavefront gave up waiting (diagnostic only)
+#define CC_DEV_CORRUPT 8u         // a depth-first consistency check failed (results discarded)
+#define CC_DEV_LOST 16u           // a wavefront gave up on paths it was promised (results incomplete)
+// First failed consistency check (CcCtl::diag): kind << 24 | low 24 bits of the value.
+#define CC_DIAG_INBOX_COUNT 1u    // more paths announced than an inbox holds
+#define CC_DIAG_REQUESTER 2u      // a work request names no wavefront of this launch
+#define CC_DIAG_PATH 3u           // a path whose end vertices or length do not fit its graph
+#define CC_DIAG_GRAPH 4u          // a path whose graph id is not in the batch
 
 // skip bits for the paths handed to the depth-first kernel
 #define CC_SKIP_FRONT 1           // their path count is already recorded
@@ -48,7 +55,7 @@ struct CcCtl {
   int switch_level;                         // path length handed to the depth-first kernel
   int skip;                                 // CC_SKIP_* bits for the handed-over paths
   int busy;                                 // depth-first wavefronts holding or seeking work
-  int unused;
+  unsigned int diag;                        // first failed consistency check, CC_DIAG_*
   unsigned int status;                      // CC_DEV_* bits
   int bfs_max_len;                          // longest cycle length final after the levels
   int pad;
@@ -137,6 +144,7 @@ struct BatchDev {
   unsigned long long *hist;      // per-graph histograms, graph g at hist[g * hist_stride]
   int hist_stride;
   int g0;                        // first graph of this launch (stage one)
+  int n_graphs;                  // graphs in the batch (ids 0 .. n_graphs - 1)
 };
 
 // ------------------------------------------------------------------ launchers
@@ -159,18 +167,18 @@ hipError_t cc_launch_level(int W, bool enumerate, GraphDev g, CcCtl *ctl, Fronti
                            Frontier fout, Stage sprev, Stage scur, OutDev out, int t,
                            int forced_level, int blocks, unsigned int *host_done,
                            hipStream_t s);
-// The depth-first workspace lives in the frontier buffer that does not hold
-// the handed-over paths: wk0 is carved from buffer 0, wk1 from buffer 1.
-// Cycle counts of block b go to hist_out[(b % CC_SHARDS) * hist_stride + k]
-// (hist_out NULL: not counted).
+// The handed-over paths are the frontier f0 or f1 that holds the paths of
+// the switch length; the workspace wk has memory of its own.  Cycle counts
+// of block b go to hist_out[(b % CC_SHARDS) * hist_stride + k] (hist_out
+// NULL: not counted).
 hipError_t cc_launch_dfs(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f0,
-                         Frontier f1, DfsWork wk0, DfsWork wk1, OutDev out,
+                         Frontier f1, DfsWork wk, OutDev out,
                          unsigned long long *hist_out, int hist_stride, bool count_front,
                          int blocks, unsigned long long idle_timeout, hipStream_t s);
 // Batched depth-first run over the root slots bt.r0 .. bt.r1 (workspace wk).
 hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt,
                                int blocks, unsigned long long idle_timeout, hipStream_t s);
-// always: reset for a batched run (no breadth-first levels before it).
-hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, bool enum_bases,
-                                 bool always, hipStream_t s);
+// Zeroes wk's mailboxes and the claim and busy counters (always), and with
+// enum_bases computes the output base of each cycle length.
+hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s);
 hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool enumerate, hipStream_t s);

@@ -159,10 +159,12 @@ __device__ __forceinline__ void st_release(T *p, T v) {
 }
 
 // Coherent single accesses (relaxed, agent scope): each is one sc1 load or
-// store, visible across the XCDs, with no cache-wide maintenance.  The
-// depth-first donation queue moves its payload with these and orders it with
-// wait_mem() instead of agent-scope fences, which would write back or
-// invalidate the whole L2 of the XCD.
+// store, with no cache-wide maintenance.  Relaxed accesses order nothing
+// else: a payload written with them is published by a release fence before
+// its flag is stored (release_agent) and read after an acquire fence that
+// follows the load which saw the flag (acquire_agent); on gfx950 these are
+// the L2 write-back and invalidate that make the payload visible to the
+// other XCDs.
 template <typename T>
 __device__ __forceinline__ T ld_coh(T *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -173,6 +175,18 @@ __device__ __forceinline__ void st_coh(T *p, T v) {
 }
 // Waits until every memory access this wavefront issued has completed.
 __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+// Called by the whole wavefront: every lane's earlier stores are visible
+// at agent scope before any later store of the wavefront (the flag).
+__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+// Called by the whole wavefront after the load that saw the flag.
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Records a failed consistency check of the depth-first kernel (the run
+// reports an error instead of using the value).
+__device__ __forceinline__ void dfs_corrupt(CcCtl *ctl, unsigned kind, unsigned value) {
+  atomicOr(&ctl->status, CC_DEV_CORRUPT);
+  atomicCAS(&ctl->diag, 0u, (kind << 24) | (value & 0xffffffu));
+}
 
 __device__ __forceinline__ void st_system(unsigned int *p, unsigned int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -281,6 +295,8 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   const long long eN = rp[v0 + n];
   const bool bad_head = (v0 == 0 && e0 != 0) || eN < e0 || (eN - e0) > (long long)n * (n - 1);
   if (bad_head) {
+    // an invalid graph keeps no edges, so later stages find nothing in it
+    for (int i = tid; i < n * W; i += blockDim.x) adj_out[(size_t)v0 * W + i] = 0ull;
     if (tid == 0) status[g] = CC_DEV_NOT_SIMPLE;
     return;
   }
@@ -324,6 +340,7 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   }
   __syncthreads();
   if (sErr) {
+    for (int i = tid; i < n * W; i += blockDim.x) adj_out[(size_t)v0 * W + i] = 0ull;
     if (tid == 0) status[g] = sErr;
     return;
   }
@@ -785,7 +802,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
 // CC_NO_GRAPH.  The mailboxes and stacks come from wk1.
 template <int W, bool ENUM, bool BATCH>
 __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Frontier f0,
-                                                  Frontier f1, DfsWork wk0, DfsWork wk1,
+                                                  Frontier f1, DfsWork wk,
                                                   OutDev out, unsigned long long *hist_out,
                                                   int hist_stride, int count_front,
                                                   unsigned long long idle_timeout, BatchDev bt) {
@@ -801,7 +818,6 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   const int L = BATCH ? 3 : ctl->switch_level;
   const int skipbits = BATCH ? 0 : ctl->skip;
   const Frontier roots = (L & 1) ? f1 : f0;
-  const DfsWork wk = (BATCH || !(L & 1)) ? wk1 : wk0;  // the buffer not holding the roots
   const int n = g.n;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -939,8 +955,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         if (lane == 0) {
           // decline whatever is asked of us while we have nothing
           const unsigned r = ld_coh(&my_mail[0]);
-          if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r)
-            st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
+          if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r) {
+            if (r - 1u < (unsigned)nwaves) st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
+            else dfs_corrupt(ctl, CC_DIAG_REQUESTER, r);
+          }
           if (victim >= 0) {
             const unsigned resp = ld_coh(&my_mail[1]);
             if (resp == 1u) {
@@ -954,6 +972,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
                   (unsigned)wid + 1u)
                 victim = -1;
             }
+            // a taken request is always answered; if the answer never comes,
+            // give up after the idle timeout and report the run incomplete
+            if (o == 0 && victim >= 0 && wall_clock64() - t0 > idle_timeout) o = 5;
           }
           if (o == 0 && victim < 0) {
             if (!roots_done && ld_coh(&ctl->root_cursor) < nroots) o = 3;
@@ -1005,12 +1026,20 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       }
       if (outcome != 1) {
         if (outcome == 4 && lane == 0) atomicOr(&ctl->status, CC_DEV_IDLE_TIMEOUT);
+        if (outcome == 5 && lane == 0) atomicOr(&ctl->status, CC_DEV_LOST);
         break;
       }
-      // Work arrived in our inbox (the donor already counted us busy).
+      // Work arrived in our inbox (the donor already counted us busy).  The
+      // acquire pairs with the donor's release of the response word, so the
+      // count and the paths below are the ones it wrote.
+      acquire_agent();
       unsigned kk = 0;
       if (lane == 0) kk = ld_coh(&my_mail[2]);
       kk = __shfl(kk, 0, CC_WAVE);
+      if (kk > (unsigned)CC_CHUNK) {
+        if (lane == 0) dfs_corrupt(ctl, CC_DIAG_INBOX_COUNT, kk);
+        kk = 0;
+      }
       valid = (unsigned)lane < kk;
       if (valid) {
         const size_t ib = (size_t)wid * W * CC_CHUNK;
@@ -1036,6 +1065,27 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
 
     // ---- expand the batch (one path per lane)
     ++batches;
+    // Consistency checks: every index below that comes from a path stays
+    // inside its graph; a path that fails is reported and dropped.
+    int n_path = n;  // vertices of this path's graph
+    int vo = 0;
+    if (BATCH) {
+      if (valid && gid >= (unsigned)bt.n_graphs) {
+        dfs_corrupt(ctl, CC_DIAG_GRAPH, gid);
+        valid = false;
+      }
+      if (!valid) gid = 0;
+      vo = bt.vtx_off[gid];
+      n_path = bt.vtx_off[gid + 1] - vo;
+    }
+    if (valid) {
+      const int pv1 = m & 0xffu, pvt = (m >> 8) & 0xffu, pt = (m >> 16) & 0xffu;
+      if (pv1 >= n_path || pvt >= n_path || pt < 3 || pt > n_path) {
+        dfs_corrupt(ctl, CC_DIAG_PATH, m);
+        valid = false;
+      }
+    }
+    if (!valid) m = 0;
     const int v1 = m & 0xffu;
     const int vt = (m >> 8) & 0xffu;
     const int t = (m >> 16) & 0xffu;
@@ -1043,10 +1093,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
     const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
     Bits<W> nvt, nv1;
-    int n_path = n;  // vertices of this path's graph
     if (BATCH) {
-      const int vo = bt.vtx_off[gid];
-      n_path = bt.vtx_off[gid + 1] - vo;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         nvt.w[w] = bt.adj[(size_t)(vo + vt) * W + w];
@@ -1099,7 +1146,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
             const int v = bpop_lowest(cl);
             const long long cyc = sCb[k] + (long long)(slot0 + j);
             const long long pos = sVb[k] + (long long)(slot0 + j) * k;
-            if (cyc < out.cyc_cap && pos + k <= out.verts_cap) {
+            if (cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap) {
               write_cycle<W>(sNo, bor(S, bsingle<W>(sPerm[v])), k, out.verts + pos);
               out.offs[cyc] = pos;
             }
@@ -1178,6 +1225,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r) req = r;
       }
       req = __shfl(req, 0, CC_WAVE);
+      if (req != 0u && req - 1u >= (unsigned)nwaves) {
+        if (lane == 0) dfs_corrupt(ctl, CC_DIAG_REQUESTER, req);
+        req = 0u;
+      }
       if (req != 0u) {
         const int q = (int)req - 1;
         unsigned int *q_mail = wk.mail + (size_t)q * CC_MAIL;
@@ -1241,7 +1292,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
             st_coh(&q_mail[2], (unsigned)give);
             atomicAdd(&ctl->busy, 1);  // the recipient holds paths from now on
           }
-          wait_mem();
+          // every lane's inbox stores are visible before lane 0 publishes them
+          release_agent();
           if (lane == 0) st_coh(&q_mail[1], 1u);
           ++donated;
         } else if (lane == 0) {
@@ -1254,7 +1306,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   // Close the mailbox; decline a request that arrived meanwhile.
   if (lane == 0) {
     const unsigned r = atomicExch(&my_mail[0], CC_MAIL_CLOSED);
-    if (r != 0u && r != CC_MAIL_CLOSED) st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
+    if (r != 0u && r != CC_MAIL_CLOSED) {
+      if (r - 1u < (unsigned)nwaves) st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
+      else dfs_corrupt(ctl, CC_DIAG_REQUESTER, r);
+    }
     atomicAdd(&ctl->dfs_batches, batches);
     if (donated) atomicAdd(&ctl->donations, donated);
   }
@@ -1291,14 +1346,13 @@ __device__ void length_totals(CcCtl *ctl, bool enumerate, unsigned long long *sT
   __syncthreads();
 }
 
-// Resets the depth-first coordination state (and, for the writing pass of
-// enumerate mode, computes where each cycle length starts in the output).
-// Does nothing when the breadth-first levels finished on their own.
-__global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, int enum_bases,
-                              int always) {
+// Resets the depth-first coordination state: every mailbox of the
+// workspace, the claim cursor and the busy count, unconditionally (the
+// workspace has memory of its own, so nothing else ever lives there); for
+// the writing pass of enumerate mode it also computes where each cycle
+// length starts in the output.
+__global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
   __shared__ unsigned long long sTot[CC_HSLOTS];
-  if (!always && ld_relaxed(&ctl->mode) == 0) return;
-  const DfsWork wk = (!always && (ctl->switch_level & 1)) ? wk0 : wk1;
   const size_t words = (size_t)wk.nwaves * CC_MAIL;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
        i += (size_t)gridDim.x * blockDim.x)
@@ -1396,18 +1450,18 @@ hipError_t cc_launch_level(int W, bool en, GraphDev g, CcCtl *ctl, Frontier fin,
 }
 
 hipError_t cc_launch_dfs(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
-                         DfsWork wk0, DfsWork wk1, OutDev out, unsigned long long *hist_out,
+                         DfsWork wk, OutDev out, unsigned long long *hist_out,
                          int hist_stride, bool count_front, int blocks,
                          unsigned long long idle_timeout, hipStream_t s) {
   dim3 gr(blocks), bl(CC_BLOCK);
   const int cf = count_front ? 1 : 0;
   const BatchDev nb{};
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_dfs<1, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
-    else hipLaunchKernelGGL((k_dfs<1, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
+    if (en) hipLaunchKernelGGL((k_dfs<1, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
+    else hipLaunchKernelGGL((k_dfs<1, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
   } else {
-    if (en) hipLaunchKernelGGL((k_dfs<2, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
-    else hipLaunchKernelGGL((k_dfs<2, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk0, wk1, out, hist_out, hist_stride, cf, idle_timeout, nb);
+    if (en) hipLaunchKernelGGL((k_dfs<2, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
+    else hipLaunchKernelGGL((k_dfs<2, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
   }
   return hipGetLastError();
 }
@@ -1418,16 +1472,14 @@ hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchD
   const Frontier nf{};
   const OutDev no{};
   if (W == 1)
-    hipLaunchKernelGGL((k_dfs<1, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, wk, no, nullptr, 0, 1, idle_timeout, bt);
+    hipLaunchKernelGGL((k_dfs<1, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
   else
-    hipLaunchKernelGGL((k_dfs<2, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, wk, no, nullptr, 0, 1, idle_timeout, bt);
+    hipLaunchKernelGGL((k_dfs<2, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
   return hipGetLastError();
 }
 
-hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk0, DfsWork wk1, int n, bool enum_bases,
-                                 bool always, hipStream_t s) {
-  hipLaunchKernelGGL(k_dfs_prepare, dim3(64), dim3(256), 0, s, ctl, wk0, wk1, n,
-                     enum_bases ? 1 : 0, always ? 1 : 0);
+hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s) {
+  hipLaunchKernelGGL(k_dfs_prepare, dim3(64), dim3(256), 0, s, ctl, wk, n, enum_bases ? 1 : 0);
   return hipGetLastError();
 }
 

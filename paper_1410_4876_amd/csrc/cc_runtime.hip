@@ -222,11 +222,12 @@ struct RunOut {
 // One full device run: stage one, the level loop, and the depth-first
 // continuation if the budget (or CC_FORCE_DFS) requires it.
 //
-// Device memory (one stream-ordered allocation, sized by the budget): two
-// sharded frontier buffers used alternately by the levels and, in enumerate
-// mode, two staging buffers for the cycles one level closes and the next
-// decodes.  The depth-first workspace reuses the frontier buffer that does
-// not hold the handed-over paths.
+// Device memory (one stream-ordered allocation): two sharded frontier
+// buffers used alternately by the levels and, in enumerate mode, two staging
+// buffers for the cycles one level closes and the next decodes, all sized by
+// the budget; then the depth-first workspace (stacks, mailboxes, inboxes) in
+// a region of its own, which no other kernel writes, zeroed before each
+// depth-first pass.
 cc_status run_device(cc_graph *g, const RunOut &ro) {
   const int n = g->n;
   const int W = g->W;
@@ -244,8 +245,12 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   const unsigned long long cap = cap_s * CC_SHARDS;
   const size_t buf_bytes = align_up(frontier_bytes(cap_s, W, en), 1 << 16);
   const size_t stage_bytes = en ? align_up(cap * W * 8, 1 << 16) : 0;
+  const size_t dfs_bytes = align_up(
+      (size_t)std::min<int64_t>(std::max<int64_t>(budget / 2, (int64_t)64 << 20), (int64_t)2 << 30),
+      1 << 16);
   char *arena = nullptr;
-  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes + 2 * stage_bytes, s));
+  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes + 2 * stage_bytes + dfs_bytes, s));
+  char *dfs_region = arena + 2 * buf_bytes + 2 * stage_bytes;
   Frontier f[2] = {carve_frontier(arena, cap_s, W, en),
                    carve_frontier(arena + buf_bytes, cap_s, W, en)};
   Stage st[2] = {};
@@ -261,17 +266,16 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 16;
   waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
   const int want_waves = std::max(4, (g->dev.cus * waves_per_cu) / 4 * 4);
-  DfsWork wc[2], we[2];
-  int nw_c = std::min(carve_dfs(arena, buf_bytes, W, false, want_waves, maxc, &wc[0]),
-                      carve_dfs(arena + buf_bytes, buf_bytes, W, false, want_waves, maxc, &wc[1]));
-  int nw_e = en ? std::min(carve_dfs(arena, buf_bytes, W, true, want_waves, maxc, &we[0]),
-                           carve_dfs(arena + buf_bytes, buf_bytes, W, true, want_waves, maxc, &we[1]))
-                : 4;
+  // the counting pass (wc) and, in enumerate mode, the writing pass (we)
+  // use the same region one after the other
+  DfsWork wc{}, we{};
+  const int nw_c = carve_dfs(dfs_region, dfs_bytes, W, false, want_waves, maxc, &wc);
+  const int nw_e = en ? carve_dfs(dfs_region, dfs_bytes, W, true, want_waves, maxc, &we) : 4;
   if (nw_c < 4 || nw_e < 4) {
     (void)hipFreeAsync(arena, s);
     return CC_ERR_OUT_OF_MEMORY;
   }
-  for (DfsWork *d : {&wc[0], &wc[1], &we[0], &we[1]}) {
+  for (DfsWork *d : {&wc, &we}) {
     if (g->opt.dfs_donate_min > 0) d->donate_min = g->opt.dfs_donate_min;
     d->claim = g->opt.dfs_claim > 0 ? (g->opt.dfs_claim + CC_CHUNK - 1) / CC_CHUNK * CC_CHUNK : 0;
   }
@@ -319,16 +323,16 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   // Depth-first continuation (each kernel returns at once if the levels
   // finished within the budget).
   mark(2 * n + 2);
-  chk(cc_launch_dfs_prepare(ctl, wc[0], wc[1], n, false, false, s));
+  chk(cc_launch_dfs_prepare(ctl, wc, n, false, s));
   if (en) {
-    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc[0], wc[1], ro.out,
+    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, ro.out,
                       dev_field(ctl, offsetof(CcCtl, dfs_hist)), 0, true, dfs_blocks_c,
                       idle_timeout, s));
-    chk(cc_launch_dfs_prepare(ctl, we[0], we[1], n, true, false, s));
-    chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we[0], we[1], ro.out, nullptr, 0, false,
+    chk(cc_launch_dfs_prepare(ctl, we, n, true, s));
+    chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we, ro.out, nullptr, 0, false,
                       dfs_blocks_e, idle_timeout, s));
   } else {
-    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc[0], wc[1], ro.out,
+    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, ro.out,
                       dev_field(ctl, offsetof(CcCtl, hist_sh)), CC_HSLOTS, true, dfs_blocks_c,
                       idle_timeout, s));
   }
@@ -395,6 +399,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     g->info.level_bytes = bytes;
   }
   g->have_run = true;
+  g->info.device_diag = (int64_t)h.diag;
+  if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST)) return CC_ERR_INTERNAL;
   if (h.status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
   return CC_OK;
 }
@@ -433,6 +439,8 @@ const char *cc_status_string(cc_status s) {
     case CC_ERR_OUT_OF_MEMORY: return "out of device memory or frontier budget too small";
     case CC_ERR_DEVICE: return "HIP runtime or device error";
     case CC_ERR_NO_DEVICE: return "no usable gfx950 device";
+    case CC_ERR_NOT_READY: return "request not finished yet";
+    case CC_ERR_INTERNAL: return "device-side consistency check failed; results discarded";
   }
   return "unknown status";
 }
@@ -884,6 +892,7 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
   bt.rcap = rcap;
   bt.hist = (unsigned long long *)(arena + roots_b);
   bt.hist_stride = dstride;
+  bt.n_graphs = G;
   DfsWork wk{};
   const int nw = carve_dfs(arena + roots_b + hist_b, stack_b, W, false, want_waves, maxc, &wk, true);
   if (nw < 4) {
@@ -911,7 +920,7 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
     chk(cc_launch_triplets_batch(W, bt, G, s));
     bt.r0 = 0;
     bt.r1 = (unsigned long long)b->root_off[G];
-    chk(cc_launch_dfs_prepare(ctl, wk, wk, b->max_n, false, true, s));
+    chk(cc_launch_dfs_prepare(ctl, wk, b->max_n, false, s));
     chk(cc_launch_dfs_batch(W, gd, ctl, wk, bt, nw / 4, idle_timeout, s));
     launches = 3;
   } else {
@@ -923,7 +932,7 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
       bt.r1 = (unsigned long long)b->root_off[g + 1];
       const unsigned long long slots = bt.r1 - bt.r0;
       const int blocks = (int)std::min<unsigned long long>(nw / 4, std::max(1ull, (slots + 255) / 256));
-      chk(cc_launch_dfs_prepare(ctl, wk, wk, b->max_n, false, true, s));
+      chk(cc_launch_dfs_prepare(ctl, wk, b->max_n, false, s));
       chk(cc_launch_dfs_batch(W, gd, ctl, wk, bt, blocks, idle_timeout, s));
       launches += 3;
     }
@@ -952,6 +961,8 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
   b->info.paths = paths;
   b->info.levels_launched = launches;
   b->info.gpu_ms = ms;
+  b->info.device_diag = (int64_t)b->h_ctl->diag;
+  if (b->h_ctl->status & (CC_DEV_CORRUPT | CC_DEV_LOST)) return CC_ERR_INTERNAL;
   if (b->h_ctl->status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
   return CC_OK;
 }
@@ -975,3 +986,420 @@ cc_status cc_batch_labels(cc_batch *b, int32_t *labels) {
 
 }  // extern "C"
 
+
+// ------------------------------------------------------------------ serving
+// A request loop over the batched kernels.  Requests (one graph each) are
+// copied in at submission; a dispatcher thread admits pending requests into
+// a free device slot by the policy of cc_serve_policy.h, packs them, and
+// launches ingest -> stage one -> one persistent depth-first launch on that
+// slot's stream, sized to its share of the CUs.  Several slots run at once,
+// so requests that arrive while others are on the GPU start as soon as a
+// slot frees up and their work overlaps on the device.  Completion is
+// detected with an event per slot; no launch waits on the host.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+#include "cc_serve_policy.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct ServeReq {
+  int64_t id = 0;
+  int32_t n = 0;
+  std::vector<int32_t> rp, ci;
+  ccserve::Cost cost;
+  Clock::time_point t_submit, t_start, t_done;
+  int state = 0;  // 0 pending, 1 on the device, 2 done
+  cc_status status = CC_OK;
+  std::vector<int64_t> hist;
+};
+
+struct ServeSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  std::vector<ServeReq *> reqs;
+  void *dev = nullptr;   // one allocation for all device buffers
+  void *host = nullptr;  // one pinned allocation for staging
+  int *d_vtx_off = nullptr, *d_rp = nullptr, *d_ci = nullptr;
+  long long *d_root_off = nullptr, *d_bound = nullptr;
+  unsigned long long *d_adj = nullptr, *d_adj_orig = nullptr;
+  int *d_perm = nullptr, *d_label = nullptr;
+  unsigned int *d_status = nullptr;
+  unsigned long long *rX = nullptr, *d_hist = nullptr;
+  unsigned short *rvv = nullptr;
+  unsigned int *rgid = nullptr;
+  CcCtl *d_ctl = nullptr;
+  char *d_work = nullptr;
+  size_t work_bytes = 0;
+  int *h_vtx_off = nullptr, *h_rp = nullptr, *h_ci = nullptr;
+  long long *h_root_off = nullptr;
+  unsigned long long *h_hist = nullptr;
+  unsigned int *h_status = nullptr;
+  unsigned int *h_ctl_status = nullptr;
+};
+
+}  // namespace
+
+struct cc_server {
+  int device = 0;
+  DeviceInfo dev{};
+  cc_server_options opt{};
+  ccserve::Capacity cap;
+  std::mutex mu;
+  std::condition_variable cv;       // wakes the dispatcher
+  std::condition_variable done_cv;  // wakes waiters
+  std::deque<std::pair<ServeReq *, ccserve::Cost>> pending;
+  std::unordered_map<int64_t, ServeReq *> reqs;
+  std::vector<ServeSlot> slots;
+  std::thread th;
+  bool stop = false;
+  int64_t next_id = 1;
+  int64_t batches = 0, completed = 0, rejected = 0, max_batch = 0;
+  double busy_slot_ms = 0.0;
+};
+
+namespace {
+
+size_t a256(size_t x) { return align_up(x, 256); }
+
+cc_status slot_alloc(cc_server *sv, ServeSlot &sl) {
+  const ccserve::Capacity &c = sv->cap;
+  const size_t G = (size_t)c.graphs, V = (size_t)c.vertices + CC_MAXN, E = (size_t)c.entries,
+               R = (size_t)c.roots;
+  const size_t dev_fixed = a256((G + 1) * 4) + a256((V + 1) * 4) + a256(E * 4) +
+                           2 * a256((G + 1) * 8) + 2 * a256(V * 2 * 8) + 2 * a256(V * 4) +
+                           a256(G * 4) + a256(R * 2 * 8) + a256(R * 2) + a256(R * 4) +
+                           a256(G * CC_HSLOTS * 8) + a256(sizeof(CcCtl));
+  sl.work_bytes = (size_t)sv->opt.slot_work_bytes;
+  if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+    return CC_ERR_DEVICE;
+  if (hipMalloc(&sl.dev, dev_fixed + sl.work_bytes) != hipSuccess) return CC_ERR_OUT_OF_MEMORY;
+  char *p = (char *)sl.dev;
+  auto take = [&](size_t b) {
+    char *q = p;
+    p += a256(b);
+    return q;
+  };
+  sl.d_vtx_off = (int *)take((G + 1) * 4);
+  sl.d_rp = (int *)take((V + 1) * 4);
+  sl.d_ci = (int *)take(E * 4);
+  sl.d_root_off = (long long *)take((G + 1) * 8);
+  sl.d_bound = (long long *)take((G + 1) * 8);
+  sl.d_adj = (unsigned long long *)take(V * 2 * 8);
+  sl.d_adj_orig = (unsigned long long *)take(V * 2 * 8);
+  sl.d_perm = (int *)take(V * 4);
+  sl.d_label = (int *)take(V * 4);
+  sl.d_status = (unsigned int *)take(G * 4);
+  sl.rX = (unsigned long long *)take(R * 2 * 8);
+  sl.rvv = (unsigned short *)take(R * 2);
+  sl.rgid = (unsigned int *)take(R * 4);
+  sl.d_hist = (unsigned long long *)take(G * CC_HSLOTS * 8);
+  sl.d_ctl = (CcCtl *)take(sizeof(CcCtl));
+  sl.d_work = p;
+  const size_t host_b = a256((G + 1) * 4) + a256((V + 1) * 4) + a256(E * 4) + a256((G + 1) * 8) +
+                        a256(G * CC_HSLOTS * 8) + a256(G * 4) + a256(4);
+  if (hipHostMalloc(&sl.host, host_b, hipHostMallocDefault) != hipSuccess)
+    return CC_ERR_OUT_OF_MEMORY;
+  char *h = (char *)sl.host;
+  auto htake = [&](size_t b) {
+    char *q = h;
+    h += a256(b);
+    return q;
+  };
+  sl.h_vtx_off = (int *)htake((G + 1) * 4);
+  sl.h_rp = (int *)htake((V + 1) * 4);
+  sl.h_ci = (int *)htake(E * 4);
+  sl.h_root_off = (long long *)htake((G + 1) * 8);
+  sl.h_hist = (unsigned long long *)htake(G * CC_HSLOTS * 8);
+  sl.h_status = (unsigned int *)htake(G * 4);
+  sl.h_ctl_status = (unsigned int *)htake(4);
+  return CC_OK;
+}
+
+// Packs the admitted requests into the slot's staging area and enqueues the
+// whole batch on the slot's stream.  The slot and its requests belong to the
+// dispatcher while the slot is busy, so this runs without the server lock.
+hipError_t slot_launch(cc_server *sv, ServeSlot &sl, const std::vector<ServeReq *> &rs) {
+  const int G = (int)rs.size();
+  int max_n = 0, max_deg = 0;
+  long long roots = 0;
+  int32_t v = 0, e = 0;
+  sl.h_vtx_off[0] = 0;
+  sl.h_rp[0] = 0;
+  sl.h_root_off[0] = 0;
+  for (int g = 0; g < G; ++g) {
+    const ServeReq *r = rs[g];
+    max_n = std::max(max_n, r->n);
+    for (int32_t i = 0; i < r->n; ++i) {
+      sl.h_rp[v + i + 1] = e + r->rp[i + 1];
+      max_deg = std::max(max_deg, r->rp[i + 1] - r->rp[i]);
+    }
+    // an id outside the graph becomes -1, which ingest rejects as not simple
+    for (size_t i = 0; i < r->ci.size(); ++i) {
+      const int32_t c = r->ci[i];
+      sl.h_ci[e + i] = (c >= 0 && c < r->n) ? c + v : -1;
+    }
+    v += r->n;
+    e += (int32_t)r->ci.size();
+    roots += r->cost.roots;
+    sl.h_vtx_off[g + 1] = v;
+    sl.h_root_off[g + 1] = roots;
+  }
+  const int W = max_n <= 64 ? 1 : 2;
+  const int waves = std::max(4, sv->dev.cus * std::max(4, sv->opt.dfs_waves_per_cu) /
+                                    std::max(1, (int)sv->slots.size()) / 4 * 4);
+  DfsWork wk{};
+  // a path has at most max_deg - 1 extensions (its end vertex keeps one
+  // neighbour on the path)
+  const int maxc = std::max(1, std::min(max_deg, CC_MAXN) - 1);
+  const int nw = carve_dfs(sl.d_work, sl.work_bytes, W, false, waves, maxc, &wk, true);
+  if (nw < 4) return hipErrorOutOfMemory;
+  hipStream_t s = sl.stream;
+  hipError_t err = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (x != hipSuccess && err == hipSuccess) err = x;
+  };
+  chk(hipMemcpyAsync(sl.d_vtx_off, sl.h_vtx_off, (size_t)(G + 1) * 4, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(sl.d_rp, sl.h_rp, (size_t)(v + 1) * 4, hipMemcpyHostToDevice, s));
+  if (e > 0) chk(hipMemcpyAsync(sl.d_ci, sl.h_ci, (size_t)e * 4, hipMemcpyHostToDevice, s));
+  chk(hipMemcpyAsync(sl.d_root_off, sl.h_root_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, s));
+  chk(cc_launch_ingest(W, G, sl.d_vtx_off, 0, sl.d_rp, sl.d_ci, sl.d_adj, sl.d_adj_orig, sl.d_perm,
+                       sl.d_label, sl.d_status, sl.d_bound, s));
+  chk(cc_launch_zero(sl.d_ctl, sizeof(CcCtl), s));
+  chk(cc_launch_zero(sl.d_hist, (size_t)G * CC_HSLOTS * 8, s));
+  BatchDev bt{};
+  bt.vtx_off = sl.d_vtx_off;
+  bt.adj = sl.d_adj;
+  bt.perm = sl.d_perm;
+  bt.root_off = sl.d_root_off;
+  bt.rX = sl.rX;
+  bt.rvv = sl.rvv;
+  bt.rgid = sl.rgid;
+  bt.rcap = (unsigned long long)sv->cap.roots;
+  bt.r0 = 0;
+  bt.r1 = (unsigned long long)roots;
+  bt.hist = sl.d_hist;
+  bt.hist_stride = CC_HSLOTS;
+  bt.g0 = 0;
+  bt.n_graphs = G;
+  chk(cc_launch_triplets_batch(W, bt, G, s));
+  GraphDev gd{sl.d_adj, sl.d_adj_orig, sl.d_perm, max_n};
+  chk(cc_launch_dfs_prepare(sl.d_ctl, wk, max_n, false, s));
+  chk(cc_launch_dfs_batch(W, gd, sl.d_ctl, wk, bt, nw / 4,
+                          (unsigned long long)(kIdleTimeoutSeconds * (double)sv->dev.clock_hz), s));
+  chk(hipMemcpyAsync(sl.h_hist, sl.d_hist, (size_t)G * CC_HSLOTS * 8, hipMemcpyDeviceToHost, s));
+  chk(hipMemcpyAsync(sl.h_status, sl.d_status, (size_t)G * 4, hipMemcpyDeviceToHost, s));
+  chk(hipMemcpyAsync(sl.h_ctl_status, &sl.d_ctl->status, 4, hipMemcpyDeviceToHost, s));
+  chk(hipEventRecord(sl.done, s));
+  return err;
+}
+
+void slot_finish(cc_server *sv, ServeSlot &sl, hipError_t ev) {
+  const Clock::time_point now = Clock::now();
+  for (size_t g = 0; g < sl.reqs.size(); ++g) {
+    ServeReq *r = sl.reqs[g];
+    if (ev != hipSuccess) {
+      r->status = ev == hipErrorOutOfMemory ? CC_ERR_OUT_OF_MEMORY : CC_ERR_DEVICE;
+    } else if (*sl.h_ctl_status & (CC_DEV_CORRUPT | CC_DEV_LOST)) {
+      r->status = CC_ERR_INTERNAL;  // a consistency check failed: the batch is discarded
+    } else if (*sl.h_ctl_status & CC_DEV_STACK_FULL) {
+      r->status = CC_ERR_OUT_OF_MEMORY;  // a depth-first stack ran out: counts incomplete
+    } else if ((sl.h_status[g] & 0xffu) != 0u || !(sl.h_status[g] & 0x100u)) {
+      r->status = CC_ERR_NOT_SIMPLE;
+    } else {
+      r->status = CC_OK;
+      r->hist.assign((size_t)r->n + 1, 0);
+      for (int k = 0; k <= r->n; ++k) r->hist[k] = (int64_t)sl.h_hist[g * CC_HSLOTS + k];
+    }
+    r->t_done = now;
+    r->state = 2;
+    sv->completed++;
+  }
+  sl.reqs.clear();
+  sl.busy = false;
+}
+
+void dispatcher(cc_server *sv) {
+  (void)hipSetDevice(sv->device);
+  std::unique_lock<std::mutex> lk(sv->mu);
+  while (true) {
+    bool any_busy = false, progressed = false;
+    for (ServeSlot &sl : sv->slots) {
+      if (!sl.busy) continue;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipErrorNotReady) {
+        any_busy = true;
+        continue;
+      }
+      slot_finish(sv, sl, q);
+      progressed = true;
+    }
+    if (progressed) sv->done_cv.notify_all();
+    for (ServeSlot &sl : sv->slots) {
+      if (sl.busy || sv->pending.empty()) continue;
+      std::vector<ServeReq *> rs = ccserve::admit(sv->pending, sv->cap);
+      if (rs.empty()) break;  // cannot happen: oversize requests are rejected at submit
+      const Clock::time_point now = Clock::now();
+      for (ServeReq *r : rs) {
+        r->state = 1;
+        r->t_start = now;
+      }
+      sl.reqs = rs;
+      sl.busy = true;
+      any_busy = true;
+      sv->batches++;
+      sv->max_batch = std::max<int64_t>(sv->max_batch, (int64_t)rs.size());
+      lk.unlock();
+      const hipError_t e = slot_launch(sv, sl, rs);
+      lk.lock();
+      if (e != hipSuccess) {
+        (void)hipStreamSynchronize(sl.stream);
+        slot_finish(sv, sl, e);
+        sv->done_cv.notify_all();
+      }
+    }
+    if (sv->stop && sv->pending.empty() && !any_busy) break;
+    sv->cv.wait_for(lk, std::chrono::microseconds(any_busy ? 20 : 200));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void cc_server_destroy(cc_server *sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->th.joinable()) sv->th.join();
+  (void)hipSetDevice(sv->device);
+  for (ServeSlot &sl : sv->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.dev) (void)hipFree(sl.dev);
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  for (auto &kv : sv->reqs) delete kv.second;
+  delete sv;
+}
+
+cc_status cc_server_create(const cc_server_options *opt, cc_server **out) {
+  if (!out) return CC_ERR_INVALID_ARG;
+  *out = nullptr;
+  cc_server_options o{};
+  if (opt) o = *opt;
+  if (o.slots < 0 || o.max_batch_graphs < 0 || o.slot_root_slots < 0 || o.slot_work_bytes < 0 ||
+      o.dfs_waves_per_cu < 0)
+    return CC_ERR_INVALID_ARG;
+  if (o.slots == 0) o.slots = 4;
+  if (o.max_batch_graphs == 0) o.max_batch_graphs = 256;
+  if (o.slot_root_slots == 0) o.slot_root_slots = 1 << 22;
+  if (o.slot_work_bytes == 0) o.slot_work_bytes = 256ll << 20;
+  if (o.dfs_waves_per_cu == 0) o.dfs_waves_per_cu = 16;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CC_ERR_NO_DEVICE;
+  DeviceInfo di;
+  cc_status st = device_info(dev, &di);
+  if (st != CC_OK) return st;
+  cc_server *sv = new cc_server();
+  sv->device = dev;
+  sv->dev = di;
+  sv->opt = o;
+  sv->cap.graphs = o.max_batch_graphs;
+  sv->cap.vertices = (int64_t)o.max_batch_graphs * CC_MAX_VERTICES;
+  sv->cap.entries = std::max<int64_t>((int64_t)o.max_batch_graphs * 1024, 1 << 20);
+  sv->cap.roots = o.slot_root_slots;
+  sv->slots.resize((size_t)o.slots);
+  for (ServeSlot &sl : sv->slots) {
+    st = slot_alloc(sv, sl);
+    if (st != CC_OK) {
+      cc_server_destroy(sv);
+      return st;
+    }
+  }
+  sv->th = std::thread(dispatcher, sv);
+  *out = sv;
+  return CC_OK;
+}
+
+cc_status cc_server_submit(cc_server *sv, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                           int64_t *request_id) {
+  if (!sv || !request_id || n < 0 || (n > 0 && !row_ptr)) return CC_ERR_INVALID_ARG;
+  if (n > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
+  const int32_t nnz = n > 0 ? row_ptr[n] : 0;
+  if (n > 0 && (row_ptr[0] != 0 || nnz < 0 || (int64_t)nnz > (int64_t)n * (n - 1)))
+    return CC_ERR_NOT_SIMPLE;
+  if (nnz > 0 && !col_idx) return CC_ERR_INVALID_ARG;
+  for (int32_t v = 0; v < n; ++v)
+    if (row_ptr[v + 1] < row_ptr[v]) return CC_ERR_NOT_SIMPLE;
+  ServeReq *r = new ServeReq();
+  r->n = n;
+  r->rp.assign(row_ptr, row_ptr + (n > 0 ? n + 1 : 0));
+  if (n == 0) r->rp.assign(1, 0);
+  r->ci.assign(col_idx, col_idx + nnz);
+  r->cost = ccserve::cost_of(n, r->rp.data());
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    r->id = sv->next_id++;
+    *request_id = r->id;
+    sv->reqs[r->id] = r;
+    if (!ccserve::fits_empty(r->cost, sv->cap)) {
+      r->status = CC_ERR_OUT_OF_MEMORY;  // larger than a whole slot
+      r->state = 2;
+      r->t_done = r->t_submit;
+      sv->rejected++;
+      sv->completed++;
+    } else {
+      sv->pending.emplace_back(r, r->cost);
+    }
+  }
+  sv->cv.notify_all();
+  return CC_OK;
+}
+
+cc_status cc_server_result(cc_server *sv, int64_t request_id, double timeout_s, int64_t *hist,
+                           int32_t hist_len, double *latency_ms, cc_status *request_status) {
+  if (!sv || !hist || hist_len < 1) return CC_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(request_id);
+  if (it == sv->reqs.end()) return CC_ERR_INVALID_ARG;
+  ServeReq *r = it->second;
+  if (hist_len < r->n + 1) return CC_ERR_INVALID_ARG;
+  const auto deadline = Clock::now() + std::chrono::duration<double>(std::max(timeout_s, 0.0));
+  while (r->state != 2) {
+    if (sv->done_cv.wait_until(lk, deadline) == std::cv_status::timeout && r->state != 2)
+      return CC_ERR_NOT_READY;
+  }
+  for (int k = 0; k < hist_len; ++k) hist[k] = k < (int)r->hist.size() ? r->hist[k] : 0;
+  if (latency_ms)
+    *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  if (request_status) *request_status = r->status;
+  sv->reqs.erase(it);
+  delete r;
+  return CC_OK;
+}
+
+cc_status cc_server_stats(cc_server *sv, int64_t *stats, int32_t len) {
+  if (!sv || !stats || len < 5) return CC_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  stats[0] = sv->completed;
+  stats[1] = sv->batches;
+  stats[2] = (int64_t)sv->pending.size();
+  stats[3] = sv->rejected;
+  stats[4] = sv->max_batch;
+  return CC_OK;
+}
+
+}  // extern "C"

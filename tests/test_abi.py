@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(L):
 def test_status_strings_and_version(L):
     from paper_1410_4876_amd import cc
     assert L.cc_abi_version() == 1
-    for code in range(-7, 1):
+    for code in range(-9, 1):
         assert cc.status_string(code) and cc.status_string(code) != "unknown status"
     assert cc.status_string(-99) == "unknown status"
 

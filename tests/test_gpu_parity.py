@@ -112,6 +112,23 @@ def test_forced_depth_first_matches(cc, level):
         assert info["switch_level"] == level
 
 
+def test_depth_first_steal_heavy_repeated(cc):
+    """Regression: a handed-over frontier of a few dozen paths against
+    thousands of wavefronts, so nearly all work moves by donation.  Donated
+    paths were once read before they were visible on the requester's XCD;
+    every repeat must give the oracle's histogram and path counts."""
+    rng = np.random.default_rng(4)
+    graphs = [gg.permute_random(gg.grid(5, 7), rng), gg.er_gnm(60, 110, rng),
+              gg.er_gnm(100, 125, rng)]
+    want = [oracle_run(g, cycles=False) for g in graphs]
+    for rep in range(6):
+        for g, w in zip(graphs, want):
+            for level in (4, 5, 7):
+                with cc.prepare(g, force_dfs_level=level) as h:
+                    assert np.array_equal(h.histogram(), w.hist), (rep, g.name, level)
+                    assert np.array_equal(h.frontier(), w.front), (rep, g.name, level)
+
+
 def test_budget_overflow_switches_to_depth_first(cc):
     # 6x8 grid: the largest level holds 46482 paths; 512 KiB of frontier
     # budget holds about 14600 (enumerate) or 26200 (count) per level, so the
