@@ -170,8 +170,9 @@ def main():
     verts = torch.empty(n_verts, dtype=torch.int32, device="cuda")
     offs = torch.empty(n_cycles + 1, dtype=torch.int64, device="cuda")
 
-    def step(profile):
-        with cc.Graph(g.n, rp, ci, stream=stream, profile=profile) as h:
+    def step(profile, persistent_levels=False):
+        with cc.Graph(g.n, rp, ci, stream=stream, profile=profile,
+                      persistent_levels=persistent_levels) as h:
             nc, nv = h.enumerate_into(verts, offs)
             assert nc == n_cycles and nv == n_verts
             return h.last_run()
@@ -200,7 +201,7 @@ def main():
         "gpu_ms_per_step": round(sum(i["gpu_ms"] for i in infos) / len(infos), 4),
     }
     if profile:
-        # Second timed pass of the same steps with a HIP event pair around
+        # Second timed pass of the same steps with HIP event pairs around
         # every level launch (on the stream the kernels run on): the level
         # kernel's average launch duration and the bytes it must move.
         torch.cuda.synchronize()
@@ -210,19 +211,33 @@ def main():
         lvl_bytes = sum(i["level_bytes"] for i in pinfos)
         launches = sum(i["levels_launched"] for i in pinfos)
         achieved = lvl_bytes / (lvl_ms * 1e-3) / 1e9 if lvl_ms > 0 else 0.0
+        persistent = launches == len(pinfos)
         out["roofline"] = {"bound": "hbm",
-                           "kernel": "k_level (breadth-first level with staged-cycle decode)",
+                           "kernel": ("k_levels (all breadth-first levels in one cooperative "
+                                      "launch, staged-cycle decode)" if persistent else
+                                      "k_level (one breadth-first level per launch)"),
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBPS, 4),
                            "traffic": counted_traffic(),
                            "bytes_per_launch": round(lvl_bytes / max(launches, 1), 1),
                            "avg_launch_us": round(lvl_ms * 1e3 / max(launches, 1), 3),
                            "launches_per_step": round(launches / len(pinfos), 1),
-                           "measured": "per-level HIP events, second pass of the timed steps"}
+                           "measured": "HIP events around every level launch, second pass of "
+                                       "the timed steps"}
         out["breakdown_ms"] = {
             "stage1": round(sum(i["stage1_ms"] for i in pinfos) / len(pinfos), 4),
             "levels": round(lvl_ms / len(pinfos), 4),
             "dfs": round(sum(i["dfs_ms"] for i in pinfos) / len(pinfos), 4)}
+        # the same step with all levels in one cooperative launch, for comparison
+        for _ in range(2):
+            step(False, persistent_levels=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            step(False, persistent_levels=True)
+        torch.cuda.synchronize()
+        out["persistent_level_loop_ms_per_step"] = round(
+            (time.perf_counter() - t1) * 1e3 / args.steps, 4)
     if not args.no_batch:
         out["batched"] = batched_section(args)
     if not args.no_serve:

@@ -67,6 +67,9 @@ typedef enum cc_status {
 #define CC_OUTPUT_DEVICE (1u << 1) /* cc_enumerate's verts/offsets are device pointers        */
 #define CC_FORCE_DFS     (1u << 2) /* take the depth-first path from level dfs_level on      */
 #define CC_PROFILE       (1u << 3) /* time each kernel of a run with HIP events (cc_run_info) */
+#define CC_LEVEL_PERSISTENT (1u << 4) /* run all breadth-first levels in one cooperative
+                                        launch with a grid barrier between levels, instead
+                                        of one launch per level (same results)             */
 
 typedef struct cc_options {
   void *stream;                  /* hipStream_t; NULL = the null stream                 */
@@ -148,6 +151,12 @@ cc_status cc_labels(cc_graph *g, int32_t *labels);
  * that the last run expanded (front[3] = |T(G)|, Section 2), for
  * 0 <= t < len, len >= n+1 (host array). */
 cc_status cc_frontier(cc_graph *g, int64_t *front, int32_t len);
+
+/* cc_level_times -- device time in ms of each breadth-first level kernel
+ * of the last call made with CC_PROFILE: ms[t] for the level that expands
+ * paths with t vertices (0 where no level was launched), 0 <= t < len,
+ * len >= n+1 (host array).  All zeros after a call without CC_PROFILE. */
+cc_status cc_level_times(cc_graph *g, double *ms, int32_t len);
 
 /* cc_last_run -- statistics of the last count/histogram/enumerate call. */
 cc_status cc_last_run(cc_graph *g, cc_run_info *info);

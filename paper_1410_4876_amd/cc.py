@@ -32,6 +32,7 @@ CC_INPUT_DEVICE = 1 << 0
 CC_OUTPUT_DEVICE = 1 << 1
 CC_FORCE_DFS = 1 << 2
 CC_PROFILE = 1 << 3
+CC_LEVEL_PERSISTENT = 1 << 4
 CC_MAX_VERTICES = 128
 CC_BATCH_PERSISTENT = 0
 CC_BATCH_PER_GRAPH = 1
@@ -102,6 +103,8 @@ def lib():
             L.cc_labels.restype = ctypes.c_int
             L.cc_frontier.argtypes = [vp, vp, i32]
             L.cc_frontier.restype = ctypes.c_int
+            L.cc_level_times.argtypes = [vp, vp, i32]
+            L.cc_level_times.restype = ctypes.c_int
             L.cc_last_run.argtypes = [vp, ctypes.POINTER(RunInfo)]
             L.cc_last_run.restype = ctypes.c_int
             L.cc_release.argtypes = [vp]
@@ -183,7 +186,7 @@ class Graph:
     def __init__(self, n, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
                  force_dfs_level: int | None = None, dfs_waves_per_cu: int = 0,
                  bfs_blocks: int = 0, output_device: bool = True, profile: bool = False,
-                 dfs_donate_min: int = 0, dfs_claim: int = 0):
+                 dfs_donate_min: int = 0, dfs_claim: int = 0, persistent_levels: bool = False):
         L = lib()
         rp, rp_dev, self._k1 = _ptr(_as_i32(row_ptr))
         ci, ci_dev, self._k2 = _ptr(_as_i32(col_idx))
@@ -198,6 +201,8 @@ class Graph:
             flags |= CC_FORCE_DFS
         if profile:
             flags |= CC_PROFILE
+        if persistent_levels:
+            flags |= CC_LEVEL_PERSISTENT
         self.opt = Options(_stream_handle(stream), int(budget_bytes), flags,
                            int(force_dfs_level or 0), int(dfs_waves_per_cu), int(bfs_blocks),
                            int(dfs_donate_min), int(dfs_claim))
@@ -288,6 +293,12 @@ class Graph:
         f = np.zeros(self.n + 1, np.int64)
         _check(lib().cc_frontier(self.h, ctypes.c_void_p(f.ctypes.data), f.size), "cc_frontier")
         return f
+
+    def level_times(self) -> np.ndarray:
+        """Per-level device ms of the last call made with profile=True."""
+        a = np.zeros(self.n + 1, np.float64)
+        _check(lib().cc_level_times(self.h, ctypes.c_void_p(a.ctypes.data), a.size), "cc_level_times")
+        return a
 
     def last_run(self) -> dict:
         info = RunInfo()

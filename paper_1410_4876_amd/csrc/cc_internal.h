@@ -24,6 +24,7 @@
 #define CC_DEV_IDLE_TIMEOUT 4u    // an idle wavefront gave up waiting (diagnostic only)
 #define CC_DEV_CORRUPT 8u         // a depth-first consistency check failed (results discarded)
 #define CC_DEV_LOST 16u           // a wavefront gave up on paths it was promised (results incomplete)
+#define CC_DEV_BARRIER_TIMEOUT 32u  // a block of the level loop gave up at a grid barrier
 // First failed consistency check (CcCtl::diag): kind << 24 | low 24 bits of the value.
 #define CC_DIAG_INBOX_COUNT 1u    // more paths announced than an inbox holds
 #define CC_DIAG_REQUESTER 2u      // a work request names no wavefront of this launch
@@ -39,6 +40,9 @@
 struct CcCtl {
   unsigned long long count_sh[CC_SHARDS][CC_HSLOTS];  // open paths with t vertices, per shard
   unsigned long long hist_sh[CC_SHARDS][CC_HSLOTS];   // cycles with k vertices, per shard
+  unsigned int bar_arrive[CC_SHARDS][32];   // grid barrier: arrivals per shard (own line each)
+  unsigned int bar_top[32];                 // grid barrier: shards complete
+  unsigned int bar_gen[32];                 // grid barrier: generation
   unsigned long long hist[CC_HSLOTS];       // final histogram (written by k_finalize)
   unsigned long long front[CC_HSLOTS];      // paths with t vertices expanded
   unsigned long long cum_c[CC_HSLOTS];      // enumerate: cycles of length <= t (breadth-first)
@@ -51,6 +55,8 @@ struct CcCtl {
   unsigned long long root_cursor;           // depth-first: next unclaimed handed-over path
   unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
   unsigned long long donations;             // chunks given away on request (diagnostic)
+  unsigned long long level_clock[CC_HSLOTS]; // persistent level loop: clock at each level start
+  int levels_run;                           // persistent level loop: levels run
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over
   int switch_level;                         // path length handed to the depth-first kernel
   int skip;                                 // CC_SKIP_* bits for the handed-over paths
@@ -161,8 +167,18 @@ hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n
 hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s);
 hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
                               Stage st, hipStream_t s);
-// host_done (pinned host memory, may be NULL) receives the first level that
-// found nothing to do, so the host can stop launching levels early.
+// host_done (pinned host memory, may be NULL): host_done[0] receives the
+// first level that found nothing to do, so the host can stop launching
+// levels early; host_done[1] the last level that started.
+// The whole level loop as one cooperative launch of `blocks` blocks (at
+// most cc_levels_max_blocks).  With `clock` (device memory, may be NULL) the
+// start of every level is recorded.
+hipError_t cc_launch_levels(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f0,
+                            Frontier f1, Stage st0, Stage st1, OutDev out, int forced_level,
+                            int blocks, unsigned long long barrier_timeout,
+                            unsigned long long *clock, hipStream_t s);
+// Blocks of k_levels that fit on the device at once (0 if unknown).
+int cc_levels_max_blocks(int W, bool enumerate);
 hipError_t cc_launch_level(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier fin,
                            Frontier fout, Stage sprev, Stage scur, OutDev out, int t,
                            int forced_level, int blocks, unsigned int *host_done,

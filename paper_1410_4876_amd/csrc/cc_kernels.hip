@@ -188,8 +188,11 @@ __device__ __forceinline__ void dfs_corrupt(CcCtl *ctl, unsigned kind, unsigned 
   atomicCAS(&ctl->diag, 0u, (kind << 24) | (value & 0xffffffu));
 }
 
+// A word for the host: the store, then a system-scope release so the line
+// leaves the GPU caches now rather than at some later write-back.
 __device__ __forceinline__ void st_system(unsigned int *p, unsigned int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
 }
 
 // ------------------------------------------------------------ shards
@@ -517,77 +520,93 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
 // output index cum_c[t-1] + g, vertices at cum_v[t-1] + g * t, so the output
 // is ordered by length.  Every lane decodes one cycle.
 //
-// The frontier size lives in device memory, so the host launches the level
-// loop without reading anything back (Algorithm 4's fixed relaunches); if
-// `host_done` is given, the kernel also tells the host when the levels have
-// nothing left to do so that it can stop launching them.
+// The level loop runs either as one persistent kernel with a grid barrier
+// between levels (k_levels) or as one launch per level (k_level, Algorithm
+// 4's fixed relaunches without readback); both run level_body.
+
+// Shared memory of one block running levels.
 template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Frontier fin,
-                                                    Frontier fout, Stage sprev, Stage scur,
-                                                    OutDev out, int t, int forced_level,
-                                                    unsigned int *host_done) {
+struct LevelLds {
+  unsigned long long N[CC_MAXN * W];              // label-space adjacency
+  unsigned long long No[ENUM ? CC_MAXN * W : 1];  // original-id adjacency
+  int Perm[ENUM ? CC_MAXN : 1];
+  unsigned long long Pre[CC_SHARDS + 1];
+  unsigned long long PreH[ENUM ? CC_SHARDS + 1 : 1];
+  unsigned int WaveExt[CC_BLOCK / CC_WAVE];
+  unsigned int WaveClos[CC_BLOCK / CC_WAVE];
+  unsigned long long ExtBase, ClosBase;
+  unsigned long long Red[CC_BLOCK / CC_WAVE];
+  unsigned long long Cum[2];
+  int Flags;
+};
+
+// level_body results
+#define CC_LEVEL_NEXT 0      // the level was expanded; continue with t + 1
+#define CC_LEVEL_SWITCH 1    // handed over to the depth-first kernel
+#define CC_LEVEL_EMPTY 2     // no paths with t vertices: the loop is over
+
+template <int W, bool ENUM>
+__device__ void load_graph_lds(const GraphDev &g, LevelLds<W, ENUM> &L) {
+  for (int i = threadIdx.x; i < g.n * W; i += CC_BLOCK) L.N[i] = g.adj[i];
+  if (ENUM) {
+    for (int i = threadIdx.x; i < g.n * W; i += CC_BLOCK) L.No[i] = g.adj_orig[i];
+    for (int i = threadIdx.x; i < g.n; i += CC_BLOCK) L.Perm[i] = g.perm[i];
+  }
+}
+
+// One level for this block.  Every block of the grid reaches the same
+// result, computed from the same counters.  With lds_ready false the graph
+// is loaded into LDS here, together with the counters, so that a block
+// waits for one round of loads before it starts on its paths.
+template <int W, bool ENUM>
+__device__ int level_body(const GraphDev &g, CcCtl *ctl, const Frontier &fin,
+                          const Frontier &fout, const Stage &sprev, const Stage &scur,
+                          const OutDev &out, int t, int forced_level, LevelLds<W, ENUM> &L,
+                          bool lds_ready) {
   constexpr int IPT = CC_LEVEL_IPT;
   constexpr int NW = CC_BLOCK / CC_WAVE;
-  __shared__ unsigned long long sN[CC_MAXN * W];
-  __shared__ unsigned long long sNo[ENUM ? CC_MAXN * W : 1];
-  __shared__ int sPerm[ENUM ? CC_MAXN : 1];
-  __shared__ unsigned long long sPre[CC_SHARDS + 1];
-  __shared__ unsigned long long sPreH[ENUM ? CC_SHARDS + 1 : 1];
-  __shared__ unsigned int sWaveExt[NW];
-  __shared__ unsigned int sWaveClos[NW];
-  __shared__ unsigned long long sExtBase, sClosBase;
-  __shared__ unsigned long long sRed[NW];
-  __shared__ unsigned long long sCum[2];
-  __shared__ int sFlags;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / CC_WAVE;
-  if (ld_relaxed(&ctl->mode) != 0) {
-    if (host_done && blockIdx.x == 0 && tid == 0) st_system(host_done, (unsigned)t);
-    return;
-  }
-  const int n = g.n;
   if (wave == 0) {
     const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][t]);
-    shard_prefix(c, sPre);
+    shard_prefix(c, L.Pre);
     const bool ovf = c > fin.cap_s;
     bool hovf = false;
     if (ENUM) {
       const unsigned long long h = ld_relaxed(&ctl->hist_sh[lane][t]);
-      shard_prefix(h, sPreH);
+      shard_prefix(h, L.PreH);
       hovf = h > sprev.cap_s;
     }
     const unsigned long long mo = wave_ballot(ovf), mh = wave_ballot(hovf);
     if (lane == 0) {
-      sFlags = (mo ? 1 : 0) | (mh ? 2 : 0);
+      L.Flags = (mo ? 1 : 0) | (mh ? 2 : 0);
       if (ENUM) {
-        sCum[0] = ld_relaxed(&ctl->cum_c[t - 1]);
-        sCum[1] = ld_relaxed(&ctl->cum_v[t - 1]);
+        L.Cum[0] = ld_relaxed(&ctl->cum_c[t - 1]);
+        L.Cum[1] = ld_relaxed(&ctl->cum_v[t - 1]);
       }
     }
   }
-  if (ENUM) {
-    for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
-  }
+  if (!lds_ready) load_graph_lds<W, ENUM>(g, L);
   __syncthreads();
-  const int flags = sFlags;
-  const unsigned long long cnt = sPre[CC_SHARDS];
+  const int flags = L.Flags;
+  const unsigned long long cnt = L.Pre[CC_SHARDS];
 
   // ---- decode the cycles with t vertices staged by the previous level
   if (ENUM && !(flags & 2)) {
-    const unsigned long long htot = sPreH[CC_SHARDS];
-    const long long cb = (long long)sCum[0], vb = (long long)sCum[1];
+    const unsigned long long htot = L.PreH[CC_SHARDS];
+    const long long cb = (long long)L.Cum[0], vb = (long long)L.Cum[1];
     for (unsigned long long gi = (unsigned long long)blockIdx.x * CC_BLOCK + tid; gi < htot;
          gi += (unsigned long long)gridDim.x * CC_BLOCK) {
-      const int s = shard_of(sPreH, gi);
-      const unsigned long long e = (unsigned long long)s * sprev.cap_s + (gi - sPreH[s]);
+      const int s = shard_of(L.PreH, gi);
+      const unsigned long long e = (unsigned long long)s * sprev.cap_s + (gi - L.PreH[s]);
       Bits<W> C;
 #pragma unroll
       for (int w = 0; w < W; ++w) C.w[w] = sprev.C[w * sprev.cap + e];
       const long long cyc = cb + (long long)gi;
       const long long pos = vb + (long long)gi * t;
       if (cyc < out.cyc_cap && pos + t <= out.verts_cap) {
-        write_cycle<W>(sNo, C, t, out.verts + pos);
+        write_cycle<W>(L.No, C, t, out.verts + pos);
         out.offs[cyc] = pos;
       }
     }
@@ -624,21 +643,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
       ctl->bfs_max_len = sw_max;
       __threadfence();
       st_release(&ctl->mode, 1);
-      if (host_done) st_system(host_done, (unsigned)t);
     }
-    return;
+    return CC_LEVEL_SWITCH;
   }
-  if (cnt == 0) {
-    if (host_done && blockIdx.x == 0 && tid == 0) st_system(host_done, (unsigned)t);
-    return;
-  }
+  if (cnt == 0) return CC_LEVEL_EMPTY;
   const unsigned long long chunk = (unsigned long long)CC_BLOCK * IPT;
-  // Blocks without a chunk leave before staging anything more.
-  if ((unsigned long long)blockIdx.x * chunk >= cnt) return;
-  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
-  if (ENUM)
-    for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
-  __syncthreads();
+  // Blocks without a chunk have nothing more to do at this level.
+  if ((unsigned long long)blockIdx.x * chunk >= cnt) return CC_LEVEL_NEXT;
   if (blockIdx.x == 0 && tid == 0) {
     ctl->front[t] = cnt;
     atomicMax(&ctl->peak, cnt);
@@ -659,8 +670,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
       Sv[j] = bzero<W>();
       int a = 0, b = 0;
       if (valid) {
-        const int s = shard_of(sPre, i);
-        const unsigned long long e = (unsigned long long)s * fin.cap_s + (i - sPre[s]);
+        const int s = shard_of(L.Pre, i);
+        const unsigned long long e = (unsigned long long)s * fin.cap_s + (i - L.Pre[s]);
 #pragma unroll
         for (int w = 0; w < W; ++w) X.w[w] = fin.X[w * fin.cap + e];
         if (ENUM) {
@@ -671,8 +682,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
         a = vv & 0xffu;
         b = vv >> 8;
       }
-      const Bits<W> nvt = row<W>(sN, b);
-      const Bits<W> nv1 = row<W>(sN, a);
+      const Bits<W> nvt = row<W>(L.N, b);
+      const Bits<W> nv1 = row<W>(L.N, a);
       const Bits<W> cand = bandnot(nvt, X);
       clos[j] = valid ? band(cand, nv1) : bzero<W>();
       ext[j] = valid ? bandnot(cand, nv1) : bzero<W>();
@@ -685,25 +696,25 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
     const unsigned we = wave_sum_u32(my_ext);
     const unsigned wc = ENUM ? wave_sum_u32(my_clos) : 0u;
     if (lane == 0) {
-      sWaveExt[wave] = we;
-      sWaveClos[wave] = wc;
+      L.WaveExt[wave] = we;
+      L.WaveClos[wave] = wc;
     }
     __syncthreads();
     if (tid == 0) {
       unsigned te = 0, tc = 0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        te += sWaveExt[w];
-        tc += sWaveClos[w];
+        te += L.WaveExt[w];
+        tc += L.WaveClos[w];
       }
-      sExtBase = te ? atomicAdd(&ctl->count_sh[osh][k], (unsigned long long)te) : 0ull;
-      sClosBase = (ENUM && tc) ? atomicAdd(&ctl->hist_sh[osh][k], (unsigned long long)tc) : 0ull;
+      L.ExtBase = te ? atomicAdd(&ctl->count_sh[osh][k], (unsigned long long)te) : 0ull;
+      L.ClosBase = (ENUM && tc) ? atomicAdd(&ctl->hist_sh[osh][k], (unsigned long long)tc) : 0ull;
     }
     __syncthreads();
-    unsigned long long ebase = sExtBase, cbase = sClosBase;
+    unsigned long long ebase = L.ExtBase, cbase = L.ClosBase;
     for (int w = 0; w < wave; ++w) {
-      ebase += sWaveExt[w];
-      cbase += sWaveClos[w];
+      ebase += L.WaveExt[w];
+      cbase += L.WaveClos[w];
     }
     if (we) {
       unsigned long long off = 0;
@@ -722,7 +733,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
 #pragma unroll
               for (int w = 0; w < W; ++w) fout.X[w * fout.cap + o] = Xn[j].w[w];
               if (ENUM) {
-                const Bits<W> Sn = bor(Sv[j], bsingle<W>(sPerm[v]));
+                const Bits<W> Sn = bor(Sv[j], bsingle<W>(L.Perm[v]));
 #pragma unroll
                 for (int w = 0; w < W; ++w) fout.S[w * fout.cap + o] = Sn.w[w];
               }
@@ -747,7 +758,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
             const unsigned long long slot = cbase + off + lanes_below(mask);
             if (slot < scur.cap_s) {
               const unsigned long long o = (unsigned long long)osh * scur.cap_s + slot;
-              const Bits<W> C = bor(Sv[j], bsingle<W>(sPerm[v]));
+              const Bits<W> C = bor(Sv[j], bsingle<W>(L.Perm[v]));
 #pragma unroll
               for (int w = 0; w < W; ++w) scur.C[w * scur.cap + o] = C.w[w];
             }
@@ -760,13 +771,125 @@ __global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Fron
   }
   if (!ENUM) {
     acc = wave_sum_u64(acc);
-    if (lane == 0) sRed[wave] = acc;
+    if (lane == 0) L.Red[wave] = acc;
     __syncthreads();
     if (tid == 0) {
       unsigned long long sum = 0;
-      for (int i = 0; i < NW; ++i) sum += sRed[i];
+      for (int i = 0; i < NW; ++i) sum += L.Red[i];
       if (sum) atomicAdd(&ctl->hist_sh[osh][k], sum);
     }
+  }
+  return CC_LEVEL_NEXT;
+}
+
+// One launch per level.  `host_done` (pinned host memory, may be NULL)
+// receives the first level that found nothing to do, so the host can stop
+// launching levels.
+template <int W, bool ENUM>
+__global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Frontier fin,
+                                                    Frontier fout, Stage sprev, Stage scur,
+                                                    OutDev out, int t, int forced_level,
+                                                    unsigned int *host_done) {
+  __shared__ LevelLds<W, ENUM> L;
+  // host_done[1]: the last level that started, so the host keeps only a few
+  // levels queued ahead of the device
+  if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done + 1, (unsigned)t);
+  if (ld_relaxed(&ctl->mode) != 0) {
+    if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done, (unsigned)t);
+    return;
+  }
+  const int r = level_body<W, ENUM>(g, ctl, fin, fout, sprev, scur, out, t, forced_level, L,
+                                    false);
+  if (r != CC_LEVEL_NEXT && host_done && blockIdx.x == 0 && threadIdx.x == 0)
+    st_system(host_done, (unsigned)t);
+}
+
+// Grid-wide barrier of a cooperative launch (every block resident).  Blocks
+// arrive on one of CC_SHARDS counters (each on its own line, so no counter
+// serialises more than a few dozen arrivals); the last arrival of a shard
+// arrives on the top counter, and the last of those opens the next
+// generation.  Counters only grow (barrier number gen expects
+// (gen + 1) * arrivals), so nothing is reset between barriers.  The release
+// fence before arriving and the acquire fence after leaving make every
+// block's writes of the level visible to every block.  A block that waits
+// longer than `timeout` clock ticks records CC_DEV_BARRIER_TIMEOUT and
+// leaves, so every wait ends.
+__device__ void grid_barrier(CcCtl *ctl, unsigned long long timeout) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // this block saw generation gen open (or it is the first barrier)
+    const unsigned gen = ld_relaxed(&ctl->bar_gen[0]);
+    const unsigned nb = gridDim.x;
+    const unsigned sh = blockIdx.x % CC_SHARDS;
+    const unsigned in_shard = (nb - sh + CC_SHARDS - 1) / CC_SHARDS;  // blocks b = sh mod 64
+    const unsigned shards = nb < CC_SHARDS ? nb : CC_SHARDS;
+    if (atomicAdd(&ctl->bar_arrive[sh][0], 1u) == (gen + 1u) * in_shard - 1u) {
+      if (atomicAdd(&ctl->bar_top[0], 1u) == (gen + 1u) * shards - 1u)
+        __hip_atomic_store(&ctl->bar_gen[0], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const unsigned long long t0 = wall_clock64();
+    while (ld_relaxed(&ctl->bar_gen[0]) == gen) {
+      __builtin_amdgcn_s_sleep(2);
+      if (wall_clock64() - t0 > timeout) {
+        atomicOr(&ctl->status, CC_DEV_BARRIER_TIMEOUT);
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Field-wise selection (a select of whole structs would go through scratch).
+__device__ __forceinline__ Frontier pick(bool c, const Frontier &a, const Frontier &b) {
+  Frontier f;
+  f.X = c ? a.X : b.X;
+  f.S = c ? a.S : b.S;
+  f.vv = c ? a.vv : b.vv;
+  f.cap = c ? a.cap : b.cap;
+  f.cap_s = c ? a.cap_s : b.cap_s;
+  return f;
+}
+__device__ __forceinline__ Stage pick(bool c, const Stage &a, const Stage &b) {
+  Stage s;
+  s.C = c ? a.C : b.C;
+  s.cap = c ? a.cap : b.cap;
+  s.cap_s = c ? a.cap_s : b.cap_s;
+  return s;
+}
+
+// The whole level loop in one cooperative launch: the graph is loaded into
+// LDS once, levels t = 3.. run back to back with a grid barrier between
+// them, and the loop ends on the device when a level finds no paths or
+// hands over to the depth-first kernel.  With `clock` (may be NULL), block 0
+// records the wall clock at the start of every level and at the end
+// (clock[t] .. clock[t+1] is level t).
+template <int W, bool ENUM>
+__global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Frontier f0,
+                                                     Frontier f1, Stage st0, Stage st1,
+                                                     OutDev out, int forced_level,
+                                                     unsigned long long barrier_timeout,
+                                                     unsigned long long *clock) {
+  __shared__ LevelLds<W, ENUM> L;
+  load_graph_lds<W, ENUM>(g, L);
+  __syncthreads();
+  int t = 3, last = 2;  // last: the last level that ran
+  for (; t <= g.n; ++t) {
+    if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[t] = wall_clock64();
+    const bool odd = (t & 1) != 0;
+    const Frontier fin = pick(odd, f1, f0), fout = pick(odd, f0, f1);
+    const Stage sprev = pick(odd, st0, st1), scur = pick(odd, st1, st0);
+    const int r = level_body<W, ENUM>(g, ctl, fin, fout, sprev, scur, out, t, forced_level, L,
+                                      true);
+    last = t;
+    if (r != CC_LEVEL_NEXT) break;
+    grid_barrier(ctl, barrier_timeout);
+    if (ld_relaxed(&ctl->status) & CC_DEV_BARRIER_TIMEOUT) break;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (clock) clock[last + 1] = wall_clock64();  // last <= n <= CC_MAXN, so last + 1 < CC_HSLOTS
+    ctl->levels_run = last - 2;
   }
 }
 
@@ -1433,6 +1556,27 @@ hipError_t cc_launch_triplets(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f
     else hipLaunchKernelGGL((k_triplets<2, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
   }
   return hipGetLastError();
+}
+
+hipError_t cc_launch_levels(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
+                            Stage st0, Stage st1, OutDev out, int forced_level, int blocks,
+                            unsigned long long barrier_timeout, unsigned long long *clock,
+                            hipStream_t s) {
+  void *args[] = {&g, &ctl, &f0, &f1, &st0, &st1, &out, &forced_level, &barrier_timeout, &clock};
+  const void *fn = W == 1 ? (en ? (const void *)k_levels<1, true> : (const void *)k_levels<1, false>)
+                          : (en ? (const void *)k_levels<2, true> : (const void *)k_levels<2, false>);
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(CC_BLOCK), args, 0, s);
+}
+
+int cc_levels_max_blocks(int W, bool en) {
+  const void *fn = W == 1 ? (en ? (const void *)k_levels<1, true> : (const void *)k_levels<1, false>)
+                          : (en ? (const void *)k_levels<2, true> : (const void *)k_levels<2, false>);
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CC_BLOCK, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
 }
 
 hipError_t cc_launch_level(int W, bool en, GraphDev g, CcCtl *ctl, Frontier fin, Frontier fout,

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstddef>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -17,11 +18,14 @@
 namespace {
 
 constexpr int64_t kDefaultBudget = 4ll << 30;
+constexpr int kLevelsAhead = 4;    // level launches queued beyond the device's progress
+constexpr int kAheadWaitUs = 200;  // longest the host waits for that progress
 constexpr double kIdleTimeoutSeconds = 30.0;
 
 struct DeviceInfo {
   bool ok = false;
   int cus = 0;
+  bool coop = false;  // cooperative launches supported
   unsigned long long clock_hz = 0;
 };
 
@@ -47,6 +51,9 @@ cc_status device_info(int dev, DeviceInfo *out) {
       uint64_t thr = UINT64_MAX;
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
+    int coop = 0;
+    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    g_dev[dev].coop = coop != 0;
     g_dev[dev].cus = p.multiProcessorCount;
     g_dev[dev].clock_hz = (unsigned long long)rate_khz * 1000ull;
     g_dev[dev].ok = true;
@@ -114,6 +121,7 @@ struct cc_graph {
   hipEvent_t evp[2 * CC_MAXN + 8] = {};  // CC_PROFILE: around each kernel group
   bool have_run = false;
   int64_t hist[CC_HSLOTS]{};
+  double level_ms[CC_HSLOTS]{};  // CC_PROFILE: per-level device time
   int64_t front[CC_HSLOTS]{};
   cc_run_info info{};
 };
@@ -280,13 +288,14 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     d->claim = g->opt.dfs_claim > 0 ? (g->opt.dfs_claim + CC_CHUNK - 1) / CC_CHUNK * CC_CHUNK : 0;
   }
   const int dfs_blocks_c = nw_c / 4, dfs_blocks_e = nw_e / 4;
-  const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 8;
+  const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
   const int forced = (g->opt.flags & CC_FORCE_DFS) ? std::max(3, (int)g->opt.dfs_level) : -1;
   const unsigned long long idle_timeout =
       (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz);
 
   GraphDev gd{g->d_adj, g->d_adj_orig, g->d_perm, n};
   CcCtl *ctl = g->d_ctl;
+  for (double &x : g->level_ms) x = 0.0;
   hipError_t e = hipSuccess;
   int levels = 0;
   auto chk = [&](hipError_t x) {
@@ -307,18 +316,48 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   chk(cc_launch_triplets(W, en, gd, ctl, f[1], st[0], s));
   mark(1);
   // Level t expands the paths with t vertices and (enumerate mode) decodes
-  // the cycles with t vertices; level n only decodes.  The level kernels
-  // report the first level with nothing to do through a pinned host word and
-  // launching stops there (the remaining levels would all return at once).
-  // The flag may arrive late: extra launches are no-ops.
-  volatile unsigned int *done = g->h_done;
-  *done = 0u;
-  for (int t = 3; t <= n && e == hipSuccess; ++t, ++levels) {
-    if (*done != 0u) break;
-    mark(2 + 2 * (t - 3));
-    chk(cc_launch_level(W, en, gd, ctl, f[t & 1], f[(t + 1) & 1], st[(t - 1) & 1], st[t & 1],
-                        ro.out, t, forced, bfs_blocks, g->d_done, s));
-    mark(3 + 2 * (t - 3));
+  // the cycles with t vertices; level n only decodes.
+  //
+  // Default: one launch per level.  The level kernels report the first
+  // level with nothing to do through a pinned host word and launching stops
+  // there; the flag may arrive late, and extra launches are no-ops.  With
+  // CC_LEVEL_PERSISTENT, one cooperative launch runs every level with a grid
+  // barrier in between and stops on the device; on MI355X its barriers (an
+  // L2 write-back and invalidate per block) cost more than the launches they
+  // replace, so it is not the default.
+  const int coop_max = g->dev.coop && (g->opt.flags & CC_LEVEL_PERSISTENT)
+                           ? cc_levels_max_blocks(W, en)
+                           : 0;
+  const bool persistent = coop_max >= CC_SHARDS;
+  if (persistent) {
+    const int want = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
+    const int blocks = std::max(1, std::min(want, coop_max));
+    mark(2);
+    chk(cc_launch_levels(W, en, gd, ctl, f[0], f[1], st[0], st[1], ro.out, forced, blocks,
+                         (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz),
+                         prof ? dev_field(ctl, offsetof(CcCtl, level_clock)) : nullptr, s));
+    mark(3);
+  } else {
+    // The host keeps at most kLevelsAhead launches queued beyond the last
+    // level the device has started, waiting at most kAheadWaitUs for it, so
+    // that it sees the done flag a few levels after the frontier empties.
+    volatile unsigned int *done = g->h_done;
+    done[0] = 0u;
+    done[1] = 0u;
+    for (int t = 3; t <= n && e == hipSuccess; ++t, ++levels) {
+      if (t - 3 >= kLevelsAhead) {
+        const auto t_wait = std::chrono::steady_clock::now();
+        while (done[0] == 0u && (int)done[1] < t - kLevelsAhead &&
+               std::chrono::steady_clock::now() - t_wait <
+                   std::chrono::microseconds(kAheadWaitUs)) {
+        }
+      }
+      if (done[0] != 0u) break;
+      mark(2 + 2 * (t - 3));
+      chk(cc_launch_level(W, en, gd, ctl, f[t & 1], f[(t + 1) & 1], st[(t - 1) & 1],
+                          st[t & 1], ro.out, t, forced, bfs_blocks, g->d_done, s));
+      mark(3 + 2 * (t - 3));
+    }
   }
   // Depth-first continuation (each kernel returns at once if the levels
   // finished within the budget).
@@ -364,7 +403,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   g->info.paths = paths;
   g->info.peak_frontier = (int64_t)h.peak;
   g->info.switch_level = h.mode ? h.switch_level : 0;
-  g->info.levels_launched = levels;
+  g->info.levels_launched = persistent ? 1 : levels;
+  if (persistent) levels = h.levels_run;
   g->info.gpu_ms = ms;
   g->info.stage1_ms = g->info.level_ms = g->info.dfs_ms = 0.0;
   g->info.level_bytes = 0;
@@ -375,7 +415,18 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       return (double)x;
     };
     g->info.stage1_ms = span(0, 1);
-    for (int t = 3; t < 3 + levels; ++t) g->info.level_ms += span(2 + 2 * (t - 3), 3 + 2 * (t - 3));
+    if (persistent) {
+      // per-level spans from the clock block 0 read at the start of each level
+      g->info.level_ms = span(2, 3);
+      for (int t = 3; t < 3 + levels && t + 1 < CC_HSLOTS; ++t)
+        g->level_ms[t] = (double)(h.level_clock[t + 1] - h.level_clock[t]) * 1e3 /
+                         (double)g->dev.clock_hz;
+    } else {
+      for (int t = 3; t < 3 + levels; ++t) {
+        g->level_ms[t] = span(2 + 2 * (t - 3), 3 + 2 * (t - 3));
+        g->info.level_ms += g->level_ms[t];
+      }
+    }
     g->info.dfs_ms = span(2 * n + 2, 2 * n + 3);
     // Bytes the level kernels must move: each path they expand is read once
     // and each extension they write is written once (X words, S words in
@@ -400,7 +451,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   }
   g->have_run = true;
   g->info.device_diag = (int64_t)h.diag;
-  if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST)) return CC_ERR_INTERNAL;
+  if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST | CC_DEV_BARRIER_TIMEOUT)) return CC_ERR_INTERNAL;
   if (h.status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
   return CC_OK;
 }
@@ -453,7 +504,7 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   if (n > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
   if (n > 0 && !row_ptr) return CC_ERR_INVALID_ARG;
   const uint32_t flags = opt ? opt->flags : 0u;
-  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE))
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT))
     return CC_ERR_INVALID_ARG;
   if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
               opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))
@@ -480,7 +531,13 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   g->W = n <= 64 ? 1 : 2;
   const size_t adj_b = align_up((size_t)CC_MAXN * 2 * 8, 256);
   const size_t vec_b = align_up((size_t)CC_MAXN * 4, 256);
-  const size_t blob = 2 * adj_b + 2 * vec_b + 256 + align_up(sizeof(CcCtl), 256);
+  const size_t ctl_b = align_up(sizeof(CcCtl), 256);
+  // staging for a host CSR (at most CC_MAXN rows and CC_MAXN (CC_MAXN - 1)
+  // entries), so preparing a handle allocates nothing after warm-up and
+  // never splits the stream-ordered pool that holds the run arenas
+  const size_t rp_b = align_up((size_t)(CC_MAXN + 1) * 4, 256);
+  const size_t ci_b = align_up((size_t)CC_MAXN * (CC_MAXN - 1) * 4, 256);
+  const size_t blob = 2 * adj_b + 2 * vec_b + 256 + ctl_b + rp_b + ci_b;
   auto fail = [&](cc_status s) {
     cc_release(g);
     return s;
@@ -516,27 +573,24 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
     return CC_OK;
   }
   const int *d_rp = row_ptr, *d_ci = col_idx;
-  void *tmp = nullptr;
   hipStream_t s = g->stream;
   if (!(flags & CC_INPUT_DEVICE)) {
-    const size_t rb = align_up((size_t)(n + 1) * 4, 256);
-    if (hipMallocAsync(&tmp, rb + (size_t)std::max<int64_t>(nnz, 1) * 4, s) != hipSuccess)
-      return fail(CC_ERR_OUT_OF_MEMORY);
-    if (hipMemcpyAsync(tmp, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-        (nnz > 0 && hipMemcpyAsync((char *)tmp + rb, col_idx, (size_t)nnz * 4,
-                                   hipMemcpyHostToDevice, s) != hipSuccess)) {
-      (void)hipFreeAsync(tmp, s);
+    // nnz <= n (n - 1) was checked above, so the CSR fits the staging area
+    int *st_rp = (int *)(b + 2 * adj_b + 2 * vec_b + 256 + ctl_b);
+    int *st_ci = (int *)((char *)st_rp + rp_b);
+    if (hipMemcpyAsync(st_rp, row_ptr, (size_t)(n + 1) * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync(st_ci, col_idx, (size_t)nnz * 4, hipMemcpyHostToDevice, s) !=
+                        hipSuccess)) {
       (void)hipStreamSynchronize(s);
       return fail(CC_ERR_DEVICE);
     }
-    d_rp = (const int *)tmp;
-    d_ci = (const int *)((char *)tmp + rb);
+    d_rp = st_rp;
+    d_ci = st_ci;
   }
   hipError_t e = cc_launch_ingest(g->W, 1, nullptr, n, d_rp, d_ci, g->d_adj, g->d_adj_orig, g->d_perm,
                                   g->d_label, g->d_status, nullptr, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&g->h_ctl->status, g->d_status, 4, hipMemcpyDeviceToHost, s);
-  if (tmp) (void)hipFreeAsync(tmp, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(hip_err(e));
   const unsigned int stv = g->h_ctl->status;
@@ -662,6 +716,12 @@ cc_status cc_last_run(cc_graph *g, cc_run_info *info) {
   return CC_OK;
 }
 
+cc_status cc_level_times(cc_graph *g, double *ms, int32_t len) {
+  if (!g || !ms || len < g->n + 1) return CC_ERR_INVALID_ARG;
+  for (int t = 0; t < len; ++t) ms[t] = (t < CC_HSLOTS && g->have_run) ? g->level_ms[t] : 0.0;
+  return CC_OK;
+}
+
 void cc_release(cc_graph *g) {
   if (!g) return;
   (void)hipSetDevice(g->device);
@@ -731,7 +791,7 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   *out = nullptr;
   if (n_graphs < 0 || !graph_vtx_off || (n_graphs > 0 && !row_ptr)) return CC_ERR_INVALID_ARG;
   const uint32_t flags = opt ? opt->flags : 0u;
-  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE))
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT))
     return CC_ERR_INVALID_ARG;
   if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
               opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))

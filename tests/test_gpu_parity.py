@@ -239,3 +239,18 @@ def test_workload_grid7x12_count_only_4gb(cc):
         assert h.frontier().tolist() == gold["front"]
         info = h.last_run()
         print("grid7x12", info)
+
+
+def test_persistent_level_loop_matches(cc):
+    """All levels in one cooperative launch with grid barriers: the same
+    cycle sets, histograms and path counts as the per-level launches, also
+    when the loop hands over to the depth-first kernel."""
+    g = gg.permute_random(gg.grid(5, 7), np.random.default_rng(9))
+    full_parity(cc, g, persistent_levels=True)
+    full_parity(cc, gg.workload_er40(), persistent_levels=True)
+    full_parity(cc, gg.er_gnm(100, 125, np.random.default_rng(9)), persistent_levels=True)
+    info = full_parity(cc, g, persistent_levels=True, force_dfs_level=7)
+    assert info["switch_level"] == 7
+    info = full_parity(cc, gg.permute_random(gg.grid(6, 8), np.random.default_rng(5)),
+                       persistent_levels=True, budget_bytes=512 << 10)
+    assert info["switch_level"] > 3
