@@ -43,6 +43,12 @@ struct CcCtl {
   unsigned int bar_arrive[CC_SHARDS][32];   // grid barrier: arrivals per shard (own line each)
   unsigned int bar_top[32];                 // grid barrier: shards complete
   unsigned int bar_gen[32];                 // grid barrier: generation
+  unsigned int xcd_blocks[16][32];          // level loop: blocks on each XCD (own line each)
+  unsigned int xcd_arrive[16][32];          // level loop: arrivals per XCD
+  unsigned int xcd_depart[16][32];          // level loop: departures per XCD (first one invalidates)
+  unsigned int xcd_go[16][32];              // level loop: XCD L2 invalidated for generation
+  unsigned int xcd_top[32];                 // level loop: XCDs complete
+  unsigned int xcd_gen[32];                 // level loop: barrier generation
   unsigned long long hist[CC_HSLOTS];       // final histogram (written by k_finalize)
   unsigned long long front[CC_HSLOTS];      // paths with t vertices expanded
   unsigned long long cum_c[CC_HSLOTS];      // enumerate: cycles of length <= t (breadth-first)

@@ -859,6 +859,57 @@ __device__ __forceinline__ Stage pick(bool c, const Stage &a, const Stage &b) {
   return s;
 }
 
+// The XCD (accelerator complex die, with its own L2) this wavefront runs on.
+__device__ __forceinline__ unsigned xcc_id() {
+  unsigned x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  return x & 0xfu;
+}
+
+// Level-loop barrier with one L2 write-back and one L2 invalidate per XCD
+// instead of one per block.  Blocks of one XCD share its L2: once every
+// block of the XCD has arrived (each after its stores completed), the last
+// arrival writes that L2 back and arrives on the top counter; the last top
+// arrival opens the next generation.  On leaving, the first block of each
+// XCD invalidates the XCD's L2 and tells the others, and every block
+// invalidates its own CU's L1.  xcd_blocks[] holds the blocks per XCD
+// (counted once at the start of the kernel); nx the XCDs that have blocks.
+__device__ void xcd_barrier(CcCtl *ctl, unsigned xcc, unsigned nx, unsigned long long timeout) {
+  wait_mem();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned gen = ld_relaxed(&ctl->xcd_gen[0]);
+    const unsigned mine = ld_relaxed(&ctl->xcd_blocks[xcc][0]);
+    const unsigned long long t0 = wall_clock64();
+    bool late = false;
+    if (atomicAdd(&ctl->xcd_arrive[xcc][0], 1u) == (gen + 1u) * mine - 1u) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this XCD's L2 to memory
+      if (atomicAdd(&ctl->xcd_top[0], 1u) == (gen + 1u) * nx - 1u)
+        st_coh(&ctl->xcd_gen[0], gen + 1u);
+    }
+    while (ld_relaxed(&ctl->xcd_gen[0]) == gen) {
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > timeout) {
+        late = true;
+        break;
+      }
+    }
+    if (!late && atomicAdd(&ctl->xcd_depart[xcc][0], 1u) == gen * mine) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // this XCD's L2 and this CU's L1
+      st_coh(&ctl->xcd_go[xcc][0], gen + 1u);
+    } else {
+      while (!late && ld_relaxed(&ctl->xcd_go[xcc][0]) != gen + 1u) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > timeout) late = true;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      asm volatile("buffer_inv sc0" ::: "memory");  // this CU's L1
+    }
+    if (late) atomicOr(&ctl->status, CC_DEV_BARRIER_TIMEOUT);
+  }
+  __syncthreads();
+}
+
 // The whole level loop in one cooperative launch: the graph is loaded into
 // LDS once, levels t = 3.. run back to back with a grid barrier between
 // them, and the loop ends on the device when a level finds no paths or
@@ -872,8 +923,19 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Fro
                                                      unsigned long long barrier_timeout,
                                                      unsigned long long *clock) {
   __shared__ LevelLds<W, ENUM> L;
+  __shared__ unsigned sNx;
   load_graph_lds<W, ENUM>(g, L);
+  // count the blocks of each XCD once, behind a plain grid barrier
+  const unsigned xcc = xcc_id();
+  if (threadIdx.x == 0) atomicAdd(&ctl->xcd_blocks[xcc][0], 1u);
+  grid_barrier(ctl, barrier_timeout);
+  if (threadIdx.x == 0) {
+    unsigned nx = 0;
+    for (int x = 0; x < 16; ++x) nx += ld_relaxed(&ctl->xcd_blocks[x][0]) != 0u;
+    sNx = nx;
+  }
   __syncthreads();
+  const unsigned nx = sNx;
   int t = 3, last = 2;  // last: the last level that ran
   for (; t <= g.n; ++t) {
     if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[t] = wall_clock64();
@@ -884,7 +946,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Fro
                                       true);
     last = t;
     if (r != CC_LEVEL_NEXT) break;
-    grid_barrier(ctl, barrier_timeout);
+    xcd_barrier(ctl, xcc, nx, barrier_timeout);
     if (ld_relaxed(&ctl->status) & CC_DEV_BARRIER_TIMEOUT) break;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
