@@ -35,6 +35,21 @@
 #define CC_SKIP_FRONT 1           // their path count is already recorded
 #define CC_SKIP_CLOSE 2           // their closures are already recorded
 
+// State of one breadth-first step: it expands the paths with t vertices
+// held in frontier buffer fbuf, by one level or by two, and decodes the
+// cycles the previous step staged in stage pair spair (lengths slen0 and,
+// after a two-level step, slen1; 0 = none).
+struct StepState {
+  int t;
+  int fbuf;
+  int spair;
+  int slen0;
+  int slen1;
+  int prev_two;  // the previous step expanded two levels
+  int done;      // the loop is over (nothing left, or handed over)
+  int pad;
+};
+
 // Control block of one run in device memory.  Zeroed by a kernel at the start
 // of every run.  Per-shard arrays are shard-major, [s][k].
 struct CcCtl {
@@ -61,8 +76,11 @@ struct CcCtl {
   unsigned long long root_cursor;           // depth-first: next unclaimed handed-over path
   unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
   unsigned long long donations;             // chunks given away on request (diagnostic)
-  unsigned long long level_clock[CC_HSLOTS]; // persistent level loop: clock at each level start
-  int levels_run;                           // persistent level loop: levels run
+  unsigned long long level_clock[CC_HSLOTS]; // persistent level loop: clock at each step start
+  int levels_run;                           // persistent level loop: steps run
+  int root_buf;                             // frontier buffer of the handed-over paths
+  StepState ss[2];                          // step s reads ss[s & 1]; its block 0 writes the other
+  int step_level[CC_HSLOTS];                // t of each step
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over
   int switch_level;                         // path length handed to the depth-first kernel
   int skip;                                 // CC_SKIP_* bits for the handed-over paths
@@ -102,6 +120,14 @@ struct GraphDev {
   const unsigned long long *adj_orig;
   const int *perm;
   int n;
+};
+
+// The breadth-first buffers of a run: two frontier buffers used in turn,
+// and two pairs of staging buffers (one pair written by a step, the other
+// decoded by it).
+struct LevelBufs {
+  Frontier f[2];
+  Stage st[4];
 };
 
 // Enumeration output (cc_enumerate's buffers).
@@ -171,26 +197,30 @@ hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n
                             unsigned int *status, long long *bound, hipStream_t s);
 // Stage one of graphs bt.g0 .. bt.g0 + n_graphs - 1 (one block each).
 hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s);
+// Stage one: the initial triplets go to frontier f3 (buffer 1), triangles
+// to stage st (pair 0, slot 0); sets the state of step 0.
 hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
                               Stage st, hipStream_t s);
-// host_done (pinned host memory, may be NULL): host_done[0] receives the
-// first level that found nothing to do, so the host can stop launching
-// levels early; host_done[1] the last level that started.
-// The whole level loop as one cooperative launch of `blocks` blocks (at
-// most cc_levels_max_blocks).  With `clock` (device memory, may be NULL) the
-// start of every level is recorded.
-hipError_t cc_launch_levels(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f0,
-                            Frontier f1, Stage st0, Stage st1, OutDev out, int forced_level,
-                            int blocks, unsigned long long barrier_timeout,
-                            unsigned long long *clock, hipStream_t s);
+// Step `step` of the breadth-first loop, one launch.  max_children bounds
+// the extensions of one path (max degree - 1).  host_done (pinned host
+// memory, may be NULL): host_done[0] receives step + 1 once the loop is over
+// (nothing left, or handed over to the depth-first kernel), host_done[1]
+// step + 1 when the step starts, so the host can stop launching steps and
+// keep only a few queued.
+hipError_t cc_launch_step(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
+                          OutDev out, int step, int forced_level, int max_children, int blocks,
+                          unsigned int *host_done, hipStream_t s);
+// The whole loop as one cooperative launch of `blocks` blocks (at most
+// cc_levels_max_blocks).  With `clock` (device memory, may be NULL) the
+// start of every step is recorded.
+hipError_t cc_launch_levels(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
+                            OutDev out, int forced_level, int max_children, int blocks,
+                            unsigned long long barrier_timeout, unsigned long long *clock,
+                            hipStream_t s);
 // Blocks of k_levels that fit on the device at once (0 if unknown).
 int cc_levels_max_blocks(int W, bool enumerate);
-hipError_t cc_launch_level(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier fin,
-                           Frontier fout, Stage sprev, Stage scur, OutDev out, int t,
-                           int forced_level, int blocks, unsigned int *host_done,
-                           hipStream_t s);
-// The handed-over paths are the frontier f0 or f1 that holds the paths of
-// the switch length; the workspace wk has memory of its own.  Cycle counts
+// The handed-over paths are in frontier f0 or f1 (CcCtl::root_buf); the
+// workspace wk has memory of its own.  Cycle counts
 // of block b go to hist_out[(b % CC_SHARDS) * hist_stride + k] (hist_out
 // NULL: not counted).
 hipError_t cc_launch_dfs(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f0,

@@ -453,6 +453,16 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
     ctl->count_sh[s][3] = sTrip > s ? (sTrip - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
     ctl->hist_sh[s][3] = sTri > s ? (sTri - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
   }
+  if (tid == 0) {
+    // step 0 expands the triplets (frontier buffer 1) and, enumerating,
+    // decodes the triangles (stage pair 0, slot 0)
+    StepState S{};
+    S.t = 3;
+    S.fbuf = 1;
+    S.spair = 0;
+    S.slen0 = ENUM ? 3 : 0;
+    ctl->ss[0] = S;
+  }
 }
 
 // Stage one for a batch: one block per graph, same pairs as k_triplets.
@@ -502,48 +512,56 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
   if (tid == 0 && sTri) atomicAdd(&bt.hist[(size_t)g * bt.hist_stride + 3], (unsigned long long)sTri);
 }
 
-// ------------------------------------------------------ breadth-first level
-// One level of Algorithm 3 over the frontier of paths with t vertices, plus
-// (enumerate mode) the decoding of the cycles with t vertices that the
-// previous level staged.
+// ------------------------------------------------------ breadth-first steps
+// Algorithm 3 over the frontier of open paths, one step at a time.  A step
+// expands the paths with t vertices either by one level (extensions with
+// t+1 vertices, closures = cycles with t+1 vertices) or, when its output
+// provably fits, by two: each lane follows its path's extensions one more
+// level itself, so the paths with t+1 vertices are counted but never
+// written, and closures with t+1 and t+2 vertices are both found.  A step
+// also decodes the cycles the previous step staged.
 //
 // Expansion: a block takes chunks of CC_BLOCK * CC_LEVEL_IPT consecutive
-// paths (one lane per path, CC_LEVEL_IPT rounds), counts the extensions and
-// closures of the chunk, and reserves room for all of them with one atomic
-// per chunk on its own shard's counters; each wavefront then owns a
-// contiguous sub-range and ranks its lanes inside it with ballot/mbcnt, so
-// the stores of a round land on consecutive slots.  Closures of paths with t
-// vertices are cycles with t+1 vertices: counted in hist_sh[.][t+1] and, when
-// enumerating, staged as vertex bitsets for the next level to decode.
+// paths (one lane per path, CC_LEVEL_IPT rounds), counts what they produce,
+// and reserves room for all of it with one atomic per counter per chunk on
+// its own shard; each wavefront then owns contiguous sub-ranges and ranks
+// its lanes inside them with ballot/mbcnt, so the stores of a round land on
+// consecutive slots.  Closures are counted in hist_sh[.][k] and, when
+// enumerating, staged as vertex bitsets for the next step to decode.
 //
-// Decoding: cycle g of length t (global order: shards in turn) goes to
-// output index cum_c[t-1] + g, vertices at cum_v[t-1] + g * t, so the output
+// Decoding: cycle g of length k (global order: shards in turn) goes to
+// output index cum_c[k-1] + g, vertices at cum_v[k-1] + g * k, so the output
 // is ordered by length.  Every lane decodes one cycle.
 //
-// The level loop runs either as one persistent kernel with a grid barrier
-// between levels (k_levels) or as one launch per level (k_level, Algorithm
-// 4's fixed relaunches without readback); both run level_body.
+// The steps run either as one launch each (k_step; Algorithm 4's fixed
+// relaunches, without readback: the step's t and buffers live in CcCtl) or
+// all in one cooperative launch with a grid barrier between them
+// (k_levels).  Both run step_body.
 
-// Shared memory of one block running levels.
+// Shared memory of one block running steps.
 template <int W, bool ENUM>
 struct LevelLds {
   unsigned long long N[CC_MAXN * W];              // label-space adjacency
   unsigned long long No[ENUM ? CC_MAXN * W : 1];  // original-id adjacency
   int Perm[ENUM ? CC_MAXN : 1];
   unsigned long long Pre[CC_SHARDS + 1];
-  unsigned long long PreH[ENUM ? CC_SHARDS + 1 : 1];
-  unsigned int WaveExt[CC_BLOCK / CC_WAVE];
-  unsigned int WaveClos[CC_BLOCK / CC_WAVE];
-  unsigned long long ExtBase, ClosBase;
-  unsigned long long Red[CC_BLOCK / CC_WAVE];
+  unsigned long long PreH0[ENUM ? CC_SHARDS + 1 : 1];
+  unsigned long long PreH1[ENUM ? CC_SHARDS + 1 : 1];
+  unsigned int WaveA[CC_BLOCK / CC_WAVE];   // paths written (extensions or grandchildren)
+  unsigned int WaveB[CC_BLOCK / CC_WAVE];   // closures one level down
+  unsigned int WaveC[CC_BLOCK / CC_WAVE];   // closures two levels down
+  unsigned int WaveD[CC_BLOCK / CC_WAVE];   // children (two-level steps: paths not written)
+  unsigned long long BaseA, BaseB, BaseC;
   unsigned long long Cum[2];
-  int Flags;
+  unsigned long long PrevFront;
+  int Flags;      // written by wave 0: the input frontier overflowed
+  int FlagsH[2];  // written by waves 1 and 2: a staged length overflowed
 };
 
-// level_body results
-#define CC_LEVEL_NEXT 0      // the level was expanded; continue with t + 1
+// step_body results
+#define CC_LEVEL_NEXT 0      // the step expanded its paths; continue
 #define CC_LEVEL_SWITCH 1    // handed over to the depth-first kernel
-#define CC_LEVEL_EMPTY 2     // no paths with t vertices: the loop is over
+#define CC_LEVEL_EMPTY 2     // no paths left: the loop is over
 
 template <int W, bool ENUM>
 __device__ void load_graph_lds(const GraphDev &g, LevelLds<W, ENUM> &L) {
@@ -554,186 +572,350 @@ __device__ void load_graph_lds(const GraphDev &g, LevelLds<W, ENUM> &L) {
   }
 }
 
-// One level for this block.  Every block of the grid reaches the same
-// result, computed from the same counters.  With lds_ready false the graph
-// is loaded into LDS here, together with the counters, so that a block
-// waits for one round of loads before it starts on its paths.
+// Field-wise selection (a select of whole structs would go through scratch).
+__device__ __forceinline__ Frontier pick(bool c, const Frontier &a, const Frontier &b) {
+  Frontier f;
+  f.X = c ? a.X : b.X;
+  f.S = c ? a.S : b.S;
+  f.vv = c ? a.vv : b.vv;
+  f.cap = c ? a.cap : b.cap;
+  f.cap_s = c ? a.cap_s : b.cap_s;
+  return f;
+}
+__device__ __forceinline__ Stage pick(bool c, const Stage &a, const Stage &b) {
+  Stage s;
+  s.C = c ? a.C : b.C;
+  s.cap = c ? a.cap : b.cap;
+  s.cap_s = c ? a.cap_s : b.cap_s;
+  return s;
+}
+
+// Per-wavefront ranks of four counts into block-level reservations: every
+// lane adds its counts, thread 0 reserves room for the block's totals on
+// its shard's counters, and each wavefront gets its base in each range.
 template <int W, bool ENUM>
-__device__ int level_body(const GraphDev &g, CcCtl *ctl, const Frontier &fin,
-                          const Frontier &fout, const Stage &sprev, const Stage &scur,
-                          const OutDev &out, int t, int forced_level, LevelLds<W, ENUM> &L,
-                          bool lds_ready) {
-  constexpr int IPT = CC_LEVEL_IPT;
+__device__ __forceinline__ void reserve(LevelLds<W, ENUM> &L, unsigned a, unsigned b, unsigned c,
+                                        unsigned d, unsigned long long *ctrA,
+                                        unsigned long long *ctrB, unsigned long long *ctrC,
+                                        unsigned long long *ctrD, unsigned long long &baseA,
+                                        unsigned long long &baseB, unsigned long long &baseC,
+                                        unsigned &wa, unsigned &wb, unsigned &wc) {
   constexpr int NW = CC_BLOCK / CC_WAVE;
+  const int wave = threadIdx.x / CC_WAVE;
+  wa = wave_sum_u32(a);
+  wb = wave_sum_u32(b);
+  wc = wave_sum_u32(c);
+  const unsigned wd = wave_sum_u32(d);
+  if (lane_id() == 0) {
+    L.WaveA[wave] = wa;
+    L.WaveB[wave] = wb;
+    L.WaveC[wave] = wc;
+    L.WaveD[wave] = wd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long ta = 0, tb = 0, tc = 0, td = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      ta += L.WaveA[w];
+      tb += L.WaveB[w];
+      tc += L.WaveC[w];
+      td += L.WaveD[w];
+    }
+    L.BaseA = (ta && ctrA) ? atomicAdd(ctrA, ta) : 0ull;
+    L.BaseB = (tb && ctrB) ? atomicAdd(ctrB, tb) : 0ull;
+    L.BaseC = (tc && ctrC) ? atomicAdd(ctrC, tc) : 0ull;
+    if (td && ctrD) atomicAdd(ctrD, td);
+  }
+  __syncthreads();
+  baseA = L.BaseA;
+  baseB = L.BaseB;
+  baseC = L.BaseC;
+  for (int w = 0; w < wave; ++w) {
+    baseA += L.WaveA[w];
+    baseB += L.WaveB[w];
+    baseC += L.WaveC[w];
+  }
+}
+
+// Decodes staged cycle gi of length k from stage st (shard prefix pre) to
+// output index cb + gi, vertices at vb + gi * k.
+template <int W, bool ENUM>
+__device__ __forceinline__ void decode_one(const LevelLds<W, ENUM> &L, const Stage &st,
+                                           const unsigned long long *pre, unsigned long long gi,
+                                           int k, long long cb, long long vb, const OutDev &out) {
+  const int s = shard_of(pre, gi);
+  const unsigned long long e = (unsigned long long)s * st.cap_s + (gi - pre[s]);
+  Bits<W> C;
+#pragma unroll
+  for (int w = 0; w < W; ++w) C.w[w] = st.C[w * st.cap + e];
+  const long long cyc = cb + (long long)gi;
+  const long long pos = vb + (long long)gi * k;
+  if (cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap) {
+    write_cycle<W>(L.No, C, k, out.verts + pos);
+    out.offs[cyc] = pos;
+  }
+}
+
+// The state of a step, read with vector loads at agent scope: the previous
+// step's block 0 wrote it, possibly within the same launch, and a plain load
+// of a uniform address would go through the scalar cache, which no fence here
+// invalidates.
+__device__ __forceinline__ StepState load_state(CcCtl *ctl, int i) {
+  StepState S;
+  S.t = ld_relaxed(&ctl->ss[i].t);
+  S.fbuf = ld_relaxed(&ctl->ss[i].fbuf);
+  S.spair = ld_relaxed(&ctl->ss[i].spair);
+  S.slen0 = ld_relaxed(&ctl->ss[i].slen0);
+  S.slen1 = ld_relaxed(&ctl->ss[i].slen1);
+  S.prev_two = ld_relaxed(&ctl->ss[i].prev_two);
+  S.done = ld_relaxed(&ctl->ss[i].done);
+  S.pad = 0;
+  return S;
+}
+
+// One step for this block.  Every block of the grid reads the same state
+// and counters and so reaches the same result.  With lds_ready false the
+// graph is loaded into LDS here, together with the counters.
+template <int W, bool ENUM>
+__device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
+                         int step, int forced_level, int maxc, LevelLds<W, ENUM> &L,
+                         bool lds_ready) {
+  constexpr int IPT = CC_LEVEL_IPT;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / CC_WAVE;
+  const StepState S = load_state(ctl, step & 1);
+  if (S.done) return CC_LEVEL_EMPTY;
+  const int t = S.t;
+  const int n = g.n;
+  const Frontier fin = pick(S.fbuf != 0, B.f[1], B.f[0]);
+  const Frontier fout = pick(S.fbuf != 0, B.f[0], B.f[1]);
+  const int p = S.spair, q = 1 - S.spair;  // stage pairs: decoded here, written here
+  const Stage sd0 = pick(p != 0, B.st[2], B.st[0]), sd1 = pick(p != 0, B.st[3], B.st[1]);
+  const Stage sw0 = pick(q != 0, B.st[2], B.st[0]), sw1 = pick(q != 0, B.st[3], B.st[1]);
   if (wave == 0) {
     const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][t]);
     shard_prefix(c, L.Pre);
-    const bool ovf = c > fin.cap_s;
-    bool hovf = false;
-    if (ENUM) {
-      const unsigned long long h = ld_relaxed(&ctl->hist_sh[lane][t]);
-      shard_prefix(h, L.PreH);
-      hovf = h > sprev.cap_s;
-    }
-    const unsigned long long mo = wave_ballot(ovf), mh = wave_ballot(hovf);
+    const unsigned long long mo = wave_ballot(c > fin.cap_s);
     if (lane == 0) {
-      L.Flags = (mo ? 1 : 0) | (mh ? 2 : 0);
-      if (ENUM) {
-        L.Cum[0] = ld_relaxed(&ctl->cum_c[t - 1]);
-        L.Cum[1] = ld_relaxed(&ctl->cum_v[t - 1]);
+      L.Flags = mo ? 1 : 0;
+      if (ENUM && S.slen0) {
+        L.Cum[0] = ld_relaxed(&ctl->cum_c[S.slen0 - 1]);
+        L.Cum[1] = ld_relaxed(&ctl->cum_v[S.slen0 - 1]);
       }
     }
+  } else if (wave == 1 || wave == 2) {
+    // each of these waves writes its own flag every step
+    const int k = wave == 1 ? S.slen0 : S.slen1;
+    bool ovf = false;
+    if (ENUM && k) {
+      const unsigned long long h = ld_relaxed(&ctl->hist_sh[lane][k]);
+      shard_prefix(h, wave == 1 ? L.PreH0 : L.PreH1);
+      ovf = wave_ballot(h > (wave == 1 ? sd0.cap_s : sd1.cap_s)) != 0ull;
+    }
+    if (lane == 0) L.FlagsH[wave - 1] = ovf ? 2 : 0;
+  } else if (wave == 3 && S.prev_two) {
+    // the previous step counted its children (paths with t-1 vertices)
+    const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][t - 1]);
+    const unsigned long long tot = wave_sum_u64(c);
+    if (lane == 0) L.PrevFront = tot;
   }
   if (!lds_ready) load_graph_lds<W, ENUM>(g, L);
   __syncthreads();
-  const int flags = L.Flags;
+  const int flags = L.Flags | L.FlagsH[0] | L.FlagsH[1];
   const unsigned long long cnt = L.Pre[CC_SHARDS];
+  if (blockIdx.x == 0 && tid == 0) {
+    if (step < CC_HSLOTS) ctl->step_level[step] = t;
+    if (S.prev_two) ctl->front[t - 1] = L.PrevFront;
+  }
 
-  // ---- decode the cycles with t vertices staged by the previous level
-  if (ENUM && !(flags & 2)) {
-    const unsigned long long htot = L.PreH[CC_SHARDS];
-    const long long cb = (long long)L.Cum[0], vb = (long long)L.Cum[1];
-    for (unsigned long long gi = (unsigned long long)blockIdx.x * CC_BLOCK + tid; gi < htot;
+  // ---- decode the cycles the previous step staged (lengths slen0, slen1)
+  if (ENUM && S.slen0 && !(flags & 2)) {
+    const int k0 = S.slen0, k1 = S.slen1;
+    const unsigned long long h0 = L.PreH0[CC_SHARDS], h1 = k1 ? L.PreH1[CC_SHARDS] : 0ull;
+    const long long cb0 = (long long)L.Cum[0], vb0 = (long long)L.Cum[1];
+    const long long cb1 = cb0 + (long long)h0, vb1 = vb0 + (long long)h0 * k0;
+    for (unsigned long long gi = (unsigned long long)blockIdx.x * CC_BLOCK + tid; gi < h0 + h1;
          gi += (unsigned long long)gridDim.x * CC_BLOCK) {
-      const int s = shard_of(L.PreH, gi);
-      const unsigned long long e = (unsigned long long)s * sprev.cap_s + (gi - L.PreH[s]);
-      Bits<W> C;
-#pragma unroll
-      for (int w = 0; w < W; ++w) C.w[w] = sprev.C[w * sprev.cap + e];
-      const long long cyc = cb + (long long)gi;
-      const long long pos = vb + (long long)gi * t;
-      if (cyc < out.cyc_cap && pos + t <= out.verts_cap) {
-        write_cycle<W>(L.No, C, t, out.verts + pos);
-        out.offs[cyc] = pos;
-      }
+      if (gi < h0) decode_one<W, ENUM>(L, sd0, L.PreH0, gi, k0, cb0, vb0, out);
+      else decode_one<W, ENUM>(L, sd1, L.PreH1, gi - h0, k1, cb1, vb1, out);
     }
     if (blockIdx.x == 0 && tid == 0) {
-      ctl->cum_c[t] = (unsigned long long)cb + htot;
-      ctl->cum_v[t] = (unsigned long long)vb + htot * (unsigned long long)t;
+      ctl->cum_c[k0] = (unsigned long long)cb1;
+      ctl->cum_v[k0] = (unsigned long long)vb1;
+      if (k1) {
+        ctl->cum_c[k1] = (unsigned long long)(cb1 + (long long)h1);
+        ctl->cum_v[k1] = (unsigned long long)(vb1 + (long long)h1 * k1);
+      }
     }
   }
 
   // ---- hand over to the depth-first kernel when needed
-  int sw_level = 0, sw_skip = 0, sw_max = 0;
-  if (flags & 2) {
-    // The previous level staged more cycles than fit: its paths are handed
-    // over again and everything from them on is recounted.
+  int sw_level = 0, sw_skip = 0, sw_max = 0, sw_buf = 0;
+  if (flags & 3) {
+    // Only a one-level step can overflow (a two-level step is taken only
+    // when its output fits), so the paths with t-1 vertices it expanded are
+    // still intact in the other buffer.
+    if (S.prev_two) {
+      if (blockIdx.x == 0 && tid == 0) dfs_corrupt(ctl, CC_DIAG_PATH, (unsigned)t);
+      return CC_LEVEL_EMPTY;
+    }
     sw_level = t - 1;
-    sw_skip = CC_SKIP_FRONT;
-    sw_max = t - 1;
-  } else if (flags & 1) {
-    // The previous level produced more paths than fit: hand its (intact)
-    // input frontier over; that level's closures and path count are
-    // already recorded.
-    sw_level = t - 1;
-    sw_skip = CC_SKIP_FRONT | CC_SKIP_CLOSE;
-    sw_max = t;
+    sw_buf = 1 - S.fbuf;
+    if (flags & 2) {
+      // The previous step staged more cycles than fit: its paths are handed
+      // over again and everything from them on is recounted.
+      sw_skip = CC_SKIP_FRONT;
+      sw_max = t - 1;
+    } else {
+      // The previous step produced more paths than fit: its closures and
+      // path count are already recorded.
+      sw_skip = CC_SKIP_FRONT | CC_SKIP_CLOSE;
+      sw_max = t;
+    }
   } else if (t == forced_level) {
     sw_level = t;
+    sw_buf = S.fbuf;
     sw_skip = 0;
     sw_max = t;
   }
+  StepState N = S;
+  N.done = 1;
   if (sw_level) {
     if (blockIdx.x == 0 && tid == 0) {
       ctl->skip = sw_skip;
       ctl->switch_level = sw_level;
       ctl->bfs_max_len = sw_max;
+      ctl->root_buf = sw_buf;
+      ctl->ss[(step + 1) & 1] = N;
       __threadfence();
       st_release(&ctl->mode, 1);
     }
     return CC_LEVEL_SWITCH;
   }
-  if (cnt == 0) return CC_LEVEL_EMPTY;
+  if (cnt == 0) {
+    if (blockIdx.x == 0 && tid == 0) ctl->ss[(step + 1) & 1] = N;
+    return CC_LEVEL_EMPTY;
+  }
+
+  // ---- one level or two
   const unsigned long long chunk = (unsigned long long)CC_BLOCK * IPT;
-  // Blocks without a chunk have nothing more to do at this level.
-  if ((unsigned long long)blockIdx.x * chunk >= cnt) return CC_LEVEL_NEXT;
+  const unsigned long long grid = gridDim.x;
+  const unsigned long long per_shard =
+      (cnt + grid * chunk - 1) / (grid * chunk) * chunk * ((grid + CC_SHARDS - 1) / CC_SHARDS);
+  const unsigned long long mc = (unsigned long long)(maxc > 1 ? maxc : 1);
+  const bool two = t + 2 <= n && t + 1 != forced_level && per_shard * mc * mc <= fout.cap_s &&
+                   (!ENUM || per_shard * mc * mc <= sw1.cap_s);
   if (blockIdx.x == 0 && tid == 0) {
+    N.t = t + (two ? 2 : 1);
+    N.fbuf = 1 - S.fbuf;
+    N.spair = q;
+    N.slen0 = ENUM ? t + 1 : 0;
+    N.slen1 = (ENUM && two) ? t + 2 : 0;
+    N.prev_two = two ? 1 : 0;
+    N.done = 0;
+    ctl->ss[(step + 1) & 1] = N;
     ctl->front[t] = cnt;
     atomicMax(&ctl->peak, cnt);
   }
-  const int k = t + 1;
+  // Blocks without a chunk have nothing more to do in this step.
+  if ((unsigned long long)blockIdx.x * chunk >= cnt) return CC_LEVEL_NEXT;
   const int osh = blockIdx.x % CC_SHARDS;  // this block's output shard
-  unsigned long long acc = 0;
+  unsigned long long acc1 = 0, acc2 = 0;   // closures (count mode)
   for (unsigned long long c0 = (unsigned long long)blockIdx.x * chunk; c0 < cnt;
-       c0 += (unsigned long long)gridDim.x * chunk) {
-    Bits<W> Xn[IPT], Sv[IPT], clos[IPT], ext[IPT];
-    int v1[IPT];
-    unsigned my_ext = 0, my_clos = 0;
+       c0 += grid * chunk) {
+    Bits<W> X[IPT], Sv[IPT];
+    int v1[IPT], vt[IPT];
+    bool valid[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const unsigned long long i = c0 + (unsigned long long)j * CC_BLOCK + tid;
-      const bool valid = i < cnt;
-      Bits<W> X = bzero<W>();
+      valid[j] = i < cnt;
+      X[j] = bzero<W>();
       Sv[j] = bzero<W>();
-      int a = 0, b = 0;
-      if (valid) {
+      v1[j] = 0;
+      vt[j] = 0;
+      if (valid[j]) {
         const int s = shard_of(L.Pre, i);
         const unsigned long long e = (unsigned long long)s * fin.cap_s + (i - L.Pre[s]);
 #pragma unroll
-        for (int w = 0; w < W; ++w) X.w[w] = fin.X[w * fin.cap + e];
+        for (int w = 0; w < W; ++w) X[j].w[w] = fin.X[w * fin.cap + e];
         if (ENUM) {
 #pragma unroll
           for (int w = 0; w < W; ++w) Sv[j].w[w] = fin.S[w * fin.cap + e];
         }
         const unsigned vv = fin.vv[e];
-        a = vv & 0xffu;
-        b = vv >> 8;
+        v1[j] = vv & 0xffu;
+        vt[j] = vv >> 8;
       }
-      const Bits<W> nvt = row<W>(L.N, b);
-      const Bits<W> nv1 = row<W>(L.N, a);
-      const Bits<W> cand = bandnot(nvt, X);
-      clos[j] = valid ? band(cand, nv1) : bzero<W>();
-      ext[j] = valid ? bandnot(cand, nv1) : bzero<W>();
-      Xn[j] = bor(X, nvt);
-      v1[j] = a;
-      my_ext += (unsigned)bpop(ext[j]);
-      my_clos += (unsigned)bpop(clos[j]);
     }
-    if (!ENUM) acc += my_clos;
-    const unsigned we = wave_sum_u32(my_ext);
-    const unsigned wc = ENUM ? wave_sum_u32(my_clos) : 0u;
-    if (lane == 0) {
-      L.WaveExt[wave] = we;
-      L.WaveClos[wave] = wc;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      unsigned te = 0, tc = 0;
+    // counts: a = paths written, b = closures one level down, c = closures
+    // two levels down, d = children of a two-level step
+    unsigned ca = 0, cb = 0, cc = 0, cd = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        te += L.WaveExt[w];
-        tc += L.WaveClos[w];
+    for (int j = 0; j < IPT; ++j) {
+      if (!valid[j]) continue;
+      const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+      const Bits<W> cand = bandnot(nvt, X[j]);
+      cb += (unsigned)bpop(band(cand, nv1));
+      Bits<W> ext = bandnot(cand, nv1);
+      if (!two) {
+        ca += (unsigned)bpop(ext);
+      } else {
+        cd += (unsigned)bpop(ext);
+        const Bits<W> Xc = bor(X[j], nvt);
+        while (bany(ext)) {
+          const Bits<W> cand2 = bandnot(row<W>(L.N, bpop_lowest(ext)), Xc);
+          cc += (unsigned)bpop(band(cand2, nv1));
+          ca += (unsigned)bpop(bandnot(cand2, nv1));
+        }
       }
-      L.ExtBase = te ? atomicAdd(&ctl->count_sh[osh][k], (unsigned long long)te) : 0ull;
-      L.ClosBase = (ENUM && tc) ? atomicAdd(&ctl->hist_sh[osh][k], (unsigned long long)tc) : 0ull;
     }
-    __syncthreads();
-    unsigned long long ebase = L.ExtBase, cbase = L.ClosBase;
-    for (int w = 0; w < wave; ++w) {
-      ebase += L.WaveExt[w];
-      cbase += L.WaveClos[w];
+    const int kA = two ? t + 2 : t + 1;  // length of the paths written
+    unsigned long long baseA, baseB, baseC;
+    unsigned wa, wb, wc;
+    reserve<W, ENUM>(L, ca, cb, cc, cd, &ctl->count_sh[osh][kA],
+                     ENUM ? &ctl->hist_sh[osh][t + 1] : nullptr,
+                     (ENUM && two) ? &ctl->hist_sh[osh][t + 2] : nullptr,
+                     two ? &ctl->count_sh[osh][t + 1] : nullptr, baseA, baseB, baseC, wa, wb, wc);
+    if (!ENUM) {
+      acc1 += cb;
+      acc2 += cc;
     }
-    if (we) {
+    // ---- write the paths (extensions, or grandchildren)
+    if (wa) {
       unsigned long long off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        Bits<W> e = ext[j];
+        const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+        const Bits<W> Xc = bor(X[j], nvt);
+        Bits<W> ext = valid[j] ? bandnot(bandnot(nvt, X[j]), nv1) : bzero<W>();
+        // lane iterator: current child c and its remaining extensions cur
+        Bits<W> cur = two ? bzero<W>() : ext, Xg = Xc;
+        int c = -1;
         while (true) {
-          const bool has = bany(e);
+          if (two) {
+            while (!bany(cur) && bany(ext)) {
+              c = bpop_lowest(ext);
+              const Bits<W> nc = row<W>(L.N, c);
+              cur = bandnot(bandnot(nc, Xc), nv1);
+              Xg = bor(Xc, nc);
+            }
+          }
+          const bool has = bany(cur);
           const unsigned long long mask = wave_ballot(has);
           if (!mask) break;
           if (has) {
-            const int v = bpop_lowest(e);
-            const unsigned long long slot = ebase + off + lanes_below(mask);
+            const int v = bpop_lowest(cur);
+            const unsigned long long slot = baseA + off + lanes_below(mask);
             if (slot < fout.cap_s) {
               const unsigned long long o = (unsigned long long)osh * fout.cap_s + slot;
 #pragma unroll
-              for (int w = 0; w < W; ++w) fout.X[w * fout.cap + o] = Xn[j].w[w];
+              for (int w = 0; w < W; ++w) fout.X[w * fout.cap + o] = Xg.w[w];
               if (ENUM) {
-                const Bits<W> Sn = bor(Sv[j], bsingle<W>(L.Perm[v]));
+                Bits<W> Sn = bor(Sv[j], bsingle<W>(L.Perm[v]));
+                if (two) Sn = bor(Sn, bsingle<W>(L.Perm[c]));
 #pragma unroll
                 for (int w = 0; w < W; ++w) fout.S[w * fout.cap + o] = Sn.w[w];
               }
@@ -744,23 +926,57 @@ __device__ int level_body(const GraphDev &g, CcCtl *ctl, const Frontier &fin,
         }
       }
     }
+    // ---- stage the closures (enumerate mode)
+    if (ENUM && wb) {
+      unsigned long long off = 0;
+#pragma unroll
+      for (int j = 0; j < IPT; ++j) {
+        const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+        Bits<W> cl = valid[j] ? band(bandnot(nvt, X[j]), nv1) : bzero<W>();
+        while (true) {
+          const bool has = bany(cl);
+          const unsigned long long mask = wave_ballot(has);
+          if (!mask) break;
+          if (has) {
+            const int v = bpop_lowest(cl);
+            const unsigned long long slot = baseB + off + lanes_below(mask);
+            if (slot < sw0.cap_s) {
+              const unsigned long long o = (unsigned long long)osh * sw0.cap_s + slot;
+              const Bits<W> C = bor(Sv[j], bsingle<W>(L.Perm[v]));
+#pragma unroll
+              for (int w = 0; w < W; ++w) sw0.C[w * sw0.cap + o] = C.w[w];
+            }
+          }
+          off += __popcll(mask);
+        }
+      }
+    }
     if (ENUM && wc) {
       unsigned long long off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        Bits<W> c = clos[j];
+        const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+        const Bits<W> Xc = bor(X[j], nvt);
+        Bits<W> ext = valid[j] ? bandnot(bandnot(nvt, X[j]), nv1) : bzero<W>();
+        Bits<W> cur = bzero<W>();
+        int c = -1;
         while (true) {
-          const bool has = bany(c);
+          while (!bany(cur) && bany(ext)) {
+            c = bpop_lowest(ext);
+            cur = band(bandnot(row<W>(L.N, c), Xc), nv1);
+          }
+          const bool has = bany(cur);
           const unsigned long long mask = wave_ballot(has);
           if (!mask) break;
           if (has) {
-            const int v = bpop_lowest(c);
-            const unsigned long long slot = cbase + off + lanes_below(mask);
-            if (slot < scur.cap_s) {
-              const unsigned long long o = (unsigned long long)osh * scur.cap_s + slot;
-              const Bits<W> C = bor(Sv[j], bsingle<W>(L.Perm[v]));
+            const int v = bpop_lowest(cur);
+            const unsigned long long slot = baseC + off + lanes_below(mask);
+            if (slot < sw1.cap_s) {
+              const unsigned long long o = (unsigned long long)osh * sw1.cap_s + slot;
+              const Bits<W> C =
+                  bor(bor(Sv[j], bsingle<W>(L.Perm[c])), bsingle<W>(L.Perm[v]));
 #pragma unroll
-              for (int w = 0; w < W; ++w) scur.C[w * scur.cap + o] = C.w[w];
+              for (int w = 0; w < W; ++w) sw1.C[w * sw1.cap + o] = C.w[w];
             }
           }
           off += __popcll(mask);
@@ -770,38 +986,42 @@ __device__ int level_body(const GraphDev &g, CcCtl *ctl, const Frontier &fin,
     __syncthreads();  // the per-wavefront totals are rewritten by the next chunk
   }
   if (!ENUM) {
-    acc = wave_sum_u64(acc);
-    if (lane == 0) L.Red[wave] = acc;
+    acc1 = wave_sum_u64(acc1);
+    acc2 = wave_sum_u64(acc2);
+    if (lane == 0) {
+      L.WaveA[wave] = (unsigned)acc1;  // per-wavefront closures fit 32 bits per step
+      L.WaveB[wave] = (unsigned)acc2;
+    }
     __syncthreads();
     if (tid == 0) {
-      unsigned long long sum = 0;
-      for (int i = 0; i < NW; ++i) sum += L.Red[i];
-      if (sum) atomicAdd(&ctl->hist_sh[osh][k], sum);
+      unsigned long long s1 = 0, s2 = 0;
+      for (int w = 0; w < CC_BLOCK / CC_WAVE; ++w) {
+        s1 += L.WaveA[w];
+        s2 += L.WaveB[w];
+      }
+      if (s1) atomicAdd(&ctl->hist_sh[osh][t + 1], s1);
+      if (s2) atomicAdd(&ctl->hist_sh[osh][t + 2], s2);
     }
   }
   return CC_LEVEL_NEXT;
 }
 
-// One launch per level.  `host_done` (pinned host memory, may be NULL)
-// receives the first level that found nothing to do, so the host can stop
-// launching levels.
+// One launch per step.  host_done (pinned host memory, may be NULL):
+// host_done[1] = step + 1 when the step starts, host_done[0] = step + 1 when
+// the loop is over, so the host stops launching steps and keeps few queued.
 template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_BLOCK) void k_level(GraphDev g, CcCtl *ctl, Frontier fin,
-                                                    Frontier fout, Stage sprev, Stage scur,
-                                                    OutDev out, int t, int forced_level,
-                                                    unsigned int *host_done) {
+__global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, LevelBufs B,
+                                                   OutDev out, int step, int forced_level,
+                                                   int maxc, unsigned int *host_done) {
   __shared__ LevelLds<W, ENUM> L;
-  // host_done[1]: the last level that started, so the host keeps only a few
-  // levels queued ahead of the device
-  if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done + 1, (unsigned)t);
+  if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done + 1, (unsigned)step + 1u);
   if (ld_relaxed(&ctl->mode) != 0) {
-    if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done, (unsigned)t);
+    if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done, (unsigned)step + 1u);
     return;
   }
-  const int r = level_body<W, ENUM>(g, ctl, fin, fout, sprev, scur, out, t, forced_level, L,
-                                    false);
+  const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, L, false);
   if (r != CC_LEVEL_NEXT && host_done && blockIdx.x == 0 && threadIdx.x == 0)
-    st_system(host_done, (unsigned)t);
+    st_system(host_done, (unsigned)step + 1u);
 }
 
 // Grid-wide barrier of a cooperative launch (every block resident).  Blocks
@@ -839,24 +1059,6 @@ __device__ void grid_barrier(CcCtl *ctl, unsigned long long timeout) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-}
-
-// Field-wise selection (a select of whole structs would go through scratch).
-__device__ __forceinline__ Frontier pick(bool c, const Frontier &a, const Frontier &b) {
-  Frontier f;
-  f.X = c ? a.X : b.X;
-  f.S = c ? a.S : b.S;
-  f.vv = c ? a.vv : b.vv;
-  f.cap = c ? a.cap : b.cap;
-  f.cap_s = c ? a.cap_s : b.cap_s;
-  return f;
-}
-__device__ __forceinline__ Stage pick(bool c, const Stage &a, const Stage &b) {
-  Stage s;
-  s.C = c ? a.C : b.C;
-  s.cap = c ? a.cap : b.cap;
-  s.cap_s = c ? a.cap_s : b.cap_s;
-  return s;
 }
 
 // The XCD (accelerator complex die, with its own L2) this wavefront runs on.
@@ -910,16 +1112,15 @@ __device__ void xcd_barrier(CcCtl *ctl, unsigned xcc, unsigned nx, unsigned long
   __syncthreads();
 }
 
-// The whole level loop in one cooperative launch: the graph is loaded into
-// LDS once, levels t = 3.. run back to back with a grid barrier between
-// them, and the loop ends on the device when a level finds no paths or
-// hands over to the depth-first kernel.  With `clock` (may be NULL), block 0
-// records the wall clock at the start of every level and at the end
-// (clock[t] .. clock[t+1] is level t).
+// The whole loop in one cooperative launch: the graph is loaded into LDS
+// once, steps run back to back with a grid barrier between them, and the
+// loop ends on the device when a step finds no paths or hands over to the
+// depth-first kernel.  With `clock` (may be NULL), block 0 records the wall
+// clock at the start of every step and at the end (clock[s] .. clock[s+1]
+// is step s).
 template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Frontier f0,
-                                                     Frontier f1, Stage st0, Stage st1,
-                                                     OutDev out, int forced_level,
+__global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, LevelBufs B,
+                                                     OutDev out, int forced_level, int maxc,
                                                      unsigned long long barrier_timeout,
                                                      unsigned long long *clock) {
   __shared__ LevelLds<W, ENUM> L;
@@ -936,22 +1137,22 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Fro
   }
   __syncthreads();
   const unsigned nx = sNx;
-  int t = 3, last = 2;  // last: the last level that ran
-  for (; t <= g.n; ++t) {
-    if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[t] = wall_clock64();
-    const bool odd = (t & 1) != 0;
-    const Frontier fin = pick(odd, f1, f0), fout = pick(odd, f0, f1);
-    const Stage sprev = pick(odd, st0, st1), scur = pick(odd, st1, st0);
-    const int r = level_body<W, ENUM>(g, ctl, fin, fout, sprev, scur, out, t, forced_level, L,
-                                      true);
-    last = t;
-    if (r != CC_LEVEL_NEXT) break;
+  int step = 0;
+  // at most n - 2 steps (each expands at least one level); the clock array
+  // has room for them
+  for (; step < g.n - 2; ++step) {
+    if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[step] = wall_clock64();
+    const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, L, true);
+    if (r != CC_LEVEL_NEXT) {
+      ++step;
+      break;
+    }
     xcd_barrier(ctl, xcc, nx, barrier_timeout);
     if (ld_relaxed(&ctl->status) & CC_DEV_BARRIER_TIMEOUT) break;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (clock) clock[last + 1] = wall_clock64();  // last <= n <= CC_MAXN, so last + 1 < CC_HSLOTS
-    ctl->levels_run = last - 2;
+    if (clock) clock[step] = wall_clock64();  // step <= n - 2 < CC_HSLOTS
+    ctl->levels_run = step;
   }
 }
 
@@ -1002,7 +1203,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   if (!BATCH && ld_relaxed(&ctl->mode) == 0) return;
   const int L = BATCH ? 3 : ctl->switch_level;
   const int skipbits = BATCH ? 0 : ctl->skip;
-  const Frontier roots = (L & 1) ? f1 : f0;
+  const Frontier roots = (!BATCH && ctl->root_buf) ? f1 : f0;
   const int n = g.n;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -1620,11 +1821,12 @@ hipError_t cc_launch_triplets(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f
   return hipGetLastError();
 }
 
-hipError_t cc_launch_levels(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
-                            Stage st0, Stage st1, OutDev out, int forced_level, int blocks,
+hipError_t cc_launch_levels(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
+                            OutDev out, int forced_level, int max_children, int blocks,
                             unsigned long long barrier_timeout, unsigned long long *clock,
                             hipStream_t s) {
-  void *args[] = {&g, &ctl, &f0, &f1, &st0, &st1, &out, &forced_level, &barrier_timeout, &clock};
+  LevelBufs bb = b;
+  void *args[] = {&g, &ctl, &bb, &out, &forced_level, &max_children, &barrier_timeout, &clock};
   const void *fn = W == 1 ? (en ? (const void *)k_levels<1, true> : (const void *)k_levels<1, false>)
                           : (en ? (const void *)k_levels<2, true> : (const void *)k_levels<2, false>);
   return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(CC_BLOCK), args, 0, s);
@@ -1641,16 +1843,16 @@ int cc_levels_max_blocks(int W, bool en) {
   return per_cu * cus;
 }
 
-hipError_t cc_launch_level(int W, bool en, GraphDev g, CcCtl *ctl, Frontier fin, Frontier fout,
-                           Stage sprev, Stage scur, OutDev out, int t, int forced_level,
-                           int blocks, unsigned int *host_done, hipStream_t s) {
+hipError_t cc_launch_step(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
+                          OutDev out, int step, int forced_level, int max_children, int blocks,
+                          unsigned int *host_done, hipStream_t s) {
   dim3 gr(blocks), bl(CC_BLOCK);
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_level<1, true>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
-    else hipLaunchKernelGGL((k_level<1, false>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
+    if (en) hipLaunchKernelGGL((k_step<1, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
+    else hipLaunchKernelGGL((k_step<1, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
   } else {
-    if (en) hipLaunchKernelGGL((k_level<2, true>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
-    else hipLaunchKernelGGL((k_level<2, false>), gr, bl, 0, s, g, ctl, fin, fout, sprev, scur, out, t, forced_level, host_done);
+    if (en) hipLaunchKernelGGL((k_step<2, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
+    else hipLaunchKernelGGL((k_step<2, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
   }
   return hipGetLastError();
 }

@@ -244,8 +244,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   const int64_t budget =
       g->opt.frontier_budget_bytes > 0 ? g->opt.frontier_budget_bytes : kDefaultBudget;
   // bytes per unit of capacity: a path in each frontier buffer, plus a
-  // staged cycle in each staging buffer
-  const size_t per_unit = 2 * ((size_t)W * 8 * (en ? 2 : 1) + 2) + (en ? 2 * (size_t)W * 8 : 0);
+  // staged cycle in each of the four staging buffers
+  const size_t per_unit = 2 * ((size_t)W * 8 * (en ? 2 : 1) + 2) + (en ? 4 * (size_t)W * 8 : 0);
   unsigned long long cap_s = (unsigned long long)budget / per_unit / CC_SHARDS;
   // stage one writes every initial triplet (at most C(n,3)) round-robin
   const unsigned long long min_cap_s = (unsigned long long)choose3(n) / CC_SHARDS + CC_CHUNK;
@@ -257,16 +257,17 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       (size_t)std::min<int64_t>(std::max<int64_t>(budget / 2, (int64_t)64 << 20), (int64_t)2 << 30),
       1 << 16);
   char *arena = nullptr;
-  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes + 2 * stage_bytes + dfs_bytes, s));
-  char *dfs_region = arena + 2 * buf_bytes + 2 * stage_bytes;
-  Frontier f[2] = {carve_frontier(arena, cap_s, W, en),
-                   carve_frontier(arena + buf_bytes, cap_s, W, en)};
-  Stage st[2] = {};
+  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes + 4 * stage_bytes + dfs_bytes, s));
+  char *dfs_region = arena + 2 * buf_bytes + 4 * stage_bytes;
+  LevelBufs lb{};
+  lb.f[0] = carve_frontier(arena, cap_s, W, en);
+  lb.f[1] = carve_frontier(arena + buf_bytes, cap_s, W, en);
+  Frontier *f = lb.f;
   if (en) {
-    for (int i = 0; i < 2; ++i) {
-      st[i].C = (unsigned long long *)(arena + 2 * buf_bytes + i * stage_bytes);
-      st[i].cap = cap;
-      st[i].cap_s = cap_s;
+    for (int i = 0; i < 4; ++i) {
+      lb.st[i].C = (unsigned long long *)(arena + 2 * buf_bytes + i * stage_bytes);
+      lb.st[i].cap = cap;
+      lb.st[i].cap_s = cap_s;
     }
   }
 
@@ -313,18 +314,20 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   chk(hipEventRecord(g->ev0, s));
   chk(cc_launch_zero(ctl, sizeof(CcCtl), s));
   mark(0);
-  chk(cc_launch_triplets(W, en, gd, ctl, f[1], st[0], s));
+  chk(cc_launch_triplets(W, en, gd, ctl, f[1], lb.st[0], s));
   mark(1);
-  // Level t expands the paths with t vertices and (enumerate mode) decodes
-  // the cycles with t vertices; level n only decodes.
+  // Each step expands the paths of one length by one level, or by two when
+  // its output provably fits, and (enumerate mode) decodes the cycles the
+  // previous step staged.  There are at most n - 2 steps.
   //
-  // Default: one launch per level.  The level kernels report the first
-  // level with nothing to do through a pinned host word and launching stops
-  // there; the flag may arrive late, and extra launches are no-ops.  With
-  // CC_LEVEL_PERSISTENT, one cooperative launch runs every level with a grid
-  // barrier in between and stops on the device; on MI355X its barriers (an
-  // L2 write-back and invalidate per block) cost more than the launches they
-  // replace, so it is not the default.
+  // Default: one launch per step.  The step kernels report the end of the
+  // loop through a pinned host word and launching stops there; the host
+  // keeps at most kLevelsAhead launches queued beyond the last step the
+  // device has started (waiting at most kAheadWaitUs for it), so it sees
+  // the end a few steps after the frontier empties.  With
+  // CC_LEVEL_PERSISTENT, one cooperative launch runs every step with a grid
+  // barrier in between and stops on the device; on MI355X its barriers cost
+  // about as much as the launches they replace, so it is not the default.
   const int coop_max = g->dev.coop && (g->opt.flags & CC_LEVEL_PERSISTENT)
                            ? cc_levels_max_blocks(W, en)
                            : 0;
@@ -333,30 +336,26 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     const int want = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
     const int blocks = std::max(1, std::min(want, coop_max));
     mark(2);
-    chk(cc_launch_levels(W, en, gd, ctl, f[0], f[1], st[0], st[1], ro.out, forced, blocks,
+    chk(cc_launch_levels(W, en, gd, ctl, lb, ro.out, forced, maxc, blocks,
                          (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz),
                          prof ? dev_field(ctl, offsetof(CcCtl, level_clock)) : nullptr, s));
     mark(3);
   } else {
-    // The host keeps at most kLevelsAhead launches queued beyond the last
-    // level the device has started, waiting at most kAheadWaitUs for it, so
-    // that it sees the done flag a few levels after the frontier empties.
     volatile unsigned int *done = g->h_done;
     done[0] = 0u;
     done[1] = 0u;
-    for (int t = 3; t <= n && e == hipSuccess; ++t, ++levels) {
-      if (t - 3 >= kLevelsAhead) {
+    for (int step = 0; step < n - 2 && e == hipSuccess; ++step, ++levels) {
+      if (step >= kLevelsAhead) {
         const auto t_wait = std::chrono::steady_clock::now();
-        while (done[0] == 0u && (int)done[1] < t - kLevelsAhead &&
+        while (done[0] == 0u && (int)done[1] < step - kLevelsAhead + 1 &&
                std::chrono::steady_clock::now() - t_wait <
                    std::chrono::microseconds(kAheadWaitUs)) {
         }
       }
       if (done[0] != 0u) break;
-      mark(2 + 2 * (t - 3));
-      chk(cc_launch_level(W, en, gd, ctl, f[t & 1], f[(t + 1) & 1], st[(t - 1) & 1],
-                          st[t & 1], ro.out, t, forced, bfs_blocks, g->d_done, s));
-      mark(3 + 2 * (t - 3));
+      mark(2 + 2 * step);
+      chk(cc_launch_step(W, en, gd, ctl, lb, ro.out, step, forced, maxc, bfs_blocks, g->d_done, s));
+      mark(3 + 2 * step);
     }
   }
   // Depth-first continuation (each kernel returns at once if the levels
@@ -415,37 +414,50 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       return (double)x;
     };
     g->info.stage1_ms = span(0, 1);
+    // per-step device time, credited to the length t the step expanded
+    // (CcCtl::step_level); a two-level step's time goes to its t
+    const int steps = levels;
+    auto step_t = [&](int st) { return st < CC_HSLOTS ? h.step_level[st] : 0; };
     if (persistent) {
-      // per-level spans from the clock block 0 read at the start of each level
       g->info.level_ms = span(2, 3);
-      for (int t = 3; t < 3 + levels && t + 1 < CC_HSLOTS; ++t)
-        g->level_ms[t] = (double)(h.level_clock[t + 1] - h.level_clock[t]) * 1e3 /
-                         (double)g->dev.clock_hz;
+      for (int st = 0; st < steps && st + 1 < CC_HSLOTS; ++st) {
+        const int t = step_t(st);
+        if (t >= 3 && t < CC_HSLOTS)
+          g->level_ms[t] = (double)(h.level_clock[st + 1] - h.level_clock[st]) * 1e3 /
+                           (double)g->dev.clock_hz;
+      }
     } else {
-      for (int t = 3; t < 3 + levels; ++t) {
-        g->level_ms[t] = span(2 + 2 * (t - 3), 3 + 2 * (t - 3));
-        g->info.level_ms += g->level_ms[t];
+      for (int st = 0; st < steps; ++st) {
+        const double ms_s = span(2 + 2 * st, 3 + 2 * st);
+        g->info.level_ms += ms_s;
+        const int t = step_t(st);
+        if (t >= 3 && t < CC_HSLOTS) g->level_ms[t] += ms_s;
       }
     }
     g->info.dfs_ms = span(2 * n + 2, 2 * n + 3);
-    // Bytes the level kernels must move: each path they expand is read once
-    // and each extension they write is written once (X words, S words in
-    // enumerate mode, 2 bytes of end vertices); each cycle they close is
-    // staged (W words written, then read by the next level) and written as
-    // k int32 ids plus one int64 offset.
-    const int last = h.mode ? h.switch_level : n;
+    // Bytes the steps must move: each path a step expands is read once and
+    // each path it writes is written once (X words, S words in enumerate
+    // mode, 2 bytes of end vertices); each cycle is staged (W words written,
+    // then read by the next step) and written as k int32 ids plus one int64
+    // offset.  Paths a two-level step only counts move no bytes.
     const int64_t pp = (int64_t)W * 8 * (en ? 2 : 1) + 2;
     auto level_count = [&](int t) {
       unsigned long long c = 0;
       for (int sh = 0; sh < CC_SHARDS; ++sh) c += std::min(h.count_sh[sh][t], cap_s);
       return (int64_t)c;
     };
+    const int last_len = h.mode ? h.bfs_max_len : n;
     int64_t bytes = 0;
-    for (int t = 3; t <= last && t < 3 + levels; ++t) {
+    for (int st = 0; st < steps; ++st) {
+      const int t = step_t(st);
+      if (t < 3 || t > n) continue;
+      const int tn = (st + 1 < steps && st + 1 < CC_HSLOTS) ? step_t(st + 1) : t + 1;
+      if (tn <= t) continue;
       bytes += level_count(t) * pp;
-      if (t + 1 <= n) bytes += level_count(t + 1) * pp;
-      if (en && t + 1 <= n && t + 1 <= (h.mode ? h.bfs_max_len : n))
-        bytes += (int64_t)h.hist[t + 1] * (16 * W + 4 * (t + 1) + 8);
+      if (tn <= n && st + 1 < steps) bytes += level_count(tn) * pp;
+      if (en)
+        for (int k = t + 1; k <= tn && k <= n && k <= last_len; ++k)
+          bytes += (int64_t)h.hist[k] * (16 * W + 4 * k + 8);
     }
     g->info.level_bytes = bytes;
   }
