@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
-PROFILE = os.path.join(ROOT, "profiles", "k_level_grid8x8_enumerate.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_step_grid8x8_enumerate.md")
 KERNELS = os.path.join(ROOT, "paper_1410_4876_amd", "csrc", "cc_kernels.hip")
 
 
@@ -202,8 +202,9 @@ def main():
     }
     if profile:
         # Second timed pass of the same steps with HIP event pairs around
-        # every level launch (on the stream the kernels run on): the level
-        # kernel's average launch duration and the bytes it must move.
+        # every breadth-first step launch (on the stream the kernels run on):
+        # the step kernel's average launch duration and the bytes it must
+        # move.
         torch.cuda.synchronize()
         pinfos = [step(True) for _ in range(args.steps)]
         torch.cuda.synchronize()
@@ -213,16 +214,17 @@ def main():
         achieved = lvl_bytes / (lvl_ms * 1e-3) / 1e9 if lvl_ms > 0 else 0.0
         persistent = launches == len(pinfos)
         out["roofline"] = {"bound": "hbm",
-                           "kernel": ("k_levels (all breadth-first levels in one cooperative "
-                                      "launch, staged-cycle decode)" if persistent else
-                                      "k_level (one breadth-first level per launch)"),
+                           "kernel": ("k_levels (all breadth-first steps in one cooperative "
+                                      "launch)" if persistent else
+                                      "k_step (breadth-first step: one or two levels per "
+                                      "launch, staged-cycle decode)"),
                            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBPS, 4),
                            "traffic": counted_traffic(),
                            "bytes_per_launch": round(lvl_bytes / max(launches, 1), 1),
                            "avg_launch_us": round(lvl_ms * 1e3 / max(launches, 1), 3),
                            "launches_per_step": round(launches / len(pinfos), 1),
-                           "measured": "HIP events around every level launch, second pass of "
+                           "measured": "HIP events around every step launch, second pass of "
                                        "the timed steps"}
         out["breakdown_ms"] = {
             "stage1": round(sum(i["stage1_ms"] for i in pinfos) / len(pinfos), 4),

@@ -67,9 +67,11 @@ typedef enum cc_status {
 #define CC_OUTPUT_DEVICE (1u << 1) /* cc_enumerate's verts/offsets are device pointers        */
 #define CC_FORCE_DFS     (1u << 2) /* take the depth-first path from level dfs_level on      */
 #define CC_PROFILE       (1u << 3) /* time each kernel of a run with HIP events (cc_run_info) */
-#define CC_LEVEL_PERSISTENT (1u << 4) /* run all breadth-first levels in one cooperative
-                                        launch with a grid barrier between levels, instead
-                                        of one launch per level (same results)             */
+#define CC_LEVEL_PERSISTENT (1u << 4) /* run all breadth-first steps in one cooperative
+                                        launch with a grid barrier between steps, instead
+                                        of one launch per step (same results)              */
+#define CC_ONE_LEVEL_STEPS (1u << 5)  /* expand one level per breadth-first step, never two
+                                        (same results)                                     */
 
 typedef struct cc_options {
   void *stream;                  /* hipStream_t; NULL = the null stream                 */

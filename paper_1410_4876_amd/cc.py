@@ -33,6 +33,7 @@ CC_OUTPUT_DEVICE = 1 << 1
 CC_FORCE_DFS = 1 << 2
 CC_PROFILE = 1 << 3
 CC_LEVEL_PERSISTENT = 1 << 4
+CC_ONE_LEVEL_STEPS = 1 << 5
 CC_MAX_VERTICES = 128
 CC_BATCH_PERSISTENT = 0
 CC_BATCH_PER_GRAPH = 1
@@ -186,7 +187,8 @@ class Graph:
     def __init__(self, n, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
                  force_dfs_level: int | None = None, dfs_waves_per_cu: int = 0,
                  bfs_blocks: int = 0, output_device: bool = True, profile: bool = False,
-                 dfs_donate_min: int = 0, dfs_claim: int = 0, persistent_levels: bool = False):
+                 dfs_donate_min: int = 0, dfs_claim: int = 0, persistent_levels: bool = False,
+                 one_level_steps: bool = False):
         L = lib()
         rp, rp_dev, self._k1 = _ptr(_as_i32(row_ptr))
         ci, ci_dev, self._k2 = _ptr(_as_i32(col_idx))
@@ -203,6 +205,8 @@ class Graph:
             flags |= CC_PROFILE
         if persistent_levels:
             flags |= CC_LEVEL_PERSISTENT
+        if one_level_steps:
+            flags |= CC_ONE_LEVEL_STEPS
         self.opt = Options(_stream_handle(stream), int(budget_bytes), flags,
                            int(force_dfs_level or 0), int(dfs_waves_per_cu), int(bfs_blocks),
                            int(dfs_donate_min), int(dfs_claim))

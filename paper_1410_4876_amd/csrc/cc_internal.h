@@ -202,21 +202,21 @@ hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_
 hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
                               Stage st, hipStream_t s);
 // Step `step` of the breadth-first loop, one launch.  max_children bounds
-// the extensions of one path (max degree - 1).  host_done (pinned host
+// the extensions of one path (max degree - 1); two allows two-level steps.  host_done (pinned host
 // memory, may be NULL): host_done[0] receives step + 1 once the loop is over
 // (nothing left, or handed over to the depth-first kernel), host_done[1]
 // step + 1 when the step starts, so the host can stop launching steps and
 // keep only a few queued.
 hipError_t cc_launch_step(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                          OutDev out, int step, int forced_level, int max_children, int blocks,
-                          unsigned int *host_done, hipStream_t s);
+                          OutDev out, int step, int forced_level, int max_children, bool two,
+                          int blocks, unsigned int *host_done, hipStream_t s);
 // The whole loop as one cooperative launch of `blocks` blocks (at most
 // cc_levels_max_blocks).  With `clock` (device memory, may be NULL) the
 // start of every step is recorded.
 hipError_t cc_launch_levels(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                            OutDev out, int forced_level, int max_children, int blocks,
-                            unsigned long long barrier_timeout, unsigned long long *clock,
-                            hipStream_t s);
+                            OutDev out, int forced_level, int max_children, bool two,
+                            int blocks, unsigned long long barrier_timeout,
+                            unsigned long long *clock, hipStream_t s);
 // Blocks of k_levels that fit on the device at once (0 if unknown).
 int cc_levels_max_blocks(int W, bool enumerate);
 // The handed-over paths are in frontier f0 or f1 (CcCtl::root_buf); the

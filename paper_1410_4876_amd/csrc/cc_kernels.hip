@@ -679,8 +679,8 @@ __device__ __forceinline__ StepState load_state(CcCtl *ctl, int i) {
 // graph is loaded into LDS here, together with the counters.
 template <int W, bool ENUM>
 __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
-                         int step, int forced_level, int maxc, LevelLds<W, ENUM> &L,
-                         bool lds_ready) {
+                         int step, int forced_level, int maxc, bool allow_two,
+                         LevelLds<W, ENUM> &L, bool lds_ready) {
   constexpr int IPT = CC_LEVEL_IPT;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -800,12 +800,18 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   }
 
   // ---- one level or two
-  const unsigned long long chunk = (unsigned long long)CC_BLOCK * IPT;
+  // Paths per lane per chunk: up to IPT, fewer when the frontier is small,
+  // so that a small step spreads over more blocks instead of making a few
+  // lanes walk several paths one after the other.
   const unsigned long long grid = gridDim.x;
+  const int ipt = (int)min((unsigned long long)IPT,
+                           max(1ull, (cnt + grid * CC_BLOCK - 1) / (grid * CC_BLOCK)));
+  const unsigned long long chunk = (unsigned long long)CC_BLOCK * ipt;
   const unsigned long long per_shard =
       (cnt + grid * chunk - 1) / (grid * chunk) * chunk * ((grid + CC_SHARDS - 1) / CC_SHARDS);
   const unsigned long long mc = (unsigned long long)(maxc > 1 ? maxc : 1);
-  const bool two = t + 2 <= n && t + 1 != forced_level && per_shard * mc * mc <= fout.cap_s &&
+  const bool two = allow_two && t + 2 <= n && t + 1 != forced_level &&
+                   per_shard * mc * mc <= fout.cap_s &&
                    (!ENUM || per_shard * mc * mc <= sw1.cap_s);
   if (blockIdx.x == 0 && tid == 0) {
     N.t = t + (two ? 2 : 1);
@@ -831,7 +837,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       const unsigned long long i = c0 + (unsigned long long)j * CC_BLOCK + tid;
-      valid[j] = i < cnt;
+      valid[j] = j < ipt && i < cnt;
       X[j] = bzero<W>();
       Sv[j] = bzero<W>();
       v1[j] = 0;
@@ -1012,16 +1018,22 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, LevelBufs B,
                                                    OutDev out, int step, int forced_level,
-                                                   int maxc, unsigned int *host_done) {
+                                                   int maxc, int allow_two,
+                                                   unsigned int *host_done) {
   __shared__ LevelLds<W, ENUM> L;
   if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done + 1, (unsigned)step + 1u);
   if (ld_relaxed(&ctl->mode) != 0) {
     if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done, (unsigned)step + 1u);
     return;
   }
-  const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, L, false);
-  if (r != CC_LEVEL_NEXT && host_done && blockIdx.x == 0 && threadIdx.x == 0)
+  const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0, L,
+                                   false);
+  if (r != CC_LEVEL_NEXT && host_done && blockIdx.x == 0 && threadIdx.x == 0) {
+    // host_done[2]: the loop handed over to the depth-first kernel; stored
+    // and released before host_done[0]
+    if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
     st_system(host_done, (unsigned)step + 1u);
+  }
 }
 
 // Grid-wide barrier of a cooperative launch (every block resident).  Blocks
@@ -1121,6 +1133,7 @@ __device__ void xcd_barrier(CcCtl *ctl, unsigned xcc, unsigned nx, unsigned long
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, LevelBufs B,
                                                      OutDev out, int forced_level, int maxc,
+                                                     int allow_two,
                                                      unsigned long long barrier_timeout,
                                                      unsigned long long *clock) {
   __shared__ LevelLds<W, ENUM> L;
@@ -1142,7 +1155,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Lev
   // has room for them
   for (; step < g.n - 2; ++step) {
     if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[step] = wall_clock64();
-    const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, L, true);
+    const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0,
+                                     L, true);
     if (r != CC_LEVEL_NEXT) {
       ++step;
       break;
@@ -1739,10 +1753,12 @@ __device__ void length_totals(CcCtl *ctl, bool enumerate, unsigned long long *sT
 // length starts in the output.
 __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
   __shared__ unsigned long long sTot[CC_HSLOTS];
-  const size_t words = (size_t)wk.nwaves * CC_MAIL;
+  // the four words in use of every mailbox line (request, response, count,
+  // hint); the rest of the line is padding
+  const size_t words = (size_t)wk.nwaves * 4;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < words;
        i += (size_t)gridDim.x * blockDim.x)
-    wk.mail[i] = 0u;
+    wk.mail[(i >> 2) * CC_MAIL + (i & 3)] = 0u;
   if (blockIdx.x != 0) return;
   if (enum_bases) length_totals(ctl, true, sTot);
   if (threadIdx.x == 0) {
@@ -1822,11 +1838,13 @@ hipError_t cc_launch_triplets(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f
 }
 
 hipError_t cc_launch_levels(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                            OutDev out, int forced_level, int max_children, int blocks,
-                            unsigned long long barrier_timeout, unsigned long long *clock,
-                            hipStream_t s) {
+                            OutDev out, int forced_level, int max_children, bool two,
+                            int blocks, unsigned long long barrier_timeout,
+                            unsigned long long *clock, hipStream_t s) {
   LevelBufs bb = b;
-  void *args[] = {&g, &ctl, &bb, &out, &forced_level, &max_children, &barrier_timeout, &clock};
+  int allow_two = two ? 1 : 0;
+  void *args[] = {&g,           &ctl,       &bb, &out, &forced_level, &max_children,
+                  &allow_two,   &barrier_timeout, &clock};
   const void *fn = W == 1 ? (en ? (const void *)k_levels<1, true> : (const void *)k_levels<1, false>)
                           : (en ? (const void *)k_levels<2, true> : (const void *)k_levels<2, false>);
   return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(CC_BLOCK), args, 0, s);
@@ -1844,15 +1862,16 @@ int cc_levels_max_blocks(int W, bool en) {
 }
 
 hipError_t cc_launch_step(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                          OutDev out, int step, int forced_level, int max_children, int blocks,
-                          unsigned int *host_done, hipStream_t s) {
+                          OutDev out, int step, int forced_level, int max_children, bool two,
+                          int blocks, unsigned int *host_done, hipStream_t s) {
   dim3 gr(blocks), bl(CC_BLOCK);
+  const int allow_two = two ? 1 : 0;
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_step<1, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
-    else hipLaunchKernelGGL((k_step<1, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
+    if (en) hipLaunchKernelGGL((k_step<1, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
+    else hipLaunchKernelGGL((k_step<1, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
   } else {
-    if (en) hipLaunchKernelGGL((k_step<2, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
-    else hipLaunchKernelGGL((k_step<2, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, host_done);
+    if (en) hipLaunchKernelGGL((k_step<2, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
+    else hipLaunchKernelGGL((k_step<2, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
   }
   return hipGetLastError();
 }
@@ -1887,7 +1906,8 @@ hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchD
 }
 
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s) {
-  hipLaunchKernelGGL(k_dfs_prepare, dim3(64), dim3(256), 0, s, ctl, wk, n, enum_bases ? 1 : 0);
+  const int blocks = std::max(1, std::min(1024, (wk.nwaves * 4 + 255) / 256));
+  hipLaunchKernelGGL(k_dfs_prepare, dim3(blocks), dim3(256), 0, s, ctl, wk, n, enum_bases ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -289,7 +289,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     d->claim = g->opt.dfs_claim > 0 ? (g->opt.dfs_claim + CC_CHUNK - 1) / CC_CHUNK * CC_CHUNK : 0;
   }
   const int dfs_blocks_c = nw_c / 4, dfs_blocks_e = nw_e / 4;
-  const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
+  const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 5;
   const int forced = (g->opt.flags & CC_FORCE_DFS) ? std::max(3, (int)g->opt.dfs_level) : -1;
   const unsigned long long idle_timeout =
       (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz);
@@ -332,11 +332,12 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
                            ? cc_levels_max_blocks(W, en)
                            : 0;
   const bool persistent = coop_max >= CC_SHARDS;
+  const bool two_ok = !(g->opt.flags & CC_ONE_LEVEL_STEPS);
   if (persistent) {
     const int want = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
     const int blocks = std::max(1, std::min(want, coop_max));
     mark(2);
-    chk(cc_launch_levels(W, en, gd, ctl, lb, ro.out, forced, maxc, blocks,
+    chk(cc_launch_levels(W, en, gd, ctl, lb, ro.out, forced, maxc, two_ok, blocks,
                          (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz),
                          prof ? dev_field(ctl, offsetof(CcCtl, level_clock)) : nullptr, s));
     mark(3);
@@ -344,6 +345,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     volatile unsigned int *done = g->h_done;
     done[0] = 0u;
     done[1] = 0u;
+    done[2] = 0u;
     for (int step = 0; step < n - 2 && e == hipSuccess; ++step, ++levels) {
       if (step >= kLevelsAhead) {
         const auto t_wait = std::chrono::steady_clock::now();
@@ -354,25 +356,33 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       }
       if (done[0] != 0u) break;
       mark(2 + 2 * step);
-      chk(cc_launch_step(W, en, gd, ctl, lb, ro.out, step, forced, maxc, bfs_blocks, g->d_done, s));
+      chk(cc_launch_step(W, en, gd, ctl, lb, ro.out, step, forced, maxc, two_ok, bfs_blocks,
+                         g->d_done, s));
       mark(3 + 2 * step);
     }
   }
-  // Depth-first continuation (each kernel returns at once if the levels
-  // finished within the budget).
+  // Depth-first continuation.  Each of its kernels returns at once if the
+  // levels finished within the budget; they are not launched at all when
+  // the host has already seen the loop end without a hand-over (the
+  // hand-over word is released before the end-of-loop word).
+  volatile unsigned int *hd = g->h_done;
+  const bool levels_finished = !persistent && hd[0] != 0u && hd[2] == 0u;
   mark(2 * n + 2);
-  chk(cc_launch_dfs_prepare(ctl, wc, n, false, s));
-  if (en) {
+  if (levels_finished) {
+    // nothing to continue
+  } else if (!en) {
+    chk(cc_launch_dfs_prepare(ctl, wc, n, false, s));
+    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, ro.out,
+                      dev_field(ctl, offsetof(CcCtl, hist_sh)), CC_HSLOTS, true, dfs_blocks_c,
+                      idle_timeout, s));
+  } else {
+    chk(cc_launch_dfs_prepare(ctl, wc, n, false, s));
     chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, ro.out,
                       dev_field(ctl, offsetof(CcCtl, dfs_hist)), 0, true, dfs_blocks_c,
                       idle_timeout, s));
     chk(cc_launch_dfs_prepare(ctl, we, n, true, s));
     chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we, ro.out, nullptr, 0, false,
                       dfs_blocks_e, idle_timeout, s));
-  } else {
-    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, ro.out,
-                      dev_field(ctl, offsetof(CcCtl, hist_sh)), CC_HSLOTS, true, dfs_blocks_c,
-                      idle_timeout, s));
   }
   mark(2 * n + 3);
   chk(cc_launch_finalize(ctl, ro.out, n, en, s));
@@ -516,7 +526,7 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   if (n > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
   if (n > 0 && !row_ptr) return CC_ERR_INVALID_ARG;
   const uint32_t flags = opt ? opt->flags : 0u;
-  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT))
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT | CC_ONE_LEVEL_STEPS))
     return CC_ERR_INVALID_ARG;
   if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
               opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))
@@ -803,7 +813,7 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   *out = nullptr;
   if (n_graphs < 0 || !graph_vtx_off || (n_graphs > 0 && !row_ptr)) return CC_ERR_INVALID_ARG;
   const uint32_t flags = opt ? opt->flags : 0u;
-  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT))
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT | CC_ONE_LEVEL_STEPS))
     return CC_ERR_INVALID_ARG;
   if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
               opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))

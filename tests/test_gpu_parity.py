@@ -254,3 +254,13 @@ def test_persistent_level_loop_matches(cc):
     info = full_parity(cc, gg.permute_random(gg.grid(6, 8), np.random.default_rng(5)),
                        persistent_levels=True, budget_bytes=512 << 10)
     assert info["switch_level"] > 3
+
+
+def test_one_level_steps_match(cc):
+    """Every breadth-first step one level deep: the same results as the
+    default steps, which expand two levels whenever the output fits."""
+    full_parity(cc, gg.permute_random(gg.grid(5, 7), np.random.default_rng(8)), one_level_steps=True)
+    full_parity(cc, gg.er_gnm(100, 125, np.random.default_rng(8)), one_level_steps=True)
+    info = full_parity(cc, gg.permute_random(gg.grid(6, 8), np.random.default_rng(5)),
+                       one_level_steps=True, budget_bytes=512 << 10)
+    assert info["switch_level"] > 3
