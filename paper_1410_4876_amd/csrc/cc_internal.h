@@ -11,6 +11,9 @@
 #define CC_BLOCK 256              // threads per block for the expansion kernels
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk
 #define CC_LEVEL_IPT 4            // paths per lane per chunk in the level kernel
+#define CC_DEC_WORDS 1536         // per-wavefront LDS words for decoded cycles (enumerate steps)
+#define CC_DEEP_PATHS 2048        // leading steps on one block: at most this many paths
+#define CC_DEEP_CYCLES 1024       // and at most this many staged cycles to decode
 #define CC_ROOT_CLAIM 1024        // handed-over paths a depth-first wavefront claims at once
 // Frontier and staged-cycle counters are split into CC_SHARDS shards, each
 // on its own cache lines: a block appends to shard blockIdx % CC_SHARDS, so
@@ -77,9 +80,10 @@ struct CcCtl {
   unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
   unsigned long long donations;             // chunks given away on request (diagnostic)
   unsigned long long level_clock[CC_HSLOTS]; // persistent level loop: clock at each step start
-  int levels_run;                           // persistent level loop: steps run
+  int levels_run;                           // breadth-first steps run
   int root_buf;                             // frontier buffer of the handed-over paths
-  StepState ss[2];                          // step s reads ss[s & 1]; its block 0 writes the other
+  StepState ss[CC_HSLOTS];                  // step s reads ss[s]; its block 0 writes ss[s + 1]
+  int launch_step[CC_HSLOTS];               // step of step launch i, plus one (0: loop over)
   int step_level[CC_HSLOTS];                // t of each step
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over
   int switch_level;                         // path length handed to the depth-first kernel
@@ -201,14 +205,21 @@ hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_
 // to stage st (pair 0, slot 0); sets the state of step 0.
 hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
                               Stage st, hipStream_t s);
-// Step `step` of the breadth-first loop, one launch.  max_children bounds
-// the extensions of one path (max degree - 1); two allows two-level steps.  host_done (pinned host
-// memory, may be NULL): host_done[0] receives step + 1 once the loop is over
-// (nothing left, or handed over to the depth-first kernel), host_done[1]
-// step + 1 when the step starts, so the host can stop launching steps and
-// keep only a few queued.
+// The leading small steps of the breadth-first loop on one block (launch 0
+// for host_done); records the step the launches start at.  max_children
+// bounds the extensions of one path (max degree - 1); two allows two-level
+// steps.
+hipError_t cc_launch_head(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
+                          OutDev out, int forced_level, int max_children, bool two,
+                          unsigned int *host_done, hipStream_t s);
+// Launch `launch` (>= 1) of the breadth-first loop: one step on `blocks`
+// blocks, the one recorded by the previous launch.  host_done (pinned host
+// memory, may be NULL): host_done[0] receives launch + 1 once the loop is
+// over (nothing left, or handed over to the depth-first kernel; then
+// host_done[2] = 1 first), host_done[1] launch + 1 when the launch starts,
+// so the host can stop launching and keep only a few queued.
 hipError_t cc_launch_step(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                          OutDev out, int step, int forced_level, int max_children, bool two,
+                          OutDev out, int launch, int forced_level, int max_children, bool two,
                           int blocks, unsigned int *host_done, hipStream_t s);
 // The whole loop as one cooperative launch of `blocks` blocks (at most
 // cc_levels_max_blocks).  With `clock` (device memory, may be NULL) the

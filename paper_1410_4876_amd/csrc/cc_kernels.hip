@@ -556,12 +556,15 @@ struct LevelLds {
   unsigned long long PrevFront;
   int Flags;      // written by wave 0: the input frontier overflowed
   int FlagsH[2];  // written by waves 1 and 2: a staged length overflowed
+  // per-wavefront buffer of decoded cycles (vertex ids, cycle after cycle)
+  int Dec[ENUM ? CC_BLOCK / CC_WAVE : 1][ENUM ? CC_DEC_WORDS : 1];
 };
 
 // step_body results
 #define CC_LEVEL_NEXT 0      // the step expanded its paths; continue
 #define CC_LEVEL_SWITCH 1    // handed over to the depth-first kernel
 #define CC_LEVEL_EMPTY 2     // no paths left: the loop is over
+#define CC_LEVEL_DEFER 3     // too large for one block: not started (one-block steps)
 
 template <int W, bool ENUM>
 __device__ void load_graph_lds(const GraphDev &g, LevelLds<W, ENUM> &L) {
@@ -638,22 +641,49 @@ __device__ __forceinline__ void reserve(LevelLds<W, ENUM> &L, unsigned a, unsign
   }
 }
 
-// Decodes staged cycle gi of length k from stage st (shard prefix pre) to
-// output index cb + gi, vertices at vb + gi * k.
+// Orders this wavefront's LDS accesses before and after (a wavefront's LDS
+// operations complete in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Decodes the h staged cycles of length k from stage st (shard prefix pre):
+// cycle gi goes to output index cb + gi, vertices at vb + gi * k.  Wavefront
+// gw of nwg takes runs of `per` consecutive cycles: each lane walks one
+// cycle into the wavefront's LDS buffer, then the run's vertex range, which
+// is contiguous in the output, is written by consecutive lanes.
 template <int W, bool ENUM>
-__device__ __forceinline__ void decode_one(const LevelLds<W, ENUM> &L, const Stage &st,
-                                           const unsigned long long *pre, unsigned long long gi,
-                                           int k, long long cb, long long vb, const OutDev &out) {
-  const int s = shard_of(pre, gi);
-  const unsigned long long e = (unsigned long long)s * st.cap_s + (gi - pre[s]);
-  Bits<W> C;
+__device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st,
+                           const unsigned long long *pre, unsigned long long h, int k,
+                           long long cb, long long vb, const OutDev &out, unsigned long long gw,
+                           unsigned long long nwg) {
+  if (h == 0 || k < 3) return;
+  const int lane = lane_id();
+  const unsigned long long per = (unsigned long long)min(CC_WAVE, CC_DEC_WORDS / k);
+  for (unsigned long long g0 = gw * per; g0 < h; g0 += nwg * per) {
+    const unsigned long long nb = min(per, h - g0);
+    const unsigned long long gi = g0 + (unsigned long long)lane;
+    if ((unsigned long long)lane < nb) {
+      const int s = shard_of(pre, gi);
+      const unsigned long long e = (unsigned long long)s * st.cap_s + (gi - pre[s]);
+      Bits<W> C;
 #pragma unroll
-  for (int w = 0; w < W; ++w) C.w[w] = st.C[w * st.cap + e];
-  const long long cyc = cb + (long long)gi;
-  const long long pos = vb + (long long)gi * k;
-  if (cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap) {
-    write_cycle<W>(L.No, C, k, out.verts + pos);
-    out.offs[cyc] = pos;
+      for (int w = 0; w < W; ++w) C.w[w] = st.C[w * st.cap + e];
+      write_cycle<W>(L.No, C, k, buf + lane * k);
+      const long long cyc = cb + (long long)gi;
+      const long long pos = vb + (long long)gi * k;
+      if (cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap)
+        out.offs[cyc] = pos;
+    }
+    wave_lds_sync();
+    const long long base = vb + (long long)g0 * k;
+    const int words = (int)nb * k;
+    for (int d = lane; d < words; d += CC_WAVE) {
+      const long long q = base + d;
+      if (q >= 0 && q < out.verts_cap) out.verts[q] = buf[d];
+    }
+    wave_lds_sync();  // the next run overwrites buf
   }
 }
 
@@ -677,7 +707,12 @@ __device__ __forceinline__ StepState load_state(CcCtl *ctl, int i) {
 // One step for this block.  Every block of the grid reads the same state
 // and counters and so reaches the same result.  With lds_ready false the
 // graph is loaded into LDS here, together with the counters.
-template <int W, bool ENUM>
+//
+// ONE: the step runs on a grid of one block (the leading small steps).  A
+// step with more than CC_DEEP_PATHS paths or CC_DEEP_CYCLES staged cycles
+// is then left untouched (CC_LEVEL_DEFER) for the full grid; the block's
+// chunks go to the output shards in turn.
+template <int W, bool ENUM, bool ONE>
 __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
                          int step, int forced_level, int maxc, bool allow_two,
                          LevelLds<W, ENUM> &L, bool lds_ready) {
@@ -685,7 +720,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / CC_WAVE;
-  const StepState S = load_state(ctl, step & 1);
+  const StepState S = load_state(ctl, step);
   if (S.done) return CC_LEVEL_EMPTY;
   const int t = S.t;
   const int n = g.n;
@@ -725,6 +760,14 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   __syncthreads();
   const int flags = L.Flags | L.FlagsH[0] | L.FlagsH[1];
   const unsigned long long cnt = L.Pre[CC_SHARDS];
+  if (ONE && !flags) {
+    const unsigned long long staged =
+        ENUM ? (S.slen0 ? L.PreH0[CC_SHARDS] : 0ull) + (S.slen1 ? L.PreH1[CC_SHARDS] : 0ull)
+             : 0ull;
+    if (cnt > CC_DEEP_PATHS || staged > CC_DEEP_CYCLES) return CC_LEVEL_DEFER;
+  }
+  const unsigned vblk = ONE ? 0u : blockIdx.x;   // this block's place in the step
+  const unsigned vgrid = ONE ? 1u : gridDim.x;   // blocks taking part
   if (blockIdx.x == 0 && tid == 0) {
     if (step < CC_HSLOTS) ctl->step_level[step] = t;
     if (S.prev_two) ctl->front[t - 1] = L.PrevFront;
@@ -736,11 +779,11 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
     const unsigned long long h0 = L.PreH0[CC_SHARDS], h1 = k1 ? L.PreH1[CC_SHARDS] : 0ull;
     const long long cb0 = (long long)L.Cum[0], vb0 = (long long)L.Cum[1];
     const long long cb1 = cb0 + (long long)h0, vb1 = vb0 + (long long)h0 * k0;
-    for (unsigned long long gi = (unsigned long long)blockIdx.x * CC_BLOCK + tid; gi < h0 + h1;
-         gi += (unsigned long long)gridDim.x * CC_BLOCK) {
-      if (gi < h0) decode_one<W, ENUM>(L, sd0, L.PreH0, gi, k0, cb0, vb0, out);
-      else decode_one<W, ENUM>(L, sd1, L.PreH1, gi - h0, k1, cb1, vb1, out);
-    }
+    constexpr int NWB = CC_BLOCK / CC_WAVE;
+    const unsigned long long gw = (unsigned long long)vblk * NWB + wave;
+    const unsigned long long nwg = (unsigned long long)vgrid * NWB;
+    decode_run<W, ENUM>(L, L.Dec[ENUM ? wave : 0], sd0, L.PreH0, h0, k0, cb0, vb0, out, gw, nwg);
+    decode_run<W, ENUM>(L, L.Dec[ENUM ? wave : 0], sd1, L.PreH1, h1, k1, cb1, vb1, out, gw, nwg);
     if (blockIdx.x == 0 && tid == 0) {
       ctl->cum_c[k0] = (unsigned long long)cb1;
       ctl->cum_v[k0] = (unsigned long long)vb1;
@@ -788,14 +831,14 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
       ctl->switch_level = sw_level;
       ctl->bfs_max_len = sw_max;
       ctl->root_buf = sw_buf;
-      ctl->ss[(step + 1) & 1] = N;
+      ctl->ss[step + 1] = N;
       __threadfence();
       st_release(&ctl->mode, 1);
     }
     return CC_LEVEL_SWITCH;
   }
   if (cnt == 0) {
-    if (blockIdx.x == 0 && tid == 0) ctl->ss[(step + 1) & 1] = N;
+    if (blockIdx.x == 0 && tid == 0) ctl->ss[step + 1] = N;
     return CC_LEVEL_EMPTY;
   }
 
@@ -803,12 +846,16 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   // Paths per lane per chunk: up to IPT, fewer when the frontier is small,
   // so that a small step spreads over more blocks instead of making a few
   // lanes walk several paths one after the other.
-  const unsigned long long grid = gridDim.x;
+  const unsigned long long grid = vgrid;
   const int ipt = (int)min((unsigned long long)IPT,
                            max(1ull, (cnt + grid * CC_BLOCK - 1) / (grid * CC_BLOCK)));
   const unsigned long long chunk = (unsigned long long)CC_BLOCK * ipt;
+  // No shard takes the output of more than per_shard input paths: a block
+  // of the grid writes to shard blockIdx mod CC_SHARDS, a lone block's
+  // chunk i to shard i mod CC_SHARDS.
   const unsigned long long per_shard =
-      (cnt + grid * chunk - 1) / (grid * chunk) * chunk * ((grid + CC_SHARDS - 1) / CC_SHARDS);
+      ONE ? ((cnt + chunk - 1) / chunk + CC_SHARDS - 1) / CC_SHARDS * chunk
+          : (cnt + grid * chunk - 1) / (grid * chunk) * chunk * ((grid + CC_SHARDS - 1) / CC_SHARDS);
   const unsigned long long mc = (unsigned long long)(maxc > 1 ? maxc : 1);
   const bool two = allow_two && t + 2 <= n && t + 1 != forced_level &&
                    per_shard * mc * mc <= fout.cap_s &&
@@ -821,16 +868,17 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
     N.slen1 = (ENUM && two) ? t + 2 : 0;
     N.prev_two = two ? 1 : 0;
     N.done = 0;
-    ctl->ss[(step + 1) & 1] = N;
+    ctl->ss[step + 1] = N;
     ctl->front[t] = cnt;
     atomicMax(&ctl->peak, cnt);
   }
   // Blocks without a chunk have nothing more to do in this step.
-  if ((unsigned long long)blockIdx.x * chunk >= cnt) return CC_LEVEL_NEXT;
-  const int osh = blockIdx.x % CC_SHARDS;  // this block's output shard
-  unsigned long long acc1 = 0, acc2 = 0;   // closures (count mode)
-  for (unsigned long long c0 = (unsigned long long)blockIdx.x * chunk; c0 < cnt;
-       c0 += grid * chunk) {
+  if ((unsigned long long)vblk * chunk >= cnt) return CC_LEVEL_NEXT;
+  unsigned long long acc1 = 0, acc2 = 0;  // closures (count mode)
+  unsigned ci = 0;                        // chunks this block has done
+  for (unsigned long long c0 = (unsigned long long)vblk * chunk; c0 < cnt;
+       c0 += grid * chunk, ++ci) {
+    const int osh = ONE ? (int)(ci % CC_SHARDS) : (int)(blockIdx.x % CC_SHARDS);  // output shard
     Bits<W> X[IPT], Sv[IPT];
     int v1[IPT], vt[IPT];
     bool valid[IPT];
@@ -1005,34 +1053,78 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
         s1 += L.WaveA[w];
         s2 += L.WaveB[w];
       }
-      if (s1) atomicAdd(&ctl->hist_sh[osh][t + 1], s1);
-      if (s2) atomicAdd(&ctl->hist_sh[osh][t + 2], s2);
+      const int hsh = blockIdx.x % CC_SHARDS;
+      if (s1) atomicAdd(&ctl->hist_sh[hsh][t + 1], s1);
+      if (s2) atomicAdd(&ctl->hist_sh[hsh][t + 2], s2);
     }
   }
   return CC_LEVEL_NEXT;
 }
 
-// One launch per step.  host_done (pinned host memory, may be NULL):
-// host_done[1] = step + 1 when the step starts, host_done[0] = step + 1 when
-// the loop is over, so the host stops launching steps and keeps few queued.
+// The leading steps on one block, while they are small (at most
+// CC_DEEP_PATHS paths and CC_DEEP_CYCLES staged cycles): on many graphs the
+// first levels hold a few hundred paths, and a full-grid launch per step
+// would cost more than the work.  Runs before the step launches and records
+// where they start (launch_step[1]); it is launch 0 for host_done.  Its
+// steps pass data to each other through the block's own stores, ordered by
+// its barriers.
+template <int W, bool ENUM>
+__global__ __launch_bounds__(CC_BLOCK) void k_head(GraphDev g, CcCtl *ctl, LevelBufs B,
+                                                   OutDev out, int forced_level, int maxc,
+                                                   int allow_two, unsigned int *host_done) {
+  __shared__ LevelLds<W, ENUM> L;
+  if (host_done && threadIdx.x == 0) st_system(host_done + 1, 1u);
+  int step = 0, r = CC_LEVEL_NEXT;
+  for (; step < g.n - 2; ++step) {
+    r = step_body<W, ENUM, true>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0, L,
+                                 step > 0);
+    if (r != CC_LEVEL_NEXT) break;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // the first step the launches run (deferred, or past the last); none
+    // once the loop is over
+    const bool over = r == CC_LEVEL_EMPTY || r == CC_LEVEL_SWITCH;
+    const int next = over ? step + 1 : step;
+    ctl->launch_step[1] = over ? 0 : next + 1;
+    ctl->levels_run = next;
+    if ((r == CC_LEVEL_EMPTY || r == CC_LEVEL_SWITCH) && host_done) {
+      if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
+      st_system(host_done, 1u);
+    }
+  }
+}
+
+// One launch per step (launch >= 1, after k_head): it runs step
+// launch_step[launch] - 1 and records the next launch's.  host_done (pinned
+// host memory, may be NULL): host_done[1] = launch + 1 when the launch
+// starts, host_done[0] = launch + 1 when the loop is over, so the host
+// stops launching and keeps few launches queued.
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, LevelBufs B,
-                                                   OutDev out, int step, int forced_level,
+                                                   OutDev out, int launch, int forced_level,
                                                    int maxc, int allow_two,
                                                    unsigned int *host_done) {
   __shared__ LevelLds<W, ENUM> L;
-  if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done + 1, (unsigned)step + 1u);
-  if (ld_relaxed(&ctl->mode) != 0) {
-    if (host_done && blockIdx.x == 0 && threadIdx.x == 0) st_system(host_done, (unsigned)step + 1u);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (host_done && lead) st_system(host_done + 1, (unsigned)launch + 1u);
+  const int step = ld_relaxed(&ctl->launch_step[launch]) - 1;
+  if (ld_relaxed(&ctl->mode) != 0 || step < 0 || step >= g.n - 2) {
+    // handed over, or queued after the loop ended
+    if (host_done && lead) st_system(host_done, (unsigned)launch + 1u);
     return;
   }
-  const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0, L,
-                                   false);
-  if (r != CC_LEVEL_NEXT && host_done && blockIdx.x == 0 && threadIdx.x == 0) {
-    // host_done[2]: the loop handed over to the depth-first kernel; stored
-    // and released before host_done[0]
-    if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
-    st_system(host_done, (unsigned)step + 1u);
+  const int r = step_body<W, ENUM, false>(g, ctl, B, out, step, forced_level, maxc,
+                                          allow_two != 0, L, false);
+  if (lead) {
+    if (launch + 1 < CC_HSLOTS) ctl->launch_step[launch + 1] = r == CC_LEVEL_NEXT ? step + 2 : 0;
+    ctl->levels_run = step + 1;
+    if (r != CC_LEVEL_NEXT && host_done) {
+      // host_done[2]: the loop handed over to the depth-first kernel; stored
+      // and released before host_done[0]
+      if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
+      st_system(host_done, (unsigned)launch + 1u);
+    }
   }
 }
 
@@ -1155,8 +1247,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Lev
   // has room for them
   for (; step < g.n - 2; ++step) {
     if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[step] = wall_clock64();
-    const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0,
-                                     L, true);
+    const int r = step_body<W, ENUM, false>(g, ctl, B, out, step, forced_level, maxc,
+                                            allow_two != 0, L, true);
     if (r != CC_LEVEL_NEXT) {
       ++step;
       break;
@@ -1859,6 +1951,21 @@ int cc_levels_max_blocks(int W, bool en) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   return per_cu * cus;
+}
+
+hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
+                          OutDev out, int forced_level, int max_children, bool two,
+                          unsigned int *host_done, hipStream_t s) {
+  dim3 gr(1), bl(CC_BLOCK);
+  const int allow_two = two ? 1 : 0;
+  if (W == 1) {
+    if (en) hipLaunchKernelGGL((k_head<1, true>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
+    else hipLaunchKernelGGL((k_head<1, false>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
+  } else {
+    if (en) hipLaunchKernelGGL((k_head<2, true>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
+    else hipLaunchKernelGGL((k_head<2, false>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
+  }
+  return hipGetLastError();
 }
 
 hipError_t cc_launch_step(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,

@@ -18,6 +18,10 @@
 namespace {
 
 constexpr int64_t kDefaultBudget = 4ll << 30;
+// Largest device staging for cc_enumerate into host buffers taken at the
+// caller's capacities in one pass; larger capacities are sized exactly by a
+// counting run first.
+constexpr int64_t kHostStageBytes = 8ll << 30;
 constexpr int kLevelsAhead = 4;    // level launches queued beyond the device's progress
 constexpr int kAheadWaitUs = 200;  // longest the host waits for that progress
 constexpr double kIdleTimeoutSeconds = 30.0;
@@ -225,6 +229,12 @@ int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_child
 struct RunOut {
   OutDev out{};
   bool enumerate = false;
+  // Host output: the cycles are written to device staging at the end of
+  // the run's own workspace (out.verts/out.offsets are then ignored and
+  // out.*_cap give the staging capacities) and copied into these host
+  // buffers when they fit.
+  int32_t *host_verts = nullptr;
+  int64_t *host_offsets = nullptr;
 };
 
 // One full device run: stage one, the level loop, and the depth-first
@@ -256,9 +266,18 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   const size_t dfs_bytes = align_up(
       (size_t)std::min<int64_t>(std::max<int64_t>(budget / 2, (int64_t)64 << 20), (int64_t)2 << 30),
       1 << 16);
+  const bool host_out = en && ro.host_offsets != nullptr;
+  const size_t hv_bytes = host_out ? align_up((size_t)std::max<int64_t>(ro.out.verts_cap, 1) * 4, 256) : 0;
+  const size_t ho_bytes = host_out ? align_up((size_t)(ro.out.cyc_cap + 1) * 8, 256) : 0;
   char *arena = nullptr;
-  CC_TRY(hipMallocAsync((void **)&arena, 2 * buf_bytes + 4 * stage_bytes + dfs_bytes, s));
+  CC_TRY(hipMallocAsync((void **)&arena,
+                        2 * buf_bytes + 4 * stage_bytes + dfs_bytes + hv_bytes + ho_bytes, s));
   char *dfs_region = arena + 2 * buf_bytes + 4 * stage_bytes;
+  OutDev out = ro.out;
+  if (host_out) {
+    out.verts = (int *)(dfs_region + dfs_bytes);
+    out.offs = (long long *)(dfs_region + dfs_bytes + hv_bytes);
+  }
   LevelBufs lb{};
   lb.f[0] = carve_frontier(arena, cap_s, W, en);
   lb.f[1] = carve_frontier(arena + buf_bytes, cap_s, W, en);
@@ -337,7 +356,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     const int want = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
     const int blocks = std::max(1, std::min(want, coop_max));
     mark(2);
-    chk(cc_launch_levels(W, en, gd, ctl, lb, ro.out, forced, maxc, two_ok, blocks,
+    chk(cc_launch_levels(W, en, gd, ctl, lb, out, forced, maxc, two_ok, blocks,
                          (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz),
                          prof ? dev_field(ctl, offsetof(CcCtl, level_clock)) : nullptr, s));
     mark(3);
@@ -346,19 +365,25 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     done[0] = 0u;
     done[1] = 0u;
     done[2] = 0u;
-    for (int step = 0; step < n - 2 && e == hipSuccess; ++step, ++levels) {
-      if (step >= kLevelsAhead) {
+    // Launch 0 runs the leading small steps on one block; each later launch
+    // runs one step, so n - 2 of them are enough.
+    mark(2);
+    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, maxc, two_ok, g->d_done, s));
+    mark(3);
+    ++levels;
+    for (int launch = 1; launch < n - 1 && e == hipSuccess; ++launch, ++levels) {
+      if (launch >= kLevelsAhead) {
         const auto t_wait = std::chrono::steady_clock::now();
-        while (done[0] == 0u && (int)done[1] < step - kLevelsAhead + 1 &&
+        while (done[0] == 0u && (int)done[1] < launch - kLevelsAhead + 1 &&
                std::chrono::steady_clock::now() - t_wait <
                    std::chrono::microseconds(kAheadWaitUs)) {
         }
       }
       if (done[0] != 0u) break;
-      mark(2 + 2 * step);
-      chk(cc_launch_step(W, en, gd, ctl, lb, ro.out, step, forced, maxc, two_ok, bfs_blocks,
+      mark(2 + 2 * launch);
+      chk(cc_launch_step(W, en, gd, ctl, lb, out, launch, forced, maxc, two_ok, bfs_blocks,
                          g->d_done, s));
-      mark(3 + 2 * step);
+      mark(3 + 2 * launch);
     }
   }
   // Depth-first continuation.  Each of its kernels returns at once if the
@@ -372,29 +397,32 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     // nothing to continue
   } else if (!en) {
     chk(cc_launch_dfs_prepare(ctl, wc, n, false, s));
-    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, ro.out,
+    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, out,
                       dev_field(ctl, offsetof(CcCtl, hist_sh)), CC_HSLOTS, true, dfs_blocks_c,
                       idle_timeout, s));
   } else {
     chk(cc_launch_dfs_prepare(ctl, wc, n, false, s));
-    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, ro.out,
+    chk(cc_launch_dfs(W, false, gd, ctl, f[0], f[1], wc, out,
                       dev_field(ctl, offsetof(CcCtl, dfs_hist)), 0, true, dfs_blocks_c,
                       idle_timeout, s));
     chk(cc_launch_dfs_prepare(ctl, we, n, true, s));
-    chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we, ro.out, nullptr, 0, false,
+    chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we, out, nullptr, 0, false,
                       dfs_blocks_e, idle_timeout, s));
   }
   mark(2 * n + 3);
-  chk(cc_launch_finalize(ctl, ro.out, n, en, s));
+  chk(cc_launch_finalize(ctl, out, n, en, s));
   chk(hipEventRecord(g->ev1, s));
   // Read back the unsharded tail of the control block (everything for
   // profiling runs, which also report per-level traffic).
   const size_t tail = prof ? 0 : offsetof(CcCtl, hist);
   chk(hipMemcpyAsync((char *)g->h_ctl + tail, (char *)ctl + tail, sizeof(CcCtl) - tail,
                      hipMemcpyDeviceToHost, s));
-  chk(hipFreeAsync(arena, s));
+  if (!host_out) chk(hipFreeAsync(arena, s));
   chk(hipStreamSynchronize(s));
-  if (e != hipSuccess) return hip_err(e);
+  if (e != hipSuccess) {
+    if (host_out) (void)hipFreeAsync(arena, s);
+    return hip_err(e);
+  }
 
   const CcCtl &h = *g->h_ctl;
   std::memset(g->hist, 0, sizeof(g->hist));
@@ -413,7 +441,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   g->info.peak_frontier = (int64_t)h.peak;
   g->info.switch_level = h.mode ? h.switch_level : 0;
   g->info.levels_launched = persistent ? 1 : levels;
-  if (persistent) levels = h.levels_run;
+  const int launches = levels;
+  levels = std::min(std::max(h.levels_run, 0), CC_HSLOTS - 1);  // steps run
   g->info.gpu_ms = ms;
   g->info.stage1_ms = g->info.level_ms = g->info.dfs_ms = 0.0;
   g->info.level_bytes = 0;
@@ -425,7 +454,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     };
     g->info.stage1_ms = span(0, 1);
     // per-step device time, credited to the length t the step expanded
-    // (CcCtl::step_level); a two-level step's time goes to its t
+    // (CcCtl::step_level); a two-level step's time goes to its t, and a
+    // launch that ran several small steps is credited to its first
     const int steps = levels;
     auto step_t = [&](int st) { return st < CC_HSLOTS ? h.step_level[st] : 0; };
     if (persistent) {
@@ -437,10 +467,11 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
                            (double)g->dev.clock_hz;
       }
     } else {
-      for (int st = 0; st < steps; ++st) {
-        const double ms_s = span(2 + 2 * st, 3 + 2 * st);
+      for (int li = 0; li < launches; ++li) {
+        const double ms_s = span(2 + 2 * li, 3 + 2 * li);
         g->info.level_ms += ms_s;
-        const int t = step_t(st);
+        const int first = li == 0 ? 0 : (li < CC_HSLOTS ? h.launch_step[li] - 1 : -1);
+        const int t = first >= 0 ? step_t(first) : 0;
         if (t >= 3 && t < CC_HSLOTS) g->level_ms[t] += ms_s;
       }
     }
@@ -473,9 +504,25 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   }
   g->have_run = true;
   g->info.device_diag = (int64_t)h.diag;
-  if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST | CC_DEV_BARRIER_TIMEOUT)) return CC_ERR_INTERNAL;
-  if (h.status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
-  return CC_OK;
+  cc_status st = CC_OK;
+  if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST | CC_DEV_BARRIER_TIMEOUT))
+    st = CC_ERR_INTERNAL;
+  else if (h.status & CC_DEV_STACK_FULL)
+    st = CC_ERR_OUT_OF_MEMORY;
+  if (host_out) {
+    int64_t nv = 0;
+    for (int k = 0; k <= n; ++k) nv += g->hist[k] * k;
+    if (st == CC_OK && cycles <= out.cyc_cap && nv <= out.verts_cap) {
+      if (hipMemcpyAsync(ro.host_verts, out.verts, (size_t)nv * 4, hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipMemcpyAsync(ro.host_offsets, out.offs, (size_t)(cycles + 1) * 8,
+                         hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = CC_ERR_DEVICE;
+    }
+    if (hipFreeAsync(arena, s) != hipSuccess && st == CC_OK) st = CC_ERR_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess && st == CC_OK) st = CC_ERR_DEVICE;
+  }
+  return st;
 }
 
 cc_status check_handle(cc_graph *g) {
@@ -681,37 +728,34 @@ cc_status cc_enumerate(cc_graph *g, int32_t *verts, int64_t verts_cap, int64_t *
     if (*n_cycles > cycles_cap || *n_verts > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
     return CC_OK;
   }
-  // Host buffers: count first to size exact device buffers, then enumerate
-  // into them and copy back.
-  st = run_counts(g);
-  if (st != CC_OK) return st;
-  int64_t c = 0, v = 0;
-  totals(&c, &v);
-  *n_cycles = c;
-  *n_verts = v;
-  if (c > cycles_cap || v > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
-  void *dv = nullptr, *doff = nullptr;
-  hipStream_t s = g->stream;
-  if (hipMallocAsync(&dv, (size_t)std::max<int64_t>(v, 1) * 4, s) != hipSuccess)
-    return CC_ERR_OUT_OF_MEMORY;
-  if (hipMallocAsync(&doff, (size_t)(c + 1) * 8, s) != hipSuccess) {
-    (void)hipFreeAsync(dv, s);
-    (void)hipStreamSynchronize(s);
-    return CC_ERR_OUT_OF_MEMORY;
-  }
+  // Host buffers: the run writes into device staging of the caller's
+  // capacities, carved from its own workspace, and copies back what it
+  // wrote.  Capacities beyond kHostStageBytes are sized exactly by a
+  // counting run first.
   RunOut ro;
   ro.enumerate = true;
-  ro.out = OutDev{(int *)dv, (long long *)doff, v, c};
-  st = run_device(g, ro);
-  if (st == CC_OK) {
-    if (hipMemcpyAsync(verts, dv, (size_t)v * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(offsets, doff, (size_t)(c + 1) * 8, hipMemcpyDeviceToHost, s) != hipSuccess)
-      st = CC_ERR_DEVICE;
+  ro.host_verts = verts;
+  ro.host_offsets = offsets;
+  const double want = (double)verts_cap * 4 + ((double)cycles_cap + 1) * 8;
+  if (want <= (double)kHostStageBytes) {
+    ro.out = OutDev{nullptr, nullptr, verts_cap, cycles_cap};
+  } else {
+    st = run_counts(g);
+    if (st != CC_OK) return st;
+    int64_t c = 0, v = 0;
+    totals(&c, &v);
+    if (c > cycles_cap || v > verts_cap) {
+      *n_cycles = c;
+      *n_verts = v;
+      return CC_ERR_BUFFER_TOO_SMALL;
+    }
+    ro.out = OutDev{nullptr, nullptr, v, c};
   }
-  (void)hipFreeAsync(dv, s);
-  (void)hipFreeAsync(doff, s);
-  if (hipStreamSynchronize(s) != hipSuccess && st == CC_OK) st = CC_ERR_DEVICE;
-  return st;
+  st = run_device(g, ro);
+  if (st != CC_OK) return st;
+  totals(n_cycles, n_verts);
+  if (*n_cycles > cycles_cap || *n_verts > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
+  return CC_OK;
 }
 
 cc_status cc_labels(cc_graph *g, int32_t *labels) {

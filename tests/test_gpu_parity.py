@@ -156,6 +156,21 @@ def test_host_output_buffers(cc):
     with cc.prepare(g, output_device=False) as h:
         v, o = h.enumerate()
         assert_same_cycles(v, o, ores)
+        # room to spare: one pass, exact sizes returned, the rest untouched
+        vb = np.full(ores.n_verts + 1000, -7, np.int32)
+        ob = np.full(ores.n_cycles + 50, -7, np.int64)
+        nc, nv = h.enumerate_into(vb, ob)
+        assert (nc, nv) == (ores.n_cycles, ores.n_verts)
+        assert_same_cycles(vb[:nv], ob[:nc + 1], ores)
+        assert np.all(vb[nv:] == -7) and np.all(ob[nc + 1:] == -7)
+        # too small: the required sizes come back, nothing is written
+        vs = np.full(10, -7, np.int32)
+        os_ = np.full(3, -7, np.int64)
+        with pytest.raises(cc.CCError) as ei:
+            h.enumerate_into(vs, os_)
+        assert ei.value.status == cc.CC_ERR_BUFFER_TOO_SMALL
+        assert ei.value.required == (ores.n_cycles, ores.n_verts)
+        assert np.all(vs == -7) and np.all(os_ == -7)
 
 
 def test_buffer_too_small_reports_sizes(cc):

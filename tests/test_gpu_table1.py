@@ -1,0 +1,69 @@
+"""Table 1's structured graphs on the HIP path (through the C ABI).
+
+The counts are the paper's printed values (Section 5, Table 1): C3 must equal
+the histogram's length-3 entry and #clc the sum over lengths above three.
+Rows small enough to store are also enumerated; the output must be in
+canonical form, ordered by length, free of duplicates and agree with the
+histogram, and a seeded sample of the cycles is checked to be chordless
+cycles of the graph.  Grid 8x10 is count-only, as in the paper."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from ccutil import adjacency_sets, canonical_groups, is_canonical_array, is_chordless_cycle
+from paper_1410_4876_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+ROWS = json.load(open(os.path.join(GOLDEN, "table1.json")))["rows"]
+
+
+@pytest.fixture(scope="module")
+def cc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a gfx950 device"
+    from paper_1410_4876_amd import cc as mod
+    mod.lib()
+    return mod
+
+
+@pytest.mark.parametrize("row", ROWS, ids=lambda r: r["name"])
+def test_table1_counts(cc, row):
+    g = getattr(gg, row["family"])(*row["args"])
+    assert (g.n, g.m, g.max_degree) == (row["n"], row["m"], row["delta"])
+    for perm_seed in (None, 7):
+        gp = g if perm_seed is None else gg.permute_random(g, np.random.default_rng(perm_seed))
+        with cc.prepare(gp) as h:
+            hist = h.histogram()
+        assert int(hist[3]) == row["c3"], (row["name"], perm_seed)
+        assert int(hist[4:].sum()) == row["clc"], (row["name"], perm_seed)
+
+
+@pytest.mark.parametrize("row", [r for r in ROWS if not r["count_only"] and r["clc"] <= 2_000_000],
+                         ids=lambda r: r["name"])
+def test_table1_enumeration(cc, row):
+    import torch
+    g = getattr(gg, row["family"])(*row["args"])
+    g = gg.permute_random(g, np.random.default_rng(11))
+    with cc.prepare(g) as h:
+        hist = h.histogram()
+        verts, offs = h.enumerate()
+        torch.cuda.synchronize()
+    v = verts.cpu().numpy()
+    o = offs.cpu().numpy()
+    assert o.size - 1 == row["c3"] + row["clc"]
+    assert is_canonical_array(v, o)
+    assert np.all(np.diff(np.diff(o)) >= 0), "output not ordered by length"
+    groups = canonical_groups(v, o)
+    for k, a in groups.items():
+        assert a.shape[0] == hist[k], k
+        if a.shape[0] > 1:
+            assert not np.any(np.all(a[1:] == a[:-1], axis=1)), "duplicate cycle"
+    adj = adjacency_sets(g.n, g.row_ptr, g.col_idx)
+    n_cyc = o.size - 1
+    pick = np.random.default_rng(5).choice(n_cyc, size=min(n_cyc, 3000), replace=False)
+    for i in pick:
+        cyc = v[o[i]:o[i + 1]].tolist()
+        assert is_chordless_cycle(cyc, adj), cyc
