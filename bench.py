@@ -297,8 +297,10 @@ def main():
                                        "the timed steps"}
         out["breakdown_ms"] = {
             "stage1": round(sum(i["stage1_ms"] for i in pinfos) / len(pinfos), 4),
+            "head": round(sum(i["head_ms"] for i in pinfos) / len(pinfos), 4),
             "levels": round(lvl_ms / len(pinfos), 4),
             "dfs": round(sum(i["dfs_ms"] for i in pinfos) / len(pinfos), 4)}
+        out["head_steps"] = pinfos[-1]["head_steps"]
         # the same step with all levels in one cooperative launch, for comparison
         for _ in range(2):
             step(False, persistent_levels=True)

@@ -95,15 +95,21 @@ typedef struct cc_run_info {
   int64_t paths;             /* open chordless paths expanded (sum over lengths)     */
   int64_t peak_frontier;     /* largest level frontier held in breadth-first mode     */
   int32_t switch_level;      /* path length handed to the depth-first kernel, 0=none */
-  int32_t levels_launched;   /* breadth-first level kernels launched                 */
+  int32_t levels_launched;   /* full-grid breadth-first step launches (1 for the
+                                cooperative loop of CC_LEVEL_PERSISTENT)            */
   double gpu_ms;             /* device time of the call, HIP events around its work  */
   /* With CC_PROFILE only (else 0): device time of each part of the run.       */
   double stage1_ms;          /* initial triplets and triangles                       */
-  double level_ms;           /* all breadth-first level kernels                      */
+  double level_ms;           /* the full-grid breadth-first step launches            */
   double dfs_ms;             /* depth-first kernels and their preparation            */
-  int64_t level_bytes;       /* frontier and output bytes the level kernels must move */
+  int64_t level_bytes;       /* frontier and output bytes those launches must move    */
   int64_t device_diag;       /* after CC_ERR_INTERNAL: which check failed (kind << 24 |
                                 low 24 bits of the offending value), else 0          */
+  int32_t head_steps;        /* leading small steps run on one block before the
+                                full-grid launches (not with CC_LEVEL_PERSISTENT)    */
+  int32_t reserved;
+  double head_ms;            /* CC_PROFILE: device time of those leading steps       */
+  int64_t head_bytes;        /* CC_PROFILE: bytes those leading steps must move      */
 } cc_run_info;
 
 /*

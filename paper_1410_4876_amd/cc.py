@@ -70,7 +70,11 @@ class RunInfo(ctypes.Structure):
                 ("level_ms", ctypes.c_double),
                 ("dfs_ms", ctypes.c_double),
                 ("level_bytes", ctypes.c_int64),
-                ("device_diag", ctypes.c_int64)]
+                ("device_diag", ctypes.c_int64),
+                ("head_steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("head_ms", ctypes.c_double),
+                ("head_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

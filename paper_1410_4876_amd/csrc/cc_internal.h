@@ -92,7 +92,7 @@ struct CcCtl {
   unsigned int diag;                        // first failed consistency check, CC_DIAG_*
   unsigned int status;                      // CC_DEV_* bits
   int bfs_max_len;                          // longest cycle length final after the levels
-  int pad;
+  int head_steps;                           // steps run by the one-block head kernel
 };
 
 // Frontier of open paths, structure of arrays, CC_SHARDS shards of cap_s

@@ -1088,6 +1088,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_head(GraphDev g, CcCtl *ctl, Level
     const int next = over ? step + 1 : step;
     ctl->launch_step[1] = over ? 0 : next + 1;
     ctl->levels_run = next;
+    ctl->head_steps = next;
     if ((r == CC_LEVEL_EMPTY || r == CC_LEVEL_SWITCH) && host_done) {
       if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
       st_system(host_done, 1u);

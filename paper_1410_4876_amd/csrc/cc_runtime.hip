@@ -440,12 +440,15 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   g->info.paths = paths;
   g->info.peak_frontier = (int64_t)h.peak;
   g->info.switch_level = h.mode ? h.switch_level : 0;
-  g->info.levels_launched = persistent ? 1 : levels;
+  // launch 0 of the launched loop is the one-block head kernel
+  g->info.levels_launched = persistent ? 1 : std::max(levels - 1, 0);
   const int launches = levels;
+  const int head_steps = persistent ? 0 : std::max(h.head_steps, 0);
   levels = std::min(std::max(h.levels_run, 0), CC_HSLOTS - 1);  // steps run
+  g->info.head_steps = head_steps;
   g->info.gpu_ms = ms;
-  g->info.stage1_ms = g->info.level_ms = g->info.dfs_ms = 0.0;
-  g->info.level_bytes = 0;
+  g->info.stage1_ms = g->info.level_ms = g->info.dfs_ms = g->info.head_ms = 0.0;
+  g->info.level_bytes = g->info.head_bytes = 0;
   if (prof) {
     auto span = [&](int a, int b) {
       float x = 0.f;
@@ -469,7 +472,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     } else {
       for (int li = 0; li < launches; ++li) {
         const double ms_s = span(2 + 2 * li, 3 + 2 * li);
-        g->info.level_ms += ms_s;
+        (li == 0 ? g->info.head_ms : g->info.level_ms) += ms_s;
         const int first = li == 0 ? 0 : (li < CC_HSLOTS ? h.launch_step[li] - 1 : -1);
         const int t = first >= 0 ? step_t(first) : 0;
         if (t >= 3 && t < CC_HSLOTS) g->level_ms[t] += ms_s;
@@ -488,19 +491,18 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       return (int64_t)c;
     };
     const int last_len = h.mode ? h.bfs_max_len : n;
-    int64_t bytes = 0;
     for (int st = 0; st < steps; ++st) {
       const int t = step_t(st);
       if (t < 3 || t > n) continue;
       const int tn = (st + 1 < steps && st + 1 < CC_HSLOTS) ? step_t(st + 1) : t + 1;
       if (tn <= t) continue;
-      bytes += level_count(t) * pp;
+      int64_t bytes = level_count(t) * pp;
       if (tn <= n && st + 1 < steps) bytes += level_count(tn) * pp;
       if (en)
         for (int k = t + 1; k <= tn && k <= n && k <= last_len; ++k)
           bytes += (int64_t)h.hist[k] * (16 * W + 4 * k + 8);
+      (st < head_steps ? g->info.head_bytes : g->info.level_bytes) += bytes;
     }
-    g->info.level_bytes = bytes;
   }
   g->have_run = true;
   g->info.device_diag = (int64_t)h.diag;

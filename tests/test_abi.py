@@ -54,16 +54,18 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_1410_4876_amd import cc
     src = tmp_path / "layout.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "cc.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cc_options),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cc_options),'
                    ' offsetof(cc_options, frontier_budget_bytes), offsetof(cc_options, flags),'
                    ' offsetof(cc_options, bfs_blocks), sizeof(cc_run_info),'
-                   ' offsetof(cc_run_info, switch_level), offsetof(cc_run_info, gpu_ms));return 0;}\n')
+                   ' offsetof(cc_run_info, switch_level), offsetof(cc_run_info, gpu_ms),'
+                   ' offsetof(cc_run_info, head_steps), offsetof(cc_run_info, head_bytes));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = list(map(int, subprocess.check_output([str(exe)]).split()))
     want = [ctypes.sizeof(cc.Options), cc.Options.frontier_budget_bytes.offset,
             cc.Options.flags.offset, cc.Options.bfs_blocks.offset, ctypes.sizeof(cc.RunInfo),
-            cc.RunInfo.switch_level.offset, cc.RunInfo.gpu_ms.offset]
+            cc.RunInfo.switch_level.offset, cc.RunInfo.gpu_ms.offset,
+            cc.RunInfo.head_steps.offset, cc.RunInfo.head_bytes.offset]
     assert got == want
 
 
