@@ -26,6 +26,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 PROFILE = os.path.join(ROOT, "profiles", "k_step_grid8x8_enumerate.md")
 KERNELS = os.path.join(ROOT, "paper_1410_4876_amd", "csrc", "cc_kernels.hip")
 TABLE1 = os.path.join(ROOT, "tests", "golden", "table1.json")
+GRID7X12 = os.path.join(ROOT, "tests", "golden", "grid7x12.json")
 
 
 def counted_traffic():
@@ -159,6 +160,101 @@ def table1_section(args):
     return {"rows": out, "counts_equal_table1": True}
 
 
+def _timed(fn, warmup=3, runs=10):
+    """Median and mean wall ms of `runs` calls after `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return {"median": round(float(np.median(ts)), 4), "mean": round(float(np.mean(ts)), 4)}
+
+
+def er40_section():
+    """ER G(40, 100), full enumeration: a latency-bound call.  proc: CSR on
+    the device, results into device buffers; total: CSR from host memory,
+    results copied into host buffers."""
+    import torch
+
+    from paper_1410_4876_amd import cc
+    from paper_1410_4876_amd import graphgen as gg
+
+    g = gg.workload_er40()
+    rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
+    with cc.Graph(g.n, rp, ci) as h:
+        hist = h.histogram()
+    nc = int(hist.sum())
+    nv = int((hist * np.arange(hist.size)).sum())
+    dv = torch.empty(max(nv, 1), dtype=torch.int32, device="cuda")
+    do = torch.empty(nc + 1, dtype=torch.int64, device="cuda")
+    hv = np.empty(max(nv, 1), np.int32)
+    ho = np.empty(nc + 1, np.int64)
+
+    def proc():
+        with cc.Graph(g.n, rp, ci) as h:
+            h.enumerate_into(dv, do)
+        torch.cuda.synchronize()
+
+    def total():
+        with cc.Graph(g.n, g.row_ptr, g.col_idx, output_device=False) as h:
+            h.enumerate_into(hv, ho)
+
+    p = _timed(proc)
+    return {"workload": "ER G(40,100), seed index 1, full enumeration", "cycles": nc,
+            "proc_ms": p, "total_ms": _timed(total),
+            "cycles_per_s": round(nc / (p["median"] * 1e-3), 1)}
+
+
+def grid7x12_section():
+    """7x12 grid (n=84, m=149), ids permuted, count-only with an int64
+    per-length histogram and a 4 GiB frontier budget: the levels hand over
+    to the depth-first kernel.  The histogram must equal the stored oracle
+    output.  Reports the switch, the peak frontier, and each phase."""
+    import torch
+
+    from paper_1410_4876_amd import cc
+    from paper_1410_4876_amd import graphgen as gg
+
+    gold = json.load(open(GRID7X12))
+    g = gg.workload_grid7x12()
+    rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
+    budget = 4 << 30
+
+    def run(profile=False):
+        with cc.Graph(g.n, rp, ci, budget_bytes=budget, profile=profile) as h:
+            hist = h.histogram()
+            return hist, h.frontier(), h.last_run()
+
+    hist, front, _ = run()
+    assert hist.tolist() == gold["hist"] and front.tolist() == gold["front"]
+    t = _timed(lambda: run())
+    _, _, info = run(profile=True)
+    cycles, paths = int(hist.sum()), int(front.sum())
+    lvl = info["level_ms"] + info["head_ms"]
+    lvl_bytes = info["level_bytes"] + info["head_bytes"]
+    w_bytes = 8 * 2 + 2  # W=2 words of X plus the two end labels, per path
+    return {"workload": "grid 7x12 (n=84, m=149), ids permuted, count-only, 4 GiB frontier budget",
+            "cycles": cycles, "paths_expanded": paths, "ms": t,
+            "cycles_per_s": round(cycles / (t["median"] * 1e-3), 1),
+            "paths_per_s": round(paths / (t["median"] * 1e-3), 1),
+            "switch_level": info["switch_level"],
+            "peak_frontier_paths": info["peak_frontier"],
+            "peak_frontier_bytes": info["peak_frontier"] * w_bytes,
+            "breadth_first": {"ms": round(lvl, 4), "bytes": lvl_bytes,
+                              "GBps": round(lvl_bytes / (lvl * 1e-3) / 1e9, 1) if lvl > 0 else 0.0,
+                              "hbm_frac": round(lvl_bytes / (lvl * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                              if lvl > 0 else 0.0},
+            "depth_first": {"ms": round(info["dfs_ms"], 4),
+                            "paths_per_s": round(
+                                (paths - int(front[:info["switch_level"]].sum()))
+                                / (info["dfs_ms"] * 1e-3), 1) if info["dfs_ms"] > 0 else 0.0},
+            "stage1_ms": round(info["stage1_ms"], 4)}
+
+
 def serving_section(args):
     """Open-loop Poisson request stream (2000 requests/s; half p x q grids,
     p, q in 3..7, half ER graphs, n in 20..80, d in [3, 5]) replayed against
@@ -193,6 +289,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the structured graphs of the paper's Table 1")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the ER G(40,100) latency and 7x12 count-only sections")
     ap.add_argument("--no-profile", action="store_true",
                     help="time steps without per-kernel HIP events (no roofline)")
     args = ap.parse_args()
@@ -315,6 +413,9 @@ def main():
         out["batched"] = batched_section(args)
     if not args.no_serve:
         out["serving"] = serving_section(args)
+    if not args.no_extra:
+        out["er40"] = er40_section()
+        out["grid7x12"] = grid7x12_section()
     if not args.no_table1:
         out["table1"] = table1_section(args)
     if not args.no_cpu_baseline:

@@ -142,6 +142,20 @@ __device__ __forceinline__ unsigned int wave_min_u32(unsigned int v) {
 __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v) {
   return __shfl(v, 0, CC_WAVE);
 }
+// A value every lane of the wavefront holds, moved to scalar registers.
+__device__ __forceinline__ unsigned uni_u32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ unsigned long long uni_u64(unsigned long long v) {
+  return (unsigned long long)uni_u32((unsigned)v) |
+         ((unsigned long long)uni_u32((unsigned)(v >> 32)) << 32);
+}
+// Room left in a shard of cap_s slots after `base` of them are taken,
+// clamped to 32 bits (a wavefront writes fewer than 2^32 per step).
+__device__ __forceinline__ unsigned room_after(unsigned long long base, unsigned long long cap_s) {
+  const unsigned long long r = base < cap_s ? cap_s - base : 0ull;
+  return r > 0xffffffffull ? 0xffffffffu : (unsigned)r;
+}
 
 template <typename T>
 __device__ __forceinline__ T ld_acquire(T *p) {
@@ -639,6 +653,12 @@ __device__ __forceinline__ void reserve(LevelLds<W, ENUM> &L, unsigned a, unsign
     baseB += L.WaveB[w];
     baseC += L.WaveC[w];
   }
+  baseA = uni_u64(baseA);
+  baseB = uni_u64(baseB);
+  baseC = uni_u64(baseC);
+  wa = uni_u32(wa);
+  wb = uni_u32(wb);
+  wc = uni_u32(wc);
 }
 
 // Orders this wavefront's LDS accesses before and after (a wavefront's LDS
@@ -938,8 +958,16 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
       acc2 += cc;
     }
     // ---- write the paths (extensions, or grandchildren)
+    // Each output range is addressed from a wavefront-uniform pointer to its
+    // first slot in shard osh plus a 32-bit rank; ranks at or beyond the
+    // shard's room are dropped (the next step sees the overflow).
     if (wa) {
-      unsigned long long off = 0;
+      const unsigned long long b0 = min(baseA, fout.cap_s);
+      const unsigned room = room_after(baseA, fout.cap_s);
+      unsigned long long *const Xo = fout.X + (unsigned long long)osh * fout.cap_s + b0;
+      unsigned long long *const So = fout.S + (unsigned long long)osh * fout.cap_s + b0;
+      unsigned short *const Vo = fout.vv + (unsigned long long)osh * fout.cap_s + b0;
+      unsigned off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
         const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
@@ -962,27 +990,29 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
           if (!mask) break;
           if (has) {
             const int v = bpop_lowest(cur);
-            const unsigned long long slot = baseA + off + lanes_below(mask);
-            if (slot < fout.cap_s) {
-              const unsigned long long o = (unsigned long long)osh * fout.cap_s + slot;
+            const unsigned r = off + lanes_below(mask);
+            if (r < room) {
 #pragma unroll
-              for (int w = 0; w < W; ++w) fout.X[w * fout.cap + o] = Xg.w[w];
+              for (int w = 0; w < W; ++w) Xo[w * fout.cap + r] = Xg.w[w];
               if (ENUM) {
                 Bits<W> Sn = bor(Sv[j], bsingle<W>(L.Perm[v]));
                 if (two) Sn = bor(Sn, bsingle<W>(L.Perm[c]));
 #pragma unroll
-                for (int w = 0; w < W; ++w) fout.S[w * fout.cap + o] = Sn.w[w];
+                for (int w = 0; w < W; ++w) So[w * fout.cap + r] = Sn.w[w];
               }
-              fout.vv[o] = (unsigned short)(v1[j] | (v << 8));
+              Vo[r] = (unsigned short)(v1[j] | (v << 8));
             }
           }
-          off += __popcll(mask);
+          off += (unsigned)__popcll(mask);
         }
       }
     }
     // ---- stage the closures (enumerate mode)
     if (ENUM && wb) {
-      unsigned long long off = 0;
+      const unsigned room = room_after(baseB, sw0.cap_s);
+      unsigned long long *const Co =
+          sw0.C + (unsigned long long)osh * sw0.cap_s + min(baseB, sw0.cap_s);
+      unsigned off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
         const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
@@ -993,20 +1023,22 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
           if (!mask) break;
           if (has) {
             const int v = bpop_lowest(cl);
-            const unsigned long long slot = baseB + off + lanes_below(mask);
-            if (slot < sw0.cap_s) {
-              const unsigned long long o = (unsigned long long)osh * sw0.cap_s + slot;
+            const unsigned r = off + lanes_below(mask);
+            if (r < room) {
               const Bits<W> C = bor(Sv[j], bsingle<W>(L.Perm[v]));
 #pragma unroll
-              for (int w = 0; w < W; ++w) sw0.C[w * sw0.cap + o] = C.w[w];
+              for (int w = 0; w < W; ++w) Co[w * sw0.cap + r] = C.w[w];
             }
           }
-          off += __popcll(mask);
+          off += (unsigned)__popcll(mask);
         }
       }
     }
     if (ENUM && wc) {
-      unsigned long long off = 0;
+      const unsigned room = room_after(baseC, sw1.cap_s);
+      unsigned long long *const Co =
+          sw1.C + (unsigned long long)osh * sw1.cap_s + min(baseC, sw1.cap_s);
+      unsigned off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
         const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
@@ -1024,16 +1056,15 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
           if (!mask) break;
           if (has) {
             const int v = bpop_lowest(cur);
-            const unsigned long long slot = baseC + off + lanes_below(mask);
-            if (slot < sw1.cap_s) {
-              const unsigned long long o = (unsigned long long)osh * sw1.cap_s + slot;
+            const unsigned r = off + lanes_below(mask);
+            if (r < room) {
               const Bits<W> C =
                   bor(bor(Sv[j], bsingle<W>(L.Perm[c])), bsingle<W>(L.Perm[v]));
 #pragma unroll
-              for (int w = 0; w < W; ++w) sw1.C[w * sw1.cap + o] = C.w[w];
+              for (int w = 0; w < W; ++w) Co[w * sw1.cap + r] = C.w[w];
             }
           }
-          off += __popcll(mask);
+          off += (unsigned)__popcll(mask);
         }
       }
     }
