@@ -291,6 +291,8 @@ def main():
                     help="skip the structured graphs of the paper's Table 1")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the ER G(40,100) latency and 7x12 count-only sections")
+    ap.add_argument("--section", choices=["er40", "grid7x12", "table1", "batched", "serving"],
+                    help="run only this section and print its JSON (for profiling one workload)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time steps without per-kernel HIP events (no roofline)")
     args = ap.parse_args()
@@ -306,6 +308,12 @@ def main():
     from paper_1410_4876_amd import graphgen as gg
 
     torch.cuda.set_device(0)
+    if args.section:
+        fn = {"er40": er40_section, "grid7x12": grid7x12_section,
+              "table1": lambda: table1_section(args), "batched": lambda: batched_section(args),
+              "serving": lambda: serving_section(args)}[args.section]
+        print(json.dumps({args.section: fn()}), flush=True)
+        return
     if args.calibrate_copy:
         # A plain copy of known size: what the HBM byte counters read for it
         # scales the counters read for the level kernel.
