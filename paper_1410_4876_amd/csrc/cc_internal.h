@@ -12,8 +12,7 @@
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk
 #define CC_LEVEL_IPT 4            // paths per lane per chunk in the level kernel
 #define CC_DEC_WORDS 1536         // per-wavefront LDS words for decoded cycles (enumerate steps)
-#define CC_DEEP_PATHS 2048        // leading steps on one block: at most this many paths
-#define CC_DEEP_CYCLES 1024       // and at most this many staged cycles to decode
+#define CC_HEAD_THREADS 1024      // threads of the one-block head kernel
 #define CC_ROOT_CLAIM 1024        // handed-over paths a depth-first wavefront claims at once
 // Frontier and staged-cycle counters are split into CC_SHARDS shards, each
 // on its own cache lines: a block appends to shard blockIdx % CC_SHARDS, so
@@ -205,13 +204,15 @@ hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_
 // to stage st (pair 0, slot 0); sets the state of step 0.
 hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
                               Stage st, hipStream_t s);
-// The leading small steps of the breadth-first loop on one block (launch 0
-// for host_done); records the step the launches start at.  max_children
-// bounds the extensions of one path (max degree - 1); two allows two-level
-// steps.
+// Stage one and the leading levels of the breadth-first loop on one block
+// with the frontier in LDS (launch 0 for host_done), while a level's paths
+// fit in lds_bytes of dynamic shared memory (two buffers); records the step
+// the launches start at.  Replaces cc_launch_triplets in the launched loop.
 hipError_t cc_launch_head(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                          OutDev out, int forced_level, int max_children, bool two,
+                          OutDev out, int forced_level, size_t lds_bytes,
                           unsigned int *host_done, hipStream_t s);
+int cc_head_capacity(int W, bool enumerate, size_t lds_bytes);
+size_t cc_head_static_lds(int W, bool enumerate);
 // Launch `launch` (>= 1) of the breadth-first loop: one step on `blocks`
 // blocks, the one recorded by the previous launch.  host_done (pinned host
 // memory, may be NULL): host_done[0] receives launch + 1 once the loop is

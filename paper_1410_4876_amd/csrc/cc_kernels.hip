@@ -14,6 +14,8 @@
 // X' = X | N(vt), S' = S | {v} (Algorithm 1, the three cases of its loop).
 // The path-extension property of Section 2 guarantees there is no other
 // case.
+#include <atomic>
+
 #include "cc_internal.h"
 
 namespace {
@@ -409,22 +411,17 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
 // neighbours y of u above x.  Results are numbered with LDS counters and
 // dealt round-robin over the shards (item j -> shard j % CC_SHARDS, slot
 // j / CC_SHARDS), so every shard gets the same share.
-template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, Frontier f,
-                                                       Stage st) {
-  __shared__ unsigned long long sN[CC_MAXN * W];
-  __shared__ int sPerm[CC_MAXN];
-  __shared__ unsigned int sTrip, sTri;
+// Stage one on a block of T threads, with the graph already in LDS (sN,
+// sPerm) and *sTrip = *sTri = 0 before the call.  Writes the triplets to f
+// and, enumerating, the triangles to st; sets the counters and the state of
+// step 0.  Ends with a barrier; *sTrip and *sTri then hold the totals.
+template <int W, bool ENUM, int T>
+__device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, const Stage &st,
+                              const unsigned long long *sN, const int *sPerm,
+                              unsigned int *sTrip, unsigned int *sTri) {
   const int n = g.n;
   const int tid = threadIdx.x;
-  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
-  for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
-  if (tid == 0) {
-    sTrip = 0u;
-    sTri = 0u;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < n * n; idx += CC_BLOCK) {
+  for (int idx = tid; idx < n * n; idx += T) {
     const int u = idx / n, x = idx - u * n;
     const Bits<W> nu = row<W>(sN, u);
     if (x <= u || !btest(nu, x)) continue;
@@ -433,7 +430,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
     while (bany(ys)) {
       const int y = bpop_lowest(ys);
       if (btest(nx, y)) {
-        const unsigned j = atomicAdd(&sTri, 1u);
+        const unsigned j = atomicAdd(sTri, 1u);
         if (ENUM) {
           const unsigned long long slot = (j % CC_SHARDS) * st.cap_s + j / CC_SHARDS;
           if (j / CC_SHARDS < st.cap_s) {
@@ -444,7 +441,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
           }
         }
       } else {
-        const unsigned j = atomicAdd(&sTrip, 1u);
+        const unsigned j = atomicAdd(sTrip, 1u);
         if (j / CC_SHARDS < f.cap_s) {
           const unsigned long long slot = (j % CC_SHARDS) * f.cap_s + j / CC_SHARDS;
           const Bits<W> X = bor(nu, low_through<W>(u));
@@ -462,10 +459,11 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
     }
   }
   __syncthreads();
+  const unsigned trip = *sTrip, tri = *sTri;
   if (tid < CC_SHARDS) {
     const unsigned s = tid;
-    ctl->count_sh[s][3] = sTrip > s ? (sTrip - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
-    ctl->hist_sh[s][3] = sTri > s ? (sTri - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
+    ctl->count_sh[s][3] = trip > s ? (trip - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
+    ctl->hist_sh[s][3] = tri > s ? (tri - s + CC_SHARDS - 1) / CC_SHARDS : 0u;
   }
   if (tid == 0) {
     // step 0 expands the triplets (frontier buffer 1) and, enumerating,
@@ -477,11 +475,27 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
     S.slen0 = ENUM ? 3 : 0;
     ctl->ss[0] = S;
   }
+  __syncthreads();
 }
 
-// Stage one for a batch: one block per graph, same pairs as k_triplets.
-// Graph g's triplets fill its root slots from root_off[g] in order; the
-// rest of its slots are marked unused; its triangles go to its histogram.
+template <int W, bool ENUM>
+__global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, Frontier f,
+                                                       Stage st) {
+  __shared__ unsigned long long sN[CC_MAXN * W];
+  __shared__ int sPerm[CC_MAXN];
+  __shared__ unsigned int sTrip, sTri;
+  const int n = g.n;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+  for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
+  if (tid == 0) {
+    sTrip = 0u;
+    sTri = 0u;
+  }
+  __syncthreads();
+  triplets_body<W, ENUM, CC_BLOCK>(g, ctl, f, st, sN, sPerm, &sTrip, &sTri);
+}
+
 template <int W>
 __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
   __shared__ unsigned long long sN[CC_MAXN * W];
@@ -578,7 +592,6 @@ struct LevelLds {
 #define CC_LEVEL_NEXT 0      // the step expanded its paths; continue
 #define CC_LEVEL_SWITCH 1    // handed over to the depth-first kernel
 #define CC_LEVEL_EMPTY 2     // no paths left: the loop is over
-#define CC_LEVEL_DEFER 3     // too large for one block: not started (one-block steps)
 
 template <int W, bool ENUM>
 __device__ void load_graph_lds(const GraphDev &g, LevelLds<W, ENUM> &L) {
@@ -727,12 +740,7 @@ __device__ __forceinline__ StepState load_state(CcCtl *ctl, int i) {
 // One step for this block.  Every block of the grid reads the same state
 // and counters and so reaches the same result.  With lds_ready false the
 // graph is loaded into LDS here, together with the counters.
-//
-// ONE: the step runs on a grid of one block (the leading small steps).  A
-// step with more than CC_DEEP_PATHS paths or CC_DEEP_CYCLES staged cycles
-// is then left untouched (CC_LEVEL_DEFER) for the full grid; the block's
-// chunks go to the output shards in turn.
-template <int W, bool ENUM, bool ONE>
+template <int W, bool ENUM>
 __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
                          int step, int forced_level, int maxc, bool allow_two,
                          LevelLds<W, ENUM> &L, bool lds_ready) {
@@ -780,14 +788,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   __syncthreads();
   const int flags = L.Flags | L.FlagsH[0] | L.FlagsH[1];
   const unsigned long long cnt = L.Pre[CC_SHARDS];
-  if (ONE && !flags) {
-    const unsigned long long staged =
-        ENUM ? (S.slen0 ? L.PreH0[CC_SHARDS] : 0ull) + (S.slen1 ? L.PreH1[CC_SHARDS] : 0ull)
-             : 0ull;
-    if (cnt > CC_DEEP_PATHS || staged > CC_DEEP_CYCLES) return CC_LEVEL_DEFER;
-  }
-  const unsigned vblk = ONE ? 0u : blockIdx.x;   // this block's place in the step
-  const unsigned vgrid = ONE ? 1u : gridDim.x;   // blocks taking part
+  const unsigned vblk = blockIdx.x, vgrid = gridDim.x;
   if (blockIdx.x == 0 && tid == 0) {
     if (step < CC_HSLOTS) ctl->step_level[step] = t;
     if (S.prev_two) ctl->front[t - 1] = L.PrevFront;
@@ -796,7 +797,8 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   // ---- decode the cycles the previous step staged (lengths slen0, slen1)
   if (ENUM && S.slen0 && !(flags & 2)) {
     const int k0 = S.slen0, k1 = S.slen1;
-    const unsigned long long h0 = L.PreH0[CC_SHARDS], h1 = k1 ? L.PreH1[CC_SHARDS] : 0ull;
+    const unsigned long long h0 = L.PreH0[ENUM ? CC_SHARDS : 0],
+                             h1 = k1 ? L.PreH1[ENUM ? CC_SHARDS : 0] : 0ull;
     const long long cb0 = (long long)L.Cum[0], vb0 = (long long)L.Cum[1];
     const long long cb1 = cb0 + (long long)h0, vb1 = vb0 + (long long)h0 * k0;
     constexpr int NWB = CC_BLOCK / CC_WAVE;
@@ -870,12 +872,10 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   const int ipt = (int)min((unsigned long long)IPT,
                            max(1ull, (cnt + grid * CC_BLOCK - 1) / (grid * CC_BLOCK)));
   const unsigned long long chunk = (unsigned long long)CC_BLOCK * ipt;
-  // No shard takes the output of more than per_shard input paths: a block
-  // of the grid writes to shard blockIdx mod CC_SHARDS, a lone block's
-  // chunk i to shard i mod CC_SHARDS.
+  // No shard takes the output of more than per_shard input paths (a block
+  // writes to shard blockIdx mod CC_SHARDS).
   const unsigned long long per_shard =
-      ONE ? ((cnt + chunk - 1) / chunk + CC_SHARDS - 1) / CC_SHARDS * chunk
-          : (cnt + grid * chunk - 1) / (grid * chunk) * chunk * ((grid + CC_SHARDS - 1) / CC_SHARDS);
+      (cnt + grid * chunk - 1) / (grid * chunk) * chunk * ((grid + CC_SHARDS - 1) / CC_SHARDS);
   const unsigned long long mc = (unsigned long long)(maxc > 1 ? maxc : 1);
   const bool two = allow_two && t + 2 <= n && t + 1 != forced_level &&
                    per_shard * mc * mc <= fout.cap_s &&
@@ -894,11 +894,9 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   }
   // Blocks without a chunk have nothing more to do in this step.
   if ((unsigned long long)vblk * chunk >= cnt) return CC_LEVEL_NEXT;
-  unsigned long long acc1 = 0, acc2 = 0;  // closures (count mode)
-  unsigned ci = 0;                        // chunks this block has done
-  for (unsigned long long c0 = (unsigned long long)vblk * chunk; c0 < cnt;
-       c0 += grid * chunk, ++ci) {
-    const int osh = ONE ? (int)(ci % CC_SHARDS) : (int)(blockIdx.x % CC_SHARDS);  // output shard
+  const int osh = blockIdx.x % CC_SHARDS;  // this block's output shard
+  unsigned long long acc1 = 0, acc2 = 0;   // closures (count mode)
+  for (unsigned long long c0 = (unsigned long long)vblk * chunk; c0 < cnt; c0 += grid * chunk) {
     Bits<W> X[IPT], Sv[IPT];
     int v1[IPT], vt[IPT];
     bool valid[IPT];
@@ -1084,46 +1082,408 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
         s1 += L.WaveA[w];
         s2 += L.WaveB[w];
       }
-      const int hsh = blockIdx.x % CC_SHARDS;
-      if (s1) atomicAdd(&ctl->hist_sh[hsh][t + 1], s1);
-      if (s2) atomicAdd(&ctl->hist_sh[hsh][t + 2], s2);
+      if (s1) atomicAdd(&ctl->hist_sh[osh][t + 1], s1);
+      if (s2) atomicAdd(&ctl->hist_sh[osh][t + 2], s2);
     }
   }
   return CC_LEVEL_NEXT;
 }
 
-// The leading steps on one block, while they are small (at most
-// CC_DEEP_PATHS paths and CC_DEEP_CYCLES staged cycles): on many graphs the
-// first levels hold a few hundred paths, and a full-grid launch per step
-// would cost more than the work.  Runs before the step launches and records
-// where they start (launch_step[1]); it is launch 0 for host_done.  Its
-// steps pass data to each other through the block's own stores, ordered by
-// its barriers.
+// --------------------------------------------------------- one-block head
+// Stage one and the leading levels on one block of CC_HEAD_THREADS threads,
+// with the frontier in LDS: two buffers of `cap` paths in dynamic shared
+// memory (X words, S words when enumerating, then vv), used in turn.  Each
+// level takes one pass to count every path's extensions and closures, a
+// block-wide scan for exact offsets, and one pass to write the extensions
+// to the other buffer and each closure's cycle straight to the output
+// (cycles of one length come from one level, so their output range is
+// known).  Nothing is staged and no global counter is touched, so a level
+// costs a few LDS round trips and barriers.
+//
+// The head stops at the first level whose paths do not fit (or at the
+// forced depth-first level): it writes that level's paths to frontier
+// buffer 0, dealt round-robin over the shards, with the counters, the
+// cumulative output offsets and the state the step launches need, and
+// records where they start (launch_step[1]).  If the frontier empties
+// first, the loop is over (launch_step[1] = 0).  Launch 0 for host_done.
 template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_BLOCK) void k_head(GraphDev g, CcCtl *ctl, LevelBufs B,
-                                                   OutDev out, int forced_level, int maxc,
-                                                   int allow_two, unsigned int *host_done) {
-  __shared__ LevelLds<W, ENUM> L;
-  if (host_done && threadIdx.x == 0) st_system(host_done + 1, 1u);
-  int step = 0, r = CC_LEVEL_NEXT;
-  for (; step < g.n - 2; ++step) {
-    r = step_body<W, ENUM, true>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0, L,
-                                 step > 0);
-    if (r != CC_LEVEL_NEXT) break;
-    __syncthreads();
+struct HeadLds {
+  unsigned long long N[CC_MAXN * W];
+  unsigned long long No[ENUM ? CC_MAXN * W : 1];
+  int Perm[CC_MAXN];
+  unsigned long long WaveTot[CC_HEAD_THREADS / CC_WAVE];
+  unsigned long long Front[CC_HSLOTS];  // paths expanded per length
+  unsigned long long Hist[CC_HSLOTS];   // cycles found per length (above 3)
+  unsigned int Trip, Tri;
+  long long WCum[2];                    // wavefront phase results, for the block
+  int WState[4];
+};
+
+// Head results of a run of levels on one wavefront
+#define CC_HEAD_MORE 0   // the frontier outgrew the wavefront: back to the block
+#define CC_HEAD_OVER 1   // the frontier emptied
+#define CC_HEAD_STOP 2   // hand over at level t (forced level, or no room)
+
+// The head's frontier buffer b (0 or 1) inside dynamic shared memory.
+template <int W, bool ENUM>
+struct HeadBuf {
+  unsigned long long *X;
+  unsigned long long *S;
+  unsigned short *vv;
+};
+template <int W, bool ENUM>
+__device__ __forceinline__ HeadBuf<W, ENUM> head_buf(unsigned long long *dyn, int cap, int b) {
+  const int words = W * cap * (ENUM ? 2 : 1);
+  const int per = words + (cap * 2 + 7) / 8;  // 8-byte words per buffer
+  HeadBuf<W, ENUM> h;
+  h.X = dyn + b * per;
+  h.S = h.X + W * cap;
+  h.vv = (unsigned short *)(h.X + words);
+  return h;
+}
+
+// Block-wide exclusive scan of two 32-bit counts packed in one 64-bit value
+// (no carry between the halves: each half's total stays below 2^32).
+// Returns this thread's offsets; *total receives the block's totals.
+template <int NT>
+__device__ __forceinline__ unsigned long long block_scan2(unsigned long long v,
+                                                          unsigned long long *wave_tot,
+                                                          unsigned long long *total) {
+  constexpr int NW = NT / CC_WAVE;
+  const int lane = lane_id(), wave = threadIdx.x / CC_WAVE;
+  unsigned long long x = v;
+#pragma unroll
+  for (int o = 1; o < CC_WAVE; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, CC_WAVE);
+    if (lane >= o) x += y;
   }
-  if (threadIdx.x == 0) {
-    // the first step the launches run (deferred, or past the last); none
-    // once the loop is over
-    const bool over = r == CC_LEVEL_EMPTY || r == CC_LEVEL_SWITCH;
-    const int next = over ? step + 1 : step;
-    ctl->launch_step[1] = over ? 0 : next + 1;
-    ctl->levels_run = next;
-    ctl->head_steps = next;
-    if ((r == CC_LEVEL_EMPTY || r == CC_LEVEL_SWITCH) && host_done) {
-      if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
-      st_system(host_done, 1u);
+  if (lane == CC_WAVE - 1) wave_tot[wave] = x;
+  __syncthreads();
+  unsigned long long base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const unsigned long long t = wave_tot[w];
+    if (w < wave) base += t;
+    tot += t;
+  }
+  *total = tot;
+  __syncthreads();  // wave_tot is reused by the next scan
+  return base + x - v;
+}
+
+// Levels on one wavefront while the frontier has at most CC_WAVE paths, one
+// path per lane: the same count / scan / write passes as the block, with
+// the scan across lanes and no barrier (a wavefront's LDS operations
+// complete in order).  Thin graphs (a long cycle, a wheel) spend every
+// level here.  Updates t, cnt, b and the output cursors; returns
+// CC_HEAD_MORE, CC_HEAD_OVER or CC_HEAD_STOP.
+template <int W, bool ENUM>
+__device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, int cap,
+                                int forced_level, const OutDev &out, int &t, unsigned &cnt,
+                                int &b, long long &cum_c, long long &cum_v) {
+  const int lane = lane_id();
+  while (true) {
+    if (cnt == 0) return CC_HEAD_OVER;
+    if (cnt > CC_WAVE) return CC_HEAD_MORE;
+    if (t == forced_level || t + 2 >= CC_HSLOTS) return CC_HEAD_STOP;
+    const HeadBuf<W, ENUM> cur = head_buf<W, ENUM>(dyn, cap, b);
+    const HeadBuf<W, ENUM> nxt = head_buf<W, ENUM>(dyn, cap, 1 - b);
+    const bool mine = (unsigned)lane < cnt;
+    Bits<W> X = bzero<W>(), Sv = bzero<W>();
+    unsigned vv = 0;
+    if (mine) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) X.w[w] = cur.X[w * cap + lane];
+      if (ENUM) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) Sv.w[w] = cur.S[w * cap + lane];
+      }
+      vv = cur.vv[lane];
     }
+    const int vt = vv >> 8, v1 = vv & 0xffu;
+    const Bits<W> nvt = row<W>(L.N, vt);
+    const Bits<W> cand = mine ? bandnot(nvt, X) : bzero<W>();
+    const Bits<W> n1 = row<W>(L.N, v1);
+    Bits<W> ext = bandnot(cand, n1);
+    Bits<W> cl = band(cand, n1);
+    const unsigned long long v = (unsigned long long)bpop(ext) |
+                                 ((unsigned long long)bpop(cl) << 32);
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < CC_WAVE; o <<= 1) {
+      const unsigned long long y = __shfl_up(x, o, CC_WAVE);
+      if (lane >= o) x += y;
+    }
+    const unsigned long long tot = uni_u64(__shfl(x, CC_WAVE - 1, CC_WAVE));
+    const unsigned te = (unsigned)tot, tc = (unsigned)(tot >> 32);
+    if (te > (unsigned)cap) return CC_HEAD_STOP;
+    unsigned oe = (unsigned)(x - v);
+    unsigned long long oc = (x - v) >> 32;
+    const Bits<W> Xn = bor(X, nvt);
+    while (bany(ext)) {
+      const int u = bpop_lowest(ext);
+#pragma unroll
+      for (int w = 0; w < W; ++w) nxt.X[w * cap + oe] = Xn.w[w];
+      if (ENUM) {
+        const Bits<W> Sn = bor(Sv, bsingle<W>(L.Perm[u]));
+#pragma unroll
+        for (int w = 0; w < W; ++w) nxt.S[w * cap + oe] = Sn.w[w];
+      }
+      nxt.vv[oe] = (unsigned short)(v1 | (u << 8));
+      ++oe;
+    }
+    if (ENUM) {
+      while (bany(cl)) {
+        const int u = bpop_lowest(cl);
+        const long long idx = cum_c + (long long)oc;
+        const long long pos = cum_v + (long long)oc * (t + 1);
+        if (idx < out.cyc_cap && pos + t + 1 <= out.verts_cap) {
+          write_cycle<W>(L.No, bor(Sv, bsingle<W>(L.Perm[u])), t + 1, out.verts + pos);
+          out.offs[idx] = pos;
+        }
+        ++oc;
+      }
+    }
+    if (lane == 0) {
+      L.Front[t] = cnt;
+      L.Hist[t + 1] = tc;
+    }
+    wave_lds_sync();
+    cum_c += tc;
+    cum_v += (long long)tc * (t + 1);
+    cnt = te;
+    b = 1 - b;
+    ++t;
+  }
+}
+
+template <int W, bool ENUM>
+__global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl, LevelBufs B,
+                                                          OutDev out, int forced_level,
+                                                          int cap_lds, unsigned int *host_done) {
+  constexpr int T = CC_HEAD_THREADS;
+  __shared__ HeadLds<W, ENUM> L;
+  extern __shared__ unsigned long long dyn[];
+  const int tid = threadIdx.x;
+  const int n = g.n;
+  if (host_done && tid == 0) st_system(host_done + 1, 1u);
+  for (int i = tid; i < n * W; i += T) L.N[i] = g.adj[i];
+  if (ENUM)
+    for (int i = tid; i < n * W; i += T) L.No[i] = g.adj_orig[i];
+  for (int i = tid; i < n; i += T) L.Perm[i] = g.perm[i];
+  for (int k = tid; k < CC_HSLOTS; k += T) {
+    L.Front[k] = 0ull;
+    L.Hist[k] = 0ull;
+  }
+  if (tid == 0) {
+    L.Trip = 0u;
+    L.Tri = 0u;
+  }
+  __syncthreads();
+  // stage one, into the global buffers (frontier 1, stage 0), as k_triplets
+  const Frontier f1 = B.f[1], f0 = B.f[0];
+  const Stage st0 = B.st[0];
+  // a hand-over deals at most cap paths over the shards of frontier 0
+  const int cap = (int)min((unsigned long long)cap_lds, CC_SHARDS * f0.cap_s);
+  triplets_body<W, ENUM, T>(g, ctl, f1, st0, L.N, L.Perm, &L.Trip, &L.Tri);
+  const unsigned trip = L.Trip, tri = L.Tri;
+  int t = 3;
+  unsigned cnt = trip;
+  bool over = false;
+  if (trip <= (unsigned)cap && forced_level != 3 && trip / CC_SHARDS < f1.cap_s) {
+    // the triplets into LDS buffer 0 (this block wrote them: its barrier
+    // orders those stores before these loads)
+    HeadBuf<W, ENUM> cur = head_buf<W, ENUM>(dyn, cap, 0);
+    for (unsigned j = tid; j < trip; j += T) {
+      const unsigned long long e = (j % CC_SHARDS) * f1.cap_s + j / CC_SHARDS;
+#pragma unroll
+      for (int w = 0; w < W; ++w) cur.X[w * cap + j] = f1.X[w * f1.cap + e];
+      if (ENUM) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) cur.S[w * cap + j] = f1.S[w * f1.cap + e];
+      }
+      cur.vv[j] = f1.vv[e];
+    }
+    // the triangles, written to the output at once
+    long long cum_c = 0, cum_v = 0;
+    if (ENUM) {
+      for (unsigned j = tid; j < tri && j / CC_SHARDS < st0.cap_s; j += T) {
+        const unsigned long long e = (j % CC_SHARDS) * st0.cap_s + j / CC_SHARDS;
+        Bits<W> C;
+#pragma unroll
+        for (int w = 0; w < W; ++w) C.w[w] = st0.C[w * st0.cap + e];
+        const long long pos = 3ll * j;
+        if ((long long)j < out.cyc_cap && pos + 3 <= out.verts_cap) {
+          write_cycle<W>(L.No, C, 3, out.verts + pos);
+          out.offs[j] = pos;
+        }
+      }
+      cum_c = tri;
+      cum_v = 3ll * tri;
+    }
+    __syncthreads();
+    // the levels
+    int b = 0;
+    while (true) {
+      if (cnt == 0) {
+        over = true;
+        break;
+      }
+      if (t == forced_level || t + 2 >= CC_HSLOTS) break;
+      if (cnt <= CC_WAVE) {
+        // small frontier: wavefront 0 alone, then tell the block
+        if (tid < CC_WAVE) {
+          const int r = head_wave_levels<W, ENUM>(L, dyn, cap, forced_level, out, t, cnt, b,
+                                                  cum_c, cum_v);
+          if (tid == 0) {
+            L.WState[0] = r;
+            L.WState[1] = t;
+            L.WState[2] = (int)cnt;
+            L.WState[3] = b;
+            L.WCum[0] = cum_c;
+            L.WCum[1] = cum_v;
+          }
+        }
+        __syncthreads();
+        const int r = L.WState[0];
+        t = L.WState[1];
+        cnt = (unsigned)L.WState[2];
+        b = L.WState[3];
+        cum_c = L.WCum[0];
+        cum_v = L.WCum[1];
+        __syncthreads();  // WState is rewritten by the next wavefront phase
+        if (r == CC_HEAD_OVER) {
+          over = true;
+          break;
+        }
+        if (r == CC_HEAD_STOP) break;
+        continue;
+      }
+      cur = head_buf<W, ENUM>(dyn, cap, b);
+      const HeadBuf<W, ENUM> nxt = head_buf<W, ENUM>(dyn, cap, 1 - b);
+      // count: extensions (low half) and closures (high half)
+      unsigned long long mine = 0;
+      for (unsigned i = tid; i < cnt; i += T) {
+        Bits<W> X;
+#pragma unroll
+        for (int w = 0; w < W; ++w) X.w[w] = cur.X[w * cap + i];
+        const unsigned vv = cur.vv[i];
+        const Bits<W> cand = bandnot(row<W>(L.N, vv >> 8), X);
+        const Bits<W> n1 = row<W>(L.N, vv & 0xffu);
+        mine += (unsigned long long)bpop(bandnot(cand, n1)) |
+                ((unsigned long long)bpop(band(cand, n1)) << 32);
+      }
+      unsigned long long tot;
+      const unsigned long long offs = block_scan2<T>(mine, L.WaveTot, &tot);
+      const unsigned te = (unsigned)tot, tc = (unsigned)(tot >> 32);
+      if (te > (unsigned)cap) break;  // the next level does not fit: hand over at t
+      unsigned oe = (unsigned)offs;
+      unsigned long long oc = offs >> 32;
+      for (unsigned i = tid; i < cnt; i += T) {
+        Bits<W> X, Sv = bzero<W>();
+#pragma unroll
+        for (int w = 0; w < W; ++w) X.w[w] = cur.X[w * cap + i];
+        if (ENUM) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) Sv.w[w] = cur.S[w * cap + i];
+        }
+        const unsigned vv = cur.vv[i];
+        const int vt = vv >> 8, v1 = vv & 0xffu;
+        const Bits<W> nvt = row<W>(L.N, vt);
+        const Bits<W> cand = bandnot(nvt, X);
+        const Bits<W> n1 = row<W>(L.N, v1);
+        Bits<W> ext = bandnot(cand, n1);
+        const Bits<W> Xn = bor(X, nvt);
+        while (bany(ext)) {
+          const int v = bpop_lowest(ext);
+#pragma unroll
+          for (int w = 0; w < W; ++w) nxt.X[w * cap + oe] = Xn.w[w];
+          if (ENUM) {
+            const Bits<W> Sn = bor(Sv, bsingle<W>(L.Perm[v]));
+#pragma unroll
+            for (int w = 0; w < W; ++w) nxt.S[w * cap + oe] = Sn.w[w];
+          }
+          nxt.vv[oe] = (unsigned short)(v1 | (v << 8));
+          ++oe;
+        }
+        if (ENUM) {
+          Bits<W> cl = band(cand, n1);
+          while (bany(cl)) {
+            const int v = bpop_lowest(cl);
+            const long long idx = cum_c + (long long)oc;
+            const long long pos = cum_v + (long long)oc * (t + 1);
+            if (idx < out.cyc_cap && pos + t + 1 <= out.verts_cap) {
+              write_cycle<W>(L.No, bor(Sv, bsingle<W>(L.Perm[v])), t + 1, out.verts + pos);
+              out.offs[idx] = pos;
+            }
+            ++oc;
+          }
+        }
+      }
+      if (tid == 0) {
+        L.Front[t] = cnt;
+        L.Hist[t + 1] = tc;
+      }
+      cum_c += tc;
+      cum_v += (long long)tc * (t + 1);
+      __syncthreads();
+      cnt = te;
+      b = 1 - b;
+      ++t;
+    }
+    // Results and hand-over.  Steps 0 .. t-4 ran here, one level each.
+    const int steps = t - 3;
+    for (int k = 4 + tid; k <= t && k < CC_HSLOTS; k += T)
+      if (L.Hist[k]) ctl->hist_sh[0][k] = L.Hist[k];
+    for (int k = 3 + tid; k < t; k += T) {
+      ctl->front[k] = L.Front[k];
+      ctl->step_level[k - 3] = k;
+    }
+    if (!over) {
+      // this level's paths go to frontier buffer 0 for the step launches
+      cur = head_buf<W, ENUM>(dyn, cap, b);
+      for (unsigned i = tid; i < cnt; i += T) {
+        const unsigned long long e = (i % CC_SHARDS) * f0.cap_s + i / CC_SHARDS;
+#pragma unroll
+        for (int w = 0; w < W; ++w) f0.X[w * f0.cap + e] = cur.X[w * cap + i];
+        if (ENUM) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) f0.S[w * f0.cap + e] = cur.S[w * cap + i];
+        }
+        f0.vv[e] = cur.vv[i];
+      }
+      if (tid < CC_SHARDS)
+        ctl->count_sh[tid][t] = cnt > (unsigned)tid ? (cnt - tid + CC_SHARDS - 1) / CC_SHARDS : 0u;
+      if (tid == 0) {
+        StepState S{};
+        S.t = t;
+        S.fbuf = 0;
+        S.spair = 0;
+        S.slen0 = 0;
+        S.slen1 = 0;
+        S.prev_two = 0;
+        S.done = 0;
+        ctl->ss[steps] = S;
+        if (ENUM) {
+          ctl->cum_c[t] = (unsigned long long)cum_c;
+          ctl->cum_v[t] = (unsigned long long)cum_v;
+        }
+      }
+    }
+    if (tid == 0) {
+      unsigned long long pk = 0;
+      for (int k = 3; k < t; ++k) pk = max(pk, L.Front[k]);
+      ctl->peak = max(pk, (unsigned long long)cnt);
+      ctl->launch_step[1] = over ? 0 : steps + 1;
+      ctl->levels_run = steps;
+      ctl->head_steps = steps;
+      if (over && host_done) st_system(host_done, 1u);
+    }
+  } else if (tid == 0) {
+    // too many triplets for LDS: the step launches start at step 0
+    ctl->launch_step[1] = 1;
+    ctl->levels_run = 0;
+    ctl->head_steps = 0;
   }
 }
 
@@ -1146,8 +1506,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
     if (host_done && lead) st_system(host_done, (unsigned)launch + 1u);
     return;
   }
-  const int r = step_body<W, ENUM, false>(g, ctl, B, out, step, forced_level, maxc,
-                                          allow_two != 0, L, false);
+  const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0, L,
+                                   false);
   if (lead) {
     if (launch + 1 < CC_HSLOTS) ctl->launch_step[launch + 1] = r == CC_LEVEL_NEXT ? step + 2 : 0;
     ctl->levels_run = step + 1;
@@ -1279,8 +1639,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Lev
   // has room for them
   for (; step < g.n - 2; ++step) {
     if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[step] = wall_clock64();
-    const int r = step_body<W, ENUM, false>(g, ctl, B, out, step, forced_level, maxc,
-                                            allow_two != 0, L, true);
+    const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0,
+                                     L, true);
     if (r != CC_LEVEL_NEXT) {
       ++step;
       break;
@@ -1985,19 +2345,48 @@ int cc_levels_max_blocks(int W, bool en) {
   return per_cu * cus;
 }
 
+// Paths the head's LDS frontier buffers hold with `lds_bytes` of dynamic
+// shared memory (two buffers).
+int cc_head_capacity(int W, bool en, size_t lds_bytes) {
+  const size_t per_path = (size_t)W * 8 * (en ? 2 : 1) + 2;
+  long long cap = (long long)(lds_bytes / 2 / per_path) - 8;
+  return cap > 0 ? (int)std::min<long long>(cap, 1 << 20) : 0;
+}
+
 hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                          OutDev out, int forced_level, int max_children, bool two,
+                          OutDev out, int forced_level, size_t lds_bytes,
                           unsigned int *host_done, hipStream_t s) {
-  dim3 gr(1), bl(CC_BLOCK);
-  const int allow_two = two ? 1 : 0;
+  const int cap = cc_head_capacity(W, en, lds_bytes);
+  dim3 gr(1), bl(CC_HEAD_THREADS);
+  // The dynamic LDS limit is raised once per device and instantiation (the
+  // call costs host time that would otherwise stall the stream).
+  static std::atomic<size_t> raised[64][4];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const int which = (W == 1 ? 0 : 2) + (en ? 1 : 0);
+  if (dev >= 0 && dev < 64 && raised[dev][which].load() < lds_bytes) {
+    const void *fn = W == 1 ? (en ? (const void *)k_head<1, true> : (const void *)k_head<1, false>)
+                            : (en ? (const void *)k_head<2, true> : (const void *)k_head<2, false>);
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    raised[dev][which].store(lds_bytes);
+  }
   if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_head<1, true>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
-    else hipLaunchKernelGGL((k_head<1, false>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
+    if (en) hipLaunchKernelGGL((k_head<1, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
+    else hipLaunchKernelGGL((k_head<1, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
   } else {
-    if (en) hipLaunchKernelGGL((k_head<2, true>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
-    else hipLaunchKernelGGL((k_head<2, false>), gr, bl, 0, s, g, ctl, b, out, forced_level, max_children, allow_two, host_done);
+    if (en) hipLaunchKernelGGL((k_head<2, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
+    else hipLaunchKernelGGL((k_head<2, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
   }
   return hipGetLastError();
+}
+
+// Static shared memory of the head kernel (so the caller can size the
+// dynamic part).
+size_t cc_head_static_lds(int W, bool en) {
+  return W == 1 ? (en ? sizeof(HeadLds<1, true>) : sizeof(HeadLds<1, false>))
+                : (en ? sizeof(HeadLds<2, true>) : sizeof(HeadLds<2, false>));
 }
 
 hipError_t cc_launch_step(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,

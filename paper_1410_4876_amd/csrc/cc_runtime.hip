@@ -31,6 +31,7 @@ struct DeviceInfo {
   int cus = 0;
   bool coop = false;  // cooperative launches supported
   unsigned long long clock_hz = 0;
+  size_t head_lds = 0;  // dynamic LDS bytes of the head kernel
 };
 
 std::mutex g_dev_mu;
@@ -57,6 +58,12 @@ cc_status device_info(int dev, DeviceInfo *out) {
     }
     int coop = 0;
     (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    // dynamic LDS for the head kernel's two frontier buffers: what a block
+    // may hold, less the kernel's static part and a margin
+    int lds = 0;
+    (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t stat = std::max(cc_head_static_lds(1, true), cc_head_static_lds(2, true));
+    g_dev[dev].head_lds = lds > (int)stat + 4096 ? (size_t)lds - stat - 4096 : 0;
     g_dev[dev].coop = coop != 0;
     g_dev[dev].cus = p.multiProcessorCount;
     g_dev[dev].clock_hz = (unsigned long long)rate_khz * 1000ull;
@@ -330,10 +337,16 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   auto mark = [&](int i) {
     if (prof) chk(hipEventRecord(g->evp[i], s));
   };
+  const int coop_max = g->dev.coop && (g->opt.flags & CC_LEVEL_PERSISTENT)
+                           ? cc_levels_max_blocks(W, en)
+                           : 0;
+  const bool persistent = coop_max >= CC_SHARDS;
   chk(hipEventRecord(g->ev0, s));
   chk(cc_launch_zero(ctl, sizeof(CcCtl), s));
+  // Stage one: its own kernel before the persistent loop; inside the head
+  // kernel (launch 0) otherwise.
   mark(0);
-  chk(cc_launch_triplets(W, en, gd, ctl, f[1], lb.st[0], s));
+  if (persistent) chk(cc_launch_triplets(W, en, gd, ctl, f[1], lb.st[0], s));
   mark(1);
   // Each step expands the paths of one length by one level, or by two when
   // its output provably fits, and (enumerate mode) decodes the cycles the
@@ -347,10 +360,6 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   // CC_LEVEL_PERSISTENT, one cooperative launch runs every step with a grid
   // barrier in between and stops on the device; on MI355X its barriers cost
   // about as much as the launches they replace, so it is not the default.
-  const int coop_max = g->dev.coop && (g->opt.flags & CC_LEVEL_PERSISTENT)
-                           ? cc_levels_max_blocks(W, en)
-                           : 0;
-  const bool persistent = coop_max >= CC_SHARDS;
   const bool two_ok = !(g->opt.flags & CC_ONE_LEVEL_STEPS);
   if (persistent) {
     const int want = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
@@ -365,10 +374,11 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     done[0] = 0u;
     done[1] = 0u;
     done[2] = 0u;
-    // Launch 0 runs the leading small steps on one block; each later launch
-    // runs one step, so n - 2 of them are enough.
+    // Launch 0 runs stage one and the leading levels on one block with the
+    // frontier in LDS; each later launch runs one step, so n - 2 of them
+    // are enough.
     mark(2);
-    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, maxc, two_ok, g->d_done, s));
+    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, g->dev.head_lds, g->d_done, s));
     mark(3);
     ++levels;
     for (int launch = 1; launch < n - 1 && e == hipSuccess; ++launch, ++levels) {
