@@ -152,6 +152,27 @@ cc_status cc_histogram(cc_graph *g, int64_t *hist, int32_t hist_len);
 cc_status cc_enumerate(cc_graph *g, int32_t *verts, int64_t verts_cap, int64_t *offsets,
                        int64_t cycles_cap, int64_t *n_cycles, int64_t *n_verts);
 
+/*
+ * cc_enumerate_lengths -- write the chordless cycles with k_min <= k <= k_max
+ * vertices only: the slice of cc_enumerate's output that holds those
+ * lengths, with offsets starting at 0.  A caller whose buffers cannot hold
+ * every cycle pages through the output one range of lengths at a time
+ * (Section 6 names larger outputs than device memory holds as future work;
+ * the unit of a page here is one cycle length, since the order of cycles of
+ * equal length is unspecified).  Each call runs the enumeration again;
+ * cycles outside the range are found but not written.
+ *   k_min, k_max            0 <= k_min <= k_max
+ *   verts, offsets, caps    as cc_enumerate, for the range only
+ *   n_cycles, n_verts       receive the range's exact totals
+ * The range's sizes come from the histogram (from the handle's last
+ * complete call, else a counting run first).  If a buffer is too small,
+ * returns CC_ERR_BUFFER_TOO_SMALL with the required sizes and writes
+ * nothing.  Errors otherwise as cc_enumerate.
+ */
+cc_status cc_enumerate_lengths(cc_graph *g, int32_t k_min, int32_t k_max, int32_t *verts,
+                               int64_t verts_cap, int64_t *offsets, int64_t cycles_cap,
+                               int64_t *n_cycles, int64_t *n_verts);
+
 /* cc_labels -- labels[v] = degree label of vertex v (host array of n). */
 cc_status cc_labels(cc_graph *g, int32_t *labels);
 

@@ -104,6 +104,9 @@ def lib():
             L.cc_histogram.restype = ctypes.c_int
             L.cc_enumerate.argtypes = [vp, vp, i64, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
             L.cc_enumerate.restype = ctypes.c_int
+            L.cc_enumerate_lengths.argtypes = [vp, i32, i32, vp, i64, vp, i64,
+                                               ctypes.POINTER(i64), ctypes.POINTER(i64)]
+            L.cc_enumerate_lengths.restype = ctypes.c_int
             L.cc_labels.argtypes = [vp, vp]
             L.cc_labels.restype = ctypes.c_int
             L.cc_frontier.argtypes = [vp, vp, i32]
@@ -291,6 +294,72 @@ class Graph:
         got_c, got_v = self.enumerate_into(verts, offs)
         assert got_c == nc and got_v == nv
         return verts[:nv], offs
+
+    def enumerate_lengths_into(self, k_min: int, k_max: int, verts, offsets):
+        """Fill caller buffers with the cycles of k_min..k_max vertices only
+        (cc_enumerate_lengths).  Returns (n_cycles, n_verts); raises
+        CCError(CC_ERR_BUFFER_TOO_SMALL) with .required if they do not fit."""
+        vp, _, _ = _ptr(verts)
+        op, _, _ = _ptr(offsets)
+        nc, nv = ctypes.c_int64(), ctypes.c_int64()
+        vcap = int(verts.numel() if _is_torch(verts) else np.asarray(verts).size)
+        ccap = int(offsets.numel() if _is_torch(offsets) else np.asarray(offsets).size) - 1
+        st = lib().cc_enumerate_lengths(self.h, int(k_min), int(k_max), vp, vcap, op,
+                                        max(ccap, 0), ctypes.byref(nc), ctypes.byref(nv))
+        if st == CC_ERR_INTERNAL:
+            _check(st, "cc_enumerate_lengths", self._info_fn)
+        if st != CC_OK:
+            err = CCError(st, "cc_enumerate_lengths")
+            err.required = (nc.value, nv.value)
+            raise err
+        return nc.value, nv.value
+
+    def enumerate_lengths(self, k_min: int, k_max: int, device="cuda"):
+        """The cycles of k_min..k_max vertices, sized exactly from the
+        histogram: (verts, offsets) as torch tensors (output_device=True)
+        or numpy arrays."""
+        h = self.histogram()
+        k = np.arange(h.size)
+        sel = (k >= k_min) & (k <= k_max)
+        nc = int(h[sel].sum())
+        nv = int((h[sel] * k[sel]).sum())
+        if self.output_device:
+            import torch
+            verts = torch.empty(max(nv, 1), dtype=torch.int32, device=device)
+            offs = torch.empty(nc + 1, dtype=torch.int64, device=device)
+        else:
+            verts = np.empty(max(nv, 1), np.int32)
+            offs = np.empty(nc + 1, np.int64)
+        got_c, got_v = self.enumerate_lengths_into(k_min, k_max, verts, offs)
+        assert got_c == nc and got_v == nv
+        return verts[:nv], offs
+
+    def pages(self, max_verts: int, max_cycles: int | None = None, device="cuda"):
+        """Yield (k_min, k_max, verts, offsets) over consecutive ranges of
+        cycle lengths, each holding at most max_verts vertex ids (and
+        max_cycles cycles): the whole output in pieces that fit a bounded
+        buffer.  Raises ValueError if a single length does not fit."""
+        h = self.histogram()
+        lens = [k for k in range(h.size) if h[k]]
+        i = 0
+        while i < len(lens):
+            k0 = lens[i]
+            nv = nc = 0
+            j = i
+            while j < len(lens):
+                k = lens[j]
+                v2, c2 = nv + int(h[k]) * k, nc + int(h[k])
+                if v2 > max_verts or (max_cycles is not None and c2 > max_cycles):
+                    break
+                nv, nc = v2, c2
+                j += 1
+            if j == i:
+                raise ValueError(f"the {int(h[k0])} cycles of length {k0} need "
+                                 f"{int(h[k0]) * k0} vertex ids, more than max_verts={max_verts}")
+            k1 = lens[j - 1]
+            v, o = self.enumerate_lengths(k0, k1, device=device)
+            yield k0, k1, v, o
+            i = j
 
     def labels(self) -> np.ndarray:
         lab = np.zeros(max(self.n, 1), np.int32)

@@ -133,12 +133,19 @@ struct LevelBufs {
   Stage st[4];
 };
 
-// Enumeration output (cc_enumerate's buffers).
+// Enumeration output (cc_enumerate's buffers).  Only cycles with kmin <= k
+// <= kmax are written; a cycle's global output index and vertex offset
+// (over all lengths, ordered by length) are shifted down by cshift and
+// vshift, the index and offset of the first cycle of length kmin.
 struct OutDev {
   int *verts;
   long long *offs;
   long long verts_cap;
   long long cyc_cap;
+  int kmin = 0;
+  int kmax = 1 << 30;
+  long long cshift = 0;
+  long long vshift = 0;
 };
 
 // Depth-first workspace: per-wavefront stacks, mailboxes and inboxes.

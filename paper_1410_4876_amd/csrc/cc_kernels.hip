@@ -264,6 +264,17 @@ __device__ void write_cycle(const unsigned long long *sNo, Bits<W> C, int k, int
   }
 }
 
+// Where cycle `cyc` (global output index) of length k with vertices at
+// global offset `pos` goes in the caller's buffers: shifted into the
+// output window; false if the cycle is outside the window or the buffers.
+__device__ __forceinline__ bool out_slot(const OutDev &out, int k, long long &cyc,
+                                         long long &pos) {
+  if (k < out.kmin || k > out.kmax) return false;
+  cyc -= out.cshift;
+  pos -= out.vshift;
+  return cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap;
+}
+
 // ----------------------------------------------------------------- zero
 __global__ void k_zero(unsigned int *p, size_t words) {
   size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -691,7 +702,9 @@ __device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st
                            const unsigned long long *pre, unsigned long long h, int k,
                            long long cb, long long vb, const OutDev &out, unsigned long long gw,
                            unsigned long long nwg) {
-  if (h == 0 || k < 3) return;
+  if (h == 0 || k < 3 || k < out.kmin || k > out.kmax) return;
+  cb -= out.cshift;  // into the output window
+  vb -= out.vshift;
   const int lane = lane_id();
   const unsigned long long per = (unsigned long long)min(CC_WAVE, CC_DEC_WORDS / k);
   for (unsigned long long g0 = gw * per; g0 < h; g0 += nwg * per) {
@@ -1235,9 +1248,9 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, in
     if (ENUM) {
       while (bany(cl)) {
         const int u = bpop_lowest(cl);
-        const long long idx = cum_c + (long long)oc;
-        const long long pos = cum_v + (long long)oc * (t + 1);
-        if (idx < out.cyc_cap && pos + t + 1 <= out.verts_cap) {
+        long long idx = cum_c + (long long)oc;
+        long long pos = cum_v + (long long)oc * (t + 1);
+        if (out_slot(out, t + 1, idx, pos)) {
           write_cycle<W>(L.No, bor(Sv, bsingle<W>(L.Perm[u])), t + 1, out.verts + pos);
           out.offs[idx] = pos;
         }
@@ -1312,10 +1325,10 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         Bits<W> C;
 #pragma unroll
         for (int w = 0; w < W; ++w) C.w[w] = st0.C[w * st0.cap + e];
-        const long long pos = 3ll * j;
-        if ((long long)j < out.cyc_cap && pos + 3 <= out.verts_cap) {
+        long long idx = j, pos = 3ll * j;
+        if (out_slot(out, 3, idx, pos)) {
           write_cycle<W>(L.No, C, 3, out.verts + pos);
-          out.offs[j] = pos;
+          out.offs[idx] = pos;
         }
       }
       cum_c = tri;
@@ -1410,9 +1423,9 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
           Bits<W> cl = band(cand, n1);
           while (bany(cl)) {
             const int v = bpop_lowest(cl);
-            const long long idx = cum_c + (long long)oc;
-            const long long pos = cum_v + (long long)oc * (t + 1);
-            if (idx < out.cyc_cap && pos + t + 1 <= out.verts_cap) {
+            long long idx = cum_c + (long long)oc;
+            long long pos = cum_v + (long long)oc * (t + 1);
+            if (out_slot(out, t + 1, idx, pos)) {
               write_cycle<W>(L.No, bor(Sv, bsingle<W>(L.Perm[v])), t + 1, out.verts + pos);
               out.offs[idx] = pos;
             }
@@ -2024,15 +2037,18 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         if (hist_out) atomicAdd(&sHist[t + 1], (unsigned long long)c);
         if (ENUM) {
           const int k = t + 1;
-          const unsigned long long slot0 = atomicAdd(&ctl->len_cursor[k], (unsigned long long)c);
-          Bits<W> cl = clos;
-          for (int j = 0; j < c; ++j) {
-            const int v = bpop_lowest(cl);
-            const long long cyc = sCb[k] + (long long)(slot0 + j);
-            const long long pos = sVb[k] + (long long)(slot0 + j) * k;
-            if (cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap) {
-              write_cycle<W>(sNo, bor(S, bsingle<W>(sPerm[v])), k, out.verts + pos);
-              out.offs[cyc] = pos;
+          if (k >= out.kmin && k <= out.kmax) {
+            const unsigned long long slot0 =
+                atomicAdd(&ctl->len_cursor[k], (unsigned long long)c);
+            Bits<W> cl = clos;
+            for (int j = 0; j < c; ++j) {
+              const int v = bpop_lowest(cl);
+              long long cyc = sCb[k] + (long long)(slot0 + j);
+              long long pos = sVb[k] + (long long)(slot0 + j) * k;
+              if (out_slot(out, k, cyc, pos)) {
+                write_cycle<W>(sNo, bor(S, bsingle<W>(sPerm[v])), k, out.verts + pos);
+                out.offs[cyc] = pos;
+              }
             }
           }
         }
@@ -2268,8 +2284,10 @@ __global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
   length_totals(ctl, enumerate != 0, sTot);
   for (int k = threadIdx.x; k < CC_HSLOTS; k += blockDim.x) ctl->hist[k] = sTot[k];
   if (enumerate && threadIdx.x == 0) {
+    // the closing offset of the output window
     long long c = 0, v = 0;
     for (int k = 0; k <= n && k < CC_HSLOTS; ++k) {
+      if (k < out.kmin || k > out.kmax) continue;
       c += (long long)sTot[k];
       v += (long long)sTot[k] * k;
     }

@@ -131,6 +131,7 @@ struct cc_graph {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evp[2 * CC_MAXN + 8] = {};  // CC_PROFILE: around each kernel group
   bool have_run = false;
+  bool hist_ok = false;  // hist/front hold the results of a complete run
   int64_t hist[CC_HSLOTS]{};
   double level_ms[CC_HSLOTS]{};  // CC_PROFILE: per-level device time
   int64_t front[CC_HSLOTS]{};
@@ -521,13 +522,19 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     st = CC_ERR_INTERNAL;
   else if (h.status & CC_DEV_STACK_FULL)
     st = CC_ERR_OUT_OF_MEMORY;
+  g->hist_ok = st == CC_OK;
   if (host_out) {
-    int64_t nv = 0;
-    for (int k = 0; k <= n; ++k) nv += g->hist[k] * k;
-    if (st == CC_OK && cycles <= out.cyc_cap && nv <= out.verts_cap) {
-      if (hipMemcpyAsync(ro.host_verts, out.verts, (size_t)nv * 4, hipMemcpyDeviceToHost, s) !=
+    // what the run wrote: the cycles of the output window
+    int64_t cw = 0, vw = 0;
+    for (int k = 0; k <= n; ++k)
+      if (k >= out.kmin && k <= out.kmax) {
+        cw += g->hist[k];
+        vw += g->hist[k] * k;
+      }
+    if (st == CC_OK && cw <= out.cyc_cap && vw <= out.verts_cap) {
+      if (hipMemcpyAsync(ro.host_verts, out.verts, (size_t)vw * 4, hipMemcpyDeviceToHost, s) !=
               hipSuccess ||
-          hipMemcpyAsync(ro.host_offsets, out.offs, (size_t)(cycles + 1) * 8,
+          hipMemcpyAsync(ro.host_offsets, out.offs, (size_t)(cw + 1) * 8,
                          hipMemcpyDeviceToHost, s) != hipSuccess)
         st = CC_ERR_DEVICE;
     }
@@ -768,6 +775,65 @@ cc_status cc_enumerate(cc_graph *g, int32_t *verts, int64_t verts_cap, int64_t *
   totals(n_cycles, n_verts);
   if (*n_cycles > cycles_cap || *n_verts > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
   return CC_OK;
+}
+
+cc_status cc_enumerate_lengths(cc_graph *g, int32_t k_min, int32_t k_max, int32_t *verts,
+                               int64_t verts_cap, int64_t *offsets, int64_t cycles_cap,
+                               int64_t *n_cycles, int64_t *n_verts) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!n_cycles || !n_verts || verts_cap < 0 || cycles_cap < 0 || k_min < 0 || k_max < k_min)
+    return CC_ERR_INVALID_ARG;
+  if ((verts_cap > 0 && !verts) || !offsets) return CC_ERR_INVALID_ARG;
+  *n_cycles = 0;
+  *n_verts = 0;
+  const bool dev_out = (g->opt.flags & CC_OUTPUT_DEVICE) != 0;
+  if (g->n >= 3 && !g->hist_ok) {
+    // sizes of the window: the histogram, from a counting run if no
+    // complete run has produced it yet
+    st = run_counts(g);
+    if (st != CC_OK) return st;
+  }
+  int64_t cshift = 0, vshift = 0, cw = 0, vw = 0;
+  if (g->n >= 3)
+    for (int k = 0; k <= g->n; ++k) {
+      if (k < k_min) {
+        cshift += g->hist[k];
+        vshift += g->hist[k] * k;
+      } else if (k <= k_max) {
+        cw += g->hist[k];
+        vw += g->hist[k] * k;
+      }
+    }
+  *n_cycles = cw;
+  *n_verts = vw;
+  if (cw > cycles_cap || vw > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
+  if (cw == 0) {
+    // nothing in the window: only the closing offset
+    if (dev_out) {
+      const int64_t zero = 0;
+      if (hipMemcpyAsync(offsets, &zero, 8, hipMemcpyHostToDevice, g->stream) != hipSuccess ||
+          hipStreamSynchronize(g->stream) != hipSuccess)
+        return CC_ERR_DEVICE;
+    } else {
+      offsets[0] = 0;
+    }
+    return CC_OK;
+  }
+  RunOut ro;
+  ro.enumerate = true;
+  if (dev_out) {
+    ro.out = OutDev{verts, (long long *)offsets, verts_cap, cycles_cap};
+  } else {
+    ro.host_verts = verts;
+    ro.host_offsets = offsets;
+    ro.out = OutDev{nullptr, nullptr, vw, cw};
+  }
+  ro.out.kmin = k_min;
+  ro.out.kmax = k_max;
+  ro.out.cshift = cshift;
+  ro.out.vshift = vshift;
+  return run_device(g, ro);
 }
 
 cc_status cc_labels(cc_graph *g, int32_t *labels) {

@@ -95,6 +95,10 @@ def test_argument_errors_before_any_device_call(L):
     # calls on a null handle
     total = ctypes.c_int64()
     assert L.cc_count(None, ctypes.byref(total)) == cc.CC_ERR_INVALID_ARG
+    nc, nv = ctypes.c_int64(), ctypes.c_int64()
+    offs = (ctypes.c_int64 * 2)()
+    assert L.cc_enumerate_lengths(None, 3, 5, None, 0, offs, 1, ctypes.byref(nc),
+                                  ctypes.byref(nv)) == cc.CC_ERR_INVALID_ARG
     L.cc_release(None)
 
 

@@ -279,3 +279,83 @@ def test_one_level_steps_match(cc):
     info = full_parity(cc, gg.permute_random(gg.grid(6, 8), np.random.default_rng(5)),
                        one_level_steps=True, budget_bytes=512 << 10)
     assert info["switch_level"] > 3
+
+
+# ------------------------------------------------- output by ranges of lengths
+def window_groups(cc, g, windows, **kw):
+    """Enumerate g window by window (cc_enumerate_lengths); check each
+    window's output and return the canonical groups of all of them."""
+    groups = {}
+    with cc.prepare(g, **kw) as h:
+        hist = h.histogram()
+        for k0, k1 in windows:
+            v, o = h.enumerate_lengths(k0, k1)
+            v = v.cpu().numpy() if hasattr(v, "cpu") else v
+            o = o.cpu().numpy() if hasattr(o, "cpu") else o
+            lens = np.diff(o)
+            k = np.arange(hist.size)
+            sel = (k >= k0) & (k <= k1)
+            assert o[0] == 0 and o.size - 1 == int(hist[sel].sum())
+            assert int(o[-1]) == int((hist[sel] * k[sel]).sum())
+            assert np.all((lens >= k0) & (lens <= k1)) and np.all(np.diff(lens) >= 0)
+            assert is_canonical_array(v, o)
+            for kk, a in canonical_groups(v, o).items():
+                assert kk not in groups
+                groups[kk] = a
+    return groups
+
+
+@pytest.mark.parametrize("case", ["grid5x7", "er60", "er100_w2", "forced_dfs", "host_out"])
+def test_length_windows_make_up_the_whole_output(cc, case):
+    rng = np.random.default_rng(21)
+    g, kw = {
+        "grid5x7": (gg.permute_random(gg.grid(5, 7), rng), {}),
+        "er60": (gg.er_gnm(60, 110, rng), {}),
+        "er100_w2": (gg.er_gnm(100, 125, rng), {}),
+        "forced_dfs": (gg.permute_random(gg.grid(5, 7), rng), {"force_dfs_level": 6}),
+        "host_out": (gg.er_gnm(40, 100, rng), {"output_device": False}),
+    }[case]
+    ores = oracle_run(g)
+    want = canonical_groups(*ores.cycles)
+    windows = [(0, 4), (5, 5), (6, 9), (10, 17), (18, 200)]
+    got = window_groups(cc, g, windows, **kw)
+    assert sorted(got) == sorted(want)
+    for k in want:
+        assert np.array_equal(got[k], want[k]), k
+
+
+def test_length_window_errors_and_pages(cc):
+    import torch
+    g = gg.permute_random(gg.grid(5, 6), np.random.default_rng(3))
+    ores = oracle_run(g)
+    hist = ores.hist
+    with cc.prepare(g) as h:
+        # a window whose buffers are too small reports its own sizes
+        k = np.arange(hist.size)
+        sel = (k >= 8) & (k <= 12)
+        with pytest.raises(cc.CCError) as ei:
+            h.enumerate_lengths_into(8, 12, torch.empty(4, dtype=torch.int32, device="cuda"),
+                                     torch.empty(2, dtype=torch.int64, device="cuda"))
+        assert ei.value.status == cc.CC_ERR_BUFFER_TOO_SMALL
+        assert ei.value.required == (int(hist[sel].sum()), int((hist[sel] * k[sel]).sum()))
+        with pytest.raises(cc.CCError) as ei:
+            h.enumerate_lengths_into(9, 8, torch.empty(4, dtype=torch.int32, device="cuda"),
+                                     torch.empty(2, dtype=torch.int64, device="cuda"))
+        assert ei.value.status == cc.CC_ERR_INVALID_ARG
+        # an empty window: only the closing offset
+        v, o = h.enumerate_lengths(200, 300)
+        assert o.numel() == 1 and int(o[0]) == 0
+        # pages of at most 300 vertex ids cover the whole output
+        groups, pages = {}, 0
+        biggest = int((hist * k).max())
+        for k0, k1, v, o in h.pages(max_verts=max(300, biggest)):
+            pages += 1
+            assert int(o[-1]) <= max(300, biggest)
+            for kk, a in canonical_groups(v.cpu().numpy(), o.cpu().numpy()).items():
+                groups[kk] = a
+        assert pages > 1
+        want = canonical_groups(*ores.cycles)
+        assert sorted(groups) == sorted(want)
+        assert all(np.array_equal(groups[kk], want[kk]) for kk in want)
+        with pytest.raises(ValueError):
+            list(h.pages(max_verts=biggest - 1))
