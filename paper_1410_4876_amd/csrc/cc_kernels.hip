@@ -1129,7 +1129,7 @@ struct HeadLds {
   unsigned long long Hist[CC_HSLOTS];   // cycles found per length (above 3)
   unsigned int Trip, Tri;
   long long WCum[2];                    // wavefront phase results, for the block
-  int WState[4];
+  int WState[5];
 };
 
 // Head results of a run of levels on one wavefront
@@ -1193,7 +1193,7 @@ __device__ __forceinline__ unsigned long long block_scan2(unsigned long long v,
 template <int W, bool ENUM>
 __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, int cap,
                                 int forced_level, const OutDev &out, int &t, unsigned &cnt,
-                                int &b, long long &cum_c, long long &cum_v) {
+                                int &b, long long &cum_c, long long &cum_v, int &odd) {
   const int lane = lane_id();
   while (true) {
     if (cnt == 0) return CC_HEAD_OVER;
@@ -1261,6 +1261,7 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, in
       L.Front[t] = cnt;
       L.Hist[t + 1] = tc;
     }
+    if (tc && ((t + 1) & 1)) odd = 1;
     wave_lds_sync();
     cum_c += tc;
     cum_v += (long long)tc * (t + 1);
@@ -1335,8 +1336,9 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
       cum_v = 3ll * tri;
     }
     __syncthreads();
-    // the levels
-    int b = 0;
+    // the levels.  odd: a cycle of odd length has been found (a triangle
+    // included); while none has, the graph looks bipartite.
+    int b = 0, odd = tri != 0u;
     while (true) {
       if (cnt == 0) {
         over = true;
@@ -1347,12 +1349,13 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         // small frontier: wavefront 0 alone, then tell the block
         if (tid < CC_WAVE) {
           const int r = head_wave_levels<W, ENUM>(L, dyn, cap, forced_level, out, t, cnt, b,
-                                                  cum_c, cum_v);
+                                                  cum_c, cum_v, odd);
           if (tid == 0) {
             L.WState[0] = r;
             L.WState[1] = t;
             L.WState[2] = (int)cnt;
             L.WState[3] = b;
+            L.WState[4] = odd;
             L.WCum[0] = cum_c;
             L.WCum[1] = cum_v;
           }
@@ -1362,6 +1365,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         t = L.WState[1];
         cnt = (unsigned)L.WState[2];
         b = L.WState[3];
+        odd = L.WState[4];
         cum_c = L.WCum[0];
         cum_v = L.WCum[1];
         __syncthreads();  // WState is rewritten by the next wavefront phase
@@ -1390,6 +1394,12 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
       const unsigned long long offs = block_scan2<T>(mine, L.WaveTot, &tot);
       const unsigned te = (unsigned)tot, tc = (unsigned)(tot >> 32);
       if (te > (unsigned)cap) break;  // the next level does not fit: hand over at t
+      // In a graph that looks bipartite, every cycle has an even length.
+      // Hand over at an odd length when the next level probably would not
+      // fit anyway (te / cnt times te paths): the two-level steps from an
+      // odd length then find every cycle one level down and never need the
+      // walk for closures two levels down.
+      if (!odd && (t & 1) && (unsigned long long)te * te > (unsigned long long)cap * cnt) break;
       unsigned oe = (unsigned)offs;
       unsigned long long oc = offs >> 32;
       for (unsigned i = tid; i < cnt; i += T) {
@@ -1437,6 +1447,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         L.Front[t] = cnt;
         L.Hist[t + 1] = tc;
       }
+      if (tc && ((t + 1) & 1)) odd = 1;
       cum_c += tc;
       cum_v += (long long)tc * (t + 1);
       __syncthreads();
