@@ -255,6 +255,45 @@ def grid7x12_section():
             "stage1_ms": round(info["stage1_ms"], 4)}
 
 
+def paging_section():
+    """Grid 7x10 (8,136,453 cycles, 0.95 GB of vertex ids): the whole output
+    in one cc_enumerate call, and the same output paged through buffers of
+    at most 64 Mi vertex ids (256 MiB) by ranges of cycle lengths
+    (cc_enumerate_lengths).  Every page reruns the enumeration."""
+    import torch
+
+    from paper_1410_4876_amd import cc
+    from paper_1410_4876_amd import graphgen as gg
+
+    g = gg.grid(7, 10)
+    rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
+    limit = 64 << 20
+    with cc.Graph(g.n, rp, ci) as h:
+        hist = h.histogram()
+        nc = int(hist.sum())
+        nv = int((hist * np.arange(hist.size)).sum())
+        dv = torch.empty(nv, dtype=torch.int32, device="cuda")
+        do = torch.empty(nc + 1, dtype=torch.int64, device="cuda")
+
+        def whole():
+            h.enumerate_into(dv, do)
+            torch.cuda.synchronize()
+
+        def paged():
+            pages = 0
+            for _, _, v, o in h.pages(max_verts=limit):
+                pages += 1
+            torch.cuda.synchronize()
+            return pages
+
+        w = _timed(whole, warmup=2, runs=5)
+        pages = paged()
+        p = _timed(paged, warmup=1, runs=3)
+    return {"workload": "grid 7x10, full enumeration", "cycles": nc, "vertex_ids": nv,
+            "whole_ms": w, "page_limit_vertex_ids": limit, "pages": pages, "paged_ms": p}
+
+
 def serving_section(args):
     """Open-loop Poisson request stream (2000 requests/s; half p x q grids,
     p, q in 3..7, half ER graphs, n in 20..80, d in [3, 5]) replayed against
@@ -290,8 +329,9 @@ def main():
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the structured graphs of the paper's Table 1")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the ER G(40,100) latency and 7x12 count-only sections")
-    ap.add_argument("--section", choices=["er40", "grid7x12", "table1", "batched", "serving"],
+                    help="skip the ER G(40,100) latency, 7x12 count-only and paging sections")
+    ap.add_argument("--section",
+                    choices=["er40", "grid7x12", "paging", "table1", "batched", "serving"],
                     help="run only this section and print its JSON (for profiling one workload)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time steps without per-kernel HIP events (no roofline)")
@@ -309,7 +349,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.section:
-        fn = {"er40": er40_section, "grid7x12": grid7x12_section,
+        fn = {"er40": er40_section, "grid7x12": grid7x12_section, "paging": paging_section,
               "table1": lambda: table1_section(args), "batched": lambda: batched_section(args),
               "serving": lambda: serving_section(args)}[args.section]
         print(json.dumps({args.section: fn()}), flush=True)
@@ -424,6 +464,7 @@ def main():
     if not args.no_extra:
         out["er40"] = er40_section()
         out["grid7x12"] = grid7x12_section()
+        out["paging"] = paging_section()
     if not args.no_table1:
         out["table1"] = table1_section(args)
     if not args.no_cpu_baseline:
