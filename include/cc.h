@@ -44,7 +44,8 @@
 extern "C" {
 #endif
 
-#define CC_MAX_VERTICES 128
+#define CC_MAX_VERTICES 256        /* one graph (cc_prepare)                         */
+#define CC_MAX_BATCH_VERTICES 128  /* each graph of a batch or of a serving request */
 #define CC_ABI_VERSION 1
 
 typedef enum cc_status {
@@ -197,7 +198,7 @@ void cc_release(cc_graph *g);
  * Many small graphs enumerated together (count-only).  The graphs are packed
  * as one CSR: graph g owns vertices graph_vtx_off[g] .. graph_vtx_off[g+1]
  * (global ids in row_ptr/col_idx), graph_vtx_off[0] = 0, every graph has at
- * most CC_MAX_VERTICES vertices and no edge leaves its graph.
+ * most CC_MAX_BATCH_VERTICES vertices and no edge leaves its graph.
  */
 typedef struct cc_batch cc_batch;
 

@@ -34,7 +34,8 @@ CC_FORCE_DFS = 1 << 2
 CC_PROFILE = 1 << 3
 CC_LEVEL_PERSISTENT = 1 << 4
 CC_ONE_LEVEL_STEPS = 1 << 5
-CC_MAX_VERTICES = 128
+CC_MAX_VERTICES = 256
+CC_MAX_BATCH_VERTICES = 128
 CC_BATCH_PERSISTENT = 0
 CC_BATCH_PER_GRAPH = 1
 

@@ -5,8 +5,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define CC_MAXN 128
+#define CC_MAXN 256
 #define CC_HSLOTS (CC_MAXN + 2)   // per-length arrays: index 0..n+1
+#define CC_ROWS(W) (64 * (W))     // vertices a W-word bitset graph can hold
+#define CC_BATCH_MAXN 128         // largest graph of a batch (1 or 2 words)
 #define CC_WAVE 64
 #define CC_BLOCK 256              // threads per block for the expansion kernels
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk
@@ -57,6 +59,8 @@ struct StepState {
 struct CcCtl {
   unsigned long long count_sh[CC_SHARDS][CC_HSLOTS];  // open paths with t vertices, per shard
   unsigned long long hist_sh[CC_SHARDS][CC_HSLOTS];   // cycles with k vertices, per shard
+  // ---- zeroed in full before every run (the per-shard arrays above only in
+  //      the columns 0..n+1 a run uses)
   unsigned int bar_arrive[CC_SHARDS][32];   // grid barrier: arrivals per shard (own line each)
   unsigned int bar_top[32];                 // grid barrier: shards complete
   unsigned int bar_gen[32];                 // grid barrier: generation
@@ -66,24 +70,25 @@ struct CcCtl {
   unsigned int xcd_go[16][32];              // level loop: XCD L2 invalidated for generation
   unsigned int xcd_top[32];                 // level loop: XCDs complete
   unsigned int xcd_gen[32];                 // level loop: barrier generation
-  unsigned long long hist[CC_HSLOTS];       // final histogram (written by k_finalize)
-  unsigned long long front[CC_HSLOTS];      // paths with t vertices expanded
   unsigned long long cum_c[CC_HSLOTS];      // enumerate: cycles of length <= t (breadth-first)
   unsigned long long cum_v[CC_HSLOTS];      // enumerate: their vertex count
   unsigned long long dfs_hist[CC_HSLOTS];   // enumerate: depth-first part, counting pass
   unsigned long long len_cursor[CC_HSLOTS]; // enumerate: depth-first slot allocator per length
   unsigned long long len_cbase[CC_HSLOTS];  // enumerate: first cycle index of each length
   unsigned long long len_vbase[CC_HSLOTS];  // enumerate: first vertex offset of each length
+  StepState ss[CC_HSLOTS];                  // step s reads ss[s]; its block 0 writes ss[s + 1]
+  // ---- read back by the host after every run (from here to the end)
+  unsigned long long hist[CC_HSLOTS];       // final histogram (written by k_finalize)
+  unsigned long long front[CC_HSLOTS];      // paths with t vertices expanded
+  unsigned long long level_clock[CC_HSLOTS]; // persistent level loop: clock at each step start
+  int launch_step[CC_HSLOTS];               // step of step launch i, plus one (0: loop over)
+  int step_level[CC_HSLOTS];                // t of each step
   unsigned long long peak;                  // largest breadth-first frontier
   unsigned long long root_cursor;           // depth-first: next unclaimed handed-over path
   unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
   unsigned long long donations;             // chunks given away on request (diagnostic)
-  unsigned long long level_clock[CC_HSLOTS]; // persistent level loop: clock at each step start
   int levels_run;                           // breadth-first steps run
   int root_buf;                             // frontier buffer of the handed-over paths
-  StepState ss[CC_HSLOTS];                  // step s reads ss[s]; its block 0 writes ss[s + 1]
-  int launch_step[CC_HSLOTS];               // step of step launch i, plus one (0: loop over)
-  int step_level[CC_HSLOTS];                // t of each step
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over
   int switch_level;                         // path length handed to the depth-first kernel
   int skip;                                 // CC_SKIP_* bits for the handed-over paths
@@ -159,7 +164,7 @@ struct OutDev {
 struct DfsWork {
   unsigned long long *stackX;   // [nwaves][W][cap_w]
   unsigned long long *stackS;   // [nwaves][W][cap_w] (enumerate only)
-  unsigned int *stackM;         // [nwaves][cap_w]: v1 | vt<<8 | t<<16 | root<<24
+  unsigned int *stackM;         // [nwaves][cap_w]: v1 | vt<<8 | t<<16 (9 bits) | root<<31
   unsigned int *stackG;         // [nwaves][cap_w] graph id (batches only)
   unsigned long long cap_w;     // items per wavefront stack
   unsigned int *mail;           // [nwaves][CC_MAIL]
@@ -198,6 +203,8 @@ struct BatchDev {
 // ------------------------------------------------------------------ launchers
 // All return hipSuccess or the launch error.  `W` is 1 (n <= 64) or 2.
 hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s);
+// Zeroes what a run on a graph of n vertices uses of the control block.
+hipError_t cc_launch_zero_ctl(CcCtl *ctl, int n, hipStream_t s);
 // adj (label space) and adj_orig (original ids) rows are at (v0 + row) * W.
 // bound (may be NULL) receives, per graph, sum over vertices of C(deg, 2):
 // an upper bound on its initial triplets plus triangles.

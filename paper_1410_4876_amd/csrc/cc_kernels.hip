@@ -72,45 +72,60 @@ __device__ __forceinline__ int bpop(Bits<W> a) {
   for (int k = 0; k < W; ++k) r += __popcll(a.w[k]);
   return r;
 }
+// Word k of a bitset is selected by comparisons, never by a computed
+// index (that would put the words in scratch memory).
 template <int W>
 __device__ __forceinline__ bool btest(Bits<W> a, int v) {
   unsigned long long word = a.w[0];
-  if (W == 2 && v >= 64) word = a.w[W - 1];
+#pragma unroll
+  for (int k = 1; k < W; ++k)
+    if ((v >> 6) == k) word = a.w[k];
   return (word >> (v & 63)) & 1ull;
 }
 template <int W>
 __device__ __forceinline__ Bits<W> bsingle(int v) {
-  Bits<W> a = bzero<W>();
-  if (W == 1 || v < 64) a.w[0] = 1ull << (v & 63);
-  else a.w[W - 1] = 1ull << (v & 63);
+  Bits<W> a;
+#pragma unroll
+  for (int k = 0; k < W; ++k) a.w[k] = (W == 1 || (v >> 6) == k) ? 1ull << (v & 63) : 0ull;
   return a;
 }
 // Lowest set bit index (a must be non-empty); clears it.
 template <int W>
 __device__ __forceinline__ int bpop_lowest(Bits<W> &a) {
-  if (W == 1 || a.w[0]) {
-    int v = __ffsll((long long)a.w[0]) - 1;
-    a.w[0] &= a.w[0] - 1ull;
-    return v;
+  if (W <= 2) {
+    if (W == 1 || a.w[0]) {
+      const int v = __ffsll((long long)a.w[0]) - 1;
+      a.w[0] &= a.w[0] - 1ull;
+      return v;
+    }
+    const int v = __ffsll((long long)a.w[W - 1]) - 1;
+    a.w[W - 1] &= a.w[W - 1] - 1ull;
+    return 64 + v;
   }
-  int v = __ffsll((long long)a.w[W - 1]) - 1;
-  a.w[W - 1] &= a.w[W - 1] - 1ull;
-  return 64 + v;
+  // first non-empty word, picked and rewritten by comparisons
+  int k = W - 1;
+#pragma unroll
+  for (int j = W - 2; j >= 0; --j)
+    if (a.w[j]) k = j;
+  unsigned long long word = a.w[0];
+#pragma unroll
+  for (int j = 1; j < W; ++j)
+    if (k == j) word = a.w[j];
+  const int v = __ffsll((long long)word) - 1;
+  const unsigned long long rest = word & (word - 1ull);
+#pragma unroll
+  for (int j = 0; j < W; ++j)
+    if (k == j) a.w[j] = rest;
+  return 64 * k + v;
 }
 // {w : w <= u}
 template <int W>
 __device__ __forceinline__ Bits<W> low_through(int u) {
   Bits<W> a;
-  if (W == 1) {
-    a.w[0] = (u >= 63) ? ~0ull : ((2ull << u) - 1ull);
-  } else {
-    if (u >= 64) {
-      a.w[0] = ~0ull;
-      a.w[W - 1] = (u >= 127) ? ~0ull : ((2ull << (u - 64)) - 1ull);
-    } else {
-      a.w[0] = (u >= 63) ? ~0ull : ((2ull << u) - 1ull);
-      a.w[W - 1] = 0ull;
-    }
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const int b = u - 64 * k;  // bits of word k at or below u: b + 1, clamped
+    a.w[k] = b >= 63 ? ~0ull : (b < 0 ? 0ull : ((2ull << b) - 1ull));
   }
   return a;
 }
@@ -276,6 +291,21 @@ __device__ __forceinline__ bool out_slot(const OutDev &out, int k, long long &cy
 }
 
 // ----------------------------------------------------------------- zero
+// The control block before a run on a graph of cols - 2 vertices: the
+// per-shard counters in the columns the run uses, everything after them.
+__global__ void k_zero_ctl(CcCtl *ctl, int cols) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nt = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = tid; i < (size_t)CC_SHARDS * cols; i += nt) {
+    const size_t s = i / cols, k = i - s * cols;
+    ctl->count_sh[s][k] = 0ull;
+    ctl->hist_sh[s][k] = 0ull;
+  }
+  unsigned int *rest = &ctl->bar_arrive[0][0];
+  const size_t words = (sizeof(CcCtl) - offsetof(CcCtl, bar_arrive)) / 4;
+  for (size_t i = tid; i < words; i += nt) rest[i] = 0u;
+}
+
 __global__ void k_zero(unsigned int *p, size_t words) {
   size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -286,7 +316,7 @@ __global__ void k_zero(unsigned int *p, size_t words) {
 // One block per graph.  Validates the CSR (simple, symmetric), builds the
 // adjacency bitsets, computes the degree labelling (Section 2: repeatedly
 // take the remaining vertex of minimum remaining degree, smallest id on
-// ties; it gets the next label) with one wavefront holding two vertices per
+// ties; it gets the next label) with one wavefront holding W vertices per
 // lane, and writes the bitsets renumbered by label plus the original ones.
 template <int W>
 __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vtx_off,
@@ -298,8 +328,8 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
                                                 int *__restrict__ label_out,
                                                 unsigned int *__restrict__ status,
                                                 long long *__restrict__ bound) {
-  __shared__ unsigned long long sA[CC_MAXN * W];
-  __shared__ int sLab[CC_MAXN];
+  __shared__ unsigned long long sA[CC_ROWS(W) * W];
+  __shared__ int sLab[CC_ROWS(W)];
   __shared__ unsigned int sErr;
   __shared__ unsigned int sDeg;
   __shared__ unsigned long long sPairs;
@@ -315,7 +345,7 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
     sDeg = 0u;
     sPairs = 0ull;
   }
-  for (int i = tid; i < CC_MAXN * W; i += blockDim.x) sA[i] = 0ull;
+  for (int i = tid; i < CC_ROWS(W) * W; i += blockDim.x) sA[i] = 0ull;
   __syncthreads();
   if (n < 0 || n > 64 * W) {
     if (tid == 0) status[g] = CC_DEV_NOT_SIMPLE;
@@ -336,7 +366,7 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
       atomicOr(&sErr, CC_DEV_NOT_SIMPLE);
       continue;
     }
-    unsigned long long r0 = 0ull, r1 = 0ull;
+    Bits<W> r = bzero<W>();
     bool bad = false;
     for (long long e = a; e < b && !bad; ++e) {
       const int w = ci[e] - v0;
@@ -344,18 +374,12 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
         bad = true;
         break;
       }
-      const unsigned long long bit = 1ull << (w & 63);
-      if (w < 64) {
-        bad = (r0 & bit) != 0ull;
-        r0 |= bit;
-      } else {
-        bad = (r1 & bit) != 0ull;
-        r1 |= bit;
-      }
+      bad = btest(r, w);
+      r = bor(r, bsingle<W>(w));
     }
     if (bad) atomicOr(&sErr, CC_DEV_NOT_SIMPLE);
-    sA[v * W] = r0;
-    if (W == 2) sA[v * W + W - 1] = r1;
+#pragma unroll
+    for (int k = 0; k < W; ++k) sA[v * W + k] = r.w[k];
     atomicMax(&sDeg, (unsigned)(b - a));
     atomicAdd(&sPairs, (unsigned long long)((b - a) * (b - a - 1) / 2));
   }
@@ -375,25 +399,32 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
     return;
   }
   if (tid < CC_WAVE) {
-    const int va = tid, vb = tid + CC_WAVE;
-    int dega = va < n ? bpop(row<W>(sA, va)) : 0;
-    int degb = vb < n ? bpop(row<W>(sA, vb)) : 0;
-    bool alivea = va < n, aliveb = vb < n;
+    // lane holds vertices tid + 64 j, j < W; key = degree << 8 | id picks
+    // the minimum degree, then the smallest id
+    int deg[W];
+    bool alive[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int v = tid + CC_WAVE * j;
+      alive[j] = v < n;
+      deg[j] = alive[j] ? bpop(row<W>(sA, v)) : 0;
+    }
     for (int i = 0; i < n; ++i) {
-      unsigned ka = alivea ? (((unsigned)dega << 8) | (unsigned)va) : 0xffffffffu;
-      unsigned kb = aliveb ? (((unsigned)degb << 8) | (unsigned)vb) : 0xffffffffu;
-      const unsigned key = wave_min_u32(min(ka, kb));
+      unsigned mine = 0xffffffffu;
+#pragma unroll
+      for (int j = 0; j < W; ++j)
+        if (alive[j]) mine = min(mine, ((unsigned)deg[j] << 8) | (unsigned)(tid + CC_WAVE * j));
+      const unsigned key = wave_min_u32(mine);
       const int u = (int)(key & 0xffu);
-      if (va == u) {
-        alivea = false;
-        sLab[u] = i;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int v = tid + CC_WAVE * j;
+        if (v == u) {
+          alive[j] = false;
+          sLab[u] = i;
+        }
+        if (alive[j] && btest(row<W>(sA, v), u)) --deg[j];
       }
-      if (vb == u) {
-        aliveb = false;
-        sLab[u] = i;
-      }
-      if (alivea && btest(row<W>(sA, va), u)) --dega;
-      if (aliveb && btest(row<W>(sA, vb), u)) --degb;
     }
   }
   __syncthreads();
@@ -492,8 +523,8 @@ __device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, 
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, Frontier f,
                                                        Stage st) {
-  __shared__ unsigned long long sN[CC_MAXN * W];
-  __shared__ int sPerm[CC_MAXN];
+  __shared__ unsigned long long sN[CC_ROWS(W) * W];
+  __shared__ int sPerm[CC_ROWS(W)];
   __shared__ unsigned int sTrip, sTri;
   const int n = g.n;
   const int tid = threadIdx.x;
@@ -509,7 +540,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, F
 
 template <int W>
 __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
-  __shared__ unsigned long long sN[CC_MAXN * W];
+  __shared__ unsigned long long sN[CC_ROWS(W) * W];
   __shared__ unsigned int sTrip, sTri;
   const int g = bt.g0 + blockIdx.x;
   const int tid = threadIdx.x;
@@ -580,9 +611,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
 // Shared memory of one block running steps.
 template <int W, bool ENUM>
 struct LevelLds {
-  unsigned long long N[CC_MAXN * W];              // label-space adjacency
-  unsigned long long No[ENUM ? CC_MAXN * W : 1];  // original-id adjacency
-  int Perm[ENUM ? CC_MAXN : 1];
+  unsigned long long N[CC_ROWS(W) * W];              // label-space adjacency
+  unsigned long long No[ENUM ? CC_ROWS(W) * W : 1];  // original-id adjacency
+  int Perm[ENUM ? CC_ROWS(W) : 1];
   unsigned long long Pre[CC_SHARDS + 1];
   unsigned long long PreH0[ENUM ? CC_SHARDS + 1 : 1];
   unsigned long long PreH1[ENUM ? CC_SHARDS + 1 : 1];
@@ -1121,9 +1152,9 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
 // first, the loop is over (launch_step[1] = 0).  Launch 0 for host_done.
 template <int W, bool ENUM>
 struct HeadLds {
-  unsigned long long N[CC_MAXN * W];
-  unsigned long long No[ENUM ? CC_MAXN * W : 1];
-  int Perm[CC_MAXN];
+  unsigned long long N[CC_ROWS(W) * W];
+  unsigned long long No[ENUM ? CC_ROWS(W) * W : 1];
+  int Perm[CC_ROWS(W)];
   unsigned long long WaveTot[CC_HEAD_THREADS / CC_WAVE];
   unsigned long long Front[CC_HSLOTS];  // paths expanded per length
   unsigned long long Hist[CC_HSLOTS];   // cycles found per length (above 3)
@@ -1714,9 +1745,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
                                                   OutDev out, unsigned long long *hist_out,
                                                   int hist_stride, int count_front,
                                                   unsigned long long idle_timeout, BatchDev bt) {
-  __shared__ unsigned long long sN[BATCH ? 1 : CC_MAXN * W];
-  __shared__ unsigned long long sNo[ENUM ? CC_MAXN * W : 1];
-  __shared__ int sPerm[BATCH ? 1 : CC_MAXN];
+  __shared__ unsigned long long sN[BATCH ? 1 : CC_ROWS(W) * W];
+  __shared__ unsigned long long sNo[ENUM ? CC_ROWS(W) * W : 1];
+  __shared__ int sPerm[BATCH ? 1 : CC_ROWS(W)];
   __shared__ unsigned long long sHist[CC_HSLOTS];
   __shared__ unsigned long long sFront[CC_HSLOTS];
   __shared__ long long sCb[ENUM ? CC_HSLOTS : 1];
@@ -1761,7 +1792,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   unsigned int *my_mail = wk.mail + (size_t)wid * CC_MAIL;
   const unsigned long long maxc = (unsigned long long)max(wk.max_children, 1);
   const unsigned long long dmin = (unsigned long long)max(wk.donate_min, 2);
-  const unsigned int root_meta = ((unsigned)L << 16) | (1u << 24);
+  const unsigned int root_meta = ((unsigned)L << 16) | (1u << 31);
   // Claim size: up to CC_ROOT_CLAIM paths, but small enough that every
   // wavefront gets several claims when the handed-over frontier is small.
   const unsigned long long claim =
@@ -1987,7 +2018,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       n_path = bt.vtx_off[gid + 1] - vo;
     }
     if (valid) {
-      const int pv1 = m & 0xffu, pvt = (m >> 8) & 0xffu, pt = (m >> 16) & 0xffu;
+      const int pv1 = m & 0xffu, pvt = (m >> 8) & 0xffu, pt = (m >> 16) & 0x1ffu;
       if (pv1 >= n_path || pvt >= n_path || pt < 3 || pt > n_path) {
         dfs_corrupt(ctl, CC_DIAG_PATH, m);
         valid = false;
@@ -1996,8 +2027,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     if (!valid) m = 0;
     const int v1 = m & 0xffu;
     const int vt = (m >> 8) & 0xffu;
-    const int t = (m >> 16) & 0xffu;
-    const bool root = (m >> 24) != 0;
+    const int t = (m >> 16) & 0x1ffu;
+    const bool root = (m >> 31) != 0;
     const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
     const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
     Bits<W> nvt, nv1;
@@ -2237,12 +2268,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
 // breadth-first levels (summed over shards); longer ones, when the
 // depth-first kernel took over in enumerate mode, from its counting pass.
 // Count mode accumulates everything in the shards.  One block.
-__device__ void length_totals(CcCtl *ctl, bool enumerate, unsigned long long *sTot) {
+__device__ void length_totals(CcCtl *ctl, int n, bool enumerate, unsigned long long *sTot) {
   const int tid = threadIdx.x;
   for (int k = tid; k < CC_HSLOTS; k += blockDim.x) sTot[k] = 0ull;
   __syncthreads();
   const bool dfs = ld_relaxed(&ctl->mode) != 0;
-  const int kmax = (enumerate && dfs) ? ctl->bfs_max_len : CC_HSLOTS - 1;
+  // a run on n vertices uses the columns 0..n+1 (the only ones zeroed)
+  const int kmax = min((enumerate && dfs) ? ctl->bfs_max_len : CC_HSLOTS - 1, n + 1);
   for (int p = tid; p < CC_SHARDS * CC_HSLOTS; p += blockDim.x) {
     const int s = p / CC_HSLOTS, k = p - s * CC_HSLOTS;
     if (k <= kmax) {
@@ -2271,7 +2303,7 @@ __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
        i += (size_t)gridDim.x * blockDim.x)
     wk.mail[(i >> 2) * CC_MAIL + (i & 3)] = 0u;
   if (blockIdx.x != 0) return;
-  if (enum_bases) length_totals(ctl, true, sTot);
+  if (enum_bases) length_totals(ctl, n, true, sTot);
   if (threadIdx.x == 0) {
     ctl->root_cursor = 0;
     ctl->busy = 0;
@@ -2292,7 +2324,7 @@ __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
 // total vertex count.  One block.
 __global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
   __shared__ unsigned long long sTot[CC_HSLOTS];
-  length_totals(ctl, enumerate != 0, sTot);
+  length_totals(ctl, n, enumerate != 0, sTot);
   for (int k = threadIdx.x; k < CC_HSLOTS; k += blockDim.x) ctl->hist[k] = sTot[k];
   if (enumerate && threadIdx.x == 0) {
     // the closing offset of the output window
@@ -2309,6 +2341,12 @@ __global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+hipError_t cc_launch_zero_ctl(CcCtl *ctl, int n, hipStream_t s) {
+  const int cols = std::min(std::max(n, 0) + 2, CC_HSLOTS);
+  hipLaunchKernelGGL(k_zero_ctl, dim3(64), dim3(256), 0, s, ctl, cols);
+  return hipGetLastError();
+}
+
 hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
   const int blocks = (int)min((size_t)1024, (words + 255) / 256 + 1);
@@ -2316,38 +2354,112 @@ hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Each launcher picks the instantiation for W = 1, 2 or 4 words per bitset
+// (n <= 64, 128, 256); batches hold graphs of at most 128 vertices.
+#define CC_BY_W(W, F, ...)                                  \
+  ((W) == 1 ? F<1>(__VA_ARGS__)                             \
+   : (W) == 2 ? F<2>(__VA_ARGS__)                           \
+   : (W) == 4 ? F<4>(__VA_ARGS__) : hipErrorInvalidValue)
+
+namespace {
+template <int W>
+hipError_t launch_ingest(int n_graphs, const int *graph_vtx_off, int n_single, const int *row_ptr,
+                         const int *col_idx, unsigned long long *adj, unsigned long long *adj_orig,
+                         int *perm, int *label, unsigned int *status, long long *bound,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_ingest<W>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
+                     row_ptr, col_idx, adj, adj_orig, perm, label, status, bound);
+  return hipGetLastError();
+}
+template <int W>
+hipError_t launch_triplets_batch(BatchDev bt, int n_graphs, hipStream_t s) {
+  if (W > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_triplets_batch<W <= 2 ? W : 2>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
+  return hipGetLastError();
+}
+template <int W>
+hipError_t launch_triplets(bool en, GraphDev g, CcCtl *ctl, Frontier f3, Stage st, hipStream_t s) {
+  if (en) hipLaunchKernelGGL((k_triplets<W, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
+  else hipLaunchKernelGGL((k_triplets<W, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
+  return hipGetLastError();
+}
+template <int W>
+const void *levels_fn(bool en) {
+  return en ? (const void *)k_levels<W, true> : (const void *)k_levels<W, false>;
+}
+template <int W>
+hipError_t launch_levels(bool en, void **args, int blocks, hipStream_t s) {
+  return hipLaunchCooperativeKernel(levels_fn<W>(en), dim3(blocks), dim3(CC_BLOCK), args, 0, s);
+}
+template <int W>
+hipError_t levels_occupancy(bool en, int *per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, levels_fn<W>(en), CC_BLOCK, 0);
+}
+template <int W>
+const void *head_fn(bool en) {
+  return en ? (const void *)k_head<W, true> : (const void *)k_head<W, false>;
+}
+template <int W>
+hipError_t head_raise(bool en, size_t lds_bytes) {
+  return hipFuncSetAttribute(head_fn<W>(en), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds_bytes);
+}
+template <int W>
+hipError_t launch_head(bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b, OutDev out,
+                       int forced_level, int cap, size_t lds_bytes, unsigned int *host_done,
+                       hipStream_t s) {
+  dim3 gr(1), bl(CC_HEAD_THREADS);
+  if (en) hipLaunchKernelGGL((k_head<W, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
+  else hipLaunchKernelGGL((k_head<W, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
+  return hipGetLastError();
+}
+template <int W>
+hipError_t launch_step(bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b, OutDev out, int step,
+                       int forced_level, int max_children, int allow_two, int blocks,
+                       unsigned int *host_done, hipStream_t s) {
+  dim3 gr(blocks), bl(CC_BLOCK);
+  if (en) hipLaunchKernelGGL((k_step<W, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
+  else hipLaunchKernelGGL((k_step<W, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
+  return hipGetLastError();
+}
+template <int W>
+hipError_t launch_dfs(bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1, DfsWork wk,
+                      OutDev out, unsigned long long *hist_out, int hist_stride, int cf,
+                      int blocks, unsigned long long idle_timeout, hipStream_t s) {
+  dim3 gr(blocks), bl(CC_BLOCK);
+  const BatchDev nb{};
+  if (en) hipLaunchKernelGGL((k_dfs<W, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
+  else hipLaunchKernelGGL((k_dfs<W, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
+  return hipGetLastError();
+}
+template <int W>
+hipError_t launch_dfs_batch(GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,
+                            unsigned long long idle_timeout, hipStream_t s) {
+  if (W > 2) return hipErrorInvalidValue;
+  dim3 gr(blocks), bl(CC_BLOCK);
+  const Frontier nf{};
+  const OutDev no{};
+  hipLaunchKernelGGL((k_dfs<W <= 2 ? W : 2, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n_single,
                             const int *row_ptr, const int *col_idx, unsigned long long *adj,
                             unsigned long long *adj_orig, int *perm, int *label,
                             unsigned int *status, long long *bound, hipStream_t s) {
-  if (W == 1)
-    hipLaunchKernelGGL(k_ingest<1>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
-                       row_ptr, col_idx, adj, adj_orig, perm, label, status, bound);
-  else
-    hipLaunchKernelGGL(k_ingest<2>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
-                       row_ptr, col_idx, adj, adj_orig, perm, label, status, bound);
-  return hipGetLastError();
+  return CC_BY_W(W, launch_ingest, n_graphs, graph_vtx_off, n_single, row_ptr, col_idx, adj,
+                 adj_orig, perm, label, status, bound, s);
 }
 
 hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s) {
   if (n_graphs <= 0) return hipSuccess;
-  if (W == 1)
-    hipLaunchKernelGGL(k_triplets_batch<1>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
-  else
-    hipLaunchKernelGGL(k_triplets_batch<2>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
-  return hipGetLastError();
+  return CC_BY_W(W, launch_triplets_batch, bt, n_graphs, s);
 }
 
 hipError_t cc_launch_triplets(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f3, Stage st,
                               hipStream_t s) {
-  if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_triplets<1, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
-    else hipLaunchKernelGGL((k_triplets<1, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
-  } else {
-    if (en) hipLaunchKernelGGL((k_triplets<2, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
-    else hipLaunchKernelGGL((k_triplets<2, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
-  }
-  return hipGetLastError();
+  return CC_BY_W(W, launch_triplets, en, g, ctl, f3, st, s);
 }
 
 hipError_t cc_launch_levels(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
@@ -2358,16 +2470,12 @@ hipError_t cc_launch_levels(int W, bool en, GraphDev g, CcCtl *ctl, const LevelB
   int allow_two = two ? 1 : 0;
   void *args[] = {&g,           &ctl,       &bb, &out, &forced_level, &max_children,
                   &allow_two,   &barrier_timeout, &clock};
-  const void *fn = W == 1 ? (en ? (const void *)k_levels<1, true> : (const void *)k_levels<1, false>)
-                          : (en ? (const void *)k_levels<2, true> : (const void *)k_levels<2, false>);
-  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(CC_BLOCK), args, 0, s);
+  return CC_BY_W(W, launch_levels, en, args, blocks, s);
 }
 
 int cc_levels_max_blocks(int W, bool en) {
-  const void *fn = W == 1 ? (en ? (const void *)k_levels<1, true> : (const void *)k_levels<1, false>)
-                          : (en ? (const void *)k_levels<2, true> : (const void *)k_levels<2, false>);
   int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CC_BLOCK, 0) != hipSuccess ||
+  if (CC_BY_W(W, levels_occupancy, en, &per_cu) != hipSuccess ||
       hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
@@ -2386,80 +2494,49 @@ hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBuf
                           OutDev out, int forced_level, size_t lds_bytes,
                           unsigned int *host_done, hipStream_t s) {
   const int cap = cc_head_capacity(W, en, lds_bytes);
-  dim3 gr(1), bl(CC_HEAD_THREADS);
   // The dynamic LDS limit is raised once per device and instantiation (the
   // call costs host time that would otherwise stall the stream).
-  static std::atomic<size_t> raised[64][4];
+  static std::atomic<size_t> raised[64][6];
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  const int which = (W == 1 ? 0 : 2) + (en ? 1 : 0);
+  const int which = (W == 1 ? 0 : W == 2 ? 2 : 4) + (en ? 1 : 0);
   if (dev >= 0 && dev < 64 && raised[dev][which].load() < lds_bytes) {
-    const void *fn = W == 1 ? (en ? (const void *)k_head<1, true> : (const void *)k_head<1, false>)
-                            : (en ? (const void *)k_head<2, true> : (const void *)k_head<2, false>);
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    e = CC_BY_W(W, head_raise, en, lds_bytes);
     if (e != hipSuccess) return e;
     raised[dev][which].store(lds_bytes);
   }
-  if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_head<1, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
-    else hipLaunchKernelGGL((k_head<1, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
-  } else {
-    if (en) hipLaunchKernelGGL((k_head<2, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
-    else hipLaunchKernelGGL((k_head<2, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
-  }
-  return hipGetLastError();
+  return CC_BY_W(W, launch_head, en, g, ctl, b, out, forced_level, cap, lds_bytes, host_done, s);
 }
 
 // Static shared memory of the head kernel (so the caller can size the
 // dynamic part).
 size_t cc_head_static_lds(int W, bool en) {
-  return W == 1 ? (en ? sizeof(HeadLds<1, true>) : sizeof(HeadLds<1, false>))
-                : (en ? sizeof(HeadLds<2, true>) : sizeof(HeadLds<2, false>));
+  switch (W) {
+    case 1: return en ? sizeof(HeadLds<1, true>) : sizeof(HeadLds<1, false>);
+    case 2: return en ? sizeof(HeadLds<2, true>) : sizeof(HeadLds<2, false>);
+    default: return en ? sizeof(HeadLds<4, true>) : sizeof(HeadLds<4, false>);
+  }
 }
 
 hipError_t cc_launch_step(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
                           OutDev out, int step, int forced_level, int max_children, bool two,
                           int blocks, unsigned int *host_done, hipStream_t s) {
-  dim3 gr(blocks), bl(CC_BLOCK);
-  const int allow_two = two ? 1 : 0;
-  if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_step<1, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
-    else hipLaunchKernelGGL((k_step<1, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
-  } else {
-    if (en) hipLaunchKernelGGL((k_step<2, true>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
-    else hipLaunchKernelGGL((k_step<2, false>), gr, bl, 0, s, g, ctl, b, out, step, forced_level, max_children, allow_two, host_done);
-  }
-  return hipGetLastError();
+  return CC_BY_W(W, launch_step, en, g, ctl, b, out, step, forced_level, max_children,
+                 two ? 1 : 0, blocks, host_done, s);
 }
 
 hipError_t cc_launch_dfs(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
                          DfsWork wk, OutDev out, unsigned long long *hist_out,
                          int hist_stride, bool count_front, int blocks,
                          unsigned long long idle_timeout, hipStream_t s) {
-  dim3 gr(blocks), bl(CC_BLOCK);
-  const int cf = count_front ? 1 : 0;
-  const BatchDev nb{};
-  if (W == 1) {
-    if (en) hipLaunchKernelGGL((k_dfs<1, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
-    else hipLaunchKernelGGL((k_dfs<1, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
-  } else {
-    if (en) hipLaunchKernelGGL((k_dfs<2, true, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
-    else hipLaunchKernelGGL((k_dfs<2, false, false>), gr, bl, 0, s, g, ctl, f0, f1, wk, out, hist_out, hist_stride, cf, idle_timeout, nb);
-  }
-  return hipGetLastError();
+  return CC_BY_W(W, launch_dfs, en, g, ctl, f0, f1, wk, out, hist_out, hist_stride,
+                 count_front ? 1 : 0, blocks, idle_timeout, s);
 }
 
 hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,
                                unsigned long long idle_timeout, hipStream_t s) {
-  dim3 gr(blocks), bl(CC_BLOCK);
-  const Frontier nf{};
-  const OutDev no{};
-  if (W == 1)
-    hipLaunchKernelGGL((k_dfs<1, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
-  else
-    hipLaunchKernelGGL((k_dfs<2, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
-  return hipGetLastError();
+  return CC_BY_W(W, launch_dfs_batch, g, ctl, wk, bt, blocks, idle_timeout, s);
 }
 
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s) {

@@ -15,6 +15,9 @@
 #include "cc.h"
 #include "cc_internal.h"
 
+static_assert(CC_BATCH_MAXN == CC_MAX_BATCH_VERTICES, "batch vertex limit");
+static_assert(CC_MAXN == CC_MAX_VERTICES, "vertex limit");
+
 namespace {
 
 constexpr int64_t kDefaultBudget = 4ll << 30;
@@ -31,7 +34,7 @@ struct DeviceInfo {
   int cus = 0;
   bool coop = false;  // cooperative launches supported
   unsigned long long clock_hz = 0;
-  size_t head_lds = 0;  // dynamic LDS bytes of the head kernel
+  size_t lds_block = 0;  // LDS a block may hold
 };
 
 std::mutex g_dev_mu;
@@ -62,8 +65,7 @@ cc_status device_info(int dev, DeviceInfo *out) {
     // may hold, less the kernel's static part and a margin
     int lds = 0;
     (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    const size_t stat = std::max(cc_head_static_lds(1, true), cc_head_static_lds(2, true));
-    g_dev[dev].head_lds = lds > (int)stat + 4096 ? (size_t)lds - stat - 4096 : 0;
+    g_dev[dev].lds_block = lds > 0 ? (size_t)lds : 0;
     g_dev[dev].coop = coop != 0;
     g_dev[dev].cus = p.multiProcessorCount;
     g_dev[dev].clock_hz = (unsigned long long)rate_khz * 1000ull;
@@ -132,6 +134,7 @@ struct cc_graph {
   hipEvent_t evp[2 * CC_MAXN + 8] = {};  // CC_PROFILE: around each kernel group
   bool have_run = false;
   bool hist_ok = false;  // hist/front hold the results of a complete run
+  int64_t pairs = 0;     // sum over vertices of C(deg, 2)
   int64_t hist[CC_HSLOTS]{};
   double level_ms[CC_HSLOTS]{};  // CC_PROFILE: per-level device time
   int64_t front[CC_HSLOTS]{};
@@ -265,8 +268,10 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   // staged cycle in each of the four staging buffers
   const size_t per_unit = 2 * ((size_t)W * 8 * (en ? 2 : 1) + 2) + (en ? 4 * (size_t)W * 8 : 0);
   unsigned long long cap_s = (unsigned long long)budget / per_unit / CC_SHARDS;
-  // stage one writes every initial triplet (at most C(n,3)) round-robin
-  const unsigned long long min_cap_s = (unsigned long long)choose3(n) / CC_SHARDS + CC_CHUNK;
+  // stage one writes every initial triplet (at most sum C(deg, 2), counted
+  // by the ingest) round-robin over the shards
+  const unsigned long long min_cap_s =
+      (unsigned long long)std::min<int64_t>(g->pairs, choose3(n)) / CC_SHARDS + CC_CHUNK;
   cap_s = align_up(std::max(cap_s, min_cap_s), 64);
   const unsigned long long cap = cap_s * CC_SHARDS;
   const size_t buf_bytes = align_up(frontier_bytes(cap_s, W, en), 1 << 16);
@@ -343,7 +348,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
                            : 0;
   const bool persistent = coop_max >= CC_SHARDS;
   chk(hipEventRecord(g->ev0, s));
-  chk(cc_launch_zero(ctl, sizeof(CcCtl), s));
+  chk(cc_launch_zero_ctl(ctl, n, s));
   // Stage one: its own kernel before the persistent loop; inside the head
   // kernel (launch 0) otherwise.
   mark(0);
@@ -379,7 +384,11 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     // frontier in LDS; each later launch runs one step, so n - 2 of them
     // are enough.
     mark(2);
-    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, g->dev.head_lds, g->d_done, s));
+    // the head's dynamic LDS: what a block may hold, less the kernel's
+    // static part and a margin
+    const size_t stat = cc_head_static_lds(W, en) + 4096;
+    const size_t head_lds = g->dev.lds_block > stat ? g->dev.lds_block - stat : 0;
+    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, head_lds, g->d_done, s));
     mark(3);
     ++levels;
     for (int launch = 1; launch < n - 1 && e == hipSuccess; ++launch, ++levels) {
@@ -616,8 +625,8 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   if (opt) g->opt = *opt;
   g->stream = (hipStream_t)g->opt.stream;
   g->n = n;
-  g->W = n <= 64 ? 1 : 2;
-  const size_t adj_b = align_up((size_t)CC_MAXN * 2 * 8, 256);
+  g->W = n <= 64 ? 1 : n <= 128 ? 2 : 4;
+  const size_t adj_b = align_up((size_t)CC_MAXN * 4 * 8, 256);  // n rows of W <= 4 words
   const size_t vec_b = align_up((size_t)CC_MAXN * 4, 256);
   const size_t ctl_b = align_up(sizeof(CcCtl), 256);
   // staging for a host CSR (at most CC_MAXN rows and CC_MAXN (CC_MAXN - 1)
@@ -675,15 +684,19 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
     d_rp = st_rp;
     d_ci = st_ci;
   }
+  // status word, then (8 bytes on) the sum over vertices of C(deg, 2),
+  // which bounds the initial triplets and triangles
+  long long *d_pairs = (long long *)((char *)g->d_status + 8);
   hipError_t e = cc_launch_ingest(g->W, 1, nullptr, n, d_rp, d_ci, g->d_adj, g->d_adj_orig, g->d_perm,
-                                  g->d_label, g->d_status, nullptr, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(&g->h_ctl->status, g->d_status, 4, hipMemcpyDeviceToHost, s);
+                                  g->d_label, g->d_status, d_pairs, s);
+  unsigned long long back[2] = {0ull, 0ull};
+  if (e == hipSuccess) e = hipMemcpyAsync(back, g->d_status, 16, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(hip_err(e));
-  const unsigned int stv = g->h_ctl->status;
+  const unsigned int stv = (unsigned int)back[0];
   if ((stv & 0xffu) != 0u || !(stv & 0x100u)) return fail(CC_ERR_NOT_SIMPLE);
   g->max_deg = (int)(stv >> 16);
+  g->pairs = (int64_t)back[1];
   *out = g;
   return CC_OK;
 }
@@ -959,7 +972,7 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   for (int g = 0; g < n_graphs; ++g) {
     const int ng = off[g + 1] - off[g];
     if (ng < 0) return CC_ERR_INVALID_ARG;
-    if (ng > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
+    if (ng > CC_BATCH_MAXN) return CC_ERR_TOO_LARGE;
     max_n = std::max(max_n, ng);
   }
   const int32_t N = off[n_graphs];
@@ -1274,7 +1287,7 @@ size_t a256(size_t x) { return align_up(x, 256); }
 
 cc_status slot_alloc(cc_server *sv, ServeSlot &sl) {
   const ccserve::Capacity &c = sv->cap;
-  const size_t G = (size_t)c.graphs, V = (size_t)c.vertices + CC_MAXN, E = (size_t)c.entries,
+  const size_t G = (size_t)c.graphs, V = (size_t)c.vertices + CC_BATCH_MAXN, E = (size_t)c.entries,
                R = (size_t)c.roots;
   const size_t dev_fixed = a256((G + 1) * 4) + a256((V + 1) * 4) + a256(E * 4) +
                            2 * a256((G + 1) * 8) + 2 * a256(V * 2 * 8) + 2 * a256(V * 4) +
@@ -1521,7 +1534,7 @@ cc_status cc_server_create(const cc_server_options *opt, cc_server **out) {
   sv->dev = di;
   sv->opt = o;
   sv->cap.graphs = o.max_batch_graphs;
-  sv->cap.vertices = (int64_t)o.max_batch_graphs * CC_MAX_VERTICES;
+  sv->cap.vertices = (int64_t)o.max_batch_graphs * CC_BATCH_MAXN;
   sv->cap.entries = std::max<int64_t>((int64_t)o.max_batch_graphs * 1024, 1 << 20);
   sv->cap.roots = o.slot_root_slots;
   sv->slots.resize((size_t)o.slots);
@@ -1540,7 +1553,7 @@ cc_status cc_server_create(const cc_server_options *opt, cc_server **out) {
 cc_status cc_server_submit(cc_server *sv, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                            int64_t *request_id) {
   if (!sv || !request_id || n < 0 || (n > 0 && !row_ptr)) return CC_ERR_INVALID_ARG;
-  if (n > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
+  if (n > CC_MAX_BATCH_VERTICES) return CC_ERR_TOO_LARGE;
   const int32_t nnz = n > 0 ? row_ptr[n] : 0;
   if (n > 0 && (row_ptr[0] != 0 || nnz < 0 || (int64_t)nnz > (int64_t)n * (n - 1)))
     return CC_ERR_NOT_SIMPLE;

@@ -66,6 +66,12 @@ def full_parity(cc, g, **kw):
     return info
 
 
+def four_word_union():
+    """256 vertices, ids permuted: two 6x8 grids, two 5x6 grids and C_100."""
+    g = gg.disjoint_union(gg.grid(6, 8), gg.grid(6, 8), gg.grid(5, 6), gg.grid(5, 6), gg.cycle(100))
+    return gg.permute_random(g, np.random.default_rng(256))
+
+
 def small_suite():
     rng = np.random.default_rng(4242)
     out = [gg.cycle(3), gg.cycle(4), gg.cycle(64), gg.cycle(65), gg.cycle(128),
@@ -74,6 +80,11 @@ def small_suite():
            gg.complete_multipartite(3, 4, 5), gg.grid(5, 6), gg.grid(6, 6), gg.grid(4, 10),
            gg.permute_random(gg.grid(5, 10), rng), gg.path_graph(30), gg.random_tree(60, rng),
            gg.cone(gg.cycle(20)), gg.disjoint_union(gg.grid(4, 4), gg.wheel(5), gg.complete(4))]
+    # More than 128 vertices: four-word bitsets
+    out += [gg.cycle(200), gg.cycle(256), gg.wheel(150), gg.cone(gg.cycle(150)),
+            gg.disjoint_union(gg.grid(5, 6), gg.grid(6, 6), gg.grid(4, 10), gg.grid(3, 10)),
+            gg.permute_random(gg.disjoint_union(gg.grid(6, 8), gg.grid(5, 7), gg.cycle(100)), rng),
+            four_word_union()]
     # Sparse enough that the oracle finishes in seconds; n > 64 exercises
     # two-word bitsets.
     for n, m in [(10, 20), (14, 30), (30, 60), (40, 100), (63, 120), (64, 128), (65, 130),
@@ -359,3 +370,26 @@ def test_length_window_errors_and_pages(cc):
         assert all(np.array_equal(groups[kk], want[kk]) for kk in want)
         with pytest.raises(ValueError):
             list(h.pages(max_verts=biggest - 1))
+
+
+# ------------------------------------------------ more than 128 vertices
+@pytest.mark.parametrize("level", [3, 5, 9])
+def test_four_word_forced_depth_first(cc, level):
+    info = full_parity(cc, four_word_union(), force_dfs_level=level)
+    assert info["switch_level"] == level
+
+
+def test_four_word_budget_switch_and_windows(cc):
+    g = four_word_union()
+    info = full_parity(cc, g, budget_bytes=1 << 20)
+    assert info["switch_level"] > 3
+    want = canonical_groups(*oracle_run(g).cycles)
+    got = window_groups(cc, g, [(0, 6), (7, 12), (13, 300)])
+    assert sorted(got) == sorted(want)
+    assert all(np.array_equal(got[k], want[k]) for k in want)
+
+
+def test_too_large_graph_rejected(cc):
+    with pytest.raises(cc.CCError) as ei:
+        cc.prepare(gg.cycle(257))
+    assert ei.value.status == cc.CC_ERR_TOO_LARGE
