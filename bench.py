@@ -294,6 +294,40 @@ def paging_section():
             "whole_ms": w, "page_limit_vertex_ids": limit, "pages": pages, "paged_ms": p}
 
 
+def large_n_section():
+    """Graphs of more than 128 vertices (four-word bitsets), full enumeration
+    with CSR and results on the device: C_256, and 256 vertices made of two
+    6x8 grids, two 5x6 grids and C_100 with ids permuted."""
+    import torch
+
+    from paper_1410_4876_amd import cc
+    from paper_1410_4876_amd import graphgen as gg
+
+    union = gg.permute_random(gg.disjoint_union(gg.grid(6, 8), gg.grid(6, 8), gg.grid(5, 6),
+                                                gg.grid(5, 6), gg.cycle(100)),
+                              np.random.default_rng(256))
+    out = []
+    for g in [gg.cycle(256), union]:
+        rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
+        ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
+        with cc.Graph(g.n, rp, ci) as h:
+            hist = h.histogram()
+        nc = int(hist.sum())
+        nv = int((hist * np.arange(hist.size)).sum())
+        dv = torch.empty(max(nv, 1), dtype=torch.int32, device="cuda")
+        do = torch.empty(nc + 1, dtype=torch.int64, device="cuda")
+
+        def proc():
+            with cc.Graph(g.n, rp, ci) as h:
+                h.enumerate_into(dv, do)
+            torch.cuda.synchronize()
+
+        t = _timed(proc)
+        out.append({"graph": g.name, "n": g.n, "m": g.m, "cycles": nc, "proc_ms": t,
+                    "cycles_per_s": round(nc / (t["median"] * 1e-3), 1)})
+    return {"rows": out}
+
+
 def serving_section(args):
     """Open-loop Poisson request stream (2000 requests/s; half p x q grids,
     p, q in 3..7, half ER graphs, n in 20..80, d in [3, 5]) replayed against
@@ -331,7 +365,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the ER G(40,100) latency, 7x12 count-only and paging sections")
     ap.add_argument("--section",
-                    choices=["er40", "grid7x12", "paging", "table1", "batched", "serving"],
+                    choices=["er40", "grid7x12", "paging", "large_n", "table1", "batched",
+                             "serving"],
                     help="run only this section and print its JSON (for profiling one workload)")
     ap.add_argument("--no-profile", action="store_true",
                     help="time steps without per-kernel HIP events (no roofline)")
@@ -350,6 +385,7 @@ def main():
     torch.cuda.set_device(0)
     if args.section:
         fn = {"er40": er40_section, "grid7x12": grid7x12_section, "paging": paging_section,
+              "large_n": large_n_section,
               "table1": lambda: table1_section(args), "batched": lambda: batched_section(args),
               "serving": lambda: serving_section(args)}[args.section]
         print(json.dumps({args.section: fn()}), flush=True)
@@ -465,6 +501,7 @@ def main():
         out["er40"] = er40_section()
         out["grid7x12"] = grid7x12_section()
         out["paging"] = paging_section()
+        out["large_n"] = large_n_section()
     if not args.no_table1:
         out["table1"] = table1_section(args)
     if not args.no_cpu_baseline:

@@ -2,7 +2,7 @@
 //
 // Vertices are renumbered by their degree label (Section 2), so "label
 // greater than the label of v2" is an integer comparison and every vertex
-// set is a W-word bitset (W = ceil(n / 64), n <= 128).  An open chordless
+// set is a W-word bitset (W = 1, 2 or 4 for n <= 64, 128, 256).  An open chordless
 // path p = <v1, ..., vt> is carried as (X, S, v1, vt) where
 //   X = N(v2) U ... U N(v(t-1)) U {w : w <= v2}   (the exclusion set)
 //   S = {v1, ..., vt}                               (enumerate mode only)
