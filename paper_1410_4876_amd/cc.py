@@ -257,7 +257,14 @@ class Graph:
         h = np.zeros(self.n + 1, np.int64)
         _check(lib().cc_histogram(self.h, ctypes.c_void_p(h.ctypes.data), h.size), "cc_histogram",
                self._info_fn)
+        self._hist = h.copy()
         return h
+
+    def _sizes(self) -> np.ndarray:
+        """The histogram, from an earlier call when there was one (it only
+        depends on the graph)."""
+        h = getattr(self, "_hist", None)
+        return h.copy() if h is not None else self.histogram()
 
     def enumerate_into(self, verts, offsets):
         """Fill caller buffers (torch device tensors when the graph was
@@ -319,7 +326,7 @@ class Graph:
         """The cycles of k_min..k_max vertices, sized exactly from the
         histogram: (verts, offsets) as torch tensors (output_device=True)
         or numpy arrays."""
-        h = self.histogram()
+        h = self._sizes()
         k = np.arange(h.size)
         sel = (k >= k_min) & (k <= k_max)
         nc = int(h[sel].sum())
@@ -340,7 +347,7 @@ class Graph:
         cycle lengths, each holding at most max_verts vertex ids (and
         max_cycles cycles): the whole output in pieces that fit a bounded
         buffer.  Raises ValueError if a single length does not fit."""
-        h = self.histogram()
+        h = self._sizes()
         lens = [k for k in range(h.size) if h[k]]
         i = 0
         while i < len(lens):

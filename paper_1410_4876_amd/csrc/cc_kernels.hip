@@ -2275,12 +2275,27 @@ __device__ void length_totals(CcCtl *ctl, int n, bool enumerate, unsigned long l
   const bool dfs = ld_relaxed(&ctl->mode) != 0;
   // a run on n vertices uses the columns 0..n+1 (the only ones zeroed)
   const int kmax = min((enumerate && dfs) ? ctl->bfs_max_len : CC_HSLOTS - 1, n + 1);
-  for (int p = tid; p < CC_SHARDS * CC_HSLOTS; p += blockDim.x) {
-    const int s = p / CC_HSLOTS, k = p - s * CC_HSLOTS;
-    if (k <= kmax) {
-      const unsigned long long v = ld_relaxed(&ctl->hist_sh[s][k]);
-      if (v) atomicAdd(&sTot[k], v);
+  // the shard counters of the used columns, several loads in flight per
+  // thread before their sums go into LDS
+  constexpr int PER = 8;
+  const int cols = max(kmax + 1, 0), total = CC_SHARDS * cols;
+  for (int base = tid; base < total; base += blockDim.x * PER) {
+    unsigned long long v[PER];
+    int kk[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int p = base + j * (int)blockDim.x;
+      kk[j] = -1;
+      v[j] = 0ull;
+      if (p < total) {
+        const int s = p / cols;
+        kk[j] = p - s * cols;
+        v[j] = ld_relaxed(&ctl->hist_sh[s][kk[j]]);
+      }
     }
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      if (kk[j] >= 0 && v[j]) atomicAdd(&sTot[kk[j]], v[j]);
   }
   __syncthreads();
   if (enumerate && dfs)
