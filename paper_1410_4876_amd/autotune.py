@@ -17,7 +17,7 @@ import time
 import numpy as np
 
 DEFAULT_GRID = {
-    "dfs_waves_per_cu": [8, 16, 24, 32],
+    "dfs_waves_per_cu": [8, 12, 16, 24, 32],
     "dfs_donate_min": [64, 128, 256],
     "dfs_claim": [0, 128, 1024],
 }
@@ -46,19 +46,20 @@ def _load_cache(path):
 def tune_batch(workload_class: str = "er_n16-64_d2.5-5", calibration=None, grid=None,
                repeats: int = 2, force: bool = False, cache_path: str | None = None) -> dict:
     """Best options for batched runs of `workload_class`.  `calibration` is a
-    graphgen.Batch (default: 512 ER graphs shaped like the 4096-graph
-    workload, seed index 1004).  Returns {"options": {...}, "ms": best,
+    graphgen.Batch (default: 4096 ER graphs shaped like the 4096-graph
+    workload, seed index 1004; a smaller calibration batch has too little
+    work per wavefront and favours too few wavefronts).  Returns {"options": {...}, "ms": best,
     "table": [...]}."""
     from . import cc
     from . import graphgen as gg
 
     cache_path = cache_path or _cache_path()
-    key = f"{_device_key()}|{workload_class}"
+    key = f"{_device_key()}|{workload_class}|cal4096"
     cache = _load_cache(cache_path)
     if key in cache and not force:
         return cache[key]
     if calibration is None:
-        calibration = gg.pack_batch(gg.er_batch_graphs(512, k=1004))
+        calibration = gg.pack_batch(gg.er_batch_graphs(4096, k=1004))
     grid = grid or DEFAULT_GRID
     names = list(grid)
     table = []
