@@ -80,7 +80,7 @@ typedef struct cc_options {
   uint32_t flags;                /* CC_* flags above                                     */
   int32_t dfs_level;             /* with CC_FORCE_DFS: path length t >= 3 whose frontier
                                     is handed to the depth-first kernel                  */
-  int32_t dfs_waves_per_cu;      /* depth-first kernel occupancy; 0 = default            */
+  int32_t dfs_waves_per_cu;      /* depth-first kernel occupancy; 0 = default (24)       */
   int32_t bfs_blocks;            /* grid of the level kernel; 0 = default                */
   int32_t dfs_donate_min;        /* depth-first: a wavefront donates work to idle ones once
                                     it holds at least this many paths; 0 = default      */

@@ -304,7 +304,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   }
 
   const int maxc = std::max(1, g->max_deg - 1);
-  int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 16;
+  int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 24;
   waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
   const int want_waves = std::max(4, (g->dev.cus * waves_per_cu) / 4 * 4);
   // the counting pass (wc) and, in enumerate mode, the writing pass (we)
@@ -1083,7 +1083,7 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
   const int dstride = b->max_n + 2;
   const unsigned long long rcap = std::max<long long>(b->root_off[G], 1);
   const int maxc = std::max(1, b->max_deg - 1);
-  int waves_per_cu = b->opt.dfs_waves_per_cu > 0 ? b->opt.dfs_waves_per_cu : 16;
+  int waves_per_cu = b->opt.dfs_waves_per_cu > 0 ? b->opt.dfs_waves_per_cu : 24;
   waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
   const bool per_graph = mode == CC_BATCH_PER_GRAPH;
   // per-graph launches use a small grid: at most 64 blocks per graph
