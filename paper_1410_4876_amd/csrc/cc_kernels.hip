@@ -146,16 +146,40 @@ __device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, CC_WAVE);
   return v;
 }
+// Sum over a fully active wavefront by data-parallel moves, the same
+// pattern as wave_min_u32 below (butterflies within rows, then row
+// broadcasts), returned to every lane from lane 63.
+__device__ __forceinline__ unsigned wave_sum_u32_full(unsigned v) {
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+  return (unsigned)__builtin_amdgcn_readlane((int)v, CC_WAVE - 1);
+}
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, CC_WAVE);
   return v;
 }
-__device__ __forceinline__ unsigned int wave_min_u32(unsigned int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, CC_WAVE));
-  return v;
+// Minimum over the wavefront by data-parallel primitives (cross-lane moves
+// inside the vector ALU, no LDS round trip): within quads, half-rows and
+// rows of 16 lanes, then row 0 into row 1 and row 2 into row 3, then the
+// lower half into the upper; lane 63 ends with the minimum, which is
+// returned to every lane.  Lanes a move does not write keep the identity.
+// The whole wavefront must be active.
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+  const int id = -1;  // 0xffffffff
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0xb1, 0xf, 0xf, false));   // quad 1,0,3,2
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x4e, 0xf, 0xf, false));   // quad 2,3,0,1
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xf, 0xf, false));  // half-row mirror
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xf, 0xf, false));  // row mirror
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x142, 0xa, 0xf, false));  // row bcast 15
+  v = min(v, (unsigned)__builtin_amdgcn_update_dpp(id, (int)v, 0x143, 0xc, 0xf, false));  // row bcast 31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, CC_WAVE - 1);
 }
+
 __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v) {
   return __shfl(v, 0, CC_WAVE);
 }
@@ -253,6 +277,30 @@ __device__ __forceinline__ int shard_of(const unsigned long long *pre, unsigned 
     else hi = mid;
   }
   return lo;
+}
+
+// Lane l's value of v, in scalar registers (l uniform).
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// For a wavefront whose lanes hold the consecutive indices b + lane (b
+// uniform), with lane s holding end = pre[s + 1]: when one shard holds all
+// of b .. b+63, sets `base` so that index b + lane is element base + lane
+// of the sharded array (cap_s per shard) and returns true; otherwise the
+// lanes look their shards up one by one (shard_of).  Called by a whole
+// wavefront.
+__device__ __forceinline__ bool run_in_one_shard(unsigned long long end, unsigned long long b,
+                                                 unsigned long long cap_s,
+                                                 unsigned long long &base) {
+  const int s = (int)__popcll(wave_ballot(end <= b));  // shards ending at or before b
+  if (s >= CC_SHARDS) return false;
+  if (b + CC_WAVE > lane_u64(end, s)) return false;
+  const unsigned long long p = lane_u64(end, s > 0 ? s - 1 : 0);
+  base = (unsigned long long)s * cap_s + b - (s > 0 ? p : 0ull);
+  return true;
 }
 
 // -------------------------------------------------------------- decoding
@@ -368,14 +416,22 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
     }
     Bits<W> r = bzero<W>();
     bool bad = false;
-    for (long long e = a; e < b && !bad; ++e) {
-      const int w = ci[e] - v0;
-      if (w < 0 || w >= n || w == v) {
-        bad = true;
-        break;
+    // four neighbour ids in flight per round
+    for (long long e = a; e < b && !bad; e += 4) {
+      int w4[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w4[k] = e + k < b ? ci[e + k] - v0 : -1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (e + k >= b || bad) continue;
+        const int w = w4[k];
+        if (w < 0 || w >= n || w == v) {
+          bad = true;
+        } else {
+          bad = btest(r, w);
+          r = bor(r, bsingle<W>(w));
+        }
       }
-      bad = btest(r, w);
-      r = bor(r, bsingle<W>(w));
     }
     if (bad) atomicOr(&sErr, CC_DEV_NOT_SIMPLE);
 #pragma unroll
@@ -403,11 +459,13 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
     // the minimum degree, then the smallest id
     int deg[W];
     bool alive[W];
+    Bits<W> nb[W];  // the lane's rows, kept in registers for all rounds
 #pragma unroll
     for (int j = 0; j < W; ++j) {
       const int v = tid + CC_WAVE * j;
       alive[j] = v < n;
-      deg[j] = alive[j] ? bpop(row<W>(sA, v)) : 0;
+      nb[j] = alive[j] ? row<W>(sA, v) : bzero<W>();
+      deg[j] = bpop(nb[j]);
     }
     for (int i = 0; i < n; ++i) {
       unsigned mine = 0xffffffffu;
@@ -423,7 +481,7 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
           alive[j] = false;
           sLab[u] = i;
         }
-        if (alive[j] && btest(row<W>(sA, v), u)) --deg[j];
+        if (alive[j] && btest(nb[j], u)) --deg[j];
       }
     }
   }
@@ -674,10 +732,10 @@ __device__ __forceinline__ void reserve(LevelLds<W, ENUM> &L, unsigned a, unsign
                                         unsigned &wa, unsigned &wb, unsigned &wc) {
   constexpr int NW = CC_BLOCK / CC_WAVE;
   const int wave = threadIdx.x / CC_WAVE;
-  wa = wave_sum_u32(a);
-  wb = wave_sum_u32(b);
-  wc = wave_sum_u32(c);
-  const unsigned wd = wave_sum_u32(d);
+  wa = wave_sum_u32_full(a);
+  wb = wave_sum_u32_full(b);
+  wc = wave_sum_u32_full(c);
+  const unsigned wd = wave_sum_u32_full(d);
   if (lane_id() == 0) {
     L.WaveA[wave] = wa;
     L.WaveB[wave] = wb;
@@ -738,12 +796,20 @@ __device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st
   vb -= out.vshift;
   const int lane = lane_id();
   const unsigned long long per = (unsigned long long)min(CC_WAVE, CC_DEC_WORDS / k);
+  const unsigned long long end = pre[lane + 1];
   for (unsigned long long g0 = gw * per; g0 < h; g0 += nwg * per) {
     const unsigned long long nb = min(per, h - g0);
     const unsigned long long gi = g0 + (unsigned long long)lane;
+    unsigned long long rb = 0;
+    const bool one = run_in_one_shard(end, g0, st.cap_s, rb);
     if ((unsigned long long)lane < nb) {
-      const int s = shard_of(pre, gi);
-      const unsigned long long e = (unsigned long long)s * st.cap_s + (gi - pre[s]);
+      unsigned long long e;
+      if (one) {
+        e = rb + (unsigned long long)lane;
+      } else {
+        const int s = shard_of(pre, gi);
+        e = (unsigned long long)s * st.cap_s + (gi - pre[s]);
+      }
       Bits<W> C;
 #pragma unroll
       for (int w = 0; w < W; ++w) C.w[w] = st.C[w * st.cap + e];
@@ -833,6 +899,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   const int flags = L.Flags | L.FlagsH[0] | L.FlagsH[1];
   const unsigned long long cnt = L.Pre[CC_SHARDS];
   const unsigned vblk = blockIdx.x, vgrid = gridDim.x;
+  const unsigned long long shard_end = L.Pre[lane + 1];  // lane s: end of input shard s
   if (blockIdx.x == 0 && tid == 0) {
     if (step < CC_HSLOTS) ctl->step_level[step] = t;
     if (S.prev_two) ctl->front[t - 1] = L.PrevFront;
@@ -946,15 +1013,24 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
     bool valid[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-      const unsigned long long i = c0 + (unsigned long long)j * CC_BLOCK + tid;
+      const unsigned long long wb =
+          c0 + (unsigned long long)j * CC_BLOCK + (unsigned long long)wave * CC_WAVE;
+      const unsigned long long i = wb + (unsigned long long)lane;
       valid[j] = j < ipt && i < cnt;
       X[j] = bzero<W>();
       Sv[j] = bzero<W>();
       v1[j] = 0;
       vt[j] = 0;
+      unsigned long long rb = 0;
+      const bool one = run_in_one_shard(shard_end, wb, fin.cap_s, rb);
       if (valid[j]) {
-        const int s = shard_of(L.Pre, i);
-        const unsigned long long e = (unsigned long long)s * fin.cap_s + (i - L.Pre[s]);
+        unsigned long long e;
+        if (one) {
+          e = rb + (unsigned long long)lane;
+        } else {
+          const int s = shard_of(L.Pre, i);
+          e = (unsigned long long)s * fin.cap_s + (i - L.Pre[s]);
+        }
 #pragma unroll
         for (int w = 0; w < W; ++w) X[j].w[w] = fin.X[w * fin.cap + e];
         if (ENUM) {
