@@ -164,8 +164,15 @@ def _check(st: int, where: str, info_fn=None):
         raise err
 
 
+_torch_types: dict = {}
+
+
 def _is_torch(x) -> bool:
-    return type(x).__module__.startswith("torch")
+    t = type(x)
+    r = _torch_types.get(t)
+    if r is None:
+        r = _torch_types[t] = t.__module__.startswith("torch")
+    return r
 
 
 def _ptr(x):
@@ -396,7 +403,9 @@ def _as_i32(x):
         return None
     if _is_torch(x):
         import torch
-        return x.to(torch.int32).contiguous()
+        if x.dtype != torch.int32:
+            x = x.to(torch.int32)
+        return x if x.is_contiguous() else x.contiguous()
     a = np.asarray(x)
     if a.size == 0:
         a = np.zeros(1, np.int32)

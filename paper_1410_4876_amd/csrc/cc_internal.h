@@ -207,11 +207,14 @@ hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t cc_launch_zero_ctl(CcCtl *ctl, int n, hipStream_t s);
 // adj (label space) and adj_orig (original ids) rows are at (v0 + row) * W.
 // bound (may be NULL) receives, per graph, sum over vertices of C(deg, 2):
-// an upper bound on its initial triplets plus triangles.
+// an upper bound on its initial triplets plus triangles.  reply (one graph
+// only; may be NULL) is host-mapped memory that receives the status in
+// word 1 and the bound in words 2..3, then 1 in word 0.
 hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n_single,
                             const int *row_ptr, const int *col_idx, unsigned long long *adj,
                             unsigned long long *adj_orig, int *perm, int *label,
-                            unsigned int *status, long long *bound, hipStream_t s);
+                            unsigned int *status, long long *bound, unsigned int *reply,
+                            hipStream_t s);
 // Stage one of graphs bt.g0 .. bt.g0 + n_graphs - 1 (one block each).
 hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s);
 // Stage one: the initial triplets go to frontier f3 (buffer 1), triangles

@@ -361,6 +361,18 @@ __global__ void k_zero(unsigned int *p, size_t words) {
 }
 
 // --------------------------------------------------------------- ingest
+// The ingest's result for a host spinning on mapped memory: the status word
+// and the pairs bound, a system-scope release, then the ready word.
+__device__ void ingest_reply(unsigned int *reply, unsigned int st, long long pairs) {
+  __hip_atomic_store(reply + 1, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(reply + 2, (unsigned)(unsigned long long)pairs, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(reply + 3, (unsigned)((unsigned long long)pairs >> 32), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  st_system(reply, 1u);
+}
+
 // One block per graph.  Validates the CSR (simple, symmetric), builds the
 // adjacency bitsets, computes the degree labelling (Section 2: repeatedly
 // take the remaining vertex of minimum remaining degree, smallest id on
@@ -375,7 +387,8 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
                                                 int *__restrict__ perm_out,
                                                 int *__restrict__ label_out,
                                                 unsigned int *__restrict__ status,
-                                                long long *__restrict__ bound) {
+                                                long long *__restrict__ bound,
+                                                unsigned int *reply) {
   __shared__ unsigned long long sA[CC_ROWS(W) * W];
   __shared__ int sLab[CC_ROWS(W)];
   __shared__ unsigned int sErr;
@@ -396,7 +409,10 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   for (int i = tid; i < CC_ROWS(W) * W; i += blockDim.x) sA[i] = 0ull;
   __syncthreads();
   if (n < 0 || n > 64 * W) {
-    if (tid == 0) status[g] = CC_DEV_NOT_SIMPLE;
+    if (tid == 0) {
+      status[g] = CC_DEV_NOT_SIMPLE;
+      if (reply) ingest_reply(reply, CC_DEV_NOT_SIMPLE, 0);
+    }
     return;
   }
   const long long e0 = rp[v0];
@@ -405,7 +421,10 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   if (bad_head) {
     // an invalid graph keeps no edges, so later stages find nothing in it
     for (int i = tid; i < n * W; i += blockDim.x) adj_out[(size_t)v0 * W + i] = 0ull;
-    if (tid == 0) status[g] = CC_DEV_NOT_SIMPLE;
+    if (tid == 0) {
+      status[g] = CC_DEV_NOT_SIMPLE;
+      if (reply) ingest_reply(reply, CC_DEV_NOT_SIMPLE, 0);
+    }
     return;
   }
   for (int v = tid; v < n; v += blockDim.x) {
@@ -451,7 +470,10 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   __syncthreads();
   if (sErr) {
     for (int i = tid; i < n * W; i += blockDim.x) adj_out[(size_t)v0 * W + i] = 0ull;
-    if (tid == 0) status[g] = sErr;
+    if (tid == 0) {
+      status[g] = sErr;
+      if (reply) ingest_reply(reply, sErr, 0);
+    }
     return;
   }
   if (tid < CC_WAVE) {
@@ -501,6 +523,7 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   if (tid == 0) {
     status[g] = 0x100u | (sDeg << 16);  // bit 8: ok; bits 16..: max degree
     if (bound) bound[g] = (long long)sPairs;
+    if (reply) ingest_reply(reply, 0x100u | (sDeg << 16), (long long)sPairs);
   }
 }
 
@@ -2457,9 +2480,10 @@ template <int W>
 hipError_t launch_ingest(int n_graphs, const int *graph_vtx_off, int n_single, const int *row_ptr,
                          const int *col_idx, unsigned long long *adj, unsigned long long *adj_orig,
                          int *perm, int *label, unsigned int *status, long long *bound,
-                         hipStream_t s) {
+                         unsigned int *reply, hipStream_t s) {
+  if (reply && n_graphs != 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ingest<W>, dim3(n_graphs), dim3(128), 0, s, graph_vtx_off, n_single,
-                     row_ptr, col_idx, adj, adj_orig, perm, label, status, bound);
+                     row_ptr, col_idx, adj, adj_orig, perm, label, status, bound, reply);
   return hipGetLastError();
 }
 template <int W>
@@ -2538,9 +2562,10 @@ hipError_t launch_dfs_batch(GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int
 hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n_single,
                             const int *row_ptr, const int *col_idx, unsigned long long *adj,
                             unsigned long long *adj_orig, int *perm, int *label,
-                            unsigned int *status, long long *bound, hipStream_t s) {
+                            unsigned int *status, long long *bound, unsigned int *reply,
+                            hipStream_t s) {
   return CC_BY_W(W, launch_ingest, n_graphs, graph_vtx_off, n_single, row_ptr, col_idx, adj,
-                 adj_orig, perm, label, status, bound, s);
+                 adj_orig, perm, label, status, bound, reply, s);
 }
 
 hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s) {

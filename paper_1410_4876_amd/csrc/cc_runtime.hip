@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstddef>
 #include <chrono>
@@ -25,6 +26,9 @@ constexpr int64_t kDefaultBudget = 4ll << 30;
 // caller's capacities in one pass; larger capacities are sized exactly by a
 // counting run first.
 constexpr int64_t kHostStageBytes = 8ll << 30;
+constexpr int kReplyWord = 8;       // ingest reply: words 8..11 of the pinned flag area
+constexpr int kReplySpinUs = 2000;  // polling for it before a stream synchronisation
+static_assert(kReplyWord + 4 <= 16, "the pinned flag area holds 16 words");
 constexpr int kLevelsAhead = 4;    // level launches queued beyond the device's progress
 constexpr int kAheadWaitUs = 200;  // longest the host waits for that progress
 constexpr double kIdleTimeoutSeconds = 30.0;
@@ -687,16 +691,29 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   // status word, then (8 bytes on) the sum over vertices of C(deg, 2),
   // which bounds the initial triplets and triangles
   long long *d_pairs = (long long *)((char *)g->d_status + 8);
+  // The ingest also answers in mapped host memory (words kReplyWord.. of
+  // the pinned flag area), which the host polls: cheaper than a copy and a
+  // stream synchronisation.  The stream may hold earlier work of the
+  // caller's, so polling gives way to a synchronisation after kReplySpinUs.
+  volatile unsigned int *rep = g->h_done + kReplyWord;
+  rep[0] = 0u;
+  std::atomic_thread_fence(std::memory_order_seq_cst);
   hipError_t e = cc_launch_ingest(g->W, 1, nullptr, n, d_rp, d_ci, g->d_adj, g->d_adj_orig, g->d_perm,
-                                  g->d_label, g->d_status, d_pairs, s);
-  unsigned long long back[2] = {0ull, 0ull};
-  if (e == hipSuccess) e = hipMemcpyAsync(back, g->d_status, 16, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+                                  g->d_label, g->d_status, d_pairs, g->d_done + kReplyWord, s);
+  if (e == hipSuccess) {
+    const auto t0 = std::chrono::steady_clock::now();
+    while (rep[0] == 0u &&
+           std::chrono::steady_clock::now() - t0 < std::chrono::microseconds(kReplySpinUs)) {
+    }
+    if (rep[0] == 0u) e = hipStreamSynchronize(s);
+  }
   if (e != hipSuccess) return fail(hip_err(e));
-  const unsigned int stv = (unsigned int)back[0];
+  if (rep[0] == 0u) return fail(CC_ERR_DEVICE);
+  std::atomic_thread_fence(std::memory_order_acquire);
+  const unsigned int stv = rep[1];
   if ((stv & 0xffu) != 0u || !(stv & 0x100u)) return fail(CC_ERR_NOT_SIMPLE);
   g->max_deg = (int)(stv >> 16);
-  g->pairs = (int64_t)back[1];
+  g->pairs = (int64_t)((unsigned long long)rep[2] | ((unsigned long long)rep[3] << 32));
   *out = g;
   return CC_OK;
 }
@@ -1049,7 +1066,8 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   std::vector<unsigned int> stat((size_t)n_graphs);
   std::vector<long long> bound((size_t)n_graphs);
   hipError_t e = cc_launch_ingest(b->W, n_graphs, b->d_vtx_off, 0, d_rp, d_ci, b->d_adj,
-                                  b->d_adj_orig, b->d_perm, b->d_label, b->d_status, b->d_bound, s);
+                                  b->d_adj_orig, b->d_perm, b->d_label, b->d_status, b->d_bound,
+                                  nullptr, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(stat.data(), b->d_status, (size_t)n_graphs * 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
@@ -1388,7 +1406,7 @@ hipError_t slot_launch(cc_server *sv, ServeSlot &sl, const std::vector<ServeReq 
   if (e > 0) chk(hipMemcpyAsync(sl.d_ci, sl.h_ci, (size_t)e * 4, hipMemcpyHostToDevice, s));
   chk(hipMemcpyAsync(sl.d_root_off, sl.h_root_off, (size_t)(G + 1) * 8, hipMemcpyHostToDevice, s));
   chk(cc_launch_ingest(W, G, sl.d_vtx_off, 0, sl.d_rp, sl.d_ci, sl.d_adj, sl.d_adj_orig, sl.d_perm,
-                       sl.d_label, sl.d_status, sl.d_bound, s));
+                       sl.d_label, sl.d_status, sl.d_bound, nullptr, s));
   chk(cc_launch_zero(sl.d_ctl, sizeof(CcCtl), s));
   chk(cc_launch_zero(sl.d_hist, (size_t)G * CC_HSLOTS * 8, s));
   BatchDev bt{};
