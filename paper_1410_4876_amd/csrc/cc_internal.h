@@ -225,9 +225,10 @@ hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Fro
 // with the frontier in LDS (launch 0 for host_done), while a level's paths
 // fit in lds_bytes of dynamic shared memory (two buffers); records the step
 // the launches start at.  Replaces cc_launch_triplets in the launched loop.
+// With zero_ctl it first zeroes the control block as cc_launch_zero_ctl.
 hipError_t cc_launch_head(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
                           OutDev out, int forced_level, size_t lds_bytes,
-                          unsigned int *host_done, hipStream_t s);
+                          unsigned int *host_done, bool zero_ctl, hipStream_t s);
 int cc_head_capacity(int W, bool enumerate, size_t lds_bytes);
 size_t cc_head_static_lds(int W, bool enumerate);
 // Launch `launch` (>= 1) of the breadth-first loop: one step on `blocks`

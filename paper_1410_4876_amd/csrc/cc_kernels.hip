@@ -341,9 +341,7 @@ __device__ __forceinline__ bool out_slot(const OutDev &out, int k, long long &cy
 // ----------------------------------------------------------------- zero
 // The control block before a run on a graph of cols - 2 vertices: the
 // per-shard counters in the columns the run uses, everything after them.
-__global__ void k_zero_ctl(CcCtl *ctl, int cols) {
-  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t nt = (size_t)gridDim.x * blockDim.x;
+__device__ __forceinline__ void zero_ctl_body(CcCtl *ctl, int cols, size_t tid, size_t nt) {
   for (size_t i = tid; i < (size_t)CC_SHARDS * cols; i += nt) {
     const size_t s = i / cols, k = i - s * cols;
     ctl->count_sh[s][k] = 0ull;
@@ -352,6 +350,10 @@ __global__ void k_zero_ctl(CcCtl *ctl, int cols) {
   unsigned int *rest = &ctl->bar_arrive[0][0];
   const size_t words = (sizeof(CcCtl) - offsetof(CcCtl, bar_arrive)) / 4;
   for (size_t i = tid; i < words; i += nt) rest[i] = 0u;
+}
+__global__ void k_zero_ctl(CcCtl *ctl, int cols) {
+  zero_ctl_body(ctl, cols, (size_t)blockIdx.x * blockDim.x + threadIdx.x,
+                (size_t)gridDim.x * blockDim.x);
 }
 
 __global__ void k_zero(unsigned int *p, size_t words) {
@@ -709,6 +711,7 @@ struct LevelLds {
   int FlagsH[2];  // written by waves 1 and 2: a staged length overflowed
   // per-wavefront buffer of decoded cycles (vertex ids, cycle after cycle)
   int Dec[ENUM ? CC_BLOCK / CC_WAVE : 1][ENUM ? CC_DEC_WORDS : 1];
+  unsigned long long Tot[CC_ROWS(W) + 2];  // per-length totals (the step that ends the loop)
 };
 
 // step_body results
@@ -857,16 +860,16 @@ __device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st
 // step's block 0 wrote it, possibly within the same launch, and a plain load
 // of a uniform address would go through the scalar cache, which no fence here
 // invalidates.
-__device__ __forceinline__ StepState load_state(CcCtl *ctl, int i) {
+__device__ __forceinline__ StepState load_state(StepState *p) {
   StepState S;
-  S.t = ld_relaxed(&ctl->ss[i].t);
-  S.fbuf = ld_relaxed(&ctl->ss[i].fbuf);
-  S.spair = ld_relaxed(&ctl->ss[i].spair);
-  S.slen0 = ld_relaxed(&ctl->ss[i].slen0);
-  S.slen1 = ld_relaxed(&ctl->ss[i].slen1);
-  S.prev_two = ld_relaxed(&ctl->ss[i].prev_two);
-  S.done = ld_relaxed(&ctl->ss[i].done);
-  S.pad = 0;
+  S.t = ld_relaxed(&p->t);
+  S.fbuf = ld_relaxed(&p->fbuf);
+  S.spair = ld_relaxed(&p->spair);
+  S.slen0 = ld_relaxed(&p->slen0);
+  S.slen1 = ld_relaxed(&p->slen1);
+  S.prev_two = ld_relaxed(&p->prev_two);
+  S.done = ld_relaxed(&p->done);
+  S.pad = ld_relaxed(&p->pad);
   return S;
 }
 
@@ -875,13 +878,12 @@ __device__ __forceinline__ StepState load_state(CcCtl *ctl, int i) {
 // graph is loaded into LDS here, together with the counters.
 template <int W, bool ENUM>
 __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
-                         int step, int forced_level, int maxc, bool allow_two,
-                         LevelLds<W, ENUM> &L, bool lds_ready) {
+                         int step, const StepState &S, int forced_level, int maxc,
+                         bool allow_two, LevelLds<W, ENUM> &L, bool lds_ready) {
   constexpr int IPT = CC_LEVEL_IPT;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / CC_WAVE;
-  const StepState S = load_state(ctl, step);
   if (S.done) return CC_LEVEL_EMPTY;
   const int t = S.t;
   const int n = g.n;
@@ -1232,6 +1234,68 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   return CC_LEVEL_NEXT;
 }
 
+// Per-length cycle totals: lengths up to bfs_max_len come from the
+// breadth-first levels (summed over shards); longer ones, when the
+// depth-first kernel took over in enumerate mode, from its counting pass.
+// Count mode accumulates everything in the shards.  One block; sTot has
+// `slots` entries, at least n + 2 (all of CC_HSLOTS when the depth-first
+// kernel may have counted).
+__device__ void length_totals(CcCtl *ctl, int n, bool enumerate, unsigned long long *sTot,
+                              int slots = CC_HSLOTS) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < slots; k += blockDim.x) sTot[k] = 0ull;
+  __syncthreads();
+  const bool dfs = ld_relaxed(&ctl->mode) != 0;
+  // a run on n vertices uses the columns 0..n+1 (the only ones zeroed)
+  const int kmax = min((enumerate && dfs) ? ctl->bfs_max_len : CC_HSLOTS - 1, n + 1);
+  // the shard counters of the used columns, several loads in flight per
+  // thread before their sums go into LDS
+  constexpr int PER = 8;
+  const int cols = max(kmax + 1, 0), total = CC_SHARDS * cols;
+  for (int base = tid; base < total; base += blockDim.x * PER) {
+    unsigned long long v[PER];
+    int kk[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int p = base + j * (int)blockDim.x;
+      kk[j] = -1;
+      v[j] = 0ull;
+      if (p < total) {
+        const int s = p / cols;
+        kk[j] = p - s * cols;
+        v[j] = ld_relaxed(&ctl->hist_sh[s][kk[j]]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      if (kk[j] >= 0 && v[j]) atomicAdd(&sTot[kk[j]], v[j]);
+  }
+  __syncthreads();
+  if (enumerate && dfs)
+    for (int k = tid; k < slots; k += blockDim.x)
+      if (k > kmax) sTot[k] = ctl->dfs_hist[k];
+  __syncthreads();
+}
+
+// Final histogram (ctl->hist; entries from `slots` on stay as zeroed); in
+// enumerate mode also closes the offsets array with the total vertex count.
+// One block, sTot as for length_totals.
+__device__ void finalize_body(CcCtl *ctl, const OutDev &out, int n, bool enumerate,
+                              unsigned long long *sTot, int slots) {
+  length_totals(ctl, n, enumerate, sTot, slots);
+  for (int k = threadIdx.x; k < slots; k += blockDim.x) ctl->hist[k] = sTot[k];
+  if (enumerate && threadIdx.x == 0) {
+    // the closing offset of the output window
+    long long c = 0, v = 0;
+    for (int k = 0; k <= n && k < slots; ++k) {
+      if (k < out.kmin || k > out.kmax) continue;
+      c += (long long)sTot[k];
+      v += (long long)sTot[k] * k;
+    }
+    if (c <= out.cyc_cap && v <= out.verts_cap && out.offs) out.offs[c] = v;
+  }
+}
+
 // --------------------------------------------------------- one-block head
 // Stage one and the leading levels on one block of CC_HEAD_THREADS threads,
 // with the frontier in LDS: two buffers of `cap` paths in dynamic shared
@@ -1404,13 +1468,18 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, in
 template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl, LevelBufs B,
                                                           OutDev out, int forced_level,
-                                                          int cap_lds, unsigned int *host_done) {
+                                                          int cap_lds, unsigned int *host_done,
+                                                          int zero_cols) {
   constexpr int T = CC_HEAD_THREADS;
   __shared__ HeadLds<W, ENUM> L;
   extern __shared__ unsigned long long dyn[];
   const int tid = threadIdx.x;
   const int n = g.n;
   if (host_done && tid == 0) st_system(host_done + 1, 1u);
+  // the run's control block, as k_zero_ctl (the barrier below orders these
+  // stores before this block's later use of it; later kernels follow in
+  // stream order)
+  if (zero_cols > 0) zero_ctl_body(ctl, zero_cols, tid, T);
   for (int i = tid; i < n * W; i += T) L.N[i] = g.adj[i];
   if (ENUM)
     for (int i = tid; i < n * W; i += T) L.No[i] = g.adj_orig[i];
@@ -1660,15 +1729,25 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
     if (host_done && lead) st_system(host_done, (unsigned)launch + 1u);
     return;
   }
-  const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0, L,
-                                   false);
+  const int r = step_body<W, ENUM>(g, ctl, B, out, step, load_state(&ctl->ss[step]),
+                                   forced_level, maxc, allow_two != 0, L, false);
+  // The step that finds the frontier empty ends the run: block 0 (r is the
+  // same for all its threads) also writes the final histogram and closing
+  // offset, and host_done[3] tells the host to launch no finalize kernel.
+  const bool fin = r == CC_LEVEL_EMPTY && blockIdx.x == 0 && host_done;
+  if (fin) {
+    __syncthreads();
+    finalize_body(ctl, out, g.n, ENUM, L.Tot, CC_ROWS(W) + 2);
+  }
   if (lead) {
     if (launch + 1 < CC_HSLOTS) ctl->launch_step[launch + 1] = r == CC_LEVEL_NEXT ? step + 2 : 0;
     ctl->levels_run = step + 1;
     if (r != CC_LEVEL_NEXT && host_done) {
-      // host_done[2]: the loop handed over to the depth-first kernel; stored
-      // and released before host_done[0]
+      // host_done[2]: the loop handed over to the depth-first kernel;
+      // host_done[3]: this launch finalized; both stored and released
+      // before host_done[0]
       if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
+      if (fin) st_system(host_done + 3, 1u);
       st_system(host_done, (unsigned)launch + 1u);
     }
   }
@@ -1793,8 +1872,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Lev
   // has room for them
   for (; step < g.n - 2; ++step) {
     if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[step] = wall_clock64();
-    const int r = step_body<W, ENUM>(g, ctl, B, out, step, forced_level, maxc, allow_two != 0,
-                                     L, true);
+    const int r = step_body<W, ENUM>(g, ctl, B, out, step, load_state(&ctl->ss[step]),
+                                     forced_level, maxc, allow_two != 0, L, true);
     if (r != CC_LEVEL_NEXT) {
       ++step;
       break;
@@ -2363,46 +2442,6 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   }
 }
 
-// Per-length cycle totals: lengths up to bfs_max_len come from the
-// breadth-first levels (summed over shards); longer ones, when the
-// depth-first kernel took over in enumerate mode, from its counting pass.
-// Count mode accumulates everything in the shards.  One block.
-__device__ void length_totals(CcCtl *ctl, int n, bool enumerate, unsigned long long *sTot) {
-  const int tid = threadIdx.x;
-  for (int k = tid; k < CC_HSLOTS; k += blockDim.x) sTot[k] = 0ull;
-  __syncthreads();
-  const bool dfs = ld_relaxed(&ctl->mode) != 0;
-  // a run on n vertices uses the columns 0..n+1 (the only ones zeroed)
-  const int kmax = min((enumerate && dfs) ? ctl->bfs_max_len : CC_HSLOTS - 1, n + 1);
-  // the shard counters of the used columns, several loads in flight per
-  // thread before their sums go into LDS
-  constexpr int PER = 8;
-  const int cols = max(kmax + 1, 0), total = CC_SHARDS * cols;
-  for (int base = tid; base < total; base += blockDim.x * PER) {
-    unsigned long long v[PER];
-    int kk[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int p = base + j * (int)blockDim.x;
-      kk[j] = -1;
-      v[j] = 0ull;
-      if (p < total) {
-        const int s = p / cols;
-        kk[j] = p - s * cols;
-        v[j] = ld_relaxed(&ctl->hist_sh[s][kk[j]]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < PER; ++j)
-      if (kk[j] >= 0 && v[j]) atomicAdd(&sTot[kk[j]], v[j]);
-  }
-  __syncthreads();
-  if (enumerate && dfs)
-    for (int k = tid; k < CC_HSLOTS; k += blockDim.x)
-      if (k > kmax) sTot[k] = ctl->dfs_hist[k];
-  __syncthreads();
-}
-
 // Resets the depth-first coordination state: every mailbox of the
 // workspace, the claim cursor and the busy count, unconditionally (the
 // workspace has memory of its own, so nothing else ever lives there); for
@@ -2438,18 +2477,7 @@ __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
 // total vertex count.  One block.
 __global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
   __shared__ unsigned long long sTot[CC_HSLOTS];
-  length_totals(ctl, n, enumerate != 0, sTot);
-  for (int k = threadIdx.x; k < CC_HSLOTS; k += blockDim.x) ctl->hist[k] = sTot[k];
-  if (enumerate && threadIdx.x == 0) {
-    // the closing offset of the output window
-    long long c = 0, v = 0;
-    for (int k = 0; k <= n && k < CC_HSLOTS; ++k) {
-      if (k < out.kmin || k > out.kmax) continue;
-      c += (long long)sTot[k];
-      v += (long long)sTot[k] * k;
-    }
-    if (c <= out.cyc_cap && v <= out.verts_cap && out.offs) out.offs[c] = v;
-  }
+  finalize_body(ctl, out, n, enumerate != 0, sTot, CC_HSLOTS);
 }
 
 }  // namespace
@@ -2522,10 +2550,10 @@ hipError_t head_raise(bool en, size_t lds_bytes) {
 template <int W>
 hipError_t launch_head(bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b, OutDev out,
                        int forced_level, int cap, size_t lds_bytes, unsigned int *host_done,
-                       hipStream_t s) {
+                       int zero_cols, hipStream_t s) {
   dim3 gr(1), bl(CC_HEAD_THREADS);
-  if (en) hipLaunchKernelGGL((k_head<W, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
-  else hipLaunchKernelGGL((k_head<W, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done);
+  if (en) hipLaunchKernelGGL((k_head<W, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols);
+  else hipLaunchKernelGGL((k_head<W, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols);
   return hipGetLastError();
 }
 template <int W>
@@ -2608,8 +2636,9 @@ int cc_head_capacity(int W, bool en, size_t lds_bytes) {
 
 hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
                           OutDev out, int forced_level, size_t lds_bytes,
-                          unsigned int *host_done, hipStream_t s) {
+                          unsigned int *host_done, bool zero_ctl, hipStream_t s) {
   const int cap = cc_head_capacity(W, en, lds_bytes);
+  const int zero_cols = zero_ctl ? std::min(std::max(g.n, 0) + 2, CC_HSLOTS) : 0;
   // The dynamic LDS limit is raised once per device and instantiation (the
   // call costs host time that would otherwise stall the stream).
   static std::atomic<size_t> raised[64][6];
@@ -2622,7 +2651,8 @@ hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBuf
     if (e != hipSuccess) return e;
     raised[dev][which].store(lds_bytes);
   }
-  return CC_BY_W(W, launch_head, en, g, ctl, b, out, forced_level, cap, lds_bytes, host_done, s);
+  return CC_BY_W(W, launch_head, en, g, ctl, b, out, forced_level, cap, lds_bytes, host_done,
+                 zero_cols, s);
 }
 
 // Static shared memory of the head kernel (so the caller can size the

@@ -352,9 +352,9 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
                            : 0;
   const bool persistent = coop_max >= CC_SHARDS;
   chk(hipEventRecord(g->ev0, s));
-  chk(cc_launch_zero_ctl(ctl, n, s));
-  // Stage one: its own kernel before the persistent loop; inside the head
-  // kernel (launch 0) otherwise.
+  // Zeroing the control block and stage one: kernels of their own before
+  // the persistent loop; inside the head kernel (launch 0) otherwise.
+  if (persistent) chk(cc_launch_zero_ctl(ctl, n, s));
   mark(0);
   if (persistent) chk(cc_launch_triplets(W, en, gd, ctl, f[1], lb.st[0], s));
   mark(1);
@@ -384,6 +384,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     done[0] = 0u;
     done[1] = 0u;
     done[2] = 0u;
+    done[3] = 0u;
     // Launch 0 runs stage one and the leading levels on one block with the
     // frontier in LDS; each later launch runs one step, so n - 2 of them
     // are enough.
@@ -392,7 +393,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     // static part and a margin
     const size_t stat = cc_head_static_lds(W, en) + 4096;
     const size_t head_lds = g->dev.lds_block > stat ? g->dev.lds_block - stat : 0;
-    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, head_lds, g->d_done, s));
+    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, head_lds, g->d_done, true, s));
     mark(3);
     ++levels;
     for (int launch = 1; launch < n - 1 && e == hipSuccess; ++launch, ++levels) {
@@ -434,7 +435,9 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
                       dfs_blocks_e, idle_timeout, s));
   }
   mark(2 * n + 3);
-  chk(cc_launch_finalize(ctl, out, n, en, s));
+  // the step that found the frontier empty has already finalized when it
+  // says so (host_done[3], released before the end-of-loop word)
+  if (!(levels_finished && hd[3] != 0u)) chk(cc_launch_finalize(ctl, out, n, en, s));
   chk(hipEventRecord(g->ev1, s));
   // Read back the unsharded tail of the control block (everything for
   // profiling runs, which also report per-level traffic).
