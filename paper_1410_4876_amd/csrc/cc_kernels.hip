@@ -251,17 +251,32 @@ __device__ __forceinline__ void st_system(unsigned int *p, unsigned int v) {
 }
 
 // ------------------------------------------------------------ shards
+// The value of another lane by a data-parallel move (both halves moved the
+// same way); lanes the move does not write, or whose source lane is out of
+// range, get 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, ROW_MASK,
+                                                            0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL,
+                                                            ROW_MASK, 0xf, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
 // Wavefront-wide inclusive scan of one value per lane (lane = shard); writes
 // pre[0] = 0 and pre[s + 1] = sum of shards 0..s.  Called by a whole
-// wavefront.
+// (fully active) wavefront.
 __device__ __forceinline__ void shard_prefix(unsigned long long v, unsigned long long *pre) {
   const int lane = lane_id();
+  // inclusive scan: shifts by 1, 2, 4, 8 within rows of 16 lanes, then
+  // row 0's total into row 1 and row 2's into row 3, then rows 0-1's total
+  // (lane 31) into rows 2 and 3
   unsigned long long x = v;
-#pragma unroll
-  for (int o = 1; o < CC_WAVE; o <<= 1) {
-    const unsigned long long y = __shfl_up(x, o, CC_WAVE);
-    if (lane >= o) x += y;
-  }
+  x += dpp_u64<0x111, 0xf>(x);
+  x += dpp_u64<0x112, 0xf>(x);
+  x += dpp_u64<0x114, 0xf>(x);
+  x += dpp_u64<0x118, 0xf>(x);
+  x += dpp_u64<0x142, 0xa>(x);
+  x += dpp_u64<0x143, 0xc>(x);
   pre[lane + 1] = x;
   if (lane == 0) pre[0] = 0ull;
 }
