@@ -690,11 +690,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
 // also decodes the cycles the previous step staged.
 //
 // Expansion: a block takes chunks of CC_BLOCK * CC_LEVEL_IPT consecutive
-// paths (one lane per path, CC_LEVEL_IPT rounds), counts what they produce,
-// and reserves room for all of it with one atomic per counter per chunk on
-// its own shard; each wavefront then owns contiguous sub-ranges and ranks
-// its lanes inside them with ballot/mbcnt, so the stores of a round land on
-// consecutive slots.  Closures are counted in hist_sh[.][k] and, when
+// paths (one lane per path, CC_LEVEL_IPT rounds); each wavefront counts what
+// its lanes produce, reserves room for it with one atomic per counter on
+// the block's shard, and ranks its lanes inside the reserved ranges with
+// ballot/mbcnt, so the stores of a round land on consecutive slots.  Closures are counted in hist_sh[.][k] and, when
 // enumerating, staged as vertex bitsets for the next step to decode.
 //
 // Decoding: cycle g of length k (global order: shards in turn) goes to
@@ -715,11 +714,8 @@ struct LevelLds {
   unsigned long long Pre[CC_SHARDS + 1];
   unsigned long long PreH0[ENUM ? CC_SHARDS + 1 : 1];
   unsigned long long PreH1[ENUM ? CC_SHARDS + 1 : 1];
-  unsigned int WaveA[CC_BLOCK / CC_WAVE];   // paths written (extensions or grandchildren)
-  unsigned int WaveB[CC_BLOCK / CC_WAVE];   // closures one level down
-  unsigned int WaveC[CC_BLOCK / CC_WAVE];   // closures two levels down
-  unsigned int WaveD[CC_BLOCK / CC_WAVE];   // children (two-level steps: paths not written)
-  unsigned long long BaseA, BaseB, BaseC;
+  unsigned int WaveA[CC_BLOCK / CC_WAVE];   // count mode: closures one level down
+  unsigned int WaveB[CC_BLOCK / CC_WAVE];   // count mode: closures two levels down
   unsigned long long Cum[2];
   unsigned long long PrevFront;
   int Flags;      // written by wave 0: the input frontier overflowed
@@ -761,58 +757,31 @@ __device__ __forceinline__ Stage pick(bool c, const Stage &a, const Stage &b) {
   return s;
 }
 
-// Per-wavefront ranks of four counts into block-level reservations: every
-// lane adds its counts, thread 0 reserves room for the block's totals on
-// its shard's counters, and each wavefront gets its base in each range.
-template <int W, bool ENUM>
-__device__ __forceinline__ void reserve(LevelLds<W, ENUM> &L, unsigned a, unsigned b, unsigned c,
-                                        unsigned d, unsigned long long *ctrA,
-                                        unsigned long long *ctrB, unsigned long long *ctrC,
-                                        unsigned long long *ctrD, unsigned long long &baseA,
-                                        unsigned long long &baseB, unsigned long long &baseC,
-                                        unsigned &wa, unsigned &wb, unsigned &wc) {
-  constexpr int NW = CC_BLOCK / CC_WAVE;
-  const int wave = threadIdx.x / CC_WAVE;
+// Reservations of four counts per wavefront: every lane adds its counts,
+// lane 0 reserves room for the wavefront's totals on the shard's counters,
+// and the bases come back in scalar registers.  No block barrier: each
+// wavefront goes on as soon as its own atomics return.  Called by a whole
+// (fully active) wavefront.
+__device__ __forceinline__ void reserve(unsigned a, unsigned b, unsigned c, unsigned d,
+                                        unsigned long long *ctrA, unsigned long long *ctrB,
+                                        unsigned long long *ctrC, unsigned long long *ctrD,
+                                        unsigned long long &baseA, unsigned long long &baseB,
+                                        unsigned long long &baseC, unsigned &wa, unsigned &wb,
+                                        unsigned &wc) {
   wa = wave_sum_u32_full(a);
   wb = wave_sum_u32_full(b);
   wc = wave_sum_u32_full(c);
   const unsigned wd = wave_sum_u32_full(d);
+  unsigned long long ba = 0, bb = 0, bc = 0;
   if (lane_id() == 0) {
-    L.WaveA[wave] = wa;
-    L.WaveB[wave] = wb;
-    L.WaveC[wave] = wc;
-    L.WaveD[wave] = wd;
+    if (wa && ctrA) ba = atomicAdd(ctrA, (unsigned long long)wa);
+    if (wb && ctrB) bb = atomicAdd(ctrB, (unsigned long long)wb);
+    if (wc && ctrC) bc = atomicAdd(ctrC, (unsigned long long)wc);
+    if (wd && ctrD) atomicAdd(ctrD, (unsigned long long)wd);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long ta = 0, tb = 0, tc = 0, td = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      ta += L.WaveA[w];
-      tb += L.WaveB[w];
-      tc += L.WaveC[w];
-      td += L.WaveD[w];
-    }
-    L.BaseA = (ta && ctrA) ? atomicAdd(ctrA, ta) : 0ull;
-    L.BaseB = (tb && ctrB) ? atomicAdd(ctrB, tb) : 0ull;
-    L.BaseC = (tc && ctrC) ? atomicAdd(ctrC, tc) : 0ull;
-    if (td && ctrD) atomicAdd(ctrD, td);
-  }
-  __syncthreads();
-  baseA = L.BaseA;
-  baseB = L.BaseB;
-  baseC = L.BaseC;
-  for (int w = 0; w < wave; ++w) {
-    baseA += L.WaveA[w];
-    baseB += L.WaveB[w];
-    baseC += L.WaveC[w];
-  }
-  baseA = uni_u64(baseA);
-  baseB = uni_u64(baseB);
-  baseC = uni_u64(baseC);
-  wa = uni_u32(wa);
-  wb = uni_u32(wb);
-  wc = uni_u32(wc);
+  baseA = lane_u64(ba, 0);
+  baseB = lane_u64(bb, 0);
+  baseC = lane_u64(bc, 0);
 }
 
 // Orders this wavefront's LDS accesses before and after (a wavefront's LDS
@@ -1107,10 +1076,9 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
     const int kA = two ? t + 2 : t + 1;  // length of the paths written
     unsigned long long baseA, baseB, baseC;
     unsigned wa, wb, wc;
-    reserve<W, ENUM>(L, ca, cb, cc, cd, &ctl->count_sh[osh][kA],
-                     ENUM ? &ctl->hist_sh[osh][t + 1] : nullptr,
-                     (ENUM && two) ? &ctl->hist_sh[osh][t + 2] : nullptr,
-                     two ? &ctl->count_sh[osh][t + 1] : nullptr, baseA, baseB, baseC, wa, wb, wc);
+    reserve(ca, cb, cc, cd, &ctl->count_sh[osh][kA], ENUM ? &ctl->hist_sh[osh][t + 1] : nullptr,
+            (ENUM && two) ? &ctl->hist_sh[osh][t + 2] : nullptr,
+            two ? &ctl->count_sh[osh][t + 1] : nullptr, baseA, baseB, baseC, wa, wb, wc);
     if (!ENUM) {
       acc1 += cb;
       acc2 += cc;
@@ -1226,7 +1194,6 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
         }
       }
     }
-    __syncthreads();  // the per-wavefront totals are rewritten by the next chunk
   }
   if (!ENUM) {
     acc1 = wave_sum_u64(acc1);
