@@ -805,7 +805,11 @@ __device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st
   cb -= out.cshift;  // into the output window
   vb -= out.vshift;
   const int lane = lane_id();
-  const unsigned long long per = (unsigned long long)min(CC_WAVE, CC_DEC_WORDS / k);
+  // each lane's cycle at an odd stride in buf, so the lanes' stores of one
+  // position fall in distinct LDS banks
+  const int sk = k | 1;
+  const unsigned long long per = (unsigned long long)min(CC_WAVE, CC_DEC_WORDS / sk);
+  const float rk = 1.0f / (float)k;
   const unsigned long long end = pre[lane + 1];
   for (unsigned long long g0 = gw * per; g0 < h; g0 += nwg * per) {
     const unsigned long long nb = min(per, h - g0);
@@ -823,7 +827,7 @@ __device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st
       Bits<W> C;
 #pragma unroll
       for (int w = 0; w < W; ++w) C.w[w] = st.C[w * st.cap + e];
-      write_cycle<W>(L.No, C, k, buf + lane * k);
+      write_cycle<W>(L.No, C, k, buf + lane * sk);
       const long long cyc = cb + (long long)gi;
       const long long pos = vb + (long long)gi * k;
       if (cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap)
@@ -833,8 +837,14 @@ __device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st
     const long long base = vb + (long long)g0 * k;
     const int words = (int)nb * k;
     for (int d = lane; d < words; d += CC_WAVE) {
+      // word d is position d mod k of the run's cycle d / k; the quotient
+      // by a float reciprocal is exact: (d + 1/2) / k lies at least 1/(2k)
+      // from an integer, and the product's relative error (~2^-23) moves it
+      // by less than d/k * 2^-23, far less for d < CC_DEC_WORDS
+      const int c = (int)(((float)d + 0.5f) * rk);
+      const int j = d - c * k;
       const long long q = base + d;
-      if (q >= 0 && q < out.verts_cap) out.verts[q] = buf[d];
+      if (q >= 0 && q < out.verts_cap) out.verts[q] = buf[c * sk + j];
     }
     wave_lds_sync();  // the next run overwrites buf
   }
