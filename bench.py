@@ -24,24 +24,35 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
 PROFILE = os.path.join(ROOT, "profiles", "k_step_grid8x8_enumerate.md")
-KERNELS = os.path.join(ROOT, "paper_1410_4876_amd", "csrc", "cc_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1410_4876_amd", "csrc")
 TABLE1 = os.path.join(ROOT, "tests", "golden", "table1.json")
 GRID7X12 = os.path.join(ROOT, "tests", "golden", "grid7x12.json")
 
 
+def library_sources_sha256():
+    """sha256 over the library's sources (kernels, their header, the
+    runtime that sizes their launches), in name order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
+
+
 def counted_traffic():
     """HBM bytes per level launch from the committed rocprofv3 PMC summary,
-    or None when the kernel source has changed since the counters were
+    or None when the library sources have changed since the counters were
     taken."""
-    import hashlib
     import re
     try:
         text = open(PROFILE).read()
         data = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
-        src = hashlib.sha256(open(KERNELS, "rb").read()).hexdigest()
+        src = library_sources_sha256()
     except (OSError, AttributeError, ValueError):
         return None
-    return data["traffic_bytes_per_launch"] if data.get("kernel_source_sha256") == src else None
+    return data["traffic_bytes_per_launch"] if data.get("library_sources_sha256") == src else None
 
 
 def cpu_baseline(g, budget_s=30.0):

@@ -13,7 +13,7 @@
 #define CC_BLOCK 256              // threads per block for the expansion kernels
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk
 #define CC_LEVEL_IPT 4            // paths per lane per chunk in the level kernel
-#define CC_DEC_WORDS 1536         // per-wavefront LDS words for decoded cycles (enumerate steps)
+#define CC_DEC_WORDS 1280         // per-wavefront LDS words for decoded cycles (enumerate steps)
 #define CC_HEAD_THREADS 1024      // threads of the one-block head kernel
 #define CC_ROOT_CLAIM 1024        // handed-over paths a depth-first wavefront claims at once
 // Frontier and staged-cycle counters are split into CC_SHARDS shards, each
@@ -249,6 +249,8 @@ hipError_t cc_launch_levels(int W, bool enumerate, GraphDev g, CcCtl *ctl, const
                             unsigned long long *clock, hipStream_t s);
 // Blocks of k_levels that fit on the device at once (0 if unknown).
 int cc_levels_max_blocks(int W, bool enumerate);
+// Blocks of the step kernel resident per CU (its grid is that many per CU).
+int cc_step_blocks_per_cu(int W, bool enumerate);
 // The handed-over paths are in frontier f0 or f1 (CcCtl::root_buf); the
 // workspace wk has memory of its own.  Cycle counts
 // of block b go to hist_out[(b % CC_SHARDS) * hist_stride + k] (hist_out

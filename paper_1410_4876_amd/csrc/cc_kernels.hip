@@ -2531,6 +2531,11 @@ hipError_t levels_occupancy(bool en, int *per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, levels_fn<W>(en), CC_BLOCK, 0);
 }
 template <int W>
+hipError_t step_occupancy(bool en, int *per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      per_cu, en ? (const void *)k_step<W, true> : (const void *)k_step<W, false>, CC_BLOCK, 0);
+}
+template <int W>
 const void *head_fn(bool en) {
   return en ? (const void *)k_head<W, true> : (const void *)k_head<W, false>;
 }
@@ -2616,6 +2621,21 @@ int cc_levels_max_blocks(int W, bool en) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   return per_cu * cus;
+}
+
+int cc_step_blocks_per_cu(int W, bool en) {
+  // the same for every device of a process here (one architecture); asked
+  // once per instantiation
+  static std::atomic<int> cached[6];
+  const int which = (W == 1 ? 0 : W == 2 ? 2 : 4) + (en ? 1 : 0);
+  int v = cached[which].load();
+  if (v <= 0) {
+    int per_cu = 0;
+    if (CC_BY_W(W, step_occupancy, en, &per_cu) != hipSuccess || per_cu <= 0) return 4;
+    cached[which].store(per_cu);
+    v = per_cu;
+  }
+  return v;
 }
 
 // Paths the head's LDS frontier buffers hold with `lds_bytes` of dynamic

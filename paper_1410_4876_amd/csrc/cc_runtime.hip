@@ -29,6 +29,7 @@ constexpr int64_t kHostStageBytes = 8ll << 30;
 constexpr int kReplyWord = 8;       // ingest reply: words 8..11 of the pinned flag area
 constexpr int kReplySpinUs = 2000;  // polling for it before a stream synchronisation
 static_assert(kReplyWord + 4 <= 16, "the pinned flag area holds 16 words");
+constexpr int kStepBlocksPerCu = 6;  // cap on the step grid per CU (7 ran 20 % slower)
 constexpr int kLevelsAhead = 3;    // level launches queued beyond the device's progress
 constexpr int kAheadWaitUs = 200;  // longest the host waits for that progress
 constexpr double kIdleTimeoutSeconds = 30.0;
@@ -325,7 +326,12 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     d->claim = g->opt.dfs_claim > 0 ? (g->opt.dfs_claim + CC_CHUNK - 1) / CC_CHUNK * CC_CHUNK : 0;
   }
   const int dfs_blocks_c = nw_c / 4, dfs_blocks_e = nw_e / 4;
-  const int bfs_blocks = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 5;
+  // one resident wave of step blocks: as many per CU as registers and LDS
+  // allow, at most kStepBlocksPerCu
+  const int bfs_blocks =
+      g->opt.bfs_blocks > 0
+          ? g->opt.bfs_blocks
+          : g->dev.cus * std::min(cc_step_blocks_per_cu(W, en), kStepBlocksPerCu);
   const int forced = (g->opt.flags & CC_FORCE_DFS) ? std::max(3, (int)g->opt.dfs_level) : -1;
   const unsigned long long idle_timeout =
       (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz);
