@@ -438,6 +438,9 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
   if (bad_head) {
     // an invalid graph keeps no edges, so later stages find nothing in it
     for (int i = tid; i < n * W; i += blockDim.x) adj_out[(size_t)v0 * W + i] = 0ull;
+    // every thread took this branch from the same two loads; once all have
+    // made them the host may free the CSR, so the reply waits for them
+    __syncthreads();
     if (tid == 0) {
       status[g] = CC_DEV_NOT_SIMPLE;
       if (reply) ingest_reply(reply, CC_DEV_NOT_SIMPLE, 0);
