@@ -217,6 +217,32 @@ def test_rejects_non_simple(cc, case):
         assert ei.value.status == cc.CC_ERR_NOT_SIMPLE
 
 
+@pytest.mark.parametrize("case", ["first_not_zero", "negative_total", "too_many_entries"])
+def test_rejects_invalid_csr_header(cc, case):
+    """CSR headers no simple graph on 3 vertices has.  Host arrays are
+    rejected before any launch; device arrays by the ingest kernel, which
+    answers the host through mapped memory.  A valid graph prepared right
+    after each rejection must come out right (the reply words are reused)."""
+    import torch
+    rp, ci = {
+        "first_not_zero": ([1, 2, 3, 4], [1, 0, 0, 0]),
+        "negative_total": ([0, 1, 1, -1], [1]),
+        "too_many_entries": ([0, 3, 6, 9], [1, 2, 1, 0, 2, 0, 0, 1, 0]),
+    }[case]
+    tri = gg.complete(3)
+    for dev in (False, True):
+        r = np.array(rp, np.int32)
+        c = np.array(ci, np.int32)
+        if dev:
+            r = torch.tensor(r, device="cuda")
+            c = torch.tensor(c, device="cuda")
+        with pytest.raises(cc.CCError) as ei:
+            cc.Graph(3, r, c)
+        assert ei.value.status == cc.CC_ERR_NOT_SIMPLE
+        with cc.prepare(tri) as h:
+            assert h.histogram().tolist() == [0, 0, 0, 1]
+
+
 def test_repeated_runs_identical(cc):
     g = gg.er_gnm(50, 120, np.random.default_rng(3))
     with cc.prepare(g) as h:
