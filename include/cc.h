@@ -81,7 +81,8 @@ typedef struct cc_options {
   int32_t dfs_level;             /* with CC_FORCE_DFS: path length t >= 3 whose frontier
                                     is handed to the depth-first kernel                  */
   int32_t dfs_waves_per_cu;      /* depth-first kernel occupancy; 0 = default (24)       */
-  int32_t bfs_blocks;            /* grid of the level kernel; 0 = default                */
+  int32_t bfs_blocks;            /* grid of the level kernel; 0 = one resident wave of
+                                    blocks (occupancy query, at most 6 per CU)          */
   int32_t dfs_donate_min;        /* depth-first: a wavefront donates work to idle ones once
                                     it holds at least this many paths; 0 = default      */
   int32_t dfs_claim;             /* depth-first: handed-over paths claimed per atomic
