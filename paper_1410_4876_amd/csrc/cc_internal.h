@@ -13,6 +13,7 @@
 #define CC_BLOCK 256              // threads per block for the expansion kernels
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk
 #define CC_LEVEL_IPT 4            // paths per lane per chunk in the level kernel
+#define CC_LEVEL_IPT_W4 3         // the same for four-word bitsets (n > 128)
 #define CC_DEC_WORDS 1280         // per-wavefront LDS words for decoded cycles (enumerate steps)
 #define CC_HEAD_THREADS 1024      // threads of the one-block head kernel
 #define CC_ROOT_CLAIM 1024        // handed-over paths a depth-first wavefront claims at once

@@ -693,11 +693,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
 // also decodes the cycles the previous step staged.
 //
 // Expansion: a block takes chunks of CC_BLOCK * CC_LEVEL_IPT consecutive
-// paths (one lane per path, CC_LEVEL_IPT rounds); each wavefront counts what
-// its lanes produce, reserves room for it with one atomic per counter on
-// the block's shard, and ranks its lanes inside the reserved ranges with
-// ballot/mbcnt, so the stores of a round land on consecutive slots.  Closures are counted in hist_sh[.][k] and, when
-// enumerating, staged as vertex bitsets for the next step to decode.
+// paths (one lane per path, CC_LEVEL_IPT rounds; CC_LEVEL_IPT_W4 with
+// four-word bitsets, whose larger lane state favours fewer); each wavefront
+// counts what its lanes produce, reserves room for it with one atomic per
+// counter on the block's shard, and ranks its lanes inside the reserved
+// ranges with ballot/mbcnt, so the stores of a round land on consecutive
+// slots.  Closures are counted in hist_sh[.][k] and, when enumerating,
+// staged as vertex bitsets for the next step to decode.
 //
 // Decoding: cycle g of length k (global order: shards in turn) goes to
 // output index cum_c[k-1] + g, vertices at cum_v[k-1] + g * k, so the output
@@ -877,7 +879,7 @@ template <int W, bool ENUM>
 __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
                          int step, const StepState &S, int forced_level, int maxc,
                          bool allow_two, LevelLds<W, ENUM> &L, bool lds_ready) {
-  constexpr int IPT = CC_LEVEL_IPT;
+  constexpr int IPT = W == 4 ? CC_LEVEL_IPT_W4 : CC_LEVEL_IPT;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / CC_WAVE;
