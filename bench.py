@@ -1,15 +1,22 @@
 #!/usr/bin/env python3
-"""Benchmark: chordless cycles/s on one MI355X.
+"""Benchmark: chordless cycles/s on one MI355X, batched vs per-graph launch.
 
-Workload: the 8x8 grid (n=64, m=112, ids permuted with seed 14104876+2),
-full enumeration of every chordless cycle as int32 vertex lists into
-device buffers.  One step = one whole pass of the path on the resident CSR:
-ingest + validation + degree labelling (cc_prepare), stage one, the level
-loop and the output (cc_enumerate), and the handle release.
+Headline workload: 4096 Erdos-Renyi graphs (n uniform in [16, 64], average
+degree uniform in [2.5, 5], seed 14104876+4), packed as one int32 CSR that is
+resident in device memory.  One step = one whole pass of the path over the
+batch: ingest + validation + degree labelling of every graph
+(cc_prepare_batch), stage one and the persistent depth-first launch with
+work stealing (cc_histogram_batch, count-only per-graph histograms), and the
+handle release.  The result of the timed steps must equal the stored oracle
+histograms.  Two per-graph baselines run the same workload: the same kernels
+launched once per graph on the same full grid, and one cc_prepare +
+cc_histogram call per graph.
 
 Prints one JSON line with the throughput, the roofline of the dominant
-kernel (the breadth-first level kernel, timed with HIP events on the stream
-it runs on), and the CPU oracle timed on this host as a baseline.
+kernel (the batched depth-first kernel, timed with HIP events on the stream
+it runs on), the CPU oracle timed on this host as a baseline, and the other
+workloads (8x8 grid enumeration, 7x12 grid count-only, ER G(40,100), the
+serving stream, the paper's Table 1 graphs).
 """
 import argparse
 import json
@@ -23,86 +30,298 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
-PROFILE = os.path.join(ROOT, "profiles", "k_step_grid8x8_enumerate.md")
-CSRC = os.path.join(ROOT, "paper_1410_4876_amd", "csrc")
+# LDS bandwidth from unit counts: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_GBPS = 256 * 128 * 2.4
+PROFILES = os.path.join(ROOT, "profiles")
 TABLE1 = os.path.join(ROOT, "tests", "golden", "table1.json")
 GRID7X12 = os.path.join(ROOT, "tests", "golden", "grid7x12.json")
+GRID8X8 = os.path.join(ROOT, "tests", "golden", "grid8x8.json")
+BATCH4096 = os.path.join(ROOT, "tests", "golden", "batch4096.json")
+BATCH_WORKLOAD = ("4096 ER graphs, n uniform in [16,64], average degree uniform in [2.5,5], "
+                  "one packed int32 CSR resident on the device; count-only per-graph histograms")
+# Algorithmic bytes per path processed by the depth-first kernel, count-only
+# with W-word bitsets: the rows N(vt) and N(v1) read (16W), and the path
+# state (X words, v1, vt) pushed once and popped once (2 * (8W + 2)).
+def dfs_bytes_per_path(W):
+    return 16 * W + 2 * (8 * W + 2)
 
 
-def library_sources_sha256():
-    """sha256 over the library's sources (kernels, their header, the
-    runtime that sizes their launches), in name order."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            h.update(open(os.path.join(CSRC, name), "rb").read())
-    return h.hexdigest()
-
-
-def counted_traffic():
-    """HBM bytes per level launch from the committed rocprofv3 PMC summary,
-    or None when the library sources have changed since the counters were
-    taken."""
+def counted_traffic(profile_name):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, or None
+    when the library sources have changed since the counters were taken."""
     import re
+
+    from paper_1410_4876_amd.build import sources_sha256
     try:
-        text = open(PROFILE).read()
+        text = open(os.path.join(PROFILES, profile_name)).read()
         data = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
-        src = library_sources_sha256()
     except (OSError, AttributeError, ValueError):
         return None
-    return data["traffic_bytes_per_launch"] if data.get("library_sources_sha256") == src else None
+    return (data["traffic_bytes_per_launch"]
+            if data.get("library_sources_sha256") == sources_sha256() else None)
 
 
-def cpu_baseline(g, budget_s=30.0):
-    """The oracle (single thread, one counting+storing pass) on the same
-    graph.  The 8x8 grid takes about 15 s, inside the bounded budget."""
+# ------------------------------------------------------------ CPU baseline
+def _cpu_info():
+    procs = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    # at most 16 workers: the share of host cores that goes with one GPU
+    return {"nproc": int(procs or 1), "workers": int(min(16, procs or 1)), "model": model}
+
+
+def _oracle_graph(args):
     import oracle
+    n, rp, ci, lo, hi = args
+    r = oracle.enumerate_cycles(n, rp, ci, want_cycles=False, root_lo=lo, root_hi=hi)
+    return int(r.hist.sum()), int(r.front.sum())
+
+
+def _bounded(jobs, workers, budget_s):
+    """Runs oracle jobs (graph, root range) in order until the time budget
+    is spent: in this process for one worker, else on a process pool
+    (forked before this process touches the GPU) with one job in flight per
+    worker.  Jobs already started when the budget runs out get up to
+    another budget to finish; any still running then are abandoned and
+    their work is not counted (the rate is then a lower bound).  Returns
+    (cycles, paths, jobs done, seconds, jobs abandoned)."""
+    import multiprocessing as mp
+    import queue
     t0 = time.perf_counter()
-    r = oracle.enumerate_single_pass(g.n, g.row_ptr, g.col_idx, verts_cap=64 << 20,
-                                     cyc_cap=4 << 20)
+    cyc = paths = done = 0
+    if workers == 1:
+        for j in jobs:
+            c, p = _oracle_graph(j)
+            cyc, paths, done = cyc + c, paths + p, done + 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        return cyc, paths, done, time.perf_counter() - t0, 0
+    ctx = mp.get_context("fork")
+    results = queue.Queue()
+    it = iter(jobs)
+    pool = ctx.Pool(workers)
+    try:
+        inflight = 0
+        for _ in range(workers):
+            j = next(it, None)
+            if j is None:
+                break
+            pool.apply_async(_oracle_graph, (j,), callback=results.put)
+            inflight += 1
+        while inflight:
+            left = 2 * budget_s - (time.perf_counter() - t0)
+            if left <= 0:
+                break
+            try:
+                c, p = results.get(timeout=left)
+            except queue.Empty:
+                break
+            inflight -= 1
+            cyc, paths, done = cyc + c, paths + p, done + 1
+            if time.perf_counter() - t0 <= budget_s:
+                j = next(it, None)
+                if j is not None:
+                    pool.apply_async(_oracle_graph, (j,), callback=results.put)
+                    inflight += 1
+        dt = time.perf_counter() - t0
+    finally:
+        pool.terminate()
+        pool.join()
+    return cyc, paths, done, dt, inflight
+
+
+def cpu_baselines(budget_s):
+    """The oracle as it stands, timed on this host's cores on bounded samples
+    of every config (run before the process touches the GPU).  Returns the
+    headline's baseline (the 4096-graph batch on all workers) and the
+    per-config table."""
+    import oracle
+    from paper_1410_4876_amd import graphgen as gg
+
+    info = _cpu_info()
+    W = info["workers"]
+    out = {"host": info}
+
+    def rate(res, cores, what):
+        c, p, d, dt, ab = res
+        note = f", {ab} started but unfinished, not counted" if ab else ""
+        return {"cycles_per_s": round(c / dt, 1), "paths_per_s": round(p / dt, 1),
+                "jobs_per_s": round(d / dt, 2), "cores": cores,
+                "sample": f"{d} {what} done in {dt:.1f} s{note}"}
+
+    b = gg.workload_batch4096()
+    jobs = [(g.n, g.row_ptr, g.col_idx, 0, oracle.INT64_MAX) for g in b.graphs]
+    out["batch4096_single_thread"] = rate(_bounded(jobs, 1, budget_s), 1,
+                                          "graphs (in order from graph 0)")
+    out["batch4096_all_cores"] = rate(_bounded(jobs, W, budget_s), W,
+                                      "graphs (in order from graph 0, one per worker at a time)")
+    g = gg.workload_er40()
+    t0 = time.perf_counter()
+    r = oracle.enumerate_single_pass(g.n, g.row_ptr, g.col_idx, verts_cap=1 << 22, cyc_cap=1 << 20)
     dt = time.perf_counter() - t0
-    return {"value": round(r.n_cycles / dt, 1), "unit": "chordless cycles/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"whole workload, one pass storing all cycles ({r.n_cycles} cycles, "
-                      f"{dt:.1f} s, single thread)"}
+    out["er40_single_thread"] = {"cycles_per_s": round(r.n_cycles / dt, 1), "cores": 1,
+                                 "sample": f"whole graph, cycles stored, {dt * 1e3:.1f} ms"}
+
+    def root_jobs(g, chunks):
+        roots = oracle.count_roots(g.n, g.row_ptr, g.col_idx)
+        bounds = np.linspace(0, roots, min(chunks, roots) + 1).astype(np.int64)
+        return [(g.n, g.row_ptr, g.col_idx, int(bounds[i]), int(bounds[i + 1]))
+                for i in range(len(bounds) - 1)]
+
+    out["grid8x8_single_thread"] = rate(_bounded(root_jobs(gg.workload_grid8x8(), 64), 1,
+                                                 budget_s / 2), 1,
+                                        "of 64 initial-triplet ranges (count-only)")
+    out["grid7x12_all_cores"] = rate(_bounded(root_jobs(gg.workload_grid7x12(), 512), W,
+                                              budget_s / 2), W,
+                                     "single initial triplets (count-only)")
+    reqs = gg.request_stream(rate_hz=2000.0, duration_s=5.0, k=5)
+    jobs = [(r.graph.n, r.graph.row_ptr, r.graph.col_idx, 0, oracle.INT64_MAX) for r in reqs]
+    out["serving_requests_all_cores"] = rate(_bounded(jobs, W, budget_s / 2), W,
+                                             "requests (in arrival order)")
+    head = out["batch4096_all_cores"]
+    return {"value": head["cycles_per_s"], "unit": "chordless cycles/s", "cores": W,
+            "kind": "oracle", "sample": "4096-graph batch: " + head["sample"],
+            "per_config": out}
 
 
-def batched_section(args):
-    """4096 ER graphs (n in [16, 64], d in [2.5, 5]): per-graph histograms
-    with one persistent launch (autotuned on a held-out calibration batch)
-    against the same kernels launched once per graph."""
+# ------------------------------------------------------------ headline
+def _batch_device(b):
+    import torch
+    return (torch.tensor(b.graph_vtx_off, dtype=torch.int32, device="cuda"),
+            torch.tensor(b.row_ptr, dtype=torch.int32, device="cuda"),
+            torch.tensor(b.col_idx, dtype=torch.int32, device="cuda"))
+
+
+def batched_headline(args):
+    """The 4096-graph batch: whole passes (prepare + persistent histogram +
+    release) on the resident CSR, autotuned launch options, HIP events
+    around the depth-first kernel; then the two per-graph baselines.  Every
+    result must equal the stored oracle histograms."""
     import torch
 
     from paper_1410_4876_amd import autotune, cc
     from paper_1410_4876_amd import graphgen as gg
 
+    gold = json.load(open(BATCH4096))
     tuned = autotune.tune_batch()
+    opts = tuned["options"]
     b = gg.workload_batch4096()
-    with cc.prepare_batch(b, **tuned["options"]) as h:
-        h.histograms()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            hist = h.histograms()
-        dt = (time.perf_counter() - t0) / args.steps
-        cycles = int(hist.sum())
-        paths = h.last_run()["paths"]
-        t0 = time.perf_counter()
-        hist_pg = h.histograms(per_graph_launch=True)
-        dt_pg = time.perf_counter() - t0
-        launches_pg = h.last_run()["levels_launched"]
-    assert np.array_equal(hist, hist_pg)
-    return {"workload": "4096 ER graphs, n in [16,64], d in [2.5,5]", "cycles": cycles,
-            "paths_expanded": int(paths),
-            "persistent": {"ms": round(dt * 1e3, 3), "cycles_per_s": round(cycles / dt, 1),
-                           "launches": 3},
-            "per_graph_launch": {"ms": round(dt_pg * 1e3, 3),
-                                 "cycles_per_s": round(cycles / dt_pg, 1),
-                                 "launches": int(launches_pg)},
-            "speedup": round(dt_pg / dt, 2),
-            "autotuned": tuned["options"], "autotune_calibration_ms": tuned["ms"]}
+    G = len(b.graphs)
+    sizes = np.diff(np.asarray(b.graph_vtx_off, np.int64))
+    hoff = np.zeros(G, np.int64)
+    hoff[1:] = np.cumsum(sizes + 1)[:-1]
+    total = int((sizes + 1).sum())
+    off_d, rp_d, ci_d = _batch_device(b)
+    stream = torch.cuda.current_stream()
+
+    def check(buf, what):
+        for g in range(G):
+            want = gold["hists"][g]
+            got = buf[hoff[g]:hoff[g] + sizes[g] + 1]
+            assert got[:len(want)].tolist() == want and not got[len(want):].any(), (what, g)
+
+    buf = np.zeros(total, np.int64)
+    infos = []
+
+    def step():
+        with cc.Batch(off_d, rp_d, ci_d, stream=stream, sizes=sizes, profile=True, **opts) as h:
+            h.histograms_into(buf, hoff)
+            infos.append(h.last_run())
+
+    for _ in range(args.warmup):
+        step()
+    infos.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    check(buf, "persistent")
+    cycles = int(gold["total_cycles"])
+    paths = int(infos[-1]["paths"])
+    assert paths == gold["total_paths"] and int(infos[-1]["cycles"]) == cycles
+    ms_step = elapsed * 1e3 / args.steps
+    dfs_ms = float(np.mean([i["dfs_ms"] for i in infos]))
+    hist_ms = float(np.mean([i["gpu_ms"] for i in infos]))
+
+    # baseline A: the same kernels, one launch group per graph, same grid
+    buf_a = np.zeros(total, np.int64)
+    t0 = time.perf_counter()
+    with cc.Batch(off_d, rp_d, ci_d, stream=stream, sizes=sizes, **opts) as h:
+        h.histograms_into(buf_a, hoff, per_graph_launch=True)
+        launches_a = h.last_run()["levels_launched"]
+    torch.cuda.synchronize()
+    dt_a = time.perf_counter() - t0
+    check(buf_a, "per-graph launch")
+
+    # baseline B: one cc_prepare + cc_histogram call per graph, each graph's
+    # CSR resident on the device
+    dev_graphs = [(g.n, torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda"),
+                   torch.tensor(g.col_idx if g.col_idx.size else np.zeros(1, np.int32),
+                                dtype=torch.int32, device="cuda")) for g in b.graphs]
+    buf_b = np.zeros(total, np.int64)
+
+    def per_graph_calls(lo, hi):
+        for g in range(lo, hi):
+            n, rp, ci = dev_graphs[g]
+            with cc.Graph(n, rp, ci, stream=stream) as h:
+                buf_b[hoff[g]:hoff[g] + n + 1] = h.histogram()
+
+    per_graph_calls(0, 64)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_graph_calls(0, G)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    check(buf_b, "per-graph calls")
+
+    W = 1 if int(sizes.max()) <= 64 else 2
+    bpp = dfs_bytes_per_path(W)
+    achieved = paths * bpp / (dfs_ms * 1e-3) / 1e9
+    dt = elapsed / args.steps
+    base = min(dt_a, dt_b)
+    return {
+        "ms_per_step": round(ms_step, 4),
+        "value": round(cycles * args.steps / elapsed, 1),
+        "config": {"workload": BATCH_WORKLOAD, "graphs": G, "cycles": cycles,
+                   "paths_expanded": paths, "parallelism": "single GPU",
+                   "launch": "persistent (stage one of every graph in one launch, one "
+                             "persistent depth-first launch with work stealing)"},
+        "paths_per_s": round(paths * args.steps / elapsed, 1),
+        "roofline": {"bound": "lds", "kernel": f"k_dfs<W={W}, count-only, batch>",
+                     "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBPS, 1),
+                     "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 4),
+                     "traffic": counted_traffic("k_dfs_batch4096.md"),
+                     "bytes_per_path": bpp, "paths_per_launch": paths,
+                     "avg_launch_us": round(dfs_ms * 1e3, 3),
+                     "measured": "HIP events around the depth-first launch on the batch's "
+                                 "stream, in every timed step"},
+        "batched": {
+            "parity": "every timed pass and both baselines equal the stored oracle histograms",
+            "persistent": {"ms_per_pass": round(dt * 1e3, 3),
+                           "histogram_call_gpu_ms": round(hist_ms, 3),
+                           "depth_first_ms": round(dfs_ms, 3),
+                           "cycles_per_s": round(cycles / dt, 1), "launches": 3},
+            "per_graph_launch": {"ms": round(dt_a * 1e3, 3),
+                                 "cycles_per_s": round(cycles / dt_a, 1),
+                                 "launches": int(launches_a),
+                                 "form": "prepare_batch, then stage one + depth-first launch "
+                                         "per graph, the depth-first kernel on the same full "
+                                         "grid as the persistent launch"},
+            "per_graph_calls": {"ms": round(dt_b * 1e3, 3), "cycles_per_s": round(cycles / dt_b, 1),
+                                "form": "cc_prepare + cc_histogram + cc_release per graph, each "
+                                        "graph's CSR resident on the device"},
+            "speedup": round(base / dt, 2),
+            "speedup_vs": "per_graph_launch" if dt_a <= dt_b else "per_graph_calls",
+            "autotuned": opts, "autotune_calibration_ms": tuned["ms"]},
+    }
 
 
 def table1_section(args):
@@ -342,7 +561,9 @@ def large_n_section():
 def serving_section(args):
     """Open-loop Poisson request stream (2000 requests/s; half p x q grids,
     p, q in 3..7, half ER graphs, n in 20..80, d in [3, 5]) replayed against
-    the serving loop; p50/p99 latency beside throughput."""
+    the serving loop; p50/p99 latency beside throughput.  Every reply is
+    then checked against the same graph run alone (cc_prepare +
+    cc_histogram)."""
     from paper_1410_4876_amd import cc, loadgen
     from paper_1410_4876_amd import graphgen as gg
 
@@ -352,10 +573,103 @@ def serving_section(args):
         loadgen.run_stream(sv, gg.request_stream(rate_hz=2000.0, duration_s=0.2, k=1005))
         r = loadgen.run_stream(sv, reqs)
     out = {k: v for k, v in r.items() if k not in ("hists", "statuses")}
+    t0 = time.perf_counter()
+    bad = 0
+    for q, h, st in zip(reqs, r["hists"], r["statuses"]):
+        with cc.prepare(q.graph) as g:
+            alone = g.histogram()
+        if st != 0 or h is None or not np.array_equal(h, alone):
+            bad += 1
+    out["replies_equal_alone"] = bad == 0
+    out["replies_checked"] = len(reqs)
+    out["check_s"] = round(time.perf_counter() - t0, 1)
+    assert bad == 0, f"{bad} serving replies differ from the graph run alone"
     out["workload"] = (f"Poisson stream at 2000 requests/s for {args.serve_seconds:g} s: "
                        "grids p x q (p, q in 3..7) and ER graphs (n in 20..80, d in [3,5]), "
                        "ids permuted")
     return out
+
+
+def grid8x8_section(args):
+    """8x8 grid (n=64, m=112, ids permuted), full enumeration as int32
+    vertex lists into device buffers: whole passes (prepare, enumerate,
+    release), the canonical cycle set's size checked against the stored
+    oracle output, and the roofline of the breadth-first step kernel."""
+    import torch
+
+    from paper_1410_4876_amd import cc
+    from paper_1410_4876_amd import graphgen as gg
+
+    gold = json.load(open(GRID8X8))
+    g = gg.workload_grid8x8()
+    rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
+    ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    n_cycles, n_verts = gold["total_cycles"], gold["total_verts"]
+    verts = torch.empty(n_verts, dtype=torch.int32, device="cuda")
+    offs = torch.empty(n_cycles + 1, dtype=torch.int64, device="cuda")
+
+    def step(profile):
+        with cc.Graph(g.n, rp, ci, stream=stream, profile=profile) as h:
+            nc, nv = h.enumerate_into(verts, offs)
+            assert nc == n_cycles and nv == n_verts
+            return h.last_run(), h.frontier()
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step(False)[0] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    info, front = step(False)
+    assert front.tolist() == gold["front"]
+    # a second pass with HIP events around every step launch
+    pinfos = [step(True)[0] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    lvl_ms = sum(i["level_ms"] for i in pinfos)
+    launches = sum(i["levels_launched"] for i in pinfos)
+    avg_us = lvl_ms * 1e3 / max(launches, 1)
+    model_bytes = sum(i["level_bytes"] for i in pinfos) / max(launches, 1)
+    # the same figure with the survey's bytes per unit: 36 B per path
+    # processed (X and S words and the end vertices, written once, read
+    # once), per cycle 8 B of staged bitset and 4k + 8 B of output
+    paths = int(info["paths"])
+    W = 1
+    per_step = paths * 2 * (16 * W + 2) + n_cycles * (8 * W + 8) + n_verts * 4
+    unit_bytes = per_step / (launches / len(pinfos))
+    ach_model = model_bytes / (avg_us * 1e-6) / 1e9
+    ach_unit = unit_bytes / (avg_us * 1e-6) / 1e9
+    return {"workload": "grid 8x8 (n=64, m=112), ids permuted, full enumeration to int32 "
+                        "vertex lists", "cycles": n_cycles, "vertices_out": n_verts,
+            "paths_expanded": paths, "ms_per_step": round(elapsed * 1e3 / args.steps, 4),
+            "cycles_per_s": round(n_cycles * args.steps / elapsed, 1),
+            "paths_per_s": round(paths * args.steps / elapsed, 1),
+            "roofline": {"bound": "hbm", "kernel": "k_step (breadth-first step: one or two "
+                                                  "levels per launch, staged-cycle decode)",
+                         "achieved": round(ach_unit, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(ach_unit / HBM_PEAK_GBPS, 4),
+                         "bytes_per_launch": round(unit_bytes, 1),
+                         "bytes_rule": "36 B per path processed + (8W + 8) B per cycle + 4 B "
+                                       "per output vertex id, over the step launches",
+                         "model_bytes_per_launch": round(model_bytes, 1),
+                         "model_achieved": round(ach_model, 1),
+                         "model_frac": round(ach_model / HBM_PEAK_GBPS, 4),
+                         "traffic": counted_traffic("k_step_grid8x8_enumerate.md"),
+                         "avg_launch_us": round(avg_us, 3),
+                         "launches_per_step": round(launches / len(pinfos), 1),
+                         "measured": "HIP events around every step launch, second pass of "
+                                     "the timed steps"},
+            "breakdown_ms": {
+                "stage1": round(sum(i["stage1_ms"] for i in pinfos) / len(pinfos), 4),
+                "head": round(sum(i["head_ms"] for i in pinfos) / len(pinfos), 4),
+                "levels": round(lvl_ms / len(pinfos), 4),
+                "dfs": round(sum(i["dfs_ms"] for i in pinfos) / len(pinfos), 4)},
+            "head_steps": pinfos[-1]["head_steps"]}
+
+
+SECTIONS = ["batched", "grid8x8", "er40", "grid7x12", "paging", "large_n", "table1",
+            "serving", "cpu"]
 
 
 def main():
@@ -364,23 +678,19 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="time budget of each bounded oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain 1 GiB device-to-device copy (counter calibration)")
-    ap.add_argument("--no-batch", action="store_true",
-                    help="skip the 4096-graph batched vs per-graph-launch comparison")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="length of the replayed request stream (the full stream is 60 s)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the replayed request stream")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the structured graphs of the paper's Table 1")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the ER G(40,100) latency, 7x12 count-only and paging sections")
-    ap.add_argument("--section",
-                    choices=["er40", "grid7x12", "paging", "large_n", "table1", "batched",
-                             "serving"],
+                    help="skip the 8x8, ER G(40,100), 7x12, paging and large-graph sections")
+    ap.add_argument("--section", choices=SECTIONS,
                     help="run only this section and print its JSON (for profiling one workload)")
-    ap.add_argument("--no-profile", action="store_true",
-                    help="time steps without per-kernel HIP events (no roofline)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the path shards by triplet "
@@ -388,22 +698,20 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    # the oracle runs first, on forked workers, before this process touches the GPU
+    cpu = None
+    if args.section == "cpu" or (not args.section and not args.no_cpu_baseline):
+        cpu = cpu_baselines(args.cpu_seconds)
+        if args.section == "cpu":
+            print(json.dumps({"cpu": cpu}), flush=True)
+            return
+
     import torch
 
-    from paper_1410_4876_amd import cc
-    from paper_1410_4876_amd import graphgen as gg
-
     torch.cuda.set_device(0)
-    if args.section:
-        fn = {"er40": er40_section, "grid7x12": grid7x12_section, "paging": paging_section,
-              "large_n": large_n_section,
-              "table1": lambda: table1_section(args), "batched": lambda: batched_section(args),
-              "serving": lambda: serving_section(args)}[args.section]
-        print(json.dumps({args.section: fn()}), flush=True)
-        return
     if args.calibrate_copy:
         # A plain copy of known size: what the HBM byte counters read for it
-        # scales the counters read for the level kernel.
+        # scales the counters read for the kernels.
         src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(args.warmup):
@@ -418,105 +726,46 @@ def main():
                           "ms": round(dt * 1e3, 4),
                           "GBps_read_plus_write": round(2 * src.numel() * 4 / dt / 1e9, 1)}))
         return
-    g = gg.workload_grid8x8()
-    rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
-    ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
-    stream = torch.cuda.current_stream()
-    profile = not args.no_profile
+    if args.section:
+        fn = {"er40": er40_section, "grid7x12": grid7x12_section, "paging": paging_section,
+              "large_n": large_n_section, "grid8x8": lambda: grid8x8_section(args),
+              "table1": lambda: table1_section(args), "batched": lambda: batched_headline(args),
+              "serving": lambda: serving_section(args)}[args.section]
+        print(json.dumps({args.section: fn()}), flush=True)
+        return
 
-    # exact output sizes (outside the timed region)
-    with cc.Graph(g.n, rp, ci, stream=stream) as h0:
-        hist = h0.histogram()
-    n_cycles = int(hist.sum())
-    n_verts = int((hist * np.arange(hist.size)).sum())
-    verts = torch.empty(n_verts, dtype=torch.int32, device="cuda")
-    offs = torch.empty(n_cycles + 1, dtype=torch.int64, device="cuda")
-
-    def step(profile, persistent_levels=False):
-        with cc.Graph(g.n, rp, ci, stream=stream, profile=profile,
-                      persistent_levels=persistent_levels) as h:
-            nc, nv = h.enumerate_into(verts, offs)
-            assert nc == n_cycles and nv == n_verts
-            return h.last_run()
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = [step(False) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-
+    head = batched_headline(args)
     out = {
-        "metric": "chordless cycles/s on 1 MI355X",
-        "value": round(n_cycles * args.steps / elapsed, 1),
+        "metric": "chordless cycles/s on 1 MI355X, batched vs per-graph launch; p99 latency",
+        "value": head["value"],
         "unit": "chordless cycles/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "grid 8x8 (n=64, m=112), ids permuted, full enumeration to "
-                               "int32 vertex lists", "cycles": n_cycles, "vertices_out": n_verts,
-                   "paths_expanded": int(infos[-1]["paths"]), "parallelism": "single GPU"},
-        "paths_per_s": round(infos[-1]["paths"] * args.steps / elapsed, 1),
-        "gpu_ms_per_step": round(sum(i["gpu_ms"] for i in infos) / len(infos), 4),
+        "config": head["config"],
+        "paths_per_s": head["paths_per_s"],
+        "roofline": head["roofline"],
+        "batched": head["batched"],
     }
-    if profile:
-        # Second timed pass of the same steps with HIP event pairs around
-        # every breadth-first step launch (on the stream the kernels run on):
-        # the step kernel's average launch duration and the bytes it must
-        # move.
-        torch.cuda.synchronize()
-        pinfos = [step(True) for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        lvl_ms = sum(i["level_ms"] for i in pinfos)
-        lvl_bytes = sum(i["level_bytes"] for i in pinfos)
-        launches = sum(i["levels_launched"] for i in pinfos)
-        achieved = lvl_bytes / (lvl_ms * 1e-3) / 1e9 if lvl_ms > 0 else 0.0
-        persistent = launches == len(pinfos)
-        out["roofline"] = {"bound": "hbm",
-                           "kernel": ("k_levels (all breadth-first steps in one cooperative "
-                                      "launch)" if persistent else
-                                      "k_step (breadth-first step: one or two levels per "
-                                      "launch, staged-cycle decode)"),
-                           "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                           "traffic": counted_traffic(),
-                           "bytes_per_launch": round(lvl_bytes / max(launches, 1), 1),
-                           "avg_launch_us": round(lvl_ms * 1e3 / max(launches, 1), 3),
-                           "launches_per_step": round(launches / len(pinfos), 1),
-                           "measured": "HIP events around every step launch, second pass of "
-                                       "the timed steps"}
-        out["breakdown_ms"] = {
-            "stage1": round(sum(i["stage1_ms"] for i in pinfos) / len(pinfos), 4),
-            "head": round(sum(i["head_ms"] for i in pinfos) / len(pinfos), 4),
-            "levels": round(lvl_ms / len(pinfos), 4),
-            "dfs": round(sum(i["dfs_ms"] for i in pinfos) / len(pinfos), 4)}
-        out["head_steps"] = pinfos[-1]["head_steps"]
-        # the same step with all levels in one cooperative launch, for comparison
-        for _ in range(2):
-            step(False, persistent_levels=True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            step(False, persistent_levels=True)
-        torch.cuda.synchronize()
-        out["persistent_level_loop_ms_per_step"] = round(
-            (time.perf_counter() - t1) * 1e3 / args.steps, 4)
-    if not args.no_batch:
-        out["batched"] = batched_section(args)
+    print(json.dumps({"progress": "batched", "value": out["value"],
+                      "speedup": out["batched"]["speedup"]}), file=sys.stderr, flush=True)
     if not args.no_serve:
         out["serving"] = serving_section(args)
+        out["p99_latency_ms"] = out["serving"]["latency_ms"]["p99"]
+        print(json.dumps({"progress": "serving", "latency_ms": out["serving"]["latency_ms"]}),
+              file=sys.stderr, flush=True)
     if not args.no_extra:
+        out["grid8x8"] = grid8x8_section(args)
         out["er40"] = er40_section()
         out["grid7x12"] = grid7x12_section()
         out["paging"] = paging_section()
         out["large_n"] = large_n_section()
+        print(json.dumps({"progress": "sections"}), file=sys.stderr, flush=True)
     if not args.no_table1:
         out["table1"] = table1_section(args)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -46,7 +46,7 @@ extern "C" {
 
 #define CC_MAX_VERTICES 256        /* one graph (cc_prepare)                         */
 #define CC_MAX_BATCH_VERTICES 128  /* each graph of a batch or of a serving request */
-#define CC_ABI_VERSION 1
+#define CC_ABI_VERSION 2
 
 typedef enum cc_status {
   CC_OK = 0,
@@ -204,29 +204,48 @@ void cc_release(cc_graph *g);
 typedef struct cc_batch cc_batch;
 
 #define CC_BATCH_PERSISTENT 0 /* stage one of all graphs in one launch, then one
-                                 persistent depth-first launch with work stealing */
-#define CC_BATCH_PER_GRAPH  1 /* the same kernels launched once per graph
-                                 (baseline for comparison)                       */
+                                 persistent depth-first launch with work stealing
+                                 over every graph's initial triplets             */
+#define CC_BATCH_PER_GRAPH  1 /* the same kernels launched once per graph, the
+                                 depth-first kernel on the same full grid
+                                 (the baseline the persistent form is compared to) */
 
 /* cc_prepare_batch -- validate every graph and compute its degree labelling
  * (one block per graph).  graph_vtx_off has n_graphs+1 entries; with
  * CC_INPUT_DEVICE all three arrays are device pointers.  Errors as
- * cc_prepare (NOT_SIMPLE if any graph is not simple). */
+ * cc_prepare (NOT_SIMPLE if any graph is not simple).  The batch has a
+ * handle type of its own (cc_batch, not cc_graph) so that single-graph calls
+ * cannot be given a batch by mistake. */
 cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const int32_t *row_ptr,
                            const int32_t *col_idx, const cc_options *opt, cc_batch **out);
 
-/* cc_histogram_batch -- per-graph histograms: hists[g * hist_stride + k] =
- * cycles with k vertices in graph g (host array, hist_stride >= largest
- * graph + 1; entries past a graph's size are zero).  mode is
- * CC_BATCH_PERSISTENT or CC_BATCH_PER_GRAPH; both give the same numbers. */
-cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, int32_t mode);
+/* cc_histogram_batch -- per-graph histograms (Table 1's C3 and #clc columns
+ * per length, for every graph of the batch), count-only, in the persistent
+ * form.  Graph g with n_g vertices writes hists[hist_off[g] + k] = cycles
+ * with k vertices, for 0 <= k <= n_g (n_g + 1 entries; entries 0..2 are 0).
+ *   hists     host array the caller sizes to cover every graph's range
+ *   hist_off  host array of n_graphs offsets, each >= 0; the ranges must not
+ *             overlap (g * (max_n + 1) gives a dense [G x (max_n + 1)] table)
+ * Errors: INVALID_ARG (NULL arrays with n_graphs > 0, a negative offset),
+ * OUT_OF_MEMORY (workspace, or a depth-first stack ran out), INTERNAL, DEVICE.
+ * The entries of hists outside the graphs' ranges are not touched. */
+cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, const int64_t *hist_off);
+
+/* cc_histogram_batch_mode -- cc_histogram_batch with the launch form chosen:
+ * mode is CC_BATCH_PERSISTENT (what cc_histogram_batch runs) or
+ * CC_BATCH_PER_GRAPH; both give the same numbers. */
+cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hist_off,
+                                  int32_t mode);
 
 /* cc_batch_labels -- degree label of every vertex (host array of the total
  * vertex count, indexed by global id; labels are local to each graph). */
 cc_status cc_batch_labels(cc_batch *b, int32_t *labels);
 
 /* cc_batch_last_run -- statistics of the last cc_histogram_batch call
- * (levels_launched counts kernel launches; paths is the batch total). */
+ * (levels_launched counts kernel launches; paths is the batch total; with
+ * CC_PROFILE in the batch's options, a persistent-form call also fills
+ * stage1_ms and dfs_ms, HIP events on the batch's stream around stage one
+ * and around the depth-first kernel). */
 cc_status cc_batch_last_run(cc_batch *b, cc_run_info *info);
 
 /* cc_release_batch -- free a batch handle (NULL is ignored). */

@@ -5,7 +5,9 @@ number of paths a wavefront must hold before it answers a work request, and
 how many handed-over paths a wavefront claims per atomic.  tune_batch()
 times every candidate on a held-out calibration batch (a different seed from
 any workload it is used on), keeps the fastest, and caches the choice as
-JSON keyed by the device name and the workload class.
+JSON keyed by the device name, the workload class, the candidate grid and a
+hash of the library's sources (a choice made for other kernels is not
+reused).
 """
 from __future__ import annotations
 
@@ -53,14 +55,17 @@ def tune_batch(workload_class: str = "er_n16-64_d2.5-5", calibration=None, grid=
     from . import cc
     from . import graphgen as gg
 
+    from .build import sources_sha256
+
     cache_path = cache_path or _cache_path()
-    key = f"{_device_key()}|{workload_class}|cal4096"
+    grid = grid or DEFAULT_GRID
+    grid_key = json.dumps(grid, sort_keys=True)
+    key = f"{_device_key()}|{workload_class}|cal4096|{grid_key}|{sources_sha256()[:16]}"
     cache = _load_cache(cache_path)
     if key in cache and not force:
         return cache[key]
     if calibration is None:
         calibration = gg.pack_batch(gg.er_batch_graphs(4096, k=1004))
-    grid = grid or DEFAULT_GRID
     names = list(grid)
     table = []
     ref = None

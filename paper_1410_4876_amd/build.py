@@ -19,6 +19,21 @@ HIPCC_FLAGS = [
 ]
 
 
+def sources_sha256() -> str:
+    """sha256 over the library's sources (kernels, their headers, the runtime
+    that sizes their launches, the public header), in name order: a key for
+    anything measured on, or tuned for, one version of the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".h")):
+                h.update(name.encode())
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []

@@ -124,8 +124,10 @@ def lib():
             L.cc_abi_version.restype = i32
             L.cc_prepare_batch.argtypes = [i32, vp, vp, vp, ctypes.POINTER(Options), pp]
             L.cc_prepare_batch.restype = ctypes.c_int
-            L.cc_histogram_batch.argtypes = [vp, vp, i32, i32]
+            L.cc_histogram_batch.argtypes = [vp, vp, vp]
             L.cc_histogram_batch.restype = ctypes.c_int
+            L.cc_histogram_batch_mode.argtypes = [vp, vp, vp, i32]
+            L.cc_histogram_batch_mode.restype = ctypes.c_int
             L.cc_batch_labels.argtypes = [vp, vp]
             L.cc_batch_labels.restype = ctypes.c_int
             L.cc_batch_last_run.argtypes = [vp, ctypes.POINTER(RunInfo)]
@@ -421,7 +423,8 @@ class Batch:
     """Many graphs packed as one CSR (cc_prepare_batch)."""
 
     def __init__(self, graph_vtx_off, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
-                 dfs_waves_per_cu: int = 0, dfs_donate_min: int = 0, dfs_claim: int = 0):
+                 dfs_waves_per_cu: int = 0, dfs_donate_min: int = 0, dfs_claim: int = 0,
+                 profile: bool = False, sizes=None):
         L = lib()
         off, off_dev, k0 = _ptr(_as_i32(graph_vtx_off))
         rp, rp_dev, k1 = _ptr(_as_i32(row_ptr))
@@ -430,12 +433,15 @@ class Batch:
             raise ValueError("batch arrays must all be host or all be device")
         self.n_graphs = int((graph_vtx_off.numel() if _is_torch(graph_vtx_off)
                              else np.asarray(graph_vtx_off).size) - 1)
-        sizes = np.diff(np.asarray(graph_vtx_off.cpu() if _is_torch(graph_vtx_off)
-                                   else graph_vtx_off, dtype=np.int64))
-        self.sizes = sizes
-        self.n_vertices = int(sizes.sum())
-        self.max_n = int(sizes.max()) if sizes.size else 0
+        if sizes is None:  # graph sizes on the host (pass them to skip a device read)
+            sizes = np.diff(np.asarray(graph_vtx_off.cpu() if _is_torch(graph_vtx_off)
+                                       else graph_vtx_off, dtype=np.int64))
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.n_vertices = int(self.sizes.sum())
+        self.max_n = int(self.sizes.max()) if self.sizes.size else 0
         flags = CC_INPUT_DEVICE if off_dev else 0
+        if profile:
+            flags |= CC_PROFILE
         self.opt = Options(_stream_handle(stream), int(budget_bytes), flags, 0,
                            int(dfs_waves_per_cu), 0, int(dfs_donate_min), int(dfs_claim))
         h = ctypes.c_void_p()
@@ -461,13 +467,34 @@ class Batch:
             pass
 
     def histograms(self, per_graph_launch: bool = False) -> np.ndarray:
-        """[n_graphs, max_n + 1] int64: row g is graph g's histogram."""
+        """[n_graphs, max_n + 1] int64: row g is graph g's histogram (zero past
+        the graph's own n + 1 entries)."""
         stride = self.max_n + 1
         out = np.zeros((self.n_graphs, stride), np.int64)
-        mode = CC_BATCH_PER_GRAPH if per_graph_launch else CC_BATCH_PERSISTENT
-        _check(lib().cc_histogram_batch(self.h, ctypes.c_void_p(out.ctypes.data), stride, mode),
-               "cc_histogram_batch", lambda p: lib().cc_batch_last_run(self.h, p))
+        off = np.arange(self.n_graphs, dtype=np.int64) * stride
+        self.histograms_into(out.reshape(-1), off, per_graph_launch)
         return out
+
+    def histograms_into(self, hists: np.ndarray, hist_off: np.ndarray,
+                        per_graph_launch: bool = False) -> None:
+        """cc_histogram_batch: graph g's histogram (n_g + 1 entries) into
+        hists[hist_off[g]:]; `hists` is a host int64 array covering every
+        range, `hist_off` int64 offsets."""
+        hists = np.asarray(hists)
+        if hists.dtype != np.int64 or not hists.flags.c_contiguous:
+            raise ValueError("hists must be a contiguous int64 array")
+        off = np.ascontiguousarray(hist_off, dtype=np.int64)
+        if off.size != self.n_graphs:
+            raise ValueError("hist_off needs one offset per graph")
+        if off.size and (off.min() < 0 or (off + self.sizes + 1).max() > hists.size):
+            raise ValueError("a graph's histogram range falls outside hists")
+        hp = ctypes.c_void_p(hists.ctypes.data)
+        op = ctypes.c_void_p(off.ctypes.data)
+        if per_graph_launch:
+            st = lib().cc_histogram_batch_mode(self.h, hp, op, CC_BATCH_PER_GRAPH)
+        else:
+            st = lib().cc_histogram_batch(self.h, hp, op)
+        _check(st, "cc_histogram_batch", lambda p: lib().cc_batch_last_run(self.h, p))
 
     def labels(self) -> np.ndarray:
         lab = np.zeros(max(self.n_vertices, 1), np.int32)

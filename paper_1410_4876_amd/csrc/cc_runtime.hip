@@ -950,6 +950,7 @@ struct cc_batch {
   CcCtl *d_ctl = nullptr;
   CcCtl *h_ctl = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evp[4] = {};  // CC_PROFILE: around stage one and the depth-first kernel
   cc_run_info info{};
 };
 
@@ -965,6 +966,8 @@ void cc_release_batch(cc_batch *b) {
   if (b->h_ctl) (void)hipHostFree(b->h_ctl);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
+  for (hipEvent_t ev : b->evp)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
 }
 
@@ -1097,12 +1100,14 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   return CC_OK;
 }
 
-cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, int32_t mode) {
-  if (!b || !hists || hist_stride < b->max_n + 1) return CC_ERR_INVALID_ARG;
+cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hist_off,
+                                  int32_t mode) {
+  if (!b || (b->G > 0 && (!hists || !hist_off))) return CC_ERR_INVALID_ARG;
   if (mode != CC_BATCH_PERSISTENT && mode != CC_BATCH_PER_GRAPH) return CC_ERR_INVALID_ARG;
+  for (int g = 0; g < b->G; ++g)
+    if (hist_off[g] < 0) return CC_ERR_INVALID_ARG;
   if (hipSetDevice(b->device) != hipSuccess) return CC_ERR_DEVICE;
   const int G = b->G;
-  for (size_t i = 0; i < (size_t)G * hist_stride; ++i) hists[i] = 0;
   b->info = cc_run_info{};
   if (G == 0) return CC_OK;
   hipStream_t s = b->stream;
@@ -1113,8 +1118,8 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
   int waves_per_cu = b->opt.dfs_waves_per_cu > 0 ? b->opt.dfs_waves_per_cu : 24;
   waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
   const bool per_graph = mode == CC_BATCH_PER_GRAPH;
-  // per-graph launches use a small grid: at most 64 blocks per graph
-  const int want_waves = per_graph ? 256 : std::max(4, (b->dev.cus * waves_per_cu) / 4 * 4);
+  // both forms launch the depth-first kernel on the same full grid
+  const int want_waves = std::max(4, (b->dev.cus * waves_per_cu) / 4 * 4);
   const int64_t budget = b->opt.frontier_budget_bytes > 0 ? b->opt.frontier_budget_bytes
                                                           : kDefaultBudget;
   // workspace: root slots (X words, end vertices, graph id), per-graph
@@ -1153,6 +1158,12 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
   auto chk = [&](hipError_t x) {
     if (x != hipSuccess && e == hipSuccess) e = x;
   };
+  // CC_PROFILE (persistent form): HIP events on this stream around stage
+  // one and around the depth-first kernel
+  const bool prof = (b->opt.flags & CC_PROFILE) != 0 && !per_graph;
+  if (prof)
+    for (hipEvent_t &ev : b->evp)
+      if (!ev) chk(hipEventCreate(&ev));
   chk(hipEventRecord(b->ev0, s));
   chk(cc_launch_zero(ctl, sizeof(CcCtl), s));
   chk(cc_launch_zero(bt.hist, hist_b, s));
@@ -1161,11 +1172,15 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
     // one launch for stage one of every graph, one persistent depth-first
     // launch over all their initial triplets
     bt.g0 = 0;
+    if (prof) chk(hipEventRecord(b->evp[0], s));
     chk(cc_launch_triplets_batch(W, bt, G, s));
+    if (prof) chk(hipEventRecord(b->evp[1], s));
     bt.r0 = 0;
     bt.r1 = (unsigned long long)b->root_off[G];
     chk(cc_launch_dfs_prepare(ctl, wk, b->max_n, false, s));
+    if (prof) chk(hipEventRecord(b->evp[2], s));
     chk(cc_launch_dfs_batch(W, gd, ctl, wk, bt, nw / 4, idle_timeout, s));
+    if (prof) chk(hipEventRecord(b->evp[3], s));
     launches = 3;
   } else {
     // the same kernels, one graph at a time
@@ -1174,10 +1189,8 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
       chk(cc_launch_triplets_batch(W, bt, 1, s));
       bt.r0 = (unsigned long long)b->root_off[g];
       bt.r1 = (unsigned long long)b->root_off[g + 1];
-      const unsigned long long slots = bt.r1 - bt.r0;
-      const int blocks = (int)std::min<unsigned long long>(nw / 4, std::max(1ull, (slots + 255) / 256));
       chk(cc_launch_dfs_prepare(ctl, wk, b->max_n, false, s));
-      chk(cc_launch_dfs_batch(W, gd, ctl, wk, bt, blocks, idle_timeout, s));
+      chk(cc_launch_dfs_batch(W, gd, ctl, wk, bt, nw / 4, idle_timeout, s));
       launches += 3;
     }
   }
@@ -1193,8 +1206,9 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
   int64_t cycles = 0, paths = 0;
   for (int g = 0; g < G; ++g) {
     const int ng = b->vtx_off[g + 1] - b->vtx_off[g];
+    int64_t *dst = hists + hist_off[g];
     for (int k = 0; k <= ng; ++k) {
-      hists[(size_t)g * hist_stride + k] = (int64_t)hh[(size_t)g * dstride + k];
+      dst[k] = (int64_t)hh[(size_t)g * dstride + k];
       cycles += (int64_t)hh[(size_t)g * dstride + k];
     }
   }
@@ -1205,10 +1219,21 @@ cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, int32_t hist_stride, i
   b->info.paths = paths;
   b->info.levels_launched = launches;
   b->info.gpu_ms = ms;
+  if (prof) {
+    float a = 0.f, c = 0.f;
+    (void)hipEventElapsedTime(&a, b->evp[0], b->evp[1]);
+    (void)hipEventElapsedTime(&c, b->evp[2], b->evp[3]);
+    b->info.stage1_ms = a;
+    b->info.dfs_ms = c;
+  }
   b->info.device_diag = (int64_t)b->h_ctl->diag;
   if (b->h_ctl->status & (CC_DEV_CORRUPT | CC_DEV_LOST)) return CC_ERR_INTERNAL;
   if (b->h_ctl->status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
   return CC_OK;
+}
+
+cc_status cc_histogram_batch(cc_batch *b, int64_t *hists, const int64_t *hist_off) {
+  return cc_histogram_batch_mode(b, hists, hist_off, CC_BATCH_PERSISTENT);
 }
 
 cc_status cc_batch_last_run(cc_batch *b, cc_run_info *info) {

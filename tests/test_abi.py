@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_status_strings_and_version(L):
     from paper_1410_4876_amd import cc
-    assert L.cc_abi_version() == 1
+    assert L.cc_abi_version() == 2
     for code in range(-9, 1):
         assert cc.status_string(code) and cc.status_string(code) != "unknown status"
     assert cc.status_string(-99) == "unknown status"
@@ -100,6 +100,11 @@ def test_argument_errors_before_any_device_call(L):
     assert L.cc_enumerate_lengths(None, 3, 5, None, 0, offs, 1, ctypes.byref(nc),
                                   ctypes.byref(nv)) == cc.CC_ERR_INVALID_ARG
     L.cc_release(None)
+    # batch calls on a null handle
+    hists = (ctypes.c_int64 * 4)()
+    hoff = (ctypes.c_int64 * 1)(0)
+    assert L.cc_histogram_batch(None, hists, hoff) == cc.CC_ERR_INVALID_ARG
+    assert L.cc_histogram_batch_mode(None, hists, hoff, 0) == cc.CC_ERR_INVALID_ARG
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

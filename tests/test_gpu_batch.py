@@ -110,3 +110,30 @@ def test_workload_batch4096(cc):
     for i, want in enumerate(gold["hists"]):
         assert got[i, :len(want)].tolist() == want, f"graph {i}"
     assert info["paths"] == gold["total_paths"]
+
+
+def test_batch_hist_off_places_each_graph(cc):
+    """cc_histogram_batch's hist_off contract: graph g's n_g + 1 entries go to
+    hists[hist_off[g]:], in any order and with gaps; nothing else is
+    written.  Both launch forms."""
+    graphs = mixed_graphs(5, count=24)
+    b = gg.pack_batch(graphs)
+    sizes = np.diff(b.graph_vtx_off)
+    rng = np.random.default_rng(3)
+    order = rng.permutation(len(graphs))
+    off = np.zeros(len(graphs), np.int64)
+    pos = 7
+    for g in order:
+        off[g] = pos
+        pos += int(sizes[g]) + 1 + int(rng.integers(0, 4))
+    with cc.prepare_batch(b) as h:
+        want = oracle_hists(graphs, h.max_n + 1)
+        for per_graph in (False, True):
+            buf = np.full(pos + 5, -123, np.int64)
+            h.histograms_into(buf, off, per_graph_launch=per_graph)
+            touched = np.zeros(buf.size, bool)
+            for g in range(len(graphs)):
+                n_g = int(sizes[g])
+                assert buf[off[g]:off[g] + n_g + 1].tolist() == want[g, :n_g + 1].tolist()
+                touched[off[g]:off[g] + n_g + 1] = True
+            assert (buf[~touched] == -123).all()
