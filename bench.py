@@ -198,7 +198,16 @@ def _batch_device(b):
             torch.tensor(b.col_idx, dtype=torch.int32, device="cuda"))
 
 
-def batched_headline(args):
+def _dfs_diag(info):
+    """What the depth-first kernel's wavefronts did: steps, the share of
+    lanes that held a path, the share of time spent looking for work."""
+    return {"steps": int(info["dfs_steps"]), "lane_use": round(info["dfs_lane_use"], 4),
+            "idle_frac": round(info["dfs_idle_frac"], 4), "donations": int(info["dfs_donations"]),
+            "fills": int(info["dfs_fills"]), "spilled_entries": int(info["dfs_spills"]),
+            "global_hist_adds": int(info["dfs_global_adds"])}
+
+
+def batched_headline(args, baselines=True):
     """The 4096-graph batch: whole passes (prepare + persistent histogram +
     release) on the resident CSR, autotuned launch options, HIP events
     around the depth-first kernel; then the two per-graph baselines.  Every
@@ -251,6 +260,23 @@ def batched_headline(args):
     dfs_ms = float(np.mean([i["dfs_ms"] for i in infos]))
     hist_ms = float(np.mean([i["gpu_ms"] for i in infos]))
 
+    W = 1 if int(sizes.max()) <= 64 else 2
+    bpp = dfs_bytes_per_path(W)
+    achieved = paths * bpp / (dfs_ms * 1e-3) / 1e9
+    dt = elapsed / args.steps
+    roofline = {"bound": "lds", "kernel": f"k_dfs<W={W}, count-only, batch>",
+                "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBPS, 1),
+                "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 4),
+                "traffic": counted_traffic("k_dfs_batch4096.md"),
+                "bytes_per_path": bpp, "paths_per_launch": paths,
+                "avg_launch_us": round(dfs_ms * 1e3, 3),
+                "measured": "HIP events around the depth-first launch on the batch's "
+                            "stream, in every timed step"}
+    roofline["depth_first_diag"] = _dfs_diag(infos[-1])
+    if not baselines:
+        return {"ms_per_step": round(ms_step, 4), "depth_first_ms": round(dfs_ms, 3),
+                "value": round(cycles * args.steps / elapsed, 1), "roofline": roofline}
+
     # baseline A: the same kernels, one launch group per graph, same grid
     buf_a = np.zeros(total, np.int64)
     t0 = time.perf_counter()
@@ -282,10 +308,6 @@ def batched_headline(args):
     dt_b = time.perf_counter() - t0
     check(buf_b, "per-graph calls")
 
-    W = 1 if int(sizes.max()) <= 64 else 2
-    bpp = dfs_bytes_per_path(W)
-    achieved = paths * bpp / (dfs_ms * 1e-3) / 1e9
-    dt = elapsed / args.steps
     base = min(dt_a, dt_b)
     return {
         "ms_per_step": round(ms_step, 4),
@@ -295,14 +317,7 @@ def batched_headline(args):
                    "launch": "persistent (stage one of every graph in one launch, one "
                              "persistent depth-first launch with work stealing)"},
         "paths_per_s": round(paths * args.steps / elapsed, 1),
-        "roofline": {"bound": "lds", "kernel": f"k_dfs<W={W}, count-only, batch>",
-                     "achieved": round(achieved, 1), "peak": round(LDS_PEAK_GBPS, 1),
-                     "unit": "GB/s", "frac": round(achieved / LDS_PEAK_GBPS, 4),
-                     "traffic": counted_traffic("k_dfs_batch4096.md"),
-                     "bytes_per_path": bpp, "paths_per_launch": paths,
-                     "avg_launch_us": round(dfs_ms * 1e3, 3),
-                     "measured": "HIP events around the depth-first launch on the batch's "
-                                 "stream, in every timed step"},
+        "roofline": roofline,
         "batched": {
             "parity": "every timed pass and both baselines equal the stored oracle histograms",
             "persistent": {"ms_per_pass": round(dt * 1e3, 3),
@@ -478,7 +493,7 @@ def grid7x12_section():
                               "GBps": round(lvl_bytes / (lvl * 1e-3) / 1e9, 1) if lvl > 0 else 0.0,
                               "hbm_frac": round(lvl_bytes / (lvl * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
                               if lvl > 0 else 0.0},
-            "depth_first": {"ms": round(info["dfs_ms"], 4),
+            "depth_first": {"ms": round(info["dfs_ms"], 4), **_dfs_diag(info),
                             "paths_per_s": round(
                                 (paths - int(front[:info["switch_level"]].sum()))
                                 / (info["dfs_ms"] * 1e-3), 1) if info["dfs_ms"] > 0 else 0.0},
@@ -668,7 +683,7 @@ def grid8x8_section(args):
             "head_steps": pinfos[-1]["head_steps"]}
 
 
-SECTIONS = ["batched", "grid8x8", "er40", "grid7x12", "paging", "large_n", "table1",
+SECTIONS = ["batched", "batched_persistent", "grid8x8", "er40", "grid7x12", "paging", "large_n", "table1",
             "serving", "cpu"]
 
 
@@ -730,6 +745,7 @@ def main():
         fn = {"er40": er40_section, "grid7x12": grid7x12_section, "paging": paging_section,
               "large_n": large_n_section, "grid8x8": lambda: grid8x8_section(args),
               "table1": lambda: table1_section(args), "batched": lambda: batched_headline(args),
+              "batched_persistent": lambda: batched_headline(args, baselines=False),
               "serving": lambda: serving_section(args)}[args.section]
         print(json.dumps({args.section: fn()}), flush=True)
         return

@@ -112,6 +112,19 @@ typedef struct cc_run_info {
   int32_t reserved;
   double head_ms;            /* CC_PROFILE: device time of those leading steps       */
   int64_t head_bytes;        /* CC_PROFILE: bytes those leading steps must move      */
+  int64_t dfs_steps;         /* depth-first kernel: wavefront steps (up to 64 paths
+                                each) run over the call                              */
+  int64_t dfs_donations;     /* depth-first kernel: chunks of work handed to idle
+                                wavefronts                                           */
+  double dfs_lane_use;       /* depth-first kernel: paths expanded / (64 * steps)    */
+  double dfs_idle_frac;      /* depth-first kernel: share of wavefront time spent
+                                looking for work                                     */
+  int64_t dfs_fills;         /* depth-first kernel: steps whose frames came back from
+                                device memory (the LDS part of the stack was empty)  */
+  int64_t dfs_spills;        /* depth-first kernel: stack entries moved from LDS to
+                                device memory                                        */
+  int64_t dfs_global_adds;   /* depth-first kernel (batches): histogram additions in
+                                device memory                                        */
 } cc_run_info;
 
 /*

@@ -75,7 +75,14 @@ class RunInfo(ctypes.Structure):
                 ("head_steps", ctypes.c_int32),
                 ("reserved", ctypes.c_int32),
                 ("head_ms", ctypes.c_double),
-                ("head_bytes", ctypes.c_int64)]
+                ("head_bytes", ctypes.c_int64),
+                ("dfs_steps", ctypes.c_int64),
+                ("dfs_donations", ctypes.c_int64),
+                ("dfs_lane_use", ctypes.c_double),
+                ("dfs_idle_frac", ctypes.c_double),
+                ("dfs_fills", ctypes.c_int64),
+                ("dfs_spills", ctypes.c_int64),
+                ("dfs_global_adds", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

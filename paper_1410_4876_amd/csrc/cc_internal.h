@@ -88,6 +88,12 @@ struct CcCtl {
   unsigned long long root_cursor;           // depth-first: next unclaimed handed-over path
   unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
   unsigned long long donations;             // chunks given away on request (diagnostic)
+  unsigned long long dfs_lanes;             // depth-first: paths expanded over all steps
+  unsigned long long dfs_idle_clk;          // depth-first: wavefront clocks spent without work
+  unsigned long long dfs_wave_clk;          // depth-first: wavefront clocks from start to exit
+  unsigned long long dfs_fills;             // depth-first: steps that popped from device memory
+  unsigned long long dfs_spills;            // depth-first: ring entries moved to device memory
+  unsigned long long dfs_gatomics;          // depth-first: global histogram atomics
   int levels_run;                           // breadth-first steps run
   int root_buf;                             // frontier buffer of the handed-over paths
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over
@@ -154,27 +160,31 @@ struct OutDev {
   long long vshift = 0;
 };
 
-// Depth-first workspace: per-wavefront stacks, mailboxes and inboxes.
+// Depth-first workspace: per-wavefront stacks, mailboxes and inboxes.  An
+// entry is a frame: the open paths <q, v> for every v in E, sharing the
+// exclusion set X, the first vertex v1 and the length t (and, enumerating,
+// the original ids S of q).
 // Mailbox words of wavefront w (its own 128-byte line):
 //   mail[w * CC_MAIL + 0]  request: 0 none, r + 1 from wavefront r, CC_MAIL_CLOSED
 //   mail[w * CC_MAIL + 1]  response to w's own request: 0 none, 1 work, 2 declined
-//   mail[w * CC_MAIL + 2]  paths delivered into w's inbox
-//   mail[w * CC_MAIL + 3]  paths w could give away (hint for victim choice)
+//   mail[w * CC_MAIL + 2]  frames delivered into w's inbox
+//   mail[w * CC_MAIL + 3]  frames w could give away (hint for victim choice)
 #define CC_MAIL 32
 #define CC_MAIL_CLOSED 0xffffffffu
 struct DfsWork {
   unsigned long long *stackX;   // [nwaves][W][cap_w]
+  unsigned long long *stackE;   // [nwaves][W][cap_w]
   unsigned long long *stackS;   // [nwaves][W][cap_w] (enumerate only)
-  unsigned int *stackM;         // [nwaves][cap_w]: v1 | vt<<8 | t<<16 (9 bits) | root<<31
+  unsigned int *stackM;         // [nwaves][cap_w]: v1 | t<<16 (9 bits) | root<<31
   unsigned int *stackG;         // [nwaves][cap_w] graph id (batches only)
-  unsigned long long cap_w;     // items per wavefront stack
+  unsigned long long cap_w;     // entries per wavefront stack
   unsigned int *mail;           // [nwaves][CC_MAIL]
   unsigned long long *inX;      // [nwaves][W][CC_CHUNK] inbox
+  unsigned long long *inE;      // [nwaves][W][CC_CHUNK]
   unsigned long long *inS;      // [nwaves][W][CC_CHUNK] (enumerate only)
   unsigned int *inM;            // [nwaves][CC_CHUNK]
   unsigned int *inG;            // [nwaves][CC_CHUNK] (batches only)
   int nwaves;
-  int max_children;             // upper bound on extensions of one path
   int donate_check;             // batches between mailbox checks
   int donate_min;               // paths a wavefront must hold before it gives some away
   int claim;                    // handed-over paths per claim; 0 = sized from the frontier
@@ -260,6 +270,10 @@ hipError_t cc_launch_dfs(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier
                          Frontier f1, DfsWork wk, OutDev out,
                          unsigned long long *hist_out, int hist_stride, bool count_front,
                          int blocks, unsigned long long idle_timeout, hipStream_t s);
+// Blocks of the depth-first kernel resident per CU (its LDS ring and rows
+// set this); a persistent grid larger than cus times this would have blocks
+// that start only after others have left.
+int cc_dfs_blocks_per_cu(int W, bool en, bool batch);
 // Batched depth-first run over the root slots bt.r0 .. bt.r1 (workspace wk).
 hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt,
                                int blocks, unsigned long long idle_timeout, hipStream_t s);

@@ -141,11 +141,6 @@ __device__ __forceinline__ unsigned int lanes_below(unsigned long long mask) {
                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-__device__ __forceinline__ unsigned int wave_sum_u32(unsigned int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, CC_WAVE);
-  return v;
-}
 // Sum over a fully active wavefront by data-parallel moves, the same
 // pattern as wave_min_u32 below (butterflies within rows, then row
 // broadcasts), returned to every lane from lane 63.
@@ -180,9 +175,6 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
   return (unsigned)__builtin_amdgcn_readlane((int)v, CC_WAVE - 1);
 }
 
-__device__ __forceinline__ unsigned long long bcast_u64(unsigned long long v) {
-  return __shfl(v, 0, CC_WAVE);
-}
 // A value every lane of the wavefront holds, moved to scalar registers.
 __device__ __forceinline__ unsigned uni_u32(unsigned v) {
   return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
@@ -1885,45 +1877,91 @@ __global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, Lev
 }
 
 // ---------------------------------------------------------- depth-first
-// Depth-first continuation (beyond the memory budget, or on request).  Each
-// wavefront owns a LIFO stack of open paths in device memory; a step pops up
-// to 64 paths (one per lane), expands them exactly like a breadth-first level
-// and pushes the extensions back, so memory grows with depth, not with the
-// frontier.  Work enters from the handed-over frontier, which wavefronts
-// claim in private ranges (one atomic per range) and consume 64 at a time
-// whenever their stack is empty.
+// Depth-first continuation (beyond the memory budget, on request, and for
+// batches of small graphs).  The unit of work is a frame: the open paths
+// <p, v> that share a prefix p, for every v in a set E of end vertices not
+// expanded yet.  A frame holds their common exclusion set X, E, v1 and their
+// length t (and, enumerating, the original ids S of p).  Expanding one of
+// its paths takes the lowest v of E: the candidates N(v) \ X split into
+// closures (adjacent to v1: chordless cycles of t + 1 vertices) and
+// extensions, which form one new frame (X | N(v), the extensions, t + 1);
+// the rest of E stays a frame of its own.  So every path costs the same
+// constant work: one frame popped, at most two pushed.
+//
+// Each wavefront owns a LIFO stack of frames in two levels: its newest
+// entries sit in a ring of C entries in LDS, older ones in device memory
+// below them.  A step pops up to 64 frames (one per lane), expands one path
+// of each and pushes the new frames back onto the LDS top, remainders below
+// children, so the search goes depth first.  When the ring would overflow,
+// its oldest entries move to device memory in whole-wavefront chunks; when
+// it is empty, the next 64 frames come back from device memory.  Memory
+// grows with depth, not with the frontier, and most steps touch LDS only.
+// Work enters from the handed-over frontier (each path <q, vt> becomes the
+// frame of q with E = {vt}), which wavefronts claim in private ranges (one
+// atomic per range) and consume 64 at a time whenever their stack is empty.
 //
 // Load balance is by work requests through per-wavefront mailboxes (each
 // wavefront polls only its own cache line, so no address is shared by the
-// polling): an idle wavefront reads the published "paths I could give" hints
-// of 64 others, asks the richest, and waits on its own line; a busy
-// wavefront looks at its mailbox every few batches and either ships up to
-// 64 paths (the end of its private range, else the oldest, shallowest stack
+// polling): an idle wavefront reads the published "frames I could give"
+// hints of 64 others, asks the richest, and waits on its own line; a busy
+// wavefront looks at its mailbox every few steps and either ships up to 64
+// frames (the end of its private range, else the oldest, shallowest stack
 // entries) into the requester's inbox or declines.  Payloads move with
 // coherent single accesses and are published after an s_waitcnt, never with
 // cache-wide fences.
 //
-// Termination: `busy` counts wavefronts that hold paths, including paths in
+// Termination: `busy` counts wavefronts that hold work, including work in
 // transit (the donor counts the recipient before answering), so busy == 0
 // with the handed-over frontier exhausted means no work is left anywhere.
 // Cycle counts go to hist_out[(block % CC_SHARDS) * hist_stride + k].
 //
-// BATCH: many graphs at once.  Every path carries its graph id; adjacency
-// rows come from device memory (the graphs' rows stay cache-resident);
-// closures go straight to the per-graph histograms (one atomic per distinct
-// (graph, length) in a wavefront batch); the handed-over paths are the
-// batch's initial triplets in bt.r0..bt.r1, padding slots marked
-// CC_NO_GRAPH.  The mailboxes and stacks come from wk1.
+// BATCH: many graphs at once.  Every frame carries its graph id; each
+// wavefront keeps in LDS the adjacency rows of the graph its last
+// single-graph step came from (one coalesced reload when a step's frames
+// all belong to another graph; a step that mixes graphs reads its rows from
+// device memory); closures go straight to the per-graph histograms (one
+// atomic per distinct (graph, length) in a step); the handed-over paths are
+// the batch's initial triplets in bt.r0..bt.r1, padding slots marked
+// CC_NO_GRAPH.
+//
+// LDS per wavefront: the ring (X and E words, S words when enumerating, the
+// v1|t|root word, the graph id in batches) and, in batches, one graph's
+// rows.  The ring holds 256 entries when an entry has at most 24 bytes,
+// else 128; a step pushes at most 128.
+template <int W, bool ENUM, bool BATCH>
+struct DfsWaveLds {
+  static constexpr int kEntry = 16 * W + (ENUM ? 8 * W : 0) + 4 + (BATCH ? 4 : 0);
+  static constexpr unsigned kC = kEntry <= 24 ? 256u : 128u;
+  unsigned long long X[W * kC];
+  unsigned long long E[W * kC];
+  unsigned long long S[ENUM ? W * kC : 1];
+  unsigned int M[kC];
+  unsigned int G[BATCH ? kC : 1];
+  unsigned long long rows[BATCH ? CC_ROWS(W) * W : 1];
+  unsigned int hc[BATCH ? CC_BATCH_MAXN + 2 : 1];  // that graph's histogram, this
+                                                   // wavefront's share not yet added
+};
+
+// A frame in registers (one per lane).
+template <int W>
+struct Frame {
+  Bits<W> X, E, S;
+  unsigned int m, gid;
+};
+
 template <int W, bool ENUM, bool BATCH>
 __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Frontier f0,
                                                   Frontier f1, DfsWork wk,
                                                   OutDev out, unsigned long long *hist_out,
                                                   int hist_stride, int count_front,
                                                   unsigned long long idle_timeout, BatchDev bt) {
+  using WL = DfsWaveLds<W, ENUM, BATCH>;
+  constexpr unsigned C = WL::kC;
+  __shared__ WL sW[CC_BLOCK / CC_WAVE];
   __shared__ unsigned long long sN[BATCH ? 1 : CC_ROWS(W) * W];
   __shared__ unsigned long long sNo[ENUM ? CC_ROWS(W) * W : 1];
   __shared__ int sPerm[BATCH ? 1 : CC_ROWS(W)];
-  __shared__ unsigned long long sHist[CC_HSLOTS];
+  __shared__ unsigned long long sHist[BATCH ? 1 : CC_HSLOTS];
   __shared__ unsigned long long sFront[CC_HSLOTS];
   __shared__ long long sCb[ENUM ? CC_HSLOTS : 1];
   __shared__ long long sVb[ENUM ? CC_HSLOTS : 1];
@@ -1935,6 +1973,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   const int n = g.n;
   const int tid = threadIdx.x;
   const int lane = lane_id();
+  // the wavefront's index in the block, as a scalar (uniform) value: the
+  // stack bookkeeping below then stays in scalar registers
+  const int wib = __builtin_amdgcn_readfirstlane(tid / CC_WAVE);
+  WL &Q = sW[wib];
   if (!BATCH && tid < CC_WAVE) {
     const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][L]);
     shard_prefix(c <= roots.cap_s ? c : roots.cap_s, sPre);
@@ -1942,11 +1984,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   if (!BATCH) {
     for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
     for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
+    for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) sHist[i] = 0ull;
   }
-  for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
-    sHist[i] = 0ull;
-    sFront[i] = 0ull;
-  }
+  for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) sFront[i] = 0ull;
   if (ENUM) {
     for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
     for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
@@ -1957,15 +1997,17 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   __syncthreads();
   const unsigned long long nroots = BATCH ? bt.r1 - bt.r0 : sPre[CC_SHARDS];
 
-  const int wid = blockIdx.x * (CC_BLOCK / CC_WAVE) + tid / CC_WAVE;
+  const int wid = blockIdx.x * (CC_BLOCK / CC_WAVE) + wib;
   const int nwaves = gridDim.x * (CC_BLOCK / CC_WAVE);
-  const unsigned long long cap = wk.cap_w;
+  // device-memory stack of this wavefront: entries [bot, top) of cap (at
+  // most 2^20, so 32-bit indices)
+  const unsigned cap = (unsigned)wk.cap_w;
   unsigned long long *stX = wk.stackX + (unsigned long long)wid * W * cap;
+  unsigned long long *stE = wk.stackE + (unsigned long long)wid * W * cap;
   unsigned long long *stS = ENUM ? wk.stackS + (unsigned long long)wid * W * cap : nullptr;
   unsigned int *stM = wk.stackM + (unsigned long long)wid * cap;
   unsigned int *stG = BATCH ? wk.stackG + (unsigned long long)wid * cap : nullptr;
   unsigned int *my_mail = wk.mail + (size_t)wid * CC_MAIL;
-  const unsigned long long maxc = (unsigned long long)max(wk.max_children, 1);
   const unsigned long long dmin = (unsigned long long)max(wk.donate_min, 2);
   const unsigned int root_meta = ((unsigned)L << 16) | (1u << 31);
   // Claim size: up to CC_ROOT_CLAIM paths, but small enough that every
@@ -1975,365 +2017,569 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
                    : max((unsigned long long)CC_CHUNK,
                          min((unsigned long long)CC_ROOT_CLAIM,
                              nroots / ((unsigned long long)nwaves * 4) / CC_CHUNK * CC_CHUNK));
+  const int check_every = max(wk.donate_check, 1);
 
-  unsigned long long bot = 0, top = 0;     // live stack entries [bot, top)
+  unsigned lb = 0, lt = 0;                 // LDS ring entries [lb, lt), positions mod C
+  unsigned bot = 0, top = 0;               // device-memory entries, below the ring
   unsigned long long r_lo = 0, r_hi = 0;   // private range of handed-over paths
-  unsigned long long steps = 0, batches = 0, donated = 0;
+  unsigned long long batches = 0, donated = 0;
+  unsigned long long lanes_used = 0, idle_clk = 0, fills = 0, spills = 0, gatomics = 0;
   unsigned long long rng = 0x9E3779B97F4A7C15ull * (unsigned long long)(wid + 1);
+  int until_check = 1 + wid % check_every;
+  int cur_g = -1, cur_vo = 0, cur_n = 0;   // BATCH: the graph whose rows are in Q.rows
   bool roots_done = false;
+  const unsigned long long clk_start = wall_clock64();
+  if (BATCH)
+    for (int k = lane; k < CC_BATCH_MAXN + 2; k += CC_WAVE) Q.hc[k] = 0u;
   if (lane == 0) atomicAdd(&ctl->busy, 1);
 
-  while (true) {
-    Bits<W> X = bzero<W>(), S = bzero<W>();
-    unsigned int m = 0, gid = 0;
-    bool valid = false;
-    bool have = false;
-    if (top > bot) {
-      // Pop up to 64 paths from the top, keeping room for their extensions.
-      unsigned long long kk = min(top - bot, (unsigned long long)CC_CHUNK);
-      while (kk > 1 && (top - kk) + kk * maxc > cap) kk >>= 1;
-      const unsigned long long start = top - kk;
-      valid = (unsigned long long)lane < kk;
-      if (valid) {
-        const unsigned long long i = start + lane;
+  auto ring_get = [&](unsigned i, Frame<W> &f) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) X.w[w] = stX[w * cap + i];
-        if (ENUM) {
-#pragma unroll
-          for (int w = 0; w < W; ++w) S.w[w] = stS[w * cap + i];
-        }
-        m = stM[i];
-        if (BATCH) gid = stG[i];
-      }
-      top = start;
-      if (top == bot) top = bot = 0;
-      have = true;
-    } else {
-      if (r_lo >= r_hi && !roots_done) {
-        unsigned long long c = ~0ull;
-        if (lane == 0 && ld_relaxed(&ctl->root_cursor) < nroots)
-          c = atomicAdd(&ctl->root_cursor, claim);
-        c = bcast_u64(c);
-        if (c < nroots) {
-          r_lo = c;
-          r_hi = min(c + claim, nroots);
-        } else {
-          roots_done = true;
-        }
-      }
-      if (r_lo < r_hi) {
-        const unsigned long long kk = min(r_hi - r_lo, (unsigned long long)CC_CHUNK);
-        valid = (unsigned long long)lane < kk;
-        if (valid) {
-          const unsigned long long i = r_lo + lane;
-          if (BATCH) {
-            const unsigned long long e = bt.r0 + i;
-            gid = bt.rgid[e];
-            valid = gid != CC_NO_GRAPH;
-            if (valid) {
-#pragma unroll
-              for (int w = 0; w < W; ++w) X.w[w] = bt.rX[w * bt.rcap + e];
-              m = (unsigned)bt.rvv[e] | root_meta;
-            } else {
-              gid = 0;
-            }
-          } else {
-            const int s = shard_of(sPre, i);
-            const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
-#pragma unroll
-            for (int w = 0; w < W; ++w) X.w[w] = roots.X[w * roots.cap + e];
-            if (ENUM) {
-#pragma unroll
-              for (int w = 0; w < W; ++w) S.w[w] = roots.S[w * roots.cap + e];
-            }
-            m = (unsigned)roots.vv[e] | root_meta;
-          }
-        }
-        r_lo += kk;
-        have = true;
-      }
+    for (int w = 0; w < W; ++w) {
+      f.X.w[w] = Q.X[w * C + i];
+      f.E.w[w] = Q.E[w * C + i];
     }
-    if (!have) {
-      // ---- idle: ask a busy wavefront for work, or leave when none is left
-      if (lane == 0) {
-        st_coh(&my_mail[3], 0u);
-        atomicSub(&ctl->busy, 1);
+    if (ENUM) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) f.S.w[w] = Q.S[w * C + i];
+    }
+    f.m = Q.M[i];
+    if (BATCH) f.gid = Q.G[i];
+  };
+  auto ring_put = [&](unsigned i, const Frame<W> &f) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      Q.X[w * C + i] = f.X.w[w];
+      Q.E[w * C + i] = f.E.w[w];
+    }
+    if (ENUM) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) Q.S[w * C + i] = f.S.w[w];
+    }
+    Q.M[i] = f.m;
+    if (BATCH) Q.G[i] = f.gid;
+  };
+  auto dev_get = [&](unsigned d, Frame<W> &f) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      f.X.w[w] = stX[(size_t)w * cap + d];
+      f.E.w[w] = stE[(size_t)w * cap + d];
+    }
+    if (ENUM) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) f.S.w[w] = stS[(size_t)w * cap + d];
+    }
+    f.m = stM[d];
+    if (BATCH) f.gid = stG[d];
+  };
+  auto dev_put = [&](unsigned d, const Frame<W> &f) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      stX[(size_t)w * cap + d] = f.X.w[w];
+      stE[(size_t)w * cap + d] = f.E.w[w];
+    }
+    if (ENUM) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) stS[(size_t)w * cap + d] = f.S.w[w];
+    }
+    stM[d] = f.m;
+    if (BATCH) stG[d] = f.gid;
+  };
+  auto zero_frame = [&](Frame<W> &f) {
+    f.X = bzero<W>();
+    f.E = bzero<W>();
+    f.S = bzero<W>();
+    f.m = 0;
+    f.gid = 0;
+  };
+
+  // BATCH: adds the wavefront's counts for graph cur_g to its histogram in
+  // device memory and clears them.
+  auto flush_hc = [&]() {
+    if (BATCH && cur_g >= 0) {
+      wave_lds_sync();
+      for (int k = lane; k < cur_n + 2; k += CC_WAVE) {
+        const unsigned h = Q.hc[k];
+        if (h) {
+          atomicAdd(&bt.hist[(size_t)cur_g * bt.hist_stride + k], (unsigned long long)h);
+          Q.hc[k] = 0u;
+        }
       }
-      int victim = -1;                 // wavefront our pending request went to
-      unsigned long long t_req = 0;
-      int outcome = 0;                 // 1: work delivered, 2: leave, 3: roots left, 4: gave up
-      const unsigned long long t0 = wall_clock64();
-      int backoff = 1;
-      while (true) {
-        int o = 0;
-        if (lane == 0) {
-          // decline whatever is asked of us while we have nothing
-          const unsigned r = ld_coh(&my_mail[0]);
-          if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r) {
-            if (r - 1u < (unsigned)nwaves) st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
-            else dfs_corrupt(ctl, CC_DIAG_REQUESTER, r);
-          }
-          if (victim >= 0) {
-            const unsigned resp = ld_coh(&my_mail[1]);
-            if (resp == 1u) {
-              o = 1;
-            } else if (resp == 2u) {
-              st_coh(&my_mail[1], 0u);
-              victim = -1;
-            } else if (wall_clock64() - t_req > 20000ull || ld_coh(&ctl->busy) == 0) {
-              // withdraw; if the victim already took the request, keep waiting
-              if (atomicCAS(&wk.mail[(size_t)victim * CC_MAIL], (unsigned)wid + 1u, 0u) ==
-                  (unsigned)wid + 1u)
-                victim = -1;
-            }
-            // a taken request is always answered; if the answer never comes,
-            // give up after the idle timeout and report the run incomplete
-            if (o == 0 && victim >= 0 && wall_clock64() - t0 > idle_timeout) o = 5;
-          }
-          if (o == 0 && victim < 0) {
-            if (!roots_done && ld_coh(&ctl->root_cursor) < nroots) o = 3;
-            else if (ld_coh(&ctl->busy) == 0) o = 2;
-            else if (wall_clock64() - t0 > idle_timeout) o = 4;
+      wave_lds_sync();
+    }
+  };
+
+  // The frame of a handed-over path <q, vt> (a root): q's exclusion set and
+  // ids, E = {vt}.  False for a padding slot of a batch.
+  auto root_frame = [&](unsigned long long i, Frame<W> &f) -> bool {
+    if (BATCH) {
+      const unsigned long long e = bt.r0 + i;
+      const unsigned gg = bt.rgid[e];
+      if (gg == CC_NO_GRAPH) return false;
+      const unsigned vv = bt.rvv[e];
+#pragma unroll
+      for (int w = 0; w < W; ++w) f.X.w[w] = bt.rX[w * bt.rcap + e];
+      f.E = bsingle<W>((int)(vv >> 8));
+      f.m = (vv & 0xffu) | root_meta;
+      f.gid = gg;
+    } else {
+      const int s = shard_of(sPre, i);
+      const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
+      const unsigned vv = roots.vv[e];
+      const int vt = (int)(vv >> 8);
+#pragma unroll
+      for (int w = 0; w < W; ++w) f.X.w[w] = roots.X[w * roots.cap + e];
+      f.E = bsingle<W>(vt);
+      if (ENUM) {
+        Bits<W> s0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) s0.w[w] = roots.S[w * roots.cap + e];
+        f.S = bandnot(s0, bsingle<W>(sPerm[vt < n ? vt : 0]));
+      }
+      f.m = (vv & 0xffu) | root_meta;
+      f.gid = 0;
+    }
+    return true;
+  };
+
+  while (true) {
+    // The stack bookkeeping is the same in every lane: pinned to scalar
+    // registers, so the compiler branches on it without exec masks.
+    lt = uni_u32(lt);
+    lb = uni_u32(lb);
+    top = uni_u32(top);
+    bot = uni_u32(bot);
+    r_lo = uni_u64(r_lo);
+    r_hi = uni_u64(r_hi);
+    until_check = (int)uni_u32((unsigned)until_check);
+    if (BATCH) {
+      cur_g = (int)uni_u32((unsigned)cur_g);
+      cur_vo = (int)uni_u32((unsigned)cur_vo);
+      cur_n = (int)uni_u32((unsigned)cur_n);
+    }
+    if (lt == lb) {
+      // ---- the ring is empty: refill it from device memory, else from
+      // the handed-over paths, else from another wavefront
+      lb = lt = 0;
+      if (top != bot) {
+        // the newest entries of device memory, oldest first
+        ++fills;
+        const unsigned m = min(top - bot, C / 2u);
+        for (unsigned c0 = 0; c0 < m; c0 += CC_CHUNK) {
+          const unsigned j = c0 + (unsigned)lane;
+          if (j < m) {
+            Frame<W> f;
+            zero_frame(f);
+            dev_get(top - m + j, f);
+            ring_put(j, f);
           }
         }
-        o = __shfl(o, 0, CC_WAVE);
-        victim = __shfl(victim, 0, CC_WAVE);
-        if (o != 0) {
-          outcome = o;
+        lt = m;
+        top -= m;
+        if (top == bot) top = bot = 0;
+      } else if (!roots_done || r_lo < r_hi) {
+        if (r_lo >= r_hi) {
+          unsigned long long c = ~0ull;
+          if (lane == 0 && ld_relaxed(&ctl->root_cursor) < nroots)
+            c = atomicAdd(&ctl->root_cursor, claim);
+          c = lane_u64(c, 0);
+          if (c < nroots) {
+            r_lo = c;
+            r_hi = min(c + claim, nroots);
+          } else {
+            roots_done = true;
+          }
+        }
+        if (r_lo < r_hi) {
+          const unsigned long long kk = min(r_hi - r_lo, (unsigned long long)CC_CHUNK);
+          Frame<W> f;
+          zero_frame(f);
+          bool ok = false;
+          if ((unsigned long long)lane < kk) ok = root_frame(r_lo + lane, f);
+          const unsigned long long mk = wave_ballot(ok);
+          if (ok) ring_put(lanes_below(mk), f);
+          lt = (unsigned)__popcll(mk);
+          r_lo += kk;
+        }
+      } else {
+        // ---- idle: ask a busy wavefront for work, or leave when none is left
+        if (lane == 0) {
+          st_coh(&my_mail[3], 0u);
+          atomicSub(&ctl->busy, 1);
+        }
+        int victim = -1;                 // wavefront our pending request went to
+        unsigned long long t_req = 0;
+        int outcome = 0;                 // 1: work delivered, 2: leave, 3: roots left, 4: gave up
+        const unsigned long long t0 = wall_clock64();
+        int backoff = 1;
+        while (true) {
+          int o = 0;
+          if (lane == 0) {
+            // decline whatever is asked of us while we have nothing
+            const unsigned r = ld_coh(&my_mail[0]);
+            if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r) {
+              if (r - 1u < (unsigned)nwaves) st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
+              else dfs_corrupt(ctl, CC_DIAG_REQUESTER, r);
+            }
+            if (victim >= 0) {
+              const unsigned resp = ld_coh(&my_mail[1]);
+              if (resp == 1u) {
+                o = 1;
+              } else if (resp == 2u) {
+                st_coh(&my_mail[1], 0u);
+                victim = -1;
+              } else if (wall_clock64() - t_req > 20000ull || ld_coh(&ctl->busy) == 0) {
+                // withdraw; if the victim already took the request, keep waiting
+                if (atomicCAS(&wk.mail[(size_t)victim * CC_MAIL], (unsigned)wid + 1u, 0u) ==
+                    (unsigned)wid + 1u)
+                  victim = -1;
+              }
+              // a taken request is always answered; if the answer never comes,
+              // give up after the idle timeout and report the run incomplete
+              if (o == 0 && victim >= 0 && wall_clock64() - t0 > idle_timeout) o = 5;
+            }
+            if (o == 0 && victim < 0) {
+              if (!roots_done && ld_coh(&ctl->root_cursor) < nroots) o = 3;
+              else if (ld_coh(&ctl->busy) == 0) o = 2;
+              else if (wall_clock64() - t0 > idle_timeout) o = 4;
+            }
+          }
+          // lane 0's decisions, as wavefront-uniform (scalar) values
+          o = __builtin_amdgcn_readfirstlane(o);
+          victim = __builtin_amdgcn_readfirstlane(victim);
+          if (o != 0) {
+            outcome = o;
+            break;
+          }
+          if (victim < 0) {
+            // pick the richest of 64 candidates by their published hints
+            rng ^= rng << 13;
+            rng ^= rng >> 7;
+            rng ^= rng << 17;
+            const int cand = (int)(((rng >> 16) + (unsigned long long)lane * 40503ull) %
+                                   (unsigned long long)nwaves);
+            unsigned hint = cand == wid ? 0u : ld_coh(&wk.mail[(size_t)cand * CC_MAIL + 3]);
+            if (hint < dmin) hint = 0u;
+            unsigned long long key = ((unsigned long long)hint << 32) | (unsigned)cand;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+              const unsigned long long other = __shfl_xor(key, off, CC_WAVE);
+              key = other > key ? other : key;
+            }
+            key = lane_u64(key, 0);  // every lane holds the maximum
+            if ((key >> 32) != 0ull) {
+              const int v = (int)(key & 0xffffffffull);
+              int ok = 0;
+              if (lane == 0)
+                ok = atomicCAS(&wk.mail[(size_t)v * CC_MAIL], 0u, (unsigned)wid + 1u) == 0u;
+              ok = __builtin_amdgcn_readfirstlane(ok);
+              if (ok) {
+                victim = v;
+                t_req = wall_clock64();
+                backoff = 1;
+                continue;
+              }
+            }
+          }
+          for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(16);
+          backoff = min(backoff * 2, 32);
+        }
+        idle_clk += wall_clock64() - t0;
+        if (outcome == 3) {
+          if (lane == 0) atomicAdd(&ctl->busy, 1);
+          continue;
+        }
+        if (outcome != 1) {
+          if (outcome == 4 && lane == 0) atomicOr(&ctl->status, CC_DEV_IDLE_TIMEOUT);
+          if (outcome == 5 && lane == 0) atomicOr(&ctl->status, CC_DEV_LOST);
           break;
         }
-        if (victim < 0) {
-          // pick the richest of 64 candidates by their published hints
-          rng ^= rng << 13;
-          rng ^= rng >> 7;
-          rng ^= rng << 17;
-          const int cand = (int)(((rng >> 16) + (unsigned long long)lane * 40503ull) %
-                                 (unsigned long long)nwaves);
-          unsigned hint = cand == wid ? 0u : ld_coh(&wk.mail[(size_t)cand * CC_MAIL + 3]);
-          if (hint < dmin) hint = 0u;
-          unsigned long long key = ((unsigned long long)hint << 32) | (unsigned)cand;
+        // Work arrived in our inbox (the donor already counted us busy).  The
+        // acquire pairs with the donor's release of the response word, so the
+        // count and the paths below are the ones it wrote.
+        acquire_agent();
+        unsigned kk = 0;
+        if (lane == 0) kk = ld_coh(&my_mail[2]);
+        kk = (unsigned)__builtin_amdgcn_readlane((int)kk, 0);
+        if (kk > (unsigned)CC_CHUNK) {
+          if (lane == 0) dfs_corrupt(ctl, CC_DIAG_INBOX_COUNT, kk);
+          kk = 0;
+        }
+        Frame<W> f;
+        zero_frame(f);
+        bool ok = (unsigned)lane < kk;
+        if (ok) {
+          const size_t ib = (size_t)wid * W * CC_CHUNK;
 #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long other = __shfl_xor(key, off, CC_WAVE);
-            key = other > key ? other : key;
+          for (int w = 0; w < W; ++w) {
+            f.X.w[w] = ld_coh(&wk.inX[ib + w * CC_CHUNK + lane]);
+            f.E.w[w] = ld_coh(&wk.inE[ib + w * CC_CHUNK + lane]);
           }
-          if ((key >> 32) != 0ull) {
-            const int v = (int)(key & 0xffffffffull);
-            int ok = 0;
-            if (lane == 0)
-              ok = atomicCAS(&wk.mail[(size_t)v * CC_MAIL], 0u, (unsigned)wid + 1u) == 0u;
-            ok = __shfl(ok, 0, CC_WAVE);
-            if (ok) {
-              victim = v;
-              t_req = wall_clock64();
-              backoff = 1;
-              continue;
+          if (ENUM) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) f.S.w[w] = ld_coh(&wk.inS[ib + w * CC_CHUNK + lane]);
+          }
+          f.m = ld_coh(&wk.inM[(size_t)wid * CC_CHUNK + lane]);
+          if (BATCH) {
+            f.gid = ld_coh(&wk.inG[(size_t)wid * CC_CHUNK + lane]);
+            ok = f.gid != CC_NO_GRAPH;  // a padding slot of the initial triplets
+          }
+        }
+        wait_mem();
+        if (lane == 0) st_coh(&my_mail[1], 0u);
+        const unsigned long long mk = wave_ballot(ok);
+        if (ok) ring_put(lanes_below(mk), f);
+        lt = (unsigned)__popcll(mk);
+      }
+    }
+    // ---- expand from the ring until it empties or a mailbox check is due
+    while (lt != lb && until_check > 0) {
+      --until_check;
+      ++batches;
+      // Pop up to 64 frames from the top.  In the worst case every entry
+      // left in the ring and both new frames of every popped one end up in
+      // device memory: keep that within its capacity.
+      unsigned kk = min(lt - lb, (unsigned)CC_CHUNK);
+      while (kk > 1 && (top - bot) + (lt - lb) + kk > cap) kk >>= 1;
+      const unsigned start = lt - kk;
+      bool valid = (unsigned)lane < kk;
+      Frame<W> f;
+      zero_frame(f);
+      if (valid) ring_get((start + (unsigned)lane) & (C - 1u), f);
+      lt = start;
+      lanes_used += kk;
+      // Consistency checks: every index below that comes from a frame
+      // stays inside its graph; a frame that fails is reported and dropped.
+      int n_path = n;  // vertices of this frame's graph
+      int vo = 0;
+      bool ring_rows = !BATCH;  // rows from LDS (sN, or the wavefront's cached graph)
+      if (BATCH) {
+        if (valid && f.gid >= (unsigned)bt.n_graphs) {
+          dfs_corrupt(ctl, CC_DIAG_GRAPH, f.gid);
+          valid = false;
+        }
+        if (!valid) f.gid = 0;
+        const unsigned long long vm = wave_ballot(valid);
+        if (vm) {
+          const unsigned g0 = (unsigned)__builtin_amdgcn_readlane(
+              (int)f.gid, (int)(__ffsll((long long)vm) - 1));
+          if (wave_ballot(valid && f.gid != g0) == 0ull) {
+            // every frame of the step belongs to graph g0: rows from LDS
+            if ((int)g0 != cur_g) {
+              flush_hc();
+              cur_vo = bt.vtx_off[g0];
+              cur_n = min(bt.vtx_off[g0 + 1] - cur_vo, CC_ROWS(W));
+              if (cur_n < 0) cur_n = 0;
+              for (int i = lane; i < cur_n * W; i += CC_WAVE)
+                Q.rows[i] = bt.adj[(size_t)cur_vo * W + i];
+              cur_g = (int)g0;
+            }
+            ring_rows = true;
+            vo = cur_vo;
+            n_path = cur_n;
+          } else {
+            vo = bt.vtx_off[f.gid];
+            n_path = bt.vtx_off[f.gid + 1] - vo;
+          }
+        }
+      }
+      // the path to expand: <q, v> for the lowest v of E
+      int v = 0;
+      if (valid) {
+        if (!bany(f.E)) {
+          dfs_corrupt(ctl, CC_DIAG_PATH, f.m);
+          valid = false;
+        } else {
+          v = bpop_lowest(f.E);
+          const int pv1 = f.m & 0xffu, pt = (f.m >> 16) & 0x1ffu;
+          if (pv1 >= n_path || v >= n_path || pt < 3 || pt > n_path) {
+            dfs_corrupt(ctl, CC_DIAG_PATH, (f.m & 0xffff00ffu) | ((unsigned)v << 8));
+            valid = false;
+          }
+        }
+      }
+      if (!valid) {
+        f.m = 0;
+        f.E = bzero<W>();
+        v = 0;
+      }
+      const int v1 = f.m & 0xffu;
+      const int t = (f.m >> 16) & 0x1ffu;
+      const bool root = (f.m >> 31) != 0;
+      const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
+      const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
+      Bits<W> nvt, nv1;
+      if (BATCH && !ring_rows) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          nvt.w[w] = bt.adj[(size_t)(vo + v) * W + w];
+          nv1.w[w] = bt.adj[(size_t)(vo + v1) * W + w];
+        }
+      } else {
+        nvt = row<W>(BATCH ? Q.rows : sN, v);
+        nv1 = row<W>(BATCH ? Q.rows : sN, v1);
+      }
+      const Bits<W> cand = bandnot(nvt, f.X);
+      Bits<W> clos = band(cand, nv1);
+      Bits<W> ext = bandnot(cand, nv1);
+      if (!valid) {
+        clos = bzero<W>();
+        ext = bzero<W>();
+      }
+      if (count_front) {
+        // paths expanded, per length: one LDS add per distinct length
+        unsigned long long act = wave_ballot(count_path);
+        while (act) {
+          const int t0 = __builtin_amdgcn_readlane(t, (int)(__ffsll((long long)act) - 1));
+          const unsigned long long same = act & wave_ballot(t == t0);
+          if (lane == 0) atomicAdd(&sFront[t0], (unsigned long long)__popcll(same));
+          act &= ~same;
+        }
+      }
+      // the expanded path's own original ids (enumerate)
+      const Bits<W> Sp = ENUM ? bor(f.S, bsingle<W>(sPerm[v])) : bzero<W>();
+      if (BATCH && ring_rows) {
+        // every frame is of graph cur_g: one add per distinct length to the
+        // wavefront's LDS share of that graph's histogram
+        const unsigned c = count_close ? (unsigned)bpop(clos) : 0u;
+        unsigned long long act = wave_ballot(c != 0u);
+        while (act) {
+          const int t0 = __builtin_amdgcn_readlane(t, (int)(__ffsll((long long)act) - 1));
+          const unsigned long long same = act & wave_ballot(t == t0);
+          const unsigned sum = wave_sum_u32_full((same >> lane) & 1ull ? c : 0u);
+          if (lane == 0) {
+            // 32-bit shares: one that would pass 2^31 goes to device memory
+            const unsigned long long nv = (unsigned long long)Q.hc[t0 + 1] + sum;
+            if (nv >= (1ull << 31)) {
+              atomicAdd(&bt.hist[(size_t)cur_g * bt.hist_stride + t0 + 1], nv);
+              Q.hc[t0 + 1] = 0u;
+            } else {
+              Q.hc[t0 + 1] = (unsigned)nv;
             }
           }
+          act &= ~same;
         }
-        for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(16);
-        backoff = min(backoff * 2, 32);
-      }
-      if (outcome == 3) {
-        if (lane == 0) atomicAdd(&ctl->busy, 1);
-        continue;
-      }
-      if (outcome != 1) {
-        if (outcome == 4 && lane == 0) atomicOr(&ctl->status, CC_DEV_IDLE_TIMEOUT);
-        if (outcome == 5 && lane == 0) atomicOr(&ctl->status, CC_DEV_LOST);
-        break;
-      }
-      // Work arrived in our inbox (the donor already counted us busy).  The
-      // acquire pairs with the donor's release of the response word, so the
-      // count and the paths below are the ones it wrote.
-      acquire_agent();
-      unsigned kk = 0;
-      if (lane == 0) kk = ld_coh(&my_mail[2]);
-      kk = __shfl(kk, 0, CC_WAVE);
-      if (kk > (unsigned)CC_CHUNK) {
-        if (lane == 0) dfs_corrupt(ctl, CC_DIAG_INBOX_COUNT, kk);
-        kk = 0;
-      }
-      valid = (unsigned)lane < kk;
-      if (valid) {
-        const size_t ib = (size_t)wid * W * CC_CHUNK;
-#pragma unroll
-        for (int w = 0; w < W; ++w) X.w[w] = ld_coh(&wk.inX[ib + w * CC_CHUNK + lane]);
-        if (ENUM) {
-#pragma unroll
-          for (int w = 0; w < W; ++w) S.w[w] = ld_coh(&wk.inS[ib + w * CC_CHUNK + lane]);
+      } else if (BATCH) {
+        // frames of several graphs: one global add per distinct (graph,
+        // length) among the lanes
+        const unsigned c = count_close ? (unsigned)bpop(clos) : 0u;
+        const unsigned key = (f.gid << 8) | (unsigned)(t + 1);
+        unsigned long long act = wave_ballot(c != 0u);
+        while (act) {
+          const unsigned k0 =
+              (unsigned)__builtin_amdgcn_readlane((int)key, (int)(__ffsll((long long)act) - 1));
+          const unsigned long long same = act & wave_ballot(key == k0);
+          const unsigned sum = wave_sum_u32_full((same >> lane) & 1ull ? c : 0u);
+          if (lane == 0)
+            atomicAdd(&bt.hist[(size_t)(k0 >> 8) * bt.hist_stride + (k0 & 0xffu)],
+                      (unsigned long long)sum);
+          ++gatomics;
+          act &= ~same;
         }
-        m = ld_coh(&wk.inM[(size_t)wid * CC_CHUNK + lane]);
-        if (BATCH) {
-          gid = ld_coh(&wk.inG[(size_t)wid * CC_CHUNK + lane]);
-          if (gid == CC_NO_GRAPH) {  // a padding slot of the initial triplets
-            valid = false;
-            gid = 0;
-          }
-        }
-      }
-      wait_mem();
-      if (lane == 0) st_coh(&my_mail[1], 0u);
-      have = true;
-    }
-
-    // ---- expand the batch (one path per lane)
-    ++batches;
-    // Consistency checks: every index below that comes from a path stays
-    // inside its graph; a path that fails is reported and dropped.
-    int n_path = n;  // vertices of this path's graph
-    int vo = 0;
-    if (BATCH) {
-      if (valid && gid >= (unsigned)bt.n_graphs) {
-        dfs_corrupt(ctl, CC_DIAG_GRAPH, gid);
-        valid = false;
-      }
-      if (!valid) gid = 0;
-      vo = bt.vtx_off[gid];
-      n_path = bt.vtx_off[gid + 1] - vo;
-    }
-    if (valid) {
-      const int pv1 = m & 0xffu, pvt = (m >> 8) & 0xffu, pt = (m >> 16) & 0x1ffu;
-      if (pv1 >= n_path || pvt >= n_path || pt < 3 || pt > n_path) {
-        dfs_corrupt(ctl, CC_DIAG_PATH, m);
-        valid = false;
-      }
-    }
-    if (!valid) m = 0;
-    const int v1 = m & 0xffu;
-    const int vt = (m >> 8) & 0xffu;
-    const int t = (m >> 16) & 0x1ffu;
-    const bool root = (m >> 31) != 0;
-    const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
-    const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
-    Bits<W> nvt, nv1;
-    if (BATCH) {
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        nvt.w[w] = bt.adj[(size_t)(vo + vt) * W + w];
-        nv1.w[w] = bt.adj[(size_t)(vo + v1) * W + w];
-      }
-    } else {
-      nvt = row<W>(sN, vt);
-      nv1 = row<W>(sN, v1);
-    }
-    const Bits<W> cand = bandnot(nvt, X);
-    Bits<W> clos = band(cand, nv1);
-    Bits<W> ext = bandnot(cand, nv1);
-    if (!valid) {
-      clos = bzero<W>();
-      ext = bzero<W>();
-    }
-    if (count_front) {
-      // paths expanded, per length: one LDS add per distinct length
-      unsigned long long act = wave_ballot(count_path);
-      while (act) {
-        const int t0 = __shfl(t, (int)(__ffsll((long long)act) - 1), CC_WAVE);
-        const unsigned long long same = act & wave_ballot(t == t0);
-        if (lane == 0) atomicAdd(&sFront[t0], (unsigned long long)__popcll(same));
-        act &= ~same;
-      }
-    }
-    if (BATCH) {
-      // one global add per distinct (graph, length) among the lanes
-      const unsigned c = count_close ? (unsigned)bpop(clos) : 0u;
-      const unsigned long long key = ((unsigned long long)gid << 8) | (unsigned)(t + 1);
-      unsigned long long act = wave_ballot(c != 0u);
-      while (act) {
-        const unsigned long long k0 = __shfl(key, (int)(__ffsll((long long)act) - 1), CC_WAVE);
-        const unsigned long long same = act & wave_ballot(key == k0);
-        const unsigned sum = wave_sum_u32((same >> lane) & 1ull ? c : 0u);
-        if (lane == 0)
-          atomicAdd(&bt.hist[(size_t)(k0 >> 8) * bt.hist_stride + (k0 & 0xffull)],
-                    (unsigned long long)sum);
-        act &= ~same;
-      }
-    } else if (count_close) {
-      const int c = bpop(clos);
-      if (c) {
-        if (hist_out) atomicAdd(&sHist[t + 1], (unsigned long long)c);
-        if (ENUM) {
-          const int k = t + 1;
-          if (k >= out.kmin && k <= out.kmax) {
-            const unsigned long long slot0 =
-                atomicAdd(&ctl->len_cursor[k], (unsigned long long)c);
-            Bits<W> cl = clos;
-            for (int j = 0; j < c; ++j) {
-              const int v = bpop_lowest(cl);
-              long long cyc = sCb[k] + (long long)(slot0 + j);
-              long long pos = sVb[k] + (long long)(slot0 + j) * k;
-              if (out_slot(out, k, cyc, pos)) {
-                write_cycle<W>(sNo, bor(S, bsingle<W>(sPerm[v])), k, out.verts + pos);
-                out.offs[cyc] = pos;
+      } else if (count_close) {
+        const int c = bpop(clos);
+        if (c) {
+          if (hist_out) atomicAdd(&sHist[t + 1], (unsigned long long)c);
+          if (ENUM) {
+            const int k = t + 1;
+            if (k >= out.kmin && k <= out.kmax) {
+              const unsigned long long slot0 =
+                  atomicAdd(&ctl->len_cursor[k], (unsigned long long)c);
+              Bits<W> cl = clos;
+              for (int j = 0; j < c; ++j) {
+                const int w = bpop_lowest(cl);
+                long long cyc = sCb[k] + (long long)(slot0 + j);
+                long long pos = sVb[k] + (long long)(slot0 + j) * k;
+                if (out_slot(out, k, cyc, pos)) {
+                  write_cycle<W>(sNo, bor(Sp, bsingle<W>(sPerm[w])), k, out.verts + pos);
+                  out.offs[cyc] = pos;
+                }
               }
             }
           }
         }
       }
-    }
-    // A path never has more than n vertices (each extension adds a vertex
-    // outside S, and S is inside X); anything longer would mean corrupted
-    // state, so it is dropped and reported instead of looping.
-    if (t >= n_path && bany(ext)) {
-      atomicOr(&ctl->status, CC_DEV_STACK_FULL);
-      ext = bzero<W>();
-    }
-    const unsigned tot = wave_sum_u32((unsigned)bpop(ext));
-    if (tot) {
-      if (top + tot > cap && bot > 0) {
-        // Slide the live part of the stack down to index 0, 64 entries at a
-        // time: a chunk's loads all complete before its stores, and later
-        // chunks only read above what earlier chunks wrote.
-        const unsigned long long live = top - bot;
-        for (unsigned long long c0 = 0; c0 < live; c0 += CC_CHUNK) {
-          const unsigned long long i = c0 + lane;
-          if (i < live) {
-#pragma unroll
-            for (int w = 0; w < W; ++w) stX[w * cap + i] = stX[w * cap + bot + i];
-            if (ENUM) {
-#pragma unroll
-              for (int w = 0; w < W; ++w) stS[w * cap + i] = stS[w * cap + bot + i];
-            }
-            stM[i] = stM[bot + i];
-            if (BATCH) stG[i] = stG[bot + i];
-          }
-        }
-        top = live;
-        bot = 0;
+      // A path never has more than n vertices (each extension adds a vertex
+      // outside the path, and the path is inside X); anything longer would
+      // mean corrupted state, so it is dropped and reported instead of
+      // looping.
+      if (t >= n_path && bany(ext)) {
+        atomicOr(&ctl->status, CC_DEV_STACK_FULL);
+        ext = bzero<W>();
       }
-      if (top + tot > cap) {
-        if (lane == 0) atomicOr(&ctl->status, CC_DEV_STACK_FULL);
-      } else {
-        const Bits<W> Xn = bor(X, nvt);
-        const unsigned int mbase = (unsigned)v1 | ((unsigned)(t + 1) << 16);
-        unsigned long long off = 0;
-        while (true) {
-          const bool has = bany(ext);
-          const unsigned long long mask = wave_ballot(has);
-          if (!mask) break;
-          if (has) {
-            const int v = bpop_lowest(ext);
-            const unsigned long long i = top + off + lanes_below(mask);
-#pragma unroll
-            for (int w = 0; w < W; ++w) stX[w * cap + i] = Xn.w[w];
-            if (ENUM) {
-              const Bits<W> Sn = bor(S, bsingle<W>(sPerm[v]));
-#pragma unroll
-              for (int w = 0; w < W; ++w) stS[w * cap + i] = Sn.w[w];
+      // ---- push: what is left of E, then the new frame of the extensions
+      // on top of it (at most 128 entries, so the ring always takes them
+      // once its oldest entries have moved out)
+      const bool push_rem = valid && bany(f.E);
+      const bool push_ext = valid && bany(ext);
+      const unsigned long long m_rem = wave_ballot(push_rem);
+      const unsigned long long m_ext = wave_ballot(push_ext);
+      const unsigned n_rem = (unsigned)__popcll(m_rem);
+      const unsigned tot = n_rem + (unsigned)__popcll(m_ext);
+      if (tot) {
+        const unsigned used = lt - lb;
+        if (used + tot > C) {
+          // Move the ring's oldest entries to device memory, whole
+          // wavefront chunks at a time.
+          const unsigned spill =
+              min(used, (used + tot - C + (unsigned)CC_CHUNK - 1u) / CC_CHUNK * CC_CHUNK);
+          if (top + spill > cap && bot > 0) {
+            // Slide the device-memory part down to index 0, 64 entries at
+            // a time: a chunk's loads all complete before its stores, and
+            // later chunks only read above what earlier chunks wrote.
+            const unsigned live = top - bot;
+            for (unsigned c0 = 0; c0 < live; c0 += CC_CHUNK) {
+              const unsigned i = c0 + (unsigned)lane;
+              if (i < live) {
+                Frame<W> d;
+                zero_frame(d);
+                dev_get(bot + i, d);
+                dev_put(i, d);
+              }
             }
-            stM[i] = mbase | ((unsigned)v << 8);
-            if (BATCH) stG[i] = gid;
+            top = live;
+            bot = 0;
           }
-          off += __popcll(mask);
+          if (top + spill > cap) {
+            // cannot happen with the pop size above; reported, not looped on
+            if (lane == 0) atomicOr(&ctl->status, CC_DEV_STACK_FULL);
+            lb += spill;
+          } else {
+            for (unsigned c0 = 0; c0 < spill; c0 += CC_CHUNK) {
+              const unsigned j = c0 + (unsigned)lane;
+              if (j < spill) {
+                Frame<W> d;
+                zero_frame(d);
+                ring_get((lb + j) & (C - 1u), d);
+                dev_put(top + j, d);
+              }
+            }
+            top += spill;
+            lb += spill;
+            spills += spill;
+          }
+          wave_lds_sync();  // the ring slots just read may be written below
         }
-        top += tot;
+        if (push_rem) ring_put((lt + lanes_below(m_rem)) & (C - 1u), f);
+        if (push_ext) {
+          Frame<W> e;
+#pragma unroll
+          for (int w = 0; w < W; ++w) e.X.w[w] = f.X.w[w] | nvt.w[w];
+          e.E = ext;
+          e.S = Sp;
+          e.m = (unsigned)v1 | ((unsigned)(t + 1) << 16);
+          e.gid = f.gid;
+          ring_put((lt + n_rem + lanes_below(m_ext)) & (C - 1u), e);
+        }
+        lt += tot;
       }
     }
 
-    // ---- every few batches: publish what we could give, answer a request
-    ++steps;
-    if (((steps + (unsigned long long)wid) % (unsigned long long)wk.donate_check) == 0) {
-      const unsigned long long range_left = r_hi - r_lo, stack_left = top - bot;
+    // ---- every few steps: publish what we could give, answer a request
+    if (until_check <= 0) {
+      until_check = check_every;
+      const unsigned long long range_left = r_hi - r_lo, dev_left = top - bot;
+      const unsigned long long stack_left = dev_left + (unsigned long long)(lt - lb);
       const unsigned long long left = range_left + stack_left;
       unsigned req = 0;
       if (lane == 0) {
@@ -2341,7 +2587,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         const unsigned r = ld_coh(&my_mail[0]);
         if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r) req = r;
       }
-      req = __shfl(req, 0, CC_WAVE);
+      req = (unsigned)__builtin_amdgcn_readlane((int)req, 0);
       if (req != 0u && req - 1u >= (unsigned)nwaves) {
         if (lane == 0) dfs_corrupt(ctl, CC_DIAG_REQUESTER, req);
         req = 0u;
@@ -2351,63 +2597,43 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         unsigned int *q_mail = wk.mail + (size_t)q * CC_MAIL;
         const bool from_range = range_left >= dmin;
         if (from_range || stack_left >= dmin) {
-          const unsigned long long give =
-              min((from_range ? range_left : stack_left) / 2, (unsigned long long)CC_CHUNK);
-          const bool mine = (unsigned long long)lane < give;
-          Bits<W> dX = bzero<W>(), dS = bzero<W>();
-          unsigned int dm = 0, dg = 0;
+          const unsigned give = (unsigned)min(
+              (from_range ? range_left : stack_left) / 2, (unsigned long long)CC_CHUNK);
+          const bool mine = (unsigned)lane < give;
+          // the oldest stack entries: device memory first; when it holds
+          // fewer than `give`, the ring holds at least that many
+          const bool from_dev = dev_left >= give;
+          Frame<W> d;
+          zero_frame(d);
           if (from_range) {
-            if (mine) {
-              const unsigned long long i = r_hi - give + lane;
-              if (BATCH) {
-                // padding slots travel as paths with no extension
-                const unsigned long long e = bt.r0 + i;
-                dg = bt.rgid[e];
-#pragma unroll
-                for (int w = 0; w < W; ++w) dX.w[w] = bt.rX[w * bt.rcap + e];
-                dm = (unsigned)bt.rvv[e] | root_meta;
-              } else {
-                const int s = shard_of(sPre, i);
-                const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
-#pragma unroll
-                for (int w = 0; w < W; ++w) dX.w[w] = roots.X[w * roots.cap + e];
-                if (ENUM) {
-#pragma unroll
-                  for (int w = 0; w < W; ++w) dS.w[w] = roots.S[w * roots.cap + e];
-                }
-                dm = (unsigned)roots.vv[e] | root_meta;
-              }
-            }
+            // padding slots travel as frames the recipient drops
+            if (mine && !root_frame(r_hi - give + lane, d)) d.gid = CC_NO_GRAPH;
             r_hi -= give;
-          } else {
-            if (mine) {
-              const unsigned long long i = bot + lane;
-#pragma unroll
-              for (int w = 0; w < W; ++w) dX.w[w] = stX[w * cap + i];
-              if (ENUM) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) dS.w[w] = stS[w * cap + i];
-              }
-              dm = stM[i];
-              if (BATCH) dg = stG[i];
-            }
+          } else if (from_dev) {
+            if (mine) dev_get(bot + (unsigned)lane, d);
             bot += give;
             if (top == bot) top = bot = 0;
+          } else {
+            if (mine) ring_get((lb + (unsigned)lane) & (C - 1u), d);
+            lb += give;
           }
           if (mine) {
             const size_t ib = (size_t)q * W * CC_CHUNK;
 #pragma unroll
-            for (int w = 0; w < W; ++w) st_coh(&wk.inX[ib + w * CC_CHUNK + lane], dX.w[w]);
+            for (int w = 0; w < W; ++w) {
+              st_coh(&wk.inX[ib + w * CC_CHUNK + lane], d.X.w[w]);
+              st_coh(&wk.inE[ib + w * CC_CHUNK + lane], d.E.w[w]);
+            }
             if (ENUM) {
 #pragma unroll
-              for (int w = 0; w < W; ++w) st_coh(&wk.inS[ib + w * CC_CHUNK + lane], dS.w[w]);
+              for (int w = 0; w < W; ++w) st_coh(&wk.inS[ib + w * CC_CHUNK + lane], d.S.w[w]);
             }
-            st_coh(&wk.inM[(size_t)q * CC_CHUNK + lane], dm);
-            if (BATCH) st_coh(&wk.inG[(size_t)q * CC_CHUNK + lane], dg);
+            st_coh(&wk.inM[(size_t)q * CC_CHUNK + lane], d.m);
+            if (BATCH) st_coh(&wk.inG[(size_t)q * CC_CHUNK + lane], d.gid);
           }
           if (lane == 0) {
-            st_coh(&q_mail[2], (unsigned)give);
-            atomicAdd(&ctl->busy, 1);  // the recipient holds paths from now on
+            st_coh(&q_mail[2], give);
+            atomicAdd(&ctl->busy, 1);  // the recipient holds work from now on
           }
           // every lane's inbox stores are visible before lane 0 publishes them
           release_agent();
@@ -2420,6 +2646,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     }
   }
 
+  flush_hc();
   // Close the mailbox; decline a request that arrived meanwhile.
   if (lane == 0) {
     const unsigned r = atomicExch(&my_mail[0], CC_MAIL_CLOSED);
@@ -2429,15 +2656,22 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     }
     atomicAdd(&ctl->dfs_batches, batches);
     if (donated) atomicAdd(&ctl->donations, donated);
+    atomicAdd(&ctl->dfs_lanes, lanes_used);
+    atomicAdd(&ctl->dfs_idle_clk, idle_clk);
+    atomicAdd(&ctl->dfs_wave_clk, wall_clock64() - clk_start);
+    atomicAdd(&ctl->dfs_fills, fills);
+    atomicAdd(&ctl->dfs_spills, spills);
+    atomicAdd(&ctl->dfs_gatomics, gatomics);
   }
   __syncthreads();
   unsigned long long *hdst = hist_out ? hist_out + (size_t)(blockIdx.x % CC_SHARDS) * hist_stride
                                       : nullptr;
   for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
-    if (hdst && sHist[i]) atomicAdd(&hdst[i], sHist[i]);
+    if (!BATCH && hdst && sHist[i]) atomicAdd(&hdst[i], sHist[i]);
     if (count_front && sFront[i]) atomicAdd(&ctl->front[i], sFront[i]);
   }
 }
+
 
 // Resets the depth-first coordination state: every mailbox of the
 // workspace, the claim cursor and the busy count, unconditionally (the
@@ -2578,6 +2812,13 @@ hipError_t launch_dfs(bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
   return hipGetLastError();
 }
 template <int W>
+hipError_t dfs_occupancy(bool en, bool batch, int *per_cu) {
+  const void *fn = batch ? (const void *)k_dfs<W <= 2 ? W : 2, false, true>
+                         : en ? (const void *)k_dfs<W, true, false>
+                              : (const void *)k_dfs<W, false, false>;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, CC_BLOCK, 0);
+}
+template <int W>
 hipError_t launch_dfs_batch(GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,
                             unsigned long long idle_timeout, hipStream_t s) {
   if (W > 2) return hipErrorInvalidValue;
@@ -2695,6 +2936,22 @@ hipError_t cc_launch_dfs(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Fr
                          unsigned long long idle_timeout, hipStream_t s) {
   return CC_BY_W(W, launch_dfs, en, g, ctl, f0, f1, wk, out, hist_out, hist_stride,
                  count_front ? 1 : 0, blocks, idle_timeout, s);
+}
+
+int cc_dfs_blocks_per_cu(int W, bool en, bool batch) {
+  // asked once per instantiation (one architecture per process here)
+  static std::atomic<int> cached[9];
+  const int which = (W == 1 ? 0 : W == 2 ? 3 : 6) + (batch ? 2 : en ? 1 : 0);
+  int v = cached[which].load();
+  if (v <= 0) {
+    int per_cu = 0;
+    if ((batch && W > 2) || CC_BY_W(W, dfs_occupancy, en, batch, &per_cu) != hipSuccess ||
+        per_cu <= 0)
+      return 1;
+    cached[which].store(per_cu);
+    v = per_cu;
+  }
+  return v;
 }
 
 hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,

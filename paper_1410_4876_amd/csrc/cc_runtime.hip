@@ -195,11 +195,13 @@ size_t frontier_bytes(unsigned long long cap_s, int W, bool en) {
 // Carves the depth-first workspace (per-wavefront stacks, mailboxes and
 // inboxes) out of a region of `bytes`.  Returns the number of wavefronts
 // that fit (<= waves, a multiple of 4), 0 if not even 4 fit.
-int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_children,
-              DfsWork *wk, bool batch = false) {
+int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, DfsWork *wk,
+              bool batch = false) {
   DfsWork d{};
-  const size_t item = (size_t)W * 8 * (en ? 2 : 1) + 4 + (batch ? 4 : 0);
-  const unsigned long long min_cap = (unsigned long long)CC_CHUNK * (max_children + 2);
+  const size_t item = (size_t)W * 8 * (en ? 3 : 2) + 4 + (batch ? 4 : 0);
+  // a step pushes at most two frames per lane, after a full LDS ring (at
+  // most 256 entries) has moved out below them
+  const unsigned long long min_cap = 4 * CC_CHUNK + 256;
   auto need = [&](int nw, unsigned long long cap_w) {
     return (size_t)nw * (CC_MAIL * 4 + CC_CHUNK * item + cap_w * item) + 16 * 256;
   };
@@ -210,36 +212,39 @@ int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, int max_child
   cap_w = std::min<unsigned long long>(cap_w, 1ull << 20) & ~63ull;
   if (cap_w < min_cap) return 0;
   size_t off = 0;
-  d.mail = (unsigned int *)(base + off);
-  off = align_up(off + (size_t)nw * CC_MAIL * 4, 256);
-  d.inX = (unsigned long long *)(base + off);
-  off = align_up(off + (size_t)nw * W * CC_CHUNK * 8, 256);
-  if (en) {
-    d.inS = (unsigned long long *)(base + off);
-    off = align_up(off + (size_t)nw * W * CC_CHUNK * 8, 256);
-  }
-  d.inM = (unsigned int *)(base + off);
-  off = align_up(off + (size_t)nw * CC_CHUNK * 4, 256);
-  if (batch) {
-    d.inG = (unsigned int *)(base + off);
-    off = align_up(off + (size_t)nw * CC_CHUNK * 4, 256);
-  }
+  auto take = [&](size_t b) {
+    char *q = base + off;
+    off = align_up(off + b, 256);
+    return q;
+  };
+  d.mail = (unsigned int *)take((size_t)nw * CC_MAIL * 4);
+  d.inX = (unsigned long long *)take((size_t)nw * W * CC_CHUNK * 8);
+  d.inE = (unsigned long long *)take((size_t)nw * W * CC_CHUNK * 8);
+  if (en) d.inS = (unsigned long long *)take((size_t)nw * W * CC_CHUNK * 8);
+  d.inM = (unsigned int *)take((size_t)nw * CC_CHUNK * 4);
+  if (batch) d.inG = (unsigned int *)take((size_t)nw * CC_CHUNK * 4);
   d.cap_w = cap_w;
-  d.stackX = (unsigned long long *)(base + off);
-  off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
-  if (en) {
-    d.stackS = (unsigned long long *)(base + off);
-    off = align_up(off + (size_t)nw * W * cap_w * 8, 256);
-  }
-  d.stackM = (unsigned int *)(base + off);
-  off = align_up(off + (size_t)nw * cap_w * 4, 256);
-  if (batch) d.stackG = (unsigned int *)(base + off);
+  d.stackX = (unsigned long long *)take((size_t)nw * W * cap_w * 8);
+  d.stackE = (unsigned long long *)take((size_t)nw * W * cap_w * 8);
+  if (en) d.stackS = (unsigned long long *)take((size_t)nw * W * cap_w * 8);
+  d.stackM = (unsigned int *)take((size_t)nw * cap_w * 4);
+  if (batch) d.stackG = (unsigned int *)take((size_t)nw * cap_w * 4);
   d.nwaves = nw;
-  d.max_children = max_children;
   d.donate_check = 16;
   d.donate_min = 2 * CC_CHUNK;
   *wk = d;
   return nw;
+}
+
+// Depth-first diagnostics of a run from the control block's tail.
+void dfs_stats(const CcCtl &h, cc_run_info *info) {
+  info->dfs_steps = (int64_t)h.dfs_batches;
+  info->dfs_donations = (int64_t)h.donations;
+  info->dfs_lane_use = h.dfs_batches ? (double)h.dfs_lanes / (64.0 * (double)h.dfs_batches) : 0.0;
+  info->dfs_idle_frac = h.dfs_wave_clk ? (double)h.dfs_idle_clk / (double)h.dfs_wave_clk : 0.0;
+  info->dfs_fills = (int64_t)h.dfs_fills;
+  info->dfs_spills = (int64_t)h.dfs_spills;
+  info->dfs_global_adds = (int64_t)h.dfs_gatomics;
 }
 
 struct RunOut {
@@ -311,12 +316,17 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   const int maxc = std::max(1, g->max_deg - 1);
   int waves_per_cu = g->opt.dfs_waves_per_cu > 0 ? g->opt.dfs_waves_per_cu : 24;
   waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
-  const int want_waves = std::max(4, (g->dev.cus * waves_per_cu) / 4 * 4);
+  // at most what is resident at once, so every wavefront of the persistent
+  // grid runs from the start
+  auto want_waves = [&](bool enum_pass) {
+    const int wpc = std::min(waves_per_cu, 4 * cc_dfs_blocks_per_cu(W, enum_pass, false));
+    return std::max(4, (g->dev.cus * wpc) / 4 * 4);
+  };
   // the counting pass (wc) and, in enumerate mode, the writing pass (we)
   // use the same region one after the other
   DfsWork wc{}, we{};
-  const int nw_c = carve_dfs(dfs_region, dfs_bytes, W, false, want_waves, maxc, &wc);
-  const int nw_e = en ? carve_dfs(dfs_region, dfs_bytes, W, true, want_waves, maxc, &we) : 4;
+  const int nw_c = carve_dfs(dfs_region, dfs_bytes, W, false, want_waves(false), &wc);
+  const int nw_e = en ? carve_dfs(dfs_region, dfs_bytes, W, true, want_waves(true), &we) : 4;
   if (nw_c < 4 || nw_e < 4) {
     (void)hipFreeAsync(arena, s);
     return CC_ERR_OUT_OF_MEMORY;
@@ -539,6 +549,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   }
   g->have_run = true;
   g->info.device_diag = (int64_t)h.diag;
+  dfs_stats(h, &g->info);
   cc_status st = CC_OK;
   if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST | CC_DEV_BARRIER_TIMEOUT))
     st = CC_ERR_INTERNAL;
@@ -1114,9 +1125,9 @@ cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hi
   const int W = b->W;
   const int dstride = b->max_n + 2;
   const unsigned long long rcap = std::max<long long>(b->root_off[G], 1);
-  const int maxc = std::max(1, b->max_deg - 1);
   int waves_per_cu = b->opt.dfs_waves_per_cu > 0 ? b->opt.dfs_waves_per_cu : 24;
   waves_per_cu = std::min(std::max(waves_per_cu, 4), 32);
+  waves_per_cu = std::min(waves_per_cu, 4 * cc_dfs_blocks_per_cu(W, false, true));
   const bool per_graph = mode == CC_BATCH_PER_GRAPH;
   // both forms launch the depth-first kernel on the same full grid
   const int want_waves = std::max(4, (b->dev.cus * waves_per_cu) / 4 * 4);
@@ -1143,7 +1154,7 @@ cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hi
   bt.hist_stride = dstride;
   bt.n_graphs = G;
   DfsWork wk{};
-  const int nw = carve_dfs(arena + roots_b + hist_b, stack_b, W, false, want_waves, maxc, &wk, true);
+  const int nw = carve_dfs(arena + roots_b + hist_b, stack_b, W, false, want_waves, &wk, true);
   if (nw < 4) {
     (void)hipFreeAsync(arena, s);
     return CC_ERR_OUT_OF_MEMORY;
@@ -1227,6 +1238,7 @@ cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hi
     b->info.dfs_ms = c;
   }
   b->info.device_diag = (int64_t)b->h_ctl->diag;
+  dfs_stats(*b->h_ctl, &b->info);
   if (b->h_ctl->status & (CC_DEV_CORRUPT | CC_DEV_LOST)) return CC_ERR_INTERNAL;
   if (b->h_ctl->status & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
   return CC_OK;
@@ -1422,13 +1434,11 @@ hipError_t slot_launch(cc_server *sv, ServeSlot &sl, const std::vector<ServeReq 
     sl.h_root_off[g + 1] = roots;
   }
   const int W = max_n <= 64 ? 1 : 2;
-  const int waves = std::max(4, sv->dev.cus * std::max(4, sv->opt.dfs_waves_per_cu) /
-                                    std::max(1, (int)sv->slots.size()) / 4 * 4);
+  const int wpc = std::min(std::max(4, sv->opt.dfs_waves_per_cu),
+                           4 * cc_dfs_blocks_per_cu(W, false, true));
+  const int waves = std::max(4, sv->dev.cus * wpc / std::max(1, (int)sv->slots.size()) / 4 * 4);
   DfsWork wk{};
-  // a path has at most max_deg - 1 extensions (its end vertex keeps one
-  // neighbour on the path)
-  const int maxc = std::max(1, std::min(max_deg, CC_MAXN) - 1);
-  const int nw = carve_dfs(sl.d_work, sl.work_bytes, W, false, waves, maxc, &wk, true);
+  const int nw = carve_dfs(sl.d_work, sl.work_bytes, W, false, waves, &wk, true);
   if (nw < 4) return hipErrorOutOfMemory;
   hipStream_t s = sl.stream;
   hipError_t err = hipSuccess;
