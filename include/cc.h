@@ -208,6 +208,29 @@ cc_status cc_last_run(cc_graph *g, cc_run_info *info);
 /* cc_release -- free a handle and its device memory (NULL is ignored). */
 void cc_release(cc_graph *g);
 
+/*
+ * cc_histogram_noalloc -- cc_prepare + cc_histogram + cc_release in one call
+ * that allocates nothing, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Every buffer beyond the caller's inputs and output lives in one fixed
+ * device array inside the library (64 MiB per GPU, held from the library's
+ * load until the process ends; 24 MiB of it for the breadth-first
+ * frontiers, the rest for the depth-first stacks).
+ *   n        number of vertices, 0 <= n <= CC_MAX_VERTICES
+ *   row_ptr, col_idx  the graph as int32 CSR in DEVICE memory (as
+ *            cc_prepare with CC_INPUT_DEVICE)
+ *   hist     DEVICE array of hist_len >= n+1 int64: hist[k] = chordless
+ *            cycles with k vertices (as cc_histogram), zeros past n
+ *   stream   hipStream_t the work is ordered on (NULL: the null stream); the
+ *            call returns after its results are complete
+ * Errors: INVALID_ARG, TOO_LARGE (n > CC_MAX_VERTICES), NOT_SIMPLE,
+ * OUT_OF_MEMORY (the graph's initial triplets, or its depth-first stacks,
+ * need more than the fixed array holds), INTERNAL, DEVICE, NO_DEVICE.
+ * Calls that overlap on one GPU share its array and race: serialise them.
+ */
+cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                               int64_t *hist, int32_t hist_len, void *stream);
+
 /* ------------------------------------------------------------- batches
  * Many small graphs enumerated together (count-only).  The graphs are packed
  * as one CSR: graph g owns vertices graph_vtx_off[g] .. graph_vtx_off[g+1]

@@ -1268,6 +1268,153 @@ cc_status cc_batch_labels(cc_batch *b, int32_t *labels) {
 }  // extern "C"
 
 
+// ---------------------------------------------------- no-allocation variant
+// cc_histogram_noalloc: the count-only run of cc_prepare + cc_histogram for
+// callers that cannot allocate.  Every buffer the kernels need beyond the
+// caller's inputs and output (control block, bitsets, labels, the two
+// frontier buffers, the depth-first stacks and mailboxes) is carved from
+// `scratch`, a file-scope device array of kScratchBytes that each GPU holds
+// from module load until the process ends.  In host code the array's name
+// is only a stand-in: its device address comes from hipGetSymbolAddress,
+// once per device, and only that address is handed to kernels and copies.
+// No call here allocates: no hipMalloc/hipFree, no pinned host memory (the
+// host learns the ingest's answer and the run's status by small copies into
+// its own stack and a stream synchronisation), no library routine that
+// allocates.  Every call on a device uses that device's one array, so calls
+// that overlap on one device race; each call re-zeroes what must start at
+// zero (the control block, the depth-first mailboxes).
+namespace {
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr size_t kScratchFrontier = 24ull << 20;  // both frontier buffers together
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+
+// The device address of `scratch` on device dev (dev current).
+cc_status scratch_address(int dev, char **out) {
+  if (dev < 0 || dev >= 64) return CC_ERR_NO_DEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CC_ERR_DEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char *)g_scratch_ptr[dev];
+  return CC_OK;
+}
+
+}  // namespace
+
+extern "C" cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr,
+                                          const int32_t *col_idx, int64_t *hist,
+                                          int32_t hist_len, void *stream) {
+  if (n < 0 || !hist || hist_len < n + 1 || (n > 0 && (!row_ptr || !col_idx)))
+    return CC_ERR_INVALID_ARG;
+  if (n > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CC_ERR_NO_DEVICE;
+  DeviceInfo di;
+  cc_status st = device_info(dev, &di);
+  if (st != CC_OK) return st;
+  char *base = nullptr;
+  st = scratch_address(dev, &base);
+  if (st != CC_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int W = n <= 64 ? 1 : n <= 128 ? 2 : 4;
+  // fixed part of the scratch: control block, bitsets, labels, ingest answer
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char *q = base + off;
+    off = align_up(off + b, 256);
+    return q;
+  };
+  CcCtl *ctl = (CcCtl *)take(sizeof(CcCtl));
+  unsigned long long *adj = (unsigned long long *)take((size_t)CC_MAXN * 4 * 8);
+  unsigned long long *adj_orig = (unsigned long long *)take((size_t)CC_MAXN * 4 * 8);
+  int *perm = (int *)take((size_t)CC_MAXN * 4);
+  int *label = (int *)take((size_t)CC_MAXN * 4);
+  unsigned int *status = (unsigned int *)take(256);
+  long long *pairs = (long long *)((char *)status + 8);
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (x != hipSuccess && e == hipSuccess) e = x;
+  };
+  // ingest: validation, labelling, bitsets; its answer (status word, then
+  // the sum over vertices of C(deg, 2)) comes back by a copy
+  unsigned long long answer[2] = {0ull, 0ull};
+  if (n > 0) {
+    chk(cc_launch_ingest(W, 1, nullptr, n, row_ptr, col_idx, adj, adj_orig, perm, label, status,
+                         pairs, nullptr, s));
+    chk(hipMemcpyAsync(answer, status, sizeof(answer), hipMemcpyDeviceToHost, s));
+    chk(hipStreamSynchronize(s));
+    if (e != hipSuccess) return hip_err(e);
+    const unsigned stv = (unsigned)answer[0];
+    if ((stv & 0xffu) != 0u || !(stv & 0x100u)) return CC_ERR_NOT_SIMPLE;
+  }
+  if (n < 3) {
+    chk(cc_launch_zero(hist, (size_t)hist_len * 8, s));
+    chk(hipStreamSynchronize(s));
+    return hip_err(e);
+  }
+  const int max_deg = (int)((unsigned)answer[0] >> 16);
+  const int64_t npairs = (int64_t)answer[1];
+  // the frontier buffers: every initial triplet (at most sum C(deg, 2))
+  // must fit, dealt round-robin over the shards
+  const size_t per_unit = 2 * ((size_t)W * 8 + 2);
+  const unsigned long long min_cap_s =
+      (unsigned long long)std::min<int64_t>(npairs, choose3(n)) / CC_SHARDS + CC_CHUNK;
+  const unsigned long long cap_s =
+      ((unsigned long long)(kScratchFrontier / per_unit / CC_SHARDS)) & ~63ull;
+  if (cap_s < min_cap_s) return CC_ERR_OUT_OF_MEMORY;  // more initial triplets than the scratch holds
+  const size_t buf_bytes = align_up(frontier_bytes(cap_s, W, false), 256);
+  LevelBufs lb{};
+  lb.f[0] = carve_frontier(take(buf_bytes), cap_s, W, false);
+  lb.f[1] = carve_frontier(take(buf_bytes), cap_s, W, false);
+  if (off >= kScratchBytes) return CC_ERR_OUT_OF_MEMORY;
+  // the rest: the depth-first workspace
+  DfsWork wk{};
+  const int wpc = std::min(24, 4 * cc_dfs_blocks_per_cu(W, false, false));
+  const int nw = carve_dfs(base + off, kScratchBytes - off, W, false,
+                           std::max(4, di.cus * wpc / 4 * 4), &wk);
+  if (nw < 4) return CC_ERR_OUT_OF_MEMORY;
+  const unsigned long long idle_timeout =
+      (unsigned long long)(kIdleTimeoutSeconds * (double)di.clock_hz);
+  GraphDev gd{adj, adj_orig, perm, n};
+  const OutDev out{};
+  const int maxc = std::max(1, max_deg - 1);
+  const int bfs_blocks = di.cus * std::min(cc_step_blocks_per_cu(W, false), kStepBlocksPerCu);
+  const size_t stat = cc_head_static_lds(W, false) + 4096;
+  const size_t head_lds = di.lds_block > stat ? di.lds_block - stat : 0;
+  // the head zeroes the control block, runs stage one and the leading
+  // levels; every later step launch returns at once after the loop is over
+  // (the host has no mapped word to stop early, so it queues all n - 2)
+  chk(cc_launch_head(W, false, gd, ctl, lb, out, -1, head_lds, nullptr, true, s));
+  for (int launch = 1; launch < n - 1 && e == hipSuccess; ++launch)
+    chk(cc_launch_step(W, false, gd, ctl, lb, out, launch, -1, maxc, true, bfs_blocks, nullptr,
+                       s));
+  // the depth-first continuation returns at once if nothing was handed over
+  chk(cc_launch_dfs_prepare(ctl, wk, n, false, s));
+  chk(cc_launch_dfs(W, false, gd, ctl, lb.f[0], lb.f[1], wk, out,
+                    dev_field(ctl, offsetof(CcCtl, hist_sh)), CC_HSLOTS, true, nw / 4,
+                    idle_timeout, s));
+  chk(cc_launch_finalize(ctl, out, n, false, s));
+  // the histogram (n + 1 entries) into the caller's array, zeros after it
+  chk(hipMemcpyAsync(hist, ctl->hist, (size_t)(n + 1) * 8, hipMemcpyDeviceToDevice, s));
+  if (hist_len > n + 1) chk(cc_launch_zero(hist + n + 1, (size_t)(hist_len - n - 1) * 8, s));
+  unsigned int dstat = 0u;
+  chk(hipMemcpyAsync(&dstat, &ctl->status, 4, hipMemcpyDeviceToHost, s));
+  chk(hipStreamSynchronize(s));
+  if (e != hipSuccess) return hip_err(e);
+  if (dstat & (CC_DEV_CORRUPT | CC_DEV_LOST | CC_DEV_BARRIER_TIMEOUT)) return CC_ERR_INTERNAL;
+  if (dstat & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
+  return CC_OK;
+}
+
 // ------------------------------------------------------------------ serving
 // A request loop over the batched kernels.  Requests (one graph each) are
 // copied in at submission; a dispatcher thread admits pending requests into
