@@ -22,7 +22,8 @@
  *  - Cycles are reported in canonical form: starting at the vertex with the
  *    smallest original id, continuing towards the smaller of that vertex's
  *    two cycle neighbours.  Enumeration output is ordered by length; the
- *    order among cycles of equal length is unspecified.
+ *    order among cycles of equal length is unspecified unless CC_SORTED is
+ *    set (then it is ascending lexicographic order of the vertex lists).
  *  - Pointers are host pointers unless a CC_*_DEVICE flag says otherwise.
  *    Device pointers must be device-accessible memory of the current HIP
  *    device.  All GPU work is ordered on cc_options.stream; every call
@@ -68,11 +69,14 @@ typedef enum cc_status {
 #define CC_OUTPUT_DEVICE (1u << 1) /* cc_enumerate's verts/offsets are device pointers        */
 #define CC_FORCE_DFS     (1u << 2) /* take the depth-first path from level dfs_level on      */
 #define CC_PROFILE       (1u << 3) /* time each kernel of a run with HIP events (cc_run_info) */
-#define CC_LEVEL_PERSISTENT (1u << 4) /* run all breadth-first steps in one cooperative
-                                        launch with a grid barrier between steps, instead
-                                        of one launch per step (same results)              */
+/* (1u << 4) is not used */
 #define CC_ONE_LEVEL_STEPS (1u << 5)  /* expand one level per breadth-first step, never two
                                         (same results)                                     */
+#define CC_SORTED        (1u << 6) /* cc_enumerate / cc_enumerate_lengths: the cycles of each
+                                      length in ascending lexicographic order of their
+                                      canonical vertex lists, so the whole output is sorted
+                                      by (k, c0, c1, ...) (Algorithm 1's output set C in one
+                                      fixed order); sorted on the device after the run    */
 
 typedef struct cc_options {
   void *stream;                  /* hipStream_t; NULL = the null stream                 */
@@ -97,8 +101,7 @@ typedef struct cc_run_info {
   int64_t paths;             /* open chordless paths expanded (sum over lengths)     */
   int64_t peak_frontier;     /* largest level frontier held in breadth-first mode     */
   int32_t switch_level;      /* path length handed to the depth-first kernel, 0=none */
-  int32_t levels_launched;   /* full-grid breadth-first step launches (1 for the
-                                cooperative loop of CC_LEVEL_PERSISTENT)            */
+  int32_t levels_launched;   /* full-grid breadth-first step launches             */
   double gpu_ms;             /* device time of the call, HIP events around its work  */
   /* With CC_PROFILE only (else 0): device time of each part of the run.       */
   double stage1_ms;          /* initial triplets and triangles                       */
@@ -108,7 +111,7 @@ typedef struct cc_run_info {
   int64_t device_diag;       /* after CC_ERR_INTERNAL: which check failed (kind << 24 |
                                 low 24 bits of the offending value), else 0          */
   int32_t head_steps;        /* leading small steps run on one block before the
-                                full-grid launches (not with CC_LEVEL_PERSISTENT)    */
+                                full-grid launches                                   */
   int32_t reserved;
   double head_ms;            /* CC_PROFILE: device time of those leading steps       */
   int64_t head_bytes;        /* CC_PROFILE: bytes those leading steps must move      */

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 import threading
 
 import numpy as np
@@ -32,8 +33,8 @@ CC_INPUT_DEVICE = 1 << 0
 CC_OUTPUT_DEVICE = 1 << 1
 CC_FORCE_DFS = 1 << 2
 CC_PROFILE = 1 << 3
-CC_LEVEL_PERSISTENT = 1 << 4
 CC_ONE_LEVEL_STEPS = 1 << 5
+CC_SORTED = 1 << 6
 CC_MAX_VERTICES = 256
 CC_MAX_BATCH_VERTICES = 128
 CC_BATCH_PERSISTENT = 0
@@ -197,7 +198,14 @@ def _ptr(x):
 
 
 def _stream_handle(stream) -> int | None:
+    """A hipStream_t for the library: the given stream (torch.cuda.Stream or
+    a raw handle), else torch's current stream once torch has set up the GPU
+    (so device tensors written on a side stream are ordered before the
+    library's work), else the null stream."""
     if stream is None:
+        torch = sys.modules.get("torch")
+        if torch is not None and torch.cuda.is_initialized():
+            return int(torch.cuda.current_stream().cuda_stream)
         return None
     if isinstance(stream, int):
         return stream
@@ -211,8 +219,8 @@ class Graph:
     def __init__(self, n, row_ptr, col_idx, stream=None, budget_bytes: int = 0,
                  force_dfs_level: int | None = None, dfs_waves_per_cu: int = 0,
                  bfs_blocks: int = 0, output_device: bool = True, profile: bool = False,
-                 dfs_donate_min: int = 0, dfs_claim: int = 0, persistent_levels: bool = False,
-                 one_level_steps: bool = False):
+                 dfs_donate_min: int = 0, dfs_claim: int = 0, one_level_steps: bool = False,
+                 sorted_output: bool = False):
         L = lib()
         rp, rp_dev, self._k1 = _ptr(_as_i32(row_ptr))
         ci, ci_dev, self._k2 = _ptr(_as_i32(col_idx))
@@ -227,10 +235,10 @@ class Graph:
             flags |= CC_FORCE_DFS
         if profile:
             flags |= CC_PROFILE
-        if persistent_levels:
-            flags |= CC_LEVEL_PERSISTENT
         if one_level_steps:
             flags |= CC_ONE_LEVEL_STEPS
+        if sorted_output:
+            flags |= CC_SORTED
         self.opt = Options(_stream_handle(stream), int(budget_bytes), flags,
                            int(force_dfs_level or 0), int(dfs_waves_per_cu), int(bfs_blocks),
                            int(dfs_donate_min), int(dfs_claim))

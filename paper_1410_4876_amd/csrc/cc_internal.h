@@ -29,7 +29,6 @@
 #define CC_DEV_IDLE_TIMEOUT 4u    // an idle wavefront gave up waiting (diagnostic only)
 #define CC_DEV_CORRUPT 8u         // a depth-first consistency check failed (results discarded)
 #define CC_DEV_LOST 16u           // a wavefront gave up on paths it was promised (results incomplete)
-#define CC_DEV_BARRIER_TIMEOUT 32u  // a block of the level loop gave up at a grid barrier
 // First failed consistency check (CcCtl::diag): kind << 24 | low 24 bits of the value.
 #define CC_DIAG_INBOX_COUNT 1u    // more paths announced than an inbox holds
 #define CC_DIAG_REQUESTER 2u      // a work request names no wavefront of this launch
@@ -62,15 +61,6 @@ struct CcCtl {
   unsigned long long hist_sh[CC_SHARDS][CC_HSLOTS];   // cycles with k vertices, per shard
   // ---- zeroed in full before every run (the per-shard arrays above only in
   //      the columns 0..n+1 a run uses)
-  unsigned int bar_arrive[CC_SHARDS][32];   // grid barrier: arrivals per shard (own line each)
-  unsigned int bar_top[32];                 // grid barrier: shards complete
-  unsigned int bar_gen[32];                 // grid barrier: generation
-  unsigned int xcd_blocks[16][32];          // level loop: blocks on each XCD (own line each)
-  unsigned int xcd_arrive[16][32];          // level loop: arrivals per XCD
-  unsigned int xcd_depart[16][32];          // level loop: departures per XCD (first one invalidates)
-  unsigned int xcd_go[16][32];              // level loop: XCD L2 invalidated for generation
-  unsigned int xcd_top[32];                 // level loop: XCDs complete
-  unsigned int xcd_gen[32];                 // level loop: barrier generation
   unsigned long long cum_c[CC_HSLOTS];      // enumerate: cycles of length <= t (breadth-first)
   unsigned long long cum_v[CC_HSLOTS];      // enumerate: their vertex count
   unsigned long long dfs_hist[CC_HSLOTS];   // enumerate: depth-first part, counting pass
@@ -81,7 +71,6 @@ struct CcCtl {
   // ---- read back by the host after every run (from here to the end)
   unsigned long long hist[CC_HSLOTS];       // final histogram (written by k_finalize)
   unsigned long long front[CC_HSLOTS];      // paths with t vertices expanded
-  unsigned long long level_clock[CC_HSLOTS]; // persistent level loop: clock at each step start
   int launch_step[CC_HSLOTS];               // step of step launch i, plus one (0: loop over)
   int step_level[CC_HSLOTS];                // t of each step
   unsigned long long peak;                  // largest breadth-first frontier
@@ -212,10 +201,8 @@ struct BatchDev {
 };
 
 // ------------------------------------------------------------------ launchers
-// All return hipSuccess or the launch error.  `W` is 1 (n <= 64) or 2.
+// All return hipSuccess or the launch error.  `W` is 1, 2 or 4 (n <= 64, 128, 256).
 hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s);
-// Zeroes what a run on a graph of n vertices uses of the control block.
-hipError_t cc_launch_zero_ctl(CcCtl *ctl, int n, hipStream_t s);
 // adj (label space) and adj_orig (original ids) rows are at (v0 + row) * W.
 // bound (may be NULL) receives, per graph, sum over vertices of C(deg, 2):
 // an upper bound on its initial triplets plus triangles.  reply (one graph
@@ -228,15 +215,12 @@ hipError_t cc_launch_ingest(int W, int n_graphs, const int *graph_vtx_off, int n
                             hipStream_t s);
 // Stage one of graphs bt.g0 .. bt.g0 + n_graphs - 1 (one block each).
 hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_t s);
-// Stage one: the initial triplets go to frontier f3 (buffer 1), triangles
-// to stage st (pair 0, slot 0); sets the state of step 0.
-hipError_t cc_launch_triplets(int W, bool enumerate, GraphDev g, CcCtl *ctl, Frontier f3,
-                              Stage st, hipStream_t s);
 // Stage one and the leading levels of the breadth-first loop on one block
 // with the frontier in LDS (launch 0 for host_done), while a level's paths
 // fit in lds_bytes of dynamic shared memory (two buffers); records the step
-// the launches start at.  Replaces cc_launch_triplets in the launched loop.
-// With zero_ctl it first zeroes the control block as cc_launch_zero_ctl.
+// the launches start at.
+// With zero_ctl it first zeroes what a run on a graph of g.n vertices uses
+// of the control block.
 hipError_t cc_launch_head(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
                           OutDev out, int forced_level, size_t lds_bytes,
                           unsigned int *host_done, bool zero_ctl, hipStream_t s);
@@ -251,15 +235,6 @@ size_t cc_head_static_lds(int W, bool enumerate);
 hipError_t cc_launch_step(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
                           OutDev out, int launch, int forced_level, int max_children, bool two,
                           int blocks, unsigned int *host_done, hipStream_t s);
-// The whole loop as one cooperative launch of `blocks` blocks (at most
-// cc_levels_max_blocks).  With `clock` (device memory, may be NULL) the
-// start of every step is recorded.
-hipError_t cc_launch_levels(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                            OutDev out, int forced_level, int max_children, bool two,
-                            int blocks, unsigned long long barrier_timeout,
-                            unsigned long long *clock, hipStream_t s);
-// Blocks of k_levels that fit on the device at once (0 if unknown).
-int cc_levels_max_blocks(int W, bool enumerate);
 // Blocks of the step kernel resident per CU (its grid is that many per CU).
 int cc_step_blocks_per_cu(int W, bool enumerate);
 // The handed-over paths are in frontier f0 or f1 (CcCtl::root_buf); the
@@ -281,3 +256,8 @@ hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchD
 // enum_bases computes the output base of each cycle length.
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s);
 hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool enumerate, hipStream_t s);
+// After a complete enumerate run: the cycles of each length in out into
+// ascending lexicographic order (tmp: room for the output's vertex ids; ia,
+// ib: room for its cycle count each).  A no-op when the output did not fit.
+hipError_t cc_launch_sort_cycles(const CcCtl *ctl, OutDev out, int n, int *tmp, unsigned *ia,
+                                 unsigned *ib, hipStream_t s);

@@ -354,13 +354,9 @@ __device__ __forceinline__ void zero_ctl_body(CcCtl *ctl, int cols, size_t tid, 
     ctl->count_sh[s][k] = 0ull;
     ctl->hist_sh[s][k] = 0ull;
   }
-  unsigned int *rest = &ctl->bar_arrive[0][0];
-  const size_t words = (sizeof(CcCtl) - offsetof(CcCtl, bar_arrive)) / 4;
+  unsigned int *rest = (unsigned int *)&ctl->cum_c[0];
+  const size_t words = (sizeof(CcCtl) - offsetof(CcCtl, cum_c)) / 4;
   for (size_t i = tid; i < words; i += nt) rest[i] = 0u;
-}
-__global__ void k_zero_ctl(CcCtl *ctl, int cols) {
-  zero_ctl_body(ctl, cols, (size_t)blockIdx.x * blockDim.x + threadIdx.x,
-                (size_t)gridDim.x * blockDim.x);
 }
 
 __global__ void k_zero(unsigned int *p, size_t words) {
@@ -613,24 +609,6 @@ __device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, 
   __syncthreads();
 }
 
-template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_BLOCK) void k_triplets(GraphDev g, CcCtl *ctl, Frontier f,
-                                                       Stage st) {
-  __shared__ unsigned long long sN[CC_ROWS(W) * W];
-  __shared__ int sPerm[CC_ROWS(W)];
-  __shared__ unsigned int sTrip, sTri;
-  const int n = g.n;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
-  for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
-  if (tid == 0) {
-    sTrip = 0u;
-    sTri = 0u;
-  }
-  __syncthreads();
-  triplets_body<W, ENUM, CC_BLOCK>(g, ctl, f, st, sN, sPerm, &sTrip, &sTri);
-}
-
 template <int W>
 __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
   __shared__ unsigned long long sN[CC_ROWS(W) * W];
@@ -697,10 +675,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
 // output index cum_c[k-1] + g, vertices at cum_v[k-1] + g * k, so the output
 // is ordered by length.  Every lane decodes one cycle.
 //
-// The steps run either as one launch each (k_step; Algorithm 4's fixed
-// relaunches, without readback: the step's t and buffers live in CcCtl) or
-// all in one cooperative launch with a grid barrier between them
-// (k_levels).  Both run step_body.
+// The steps run as one launch each (k_step; Algorithm 4's fixed relaunches,
+// without readback: the step's t and buffers live in CcCtl).
 
 // Shared memory of one block running steps.
 template <int W, bool ENUM>
@@ -1742,140 +1718,6 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
   }
 }
 
-// Grid-wide barrier of a cooperative launch (every block resident).  Blocks
-// arrive on one of CC_SHARDS counters (each on its own line, so no counter
-// serialises more than a few dozen arrivals); the last arrival of a shard
-// arrives on the top counter, and the last of those opens the next
-// generation.  Counters only grow (barrier number gen expects
-// (gen + 1) * arrivals), so nothing is reset between barriers.  The release
-// fence before arriving and the acquire fence after leaving make every
-// block's writes of the level visible to every block.  A block that waits
-// longer than `timeout` clock ticks records CC_DEV_BARRIER_TIMEOUT and
-// leaves, so every wait ends.
-__device__ void grid_barrier(CcCtl *ctl, unsigned long long timeout) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    // this block saw generation gen open (or it is the first barrier)
-    const unsigned gen = ld_relaxed(&ctl->bar_gen[0]);
-    const unsigned nb = gridDim.x;
-    const unsigned sh = blockIdx.x % CC_SHARDS;
-    const unsigned in_shard = (nb - sh + CC_SHARDS - 1) / CC_SHARDS;  // blocks b = sh mod 64
-    const unsigned shards = nb < CC_SHARDS ? nb : CC_SHARDS;
-    if (atomicAdd(&ctl->bar_arrive[sh][0], 1u) == (gen + 1u) * in_shard - 1u) {
-      if (atomicAdd(&ctl->bar_top[0], 1u) == (gen + 1u) * shards - 1u)
-        __hip_atomic_store(&ctl->bar_gen[0], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const unsigned long long t0 = wall_clock64();
-    while (ld_relaxed(&ctl->bar_gen[0]) == gen) {
-      __builtin_amdgcn_s_sleep(2);
-      if (wall_clock64() - t0 > timeout) {
-        atomicOr(&ctl->status, CC_DEV_BARRIER_TIMEOUT);
-        break;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-}
-
-// The XCD (accelerator complex die, with its own L2) this wavefront runs on.
-__device__ __forceinline__ unsigned xcc_id() {
-  unsigned x;
-  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
-  return x & 0xfu;
-}
-
-// Level-loop barrier with one L2 write-back and one L2 invalidate per XCD
-// instead of one per block.  Blocks of one XCD share its L2: once every
-// block of the XCD has arrived (each after its stores completed), the last
-// arrival writes that L2 back and arrives on the top counter; the last top
-// arrival opens the next generation.  On leaving, the first block of each
-// XCD invalidates the XCD's L2 and tells the others, and every block
-// invalidates its own CU's L1.  xcd_blocks[] holds the blocks per XCD
-// (counted once at the start of the kernel); nx the XCDs that have blocks.
-__device__ void xcd_barrier(CcCtl *ctl, unsigned xcc, unsigned nx, unsigned long long timeout) {
-  wait_mem();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned gen = ld_relaxed(&ctl->xcd_gen[0]);
-    const unsigned mine = ld_relaxed(&ctl->xcd_blocks[xcc][0]);
-    const unsigned long long t0 = wall_clock64();
-    bool late = false;
-    if (atomicAdd(&ctl->xcd_arrive[xcc][0], 1u) == (gen + 1u) * mine - 1u) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this XCD's L2 to memory
-      if (atomicAdd(&ctl->xcd_top[0], 1u) == (gen + 1u) * nx - 1u)
-        st_coh(&ctl->xcd_gen[0], gen + 1u);
-    }
-    while (ld_relaxed(&ctl->xcd_gen[0]) == gen) {
-      __builtin_amdgcn_s_sleep(1);
-      if (wall_clock64() - t0 > timeout) {
-        late = true;
-        break;
-      }
-    }
-    if (!late && atomicAdd(&ctl->xcd_depart[xcc][0], 1u) == gen * mine) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // this XCD's L2 and this CU's L1
-      st_coh(&ctl->xcd_go[xcc][0], gen + 1u);
-    } else {
-      while (!late && ld_relaxed(&ctl->xcd_go[xcc][0]) != gen + 1u) {
-        __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t0 > timeout) late = true;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      asm volatile("buffer_inv sc0" ::: "memory");  // this CU's L1
-    }
-    if (late) atomicOr(&ctl->status, CC_DEV_BARRIER_TIMEOUT);
-  }
-  __syncthreads();
-}
-
-// The whole loop in one cooperative launch: the graph is loaded into LDS
-// once, steps run back to back with a grid barrier between them, and the
-// loop ends on the device when a step finds no paths or hands over to the
-// depth-first kernel.  With `clock` (may be NULL), block 0 records the wall
-// clock at the start of every step and at the end (clock[s] .. clock[s+1]
-// is step s).
-template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_BLOCK) void k_levels(GraphDev g, CcCtl *ctl, LevelBufs B,
-                                                     OutDev out, int forced_level, int maxc,
-                                                     int allow_two,
-                                                     unsigned long long barrier_timeout,
-                                                     unsigned long long *clock) {
-  __shared__ LevelLds<W, ENUM> L;
-  __shared__ unsigned sNx;
-  load_graph_lds<W, ENUM>(g, L);
-  // count the blocks of each XCD once, behind a plain grid barrier
-  const unsigned xcc = xcc_id();
-  if (threadIdx.x == 0) atomicAdd(&ctl->xcd_blocks[xcc][0], 1u);
-  grid_barrier(ctl, barrier_timeout);
-  if (threadIdx.x == 0) {
-    unsigned nx = 0;
-    for (int x = 0; x < 16; ++x) nx += ld_relaxed(&ctl->xcd_blocks[x][0]) != 0u;
-    sNx = nx;
-  }
-  __syncthreads();
-  const unsigned nx = sNx;
-  int step = 0;
-  // at most n - 2 steps (each expands at least one level); the clock array
-  // has room for them
-  for (; step < g.n - 2; ++step) {
-    if (clock && blockIdx.x == 0 && threadIdx.x == 0) clock[step] = wall_clock64();
-    const int r = step_body<W, ENUM>(g, ctl, B, out, step, load_state(&ctl->ss[step]),
-                                     forced_level, maxc, allow_two != 0, L, true);
-    if (r != CC_LEVEL_NEXT) {
-      ++step;
-      break;
-    }
-    xcd_barrier(ctl, xcc, nx, barrier_timeout);
-    if (ld_relaxed(&ctl->status) & CC_DEV_BARRIER_TIMEOUT) break;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (clock) clock[step] = wall_clock64();  // step <= n - 2 < CC_HSLOTS
-    ctl->levels_run = step;
-  }
-}
-
 // ---------------------------------------------------------- depth-first
 // Depth-first continuation (beyond the memory budget, on request, and for
 // batches of small graphs).  The unit of work is a frame: the open paths
@@ -2704,6 +2546,128 @@ __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
   }
 }
 
+// ------------------------------------------------------------ sorted output
+// Sorts the enumerated cycles of each length into ascending lexicographic
+// order of their canonical vertex lists (the cycles of one length are
+// fixed-size records of k original ids, all below 256, at a fixed stride, so
+// the offsets do not change).  One block per length, all lengths in one
+// launch: a stable LSD radix sort of the record indices with one byte digit
+// per position, last position first, then one gather of the records.
+//   verts   the output (window relative); tmp has room for its vertex ids;
+//   ia, ib  index scratch of at least the window's cycle count each.
+// The lengths' places in the output come from the final histogram.  If the
+// output did not fit the caller's buffers nothing is touched.
+constexpr int kSortThreads = 1024;
+__global__ __launch_bounds__(kSortThreads) void k_sort_cycles(const CcCtl *ctl, OutDev out,
+                                                              int n, int *tmp, unsigned *ia0,
+                                                              unsigned *ib0) {
+  constexpr int NW = kSortThreads / CC_WAVE;
+  __shared__ unsigned long long sh[4];
+  __shared__ unsigned base[256];
+  __shared__ unsigned wcnt[NW][257];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / CC_WAVE;
+  if (k < 3 || k > n || k < out.kmin || k > out.kmax) return;
+  if (tid == 0) {
+    unsigned long long cb = 0, vb = 0, tc = 0, tv = 0;
+    for (int j = 0; j <= n && j < CC_HSLOTS; ++j) {
+      if (j < out.kmin || j > out.kmax) continue;
+      const unsigned long long h = ctl->hist[j];
+      if (j < k) {
+        cb += h;
+        vb += h * (unsigned long long)j;
+      }
+      tc += h;
+      tv += h * (unsigned long long)j;
+    }
+    const bool fits = tc <= (unsigned long long)out.cyc_cap && tv <= (unsigned long long)out.verts_cap;
+    sh[0] = cb;
+    sh[1] = vb;
+    sh[2] = fits ? ctl->hist[k] : 0ull;
+  }
+  __syncthreads();
+  const unsigned long long cb = sh[0], vb = sh[1], cnt = sh[2];
+  if (cnt < 2) return;
+  const int *src = out.verts + vb;
+  unsigned *ia = ia0 + cb, *ib = ib0 + cb;
+  for (unsigned long long i = tid; i < cnt; i += kSortThreads) ia[i] = (unsigned)i;
+  __syncthreads();
+  for (int pos = k - 1; pos >= 0; --pos) {
+    // digit counts of the whole length, then where each digit starts
+    for (int d = tid; d < 256; d += kSortThreads) base[d] = 0u;
+    __syncthreads();
+    for (unsigned long long i = tid; i < cnt; i += kSortThreads)
+      atomicAdd(&base[src[(unsigned long long)ia[i] * k + pos] & 0xff], 1u);
+    __syncthreads();
+    if (tid < CC_WAVE) {
+      // exclusive scan of 256 counts: four per lane, then across lanes
+      unsigned c[4], s = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = base[tid * 4 + q];
+        s += c[q];
+      }
+      unsigned incl = s;
+#pragma unroll
+      for (int o = 1; o < CC_WAVE; o <<= 1) {
+        const unsigned y = __shfl_up(incl, o, CC_WAVE);
+        if (lane >= o) incl += y;
+      }
+      unsigned run = incl - s;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        base[tid * 4 + q] = run;
+        run += c[q];
+      }
+    }
+    __syncthreads();
+    // stable scatter, 1024 records at a time in index order: a record's
+    // place is its digit's start, plus the records of that digit in earlier
+    // wavefronts of the chunk, plus those at lower lanes of its wavefront
+    for (unsigned long long c0 = 0; c0 < cnt; c0 += kSortThreads) {
+      const unsigned long long i = c0 + tid;
+      const bool has = i < cnt;
+      const unsigned d = has ? (unsigned)(src[(unsigned long long)ia[i] * k + pos] & 0xff) : 256u;
+      unsigned long long same = ~0ull;
+#pragma unroll
+      for (int b = 0; b < 9; ++b) {
+        const unsigned long long mb = wave_ballot((d >> b) & 1u);
+        same &= ((d >> b) & 1u) ? mb : ~mb;
+      }
+      const unsigned rank = lanes_below(same);
+      for (int e = tid; e < NW * 257; e += kSortThreads) (&wcnt[0][0])[e] = 0u;
+      __syncthreads();
+      if (rank == 0) wcnt[wv][d] = (unsigned)__popcll(same);
+      __syncthreads();
+      if (has) {
+        unsigned off = base[d] + rank;
+        for (int w = 0; w < wv; ++w) off += wcnt[w][d];
+        ib[off] = ia[i];
+      }
+      __syncthreads();
+      for (int e = tid; e < 256; e += kSortThreads) {
+        unsigned add = 0;
+        for (int w = 0; w < NW; ++w) add += wcnt[w][e];
+        base[e] += add;
+      }
+      __syncthreads();
+    }
+    unsigned *x = ia;
+    ia = ib;
+    ib = x;
+  }
+  // records in sorted order into tmp, then back over the length's range
+  int *dst = tmp + vb;
+  const unsigned long long nv = cnt * (unsigned long long)k;
+  for (unsigned long long e = tid; e < nv; e += kSortThreads) {
+    const unsigned long long r = e / (unsigned)k, j = e - r * (unsigned)k;
+    dst[e] = src[(unsigned long long)ia[r] * k + j];
+  }
+  __syncthreads();
+  int *o = out.verts + vb;
+  for (unsigned long long e = tid; e < nv; e += kSortThreads) o[e] = dst[e];
+}
+
 // Final histogram; in enumerate mode also closes the offsets array with the
 // total vertex count.  One block.
 __global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
@@ -2714,11 +2678,6 @@ __global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t cc_launch_zero_ctl(CcCtl *ctl, int n, hipStream_t s) {
-  const int cols = std::min(std::max(n, 0) + 2, CC_HSLOTS);
-  hipLaunchKernelGGL(k_zero_ctl, dim3(64), dim3(256), 0, s, ctl, cols);
-  return hipGetLastError();
-}
 
 hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
@@ -2750,24 +2709,6 @@ hipError_t launch_triplets_batch(BatchDev bt, int n_graphs, hipStream_t s) {
   if (W > 2) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_triplets_batch<W <= 2 ? W : 2>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
   return hipGetLastError();
-}
-template <int W>
-hipError_t launch_triplets(bool en, GraphDev g, CcCtl *ctl, Frontier f3, Stage st, hipStream_t s) {
-  if (en) hipLaunchKernelGGL((k_triplets<W, true>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
-  else hipLaunchKernelGGL((k_triplets<W, false>), dim3(1), dim3(CC_BLOCK), 0, s, g, ctl, f3, st);
-  return hipGetLastError();
-}
-template <int W>
-const void *levels_fn(bool en) {
-  return en ? (const void *)k_levels<W, true> : (const void *)k_levels<W, false>;
-}
-template <int W>
-hipError_t launch_levels(bool en, void **args, int blocks, hipStream_t s) {
-  return hipLaunchCooperativeKernel(levels_fn<W>(en), dim3(blocks), dim3(CC_BLOCK), args, 0, s);
-}
-template <int W>
-hipError_t levels_occupancy(bool en, int *per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, levels_fn<W>(en), CC_BLOCK, 0);
 }
 template <int W>
 hipError_t step_occupancy(bool en, int *per_cu) {
@@ -2844,30 +2785,6 @@ hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_
   return CC_BY_W(W, launch_triplets_batch, bt, n_graphs, s);
 }
 
-hipError_t cc_launch_triplets(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f3, Stage st,
-                              hipStream_t s) {
-  return CC_BY_W(W, launch_triplets, en, g, ctl, f3, st, s);
-}
-
-hipError_t cc_launch_levels(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
-                            OutDev out, int forced_level, int max_children, bool two,
-                            int blocks, unsigned long long barrier_timeout,
-                            unsigned long long *clock, hipStream_t s) {
-  LevelBufs bb = b;
-  int allow_two = two ? 1 : 0;
-  void *args[] = {&g,           &ctl,       &bb, &out, &forced_level, &max_children,
-                  &allow_two,   &barrier_timeout, &clock};
-  return CC_BY_W(W, launch_levels, en, args, blocks, s);
-}
-
-int cc_levels_max_blocks(int W, bool en) {
-  int per_cu = 0, dev = 0, cus = 0;
-  if (CC_BY_W(W, levels_occupancy, en, &per_cu) != hipSuccess ||
-      hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
-  return per_cu * cus;
-}
 
 int cc_step_blocks_per_cu(int W, bool en) {
   // the same for every device of a process here (one architecture); asked
@@ -2962,6 +2879,13 @@ hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchD
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s) {
   const int blocks = std::max(1, std::min(1024, (wk.nwaves * 4 + 255) / 256));
   hipLaunchKernelGGL(k_dfs_prepare, dim3(blocks), dim3(256), 0, s, ctl, wk, n, enum_bases ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t cc_launch_sort_cycles(const CcCtl *ctl, OutDev out, int n, int *tmp, unsigned *ia,
+                                 unsigned *ib, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_cycles, dim3(std::max(n + 1, 1)), dim3(kSortThreads), 0, s, ctl, out,
+                     n, tmp, ia, ib);
   return hipGetLastError();
 }
 

@@ -37,7 +37,6 @@ constexpr double kIdleTimeoutSeconds = 30.0;
 struct DeviceInfo {
   bool ok = false;
   int cus = 0;
-  bool coop = false;  // cooperative launches supported
   unsigned long long clock_hz = 0;
   size_t lds_block = 0;  // LDS a block may hold
 };
@@ -64,14 +63,11 @@ cc_status device_info(int dev, DeviceInfo *out) {
       uint64_t thr = UINT64_MAX;
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
-    int coop = 0;
-    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
     // dynamic LDS for the head kernel's two frontier buffers: what a block
     // may hold, less the kernel's static part and a margin
     int lds = 0;
     (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     g_dev[dev].lds_block = lds > 0 ? (size_t)lds : 0;
-    g_dev[dev].coop = coop != 0;
     g_dev[dev].cus = p.multiProcessorCount;
     g_dev[dev].clock_hz = (unsigned long long)rate_khz * 1000ull;
     g_dev[dev].ok = true;
@@ -292,9 +288,18 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   const bool host_out = en && ro.host_offsets != nullptr;
   const size_t hv_bytes = host_out ? align_up((size_t)std::max<int64_t>(ro.out.verts_cap, 1) * 4, 256) : 0;
   const size_t ho_bytes = host_out ? align_up((size_t)(ro.out.cyc_cap + 1) * 8, 256) : 0;
+  // CC_SORTED: a copy area for the vertex ids and two index arrays
+  const bool sorted = en && (g->opt.flags & CC_SORTED);
+  const size_t sv_bytes =
+      sorted ? align_up((size_t)std::max<int64_t>(ro.out.verts_cap, 1) * 4, 256) : 0;
+  const size_t si_bytes =
+      sorted ? align_up((size_t)std::max<int64_t>(ro.out.cyc_cap, 1) * 4, 256) : 0;
   char *arena = nullptr;
   CC_TRY(hipMallocAsync((void **)&arena,
-                        2 * buf_bytes + 4 * stage_bytes + dfs_bytes + hv_bytes + ho_bytes, s));
+                        2 * buf_bytes + 4 * stage_bytes + dfs_bytes + hv_bytes + ho_bytes +
+                            sv_bytes + 2 * si_bytes,
+                        s));
+  char *sort_region = arena + 2 * buf_bytes + 4 * stage_bytes + dfs_bytes + hv_bytes + ho_bytes;
   char *dfs_region = arena + 2 * buf_bytes + 4 * stage_bytes;
   OutDev out = ro.out;
   if (host_out) {
@@ -363,39 +368,19 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   auto mark = [&](int i) {
     if (prof) chk(hipEventRecord(g->evp[i], s));
   };
-  const int coop_max = g->dev.coop && (g->opt.flags & CC_LEVEL_PERSISTENT)
-                           ? cc_levels_max_blocks(W, en)
-                           : 0;
-  const bool persistent = coop_max >= CC_SHARDS;
   chk(hipEventRecord(g->ev0, s));
-  // Zeroing the control block and stage one: kernels of their own before
-  // the persistent loop; inside the head kernel (launch 0) otherwise.
-  if (persistent) chk(cc_launch_zero_ctl(ctl, n, s));
   mark(0);
-  if (persistent) chk(cc_launch_triplets(W, en, gd, ctl, f[1], lb.st[0], s));
   mark(1);
   // Each step expands the paths of one length by one level, or by two when
   // its output provably fits, and (enumerate mode) decodes the cycles the
-  // previous step staged.  There are at most n - 2 steps.
-  //
-  // Default: one launch per step.  The step kernels report the end of the
-  // loop through a pinned host word and launching stops there; the host
-  // keeps at most kLevelsAhead launches queued beyond the last step the
-  // device has started (waiting at most kAheadWaitUs for it), so it sees
-  // the end a few steps after the frontier empties.  With
-  // CC_LEVEL_PERSISTENT, one cooperative launch runs every step with a grid
-  // barrier in between and stops on the device; on MI355X its barriers cost
-  // about as much as the launches they replace, so it is not the default.
+  // previous step staged.  There are at most n - 2 steps, one launch each.
+  // The step kernels report the end of the loop through a pinned host word
+  // and launching stops there; the host keeps at most kLevelsAhead launches
+  // queued beyond the last step the device has started (waiting at most
+  // kAheadWaitUs for it), so it sees the end a few steps after the frontier
+  // empties.
   const bool two_ok = !(g->opt.flags & CC_ONE_LEVEL_STEPS);
-  if (persistent) {
-    const int want = g->opt.bfs_blocks > 0 ? g->opt.bfs_blocks : g->dev.cus * 4;
-    const int blocks = std::max(1, std::min(want, coop_max));
-    mark(2);
-    chk(cc_launch_levels(W, en, gd, ctl, lb, out, forced, maxc, two_ok, blocks,
-                         (unsigned long long)(kIdleTimeoutSeconds * (double)g->dev.clock_hz),
-                         prof ? dev_field(ctl, offsetof(CcCtl, level_clock)) : nullptr, s));
-    mark(3);
-  } else {
+  {
     volatile unsigned int *done = g->h_done;
     done[0] = 0u;
     done[1] = 0u;
@@ -432,7 +417,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   // the host has already seen the loop end without a hand-over (the
   // hand-over word is released before the end-of-loop word).
   volatile unsigned int *hd = g->h_done;
-  const bool levels_finished = !persistent && hd[0] != 0u && hd[2] == 0u;
+  const bool levels_finished = hd[0] != 0u && hd[2] == 0u;
   mark(2 * n + 2);
   if (levels_finished) {
     // nothing to continue
@@ -454,6 +439,9 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   // the step that found the frontier empty has already finalized when it
   // says so (host_done[3], released before the end-of-loop word)
   if (!(levels_finished && hd[3] != 0u)) chk(cc_launch_finalize(ctl, out, n, en, s));
+  if (sorted)
+    chk(cc_launch_sort_cycles(ctl, out, n, (int *)sort_region, (unsigned *)(sort_region + sv_bytes),
+                              (unsigned *)(sort_region + sv_bytes + si_bytes), s));
   chk(hipEventRecord(g->ev1, s));
   // Read back the unsharded tail of the control block (everything for
   // profiling runs, which also report per-level traffic).
@@ -484,9 +472,9 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   g->info.peak_frontier = (int64_t)h.peak;
   g->info.switch_level = h.mode ? h.switch_level : 0;
   // launch 0 of the launched loop is the one-block head kernel
-  g->info.levels_launched = persistent ? 1 : std::max(levels - 1, 0);
+  g->info.levels_launched = std::max(levels - 1, 0);
   const int launches = levels;
-  const int head_steps = persistent ? 0 : std::max(h.head_steps, 0);
+  const int head_steps = std::max(h.head_steps, 0);
   levels = std::min(std::max(h.levels_run, 0), CC_HSLOTS - 1);  // steps run
   g->info.head_steps = head_steps;
   g->info.gpu_ms = ms;
@@ -504,22 +492,12 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     // launch that ran several small steps is credited to its first
     const int steps = levels;
     auto step_t = [&](int st) { return st < CC_HSLOTS ? h.step_level[st] : 0; };
-    if (persistent) {
-      g->info.level_ms = span(2, 3);
-      for (int st = 0; st < steps && st + 1 < CC_HSLOTS; ++st) {
-        const int t = step_t(st);
-        if (t >= 3 && t < CC_HSLOTS)
-          g->level_ms[t] = (double)(h.level_clock[st + 1] - h.level_clock[st]) * 1e3 /
-                           (double)g->dev.clock_hz;
-      }
-    } else {
-      for (int li = 0; li < launches; ++li) {
-        const double ms_s = span(2 + 2 * li, 3 + 2 * li);
-        (li == 0 ? g->info.head_ms : g->info.level_ms) += ms_s;
-        const int first = li == 0 ? 0 : (li < CC_HSLOTS ? h.launch_step[li] - 1 : -1);
-        const int t = first >= 0 ? step_t(first) : 0;
-        if (t >= 3 && t < CC_HSLOTS) g->level_ms[t] += ms_s;
-      }
+    for (int li = 0; li < launches; ++li) {
+      const double ms_s = span(2 + 2 * li, 3 + 2 * li);
+      (li == 0 ? g->info.head_ms : g->info.level_ms) += ms_s;
+      const int first = li == 0 ? 0 : (li < CC_HSLOTS ? h.launch_step[li] - 1 : -1);
+      const int t = first >= 0 ? step_t(first) : 0;
+      if (t >= 3 && t < CC_HSLOTS) g->level_ms[t] += ms_s;
     }
     g->info.dfs_ms = span(2 * n + 2, 2 * n + 3);
     // Bytes the steps must move: each path a step expands is read once and
@@ -551,7 +529,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
   g->info.device_diag = (int64_t)h.diag;
   dfs_stats(h, &g->info);
   cc_status st = CC_OK;
-  if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST | CC_DEV_BARRIER_TIMEOUT))
+  if (h.status & (CC_DEV_CORRUPT | CC_DEV_LOST))
     st = CC_ERR_INTERNAL;
   else if (h.status & CC_DEV_STACK_FULL)
     st = CC_ERR_OUT_OF_MEMORY;
@@ -625,7 +603,8 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   if (n > CC_MAX_VERTICES) return CC_ERR_TOO_LARGE;
   if (n > 0 && !row_ptr) return CC_ERR_INVALID_ARG;
   const uint32_t flags = opt ? opt->flags : 0u;
-  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT | CC_ONE_LEVEL_STEPS))
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_ONE_LEVEL_STEPS |
+                CC_SORTED))
     return CC_ERR_INVALID_ARG;
   if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
               opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))
@@ -988,7 +967,7 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   *out = nullptr;
   if (n_graphs < 0 || !graph_vtx_off || (n_graphs > 0 && !row_ptr)) return CC_ERR_INVALID_ARG;
   const uint32_t flags = opt ? opt->flags : 0u;
-  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_FORCE_DFS | CC_PROFILE | CC_LEVEL_PERSISTENT | CC_ONE_LEVEL_STEPS))
+  if (flags & ~(CC_INPUT_DEVICE | CC_OUTPUT_DEVICE | CC_PROFILE))
     return CC_ERR_INVALID_ARG;
   if (opt && (opt->frontier_budget_bytes < 0 || opt->dfs_donate_min < 0 || opt->dfs_claim < 0 ||
               opt->dfs_waves_per_cu < 0 || opt->bfs_blocks < 0))
@@ -1410,7 +1389,7 @@ extern "C" cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr,
   chk(hipMemcpyAsync(&dstat, &ctl->status, 4, hipMemcpyDeviceToHost, s));
   chk(hipStreamSynchronize(s));
   if (e != hipSuccess) return hip_err(e);
-  if (dstat & (CC_DEV_CORRUPT | CC_DEV_LOST | CC_DEV_BARRIER_TIMEOUT)) return CC_ERR_INTERNAL;
+  if (dstat & (CC_DEV_CORRUPT | CC_DEV_LOST)) return CC_ERR_INTERNAL;
   if (dstat & CC_DEV_STACK_FULL) return CC_ERR_OUT_OF_MEMORY;
   return CC_OK;
 }

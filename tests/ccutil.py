@@ -148,3 +148,70 @@ def groups_digest(groups) -> str:
         h.update(np.int64(k).tobytes())
         h.update(np.ascontiguousarray(groups[k], dtype=np.int64).tobytes())
     return h.hexdigest()
+
+
+def groups_all_chordless(groups, n, row_ptr, col_idx) -> bool:
+    """Every row of every group (k vertex ids) is a chordless cycle in the
+    vertex order given: k distinct vertices, consecutive ones adjacent
+    (cyclically), and exactly k edges among them (so no chord).  Vectorised
+    over the rows with per-vertex adjacency bitsets; n <= 256."""
+    words = max(1, (n + 63) // 64)
+    adj = np.zeros((max(n, 1), words), dtype=np.uint64)
+    for v in range(n):
+        for w in col_idx[row_ptr[v]:row_ptr[v + 1]]:
+            adj[v, int(w) // 64] |= np.uint64(1) << np.uint64(int(w) % 64)
+    one = np.uint64(1)
+    for k, a in groups.items():
+        a = np.asarray(a, dtype=np.int64)
+        if a.shape[0] == 0:
+            continue
+        S = np.zeros((a.shape[0], words), dtype=np.uint64)
+        for i in range(k):
+            for w in range(words):
+                sel = (a[:, i] // 64) == w
+                S[sel, w] |= one << (a[sel, i] % 64).astype(np.uint64)
+        if not np.all(np.bitwise_count(S).sum(axis=1) == k):
+            return False  # repeated vertex
+        deg2 = np.zeros(a.shape[0], dtype=np.int64)
+        for i in range(k):
+            deg2 += np.bitwise_count(adj[a[:, i]] & S).sum(axis=1).astype(np.int64)
+            nxt = a[:, (i + 1) % k]
+            bit = (adj[a[:, i], nxt // 64] >> (nxt % 64).astype(np.uint64)) & one
+            if not np.all(bit == one):
+                return False  # consecutive vertices not adjacent
+        if not np.all(deg2 == 2 * k):
+            return False  # a chord
+    return True
+
+
+def brute_force_front(n, row_ptr, col_idx, labels):
+    """front[t] by brute force: the vertex sequences (v1, ..., vt), t >= 3,
+    that form an induced path (distinct, consecutive ones adjacent, no other
+    pair adjacent) whose second vertex has the smallest label of the path and
+    whose first vertex has a smaller label than its third.  These are exactly
+    the open chordless paths the method expands (Section 2): the initial
+    triplets for t = 3 and their extensions.  Depth-first over sequences;
+    intended for n <= 10."""
+    adj = adjacency_sets(n, row_ptr, col_idx)
+    lab = [int(x) for x in labels]
+    front = np.zeros(n + 1, np.int64)
+
+    def grow(path):
+        t = len(path)
+        if t >= 3:
+            front[t] += 1
+        last = path[-1]
+        for v in adj[last]:
+            if v in path or lab[v] < lab[path[1]]:
+                continue
+            if any(v in adj[u] for u in path[:-1]):
+                continue  # a chord, or a closure through v1
+            if t == 2 and lab[path[0]] > lab[v]:
+                continue
+            grow(path + [v])
+
+    for v1 in range(n):
+        for v2 in adj[v1]:
+            if lab[v2] < lab[v1]:
+                grow([v1, v2])
+    return front

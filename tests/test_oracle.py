@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from ccutil import (adjacency_sets, brute_force_sets, canonical, hist_of_sets,
+from ccutil import (adjacency_sets, brute_force_front, brute_force_sets, canonical, hist_of_sets,
                     is_chordless_cycle, triangles_by_trace)
 from paper_1410_4876_amd import graphgen as gg
 
@@ -78,6 +78,36 @@ def test_hypercube_and_misc_vs_brute():
 def test_cycle_graph(n):
     r = run(gg.permute_random(gg.cycle(n), np.random.default_rng(n)))
     assert r.count == 1 and r.hist[n] == 1
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 9, 30, 100])
+def test_cycle_graph_front_closed_form(n):
+    """C_n: one initial triplet (around the vertex labelled 0), then one
+    forced extension per level, so front[t] = 1 for 3 <= t <= n-1 and the
+    extension to n vertices closes the cycle instead (Section 2)."""
+    g = gg.permute_random(gg.cycle(n), np.random.default_rng(n))
+    r = oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=False)
+    want = np.zeros(n + 1, np.int64)
+    want[3:n] = 1
+    assert r.front.tolist() == want.tolist()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_front_matches_brute_force(seed):
+    """front[t] (open chordless paths with t vertices expanded) equals the
+    number of induced paths (v1..vt) whose second vertex has the smallest
+    label and whose first is below the third, counted by brute force from
+    that definition on random graphs of at most 9 vertices."""
+    rng = np.random.default_rng(300 + seed)
+    for _ in range(12):
+        n = int(rng.integers(3, 10))
+        g = gg.er_gnm(n, int(rng.integers(0, n * (n - 1) // 2 + 1)), rng)
+        r = oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=False)
+        assert np.array_equal(r.front, brute_force_front(g.n, g.row_ptr, g.col_idx, r.labels))
+    for g in [gg.permute_random(gg.grid(3, 3), rng), gg.wheel(6), gg.hypercube(3),
+              gg.complete_bipartite(3, 4), gg.ladder(4)]:
+        r = oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=False)
+        assert np.array_equal(r.front, brute_force_front(g.n, g.row_ptr, g.col_idx, r.labels))
 
 
 @pytest.mark.parametrize("n", [3, 4, 7, 12, 20])
