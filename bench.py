@@ -501,10 +501,13 @@ def grid7x12_section():
 
 
 def paging_section():
-    """Grid 7x10 (8,136,453 cycles, 0.95 GB of vertex ids): the whole output
-    in one cc_enumerate call, and the same output paged through buffers of
-    at most 64 Mi vertex ids (256 MiB) by ranges of cycle lengths
-    (cc_enumerate_lengths).  Every page reruns the enumeration."""
+    """Grid 7x10 (8,136,453 cycles, 258M vertex ids): the whole output in one
+    cc_enumerate call, against the same output paged through buffers of at
+    most 64 Mi vertex ids (256 MiB), two ways: by ranges of stage-one roots
+    (cc_enumerate_roots; each page runs only the search below its roots) and
+    by ranges of cycle lengths (cc_enumerate_lengths; each page reruns the
+    whole enumeration).  The root pages are checked to add up to the
+    histogram."""
     import torch
 
     from paper_1410_4876_amd import cc
@@ -525,18 +528,36 @@ def paging_section():
             h.enumerate_into(dv, do)
             torch.cuda.synchronize()
 
-        def paged():
+        def by_lengths():
             pages = 0
-            for _, _, v, o in h.pages(max_verts=limit):
+            for _ in h.pages(max_verts=limit):
                 pages += 1
             torch.cuda.synchronize()
             return pages
 
+        def by_roots(check=False):
+            pages, cyc, ids = 0, 0, 0
+            for lo, hi, v, o in h.pages_by_roots(max_verts=limit):
+                pages += 1
+                if check:
+                    cyc += o.numel() - 1
+                    ids += int(o[-1])
+            torch.cuda.synchronize()
+            if check:
+                assert cyc == nc and ids == nv
+            return pages
+
         w = _timed(whole, warmup=2, runs=5)
-        pages = paged()
-        p = _timed(paged, warmup=1, runs=3)
+        pages_l = by_lengths()
+        pl = _timed(by_lengths, warmup=1, runs=3)
+        pages_r = by_roots(check=True)
+        pr = _timed(by_roots, warmup=1, runs=3)
     return {"workload": "grid 7x10, full enumeration", "cycles": nc, "vertex_ids": nv,
-            "whole_ms": w, "page_limit_vertex_ids": limit, "pages": pages, "paged_ms": p}
+            "whole_ms": w, "page_limit_vertex_ids": limit,
+            "by_roots": {"pages": pages_r, "ms": pr,
+                         "vs_whole": round(pr["median"] / w["median"], 2)},
+            "by_lengths": {"pages": pages_l, "ms": pl,
+                           "vs_whole": round(pl["median"] / w["median"], 2)}}
 
 
 def large_n_section():

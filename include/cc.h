@@ -191,6 +191,34 @@ cc_status cc_enumerate_lengths(cc_graph *g, int32_t k_min, int32_t k_max, int32_
                                int64_t verts_cap, int64_t *offsets, int64_t cycles_cap,
                                int64_t *n_cycles, int64_t *n_verts);
 
+/*
+ * Stage-one roots.  Every chordless cycle is found from exactly one root:
+ * its canonical triplet <x, u, y> (Section 2: u the cycle's lowest label, x
+ * and y its neighbours on the cycle, l(x) < l(y)), or the triangle it is.
+ * The roots of a graph are the (u, x, y) with x, y neighbours of u and
+ * l(u) < l(x) < l(y), triangles included, numbered 0 .. total-1 in the order
+ * of u's original id, then x's, then y's.  A range of roots therefore
+ * selects a fixed part of the cycle set, and consecutive ranges partition
+ * it: an output larger than a caller's buffers (Section 6 names larger
+ * outputs as future work) is paged by ranges of roots, each page costing
+ * only the search below its own roots, and a page may split a length.
+ */
+/* cc_root_total -- *n_roots = number of stage-one roots. */
+cc_status cc_root_total(cc_graph *g, int64_t *n_roots);
+
+/* cc_histogram_roots -- as cc_histogram, for the cycles found from roots
+ * root_lo <= index < root_hi only (0 <= root_lo <= root_hi). */
+cc_status cc_histogram_roots(cc_graph *g, int64_t root_lo, int64_t root_hi, int64_t *hist,
+                             int32_t hist_len);
+
+/* cc_enumerate_roots -- as cc_enumerate, for the cycles found from roots
+ * root_lo <= index < root_hi only: ordered by length, offsets from 0,
+ * sizes from cc_histogram_roots of the same range; BUFFER_TOO_SMALL reports
+ * the range's sizes.  CC_SORTED sorts each length of the page. */
+cc_status cc_enumerate_roots(cc_graph *g, int64_t root_lo, int64_t root_hi, int32_t *verts,
+                             int64_t verts_cap, int64_t *offsets, int64_t cycles_cap,
+                             int64_t *n_cycles, int64_t *n_verts);
+
 /* cc_labels -- labels[v] = degree label of vertex v (host array of n). */
 cc_status cc_labels(cc_graph *g, int32_t *labels);
 

@@ -116,6 +116,13 @@ def lib():
             L.cc_enumerate_lengths.argtypes = [vp, i32, i32, vp, i64, vp, i64,
                                                ctypes.POINTER(i64), ctypes.POINTER(i64)]
             L.cc_enumerate_lengths.restype = ctypes.c_int
+            L.cc_root_total.argtypes = [vp, ctypes.POINTER(i64)]
+            L.cc_root_total.restype = ctypes.c_int
+            L.cc_histogram_roots.argtypes = [vp, i64, i64, vp, i32]
+            L.cc_histogram_roots.restype = ctypes.c_int
+            L.cc_enumerate_roots.argtypes = [vp, i64, i64, vp, i64, vp, i64,
+                                             ctypes.POINTER(i64), ctypes.POINTER(i64)]
+            L.cc_enumerate_roots.restype = ctypes.c_int
             L.cc_labels.argtypes = [vp, vp]
             L.cc_labels.restype = ctypes.c_int
             L.cc_frontier.argtypes = [vp, vp, i32]
@@ -392,6 +399,92 @@ class Graph:
             v, o = self.enumerate_lengths(k0, k1, device=device)
             yield k0, k1, v, o
             i = j
+
+    # -- pages by ranges of stage-one roots
+    def root_total(self) -> int:
+        """Number of stage-one roots (cc_root_total)."""
+        r = ctypes.c_int64()
+        _check(lib().cc_root_total(self.h, ctypes.byref(r)), "cc_root_total")
+        return r.value
+
+    def histogram_roots(self, root_lo: int, root_hi: int) -> np.ndarray:
+        """Histogram of the cycles found from roots root_lo..root_hi-1."""
+        h = np.zeros(self.n + 1, np.int64)
+        _check(lib().cc_histogram_roots(self.h, int(root_lo), int(root_hi),
+                                        ctypes.c_void_p(h.ctypes.data), h.size),
+               "cc_histogram_roots", self._info_fn)
+        return h
+
+    def enumerate_roots_into(self, root_lo: int, root_hi: int, verts, offsets):
+        """The cycles found from roots root_lo..root_hi-1 into caller buffers.
+        Returns (n_cycles, n_verts); raises CCError(CC_ERR_BUFFER_TOO_SMALL)
+        with .required if they do not fit."""
+        vp, _, _ = _ptr(verts)
+        op, _, _ = _ptr(offsets)
+        nc, nv = ctypes.c_int64(), ctypes.c_int64()
+        vcap = int(verts.numel() if _is_torch(verts) else np.asarray(verts).size)
+        ccap = int(offsets.numel() if _is_torch(offsets) else np.asarray(offsets).size) - 1
+        st = lib().cc_enumerate_roots(self.h, int(root_lo), int(root_hi), vp, vcap, op,
+                                      max(ccap, 0), ctypes.byref(nc), ctypes.byref(nv))
+        if st == CC_ERR_INTERNAL:
+            _check(st, "cc_enumerate_roots", self._info_fn)
+        if st != CC_OK:
+            err = CCError(st, "cc_enumerate_roots")
+            err.required = (nc.value, nv.value)
+            raise err
+        return nc.value, nv.value
+
+    def pages_by_roots(self, max_verts: int, max_cycles: int | None = None, device="cuda"):
+        """Yield (root_lo, root_hi, verts, offsets): the whole output in pages
+        of consecutive root ranges, each holding at most max_verts vertex ids
+        (and max_cycles cycles).  The ranges start from an even split of the
+        roots sized by the whole histogram; a range whose cycles do not fit
+        is halved.  A page never reruns the whole graph.  With device output
+        every page is written into the same two buffers of the page limits
+        (the arrays yielded are views of them, valid until the next page);
+        with host output each page gets arrays of its exact size.  Raises
+        ValueError if the cycles of a single root do not fit."""
+        total = self.root_total()
+        if total == 0:
+            return
+        want = self._sizes()
+        nv_all = int((want * np.arange(want.size)).sum())
+        parts = max(1, -(-nv_all // max(max_verts, 1)))
+        bounds = [total * i // parts for i in range(parts + 1)]
+        todo = [(bounds[i], bounds[i + 1]) for i in range(parts) if bounds[i] < bounds[i + 1]]
+        cyc_cap = max_cycles if max_cycles is not None else max_verts // 3
+        if self.output_device:
+            import torch
+            verts = torch.empty(max(max_verts, 1), dtype=torch.int32, device=device)
+            offs = torch.empty(cyc_cap + 1, dtype=torch.int64, device=device)
+        while todo:
+            lo, hi = todo.pop(0)
+            if not self.output_device:
+                # host buffers: the library sizes the range by a counting run
+                h = self.histogram_roots(lo, hi)
+                nc, nv = int(h.sum()), int((h * np.arange(h.size)).sum())
+                fits = nv <= max_verts and nc <= cyc_cap
+                if fits:
+                    verts = np.empty(max(nv, 1), np.int32)
+                    offs = np.empty(nc + 1, np.int64)
+                    self.enumerate_roots_into(lo, hi, verts, offs)
+            else:
+                try:
+                    nc, nv = self.enumerate_roots_into(lo, hi, verts, offs)
+                    fits = True
+                except CCError as e:
+                    if e.status != CC_ERR_BUFFER_TOO_SMALL:
+                        raise
+                    nc, nv = e.required
+                    fits = False
+            if not fits:
+                if hi - lo == 1:
+                    raise ValueError(f"the {nc} cycles of root {lo} need {nv} vertex ids, "
+                                     f"more than max_verts={max_verts}")
+                mid = (lo + hi) // 2
+                todo[:0] = [(lo, mid), (mid, hi)]
+                continue
+            yield lo, hi, verts[:nv], offs[:nc + 1]
 
     def labels(self) -> np.ndarray:
         lab = np.zeros(max(self.n, 1), np.int32)

@@ -68,6 +68,9 @@ struct CcCtl {
   unsigned long long len_cbase[CC_HSLOTS];  // enumerate: first cycle index of each length
   unsigned long long len_vbase[CC_HSLOTS];  // enumerate: first vertex offset of each length
   StepState ss[CC_HSLOTS];                  // step s reads ss[s]; its block 0 writes ss[s + 1]
+  long long root_base[CC_MAXN];             // root range runs: index of the first stage-one
+                                            // root of each vertex (by label)
+  int orig_label[CC_MAXN];                  // root range runs: label of each original id
   // ---- read back by the host after every run (from here to the end)
   unsigned long long hist[CC_HSLOTS];       // final histogram (written by k_finalize)
   unsigned long long front[CC_HSLOTS];      // paths with t vertices expanded
@@ -114,6 +117,14 @@ struct Stage {
   unsigned long long *C;
   unsigned long long cap;
   unsigned long long cap_s;
+};
+
+// A range of stage-one roots: the (u, x, y) with l(u) < l(x) < l(y) and x, y
+// neighbours of u, triangles included, numbered by u's original id, then
+// x's, then y's; a run keeps the roots lo <= index < hi (all: 0, LLONG_MAX).
+struct RootRange {
+  long long lo = 0;
+  long long hi = 0x7fffffffffffffffll;
 };
 
 // Relabelled graph: adjacency bitsets in label space (row l = neighbours of
@@ -220,10 +231,13 @@ hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_
 // fit in lds_bytes of dynamic shared memory (two buffers); records the step
 // the launches start at.
 // With zero_ctl it first zeroes what a run on a graph of g.n vertices uses
-// of the control block.
+// of the control block.  Only the stage-one roots in `roots` are kept.
 hipError_t cc_launch_head(int W, bool enumerate, GraphDev g, CcCtl *ctl, const LevelBufs &b,
                           OutDev out, int forced_level, size_t lds_bytes,
-                          unsigned int *host_done, bool zero_ctl, hipStream_t s);
+                          unsigned int *host_done, bool zero_ctl, RootRange roots,
+                          hipStream_t s);
+// out (device) receives the number of stage-one roots of graph g.
+hipError_t cc_launch_root_total(int W, GraphDev g, long long *out, hipStream_t s);
 int cc_head_capacity(int W, bool enumerate, size_t lds_bytes);
 size_t cc_head_static_lds(int W, bool enumerate);
 // Launch `launch` (>= 1) of the breadth-first loop: one step on `blocks`

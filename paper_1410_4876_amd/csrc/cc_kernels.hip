@@ -546,20 +546,47 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
 // sPerm) and *sTrip = *sTri = 0 before the call.  Writes the triplets to f
 // and, enumerating, the triangles to st; sets the counters and the state of
 // step 0.  Ends with a barrier; *sTrip and *sTri then hold the totals.
+// With a range of roots (rr.lo > 0 or rr.hi < LLONG_MAX) every root (u, x,
+// y) gets its index in the order of u's original id, then x's, then y's
+// (ctl->root_base[u] holds the index of u's first root): the pairs of
+// higher-labelled neighbours x' of u that come before x by original id
+// each contribute their own higher-labelled partners, and y is ranked among
+// x's partners by original id.  Only roots inside the range are kept.
 template <int W, bool ENUM, int T>
 __device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, const Stage &st,
                               const unsigned long long *sN, const int *sPerm,
-                              unsigned int *sTrip, unsigned int *sTri) {
+                              unsigned int *sTrip, unsigned int *sTri, const RootRange rr) {
   const int n = g.n;
   const int tid = threadIdx.x;
+  const bool ranged = rr.lo > 0 || rr.hi < 0x7fffffffffffffffll;
   for (int idx = tid; idx < n * n; idx += T) {
     const int u = idx / n, x = idx - u * n;
     const Bits<W> nu = row<W>(sN, u);
     if (x <= u || !btest(nu, x)) continue;
     const Bits<W> nx = row<W>(sN, x);
-    Bits<W> ys = bandnot(nu, low_through<W>(x));
+    const Bits<W> ys0 = bandnot(nu, low_through<W>(x));
+    long long base = 0;
+    if (ranged) {
+      const Bits<W> up = bandnot(nu, low_through<W>(u));  // neighbours above u
+      base = ctl->root_base[u];
+      Bits<W> it = up;
+      while (bany(it)) {
+        const int xp = bpop_lowest(it);
+        if (sPerm[xp] < sPerm[x]) base += bpop(bandnot(up, low_through<W>(xp)));
+      }
+    }
+    Bits<W> ys = ys0;
     while (bany(ys)) {
       const int y = bpop_lowest(ys);
+      if (ranged) {
+        long long ix = base;
+        Bits<W> it = ys0;
+        while (bany(it)) {
+          const int yp = bpop_lowest(it);
+          ix += sPerm[yp] < sPerm[y] ? 1 : 0;
+        }
+        if (ix < rr.lo || ix >= rr.hi) continue;
+      }
       if (btest(nx, y)) {
         const unsigned j = atomicAdd(sTri, 1u);
         if (ENUM) {
@@ -607,6 +634,21 @@ __device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, 
     ctl->ss[0] = S;
   }
   __syncthreads();
+}
+
+// Number of stage-one roots (triangles and initial triplets): the sum over
+// vertices of C(d+, 2), d+ = neighbours with a higher label.  One block.
+template <int W>
+__global__ __launch_bounds__(CC_BLOCK) void k_root_total(GraphDev g, long long *out) {
+  __shared__ unsigned long long sum;
+  if (threadIdx.x == 0) sum = 0ull;
+  __syncthreads();
+  for (int l = threadIdx.x; l < g.n; l += CC_BLOCK) {
+    const unsigned long long dp = (unsigned long long)bpop(bandnot(row<W>(g.adj, l), low_through<W>(l)));
+    if (dp > 1) atomicAdd(&sum, dp * (dp - 1) / 2);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (long long)sum;
 }
 
 template <int W>
@@ -1434,7 +1476,7 @@ template <int W, bool ENUM>
 __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl, LevelBufs B,
                                                           OutDev out, int forced_level,
                                                           int cap_lds, unsigned int *host_done,
-                                                          int zero_cols) {
+                                                          int zero_cols, RootRange rr) {
   constexpr int T = CC_HEAD_THREADS;
   __shared__ HeadLds<W, ENUM> L;
   extern __shared__ unsigned long long dyn[];
@@ -1458,12 +1500,28 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
     L.Tri = 0u;
   }
   __syncthreads();
-  // stage one, into the global buffers (frontier 1, stage 0), as k_triplets
+  if (rr.lo > 0 || rr.hi < 0x7fffffffffffffffll) {
+    // the index of each vertex's first root: prefix over original ids of
+    // C(d+, 2), d+ = neighbours with a higher label
+    for (int l = tid; l < n; l += T) ctl->orig_label[L.Perm[l]] = l;
+    __syncthreads();
+    if (tid == 0) {
+      long long acc = 0;
+      for (int v = 0; v < n; ++v) {
+        const int l = ctl->orig_label[v];
+        const long long dp = bpop(bandnot(row<W>(L.N, l), low_through<W>(l)));
+        ctl->root_base[l] = acc;
+        acc += dp * (dp - 1) / 2;
+      }
+    }
+    __syncthreads();
+  }
+  // stage one, into the global buffers (frontier 1, stage 0)
   const Frontier f1 = B.f[1], f0 = B.f[0];
   const Stage st0 = B.st[0];
   // a hand-over deals at most cap paths over the shards of frontier 0
   const int cap = (int)min((unsigned long long)cap_lds, CC_SHARDS * f0.cap_s);
-  triplets_body<W, ENUM, T>(g, ctl, f1, st0, L.N, L.Perm, &L.Trip, &L.Tri);
+  triplets_body<W, ENUM, T>(g, ctl, f1, st0, L.N, L.Perm, &L.Trip, &L.Tri, rr);
   const unsigned trip = L.Trip, tri = L.Tri;
   int t = 3;
   unsigned cnt = trip;
@@ -2727,10 +2785,15 @@ hipError_t head_raise(bool en, size_t lds_bytes) {
 template <int W>
 hipError_t launch_head(bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b, OutDev out,
                        int forced_level, int cap, size_t lds_bytes, unsigned int *host_done,
-                       int zero_cols, hipStream_t s) {
+                       int zero_cols, RootRange rr, hipStream_t s) {
   dim3 gr(1), bl(CC_HEAD_THREADS);
-  if (en) hipLaunchKernelGGL((k_head<W, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols);
-  else hipLaunchKernelGGL((k_head<W, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols);
+  if (en) hipLaunchKernelGGL((k_head<W, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols, rr);
+  else hipLaunchKernelGGL((k_head<W, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols, rr);
+  return hipGetLastError();
+}
+template <int W>
+hipError_t launch_root_total(GraphDev g, long long *out, hipStream_t s) {
+  hipLaunchKernelGGL((k_root_total<W>), dim3(1), dim3(CC_BLOCK), 0, s, g, out);
   return hipGetLastError();
 }
 template <int W>
@@ -2809,9 +2872,14 @@ int cc_head_capacity(int W, bool en, size_t lds_bytes) {
   return cap > 0 ? (int)std::min<long long>(cap, 1 << 20) : 0;
 }
 
+hipError_t cc_launch_root_total(int W, GraphDev g, long long *out, hipStream_t s) {
+  return CC_BY_W(W, launch_root_total, g, out, s);
+}
+
 hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b,
                           OutDev out, int forced_level, size_t lds_bytes,
-                          unsigned int *host_done, bool zero_ctl, hipStream_t s) {
+                          unsigned int *host_done, bool zero_ctl, RootRange roots,
+                          hipStream_t s) {
   const int cap = cc_head_capacity(W, en, lds_bytes);
   const int zero_cols = zero_ctl ? std::min(std::max(g.n, 0) + 2, CC_HSLOTS) : 0;
   // The dynamic LDS limit is raised once per device and instantiation (the
@@ -2827,7 +2895,7 @@ hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBuf
     raised[dev][which].store(lds_bytes);
   }
   return CC_BY_W(W, launch_head, en, g, ctl, b, out, forced_level, cap, lds_bytes, host_done,
-                 zero_cols, s);
+                 zero_cols, roots, s);
 }
 
 // Static shared memory of the head kernel (so the caller can size the

@@ -252,6 +252,7 @@ struct RunOut {
   // buffers when they fit.
   int32_t *host_verts = nullptr;
   int64_t *host_offsets = nullptr;
+  RootRange roots;  // stage-one roots the run starts from (default: all)
 };
 
 // One full device run: stage one, the level loop, and the depth-first
@@ -394,7 +395,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     // static part and a margin
     const size_t stat = cc_head_static_lds(W, en) + 4096;
     const size_t head_lds = g->dev.lds_block > stat ? g->dev.lds_block - stat : 0;
-    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, head_lds, g->d_done, true, s));
+    chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, head_lds, g->d_done, true, ro.roots, s));
     mark(3);
     ++levels;
     for (int launch = 1; launch < n - 1 && e == hipSuccess; ++launch, ++levels) {
@@ -533,7 +534,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     st = CC_ERR_INTERNAL;
   else if (h.status & CC_DEV_STACK_FULL)
     st = CC_ERR_OUT_OF_MEMORY;
-  g->hist_ok = st == CC_OK;
+  // the whole graph's histogram, unless the run started from part of its roots
+  g->hist_ok = st == CC_OK && ro.roots.lo == 0 && ro.roots.hi == RootRange{}.hi;
   if (host_out) {
     // what the run wrote: the cycles of the output window
     int64_t cw = 0, vw = 0;
@@ -561,7 +563,7 @@ cc_status check_handle(cc_graph *g) {
   return CC_OK;
 }
 
-cc_status run_counts(cc_graph *g) {
+cc_status run_counts(cc_graph *g, RootRange roots = RootRange{}) {
   if (g->n < 3) {
     std::memset(g->hist, 0, sizeof(g->hist));
     std::memset(g->front, 0, sizeof(g->front));
@@ -570,6 +572,7 @@ cc_status run_counts(cc_graph *g) {
     return CC_OK;
   }
   RunOut ro;
+  ro.roots = roots;
   return run_device(g, ro);
 }
 
@@ -863,6 +866,98 @@ cc_status cc_enumerate_lengths(cc_graph *g, int32_t k_min, int32_t k_max, int32_
   ro.out.cshift = cshift;
   ro.out.vshift = vshift;
   return run_device(g, ro);
+}
+
+cc_status cc_root_total(cc_graph *g, int64_t *n_roots) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!n_roots) return CC_ERR_INVALID_ARG;
+  *n_roots = 0;
+  if (g->n < 3) return CC_OK;
+  // computed into the handle's status area (after the status word and the
+  // pair bound), then read back
+  long long *d_out = (long long *)((char *)g->d_status + 16);
+  long long v = 0;
+  GraphDev gd{g->d_adj, g->d_adj_orig, g->d_perm, g->n};
+  if (cc_launch_root_total(g->W, gd, d_out, g->stream) != hipSuccess ||
+      hipMemcpyAsync(&v, d_out, 8, hipMemcpyDeviceToHost, g->stream) != hipSuccess ||
+      hipStreamSynchronize(g->stream) != hipSuccess)
+    return CC_ERR_DEVICE;
+  *n_roots = v;
+  return CC_OK;
+}
+
+cc_status cc_histogram_roots(cc_graph *g, int64_t root_lo, int64_t root_hi, int64_t *hist,
+                             int32_t hist_len) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!hist || hist_len < g->n + 1 || root_lo < 0 || root_hi < root_lo)
+    return CC_ERR_INVALID_ARG;
+  st = run_counts(g, RootRange{root_lo, root_hi});
+  if (st != CC_OK) return st;
+  for (int k = 0; k < hist_len; ++k) hist[k] = k <= g->n ? g->hist[k] : 0;
+  return CC_OK;
+}
+
+cc_status cc_enumerate_roots(cc_graph *g, int64_t root_lo, int64_t root_hi, int32_t *verts,
+                             int64_t verts_cap, int64_t *offsets, int64_t cycles_cap,
+                             int64_t *n_cycles, int64_t *n_verts) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!n_cycles || !n_verts || verts_cap < 0 || cycles_cap < 0 || root_lo < 0 ||
+      root_hi < root_lo)
+    return CC_ERR_INVALID_ARG;
+  if ((verts_cap > 0 && !verts) || !offsets) return CC_ERR_INVALID_ARG;
+  *n_cycles = 0;
+  *n_verts = 0;
+  const bool dev_out = (g->opt.flags & CC_OUTPUT_DEVICE) != 0;
+  const RootRange rr{root_lo, root_hi};
+  auto totals = [&](int64_t *c, int64_t *v) {
+    *c = 0;
+    *v = 0;
+    for (int k = 0; k <= g->n; ++k) {
+      *c += g->hist[k];
+      *v += g->hist[k] * k;
+    }
+  };
+  if (g->n < 3 || root_lo == root_hi) {
+    if (g->n < 3) (void)run_counts(g);
+    if (dev_out) {
+      const int64_t zero = 0;
+      if (hipMemcpyAsync(offsets, &zero, 8, hipMemcpyHostToDevice, g->stream) != hipSuccess ||
+          hipStreamSynchronize(g->stream) != hipSuccess)
+        return CC_ERR_DEVICE;
+    } else {
+      offsets[0] = 0;
+    }
+    return CC_OK;
+  }
+  RunOut ro;
+  ro.enumerate = true;
+  ro.roots = rr;
+  if (dev_out) {
+    ro.out = OutDev{verts, (long long *)offsets, verts_cap, cycles_cap};
+  } else {
+    // host buffers: the range's exact sizes first (a counting run of the
+    // same roots), then the run writes device staging of those sizes
+    st = run_counts(g, rr);
+    if (st != CC_OK) return st;
+    int64_t c = 0, v = 0;
+    totals(&c, &v);
+    if (c > cycles_cap || v > verts_cap) {
+      *n_cycles = c;
+      *n_verts = v;
+      return CC_ERR_BUFFER_TOO_SMALL;
+    }
+    ro.host_verts = verts;
+    ro.host_offsets = offsets;
+    ro.out = OutDev{nullptr, nullptr, v, c};
+  }
+  st = run_device(g, ro);
+  if (st != CC_OK) return st;
+  totals(n_cycles, n_verts);
+  if (*n_cycles > cycles_cap || *n_verts > verts_cap) return CC_ERR_BUFFER_TOO_SMALL;
+  return CC_OK;
 }
 
 cc_status cc_labels(cc_graph *g, int32_t *labels) {
@@ -1372,7 +1467,7 @@ extern "C" cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr,
   // the head zeroes the control block, runs stage one and the leading
   // levels; every later step launch returns at once after the loop is over
   // (the host has no mapped word to stop early, so it queues all n - 2)
-  chk(cc_launch_head(W, false, gd, ctl, lb, out, -1, head_lds, nullptr, true, s));
+  chk(cc_launch_head(W, false, gd, ctl, lb, out, -1, head_lds, nullptr, true, RootRange{}, s));
   for (int launch = 1; launch < n - 1 && e == hipSuccess; ++launch)
     chk(cc_launch_step(W, false, gd, ctl, lb, out, launch, -1, maxc, true, bfs_blocks, nullptr,
                        s));

@@ -481,3 +481,78 @@ def test_inputs_written_on_a_side_stream(cc):
     with torch.cuda.stream(side):
         with cc.Graph(g.n, rp, ci) as h:
             assert np.array_equal(h.histogram(), want)
+
+
+@pytest.mark.parametrize("case", ["er40", "grid6x7", "k_4_5", "er100_w2", "four_word", "forced_dfs"])
+def test_root_ranges_equal_oracle_ranges(cc, case):
+    """A range of stage-one roots selects the same cycles, histogram and
+    expanded-path counts on the GPU as the oracle's run over that range
+    (the oracle numbers roots by u's original id, then x's, then y's)."""
+    import torch
+    kw = {}
+    if case == "er40":
+        g = gg.workload_er40()
+    elif case == "grid6x7":
+        g = gg.permute_random(gg.grid(6, 7), np.random.default_rng(67))
+    elif case == "k_4_5":
+        g = gg.permute_random(gg.complete_multipartite(4, 5, 3), np.random.default_rng(45))
+    elif case == "er100_w2":
+        g = gg.er_gnm(100, 150, np.random.default_rng(100))
+    elif case == "four_word":
+        g = four_word_union()
+    else:
+        g = gg.permute_random(gg.grid(5, 7), np.random.default_rng(75))
+        kw["force_dfs_level"] = 5
+    total = oracle.count_roots(g.n, g.row_ptr, g.col_idx)
+    rng = np.random.default_rng(7)
+    cuts = sorted(set([0, total] + [int(x) for x in rng.integers(0, total + 1, 4)]))
+    ranges = list(zip(cuts[:-1], cuts[1:])) + [(0, total), (total // 2, total // 2),
+                                                (total - 1, total)]
+    with cc.prepare(g, **kw) as h:
+        assert h.root_total() == total
+        for lo, hi in ranges:
+            ores = oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=True,
+                                           root_lo=lo, root_hi=hi)
+            assert np.array_equal(h.histogram_roots(lo, hi), ores.hist), (lo, hi)
+            assert np.array_equal(h.frontier(), ores.front), (lo, hi)
+            nc, nv = int(ores.hist.sum()), int((ores.hist * np.arange(g.n + 1)).sum())
+            v = torch.empty(max(nv, 1), dtype=torch.int32, device="cuda")
+            o = torch.empty(nc + 1, dtype=torch.int64, device="cuda")
+            assert h.enumerate_roots_into(lo, hi, v, o) == (nc, nv)
+            torch.cuda.synchronize()
+            assert_same_cycles(v.cpu().numpy()[:nv], o.cpu().numpy(), ores)
+        # the whole-graph histogram is still right after range runs
+        assert np.array_equal(h.histogram(), oracle_run(g, cycles=False).hist)
+
+
+@pytest.mark.parametrize("out_dev", [True, False])
+def test_pages_by_roots_partition_the_output(cc, out_dev):
+    """Pages of consecutive root ranges under a bound: every page fits, and
+    together they are exactly the oracle's cycle set (no cycle twice)."""
+    g = gg.permute_random(gg.grid(6, 8), np.random.default_rng(68))
+    ores = oracle_run(g)
+    nv_all = int((ores.hist * np.arange(g.n + 1)).sum())
+    # at least the output of the heaviest single root, else a fraction of all
+    total = oracle.count_roots(g.n, g.row_ptr, g.col_idx)
+    per_root = [oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=False,
+                                        root_lo=r, root_hi=r + 1).hist for r in range(total)]
+    heaviest = max(int((hr * np.arange(g.n + 1)).sum()) for hr in per_root)
+    limit = max(heaviest, nv_all // 7 + 1)
+    verts, offs, seen_hi = [], [0], 0
+    with cc.prepare(g, output_device=out_dev) as h:
+        for lo, hi, v, o in h.pages_by_roots(max_verts=limit):
+            assert lo == seen_hi and hi > lo
+            seen_hi = hi
+            v = v.cpu().numpy() if out_dev else np.asarray(v)
+            o = o.cpu().numpy() if out_dev else np.asarray(o)
+            assert o[-1] <= limit
+            verts.append(v[:o[-1]])
+            offs.extend((o[1:] + offs[-1]).tolist())
+        assert seen_hi == h.root_total()
+    a = canonical_groups(np.concatenate(verts), np.array(offs))
+    b = canonical_groups(*ores.cycles)
+    assert sorted(a) == sorted(b)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+        if a[k].shape[0] > 1:
+            assert not np.any(np.all(a[k][1:] == a[k][:-1], axis=1))
