@@ -86,6 +86,8 @@ struct CcCtl {
   unsigned long long dfs_fills;             // depth-first: steps that popped from device memory
   unsigned long long dfs_spills;            // depth-first: ring entries moved to device memory
   unsigned long long dfs_gatomics;          // depth-first: global histogram atomics
+  unsigned long long dfs_paths;             // depth-first, batches: paths expanded (batches
+                                            // keep no per-length counts)
   int levels_run;                           // breadth-first steps run
   int root_buf;                             // frontier buffer of the handed-over paths
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over

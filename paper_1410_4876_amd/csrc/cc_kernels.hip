@@ -1838,8 +1838,8 @@ struct DfsWaveLds {
   unsigned int M[kC];
   unsigned int G[BATCH ? kC : 1];
   unsigned long long rows[BATCH ? CC_ROWS(W) * W : 1];
-  unsigned int hc[BATCH ? CC_BATCH_MAXN + 2 : 1];  // that graph's histogram, this
-                                                   // wavefront's share not yet added
+  unsigned long long hc[BATCH ? CC_BATCH_MAXN + 2 : 1];  // that graph's histogram, this
+                                                         // wavefront's share not yet added
 };
 
 // A frame in registers (one per lane).
@@ -1862,7 +1862,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   __shared__ unsigned long long sNo[ENUM ? CC_ROWS(W) * W : 1];
   __shared__ int sPerm[BATCH ? 1 : CC_ROWS(W)];
   __shared__ unsigned long long sHist[BATCH ? 1 : CC_HSLOTS];
-  __shared__ unsigned long long sFront[CC_HSLOTS];
+  __shared__ unsigned long long sFront[BATCH ? 1 : CC_HSLOTS];
   __shared__ long long sCb[ENUM ? CC_HSLOTS : 1];
   __shared__ long long sVb[ENUM ? CC_HSLOTS : 1];
   __shared__ unsigned long long sPre[CC_SHARDS + 1];
@@ -1886,7 +1886,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
     for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) sHist[i] = 0ull;
   }
-  for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) sFront[i] = 0ull;
+  if (!BATCH)
+    for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) sFront[i] = 0ull;
   if (ENUM) {
     for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
     for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
@@ -1924,13 +1925,14 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   unsigned long long r_lo = 0, r_hi = 0;   // private range of handed-over paths
   unsigned long long batches = 0, donated = 0;
   unsigned long long lanes_used = 0, idle_clk = 0, fills = 0, spills = 0, gatomics = 0;
+  unsigned long long paths_cnt = 0;        // BATCH: paths expanded (no per-length counts)
   unsigned long long rng = 0x9E3779B97F4A7C15ull * (unsigned long long)(wid + 1);
   int until_check = 1 + wid % check_every;
   int cur_g = -1, cur_vo = 0, cur_n = 0;   // BATCH: the graph whose rows are in Q.rows
   bool roots_done = false;
   const unsigned long long clk_start = wall_clock64();
   if (BATCH)
-    for (int k = lane; k < CC_BATCH_MAXN + 2; k += CC_WAVE) Q.hc[k] = 0u;
+    for (int k = lane; k < CC_BATCH_MAXN + 2; k += CC_WAVE) Q.hc[k] = 0ull;
   if (lane == 0) atomicAdd(&ctl->busy, 1);
 
   auto ring_get = [&](unsigned i, Frame<W> &f) {
@@ -1999,10 +2001,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     if (BATCH && cur_g >= 0) {
       wave_lds_sync();
       for (int k = lane; k < cur_n + 2; k += CC_WAVE) {
-        const unsigned h = Q.hc[k];
+        const unsigned long long h = Q.hc[k];
         if (h) {
-          atomicAdd(&bt.hist[(size_t)cur_g * bt.hist_stride + k], (unsigned long long)h);
-          Q.hc[k] = 0u;
+          atomicAdd(&bt.hist[(size_t)cur_g * bt.hist_stride + k], h);
+          Q.hc[k] = 0ull;
         }
       }
       wave_lds_sync();
@@ -2254,11 +2256,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       int vo = 0;
       bool ring_rows = !BATCH;  // rows from LDS (sN, or the wavefront's cached graph)
       if (BATCH) {
-        if (valid && f.gid >= (unsigned)bt.n_graphs) {
-          dfs_corrupt(ctl, CC_DIAG_GRAPH, f.gid);
-          valid = false;
+        // (checks: one wavefront-uniform branch, taken only on bad state)
+        const bool bad_g = valid && f.gid >= (unsigned)bt.n_graphs;
+        if (wave_ballot(bad_g)) {
+          if (bad_g) dfs_corrupt(ctl, CC_DIAG_GRAPH, f.gid);
+          valid = valid && !bad_g;
         }
-        if (!valid) f.gid = 0;
+        f.gid = valid ? f.gid : 0u;
         const unsigned long long vm = wave_ballot(valid);
         if (vm) {
           const unsigned g0 = (unsigned)__builtin_amdgcn_readlane(
@@ -2283,19 +2287,19 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
           }
         }
       }
-      // the path to expand: <q, v> for the lowest v of E
-      int v = 0;
-      if (valid) {
-        if (!bany(f.E)) {
-          dfs_corrupt(ctl, CC_DIAG_PATH, f.m);
-          valid = false;
-        } else {
-          v = bpop_lowest(f.E);
-          const int pv1 = f.m & 0xffu, pt = (f.m >> 16) & 0x1ffu;
-          if (pv1 >= n_path || v >= n_path || pt < 3 || pt > n_path) {
-            dfs_corrupt(ctl, CC_DIAG_PATH, (f.m & 0xffff00ffu) | ((unsigned)v << 8));
-            valid = false;
-          }
+      // the path to expand: <q, v> for the lowest v of E (an empty E gives
+      // some v, and the frame is rejected below)
+      const bool has_e = bany(f.E);
+      int v = bpop_lowest(f.E);
+      {
+        const int pv1 = f.m & 0xffu, pt = (f.m >> 16) & 0x1ffu;
+        const bool bad = valid && (!has_e || pv1 >= n_path || (unsigned)v >= (unsigned)n_path ||
+                                   pt < 3 || pt > n_path);
+        if (wave_ballot(bad)) {
+          if (bad)
+            dfs_corrupt(ctl, CC_DIAG_PATH,
+                        has_e ? (f.m & 0xffff00ffu) | ((unsigned)(v & 0xff) << 8) : f.m);
+          valid = valid && !bad;
         }
       }
       if (!valid) {
@@ -2326,39 +2330,20 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         clos = bzero<W>();
         ext = bzero<W>();
       }
-      if (count_front) {
-        // paths expanded, per length: one LDS add per distinct length
-        unsigned long long act = wave_ballot(count_path);
-        while (act) {
-          const int t0 = __builtin_amdgcn_readlane(t, (int)(__ffsll((long long)act) - 1));
-          const unsigned long long same = act & wave_ballot(t == t0);
-          if (lane == 0) atomicAdd(&sFront[t0], (unsigned long long)__popcll(same));
-          act &= ~same;
-        }
+      if (BATCH) {
+        // batches count paths expanded in total only
+        paths_cnt += (unsigned)__popcll(wave_ballot(count_path));
+      } else if (count_front && count_path) {
+        // paths expanded, per length
+        atomicAdd(&sFront[t], 1ull);
       }
       // the expanded path's own original ids (enumerate)
       const Bits<W> Sp = ENUM ? bor(f.S, bsingle<W>(sPerm[v])) : bzero<W>();
       if (BATCH && ring_rows) {
-        // every frame is of graph cur_g: one add per distinct length to the
+        // every frame is of graph cur_g: each lane adds its closures to the
         // wavefront's LDS share of that graph's histogram
         const unsigned c = count_close ? (unsigned)bpop(clos) : 0u;
-        unsigned long long act = wave_ballot(c != 0u);
-        while (act) {
-          const int t0 = __builtin_amdgcn_readlane(t, (int)(__ffsll((long long)act) - 1));
-          const unsigned long long same = act & wave_ballot(t == t0);
-          const unsigned sum = wave_sum_u32_full((same >> lane) & 1ull ? c : 0u);
-          if (lane == 0) {
-            // 32-bit shares: one that would pass 2^31 goes to device memory
-            const unsigned long long nv = (unsigned long long)Q.hc[t0 + 1] + sum;
-            if (nv >= (1ull << 31)) {
-              atomicAdd(&bt.hist[(size_t)cur_g * bt.hist_stride + t0 + 1], nv);
-              Q.hc[t0 + 1] = 0u;
-            } else {
-              Q.hc[t0 + 1] = (unsigned)nv;
-            }
-          }
-          act &= ~same;
-        }
+        if (c) atomicAdd(&Q.hc[t + 1], (unsigned long long)c);
       } else if (BATCH) {
         // frames of several graphs: one global add per distinct (graph,
         // length) among the lanes
@@ -2403,9 +2388,12 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       // outside the path, and the path is inside X); anything longer would
       // mean corrupted state, so it is dropped and reported instead of
       // looping.
-      if (t >= n_path && bany(ext)) {
-        atomicOr(&ctl->status, CC_DEV_STACK_FULL);
-        ext = bzero<W>();
+      {
+        const bool too_long = t >= n_path && bany(ext);
+        if (wave_ballot(too_long)) {
+          if (lane == 0) atomicOr(&ctl->status, CC_DEV_STACK_FULL);
+          if (too_long) ext = bzero<W>();
+        }
       }
       // ---- push: what is left of E, then the new frame of the extensions
       // on top of it (at most 128 entries, so the ring always takes them
@@ -2562,13 +2550,14 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     atomicAdd(&ctl->dfs_fills, fills);
     atomicAdd(&ctl->dfs_spills, spills);
     atomicAdd(&ctl->dfs_gatomics, gatomics);
+    if (BATCH) atomicAdd(&ctl->dfs_paths, paths_cnt);
   }
   __syncthreads();
   unsigned long long *hdst = hist_out ? hist_out + (size_t)(blockIdx.x % CC_SHARDS) * hist_stride
                                       : nullptr;
   for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
     if (!BATCH && hdst && sHist[i]) atomicAdd(&hdst[i], sHist[i]);
-    if (count_front && sFront[i]) atomicAdd(&ctl->front[i], sFront[i]);
+    if (!BATCH && count_front && sFront[i]) atomicAdd(&ctl->front[i], sFront[i]);
   }
 }
 

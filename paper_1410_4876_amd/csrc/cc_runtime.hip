@@ -1297,7 +1297,7 @@ cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hi
       cycles += (int64_t)hh[(size_t)g * dstride + k];
     }
   }
-  for (int t = 0; t < CC_HSLOTS; ++t) paths += (int64_t)b->h_ctl->front[t];
+  paths = (int64_t)b->h_ctl->dfs_paths;
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
   b->info.cycles = cycles;
