@@ -80,14 +80,14 @@ struct CcCtl {
   unsigned long long root_cursor;           // depth-first: next unclaimed handed-over path
   unsigned long long dfs_batches;           // depth-first batches processed (diagnostic)
   unsigned long long donations;             // chunks given away on request (diagnostic)
-  unsigned long long dfs_lanes;             // depth-first: paths expanded over all steps
+  unsigned long long dfs_lanes;             // depth-first: paths expanded over all steps (the
+                                            // path total of a batch, which keeps no
+                                            // per-length counts)
   unsigned long long dfs_idle_clk;          // depth-first: wavefront clocks spent without work
   unsigned long long dfs_wave_clk;          // depth-first: wavefront clocks from start to exit
   unsigned long long dfs_fills;             // depth-first: steps that popped from device memory
   unsigned long long dfs_spills;            // depth-first: ring entries moved to device memory
   unsigned long long dfs_gatomics;          // depth-first: global histogram atomics
-  unsigned long long dfs_paths;             // depth-first, batches: paths expanded (batches
-                                            // keep no per-length counts)
   int levels_run;                           // breadth-first steps run
   int root_buf;                             // frontier buffer of the handed-over paths
   int mode;                                 // 0 = breadth-first, 1 = depth-first took over

@@ -133,7 +133,10 @@ __device__ __forceinline__ Bits<W> low_through(int u) {
 // ------------------------------------------------------- wave primitives
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ unsigned long long wave_ballot(bool p) { return __ballot(p); }
+// (the builtin takes the predicate as a lane mask, as compares produce it)
+__device__ __forceinline__ unsigned long long wave_ballot(bool p) {
+  return __builtin_amdgcn_ballot_w64(p);
+}
 
 // Number of set bits of `mask` at lanes below this one.
 __device__ __forceinline__ unsigned int lanes_below(unsigned long long mask) {
@@ -1824,19 +1827,18 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
 // the batch's initial triplets in bt.r0..bt.r1, padding slots marked
 // CC_NO_GRAPH.
 //
-// LDS per wavefront: the ring (X and E words, S words when enumerating, the
-// v1|t|root word, the graph id in batches) and, in batches, one graph's
-// rows.  The ring holds 256 entries when an entry has at most 24 bytes,
-// else 128; a step pushes at most 128.
+// LDS per wavefront: the ring (X and E words, S words when enumerating, and
+// one meta word: v1|t|root in the low half, the graph id of a batch in the
+// high half) and, in batches, one graph's rows.  The ring holds 256 entries
+// when an entry has at most 24 bytes, else 128; a step pushes at most 128.
 template <int W, bool ENUM, bool BATCH>
 struct DfsWaveLds {
-  static constexpr int kEntry = 16 * W + (ENUM ? 8 * W : 0) + 4 + (BATCH ? 4 : 0);
+  static constexpr int kEntry = 16 * W + (ENUM ? 8 * W : 0) + 8;
   static constexpr unsigned kC = kEntry <= 24 ? 256u : 128u;
   unsigned long long X[W * kC];
   unsigned long long E[W * kC];
   unsigned long long S[ENUM ? W * kC : 1];
-  unsigned int M[kC];
-  unsigned int G[BATCH ? kC : 1];
+  unsigned long long MG[kC];
   unsigned long long rows[BATCH ? CC_ROWS(W) * W : 1];
   unsigned long long hc[BATCH ? CC_BATCH_MAXN + 2 : 1];  // that graph's histogram, this
                                                          // wavefront's share not yet added
@@ -1923,11 +1925,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   unsigned lb = 0, lt = 0;                 // LDS ring entries [lb, lt), positions mod C
   unsigned bot = 0, top = 0;               // device-memory entries, below the ring
   unsigned long long r_lo = 0, r_hi = 0;   // private range of handed-over paths
-  unsigned long long batches = 0, donated = 0;
-  unsigned long long lanes_used = 0, idle_clk = 0, fills = 0, spills = 0, gatomics = 0;
-  unsigned long long paths_cnt = 0;        // BATCH: paths expanded (no per-length counts)
+  // diagnostics, 32-bit in the loop (added to the control block before
+  // any of them could pass 2^31, and at exit)
+  unsigned batches = 0, donated = 0, lanes_used = 0, fills = 0, spills = 0, gatomics = 0;
+  unsigned long long idle_clk = 0;
   unsigned long long rng = 0x9E3779B97F4A7C15ull * (unsigned long long)(wid + 1);
   int until_check = 1 + wid % check_every;
+  unsigned mail_seen = 0u;                 // lane 0: the request word, as loaded at the last check
   int cur_g = -1, cur_vo = 0, cur_n = 0;   // BATCH: the graph whose rows are in Q.rows
   bool roots_done = false;
   const unsigned long long clk_start = wall_clock64();
@@ -1945,8 +1949,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
 #pragma unroll
       for (int w = 0; w < W; ++w) f.S.w[w] = Q.S[w * C + i];
     }
-    f.m = Q.M[i];
-    if (BATCH) f.gid = Q.G[i];
+    const unsigned long long mg = Q.MG[i];
+    f.m = (unsigned)mg;
+    f.gid = BATCH ? (unsigned)(mg >> 32) : 0u;
   };
   auto ring_put = [&](unsigned i, const Frame<W> &f) {
 #pragma unroll
@@ -1958,8 +1963,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
 #pragma unroll
       for (int w = 0; w < W; ++w) Q.S[w * C + i] = f.S.w[w];
     }
-    Q.M[i] = f.m;
-    if (BATCH) Q.G[i] = f.gid;
+    Q.MG[i] = (unsigned long long)f.m | (BATCH ? (unsigned long long)f.gid << 32 : 0ull);
   };
   auto dev_get = [&](unsigned d, Frame<W> &f) {
 #pragma unroll
@@ -2009,6 +2013,18 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       }
       wave_lds_sync();
     }
+  };
+
+  auto flush_diag = [&]() {
+    if (lane == 0) {
+      atomicAdd(&ctl->dfs_batches, (unsigned long long)batches);
+      if (donated) atomicAdd(&ctl->donations, (unsigned long long)donated);
+      atomicAdd(&ctl->dfs_lanes, (unsigned long long)lanes_used);
+      if (fills) atomicAdd(&ctl->dfs_fills, (unsigned long long)fills);
+      if (spills) atomicAdd(&ctl->dfs_spills, (unsigned long long)spills);
+      if (gatomics) atomicAdd(&ctl->dfs_gatomics, (unsigned long long)gatomics);
+    }
+    batches = donated = lanes_used = fills = spills = gatomics = 0u;
   };
 
   // The frame of a handed-over path <q, vt> (a root): q's exclusion set and
@@ -2238,52 +2254,101 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     while (lt != lb && until_check > 0) {
       --until_check;
       ++batches;
+      // Keep a wavefront's worth of frames: top a short ring up from below
+      // its bottom, with the newest entries of device memory, else with
+      // paths of the private range of handed-over paths.  (Not in batches:
+      // their rings are nearly always full, and a top-up would mix graphs
+      // in one step.)
+      if (!BATCH && lt - lb < (unsigned)CC_CHUNK) {
+        if (top != bot) {
+          ++fills;
+          const unsigned m = min(top - bot, C / 2u - (lt - lb));
+          for (unsigned c0 = 0; c0 < m; c0 += CC_CHUNK) {
+            const unsigned j = c0 + (unsigned)lane;
+            if (j < m) {
+              Frame<W> f;
+              zero_frame(f);
+              dev_get(top - m + j, f);
+              ring_put((lb - m + j) & (C - 1u), f);
+            }
+          }
+          lb -= m;
+          top -= m;
+          if (top == bot) top = bot = 0;
+          wave_lds_sync();
+        } else if (r_lo < r_hi) {
+          const unsigned long long kr =
+              min(r_hi - r_lo, (unsigned long long)(CC_CHUNK - (lt - lb)));
+          Frame<W> f;
+          zero_frame(f);
+          bool ok = false;
+          if ((unsigned long long)lane < kr) ok = root_frame(r_lo + lane, f);
+          const unsigned long long mk = wave_ballot(ok);
+          const unsigned cnt = (unsigned)__popcll(mk);
+          if (ok) ring_put((lb - cnt + lanes_below(mk)) & (C - 1u), f);
+          lb -= cnt;
+          r_lo += kr;
+          wave_lds_sync();
+        }
+      }
       // Pop up to 64 frames from the top.  In the worst case every entry
       // left in the ring and both new frames of every popped one end up in
       // device memory: keep that within its capacity.
       unsigned kk = min(lt - lb, (unsigned)CC_CHUNK);
       while (kk > 1 && (top - bot) + (lt - lb) + kk > cap) kk >>= 1;
       const unsigned start = lt - kk;
-      bool valid = (unsigned)lane < kk;
+      const bool in_step = (unsigned)lane < kk;
+      bool valid = in_step;
+      // every lane reads a ring slot; those past the popped ones hold stale
+      // entries that nothing below uses (valid is false for them)
       Frame<W> f;
-      zero_frame(f);
-      if (valid) ring_get((start + (unsigned)lane) & (C - 1u), f);
+      ring_get((start + (unsigned)lane) & (C - 1u), f);
       lt = start;
       lanes_used += kk;
       // Consistency checks: every index below that comes from a frame
       // stays inside its graph; a frame that fails is reported and dropped.
+      // (Each check is one wavefront-uniform branch, taken only on bad
+      // state; predicates are combined without short-circuit branches.)
       int n_path = n;  // vertices of this frame's graph
       int vo = 0;
       bool ring_rows = !BATCH;  // rows from LDS (sN, or the wavefront's cached graph)
       if (BATCH) {
-        // (checks: one wavefront-uniform branch, taken only on bad state)
-        const bool bad_g = valid && f.gid >= (unsigned)bt.n_graphs;
-        if (wave_ballot(bad_g)) {
-          if (bad_g) dfs_corrupt(ctl, CC_DIAG_GRAPH, f.gid);
-          valid = valid && !bad_g;
-        }
-        f.gid = valid ? f.gid : 0u;
-        const unsigned long long vm = wave_ballot(valid);
-        if (vm) {
-          const unsigned g0 = (unsigned)__builtin_amdgcn_readlane(
-              (int)f.gid, (int)(__ffsll((long long)vm) - 1));
-          if (wave_ballot(valid && f.gid != g0) == 0ull) {
-            // every frame of the step belongs to graph g0: rows from LDS
-            if ((int)g0 != cur_g) {
-              flush_hc();
-              cur_vo = bt.vtx_off[g0];
-              cur_n = min(bt.vtx_off[g0 + 1] - cur_vo, CC_ROWS(W));
-              if (cur_n < 0) cur_n = 0;
-              for (int i = lane; i < cur_n * W; i += CC_WAVE)
-                Q.rows[i] = bt.adj[(size_t)cur_vo * W + i];
-              cur_g = (int)g0;
+        // usual case: every frame of the step is of the graph whose rows the
+        // wavefront holds (lane 0 always has a frame)
+        const unsigned g0 = uni_u32(f.gid);
+        if ((int)g0 == cur_g && wave_ballot(in_step & (f.gid != g0)) == 0ull) {
+          ring_rows = true;
+          vo = cur_vo;
+          n_path = cur_n;
+        } else {
+          const bool bad_g = valid & (f.gid >= (unsigned)bt.n_graphs);
+          if (wave_ballot(bad_g)) {
+            if (bad_g) dfs_corrupt(ctl, CC_DIAG_GRAPH, f.gid);
+            valid = valid & !bad_g;
+          }
+          f.gid = valid ? f.gid : 0u;
+          const unsigned long long vm = wave_ballot(valid);
+          if (vm) {
+            const unsigned g1 = (unsigned)__builtin_amdgcn_readlane(
+                (int)f.gid, (int)(__ffsll((long long)vm) - 1));
+            if (wave_ballot(valid & (f.gid != g1)) == 0ull) {
+              // one graph: its rows into LDS
+              if ((int)g1 != cur_g) {
+                flush_hc();
+                cur_vo = bt.vtx_off[g1];
+                cur_n = min(bt.vtx_off[g1 + 1] - cur_vo, CC_ROWS(W));
+                if (cur_n < 0) cur_n = 0;
+                for (int i = lane; i < cur_n * W; i += CC_WAVE)
+                  Q.rows[i] = bt.adj[(size_t)cur_vo * W + i];
+                cur_g = (int)g1;
+              }
+              ring_rows = true;
+              vo = cur_vo;
+              n_path = cur_n;
+            } else {
+              vo = bt.vtx_off[f.gid];
+              n_path = bt.vtx_off[f.gid + 1] - vo;
             }
-            ring_rows = true;
-            vo = cur_vo;
-            n_path = cur_n;
-          } else {
-            vo = bt.vtx_off[f.gid];
-            n_path = bt.vtx_off[f.gid + 1] - vo;
           }
         }
       }
@@ -2293,13 +2358,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       int v = bpop_lowest(f.E);
       {
         const int pv1 = f.m & 0xffu, pt = (f.m >> 16) & 0x1ffu;
-        const bool bad = valid && (!has_e || pv1 >= n_path || (unsigned)v >= (unsigned)n_path ||
-                                   pt < 3 || pt > n_path);
+        const bool bad = valid & (!has_e | (pv1 >= n_path) | ((unsigned)v >= (unsigned)n_path) |
+                                  (pt < 3) | (pt > n_path));
         if (wave_ballot(bad)) {
           if (bad)
             dfs_corrupt(ctl, CC_DIAG_PATH,
                         has_e ? (f.m & 0xffff00ffu) | ((unsigned)(v & 0xff) << 8) : f.m);
-          valid = valid && !bad;
+          valid = valid & !bad;
         }
       }
       if (!valid) {
@@ -2330,10 +2395,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         clos = bzero<W>();
         ext = bzero<W>();
       }
-      if (BATCH) {
-        // batches count paths expanded in total only
-        paths_cnt += (unsigned)__popcll(wave_ballot(count_path));
-      } else if (count_front && count_path) {
+      if (!BATCH && count_front && count_path) {
         // paths expanded, per length
         atomicAdd(&sFront[t], 1ull);
       }
@@ -2466,14 +2528,18 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     // ---- every few steps: publish what we could give, answer a request
     if (until_check <= 0) {
       until_check = check_every;
+      if ((batches | lanes_used | spills) >= (1u << 31)) flush_diag();
       const unsigned long long range_left = r_hi - r_lo, dev_left = top - bot;
       const unsigned long long stack_left = dev_left + (unsigned long long)(lt - lb);
       const unsigned long long left = range_left + stack_left;
+      // The request word was loaded at the previous check, so a check never
+      // waits for memory unless there is a request to take.
       unsigned req = 0;
+      const unsigned r = (unsigned)__builtin_amdgcn_readlane((int)mail_seen, 0);
       if (lane == 0) {
         st_coh(&my_mail[3], (unsigned)min(left, 0x7fffffffull));
-        const unsigned r = ld_coh(&my_mail[0]);
         if (r != 0u && r != CC_MAIL_CLOSED && atomicCAS(&my_mail[0], r, 0u) == r) req = r;
+        mail_seen = ld_coh(&my_mail[0]);
       }
       req = (unsigned)__builtin_amdgcn_readlane((int)req, 0);
       if (req != 0u && req - 1u >= (unsigned)nwaves) {
@@ -2542,16 +2608,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       if (r - 1u < (unsigned)nwaves) st_coh(&wk.mail[(size_t)(r - 1) * CC_MAIL + 1], 2u);
       else dfs_corrupt(ctl, CC_DIAG_REQUESTER, r);
     }
-    atomicAdd(&ctl->dfs_batches, batches);
-    if (donated) atomicAdd(&ctl->donations, donated);
-    atomicAdd(&ctl->dfs_lanes, lanes_used);
     atomicAdd(&ctl->dfs_idle_clk, idle_clk);
     atomicAdd(&ctl->dfs_wave_clk, wall_clock64() - clk_start);
-    atomicAdd(&ctl->dfs_fills, fills);
-    atomicAdd(&ctl->dfs_spills, spills);
-    atomicAdd(&ctl->dfs_gatomics, gatomics);
-    if (BATCH) atomicAdd(&ctl->dfs_paths, paths_cnt);
   }
+  flush_diag();
   __syncthreads();
   unsigned long long *hdst = hist_out ? hist_out + (size_t)(blockIdx.x % CC_SHARDS) * hist_stride
                                       : nullptr;

@@ -111,6 +111,99 @@ bool pool_give(const HandleRes &r) {
   return true;
 }
 
+// Batches recycle theirs the same way: the device blob (graph data and
+// control block), pinned staging for every host copy of a pass, the pinned
+// control-block readback and the events.  A batch takes the smallest free
+// set on its device that is large enough; a set that is too small is freed
+// and a larger one allocated.
+struct BatchRes {
+  int device = -1;
+  void *d_blob = nullptr;
+  size_t blob_bytes = 0;
+  char *h_stage = nullptr;
+  size_t stage_bytes = 0;
+  void *h_ctl = nullptr;
+  hipEvent_t ev[6] = {};
+};
+std::mutex g_bpool_mu;
+BatchRes g_bpool[16];
+int g_bpool_n = 0;
+
+void batch_res_free(BatchRes &r) {
+  (void)hipSetDevice(r.device);
+  if (r.d_blob) (void)hipFree(r.d_blob);
+  if (r.h_stage) (void)hipHostFree(r.h_stage);
+  if (r.h_ctl) (void)hipHostFree(r.h_ctl);
+  for (hipEvent_t e : r.ev)
+    if (e) (void)hipEventDestroy(e);
+  r = BatchRes{};
+}
+
+// A set on `device` (the current device) with at least `stage` pinned
+// bytes; its blob is grown later by batch_res_blob.
+bool batch_res_take(int device, size_t stage, BatchRes *out) {
+  BatchRes r;
+  {
+    std::lock_guard<std::mutex> lk(g_bpool_mu);
+    int best = -1, any = -1;
+    for (int i = 0; i < g_bpool_n; ++i) {
+      if (g_bpool[i].device != device) continue;
+      any = i;
+      if (g_bpool[i].stage_bytes >= stage &&
+          (best < 0 || g_bpool[i].stage_bytes < g_bpool[best].stage_bytes))
+        best = i;
+    }
+    const int pick = best >= 0 ? best : any;
+    if (pick >= 0) {
+      r = g_bpool[pick];
+      g_bpool[pick] = g_bpool[--g_bpool_n];
+    }
+  }
+  r.device = device;
+  bool ok = true;
+  if (r.stage_bytes < stage) {
+    if (r.h_stage) (void)hipHostFree(r.h_stage);
+    r.h_stage = nullptr;
+    r.stage_bytes = 0;
+    ok = hipHostMalloc((void **)&r.h_stage, stage, hipHostMallocDefault) == hipSuccess;
+    if (ok) r.stage_bytes = stage;
+  }
+  if (ok && !r.h_ctl) ok = hipHostMalloc(&r.h_ctl, sizeof(CcCtl), hipHostMallocDefault) == hipSuccess;
+  for (hipEvent_t &e : r.ev)
+    if (ok && !e) ok = hipEventCreate(&e) == hipSuccess;
+  if (!ok) {
+    batch_res_free(r);
+    return false;
+  }
+  *out = r;
+  return true;
+}
+
+// Grows the set's device blob to at least `bytes` (a device-wide
+// synchronisation only when it grows).
+bool batch_res_blob(BatchRes &r, size_t bytes) {
+  if (r.blob_bytes >= bytes) return true;
+  if (r.d_blob) (void)hipFree(r.d_blob);
+  r.d_blob = nullptr;
+  r.blob_bytes = 0;
+  if (hipMalloc(&r.d_blob, bytes) != hipSuccess) return false;
+  r.blob_bytes = bytes;
+  return true;
+}
+
+void batch_res_give(BatchRes &r) {
+  if (r.device < 0) return;
+  {
+    std::lock_guard<std::mutex> lk(g_bpool_mu);
+    if (g_bpool_n < 16) {
+      g_bpool[g_bpool_n++] = r;
+      r = BatchRes{};
+      return;
+    }
+  }
+  batch_res_free(r);
+}
+
 }  // namespace
 
 struct cc_graph {
@@ -226,7 +319,7 @@ int carve_dfs(char *base, size_t bytes, int W, bool en, int waves, DfsWork *wk,
   d.stackM = (unsigned int *)take((size_t)nw * cap_w * 4);
   if (batch) d.stackG = (unsigned int *)take((size_t)nw * cap_w * 4);
   d.nwaves = nw;
-  d.donate_check = 16;
+  d.donate_check = 32;
   d.donate_min = 2 * CC_CHUNK;
   *wk = d;
   return nw;
@@ -1023,7 +1116,15 @@ struct cc_batch {
   int max_deg = 0;
   std::vector<int32_t> vtx_off;        // host copy
   std::vector<long long> root_off;     // host copy, [G+1]
+  BatchRes res;                        // recycled device blob, pinned staging, events
   void *d_blob = nullptr;              // vtx_off | root_off | adj | adj_orig | perm | label | status | bound | ctl
+  // pinned staging (in res.h_stage) for the host copies of a pass
+  int32_t *s_off = nullptr;            // [G+1] vertex offsets
+  int32_t *s_nnz = nullptr;            // adjacency entries of a device CSR
+  unsigned int *s_stat = nullptr;      // [G] ingest status words
+  long long *s_bound = nullptr;        // [G] sum over vertices of C(deg, 2)
+  long long *s_root = nullptr;         // [G+1] root slot offsets
+  unsigned long long *s_hist = nullptr;  // [G * (max_n + 2)] histograms
   int *d_vtx_off = nullptr;
   long long *d_root_off = nullptr;
   unsigned long long *d_adj = nullptr;
@@ -1044,15 +1145,9 @@ extern "C" {
 void cc_release_batch(cc_batch *b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
-  if (b->d_blob) {
-    (void)hipStreamSynchronize(b->stream);
-    (void)hipFree(b->d_blob);
-  }
-  if (b->h_ctl) (void)hipHostFree(b->h_ctl);
-  if (b->ev0) (void)hipEventDestroy(b->ev0);
-  if (b->ev1) (void)hipEventDestroy(b->ev1);
-  for (hipEvent_t ev : b->evp)
-    if (ev) (void)hipEventDestroy(ev);
+  // the stream's work on the blob and staging ends before they are reused
+  if (b->res.device >= 0) (void)hipStreamSynchronize(b->stream);
+  batch_res_give(b->res);
   delete b;
 }
 
@@ -1072,34 +1167,6 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   DeviceInfo di;
   cc_status st = device_info(dev, &di);
   if (st != CC_OK) return st;
-  // sizes and offsets are needed on the host
-  std::vector<int32_t> off((size_t)n_graphs + 1);
-  int32_t nnz = 0;
-  if (flags & CC_INPUT_DEVICE) {
-    if (hipMemcpy(off.data(), graph_vtx_off, off.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
-      return CC_ERR_DEVICE;
-  } else {
-    std::memcpy(off.data(), graph_vtx_off, off.size() * 4);
-  }
-  if (off[0] != 0) return CC_ERR_INVALID_ARG;
-  int max_n = 0;
-  for (int g = 0; g < n_graphs; ++g) {
-    const int ng = off[g + 1] - off[g];
-    if (ng < 0) return CC_ERR_INVALID_ARG;
-    if (ng > CC_BATCH_MAXN) return CC_ERR_TOO_LARGE;
-    max_n = std::max(max_n, ng);
-  }
-  const int32_t N = off[n_graphs];
-  if (n_graphs > 0) {
-    if (flags & CC_INPUT_DEVICE) {
-      if (hipMemcpy(&nnz, row_ptr + N, 4, hipMemcpyDeviceToHost) != hipSuccess) return CC_ERR_DEVICE;
-    } else {
-      nnz = row_ptr[N];
-      if (row_ptr[0] != 0) return CC_ERR_NOT_SIMPLE;
-    }
-    if (nnz < 0) return CC_ERR_NOT_SIMPLE;
-    if (nnz > 0 && !col_idx) return CC_ERR_INVALID_ARG;
-  }
   cc_batch *b = new cc_batch();
   auto fail = [&](cc_status s2) {
     cc_release_batch(b);
@@ -1110,18 +1177,72 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   if (opt) b->opt = *opt;
   b->stream = (hipStream_t)b->opt.stream;
   b->G = n_graphs;
+  hipStream_t s = b->stream;
+  // pinned staging for every host copy of the batch's passes (histograms
+  // at the largest batch graph size)
+  const size_t Gp = (size_t)n_graphs + 1;
+  const size_t o_off = 0, o_nnz = align_up(Gp * 4, 256), o_stat = o_nnz + 256;
+  const size_t o_bound = o_stat + align_up(Gp * 4, 256);
+  const size_t o_root = o_bound + align_up(Gp * 8, 256);
+  const size_t o_hist = o_root + align_up(Gp * 8, 256);
+  const size_t stage = o_hist + align_up(Gp * (CC_BATCH_MAXN + 2) * 8, 256);
+  if (!batch_res_take(dev, stage, &b->res)) return fail(CC_ERR_OUT_OF_MEMORY);
+  char *hs = b->res.h_stage;
+  b->s_off = (int32_t *)(hs + o_off);
+  b->s_nnz = (int32_t *)(hs + o_nnz);
+  b->s_stat = (unsigned int *)(hs + o_stat);
+  b->s_bound = (long long *)(hs + o_bound);
+  b->s_root = (long long *)(hs + o_root);
+  b->s_hist = (unsigned long long *)(hs + o_hist);
+  b->h_ctl = (CcCtl *)b->res.h_ctl;
+  b->ev0 = b->res.ev[0];
+  b->ev1 = b->res.ev[1];
+  for (int i = 0; i < 4; ++i) b->evp[i] = b->res.ev[2 + i];
+  // sizes and offsets are needed on the host (a device CSR is read on the
+  // caller's stream, after whatever wrote it)
+  int32_t *off = b->s_off;
+  int32_t nnz = 0;
+  if (flags & CC_INPUT_DEVICE) {
+    if (hipMemcpyAsync(off, graph_vtx_off, Gp * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(CC_ERR_DEVICE);
+  } else {
+    std::memcpy(off, graph_vtx_off, Gp * 4);
+  }
+  if (off[0] != 0) return fail(CC_ERR_INVALID_ARG);
+  int max_n = 0;
+  for (int g = 0; g < n_graphs; ++g) {
+    const int ng = off[g + 1] - off[g];
+    if (ng < 0) return fail(CC_ERR_INVALID_ARG);
+    if (ng > CC_BATCH_MAXN) return fail(CC_ERR_TOO_LARGE);
+    max_n = std::max(max_n, ng);
+  }
+  const int32_t N = off[n_graphs];
+  if (n_graphs > 0) {
+    if (flags & CC_INPUT_DEVICE) {
+      if (hipMemcpyAsync(b->s_nnz, row_ptr + N, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(CC_ERR_DEVICE);
+      nnz = *b->s_nnz;
+    } else {
+      nnz = row_ptr[N];
+      if (row_ptr[0] != 0) return fail(CC_ERR_NOT_SIMPLE);
+    }
+    if (nnz < 0) return fail(CC_ERR_NOT_SIMPLE);
+    if (nnz > 0 && !col_idx) return fail(CC_ERR_INVALID_ARG);
+  }
   b->N = N;
   b->W = max_n <= 64 ? 1 : 2;
   b->max_n = max_n;
-  b->vtx_off = off;
+  b->vtx_off.assign(off, off + Gp);
   const size_t Np = (size_t)std::max(N, 1);
-  const size_t Gp = (size_t)n_graphs + 1;
   const size_t sz_off = align_up(Gp * 4, 256), sz_roff = align_up(Gp * 8, 256);
   const size_t sz_adj = align_up(Np * b->W * 8, 256), sz_vec = align_up(Np * 4, 256);
   const size_t sz_st = align_up(Gp * 4, 256), sz_bd = align_up(Gp * 8, 256);
   const size_t blob = sz_off + sz_roff + 2 * sz_adj + 2 * sz_vec + sz_st + sz_bd +
                       align_up(sizeof(CcCtl), 256);
-  if (hipMalloc(&b->d_blob, blob) != hipSuccess) return fail(CC_ERR_OUT_OF_MEMORY);
+  if (!batch_res_blob(b->res, blob)) return fail(CC_ERR_OUT_OF_MEMORY);
+  b->d_blob = b->res.d_blob;
   char *p = (char *)b->d_blob;
   b->d_vtx_off = (int *)p; p += sz_off;
   b->d_root_off = (long long *)p; p += sz_roff;
@@ -1132,19 +1253,14 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
   b->d_status = (unsigned int *)p; p += sz_st;
   b->d_bound = (long long *)p; p += sz_bd;
   b->d_ctl = (CcCtl *)p;
-  if (hipHostMalloc((void **)&b->h_ctl, sizeof(CcCtl), hipHostMallocDefault) != hipSuccess)
-    return fail(CC_ERR_OUT_OF_MEMORY);
-  if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
-    return fail(CC_ERR_DEVICE);
   b->root_off.assign(Gp, 0);
   if (n_graphs == 0) {
     *out = b;
     return CC_OK;
   }
-  hipStream_t s = b->stream;
   const int *d_rp = row_ptr, *d_ci = col_idx;
   void *tmp = nullptr;
-  if (hipMemcpyAsync(b->d_vtx_off, off.data(), Gp * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+  if (hipMemcpyAsync(b->d_vtx_off, off, Gp * 4, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(CC_ERR_DEVICE);
   if (!(flags & CC_INPUT_DEVICE)) {
     const size_t rb = align_up(((size_t)N + 1) * 4, 256);
@@ -1160,26 +1276,28 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
     d_rp = (const int *)tmp;
     d_ci = (const int *)((char *)tmp + rb);
   }
-  std::vector<unsigned int> stat((size_t)n_graphs);
-  std::vector<long long> bound((size_t)n_graphs);
   hipError_t e = cc_launch_ingest(b->W, n_graphs, b->d_vtx_off, 0, d_rp, d_ci, b->d_adj,
                                   b->d_adj_orig, b->d_perm, b->d_label, b->d_status, b->d_bound,
                                   nullptr, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(stat.data(), b->d_status, (size_t)n_graphs * 4, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(b->s_stat, b->d_status, (size_t)n_graphs * 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(bound.data(), b->d_bound, (size_t)n_graphs * 8, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(b->s_bound, b->d_bound, (size_t)n_graphs * 8, hipMemcpyDeviceToHost, s);
   if (tmp) (void)hipFreeAsync(tmp, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(hip_err(e));
+  long long *root = b->s_root;
+  root[0] = 0;
   for (int g = 0; g < n_graphs; ++g) {
-    if ((stat[g] & 0xffu) != 0u || !(stat[g] & 0x100u)) return fail(CC_ERR_NOT_SIMPLE);
-    b->max_deg = std::max(b->max_deg, (int)(stat[g] >> 16));
-    b->root_off[g + 1] = b->root_off[g] + bound[g];
+    const unsigned int stg = b->s_stat[g];
+    if ((stg & 0xffu) != 0u || !(stg & 0x100u)) return fail(CC_ERR_NOT_SIMPLE);
+    b->max_deg = std::max(b->max_deg, (int)(stg >> 16));
+    root[g + 1] = root[g] + b->s_bound[g];
   }
-  if (hipMemcpyAsync(b->d_root_off, b->root_off.data(), Gp * 8, hipMemcpyHostToDevice, s) !=
-          hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
+  b->root_off.assign(root, root + Gp);
+  // (ordered before every later use of the root offsets on this stream;
+  // the staging stays untouched until the batch is released)
+  if (hipMemcpyAsync(b->d_root_off, root, Gp * 8, hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(CC_ERR_DEVICE);
   *out = b;
   return CC_OK;
@@ -1280,8 +1398,8 @@ cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hi
     }
   }
   chk(hipEventRecord(b->ev1, s));
-  std::vector<unsigned long long> hh((size_t)G * dstride);
-  chk(hipMemcpyAsync(hh.data(), bt.hist, hh.size() * 8, hipMemcpyDeviceToHost, s));
+  unsigned long long *hh = b->s_hist;  // pinned, G * dstride words
+  chk(hipMemcpyAsync(hh, bt.hist, (size_t)G * dstride * 8, hipMemcpyDeviceToHost, s));
   const size_t tail = offsetof(CcCtl, hist);
   chk(hipMemcpyAsync((char *)b->h_ctl + tail, (char *)ctl + tail, sizeof(CcCtl) - tail,
                      hipMemcpyDeviceToHost, s));
@@ -1297,7 +1415,7 @@ cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hi
       cycles += (int64_t)hh[(size_t)g * dstride + k];
     }
   }
-  paths = (int64_t)b->h_ctl->dfs_paths;
+  paths = (int64_t)b->h_ctl->dfs_lanes;
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, b->ev0, b->ev1);
   b->info.cycles = cycles;
