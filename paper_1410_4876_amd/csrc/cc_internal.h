@@ -51,7 +51,7 @@ struct StepState {
   int slen1;
   int prev_two;  // the previous step expanded two levels
   int done;      // the loop is over (nothing left, or handed over)
-  int pad;
+  int step;      // the step this state is for
 };
 
 // Control block of one run in device memory.  Zeroed by a kernel at the start
@@ -67,7 +67,8 @@ struct CcCtl {
   unsigned long long len_cursor[CC_HSLOTS]; // enumerate: depth-first slot allocator per length
   unsigned long long len_cbase[CC_HSLOTS];  // enumerate: first cycle index of each length
   unsigned long long len_vbase[CC_HSLOTS];  // enumerate: first vertex offset of each length
-  StepState ss[CC_HSLOTS];                  // step s reads ss[s]; its block 0 writes ss[s + 1]
+  StepState ss[CC_HSLOTS];                  // step launch i reads ss[i]; its block 0 writes
+                                            // ss[i + 1] (launch 0 is the head kernel)
   long long root_base[CC_MAXN];             // root range runs: index of the first stage-one
                                             // root of each vertex (by label)
   int orig_label[CC_MAXN];                  // root range runs: label of each original id

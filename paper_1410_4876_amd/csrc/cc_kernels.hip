@@ -634,7 +634,8 @@ __device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, 
     S.fbuf = 1;
     S.spair = 0;
     S.slen0 = ENUM ? 3 : 0;
-    ctl->ss[0] = S;
+    S.step = 0;
+    ctl->ss[1] = S;  // for step launch 1, unless the head kernel goes on
   }
   __syncthreads();
 }
@@ -881,7 +882,7 @@ __device__ __forceinline__ StepState load_state(StepState *p) {
   S.slen1 = ld_relaxed(&p->slen1);
   S.prev_two = ld_relaxed(&p->prev_two);
   S.done = ld_relaxed(&p->done);
-  S.pad = ld_relaxed(&p->pad);
+  S.step = ld_relaxed(&p->step);
   return S;
 }
 
@@ -890,8 +891,8 @@ __device__ __forceinline__ StepState load_state(StepState *p) {
 // graph is loaded into LDS here, together with the counters.
 template <int W, bool ENUM>
 __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
-                         int step, const StepState &S, int forced_level, int maxc,
-                         bool allow_two, LevelLds<W, ENUM> &L, bool lds_ready) {
+                         int step, const StepState &S, StepState *next, int forced_level,
+                         int maxc, bool allow_two, LevelLds<W, ENUM> &L, bool lds_ready) {
   constexpr int IPT = W == 4 ? CC_LEVEL_IPT_W4 : CC_LEVEL_IPT;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -995,20 +996,21 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   }
   StepState N = S;
   N.done = 1;
+  N.step = step + 1;
   if (sw_level) {
     if (blockIdx.x == 0 && tid == 0) {
       ctl->skip = sw_skip;
       ctl->switch_level = sw_level;
       ctl->bfs_max_len = sw_max;
       ctl->root_buf = sw_buf;
-      ctl->ss[step + 1] = N;
+      *next = N;
       __threadfence();
       st_release(&ctl->mode, 1);
     }
     return CC_LEVEL_SWITCH;
   }
   if (cnt == 0) {
-    if (blockIdx.x == 0 && tid == 0) ctl->ss[step + 1] = N;
+    if (blockIdx.x == 0 && tid == 0) *next = N;
     return CC_LEVEL_EMPTY;
   }
 
@@ -1036,7 +1038,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
     N.slen1 = (ENUM && two) ? t + 2 : 0;
     N.prev_two = two ? 1 : 0;
     N.done = 0;
-    ctl->ss[step + 1] = N;
+    *next = N;
     ctl->front[t] = cnt;
     atomicMax(&ctl->peak, cnt);
   }
@@ -1320,9 +1322,9 @@ __device__ void finalize_body(CcCtl *ctl, const OutDev &out, int n, bool enumera
 // The head stops at the first level whose paths do not fit (or at the
 // forced depth-first level): it writes that level's paths to frontier
 // buffer 0, dealt round-robin over the shards, with the counters, the
-// cumulative output offsets and the state the step launches need, and
-// records where they start (launch_step[1]).  If the frontier empties
-// first, the loop is over (launch_step[1] = 0).  Launch 0 for host_done.
+// cumulative output offsets and the state of step launch 1 (ss[1]).  If
+// the frontier empties first, the loop is over (ss[1] says done).  Launch 0
+// for host_done.
 template <int W, bool ENUM>
 struct HeadLds {
   unsigned long long N[CC_ROWS(W) * W];
@@ -1712,7 +1714,8 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         S.slen1 = 0;
         S.prev_two = 0;
         S.done = 0;
-        ctl->ss[steps] = S;
+        S.step = steps;
+        ctl->ss[1] = S;
         if (ENUM) {
           ctl->cum_c[t] = (unsigned long long)cum_c;
           ctl->cum_v[t] = (unsigned long long)cum_v;
@@ -1724,6 +1727,11 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
       for (int k = 3; k < t; ++k) pk = max(pk, L.Front[k]);
       ctl->peak = max(pk, (unsigned long long)cnt);
       ctl->launch_step[1] = over ? 0 : steps + 1;
+      if (over) {
+        StepState S{};
+        S.done = 1;
+        ctl->ss[1] = S;
+      }
       ctl->levels_run = steps;
       ctl->head_steps = steps;
       if (over && host_done) st_system(host_done, 1u);
@@ -1736,8 +1744,9 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
   }
 }
 
-// One launch per step (launch >= 1, after k_head): it runs step
-// launch_step[launch] - 1 and records the next launch's.  host_done (pinned
+// One launch per step (launch >= 1, after k_head): it runs the step whose
+// state is in ss[launch] and writes the next launch's state (and, for the
+// host's per-level timing, launch_step[launch + 1]).  host_done (pinned
 // host memory, may be NULL): host_done[1] = launch + 1 when the launch
 // starts, host_done[0] = launch + 1 when the loop is over, so the host
 // stops launching and keeps few launches queued.
@@ -1749,14 +1758,24 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
   __shared__ LevelLds<W, ENUM> L;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (host_done && lead) st_system(host_done + 1, (unsigned)launch + 1u);
-  const int step = ld_relaxed(&ctl->launch_step[launch]) - 1;
-  if (ld_relaxed(&ctl->mode) != 0 || step < 0 || step >= g.n - 2) {
-    // handed over, or queued after the loop ended
-    if (host_done && lead) st_system(host_done, (unsigned)launch + 1u);
+  // this launch's state, written by the launch before it (one load: the
+  // step index travels in the state)
+  const StepState S = load_state(&ctl->ss[launch]);
+  const int step = S.step;
+  StepState *next = &ctl->ss[launch + 1 < CC_HSLOTS ? launch + 1 : launch];
+  if (ld_relaxed(&ctl->mode) != 0 || S.done || step < 0 || step >= g.n - 2) {
+    // handed over, or queued after the loop ended: so is the next launch
+    if (lead) {
+      StepState D{};
+      D.done = 1;
+      *next = D;
+      if (launch + 1 < CC_HSLOTS) ctl->launch_step[launch + 1] = 0;
+      if (host_done) st_system(host_done, (unsigned)launch + 1u);
+    }
     return;
   }
-  const int r = step_body<W, ENUM>(g, ctl, B, out, step, load_state(&ctl->ss[step]),
-                                   forced_level, maxc, allow_two != 0, L, false);
+  const int r = step_body<W, ENUM>(g, ctl, B, out, step, S, next, forced_level, maxc,
+                                   allow_two != 0, L, false);
   // The step that finds the frontier empty ends the run: block 0 (r is the
   // same for all its threads) also writes the final histogram and closing
   // offset, and host_done[3] tells the host to launch no finalize kernel.
@@ -1822,10 +1841,12 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
 // wavefront keeps in LDS the adjacency rows of the graph its last
 // single-graph step came from (one coalesced reload when a step's frames
 // all belong to another graph; a step that mixes graphs reads its rows from
-// device memory); closures go straight to the per-graph histograms (one
-// atomic per distinct (graph, length) in a step); the handed-over paths are
-// the batch's initial triplets in bt.r0..bt.r1, padding slots marked
-// CC_NO_GRAPH.
+// device memory) and its share of that graph's histogram, which each lane
+// adds its closures to and which goes to device memory when the wavefront
+// moves to another graph or exits (a step that mixes graphs adds to the
+// per-graph histograms directly, once per distinct (graph, length)); the
+// handed-over paths are the batch's initial triplets in bt.r0..bt.r1,
+// padding slots marked CC_NO_GRAPH.
 //
 // LDS per wavefront: the ring (X and E words, S words when enumerating, and
 // one meta word: v1|t|root in the low half, the graph id of a batch in the

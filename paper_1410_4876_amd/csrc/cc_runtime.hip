@@ -30,7 +30,7 @@ constexpr int kReplyWord = 8;       // ingest reply: words 8..11 of the pinned f
 constexpr int kReplySpinUs = 2000;  // polling for it before a stream synchronisation
 static_assert(kReplyWord + 4 <= 16, "the pinned flag area holds 16 words");
 constexpr int kStepBlocksPerCu = 6;  // cap on the step grid per CU (7 ran 20 % slower)
-constexpr int kLevelsAhead = 3;    // level launches queued beyond the device's progress
+constexpr int kLevelsAhead = 2;    // level launches queued beyond the device's progress
 constexpr int kAheadWaitUs = 200;  // longest the host waits for that progress
 constexpr double kIdleTimeoutSeconds = 30.0;
 
