@@ -46,7 +46,7 @@ extern "C" {
 #endif
 
 #define CC_MAX_VERTICES 256        /* one graph (cc_prepare)                         */
-#define CC_MAX_BATCH_VERTICES 128  /* each graph of a batch or of a serving request */
+#define CC_MAX_BATCH_VERTICES 256  /* each graph of a batch or of a serving request */
 #define CC_ABI_VERSION 2
 
 typedef enum cc_status {

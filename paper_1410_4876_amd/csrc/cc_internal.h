@@ -8,7 +8,7 @@
 #define CC_MAXN 256
 #define CC_HSLOTS (CC_MAXN + 2)   // per-length arrays: index 0..n+1
 #define CC_ROWS(W) (64 * (W))     // vertices a W-word bitset graph can hold
-#define CC_BATCH_MAXN 128         // largest graph of a batch (1 or 2 words)
+#define CC_BATCH_MAXN 256         // largest graph of a batch (1, 2 or 4 words)
 #define CC_WAVE 64
 #define CC_BLOCK 256              // threads per block for the expansion kernels
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk

@@ -1860,9 +1860,12 @@ struct DfsWaveLds {
   unsigned long long E[W * kC];
   unsigned long long S[ENUM ? W * kC : 1];
   unsigned long long MG[kC];
-  unsigned long long rows[BATCH ? CC_ROWS(W) * W : 1];
-  unsigned long long hc[BATCH ? CC_BATCH_MAXN + 2 : 1];  // that graph's histogram, this
-                                                         // wavefront's share not yet added
+  // the cached graph's rows (one- and two-word bitsets; four-word rows,
+  // 8 KiB a graph, are read from device memory)
+  static constexpr bool kRows = BATCH && W <= 2;
+  unsigned long long rows[kRows ? CC_ROWS(W) * W : 1];
+  unsigned long long hc[BATCH ? CC_ROWS(W) + 2 : 1];  // that graph's histogram, this
+                                                      // wavefront's share not yet added
 };
 
 // A frame in registers (one per lane).
@@ -1953,11 +1956,12 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   unsigned long long rng = 0x9E3779B97F4A7C15ull * (unsigned long long)(wid + 1);
   int until_check = 1 + wid % check_every;
   unsigned mail_seen = 0u;                 // lane 0: the request word, as loaded at the last check
-  int cur_g = -1, cur_vo = 0, cur_n = 0;   // BATCH: the graph whose rows are in Q.rows
+  int cur_g = -1, cur_vo = 0, cur_n = 0;   // BATCH: the graph whose rows (one- and two-word
+                                           // bitsets) and histogram share are in LDS
   bool roots_done = false;
   const unsigned long long clk_start = wall_clock64();
   if (BATCH)
-    for (int k = lane; k < CC_BATCH_MAXN + 2; k += CC_WAVE) Q.hc[k] = 0ull;
+    for (int k = lane; k < CC_ROWS(W) + 2; k += CC_WAVE) Q.hc[k] = 0ull;
   if (lane == 0) atomicAdd(&ctl->busy, 1);
 
   auto ring_get = [&](unsigned i, Frame<W> &f) {
@@ -2332,13 +2336,14 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       // state; predicates are combined without short-circuit branches.)
       int n_path = n;  // vertices of this frame's graph
       int vo = 0;
-      bool ring_rows = !BATCH;  // rows from LDS (sN, or the wavefront's cached graph)
+      // every frame of the step is of the cached graph cur_g (always, for one graph)
+      bool in_cur = !BATCH;
       if (BATCH) {
         // usual case: every frame of the step is of the graph whose rows the
         // wavefront holds (lane 0 always has a frame)
         const unsigned g0 = uni_u32(f.gid);
         if ((int)g0 == cur_g && wave_ballot(in_step & (f.gid != g0)) == 0ull) {
-          ring_rows = true;
+          in_cur = true;
           vo = cur_vo;
           n_path = cur_n;
         } else {
@@ -2359,11 +2364,12 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
                 cur_vo = bt.vtx_off[g1];
                 cur_n = min(bt.vtx_off[g1 + 1] - cur_vo, CC_ROWS(W));
                 if (cur_n < 0) cur_n = 0;
-                for (int i = lane; i < cur_n * W; i += CC_WAVE)
-                  Q.rows[i] = bt.adj[(size_t)cur_vo * W + i];
+                if (WL::kRows)
+                  for (int i = lane; i < cur_n * W; i += CC_WAVE)
+                    Q.rows[i] = bt.adj[(size_t)cur_vo * W + i];
                 cur_g = (int)g1;
               }
-              ring_rows = true;
+              in_cur = true;
               vo = cur_vo;
               n_path = cur_n;
             } else {
@@ -2399,7 +2405,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
       const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
       Bits<W> nvt, nv1;
-      if (BATCH && !ring_rows) {
+      if (BATCH && !(WL::kRows && in_cur)) {
+        // rows from device memory (a step that mixes graphs, or four-word rows)
 #pragma unroll
         for (int w = 0; w < W; ++w) {
           nvt.w[w] = bt.adj[(size_t)(vo + v) * W + w];
@@ -2422,7 +2429,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       }
       // the expanded path's own original ids (enumerate)
       const Bits<W> Sp = ENUM ? bor(f.S, bsingle<W>(sPerm[v])) : bzero<W>();
-      if (BATCH && ring_rows) {
+      if (BATCH && in_cur) {
         // every frame is of graph cur_g: each lane adds its closures to the
         // wavefront's LDS share of that graph's histogram
         const unsigned c = count_close ? (unsigned)bpop(clos) : 0u;
@@ -2815,7 +2822,7 @@ hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s) {
 }
 
 // Each launcher picks the instantiation for W = 1, 2 or 4 words per bitset
-// (n <= 64, 128, 256); batches hold graphs of at most 128 vertices.
+// (n <= 64, 128, 256), for single graphs and batches alike.
 #define CC_BY_W(W, F, ...)                                  \
   ((W) == 1 ? F<1>(__VA_ARGS__)                             \
    : (W) == 2 ? F<2>(__VA_ARGS__)                           \
@@ -2834,8 +2841,7 @@ hipError_t launch_ingest(int n_graphs, const int *graph_vtx_off, int n_single, c
 }
 template <int W>
 hipError_t launch_triplets_batch(BatchDev bt, int n_graphs, hipStream_t s) {
-  if (W > 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_triplets_batch<W <= 2 ? W : 2>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
+  hipLaunchKernelGGL(k_triplets_batch<W>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
   return hipGetLastError();
 }
 template <int W>
@@ -2887,7 +2893,7 @@ hipError_t launch_dfs(bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
 }
 template <int W>
 hipError_t dfs_occupancy(bool en, bool batch, int *per_cu) {
-  const void *fn = batch ? (const void *)k_dfs<W <= 2 ? W : 2, false, true>
+  const void *fn = batch ? (const void *)k_dfs<W, false, true>
                          : en ? (const void *)k_dfs<W, true, false>
                               : (const void *)k_dfs<W, false, false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, CC_BLOCK, 0);
@@ -2895,11 +2901,10 @@ hipError_t dfs_occupancy(bool en, bool batch, int *per_cu) {
 template <int W>
 hipError_t launch_dfs_batch(GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,
                             unsigned long long idle_timeout, hipStream_t s) {
-  if (W > 2) return hipErrorInvalidValue;
   dim3 gr(blocks), bl(CC_BLOCK);
   const Frontier nf{};
   const OutDev no{};
-  hipLaunchKernelGGL((k_dfs<W <= 2 ? W : 2, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
+  hipLaunchKernelGGL((k_dfs<W, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
   return hipGetLastError();
 }
 }  // namespace
@@ -3000,7 +3005,7 @@ int cc_dfs_blocks_per_cu(int W, bool en, bool batch) {
   int v = cached[which].load();
   if (v <= 0) {
     int per_cu = 0;
-    if ((batch && W > 2) || CC_BY_W(W, dfs_occupancy, en, batch, &per_cu) != hipSuccess ||
+    if (CC_BY_W(W, dfs_occupancy, en, batch, &per_cu) != hipSuccess ||
         per_cu <= 0)
       return 1;
     cached[which].store(per_cu);

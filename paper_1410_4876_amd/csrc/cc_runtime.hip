@@ -1232,7 +1232,7 @@ cc_status cc_prepare_batch(int32_t n_graphs, const int32_t *graph_vtx_off, const
     if (nnz > 0 && !col_idx) return fail(CC_ERR_INVALID_ARG);
   }
   b->N = N;
-  b->W = max_n <= 64 ? 1 : 2;
+  b->W = max_n <= 64 ? 1 : max_n <= 128 ? 2 : 4;
   b->max_n = max_n;
   b->vtx_off.assign(off, off + Gp);
   const size_t Np = (size_t)std::max(N, 1);
@@ -1693,8 +1693,8 @@ cc_status slot_alloc(cc_server *sv, ServeSlot &sl) {
   const size_t G = (size_t)c.graphs, V = (size_t)c.vertices + CC_BATCH_MAXN, E = (size_t)c.entries,
                R = (size_t)c.roots;
   const size_t dev_fixed = a256((G + 1) * 4) + a256((V + 1) * 4) + a256(E * 4) +
-                           2 * a256((G + 1) * 8) + 2 * a256(V * 2 * 8) + 2 * a256(V * 4) +
-                           a256(G * 4) + a256(R * 2 * 8) + a256(R * 2) + a256(R * 4) +
+                           2 * a256((G + 1) * 8) + 2 * a256(V * 4 * 8) + 2 * a256(V * 4) +
+                           a256(G * 4) + a256(R * 4 * 8) + a256(R * 2) + a256(R * 4) +
                            a256(G * CC_HSLOTS * 8) + a256(sizeof(CcCtl));
   sl.work_bytes = (size_t)sv->opt.slot_work_bytes;
   if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -1712,12 +1712,12 @@ cc_status slot_alloc(cc_server *sv, ServeSlot &sl) {
   sl.d_ci = (int *)take(E * 4);
   sl.d_root_off = (long long *)take((G + 1) * 8);
   sl.d_bound = (long long *)take((G + 1) * 8);
-  sl.d_adj = (unsigned long long *)take(V * 2 * 8);
-  sl.d_adj_orig = (unsigned long long *)take(V * 2 * 8);
+  sl.d_adj = (unsigned long long *)take(V * 4 * 8);  // up to four words a row
+  sl.d_adj_orig = (unsigned long long *)take(V * 4 * 8);
   sl.d_perm = (int *)take(V * 4);
   sl.d_label = (int *)take(V * 4);
   sl.d_status = (unsigned int *)take(G * 4);
-  sl.rX = (unsigned long long *)take(R * 2 * 8);
+  sl.rX = (unsigned long long *)take(R * 4 * 8);
   sl.rvv = (unsigned short *)take(R * 2);
   sl.rgid = (unsigned int *)take(R * 4);
   sl.d_hist = (unsigned long long *)take(G * CC_HSLOTS * 8);
@@ -1772,7 +1772,7 @@ hipError_t slot_launch(cc_server *sv, ServeSlot &sl, const std::vector<ServeReq 
     sl.h_vtx_off[g + 1] = v;
     sl.h_root_off[g + 1] = roots;
   }
-  const int W = max_n <= 64 ? 1 : 2;
+  const int W = max_n <= 64 ? 1 : max_n <= 128 ? 2 : 4;
   const int wpc = std::min(std::max(4, sv->opt.dfs_waves_per_cu),
                            4 * cc_dfs_blocks_per_cu(W, false, true));
   const int waves = std::max(4, sv->dev.cus * wpc / std::max(1, (int)sv->slots.size()) / 4 * 4);

@@ -19,7 +19,7 @@ namespace ccserve {
 
 struct Capacity {
   int64_t graphs = 256;
-  int64_t vertices = 256 * 128;
+  int64_t vertices = 256 * 256;  // graphs times the largest graph
   int64_t entries = 1 << 21;  // adjacency entries (2m)
   int64_t roots = 1 << 22;
 };

@@ -75,6 +75,44 @@ def test_batch_two_word_graphs(cc):
         assert np.array_equal(h.histograms(), want)
 
 
+def four_word_graphs(seed):
+    """Graphs of 129 to 256 vertices (four-word bitsets) among small ones."""
+    rng = np.random.default_rng(seed)
+    return [gg.cycle(256),
+            gg.permute_random(gg.disjoint_union(gg.grid(6, 8), gg.grid(5, 7), gg.cycle(100)), rng),
+            gg.er_gnm(30, 60, rng),
+            gg.wheel(150),
+            gg.permute_random(gg.disjoint_union(gg.grid(5, 6), gg.grid(6, 6), gg.grid(4, 10),
+                                                gg.grid(3, 10)), rng),
+            gg.grid(3, 5),
+            gg.cone(gg.cycle(150)),
+            gg.cycle(129),
+            gg.permute_random(gg.er_gnm(60, 100, rng), rng)]
+
+
+def test_batch_four_word_graphs(cc):
+    graphs = four_word_graphs(31)
+    assert max(g.n for g in graphs) == cc.CC_MAX_BATCH_VERTICES
+    b = gg.pack_batch(graphs)
+    with cc.prepare_batch(b) as h:
+        assert h.max_n == 256
+        want = oracle_hists(graphs, h.max_n + 1)
+        assert np.array_equal(h.histograms(), want)
+        assert np.array_equal(h.histograms(per_graph_launch=True), want)
+        lab = h.labels()
+        for i, g in enumerate(graphs):
+            o = b.graph_vtx_off
+            assert np.array_equal(lab[o[i]:o[i + 1]], oracle.degree_labelling(g.n, g.row_ptr, g.col_idx))
+
+
+def test_batch_rejects_graph_over_limit(cc):
+    graphs = [gg.cycle(5), gg.cycle(cc.CC_MAX_BATCH_VERTICES + 1)]
+    b = gg.pack_batch(graphs)
+    with pytest.raises(cc.CCError) as ei:
+        cc.Batch(b.graph_vtx_off, b.row_ptr, b.col_idx)
+    assert ei.value.status == cc.CC_ERR_TOO_LARGE
+
+
 def test_batch_repeated_and_tuned(cc):
     graphs = gg.er_batch_graphs(200, k=77)
     b = gg.pack_batch(graphs)

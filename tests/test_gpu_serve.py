@@ -130,6 +130,22 @@ def test_result_timeout_keeps_the_request(cc):
         assert np.array_equal(h, alone(cc, g))
 
 
+def test_four_word_requests(cc):
+    rng = np.random.default_rng(22)
+    graphs = [gg.cycle(256), gg.wheel(150), gg.cone(gg.cycle(140)),
+              gg.permute_random(gg.disjoint_union(gg.grid(6, 8), gg.grid(5, 7), gg.cycle(100)), rng)]
+    graphs += small_stream(10, 14)
+    with cc.Server() as sv:
+        with pytest.raises(cc.CCError) as ei:
+            sv.submit_graph(gg.cycle(cc.CC_MAX_BATCH_VERTICES + 1))
+        assert ei.value.status == cc.CC_ERR_TOO_LARGE
+        ids = [sv.submit_graph(g) for g in graphs]
+        for g, rid in zip(graphs, ids):
+            h, _, status = sv.result(rid, timeout_s=120.0)
+            assert status == cc.CC_OK
+            assert np.array_equal(h, alone(cc, g))
+
+
 def test_two_word_requests(cc):
     rng = np.random.default_rng(21)
     graphs = [gg.permute_random(gg.er_gnm(n, int(n * 1.25), rng), rng) for n in (70, 90, 100, 128)]
