@@ -503,11 +503,12 @@ def grid7x12_section():
 def paging_section():
     """Grid 7x10 (8,136,453 cycles, 258M vertex ids): the whole output in one
     cc_enumerate call, against the same output paged through buffers of at
-    most 64 Mi vertex ids (256 MiB), two ways: by ranges of stage-one roots
-    (cc_enumerate_roots; each page runs only the search below its roots) and
-    by ranges of cycle lengths (cc_enumerate_lengths; each page reruns the
-    whole enumeration).  The root pages are checked to add up to the
-    histogram."""
+    most 64 Mi vertex ids (256 MiB), three ways: by ranges of stage-one roots
+    out of one run grouped by root (cc_enumerate_by_roots), by ranges of
+    roots with a run per page (cc_enumerate_roots; each page runs only the
+    search below its roots), and by ranges of cycle lengths
+    (cc_enumerate_lengths; each page reruns the whole enumeration).  The
+    root pages are checked to add up to the histogram."""
     import torch
 
     from paper_1410_4876_amd import cc
@@ -535,9 +536,9 @@ def paging_section():
             torch.cuda.synchronize()
             return pages
 
-        def by_roots(check=False):
+        def by_roots(check=False, one_run=None):
             pages, cyc, ids = 0, 0, 0
-            for lo, hi, v, o in h.pages_by_roots(max_verts=limit):
+            for lo, hi, v, o in h.pages_by_roots(max_verts=limit, one_run=one_run):
                 pages += 1
                 if check:
                     cyc += o.numel() - 1
@@ -551,11 +552,18 @@ def paging_section():
         pages_l = by_lengths()
         pl = _timed(by_lengths, warmup=1, runs=3)
         pages_r = by_roots(check=True)
-        pr = _timed(by_roots, warmup=1, runs=3)
+        pr = _timed(by_roots, warmup=1, runs=5)
+        pages_rr = by_roots(check=True, one_run=False)
+        prr = _timed(lambda: by_roots(one_run=False), warmup=1, runs=3)
     return {"workload": "grid 7x10, full enumeration", "cycles": nc, "vertex_ids": nv,
             "whole_ms": w, "page_limit_vertex_ids": limit,
             "by_roots": {"pages": pages_r, "ms": pr,
-                         "vs_whole": round(pr["median"] / w["median"], 2)},
+                         "vs_whole": round(pr["median"] / w["median"], 2),
+                         "form": "one run grouped by root (cc_enumerate_by_roots), pages "
+                                 "cut out of it (ids in place, offsets rebased)"},
+            "by_roots_runs": {"pages": pages_rr, "ms": prr,
+                              "vs_whole": round(prr["median"] / w["median"], 2),
+                              "form": "one cc_enumerate_roots run per page"},
             "by_lengths": {"pages": pages_l, "ms": pl,
                            "vs_whole": round(pl["median"] / w["median"], 2)}}
 

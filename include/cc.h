@@ -219,6 +219,28 @@ cc_status cc_enumerate_roots(cc_graph *g, int64_t root_lo, int64_t root_hi, int3
                              int64_t verts_cap, int64_t *offsets, int64_t cycles_cap,
                              int64_t *n_cycles, int64_t *n_verts);
 
+/* cc_enumerate_by_roots -- the whole output of cc_enumerate, in one run,
+ * with the cycles grouped by stage-one root (roots in the order above;
+ * within a root, by length).  root_first[r] is the index of root r's first
+ * cycle (roots without cycles get the next root's), root_first[R] = the
+ * number of cycles, R = cc_root_total; so the cycles of roots lo .. hi-1
+ * are cycles root_first[lo] .. root_first[hi]-1, one contiguous piece of
+ * the output, the same cycle set as cc_enumerate_roots(lo, hi).  This is
+ * how a large output is paged when it fits device memory twice over: one
+ * search, then pages by root ranges copied out of it.
+ *   verts, offsets          as cc_enumerate (offsets[n_cycles] = n_verts)
+ *   root_first, roots_cap   R + 1 int64 entries (roots_cap >= R + 1, else
+ *                           CC_ERR_INVALID_ARG)
+ * Device or host pointers per CC_OUTPUT_DEVICE.  The run works in device
+ * memory of its own: staging of the caller's capacities plus about 16
+ * bytes per cycle (and, for host output, the output's size again).  If a
+ * buffer is too small, returns CC_ERR_BUFFER_TOO_SMALL with the required
+ * sizes after the run; CC_ERR_INTERNAL if a cycle had no root.  CC_SORTED
+ * is ignored (the order within a root is by length only). */
+cc_status cc_enumerate_by_roots(cc_graph *g, int32_t *verts, int64_t verts_cap, int64_t *offsets,
+                                int64_t cycles_cap, int64_t *root_first, int64_t roots_cap,
+                                int64_t *n_cycles, int64_t *n_verts);
+
 /* cc_labels -- labels[v] = degree label of vertex v (host array of n). */
 cc_status cc_labels(cc_graph *g, int32_t *labels);
 

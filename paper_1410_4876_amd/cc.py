@@ -123,6 +123,9 @@ def lib():
             L.cc_enumerate_roots.argtypes = [vp, i64, i64, vp, i64, vp, i64,
                                              ctypes.POINTER(i64), ctypes.POINTER(i64)]
             L.cc_enumerate_roots.restype = ctypes.c_int
+            L.cc_enumerate_by_roots.argtypes = [vp, vp, i64, vp, i64, vp, i64,
+                                                ctypes.POINTER(i64), ctypes.POINTER(i64)]
+            L.cc_enumerate_by_roots.restype = ctypes.c_int
             L.cc_labels.argtypes = [vp, vp]
             L.cc_labels.restype = ctypes.c_int
             L.cc_frontier.argtypes = [vp, vp, i32]
@@ -434,25 +437,107 @@ class Graph:
             raise err
         return nc.value, nv.value
 
-    def pages_by_roots(self, max_verts: int, max_cycles: int | None = None, device="cuda"):
+    def enumerate_by_roots_into(self, verts, offsets, root_first):
+        """The whole output grouped by stage-one root (cc_enumerate_by_roots)
+        into caller buffers; root_first holds root_total() + 1 entries.
+        Returns (n_cycles, n_verts); raises CCError(CC_ERR_BUFFER_TOO_SMALL)
+        with .required if they do not fit."""
+        vp, _, _ = _ptr(verts)
+        op, _, _ = _ptr(offsets)
+        fp, _, _ = _ptr(root_first)
+        nc, nv = ctypes.c_int64(), ctypes.c_int64()
+        size = (lambda a: int(a.numel() if _is_torch(a) else np.asarray(a).size))
+        st = lib().cc_enumerate_by_roots(self.h, vp, size(verts), op, max(size(offsets) - 1, 0),
+                                         fp, size(root_first), ctypes.byref(nc), ctypes.byref(nv))
+        if st == CC_ERR_INTERNAL:
+            _check(st, "cc_enumerate_by_roots", self._info_fn)
+        if st != CC_OK:
+            err = CCError(st, "cc_enumerate_by_roots")
+            err.required = (nc.value, nv.value)
+            raise err
+        return nc.value, nv.value
+
+    def pages_by_roots(self, max_verts: int, max_cycles: int | None = None, device="cuda",
+                       one_run: bool | None = None):
         """Yield (root_lo, root_hi, verts, offsets): the whole output in pages
         of consecutive root ranges, each holding at most max_verts vertex ids
-        (and max_cycles cycles).  The ranges start from an even split of the
-        roots sized by the whole histogram; a range whose cycles do not fit
-        is halved.  A page never reruns the whole graph.  With device output
-        every page is written into the same two buffers of the page limits
-        (the arrays yielded are views of them, valid until the next page);
-        with host output each page gets arrays of its exact size.  Raises
-        ValueError if the cycles of a single root do not fit."""
+        (and max_cycles cycles), offsets from 0 in each page.
+
+        When the output fits device memory twice over (or one_run=True), one
+        run enumerates everything grouped by root (cc_enumerate_by_roots) and
+        the pages are copied out of it: ranges chosen greedily from the
+        roots' exact sizes.  Otherwise (or one_run=False) each page is a run
+        of its own over its roots (cc_enumerate_roots), the ranges starting
+        from an even split sized by the whole histogram and halved when
+        their cycles do not fit; no page reruns the whole graph.  With device
+        output every page is written into the same two buffers of the page
+        limits (the arrays yielded are views of them, valid until the next
+        page; in the one-run form the ids are a view of the grouped output);
+        with host output each page gets arrays of its exact size.
+        Raises ValueError if the cycles of a single root do not fit."""
         total = self.root_total()
         if total == 0:
             return
         want = self._sizes()
         nv_all = int((want * np.arange(want.size)).sum())
+        nc_all = int(want.sum())
+        cyc_cap = max_cycles if max_cycles is not None else max_verts // 3
+        if one_run is None:
+            need = 2 * (4 * nv_all + 8 * (nc_all + 1)) + 16 * nc_all + 8 * (total + 1)
+            if self.output_device:
+                import torch
+                free, _ = torch.cuda.mem_get_info()
+            else:
+                free = 0  # host output keeps the whole output in host memory: per-range runs
+            one_run = need + (256 << 20) <= free
+        if one_run:
+            yield from self._pages_one_run(total, nc_all, nv_all, max_verts, cyc_cap, device)
+            return
+        yield from self._pages_by_range_runs(total, nv_all, max_verts, cyc_cap, device)
+
+    def _pages_one_run(self, total, nc_all, nv_all, max_verts, cyc_cap, device):
+        if self.output_device:
+            import torch
+            gv = torch.empty(max(nv_all, 1), dtype=torch.int32, device=device)
+            go = torch.empty(nc_all + 1, dtype=torch.int64, device=device)
+            gf = torch.empty(total + 1, dtype=torch.int64, device=device)
+        else:
+            gv = np.empty(max(nv_all, 1), np.int32)
+            go = np.empty(nc_all + 1, np.int64)
+            gf = np.empty(total + 1, np.int64)
+        self.enumerate_by_roots_into(gv, go, gf)
+        if self.output_device:
+            both = torch.cat((gf, go[gf])).cpu().numpy()  # one copy back
+            first, vpos = both[:total + 1], both[total + 1:]
+            offs = torch.empty(cyc_cap + 1, dtype=torch.int64, device=device)
+        else:
+            first = gf
+            vpos = go[gf]
+        lo = 0
+        while lo < total:
+            # the longest range from lo that fits the page limits
+            hi_v = int(np.searchsorted(vpos, vpos[lo] + max_verts, side="right")) - 1
+            hi_c = int(np.searchsorted(first, first[lo] + cyc_cap, side="right")) - 1
+            hi = min(hi_v, hi_c, total)
+            if hi <= lo:
+                c0, c1 = int(first[lo]), int(first[lo + 1])
+                raise ValueError(f"the {c1 - c0} cycles of root {lo} need "
+                                 f"{int(vpos[lo + 1] - vpos[lo])} vertex ids, more than "
+                                 f"max_verts={max_verts}")
+            c0, c1 = int(first[lo]), int(first[hi])
+            v0, v1 = int(vpos[lo]), int(vpos[hi])
+            if self.output_device:
+                # the page's ids in place; its offsets from 0 in the page buffer
+                torch.sub(go[c0:c1 + 1], v0, out=offs[:c1 - c0 + 1])
+                yield lo, hi, gv[v0:v1], offs[:c1 - c0 + 1]
+            else:
+                yield lo, hi, gv[v0:v1].copy(), go[c0:c1 + 1] - v0
+            lo = hi
+
+    def _pages_by_range_runs(self, total, nv_all, max_verts, cyc_cap, device):
         parts = max(1, -(-nv_all // max(max_verts, 1)))
         bounds = [total * i // parts for i in range(parts + 1)]
         todo = [(bounds[i], bounds[i + 1]) for i in range(parts) if bounds[i] < bounds[i + 1]]
-        cyc_cap = max_cycles if max_cycles is not None else max_verts // 3
         if self.output_device:
             import torch
             verts = torch.empty(max(max_verts, 1), dtype=torch.int32, device=device)

@@ -276,5 +276,14 @@ hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool enumerate, hip
 // After a complete enumerate run: the cycles of each length in out into
 // ascending lexicographic order (tmp: room for the output's vertex ids; ia,
 // ib: room for its cycle count each).  A no-op when the output did not fit.
+// The cycles of a finished enumeration (verts_old/offs_old, nc of them)
+// regrouped by stage-one root into verts_new/offs_new (offs_new: nc + 1
+// entries), and first[r] = index of root r's first cycle, first[R] = nc
+// unless a cycle was malformed.  work: cc_group_roots_workspace(nc) bytes.
+size_t cc_group_roots_workspace(long long nc);
+hipError_t cc_launch_group_roots(int W, GraphDev g, const int *label, const int *verts_old,
+                                 const long long *offs_old, long long nc, long long R,
+                                 int *verts_new, long long *offs_new, long long *first, void *work,
+                                 hipStream_t s);
 hipError_t cc_launch_sort_cycles(const CcCtl *ctl, OutDev out, int n, int *tmp, unsigned *ia,
                                  unsigned *ib, hipStream_t s);

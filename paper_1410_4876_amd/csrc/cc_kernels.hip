@@ -2803,6 +2803,338 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_cycles(const CcCtl *ctl, 
   for (unsigned long long e = tid; e < nv; e += kSortThreads) o[e] = dst[e];
 }
 
+// ------------------------------------------- the output grouped by root
+// A finished enumeration, regrouped so that the cycles of each stage-one
+// root are contiguous (roots in the order the root-range calls number
+// them): every cycle gets its root's number, a stable radix sort orders the
+// cycle indices by it, a scan gives the new offsets and a gather moves the
+// vertex ids.  A range of roots is then one contiguous page.
+
+// root_base[l]: the number of the first root whose u has label l (roots by
+// u's original id, then x's, then y's).  One thread: n <= 256 steps.
+template <int W>
+__global__ void k_root_base(GraphDev g, const int *label, long long *root_base) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  long long acc = 0;
+  for (int v = 0; v < g.n; ++v) {
+    const int l = label[v];
+    if (l < 0 || l >= g.n) continue;
+    const long long dp = bpop(bandnot(row<W>(g.adj, l), low_through<W>(l)));
+    root_base[l] = acc;
+    acc += dp * (dp - 1) / 2;
+  }
+}
+
+// The root of each cycle: u is its vertex of smallest label, x and y the
+// neighbours of u on the cycle, l(x) < l(y); its number follows the
+// stage-one numbering (u's first root, plus the roots of u's higher
+// neighbours x' before x by original id, plus y's rank among x's partners
+// by original id).  key[i] = that number, idx[i] = i.
+//
+// Each wavefront takes runs of up to 64 consecutive cycles: their ids are
+// copied into its LDS buffer by coalesced loads, then each lane walks one
+// cycle there, starting at a lane-dependent position so that the lanes'
+// reads of one round fall in different banks.
+constexpr int kKeyBuf = 1024;  // ids per wavefront buffer (a cycle has at most 256)
+template <int W>
+__global__ __launch_bounds__(CC_BLOCK) void k_cycle_root_keys(GraphDev g, const int *label,
+                                                              const long long *root_base,
+                                                              const int *verts,
+                                                              const long long *offs,
+                                                              long long nc, long long R,
+                                                              unsigned *key, unsigned *idx) {
+  constexpr int NW = CC_BLOCK / CC_WAVE;
+  __shared__ unsigned long long sN[CC_ROWS(W) * W];
+  __shared__ int sLab[CC_ROWS(W)], sPerm[CC_ROWS(W)];
+  __shared__ long long sBase[CC_ROWS(W)];
+  __shared__ int sBuf[NW][kKeyBuf];
+  const int n = g.n;
+  for (int i = threadIdx.x; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+  for (int i = threadIdx.x; i < n; i += CC_BLOCK) {
+    sLab[i] = label[i];
+    sPerm[i] = g.perm[i];
+    sBase[i] = root_base[i];
+  }
+  __syncthreads();
+  const int lane = lane_id(), wave = threadIdx.x / CC_WAVE;
+  int *buf = sBuf[wave];
+  const long long nwg = (long long)gridDim.x * NW;
+  // each wavefront owns blocks of 64 consecutive cycles, walked in runs
+  // whose ids fit its buffer
+  for (long long B = ((long long)blockIdx.x * NW + wave) * CC_WAVE; B < nc; B += nwg * CC_WAVE) {
+    const long long bend = min(B + CC_WAVE, nc);
+    long long j0 = B;
+    while (j0 < bend) {
+      const long long j = j0 + lane;
+      const bool in = j < bend;
+      const long long b = in ? offs[j] : 0, e = in ? offs[j + 1] : 0;
+      const long long base = (long long)uni_u64((unsigned long long)offs[j0]);
+      // the run: the cycles from j0 whose ids fit the buffer (at least one,
+      // a cycle having at most 256 ids)
+      const int nb = max(1, (int)__popcll(wave_ballot(in && e - base <= kKeyBuf)));
+      const long long end = (long long)lane_u64((unsigned long long)e, nb - 1);
+      {
+        // sixteen loads in flight per round
+        const int m = (int)(end - base);
+        for (int q0 = 0; q0 < m; q0 += 16 * CC_WAVE) {
+          int v[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int q = q0 + u * CC_WAVE + lane;
+            v[u] = q < m ? verts[base + q] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int q = q0 + u * CC_WAVE + lane;
+            if (q < m) buf[q] = v[u];
+          }
+        }
+      }
+      wave_lds_sync();
+      if (lane < nb) {
+        const int s0 = (int)(b - base), k = (int)(e - b);
+        int p = 0, lu = n;
+        int q = k > 0 ? lane % k : 0;
+        for (int t = 0; t < k; ++t) {
+          const int v = buf[s0 + q];
+          const int l = (v >= 0 && v < n) ? sLab[v] : n;
+          if (l < lu) {
+            lu = l;
+            p = q;
+          }
+          if (++q == k) q = 0;
+        }
+        long long r = R;  // a malformed cycle (none in a finished run) sorts last
+        if (k >= 3 && lu < n) {
+          const int va = buf[s0 + (p + k - 1) % k], vc = buf[s0 + (p + 1) % k];
+          const int la = (va >= 0 && va < n) ? sLab[va] : n;
+          const int lc = (vc >= 0 && vc < n) ? sLab[vc] : n;
+          if (la < n && lc < n && la != lc) {
+            const int lx = min(la, lc), ly = max(la, lc);
+            const Bits<W> up = bandnot(row<W>(sN, lu), low_through<W>(lu));
+            long long ix = sBase[lu];
+            Bits<W> it = up;
+            while (bany(it)) {
+              const int xp = bpop_lowest(it);
+              if (sPerm[xp] < sPerm[lx]) ix += bpop(bandnot(up, low_through<W>(xp)));
+            }
+            it = bandnot(up, low_through<W>(lx));
+            while (bany(it)) {
+              const int yp = bpop_lowest(it);
+              ix += sPerm[yp] < sPerm[ly] ? 1 : 0;
+            }
+            r = ix < R ? ix : R;
+          }
+        }
+        key[j] = (unsigned)r;
+        idx[j] = (unsigned)j;
+      }
+      wave_lds_sync();  // the next run overwrites the buffer
+      j0 += nb;
+    }
+  }
+}
+
+// Stable LSD radix sort of (key, idx) by 8-bit digits, multi-block: each
+// block owns a tile of kRsTile items.  Pass: per-block digit counts
+// (digit-major table, so that its exclusive scan gives every (digit, block)
+// its first output slot), then a scatter that ranks the items of a tile in
+// index order: per wavefront by matching digits with ballots, across the
+// wavefronts of a round and across rounds by per-digit running counts.
+constexpr int kRsThreads = 256;
+constexpr int kRsIpt = 8;
+constexpr int kRsTile = kRsThreads * kRsIpt;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_count(const unsigned *key, long long n,
+                                                         int shift, long long *table, int nb) {
+  __shared__ unsigned c[256];
+  c[threadIdx.x] = 0u;
+  __syncthreads();
+  const long long t0 = (long long)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsIpt; ++r) {
+    const long long i = t0 + (long long)r * kRsThreads + threadIdx.x;
+    if (i < n) atomicAdd(&c[(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  table[(long long)threadIdx.x * nb + blockIdx.x] = (long long)c[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const unsigned *kin, const unsigned *vin,
+                                                           unsigned *kout, unsigned *vout,
+                                                           long long n, int shift,
+                                                           const long long *table, int nb) {
+  constexpr int NW = kRsThreads / CC_WAVE;
+  __shared__ long long base[256];
+  __shared__ long long wc[NW][256];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / CC_WAVE;
+  base[tid] = table[(long long)tid * nb + blockIdx.x];
+  const long long t0 = (long long)blockIdx.x * kRsTile;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int r = 0; r < kRsIpt; ++r) {
+    for (int w = 0; w < NW; ++w) wc[w][tid] = 0;
+    __syncthreads();
+    const long long i = t0 + (long long)r * kRsThreads + tid;
+    const bool valid = i < n;
+    const unsigned kv = valid ? kin[i] : 0u;
+    const unsigned vv = valid ? vin[i] : 0u;
+    const unsigned d = (kv >> shift) & 255u;
+    // lanes of this wavefront with the same digit
+    unsigned long long m = wave_ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long mb = wave_ballot(on);
+      m &= on ? mb : ~mb;
+    }
+    const int rank = __popcll(m & below);
+    if (valid && rank == 0) wc[wave][d] = __popcll(m);
+    __syncthreads();
+    {
+      // digit tid: running counts across the wavefronts of this round
+      long long run = base[tid];
+      for (int w = 0; w < NW; ++w) {
+        const long long c = wc[w][tid];
+        wc[w][tid] = run;
+        run += c;
+      }
+      base[tid] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const long long pos = wc[wave][d] + rank;
+      kout[pos] = kv;
+      vout[pos] = vv;
+    }
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of int64 values in place, by tiles of kScanTile: each tile
+// is scanned by one block (its total to totals[block]); the host scans the
+// totals the same way and adds them back.
+constexpr int kScanThreads = 1024;
+constexpr int kScanIpt = 4;
+constexpr int kScanTile = kScanThreads * kScanIpt;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(long long *x, long long n,
+                                                            long long *totals) {
+  constexpr int NW = kScanThreads / CC_WAVE;
+  __shared__ long long sw[NW];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / CC_WAVE;
+  const long long b = (long long)blockIdx.x * kScanTile + (long long)tid * kScanIpt;
+  long long v[kScanIpt];
+  long long s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanIpt; ++j) {
+    v[j] = b + j < n ? x[b + j] : 0;
+    s += v[j];
+  }
+  // inclusive scan over the wavefront, then over the wavefronts' totals
+  long long inc = s;
+#pragma unroll
+  for (int o = 1; o < CC_WAVE; o <<= 1) {
+    const long long t = __shfl_up(inc, o, CC_WAVE);
+    if (lane >= o) inc += t;
+  }
+  if (lane == CC_WAVE - 1) sw[wave] = inc;
+  __syncthreads();
+  if (tid == 0) {
+    long long run = 0;
+    for (int w = 0; w < NW; ++w) {
+      const long long t = sw[w];
+      sw[w] = run;
+      run += t;
+    }
+    if (totals) totals[blockIdx.x] = run;
+  }
+  __syncthreads();
+  long long run = sw[wave] + inc - s;
+#pragma unroll
+  for (int j = 0; j < kScanIpt; ++j) {
+    if (b + j < n) x[b + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(long long *x, long long n,
+                                                           const long long *add) {
+  const long long b = (long long)blockIdx.x * kScanTile + (long long)threadIdx.x * kScanIpt;
+  const long long a = add[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kScanIpt; ++j)
+    if (b + j < n) x[b + j] += a;
+}
+
+// New lengths in sorted order: len[j] = length of cycle idx[j]; the slot
+// after the last holds 0 (so that the exclusive scan of nc + 1 entries ends
+// with the total).
+__global__ void k_sorted_lengths(const unsigned *idx, const long long *offs, long long nc,
+                                 long long *len) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j <= nc; j += stride)
+    len[j] = j < nc ? offs[(long long)idx[j] + 1] - offs[idx[j]] : 0;
+}
+
+// Runs of 64 cycles per wavefront: the lanes read the run's source and
+// destination offsets at once, then copy the cycles' ids, U cycles at a
+// time (U loads in flight before their stores).
+__global__ __launch_bounds__(CC_BLOCK) void k_gather_cycles(const unsigned *idx,
+                                                            const long long *offs_old,
+                                                            const int *verts_old,
+                                                            const long long *offs_new,
+                                                            int *verts_new, long long nc) {
+  constexpr int U = 16;
+  const int lane = lane_id();
+  const long long nw = (long long)gridDim.x * (CC_BLOCK / CC_WAVE);
+  for (long long j0 = ((long long)blockIdx.x * (CC_BLOCK / CC_WAVE) + threadIdx.x / CC_WAVE) *
+                      CC_WAVE;
+       j0 < nc; j0 += nw * CC_WAVE) {
+    const long long j = j0 + lane;
+    const long long src = j < nc ? offs_old[idx[j]] : 0;
+    const long long dst = j < nc ? offs_new[j] : 0;
+    const int k = j < nc ? (int)(offs_new[j + 1] - dst) : 0;
+    const int cnt = (int)min((long long)CC_WAVE, nc - j0);
+    for (int c0 = 0; c0 < cnt; c0 += U) {
+      int val[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = min(c0 + u, cnt - 1);
+        const long long s = lane_u64((unsigned long long)src, c);
+        const int kc = __builtin_amdgcn_readlane(k, c);
+        val[u] = (c0 + u < cnt && lane < kc) ? verts_old[s + lane] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = min(c0 + u, cnt - 1);
+        const long long d = lane_u64((unsigned long long)dst, c);
+        const int kc = __builtin_amdgcn_readlane(k, c);
+        if (c0 + u < cnt && lane < kc) verts_new[d + lane] = val[u];
+      }
+      // ids past the first 64 of a cycle (cycles of more than 64 vertices)
+      for (int u = 0; u < U && c0 + u < cnt; ++u) {
+        const int kc = __builtin_amdgcn_readlane(k, c0 + u);
+        if (kc > CC_WAVE) {
+          const long long d = lane_u64((unsigned long long)dst, c0 + u);
+          const long long s = lane_u64((unsigned long long)src, c0 + u);
+          for (int q = lane + CC_WAVE; q < kc; q += CC_WAVE) verts_new[d + q] = verts_old[s + q];
+        }
+      }
+    }
+  }
+}
+
+// first[r] = index of root r's first cycle in the sorted order (roots
+// without cycles get the next root's), first[R] = nc.
+__global__ void k_root_first(const unsigned *key, long long nc, long long R, long long *first) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j <= nc; j += stride) {
+    const long long hi = j < nc ? min((long long)key[j], R) : R;
+    const long long lo = j > 0 ? min((long long)key[j - 1], R) + 1 : 0;
+    for (long long r = lo; r <= hi; ++r) first[r] = j;
+  }
+}
+
+
 // Final histogram; in enumerate mode also closes the offsets array with the
 // total vertex count.  One block.
 __global__ void k_finalize(CcCtl *ctl, OutDev out, int n, int enumerate) {
@@ -3030,6 +3362,103 @@ hipError_t cc_launch_sort_cycles(const CcCtl *ctl, OutDev out, int n, int *tmp, 
   hipLaunchKernelGGL(k_sort_cycles, dim3(std::max(n + 1, 1)), dim3(kSortThreads), 0, s, ctl, out,
                      n, tmp, ia, ib);
   return hipGetLastError();
+}
+
+namespace {
+// In-place exclusive scan of n int64 values; tmp holds cc_scan_tmp(n) words.
+hipError_t scan_exclusive(long long *x, long long n, long long *tmp, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(kScanThreads), 0, s, x, n, nullptr);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(kScanThreads), 0, s, x, n, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(tmp, nb, tmp + nb, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, x, n, tmp);
+  return hipGetLastError();
+}
+long long scan_tmp_words(long long n) {
+  long long w = 0;
+  while (n > kScanTile) {
+    n = (n + kScanTile - 1) / kScanTile;
+    w += n;
+  }
+  return w + 1;
+}
+template <int W>
+hipError_t launch_group_roots(GraphDev g, const int *label, const int *verts_old,
+                              const long long *offs_old, long long nc, long long R,
+                              int *verts_new, long long *offs_new, long long *first, char *work,
+                              hipStream_t s) {
+  const long long nb = std::max(1ll, (nc + kRsTile - 1) / kRsTile);
+  auto take = [&](size_t bytes) {
+    char *p = work;
+    work += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  long long *root_base = (long long *)take((size_t)CC_MAXN * 8);
+  unsigned *ka = (unsigned *)take((size_t)std::max(nc, 1ll) * 4);
+  unsigned *ia = (unsigned *)take((size_t)std::max(nc, 1ll) * 4);
+  unsigned *kb = (unsigned *)take((size_t)std::max(nc, 1ll) * 4);
+  unsigned *ib = (unsigned *)take((size_t)std::max(nc, 1ll) * 4);
+  long long *table = (long long *)take((size_t)(256 * nb) * 8);
+  long long *tmp = (long long *)take((size_t)scan_tmp_words(std::max(256 * nb, nc + 1)) * 8);
+  hipLaunchKernelGGL(k_root_base<W>, dim3(1), dim3(64), 0, s, g, label, root_base);
+  const unsigned kb_blocks = (unsigned)std::min(std::max(1ll, (nc + CC_BLOCK - 1) / CC_BLOCK), 8192ll);
+  hipLaunchKernelGGL(k_cycle_root_keys<W>, dim3(kb_blocks), dim3(CC_BLOCK), 0, s, g, label,
+                     root_base, verts_old, offs_old, nc, R, ka, ia);
+  hipError_t e = hipGetLastError();
+  // enough 8-bit digits for keys up to R (malformed cycles carry R)
+  int passes = 1;
+  while (passes < 4 && (R >> (8 * passes)) != 0) ++passes;
+  for (int p = 0; p < passes && e == hipSuccess && nc > 0; ++p) {
+    hipLaunchKernelGGL(k_rs_count, dim3((unsigned)nb), dim3(kRsThreads), 0, s, ka, nc, 8 * p,
+                       table, (int)nb);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = scan_exclusive(table, 256 * nb, tmp, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kRsThreads), 0, s, ka, ia, kb, ib,
+                         nc, 8 * p, table, (int)nb);
+      e = hipGetLastError();
+    }
+    std::swap(ka, kb);
+    std::swap(ia, ib);
+  }
+  if (e != hipSuccess) return e;
+  const unsigned lb = (unsigned)std::min(std::max(1ll, (nc + 1 + 255) / 256), 16384ll);
+  hipLaunchKernelGGL(k_sorted_lengths, dim3(lb), dim3(256), 0, s, ia, offs_old, nc, offs_new);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = scan_exclusive(offs_new, nc + 1, tmp, s);
+  if (e != hipSuccess) return e;
+  const unsigned gb = (unsigned)std::min(std::max(1ll, (nc + CC_BLOCK - 1) / CC_BLOCK), 8192ll);
+  hipLaunchKernelGGL(k_gather_cycles, dim3(gb), dim3(CC_BLOCK), 0, s, ia, offs_old, verts_old,
+                     offs_new, verts_new, nc);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned fb = (unsigned)std::min(std::max(1ll, (nc + 1 + 255) / 256), 16384ll);
+  hipLaunchKernelGGL(k_root_first, dim3(fb), dim3(256), 0, s, ka, nc, R, first);
+  return hipGetLastError();
+}
+}  // namespace
+
+size_t cc_group_roots_workspace(long long nc) {
+  const long long nb = std::max(1ll, (nc + kRsTile - 1) / kRsTile);
+  const size_t c = (size_t)std::max(nc, 1ll);
+  auto a = [](size_t b) { return (b + 255) / 256 * 256; };
+  return a((size_t)CC_MAXN * 8) + 4 * a(c * 4) + a((size_t)(256 * nb) * 8) +
+         a((size_t)scan_tmp_words(std::max(256 * nb, nc + 1)) * 8);
+}
+
+hipError_t cc_launch_group_roots(int W, GraphDev g, const int *label, const int *verts_old,
+                                 const long long *offs_old, long long nc, long long R,
+                                 int *verts_new, long long *offs_new, long long *first, void *work,
+                                 hipStream_t s) {
+  return CC_BY_W(W, launch_group_roots, g, label, verts_old, offs_old, nc, R, verts_new, offs_new,
+                 first, (char *)work, s);
 }
 
 hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool en, hipStream_t s) {

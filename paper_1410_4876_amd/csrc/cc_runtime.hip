@@ -28,7 +28,9 @@ constexpr int64_t kDefaultBudget = 4ll << 30;
 constexpr int64_t kHostStageBytes = 8ll << 30;
 constexpr int kReplyWord = 8;       // ingest reply: words 8..11 of the pinned flag area
 constexpr int kReplySpinUs = 2000;  // polling for it before a stream synchronisation
-static_assert(kReplyWord + 4 <= 16, "the pinned flag area holds 16 words");
+constexpr int kGroupWord = 12;      // cc_enumerate_by_roots check: words 12..13
+static_assert(kReplyWord + 4 <= kGroupWord && kGroupWord + 2 <= 16,
+              "the pinned flag area holds 16 words");
 constexpr int kStepBlocksPerCu = 6;  // cap on the step grid per CU (7 ran 20 % slower)
 constexpr int kLevelsAhead = 2;    // level launches queued beyond the device's progress
 constexpr int kAheadWaitUs = 200;  // longest the host waits for that progress
@@ -213,6 +215,7 @@ struct cc_graph {
   int32_t n = 0;
   int W = 1;
   int max_deg = 0;
+  int64_t n_roots = -1;  // stage-one roots, once counted (a property of the graph)
   DeviceInfo dev{};
   void *d_blob = nullptr;  // adj | perm | label | status | ctl
   unsigned long long *d_adj = nullptr;       // label-space adjacency bitsets
@@ -967,6 +970,10 @@ cc_status cc_root_total(cc_graph *g, int64_t *n_roots) {
   if (!n_roots) return CC_ERR_INVALID_ARG;
   *n_roots = 0;
   if (g->n < 3) return CC_OK;
+  if (g->n_roots >= 0) {
+    *n_roots = g->n_roots;
+    return CC_OK;
+  }
   // computed into the handle's status area (after the status word and the
   // pair bound), then read back
   long long *d_out = (long long *)((char *)g->d_status + 16);
@@ -977,6 +984,7 @@ cc_status cc_root_total(cc_graph *g, int64_t *n_roots) {
       hipStreamSynchronize(g->stream) != hipSuccess)
     return CC_ERR_DEVICE;
   *n_roots = v;
+  g->n_roots = v;
   return CC_OK;
 }
 
@@ -989,6 +997,101 @@ cc_status cc_histogram_roots(cc_graph *g, int64_t root_lo, int64_t root_hi, int6
   st = run_counts(g, RootRange{root_lo, root_hi});
   if (st != CC_OK) return st;
   for (int k = 0; k < hist_len; ++k) hist[k] = k <= g->n ? g->hist[k] : 0;
+  return CC_OK;
+}
+
+cc_status cc_enumerate_by_roots(cc_graph *g, int32_t *verts, int64_t verts_cap, int64_t *offsets,
+                                int64_t cycles_cap, int64_t *root_first, int64_t roots_cap,
+                                int64_t *n_cycles, int64_t *n_verts) {
+  cc_status st = check_handle(g);
+  if (st != CC_OK) return st;
+  if (!n_cycles || !n_verts || verts_cap < 0 || cycles_cap < 0 || roots_cap < 1)
+    return CC_ERR_INVALID_ARG;
+  if ((verts_cap > 0 && !verts) || !offsets || !root_first) return CC_ERR_INVALID_ARG;
+  *n_cycles = 0;
+  *n_verts = 0;
+  const bool dev_out = (g->opt.flags & CC_OUTPUT_DEVICE) != 0;
+  int64_t R = 0;
+  st = cc_root_total(g, &R);
+  if (st != CC_OK) return st;
+  if (roots_cap < R + 1) return CC_ERR_INVALID_ARG;
+  hipStream_t s = g->stream;
+  if (g->n < 3 || R == 0) {
+    if (g->n < 3) (void)run_counts(g);
+    const int64_t zero = 0;
+    if (dev_out) {
+      if (hipMemcpyAsync(offsets, &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(root_first, &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return CC_ERR_DEVICE;
+    } else {
+      offsets[0] = 0;
+      root_first[0] = 0;
+    }
+    return CC_OK;
+  }
+  // the enumeration, ordered by length as cc_enumerate writes it, into
+  // device staging of the caller's capacities
+  const size_t tv_b = align_up((size_t)std::max<int64_t>(verts_cap, 1) * 4, 256);
+  const size_t to_b = align_up((size_t)(cycles_cap + 1) * 8, 256);
+  char *stage = nullptr;
+  if (hipMallocAsync((void **)&stage, tv_b + to_b, s) != hipSuccess) return CC_ERR_OUT_OF_MEMORY;
+  RunOut ro;
+  ro.enumerate = true;
+  ro.out = OutDev{(int *)stage, (long long *)(stage + tv_b), verts_cap, cycles_cap};
+  st = run_device(g, ro);
+  int64_t nc = 0, nv = 0;
+  for (int k = 0; k <= g->n; ++k) {
+    nc += g->hist[k];
+    nv += g->hist[k] * k;
+  }
+  if (st == CC_OK && (nc > cycles_cap || nv > verts_cap)) {
+    *n_cycles = nc;
+    *n_verts = nv;
+    st = CC_ERR_BUFFER_TOO_SMALL;
+  }
+  if (st != CC_OK) {
+    (void)hipFreeAsync(stage, s);
+    (void)hipStreamSynchronize(s);
+    return st;
+  }
+  // regrouped into the caller's buffers (through device buffers of the
+  // exact sizes for host output)
+  const size_t work_b = align_up(cc_group_roots_workspace(nc), 256);
+  const size_t vn_b = align_up((size_t)std::max<int64_t>(nv, 1) * 4, 256);
+  const size_t on_b = align_up((size_t)(nc + 1) * 8, 256);
+  const size_t fn_b = align_up((size_t)(R + 1) * 8, 256);
+  char *work = nullptr;
+  if (hipMallocAsync((void **)&work, work_b + (dev_out ? 0 : vn_b + on_b + fn_b), s) != hipSuccess) {
+    (void)hipFreeAsync(stage, s);
+    (void)hipStreamSynchronize(s);
+    return CC_ERR_OUT_OF_MEMORY;
+  }
+  int *vn = dev_out ? verts : (int *)(work + work_b);
+  long long *on = dev_out ? (long long *)offsets : (long long *)(work + work_b + vn_b);
+  long long *fn = dev_out ? (long long *)root_first : (long long *)(work + work_b + vn_b + on_b);
+  GraphDev gd{g->d_adj, g->d_adj_orig, g->d_perm, g->n};
+  hipError_t e = cc_launch_group_roots(g->W, gd, g->d_label, (const int *)stage,
+                                       (const long long *)(stage + tv_b), nc, R, vn, on, fn, work,
+                                       s);
+  long long *h_last = (long long *)(g->h_done + kGroupWord);
+  *h_last = -1;
+  if (e == hipSuccess && !dev_out) {
+    e = hipMemcpyAsync(verts, vn, (size_t)nv * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(offsets, on, (size_t)(nc + 1) * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(root_first, fn, (size_t)(R + 1) * 8, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h_last, fn + R, 8, hipMemcpyDeviceToHost, s);
+  (void)hipFreeAsync(work, s);
+  (void)hipFreeAsync(stage, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  else (void)hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(e);
+  // every cycle got a root (first[R] == nc)
+  if (*h_last != nc) return CC_ERR_INTERNAL;
+  *n_cycles = nc;
+  *n_verts = nv;
   return CC_OK;
 }
 

@@ -99,6 +99,9 @@ def test_argument_errors_before_any_device_call(L):
     offs = (ctypes.c_int64 * 2)()
     assert L.cc_enumerate_lengths(None, 3, 5, None, 0, offs, 1, ctypes.byref(nc),
                                   ctypes.byref(nv)) == cc.CC_ERR_INVALID_ARG
+    first = (ctypes.c_int64 * 2)()
+    assert L.cc_enumerate_by_roots(None, None, 0, offs, 1, first, 2, ctypes.byref(nc),
+                                   ctypes.byref(nv)) == cc.CC_ERR_INVALID_ARG
     L.cc_release(None)
     # batch calls on a null handle
     hists = (ctypes.c_int64 * 4)()

@@ -40,9 +40,10 @@ def gpu_enumerate(cc, g, **kw):
                 h.frontier(), h.last_run())
 
 
-def assert_same_cycles(gpu_verts, gpu_offs, ores):
+def assert_same_cycles(gpu_verts, gpu_offs, ores, by_length=True):
     assert is_canonical_array(gpu_verts, gpu_offs)
-    assert np.all(np.diff(np.diff(gpu_offs)) >= 0), "output not ordered by length"
+    if by_length:
+        assert np.all(np.diff(np.diff(gpu_offs)) >= 0), "output not ordered by length"
     a = canonical_groups(gpu_verts, gpu_offs)
     b = canonical_groups(*ores.cycles)
     assert sorted(a) == sorted(b)
@@ -525,10 +526,66 @@ def test_root_ranges_equal_oracle_ranges(cc, case):
         assert np.array_equal(h.histogram(), oracle_run(g, cycles=False).hist)
 
 
+@pytest.mark.parametrize("case", ["er40", "grid6x7", "k_4_5", "er100_w2", "four_word", "forced_dfs"])
 @pytest.mark.parametrize("out_dev", [True, False])
-def test_pages_by_roots_partition_the_output(cc, out_dev):
-    """Pages of consecutive root ranges under a bound: every page fits, and
-    together they are exactly the oracle's cycle set (no cycle twice)."""
+def test_enumerate_by_roots_groups_equal_oracle_ranges(cc, case, out_dev):
+    """The whole output grouped by root in one run: root_first cuts it into
+    the oracle's root ranges (each range the same cycle set as the oracle's
+    run over it), and the whole is the oracle's cycle set."""
+    import torch
+    kw = {"output_device": out_dev}
+    if case == "er40":
+        g = gg.workload_er40()
+    elif case == "grid6x7":
+        g = gg.permute_random(gg.grid(6, 7), np.random.default_rng(67))
+    elif case == "k_4_5":
+        g = gg.permute_random(gg.complete_multipartite(4, 5, 3), np.random.default_rng(45))
+    elif case == "er100_w2":
+        g = gg.er_gnm(100, 150, np.random.default_rng(100))
+    elif case == "four_word":
+        g = four_word_union()
+    else:
+        g = gg.permute_random(gg.grid(5, 7), np.random.default_rng(75))
+        kw["force_dfs_level"] = 5
+    ores = oracle_run(g)
+    nc, nv = int(ores.hist.sum()), int((ores.hist * np.arange(g.n + 1)).sum())
+    total = oracle.count_roots(g.n, g.row_ptr, g.col_idx)
+    with cc.prepare(g, **kw) as h:
+        if out_dev:
+            v = torch.empty(max(nv, 1), dtype=torch.int32, device="cuda")
+            o = torch.empty(nc + 1, dtype=torch.int64, device="cuda")
+            f = torch.empty(total + 1, dtype=torch.int64, device="cuda")
+        else:
+            v, o, f = np.empty(max(nv, 1), np.int32), np.empty(nc + 1, np.int64), np.empty(total + 1, np.int64)
+        with pytest.raises(cc.CCError) as ei:
+            h.enumerate_by_roots_into(v, o, f[:total])
+        assert ei.value.status == cc.CC_ERR_INVALID_ARG
+        assert h.enumerate_by_roots_into(v, o, f) == (nc, nv)
+        if out_dev:
+            torch.cuda.synchronize()
+            v, o, f = v.cpu().numpy(), o.cpu().numpy(), f.cpu().numpy()
+    assert f[0] == 0 and f[-1] == nc and np.all(np.diff(f) >= 0) and o[-1] == nv
+    assert_same_cycles(v[:nv], o, ores, by_length=False)
+    for r in range(total):  # each root's cycles ordered by length
+        lens = np.diff(o[f[r]:f[r + 1] + 1])
+        assert np.all(np.diff(lens) >= 0), r
+    rng = np.random.default_rng(11)
+    cuts = sorted(set([0, total] + [int(x) for x in rng.integers(0, total + 1, 5)]))
+    for lo, hi in list(zip(cuts[:-1], cuts[1:])) + [(total - 1, total), (0, 1)]:
+        rres = oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=True,
+                                       root_lo=lo, root_hi=hi)
+        c0, c1 = int(f[lo]), int(f[hi])
+        pv, po = v[o[c0]:o[c1]], o[c0:c1 + 1] - o[c0]
+        assert_same_cycles(pv, po, rres, by_length=False)
+
+
+@pytest.mark.parametrize("one_run", [None, True, False])
+@pytest.mark.parametrize("out_dev", [True, False])
+def test_pages_by_roots_partition_the_output(cc, out_dev, one_run):
+    """Pages of consecutive root ranges under a bound: every page fits and
+    equals the oracle's run over its roots, and together they are exactly
+    the oracle's cycle set (no cycle twice) -- from one grouped run or from
+    a run per page."""
     g = gg.permute_random(gg.grid(6, 8), np.random.default_rng(68))
     ores = oracle_run(g)
     nv_all = int((ores.hist * np.arange(g.n + 1)).sum())
@@ -540,12 +597,15 @@ def test_pages_by_roots_partition_the_output(cc, out_dev):
     limit = max(heaviest, nv_all // 7 + 1)
     verts, offs, seen_hi = [], [0], 0
     with cc.prepare(g, output_device=out_dev) as h:
-        for lo, hi, v, o in h.pages_by_roots(max_verts=limit):
+        for lo, hi, v, o in h.pages_by_roots(max_verts=limit, one_run=one_run):
             assert lo == seen_hi and hi > lo
             seen_hi = hi
             v = v.cpu().numpy() if out_dev else np.asarray(v)
             o = o.cpu().numpy() if out_dev else np.asarray(o)
             assert o[-1] <= limit
+            rres = oracle.enumerate_cycles(g.n, g.row_ptr, g.col_idx, want_cycles=True,
+                                           root_lo=lo, root_hi=hi)
+            assert_same_cycles(v[:o[-1]], o, rres, by_length=one_run is False)
             verts.append(v[:o[-1]])
             offs.extend((o[1:] + offs[-1]).tolist())
         assert seen_hi == h.root_total()
