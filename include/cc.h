@@ -45,7 +45,9 @@
 extern "C" {
 #endif
 
-#define CC_MAX_VERTICES 256        /* one graph (cc_prepare)                         */
+#define CC_MAX_VERTICES 1024       /* one graph (cc_prepare); beyond 256 vertices the
+                                      adjacency rows are read from device memory and
+                                      every breadth-first level runs on the full grid */
 #define CC_MAX_BATCH_VERTICES 256  /* each graph of a batch or of a serving request */
 #define CC_ABI_VERSION 2
 

@@ -35,7 +35,7 @@ CC_FORCE_DFS = 1 << 2
 CC_PROFILE = 1 << 3
 CC_ONE_LEVEL_STEPS = 1 << 5
 CC_SORTED = 1 << 6
-CC_MAX_VERTICES = 256
+CC_MAX_VERTICES = 1024
 CC_MAX_BATCH_VERTICES = 256
 CC_BATCH_PERSISTENT = 0
 CC_BATCH_PER_GRAPH = 1

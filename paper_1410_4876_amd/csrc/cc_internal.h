@@ -5,15 +5,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define CC_MAXN 256
+#define CC_MAXN 1024
 #define CC_HSLOTS (CC_MAXN + 2)   // per-length arrays: index 0..n+1
 #define CC_ROWS(W) (64 * (W))     // vertices a W-word bitset graph can hold
+#define CC_SLOTS(W) (CC_ROWS(W) + 2)  // per-length arrays of a W-word graph
+// Graphs of more than 256 vertices (8 and 16 words): adjacency rows stay in
+// device memory (their LDS copies would not fit), end vertices take 16 bits
+// (the frontier's end-vertex word is 32 bits wide), and the breadth-first
+// head kernel only runs stage one.
+#define CC_BIG(W) ((W) > 4)
 #define CC_BATCH_MAXN 256         // largest graph of a batch (1, 2 or 4 words)
 #define CC_WAVE 64
 #define CC_BLOCK 256              // threads per block for the expansion kernels
 #define CC_CHUNK 64               // paths per wavefront batch / donated chunk
 #define CC_LEVEL_IPT 4            // paths per lane per chunk in the level kernel
 #define CC_LEVEL_IPT_W4 3         // the same for four-word bitsets (n > 128)
+#define CC_LEVEL_IPT_BIG 1        // and for eight and sixteen words (n > 256)
 #define CC_DEC_WORDS 1280         // per-wavefront LDS words for decoded cycles (enumerate steps)
 #define CC_HEAD_THREADS 1024      // threads of the one-block head kernel
 #define CC_ROOT_CLAIM 1024        // handed-over paths a depth-first wavefront claims at once
@@ -104,11 +111,13 @@ struct CcCtl {
 // Frontier of open paths, structure of arrays, CC_SHARDS shards of cap_s
 // paths.  Path `off` of shard s is element i = s * cap_s + off; word w of its
 // exclusion set X (label space) is X[w * cap + i]; likewise its vertex set S
-// (original-id space, enumerate mode only); vv[i] = v1 | vt << 8 (labels).
+// (original-id space, enumerate mode only); the end vertices (labels) are
+// vv[i] = v1 | vt << 8, or vw[i] = v1 | vt << 16 beyond 256 vertices.
 struct Frontier {
   unsigned long long *X;
   unsigned long long *S;
-  unsigned short *vv;
+  unsigned short *vv;       // n <= 256
+  unsigned int *vw;         // n > 256: v1 | vt << 16
   unsigned long long cap;    // CC_SHARDS * cap_s
   unsigned long long cap_s;
 };

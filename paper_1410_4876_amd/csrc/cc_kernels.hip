@@ -2,8 +2,9 @@
 //
 // Vertices are renumbered by their degree label (Section 2), so "label
 // greater than the label of v2" is an integer comparison and every vertex
-// set is a W-word bitset (W = 1, 2 or 4 for n <= 64, 128, 256).  An open chordless
-// path p = <v1, ..., vt> is carried as (X, S, v1, vt) where
+// set is a W-word bitset (W = 1, 2, 4, 8 or 16 for n <= 64, 128, 256, 512,
+// 1024).  An open chordless path p = <v1, ..., vt> is carried as
+// (X, S, v1, vt) where
 //   X = N(v2) U ... U N(v(t-1)) U {w : w <= v2}   (the exclusion set)
 //   S = {v1, ..., vt}                               (enumerate mode only)
 // For the next vertex, Algorithm 3's tests (v not on p, label above v2, no
@@ -128,6 +129,27 @@ __device__ __forceinline__ Bits<W> low_through(int u) {
     a.w[k] = b >= 63 ? ~0ull : (b < 0 ? 0ull : ((2ull << b) - 1ull));
   }
   return a;
+}
+
+// End vertices of a frontier path: v1 | vt << 8 in 16 bits up to 256
+// vertices, v1 | vt << 16 in 32 bits beyond.
+template <int W>
+__device__ __forceinline__ unsigned vv_load(const Frontier &f, unsigned long long e) {
+  if constexpr (CC_BIG(W)) return f.vw[e];
+  else return (unsigned)f.vv[e];
+}
+template <int W>
+__device__ __forceinline__ void vv_store(const Frontier &f, unsigned long long e, int v1, int vt) {
+  if constexpr (CC_BIG(W)) f.vw[e] = (unsigned)v1 | ((unsigned)vt << 16);
+  else f.vv[e] = (unsigned short)(v1 | (vt << 8));
+}
+template <int W>
+__device__ __forceinline__ int vv_v1(unsigned x) {
+  return CC_BIG(W) ? (int)(x & 0xffffu) : (int)(x & 0xffu);
+}
+template <int W>
+__device__ __forceinline__ int vv_vt(unsigned x) {
+  return CC_BIG(W) ? (int)(x >> 16) : (int)(x >> 8);
 }
 
 // ------------------------------------------------------- wave primitives
@@ -487,7 +509,39 @@ __global__ __launch_bounds__(128) void k_ingest(const int *__restrict__ graph_vt
     }
     return;
   }
-  if (tid < CC_WAVE) {
+  if constexpr (CC_BIG(W)) {
+    if (tid < CC_WAVE) {
+      // lane holds vertices tid + 64 j, j < W; key = degree << 10 | id
+      // picks the minimum degree, then the smallest id.  The rows stay in
+      // LDS: removing u reads u's row once (the same words for every lane),
+      // and vertex tid + 64 j is bit tid of its word j.
+      int deg[W];
+      bool alive[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int v = tid + CC_WAVE * j;
+        alive[j] = v < n;
+        deg[j] = alive[j] ? bpop(row<W>(sA, v)) : 0;
+      }
+      for (int i = 0; i < n; ++i) {
+        unsigned mine = 0xffffffffu;
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+          if (alive[j]) mine = min(mine, ((unsigned)deg[j] << 10) | (unsigned)(tid + CC_WAVE * j));
+        const unsigned key = wave_min_u32(mine);
+        const int u = (int)(key & 0x3ffu);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const int v = tid + CC_WAVE * j;
+          if (v == u) {
+            alive[j] = false;
+            sLab[u] = i;
+          }
+          if (alive[j] && ((sA[u * W + j] >> tid) & 1ull)) --deg[j];
+        }
+      }
+    }
+  } else if (tid < CC_WAVE) {
     // lane holds vertices tid + 64 j, j < W; key = degree << 8 | id picks
     // the minimum degree, then the smallest id
     int deg[W];
@@ -614,7 +668,7 @@ __device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, 
 #pragma unroll
             for (int k = 0; k < W; ++k) f.S[k * f.cap + slot] = S.w[k];
           }
-          f.vv[slot] = (unsigned short)(x | (y << 8));
+          vv_store<W>(f, slot, x, y);
         }
       }
     }
@@ -727,8 +781,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_triplets_batch(BatchDev bt) {
 // Shared memory of one block running steps.
 template <int W, bool ENUM>
 struct LevelLds {
-  unsigned long long N[CC_ROWS(W) * W];              // label-space adjacency
-  unsigned long long No[ENUM ? CC_ROWS(W) * W : 1];  // original-id adjacency
+  // label-space and original-id adjacency (beyond 256 vertices the rows are
+  // read from device memory instead)
+  unsigned long long N[CC_BIG(W) ? 1 : CC_ROWS(W) * W];
+  unsigned long long No[ENUM && !CC_BIG(W) ? CC_ROWS(W) * W : 1];
   int Perm[ENUM ? CC_ROWS(W) : 1];
   unsigned long long Pre[CC_SHARDS + 1];
   unsigned long long PreH0[ENUM ? CC_SHARDS + 1 : 1];
@@ -751,9 +807,11 @@ struct LevelLds {
 
 template <int W, bool ENUM>
 __device__ void load_graph_lds(const GraphDev &g, LevelLds<W, ENUM> &L) {
-  for (int i = threadIdx.x; i < g.n * W; i += CC_BLOCK) L.N[i] = g.adj[i];
+  if (!CC_BIG(W))
+    for (int i = threadIdx.x; i < g.n * W; i += CC_BLOCK) L.N[i] = g.adj[i];
   if (ENUM) {
-    for (int i = threadIdx.x; i < g.n * W; i += CC_BLOCK) L.No[i] = g.adj_orig[i];
+    if (!CC_BIG(W))
+      for (int i = threadIdx.x; i < g.n * W; i += CC_BLOCK) L.No[i] = g.adj_orig[i];
     for (int i = threadIdx.x; i < g.n; i += CC_BLOCK) L.Perm[i] = g.perm[i];
   }
 }
@@ -764,6 +822,7 @@ __device__ __forceinline__ Frontier pick(bool c, const Frontier &a, const Fronti
   f.X = c ? a.X : b.X;
   f.S = c ? a.S : b.S;
   f.vv = c ? a.vv : b.vv;
+  f.vw = c ? a.vw : b.vw;
   f.cap = c ? a.cap : b.cap;
   f.cap_s = c ? a.cap_s : b.cap_s;
   return f;
@@ -816,7 +875,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // cycle into the wavefront's LDS buffer, then the run's vertex range, which
 // is contiguous in the output, is written by consecutive lanes.
 template <int W, bool ENUM>
-__device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st,
+__device__ void decode_run(const unsigned long long *No, int *buf, const Stage &st,
                            const unsigned long long *pre, unsigned long long h, int k,
                            long long cb, long long vb, const OutDev &out, unsigned long long gw,
                            unsigned long long nwg) {
@@ -846,7 +905,7 @@ __device__ void decode_run(const LevelLds<W, ENUM> &L, int *buf, const Stage &st
       Bits<W> C;
 #pragma unroll
       for (int w = 0; w < W; ++w) C.w[w] = st.C[w * st.cap + e];
-      write_cycle<W>(L.No, C, k, buf + lane * sk);
+      write_cycle<W>(No, C, k, buf + lane * sk);
       const long long cyc = cb + (long long)gi;
       const long long pos = vb + (long long)gi * k;
       if (cyc >= 0 && pos >= 0 && cyc < out.cyc_cap && pos + k <= out.verts_cap)
@@ -893,10 +952,13 @@ template <int W, bool ENUM>
 __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, const OutDev &out,
                          int step, const StepState &S, StepState *next, int forced_level,
                          int maxc, bool allow_two, LevelLds<W, ENUM> &L, bool lds_ready) {
-  constexpr int IPT = W == 4 ? CC_LEVEL_IPT_W4 : CC_LEVEL_IPT;
+  constexpr int IPT = CC_BIG(W) ? CC_LEVEL_IPT_BIG : W == 4 ? CC_LEVEL_IPT_W4 : CC_LEVEL_IPT;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / CC_WAVE;
+  // the adjacency rows: in LDS, or in device memory beyond 256 vertices
+  const unsigned long long *const Nr = CC_BIG(W) ? g.adj : L.N;
+  const unsigned long long *const Nor = CC_BIG(W) ? g.adj_orig : L.No;
   if (S.done) return CC_LEVEL_EMPTY;
   const int t = S.t;
   const int n = g.n;
@@ -953,8 +1015,8 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
     constexpr int NWB = CC_BLOCK / CC_WAVE;
     const unsigned long long gw = (unsigned long long)vblk * NWB + wave;
     const unsigned long long nwg = (unsigned long long)vgrid * NWB;
-    decode_run<W, ENUM>(L, L.Dec[ENUM ? wave : 0], sd0, L.PreH0, h0, k0, cb0, vb0, out, gw, nwg);
-    decode_run<W, ENUM>(L, L.Dec[ENUM ? wave : 0], sd1, L.PreH1, h1, k1, cb1, vb1, out, gw, nwg);
+    decode_run<W, ENUM>(Nor, L.Dec[ENUM ? wave : 0], sd0, L.PreH0, h0, k0, cb0, vb0, out, gw, nwg);
+    decode_run<W, ENUM>(Nor, L.Dec[ENUM ? wave : 0], sd1, L.PreH1, h1, k1, cb1, vb1, out, gw, nwg);
     if (blockIdx.x == 0 && tid == 0) {
       ctl->cum_c[k0] = (unsigned long long)cb1;
       ctl->cum_v[k0] = (unsigned long long)vb1;
@@ -1076,9 +1138,9 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
 #pragma unroll
           for (int w = 0; w < W; ++w) Sv[j].w[w] = fin.S[w * fin.cap + e];
         }
-        const unsigned vv = fin.vv[e];
-        v1[j] = vv & 0xffu;
-        vt[j] = vv >> 8;
+        const unsigned vv = vv_load<W>(fin, e);
+        v1[j] = vv_v1<W>(vv);
+        vt[j] = vv_vt<W>(vv);
       }
     }
     // counts: a = paths written, b = closures one level down, c = closures
@@ -1087,7 +1149,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
       if (!valid[j]) continue;
-      const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+      const Bits<W> nvt = row<W>(Nr, vt[j]), nv1 = row<W>(Nr, v1[j]);
       const Bits<W> cand = bandnot(nvt, X[j]);
       cb += (unsigned)bpop(band(cand, nv1));
       Bits<W> ext = bandnot(cand, nv1);
@@ -1097,7 +1159,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
         cd += (unsigned)bpop(ext);
         const Bits<W> Xc = bor(X[j], nvt);
         while (bany(ext)) {
-          const Bits<W> cand2 = bandnot(row<W>(L.N, bpop_lowest(ext)), Xc);
+          const Bits<W> cand2 = bandnot(row<W>(Nr, bpop_lowest(ext)), Xc);
           cc += (unsigned)bpop(band(cand2, nv1));
           ca += (unsigned)bpop(bandnot(cand2, nv1));
         }
@@ -1122,11 +1184,11 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
       const unsigned room = room_after(baseA, fout.cap_s);
       unsigned long long *const Xo = fout.X + (unsigned long long)osh * fout.cap_s + b0;
       unsigned long long *const So = fout.S + (unsigned long long)osh * fout.cap_s + b0;
-      unsigned short *const Vo = fout.vv + (unsigned long long)osh * fout.cap_s + b0;
+      const unsigned long long vo0 = (unsigned long long)osh * fout.cap_s + b0;
       unsigned off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+        const Bits<W> nvt = row<W>(Nr, vt[j]), nv1 = row<W>(Nr, v1[j]);
         const Bits<W> Xc = bor(X[j], nvt);
         Bits<W> ext = valid[j] ? bandnot(bandnot(nvt, X[j]), nv1) : bzero<W>();
         // lane iterator: current child c and its remaining extensions cur
@@ -1136,7 +1198,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
           if (two) {
             while (!bany(cur) && bany(ext)) {
               c = bpop_lowest(ext);
-              const Bits<W> nc = row<W>(L.N, c);
+              const Bits<W> nc = row<W>(Nr, c);
               cur = bandnot(bandnot(nc, Xc), nv1);
               Xg = bor(Xc, nc);
             }
@@ -1156,7 +1218,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
 #pragma unroll
                 for (int w = 0; w < W; ++w) So[w * fout.cap + r] = Sn.w[w];
               }
-              Vo[r] = (unsigned short)(v1[j] | (v << 8));
+              vv_store<W>(fout, vo0 + r, v1[j], v);
             }
           }
           off += (unsigned)__popcll(mask);
@@ -1171,7 +1233,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
       unsigned off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+        const Bits<W> nvt = row<W>(Nr, vt[j]), nv1 = row<W>(Nr, v1[j]);
         Bits<W> cl = valid[j] ? band(bandnot(nvt, X[j]), nv1) : bzero<W>();
         while (true) {
           const bool has = bany(cl);
@@ -1197,7 +1259,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
       unsigned off = 0;
 #pragma unroll
       for (int j = 0; j < IPT; ++j) {
-        const Bits<W> nvt = row<W>(L.N, vt[j]), nv1 = row<W>(L.N, v1[j]);
+        const Bits<W> nvt = row<W>(Nr, vt[j]), nv1 = row<W>(Nr, v1[j]);
         const Bits<W> Xc = bor(X[j], nvt);
         Bits<W> ext = valid[j] ? bandnot(bandnot(nvt, X[j]), nv1) : bzero<W>();
         Bits<W> cur = bzero<W>();
@@ -1205,7 +1267,7 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
         while (true) {
           while (!bany(cur) && bany(ext)) {
             c = bpop_lowest(ext);
-            cur = band(bandnot(row<W>(L.N, c), Xc), nv1);
+            cur = band(bandnot(row<W>(Nr, c), Xc), nv1);
           }
           const bool has = bany(cur);
           const unsigned long long mask = wave_ballot(has);
@@ -1327,12 +1389,14 @@ __device__ void finalize_body(CcCtl *ctl, const OutDev &out, int n, bool enumera
 // for host_done.
 template <int W, bool ENUM>
 struct HeadLds {
-  unsigned long long N[CC_ROWS(W) * W];
-  unsigned long long No[ENUM ? CC_ROWS(W) * W : 1];
+  // rows in LDS up to 256 vertices (beyond, the head runs stage one only,
+  // on rows in device memory)
+  unsigned long long N[CC_BIG(W) ? 1 : CC_ROWS(W) * W];
+  unsigned long long No[ENUM && !CC_BIG(W) ? CC_ROWS(W) * W : 1];
   int Perm[CC_ROWS(W)];
   unsigned long long WaveTot[CC_HEAD_THREADS / CC_WAVE];
-  unsigned long long Front[CC_HSLOTS];  // paths expanded per length
-  unsigned long long Hist[CC_HSLOTS];   // cycles found per length (above 3)
+  unsigned long long Front[CC_SLOTS(W)];  // paths expanded per length
+  unsigned long long Hist[CC_SLOTS(W)];   // cycles found per length (above 3)
   unsigned int Trip, Tri;
   long long WCum[2];                    // wavefront phase results, for the block
   int WState[5];
@@ -1404,7 +1468,7 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, in
   while (true) {
     if (cnt == 0) return CC_HEAD_OVER;
     if (cnt > CC_WAVE) return CC_HEAD_MORE;
-    if (t == forced_level || t + 2 >= CC_HSLOTS) return CC_HEAD_STOP;
+    if (t == forced_level || t + 2 >= CC_SLOTS(W)) return CC_HEAD_STOP;
     const HeadBuf<W, ENUM> cur = head_buf<W, ENUM>(dyn, cap, b);
     const HeadBuf<W, ENUM> nxt = head_buf<W, ENUM>(dyn, cap, 1 - b);
     const bool mine = (unsigned)lane < cnt;
@@ -1492,11 +1556,14 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
   // stores before this block's later use of it; later kernels follow in
   // stream order)
   if (zero_cols > 0) zero_ctl_body(ctl, zero_cols, tid, T);
-  for (int i = tid; i < n * W; i += T) L.N[i] = g.adj[i];
-  if (ENUM)
-    for (int i = tid; i < n * W; i += T) L.No[i] = g.adj_orig[i];
+  if (!CC_BIG(W)) {
+    for (int i = tid; i < n * W; i += T) L.N[i] = g.adj[i];
+    if (ENUM)
+      for (int i = tid; i < n * W; i += T) L.No[i] = g.adj_orig[i];
+  }
+  const unsigned long long *const Nh = CC_BIG(W) ? g.adj : L.N;
   for (int i = tid; i < n; i += T) L.Perm[i] = g.perm[i];
-  for (int k = tid; k < CC_HSLOTS; k += T) {
+  for (int k = tid; k < CC_SLOTS(W); k += T) {
     L.Front[k] = 0ull;
     L.Hist[k] = 0ull;
   }
@@ -1514,7 +1581,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
       long long acc = 0;
       for (int v = 0; v < n; ++v) {
         const int l = ctl->orig_label[v];
-        const long long dp = bpop(bandnot(row<W>(L.N, l), low_through<W>(l)));
+        const long long dp = bpop(bandnot(row<W>(Nh, l), low_through<W>(l)));
         ctl->root_base[l] = acc;
         acc += dp * (dp - 1) / 2;
       }
@@ -1526,12 +1593,24 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
   const Stage st0 = B.st[0];
   // a hand-over deals at most cap paths over the shards of frontier 0
   const int cap = (int)min((unsigned long long)cap_lds, CC_SHARDS * f0.cap_s);
-  triplets_body<W, ENUM, T>(g, ctl, f1, st0, L.N, L.Perm, &L.Trip, &L.Tri, rr);
+  triplets_body<W, ENUM, T>(g, ctl, f1, st0, Nh, L.Perm, &L.Trip, &L.Tri, rr);
   const unsigned trip = L.Trip, tri = L.Tri;
   int t = 3;
   unsigned cnt = trip;
   bool over = false;
-  if (trip <= (unsigned)cap && forced_level != 3 && trip / CC_SHARDS < f1.cap_s) {
+  if constexpr (CC_BIG(W)) {
+    // beyond 256 vertices the step launches run every level from step 0
+    (void)cap;
+    (void)tri;
+    (void)t;
+    (void)cnt;
+    (void)over;
+    if (tid == 0) {
+      ctl->launch_step[1] = 1;
+      ctl->levels_run = 0;
+      ctl->head_steps = 0;
+    }
+  } else if (trip <= (unsigned)cap && forced_level != 3 && trip / CC_SHARDS < f1.cap_s) {
     // the triplets into LDS buffer 0 (this block wrote them: its barrier
     // orders those stores before these loads)
     HeadBuf<W, ENUM> cur = head_buf<W, ENUM>(dyn, cap, 0);
@@ -1571,7 +1650,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         over = true;
         break;
       }
-      if (t == forced_level || t + 2 >= CC_HSLOTS) break;
+      if (t == forced_level || t + 2 >= CC_SLOTS(W)) break;
       if (cnt <= CC_WAVE) {
         // small frontier: wavefront 0 alone, then tell the block
         if (tid < CC_WAVE) {
@@ -1684,7 +1763,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
     }
     // Results and hand-over.  Steps 0 .. t-4 ran here, one level each.
     const int steps = t - 3;
-    for (int k = 4 + tid; k <= t && k < CC_HSLOTS; k += T)
+    for (int k = 4 + tid; k <= t && k < CC_SLOTS(W); k += T)
       if (L.Hist[k]) ctl->hist_sh[0][k] = L.Hist[k];
     for (int k = 3 + tid; k < t; k += T) {
       ctl->front[k] = L.Front[k];
@@ -1701,7 +1780,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
 #pragma unroll
           for (int w = 0; w < W; ++w) f0.S[w * f0.cap + e] = cur.S[w * cap + i];
         }
-        f0.vv[e] = cur.vv[i];
+        vv_store<W>(f0, e, vv_v1<W>(cur.vv[i]), vv_vt<W>(cur.vv[i]));
       }
       if (tid < CC_SHARDS)
         ctl->count_sh[tid][t] = cnt > (unsigned)tid ? (cnt - tid + CC_SHARDS - 1) / CC_SHARDS : 0u;
@@ -1855,7 +1934,10 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
 template <int W, bool ENUM, bool BATCH>
 struct DfsWaveLds {
   static constexpr int kEntry = 16 * W + (ENUM ? 8 * W : 0) + 8;
-  static constexpr unsigned kC = kEntry <= 24 ? 256u : 128u;
+  static constexpr unsigned kC = kEntry <= 24 ? 256u : kEntry <= 256 ? 128u : 64u;
+  // frames a step pops: a step pushes at most two per frame, which the ring
+  // always takes once its oldest entries have moved out
+  static constexpr unsigned kPop = kC >= 128u ? (unsigned)CC_CHUNK : kC / 2u;
   unsigned long long X[W * kC];
   unsigned long long E[W * kC];
   unsigned long long S[ENUM ? W * kC : 1];
@@ -1884,13 +1966,15 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   using WL = DfsWaveLds<W, ENUM, BATCH>;
   constexpr unsigned C = WL::kC;
   __shared__ WL sW[CC_BLOCK / CC_WAVE];
-  __shared__ unsigned long long sN[BATCH ? 1 : CC_ROWS(W) * W];
-  __shared__ unsigned long long sNo[ENUM ? CC_ROWS(W) * W : 1];
+  constexpr unsigned POP = WL::kPop;
+  // rows in LDS up to 256 vertices, in device memory beyond
+  __shared__ unsigned long long sN[BATCH || CC_BIG(W) ? 1 : CC_ROWS(W) * W];
+  __shared__ unsigned long long sNo[ENUM && !CC_BIG(W) ? CC_ROWS(W) * W : 1];
   __shared__ int sPerm[BATCH ? 1 : CC_ROWS(W)];
-  __shared__ unsigned long long sHist[BATCH ? 1 : CC_HSLOTS];
-  __shared__ unsigned long long sFront[BATCH ? 1 : CC_HSLOTS];
-  __shared__ long long sCb[ENUM ? CC_HSLOTS : 1];
-  __shared__ long long sVb[ENUM ? CC_HSLOTS : 1];
+  __shared__ unsigned long long sHist[BATCH ? 1 : CC_SLOTS(W)];
+  __shared__ unsigned long long sFront[BATCH ? 1 : CC_SLOTS(W)];
+  __shared__ long long sCb[ENUM ? CC_SLOTS(W) : 1];
+  __shared__ long long sVb[ENUM ? CC_SLOTS(W) : 1];
   __shared__ unsigned long long sPre[CC_SHARDS + 1];
   if (!BATCH && ld_relaxed(&ctl->mode) == 0) return;
   const int L = BATCH ? 3 : ctl->switch_level;
@@ -1908,15 +1992,19 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     shard_prefix(c <= roots.cap_s ? c : roots.cap_s, sPre);
   }
   if (!BATCH) {
-    for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+    if (!CC_BIG(W))
+      for (int i = tid; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
     for (int i = tid; i < n; i += CC_BLOCK) sPerm[i] = g.perm[i];
-    for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) sHist[i] = 0ull;
+    for (int i = tid; i < CC_SLOTS(W); i += CC_BLOCK) sHist[i] = 0ull;
   }
   if (!BATCH)
-    for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) sFront[i] = 0ull;
+    for (int i = tid; i < CC_SLOTS(W); i += CC_BLOCK) sFront[i] = 0ull;
+  const unsigned long long *const Nr = CC_BIG(W) ? g.adj : sN;
+  const unsigned long long *const Nor = CC_BIG(W) ? g.adj_orig : sNo;
   if (ENUM) {
-    for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
-    for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
+    if (!CC_BIG(W))
+      for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
+    for (int i = tid; i < CC_SLOTS(W); i += CC_BLOCK) {
       sCb[i] = (long long)ctl->len_cbase[i];
       sVb[i] = (long long)ctl->len_vbase[i];
     }
@@ -2068,8 +2156,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
     } else {
       const int s = shard_of(sPre, i);
       const unsigned long long e = (unsigned long long)s * roots.cap_s + (i - sPre[s]);
-      const unsigned vv = roots.vv[e];
-      const int vt = (int)(vv >> 8);
+      const unsigned vv = vv_load<W>(roots, e);
+      const int vt = vv_vt<W>(vv);
 #pragma unroll
       for (int w = 0; w < W; ++w) f.X.w[w] = roots.X[w * roots.cap + e];
       f.E = bsingle<W>(vt);
@@ -2079,7 +2167,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         for (int w = 0; w < W; ++w) s0.w[w] = roots.S[w * roots.cap + e];
         f.S = bandnot(s0, bsingle<W>(sPerm[vt < n ? vt : 0]));
       }
-      f.m = (vv & 0xffu) | root_meta;
+      f.m = (unsigned)vv_v1<W>(vv) | root_meta;
       f.gid = 0;
     }
     return true;
@@ -2284,7 +2372,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       // paths of the private range of handed-over paths.  (Not in batches:
       // their rings are nearly always full, and a top-up would mix graphs
       // in one step.)
-      if (!BATCH && lt - lb < (unsigned)CC_CHUNK) {
+      if (!BATCH && lt - lb < POP) {
         if (top != bot) {
           ++fills;
           const unsigned m = min(top - bot, C / 2u - (lt - lb));
@@ -2303,7 +2391,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
           wave_lds_sync();
         } else if (r_lo < r_hi) {
           const unsigned long long kr =
-              min(r_hi - r_lo, (unsigned long long)(CC_CHUNK - (lt - lb)));
+              min(r_hi - r_lo, (unsigned long long)(POP - (lt - lb)));
           Frame<W> f;
           zero_frame(f);
           bool ok = false;
@@ -2319,7 +2407,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       // Pop up to 64 frames from the top.  In the worst case every entry
       // left in the ring and both new frames of every popped one end up in
       // device memory: keep that within its capacity.
-      unsigned kk = min(lt - lb, (unsigned)CC_CHUNK);
+      unsigned kk = min(lt - lb, POP);
       while (kk > 1 && (top - bot) + (lt - lb) + kk > cap) kk >>= 1;
       const unsigned start = lt - kk;
       const bool in_step = (unsigned)lane < kk;
@@ -2384,13 +2472,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
       const bool has_e = bany(f.E);
       int v = bpop_lowest(f.E);
       {
-        const int pv1 = f.m & 0xffu, pt = (f.m >> 16) & 0x1ffu;
+        const int pv1 = f.m & 0xffffu, pt = (f.m >> 16) & 0x7ffu;
         const bool bad = valid & (!has_e | (pv1 >= n_path) | ((unsigned)v >= (unsigned)n_path) |
                                   (pt < 3) | (pt > n_path));
         if (wave_ballot(bad)) {
           if (bad)
             dfs_corrupt(ctl, CC_DIAG_PATH,
-                        has_e ? (f.m & 0xffff00ffu) | ((unsigned)(v & 0xff) << 8) : f.m);
+                        has_e && !CC_BIG(W) ? (f.m & 0xffff00ffu) | ((unsigned)(v & 0xff) << 8) : f.m);
           valid = valid & !bad;
         }
       }
@@ -2399,8 +2487,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         f.E = bzero<W>();
         v = 0;
       }
-      const int v1 = f.m & 0xffu;
-      const int t = (f.m >> 16) & 0x1ffu;
+      const int v1 = f.m & 0xffffu;
+      const int t = (f.m >> 16) & 0x7ffu;
       const bool root = (f.m >> 31) != 0;
       const bool count_path = valid && !(root && (skipbits & CC_SKIP_FRONT));
       const bool count_close = valid && !(root && (skipbits & CC_SKIP_CLOSE));
@@ -2413,8 +2501,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
           nv1.w[w] = bt.adj[(size_t)(vo + v1) * W + w];
         }
       } else {
-        nvt = row<W>(BATCH ? Q.rows : sN, v);
-        nv1 = row<W>(BATCH ? Q.rows : sN, v1);
+        nvt = row<W>(BATCH ? Q.rows : Nr, v);
+        nv1 = row<W>(BATCH ? Q.rows : Nr, v1);
       }
       const Bits<W> cand = bandnot(nvt, f.X);
       Bits<W> clos = band(cand, nv1);
@@ -2466,7 +2554,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
                 long long cyc = sCb[k] + (long long)(slot0 + j);
                 long long pos = sVb[k] + (long long)(slot0 + j) * k;
                 if (out_slot(out, k, cyc, pos)) {
-                  write_cycle<W>(sNo, bor(Sp, bsingle<W>(sPerm[w])), k, out.verts + pos);
+                  write_cycle<W>(Nor, bor(Sp, bsingle<W>(sPerm[w])), k, out.verts + pos);
                   out.offs[cyc] = pos;
                 }
               }
@@ -2486,8 +2574,8 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
         }
       }
       // ---- push: what is left of E, then the new frame of the extensions
-      // on top of it (at most 128 entries, so the ring always takes them
-      // once its oldest entries have moved out)
+      // on top of it (at most 2 POP <= C entries, so the ring always takes
+      // them once its oldest entries have moved out)
       const bool push_rem = valid && bany(f.E);
       const bool push_ext = valid && bany(ext);
       const unsigned long long m_rem = wave_ballot(push_rem);
@@ -2643,7 +2731,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   __syncthreads();
   unsigned long long *hdst = hist_out ? hist_out + (size_t)(blockIdx.x % CC_SHARDS) * hist_stride
                                       : nullptr;
-  for (int i = tid; i < CC_HSLOTS; i += CC_BLOCK) {
+  for (int i = tid; i < CC_SLOTS(W); i += CC_BLOCK) {
     if (!BATCH && hdst && sHist[i]) atomicAdd(&hdst[i], sHist[i]);
     if (!BATCH && count_front && sFront[i]) atomicAdd(&ctl->front[i], sFront[i]);
   }
@@ -2684,10 +2772,11 @@ __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
 // ------------------------------------------------------------ sorted output
 // Sorts the enumerated cycles of each length into ascending lexicographic
 // order of their canonical vertex lists (the cycles of one length are
-// fixed-size records of k original ids, all below 256, at a fixed stride, so
-// the offsets do not change).  One block per length, all lengths in one
-// launch: a stable LSD radix sort of the record indices with one byte digit
-// per position, last position first, then one gather of the records.
+// fixed-size records of k original ids at a fixed stride, so the offsets do
+// not change).  One block per length, all lengths in one launch: a stable
+// LSD radix sort of the record indices with one byte digit per position (two,
+// low byte first, when ids reach 256), last position first, then one gather
+// of the records.
 //   verts   the output (window relative); tmp has room for its vertex ids;
 //   ia, ib  index scratch of at least the window's cycle count each.
 // The lengths' places in the output come from the final histogram.  If the
@@ -2727,12 +2816,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_cycles(const CcCtl *ctl, 
   unsigned *ia = ia0 + cb, *ib = ib0 + cb;
   for (unsigned long long i = tid; i < cnt; i += kSortThreads) ia[i] = (unsigned)i;
   __syncthreads();
-  for (int pos = k - 1; pos >= 0; --pos) {
+  const int nd = n > 256 ? 2 : 1;  // byte digits per position
+  for (int p = k * nd - 1; p >= 0; --p) {
+    const int pos = p / nd, sh = (nd - 1 - p % nd) * 8;
     // digit counts of the whole length, then where each digit starts
     for (int d = tid; d < 256; d += kSortThreads) base[d] = 0u;
     __syncthreads();
     for (unsigned long long i = tid; i < cnt; i += kSortThreads)
-      atomicAdd(&base[src[(unsigned long long)ia[i] * k + pos] & 0xff], 1u);
+      atomicAdd(&base[(src[(unsigned long long)ia[i] * k + pos] >> sh) & 0xff], 1u);
     __syncthreads();
     if (tid < CC_WAVE) {
       // exclusive scan of 256 counts: four per lane, then across lanes
@@ -2762,7 +2853,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_cycles(const CcCtl *ctl, 
     for (unsigned long long c0 = 0; c0 < cnt; c0 += kSortThreads) {
       const unsigned long long i = c0 + tid;
       const bool has = i < cnt;
-      const unsigned d = has ? (unsigned)(src[(unsigned long long)ia[i] * k + pos] & 0xff) : 256u;
+      const unsigned d =
+          has ? (unsigned)((src[(unsigned long long)ia[i] * k + pos] >> sh) & 0xff) : 256u;
       unsigned long long same = ~0ull;
 #pragma unroll
       for (int b = 0; b < 9; ++b) {
@@ -2811,7 +2903,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_cycles(const CcCtl *ctl, 
 // vertex ids.  A range of roots is then one contiguous page.
 
 // root_base[l]: the number of the first root whose u has label l (roots by
-// u's original id, then x's, then y's).  One thread: n <= 256 steps.
+// u's original id, then x's, then y's).  One thread: n <= 1024 steps.
 template <int W>
 __global__ void k_root_base(GraphDev g, const int *label, long long *root_base) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -2835,7 +2927,7 @@ __global__ void k_root_base(GraphDev g, const int *label, long long *root_base) 
 // copied into its LDS buffer by coalesced loads, then each lane walks one
 // cycle there, starting at a lane-dependent position so that the lanes'
 // reads of one round fall in different banks.
-constexpr int kKeyBuf = 1024;  // ids per wavefront buffer (a cycle has at most 256)
+constexpr int kKeyBuf = CC_MAXN;  // ids per wavefront buffer (a cycle has at most n)
 template <int W>
 __global__ __launch_bounds__(CC_BLOCK) void k_cycle_root_keys(GraphDev g, const int *label,
                                                               const long long *root_base,
@@ -2844,12 +2936,15 @@ __global__ __launch_bounds__(CC_BLOCK) void k_cycle_root_keys(GraphDev g, const 
                                                               long long nc, long long R,
                                                               unsigned *key, unsigned *idx) {
   constexpr int NW = CC_BLOCK / CC_WAVE;
-  __shared__ unsigned long long sN[CC_ROWS(W) * W];
+  // rows in LDS up to 256 vertices, in device memory beyond
+  __shared__ unsigned long long sN[CC_BIG(W) ? 1 : CC_ROWS(W) * W];
   __shared__ int sLab[CC_ROWS(W)], sPerm[CC_ROWS(W)];
   __shared__ long long sBase[CC_ROWS(W)];
   __shared__ int sBuf[NW][kKeyBuf];
   const int n = g.n;
-  for (int i = threadIdx.x; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+  if (!CC_BIG(W))
+    for (int i = threadIdx.x; i < n * W; i += CC_BLOCK) sN[i] = g.adj[i];
+  const unsigned long long *const Nk = CC_BIG(W) ? g.adj : sN;
   for (int i = threadIdx.x; i < n; i += CC_BLOCK) {
     sLab[i] = label[i];
     sPerm[i] = g.perm[i];
@@ -2870,7 +2965,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_cycle_root_keys(GraphDev g, const 
       const long long b = in ? offs[j] : 0, e = in ? offs[j + 1] : 0;
       const long long base = (long long)uni_u64((unsigned long long)offs[j0]);
       // the run: the cycles from j0 whose ids fit the buffer (at least one,
-      // a cycle having at most 256 ids)
+      // a cycle having at most n ids)
       const int nb = max(1, (int)__popcll(wave_ballot(in && e - base <= kKeyBuf)));
       const long long end = (long long)lane_u64((unsigned long long)e, nb - 1);
       {
@@ -2911,7 +3006,7 @@ __global__ __launch_bounds__(CC_BLOCK) void k_cycle_root_keys(GraphDev g, const 
           const int lc = (vc >= 0 && vc < n) ? sLab[vc] : n;
           if (la < n && lc < n && la != lc) {
             const int lx = min(la, lc), ly = max(la, lc);
-            const Bits<W> up = bandnot(row<W>(sN, lu), low_through<W>(lu));
+            const Bits<W> up = bandnot(row<W>(Nk, lu), low_through<W>(lu));
             long long ix = sBase[lu];
             Bits<W> it = up;
             while (bany(it)) {
@@ -3153,12 +3248,14 @@ hipError_t cc_launch_zero(void *p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Each launcher picks the instantiation for W = 1, 2 or 4 words per bitset
-// (n <= 64, 128, 256), for single graphs and batches alike.
+// Each launcher picks the instantiation for W = 1, 2, 4, 8 or 16 words per
+// bitset (n <= 64, 128, 256, 512, 1024); batches take W <= 4.
 #define CC_BY_W(W, F, ...)                                  \
   ((W) == 1 ? F<1>(__VA_ARGS__)                             \
    : (W) == 2 ? F<2>(__VA_ARGS__)                           \
-   : (W) == 4 ? F<4>(__VA_ARGS__) : hipErrorInvalidValue)
+   : (W) == 4 ? F<4>(__VA_ARGS__)                           \
+   : (W) == 8 ? F<8>(__VA_ARGS__)                           \
+   : (W) == 16 ? F<16>(__VA_ARGS__) : hipErrorInvalidValue)
 
 namespace {
 template <int W>
@@ -3173,7 +3270,8 @@ hipError_t launch_ingest(int n_graphs, const int *graph_vtx_off, int n_single, c
 }
 template <int W>
 hipError_t launch_triplets_batch(BatchDev bt, int n_graphs, hipStream_t s) {
-  hipLaunchKernelGGL(k_triplets_batch<W>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
+  if (CC_BIG(W)) return hipErrorInvalidValue;  // batches hold graphs of at most 256 vertices
+  hipLaunchKernelGGL(k_triplets_batch<CC_BIG(W) ? 4 : W>, dim3(n_graphs), dim3(CC_BLOCK), 0, s, bt);
   return hipGetLastError();
 }
 template <int W>
@@ -3225,7 +3323,7 @@ hipError_t launch_dfs(bool en, GraphDev g, CcCtl *ctl, Frontier f0, Frontier f1,
 }
 template <int W>
 hipError_t dfs_occupancy(bool en, bool batch, int *per_cu) {
-  const void *fn = batch ? (const void *)k_dfs<W, false, true>
+  const void *fn = batch ? (const void *)k_dfs<CC_BIG(W) ? 4 : W, false, true>
                          : en ? (const void *)k_dfs<W, true, false>
                               : (const void *)k_dfs<W, false, false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, CC_BLOCK, 0);
@@ -3233,10 +3331,11 @@ hipError_t dfs_occupancy(bool en, bool batch, int *per_cu) {
 template <int W>
 hipError_t launch_dfs_batch(GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,
                             unsigned long long idle_timeout, hipStream_t s) {
+  if (CC_BIG(W)) return hipErrorInvalidValue;  // batches hold graphs of at most 256 vertices
   dim3 gr(blocks), bl(CC_BLOCK);
   const Frontier nf{};
   const OutDev no{};
-  hipLaunchKernelGGL((k_dfs<W, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
+  hipLaunchKernelGGL((k_dfs<CC_BIG(W) ? 4 : W, false, true>), gr, bl, 0, s, g, ctl, nf, nf, wk, no, nullptr, 0, 1, idle_timeout, bt);
   return hipGetLastError();
 }
 }  // namespace
@@ -3259,8 +3358,8 @@ hipError_t cc_launch_triplets_batch(int W, BatchDev bt, int n_graphs, hipStream_
 int cc_step_blocks_per_cu(int W, bool en) {
   // the same for every device of a process here (one architecture); asked
   // once per instantiation
-  static std::atomic<int> cached[6];
-  const int which = (W == 1 ? 0 : W == 2 ? 2 : 4) + (en ? 1 : 0);
+  static std::atomic<int> cached[10];
+  const int which = (W == 1 ? 0 : W == 2 ? 2 : W == 4 ? 4 : W == 8 ? 6 : 8) + (en ? 1 : 0);
   int v = cached[which].load();
   if (v <= 0) {
     int per_cu = 0;
@@ -3291,11 +3390,11 @@ hipError_t cc_launch_head(int W, bool en, GraphDev g, CcCtl *ctl, const LevelBuf
   const int zero_cols = zero_ctl ? std::min(std::max(g.n, 0) + 2, CC_HSLOTS) : 0;
   // The dynamic LDS limit is raised once per device and instantiation (the
   // call costs host time that would otherwise stall the stream).
-  static std::atomic<size_t> raised[64][6];
+  static std::atomic<size_t> raised[64][10];
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  const int which = (W == 1 ? 0 : W == 2 ? 2 : 4) + (en ? 1 : 0);
+  const int which = (W == 1 ? 0 : W == 2 ? 2 : W == 4 ? 4 : W == 8 ? 6 : 8) + (en ? 1 : 0);
   if (dev >= 0 && dev < 64 && raised[dev][which].load() < lds_bytes) {
     e = CC_BY_W(W, head_raise, en, lds_bytes);
     if (e != hipSuccess) return e;
@@ -3311,7 +3410,9 @@ size_t cc_head_static_lds(int W, bool en) {
   switch (W) {
     case 1: return en ? sizeof(HeadLds<1, true>) : sizeof(HeadLds<1, false>);
     case 2: return en ? sizeof(HeadLds<2, true>) : sizeof(HeadLds<2, false>);
-    default: return en ? sizeof(HeadLds<4, true>) : sizeof(HeadLds<4, false>);
+    case 4: return en ? sizeof(HeadLds<4, true>) : sizeof(HeadLds<4, false>);
+    case 8: return en ? sizeof(HeadLds<8, true>) : sizeof(HeadLds<8, false>);
+    default: return en ? sizeof(HeadLds<16, true>) : sizeof(HeadLds<16, false>);
   }
 }
 
@@ -3332,8 +3433,8 @@ hipError_t cc_launch_dfs(int W, bool en, GraphDev g, CcCtl *ctl, Frontier f0, Fr
 
 int cc_dfs_blocks_per_cu(int W, bool en, bool batch) {
   // asked once per instantiation (one architecture per process here)
-  static std::atomic<int> cached[9];
-  const int which = (W == 1 ? 0 : W == 2 ? 3 : 6) + (batch ? 2 : en ? 1 : 0);
+  static std::atomic<int> cached[15];
+  const int which = (W == 1 ? 0 : W == 2 ? 3 : W == 4 ? 6 : W == 8 ? 9 : 12) + (batch ? 2 : en ? 1 : 0);
   int v = cached[which].load();
   if (v <= 0) {
     int per_cu = 0;

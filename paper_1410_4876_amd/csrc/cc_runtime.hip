@@ -258,8 +258,24 @@ unsigned long long *dev_field(CcCtl *ctl, size_t offset) {
 
 int64_t choose3(int64_t n) { return n < 3 ? 0 : n * (n - 1) * (n - 2) / 6; }
 
-// Carves one sharded frontier buffer (SoA: X words, S words, vv) of
-// CC_SHARDS * cap_s paths out of `base`.
+// 64-bit words per vertex bitset of a single graph of n vertices.
+int words_for(int n) { return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 512 ? 8 : 16; }
+
+// Bytes of a frontier path's end-vertex word: two up to 256 vertices, four
+// beyond.
+size_t vv_bytes(int W) { return W > 4 ? 4 : 2; }
+
+// The head kernel's dynamic LDS for its in-LDS frontier: what a block may
+// hold, less the kernel's static part and a margin.  None beyond 256
+// vertices, where the head runs stage one only.
+size_t head_dyn_lds(int W, bool en, size_t lds_block) {
+  if (W > 4) return 0;
+  const size_t stat = cc_head_static_lds(W, en) + 4096;
+  return lds_block > stat ? lds_block - stat : 0;
+}
+
+// Carves one sharded frontier buffer (SoA: X words, S words, end vertices)
+// of CC_SHARDS * cap_s paths out of `base`.
 Frontier carve_frontier(char *base, unsigned long long cap_s, int W, bool en) {
   Frontier f{};
   const unsigned long long cap = cap_s * CC_SHARDS;
@@ -270,7 +286,8 @@ Frontier carve_frontier(char *base, unsigned long long cap_s, int W, bool en) {
     f.S = (unsigned long long *)(base + off);
     off = align_up(off + cap * W * 8, 256);
   }
-  f.vv = (unsigned short *)(base + off);
+  if (W > 4) f.vw = (unsigned int *)(base + off);
+  else f.vv = (unsigned short *)(base + off);
   f.cap = cap;
   f.cap_s = cap_s;
   return f;
@@ -280,7 +297,7 @@ size_t frontier_bytes(unsigned long long cap_s, int W, bool en) {
   const unsigned long long cap = cap_s * CC_SHARDS;
   size_t b = align_up(cap * W * 8, 256);
   if (en) b += align_up(cap * W * 8, 256);
-  b += align_up(cap * 2, 256);
+  b += align_up(cap * vv_bytes(W), 256);
   return b;
 }
 
@@ -369,7 +386,8 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       g->opt.frontier_budget_bytes > 0 ? g->opt.frontier_budget_bytes : kDefaultBudget;
   // bytes per unit of capacity: a path in each frontier buffer, plus a
   // staged cycle in each of the four staging buffers
-  const size_t per_unit = 2 * ((size_t)W * 8 * (en ? 2 : 1) + 2) + (en ? 4 * (size_t)W * 8 : 0);
+  const size_t per_unit =
+      2 * ((size_t)W * 8 * (en ? 2 : 1) + vv_bytes(W)) + (en ? 4 * (size_t)W * 8 : 0);
   unsigned long long cap_s = (unsigned long long)budget / per_unit / CC_SHARDS;
   // stage one writes every initial triplet (at most sum C(deg, 2), counted
   // by the ingest) round-robin over the shards
@@ -487,10 +505,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     // frontier in LDS; each later launch runs one step, so n - 2 of them
     // are enough.
     mark(2);
-    // the head's dynamic LDS: what a block may hold, less the kernel's
-    // static part and a margin
-    const size_t stat = cc_head_static_lds(W, en) + 4096;
-    const size_t head_lds = g->dev.lds_block > stat ? g->dev.lds_block - stat : 0;
+    const size_t head_lds = head_dyn_lds(W, en, g->dev.lds_block);
     chk(cc_launch_head(W, en, gd, ctl, lb, out, forced, head_lds, g->d_done, true, ro.roots, s));
     mark(3);
     ++levels;
@@ -727,8 +742,8 @@ cc_status cc_prepare(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
   if (opt) g->opt = *opt;
   g->stream = (hipStream_t)g->opt.stream;
   g->n = n;
-  g->W = n <= 64 ? 1 : n <= 128 ? 2 : 4;
-  const size_t adj_b = align_up((size_t)CC_MAXN * 4 * 8, 256);  // n rows of W <= 4 words
+  g->W = words_for(n);
+  const size_t adj_b = align_up((size_t)CC_MAXN * CC_MAXN / 8, 256);  // n rows of W words
   const size_t vec_b = align_up((size_t)CC_MAXN * 4, 256);
   const size_t ctl_b = align_up(sizeof(CcCtl), 256);
   // staging for a host CSR (at most CC_MAXN rows and CC_MAXN (CC_MAXN - 1)
@@ -1503,7 +1518,7 @@ cc_status cc_histogram_batch_mode(cc_batch *b, int64_t *hists, const int64_t *hi
   chk(hipEventRecord(b->ev1, s));
   unsigned long long *hh = b->s_hist;  // pinned, G * dstride words
   chk(hipMemcpyAsync(hh, bt.hist, (size_t)G * dstride * 8, hipMemcpyDeviceToHost, s));
-  const size_t tail = offsetof(CcCtl, hist);
+  const size_t tail = offsetof(CcCtl, peak);  // a batch reads only the scalars
   chk(hipMemcpyAsync((char *)b->h_ctl + tail, (char *)ctl + tail, sizeof(CcCtl) - tail,
                      hipMemcpyDeviceToHost, s));
   chk(hipFreeAsync(arena, s));
@@ -1620,7 +1635,7 @@ extern "C" cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr,
   st = scratch_address(dev, &base);
   if (st != CC_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  const int W = n <= 64 ? 1 : n <= 128 ? 2 : 4;
+  const int W = words_for(n);
   // fixed part of the scratch: control block, bitsets, labels, ingest answer
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -1629,8 +1644,8 @@ extern "C" cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr,
     return q;
   };
   CcCtl *ctl = (CcCtl *)take(sizeof(CcCtl));
-  unsigned long long *adj = (unsigned long long *)take((size_t)CC_MAXN * 4 * 8);
-  unsigned long long *adj_orig = (unsigned long long *)take((size_t)CC_MAXN * 4 * 8);
+  unsigned long long *adj = (unsigned long long *)take((size_t)CC_MAXN * CC_MAXN / 8);
+  unsigned long long *adj_orig = (unsigned long long *)take((size_t)CC_MAXN * CC_MAXN / 8);
   int *perm = (int *)take((size_t)CC_MAXN * 4);
   int *label = (int *)take((size_t)CC_MAXN * 4);
   unsigned int *status = (unsigned int *)take(256);
@@ -1660,7 +1675,7 @@ extern "C" cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr,
   const int64_t npairs = (int64_t)answer[1];
   // the frontier buffers: every initial triplet (at most sum C(deg, 2))
   // must fit, dealt round-robin over the shards
-  const size_t per_unit = 2 * ((size_t)W * 8 + 2);
+  const size_t per_unit = 2 * ((size_t)W * 8 + vv_bytes(W));
   const unsigned long long min_cap_s =
       (unsigned long long)std::min<int64_t>(npairs, choose3(n)) / CC_SHARDS + CC_CHUNK;
   const unsigned long long cap_s =
@@ -1683,8 +1698,7 @@ extern "C" cc_status cc_histogram_noalloc(int32_t n, const int32_t *row_ptr,
   const OutDev out{};
   const int maxc = std::max(1, max_deg - 1);
   const int bfs_blocks = di.cus * std::min(cc_step_blocks_per_cu(W, false), kStepBlocksPerCu);
-  const size_t stat = cc_head_static_lds(W, false) + 4096;
-  const size_t head_lds = di.lds_block > stat ? di.lds_block - stat : 0;
+  const size_t head_lds = head_dyn_lds(W, false, di.lds_block);
   // the head zeroes the control block, runs stage one and the leading
   // levels; every later step launch returns at once after the loop is over
   // (the host has no mapped word to stop early, so it queues all n - 2)
@@ -1742,6 +1756,9 @@ struct ServeReq {
   std::vector<int64_t> hist;
 };
 
+// per-length histogram slots of a served graph (at most CC_BATCH_MAXN vertices)
+constexpr int kServeSlots = CC_BATCH_MAXN + 2;
+
 struct ServeSlot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
@@ -1798,7 +1815,7 @@ cc_status slot_alloc(cc_server *sv, ServeSlot &sl) {
   const size_t dev_fixed = a256((G + 1) * 4) + a256((V + 1) * 4) + a256(E * 4) +
                            2 * a256((G + 1) * 8) + 2 * a256(V * 4 * 8) + 2 * a256(V * 4) +
                            a256(G * 4) + a256(R * 4 * 8) + a256(R * 2) + a256(R * 4) +
-                           a256(G * CC_HSLOTS * 8) + a256(sizeof(CcCtl));
+                           a256(G * kServeSlots * 8) + a256(sizeof(CcCtl));
   sl.work_bytes = (size_t)sv->opt.slot_work_bytes;
   if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
@@ -1823,11 +1840,11 @@ cc_status slot_alloc(cc_server *sv, ServeSlot &sl) {
   sl.rX = (unsigned long long *)take(R * 4 * 8);
   sl.rvv = (unsigned short *)take(R * 2);
   sl.rgid = (unsigned int *)take(R * 4);
-  sl.d_hist = (unsigned long long *)take(G * CC_HSLOTS * 8);
+  sl.d_hist = (unsigned long long *)take(G * kServeSlots * 8);
   sl.d_ctl = (CcCtl *)take(sizeof(CcCtl));
   sl.d_work = p;
   const size_t host_b = a256((G + 1) * 4) + a256((V + 1) * 4) + a256(E * 4) + a256((G + 1) * 8) +
-                        a256(G * CC_HSLOTS * 8) + a256(G * 4) + a256(4);
+                        a256(G * kServeSlots * 8) + a256(G * 4) + a256(4);
   if (hipHostMalloc(&sl.host, host_b, hipHostMallocDefault) != hipSuccess)
     return CC_ERR_OUT_OF_MEMORY;
   char *h = (char *)sl.host;
@@ -1840,7 +1857,7 @@ cc_status slot_alloc(cc_server *sv, ServeSlot &sl) {
   sl.h_rp = (int *)htake((V + 1) * 4);
   sl.h_ci = (int *)htake(E * 4);
   sl.h_root_off = (long long *)htake((G + 1) * 8);
-  sl.h_hist = (unsigned long long *)htake(G * CC_HSLOTS * 8);
+  sl.h_hist = (unsigned long long *)htake(G * kServeSlots * 8);
   sl.h_status = (unsigned int *)htake(G * 4);
   sl.h_ctl_status = (unsigned int *)htake(4);
   return CC_OK;
@@ -1894,7 +1911,7 @@ hipError_t slot_launch(cc_server *sv, ServeSlot &sl, const std::vector<ServeReq 
   chk(cc_launch_ingest(W, G, sl.d_vtx_off, 0, sl.d_rp, sl.d_ci, sl.d_adj, sl.d_adj_orig, sl.d_perm,
                        sl.d_label, sl.d_status, sl.d_bound, nullptr, s));
   chk(cc_launch_zero(sl.d_ctl, sizeof(CcCtl), s));
-  chk(cc_launch_zero(sl.d_hist, (size_t)G * CC_HSLOTS * 8, s));
+  chk(cc_launch_zero(sl.d_hist, (size_t)G * kServeSlots * 8, s));
   BatchDev bt{};
   bt.vtx_off = sl.d_vtx_off;
   bt.adj = sl.d_adj;
@@ -1907,7 +1924,7 @@ hipError_t slot_launch(cc_server *sv, ServeSlot &sl, const std::vector<ServeReq 
   bt.r0 = 0;
   bt.r1 = (unsigned long long)roots;
   bt.hist = sl.d_hist;
-  bt.hist_stride = CC_HSLOTS;
+  bt.hist_stride = kServeSlots;
   bt.g0 = 0;
   bt.n_graphs = G;
   chk(cc_launch_triplets_batch(W, bt, G, s));
@@ -1915,7 +1932,7 @@ hipError_t slot_launch(cc_server *sv, ServeSlot &sl, const std::vector<ServeReq 
   chk(cc_launch_dfs_prepare(sl.d_ctl, wk, max_n, false, s));
   chk(cc_launch_dfs_batch(W, gd, sl.d_ctl, wk, bt, nw / 4,
                           (unsigned long long)(kIdleTimeoutSeconds * (double)sv->dev.clock_hz), s));
-  chk(hipMemcpyAsync(sl.h_hist, sl.d_hist, (size_t)G * CC_HSLOTS * 8, hipMemcpyDeviceToHost, s));
+  chk(hipMemcpyAsync(sl.h_hist, sl.d_hist, (size_t)G * kServeSlots * 8, hipMemcpyDeviceToHost, s));
   chk(hipMemcpyAsync(sl.h_status, sl.d_status, (size_t)G * 4, hipMemcpyDeviceToHost, s));
   chk(hipMemcpyAsync(sl.h_ctl_status, &sl.d_ctl->status, 4, hipMemcpyDeviceToHost, s));
   chk(hipEventRecord(sl.done, s));
@@ -1937,7 +1954,7 @@ void slot_finish(cc_server *sv, ServeSlot &sl, hipError_t ev) {
     } else {
       r->status = CC_OK;
       r->hist.assign((size_t)r->n + 1, 0);
-      for (int k = 0; k <= r->n; ++k) r->hist[k] = (int64_t)sl.h_hist[g * CC_HSLOTS + k];
+      for (int k = 0; k <= r->n; ++k) r->hist[k] = (int64_t)sl.h_hist[g * kServeSlots + k];
     }
     r->t_done = now;
     r->state = 2;

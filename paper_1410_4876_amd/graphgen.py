@@ -178,6 +178,18 @@ def random_tree(n: int, rng: np.random.Generator) -> CSR:
     return csr_from_edges(n, e, f"tree{n}")
 
 
+def tree_plus_edges(n: int, extra: int, rng: np.random.Generator) -> CSR:
+    """A random recursive tree on n vertices plus `extra` random non-tree
+    edges: sparse, with few but long chordless cycles (at most 2^extra
+    cycles in all, as the cycle space has dimension extra)."""
+    e = {(int(rng.integers(0, i)), i) for i in range(1, n)}
+    while len(e) < n - 1 + extra:
+        a, b = (int(x) for x in rng.integers(0, n, 2))
+        if a != b:
+            e.add((min(a, b), max(a, b)))
+    return csr_from_edges(n, sorted(e), f"tree{n}+{extra}")
+
+
 def random_k_tree(n: int, k: int, rng: np.random.Generator) -> CSR:
     """A k-tree: start from K_{k+1}; each new vertex joins a random existing
     k-clique.  k-trees are chordal."""

@@ -75,7 +75,7 @@ def test_argument_errors_before_any_device_call(L):
     rp = (ctypes.c_int32 * 3)(0, 1, 2)
     ci = (ctypes.c_int32 * 2)(1, 0)
     assert L.cc_prepare(-1, rp, ci, None, ctypes.byref(h)) == cc.CC_ERR_INVALID_ARG
-    assert L.cc_prepare(257, rp, ci, None, ctypes.byref(h)) == cc.CC_ERR_TOO_LARGE
+    assert L.cc_prepare(1025, rp, ci, None, ctypes.byref(h)) == cc.CC_ERR_TOO_LARGE
     assert L.cc_prepare(2, rp, ci, None, None) == cc.CC_ERR_INVALID_ARG
     assert L.cc_prepare(2, None, ci, None, ctypes.byref(h)) == cc.CC_ERR_INVALID_ARG
     bad = cc.Options(None, 0, 1 << 7, 0, 0, 0, 0, 0)

@@ -406,7 +406,7 @@ def test_four_word_budget_switch_and_windows(cc):
 
 def test_too_large_graph_rejected(cc):
     with pytest.raises(cc.CCError) as ei:
-        cc.prepare(gg.cycle(257))
+        cc.prepare(gg.cycle(1025))
     assert ei.value.status == cc.CC_ERR_TOO_LARGE
 
 

@@ -53,6 +53,10 @@ CASES = [
                                                  gg.grid(5, 6), gg.cycle(100)),
                                np.random.default_rng(256)),
      lambda: gg.grid(5, 6)),
+    # 1024 vertices (sixteen-word bitsets), then 400 (eight words)
+    (lambda: gg.permute_random(gg.tree_plus_edges(1024, 20, np.random.default_rng(3)),
+                               np.random.default_rng(33)),
+     lambda: gg.tree_plus_edges(400, 18, np.random.default_rng(2))),
 ]
 
 
@@ -79,7 +83,7 @@ def test_noalloc_on_a_side_stream(env):
 
 def test_noalloc_errors(env):
     torch, cc, L = env
-    big = gg.cycle(300)
+    big = gg.cycle(1025)
     st, _ = noalloc_hist(env, gg.csr_from_edges(3, [(0, 1), (1, 2), (2, 0)]), extra=0)
     assert st == 0
     rp = torch.tensor(big.row_ptr, dtype=torch.int32, device="cuda")
