@@ -569,9 +569,12 @@ def paging_section():
 
 
 def large_n_section():
-    """Graphs of more than 128 vertices (four-word bitsets), full enumeration
-    with CSR and results on the device: C_256, and 256 vertices made of two
-    6x8 grids, two 5x6 grids and C_100 with ids permuted."""
+    """Graphs of more than 128 vertices, full enumeration with CSR and
+    results on the device: C_256, and 256 vertices made of two 6x8 grids,
+    two 5x6 grids and C_100 with ids permuted (four-word bitsets); beyond
+    256 vertices (sixteen words, rows in device memory) C_1024, 774 vertices
+    made of four 6x8 and four 5x7 grids, C_300, a 100-spoke wheel, K_{4,5}
+    and the 5-cube, and a random 1024-vertex tree with 20 extra edges."""
     import torch
 
     from paper_1410_4876_amd import cc
@@ -580,8 +583,14 @@ def large_n_section():
     union = gg.permute_random(gg.disjoint_union(gg.grid(6, 8), gg.grid(6, 8), gg.grid(5, 6),
                                                 gg.grid(5, 6), gg.cycle(100)),
                               np.random.default_rng(256))
+    union774 = gg.permute_random(
+        gg.disjoint_union(*([gg.grid(6, 8)] * 4 + [gg.grid(5, 7)] * 4 +
+                            [gg.cycle(300), gg.wheel(100), gg.complete_bipartite(4, 5),
+                             gg.hypercube(5)])), np.random.default_rng(774))
+    tree = gg.permute_random(gg.tree_plus_edges(1024, 20, np.random.default_rng(3)),
+                             np.random.default_rng(33))
     out = []
-    for g in [gg.cycle(256), union]:
+    for g in [gg.cycle(256), union, gg.cycle(1024), union774, tree]:
         rp = torch.tensor(g.row_ptr, dtype=torch.int32, device="cuda")
         ci = torch.tensor(g.col_idx, dtype=torch.int32, device="cuda")
         with cc.Graph(g.n, rp, ci) as h:

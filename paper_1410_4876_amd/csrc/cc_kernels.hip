@@ -928,22 +928,12 @@ __device__ void decode_run(const unsigned long long *No, int *buf, const Stage &
   }
 }
 
-// The state of a step, read with vector loads at agent scope: the previous
-// step's block 0 wrote it, possibly within the same launch, and a plain load
-// of a uniform address would go through the scalar cache, which no fence here
-// invalidates.
-__device__ __forceinline__ StepState load_state(StepState *p) {
-  StepState S;
-  S.t = ld_relaxed(&p->t);
-  S.fbuf = ld_relaxed(&p->fbuf);
-  S.spair = ld_relaxed(&p->spair);
-  S.slen0 = ld_relaxed(&p->slen0);
-  S.slen1 = ld_relaxed(&p->slen1);
-  S.prev_two = ld_relaxed(&p->prev_two);
-  S.done = ld_relaxed(&p->done);
-  S.step = ld_relaxed(&p->step);
-  return S;
-}
+// The state of a step, written by block 0 of the launch before, so that a
+// plain load sees it (a launch's writes are visible to the launches after it
+// on the stream).  The same holds for the counters a step starts from: plain
+// loads are served by each XCD's L2 after one miss, where loads at agent
+// scope would take every block of the grid to memory for the same few lines.
+__device__ __forceinline__ StepState load_state(const StepState *p) { return *p; }
 
 // One step for this block.  Every block of the grid reads the same state
 // and counters and so reaches the same result.  With lds_ready false the
@@ -967,34 +957,45 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
   const int p = S.spair, q = 1 - S.spair;  // stage pairs: decoded here, written here
   const Stage sd0 = pick(p != 0, B.st[2], B.st[0]), sd1 = pick(p != 0, B.st[3], B.st[1]);
   const Stage sw0 = pick(q != 0, B.st[2], B.st[0]), sw1 = pick(q != 0, B.st[3], B.st[1]);
+  // Each wavefront issues all its loads before it uses any of them, so that
+  // their latencies overlap: the shard counters (wave 0: paths with t
+  // vertices, waves 1 and 2: the staged cycles to decode, wave 3: the
+  // previous step's children, paths with t-1 vertices), the cumulative
+  // output offsets, and the graph rows.
+  const int kh = wave == 1 ? S.slen0 : S.slen1;  // waves 1 and 2: staged length
+  unsigned long long c = 0, cum0 = 0, cum1 = 0;
   if (wave == 0) {
-    const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][t]);
+    c = ctl->count_sh[lane][t];
+    if (ENUM && S.slen0) {
+      cum0 = ctl->cum_c[S.slen0 - 1];
+      cum1 = ctl->cum_v[S.slen0 - 1];
+    }
+  } else if (wave == 1 || wave == 2) {
+    if (ENUM && kh) c = ctl->hist_sh[lane][kh];
+  } else if (wave == 3 && S.prev_two) {
+    c = ctl->count_sh[lane][t - 1];
+  }
+  if (!lds_ready) load_graph_lds<W, ENUM>(g, L);
+  if (wave == 0) {
     shard_prefix(c, L.Pre);
     const unsigned long long mo = wave_ballot(c > fin.cap_s);
     if (lane == 0) {
       L.Flags = mo ? 1 : 0;
-      if (ENUM && S.slen0) {
-        L.Cum[0] = ld_relaxed(&ctl->cum_c[S.slen0 - 1]);
-        L.Cum[1] = ld_relaxed(&ctl->cum_v[S.slen0 - 1]);
-      }
+      L.Cum[0] = cum0;
+      L.Cum[1] = cum1;
     }
   } else if (wave == 1 || wave == 2) {
     // each of these waves writes its own flag every step
-    const int k = wave == 1 ? S.slen0 : S.slen1;
     bool ovf = false;
-    if (ENUM && k) {
-      const unsigned long long h = ld_relaxed(&ctl->hist_sh[lane][k]);
-      shard_prefix(h, wave == 1 ? L.PreH0 : L.PreH1);
-      ovf = wave_ballot(h > (wave == 1 ? sd0.cap_s : sd1.cap_s)) != 0ull;
+    if (ENUM && kh) {
+      shard_prefix(c, wave == 1 ? L.PreH0 : L.PreH1);
+      ovf = wave_ballot(c > (wave == 1 ? sd0.cap_s : sd1.cap_s)) != 0ull;
     }
     if (lane == 0) L.FlagsH[wave - 1] = ovf ? 2 : 0;
   } else if (wave == 3 && S.prev_two) {
-    // the previous step counted its children (paths with t-1 vertices)
-    const unsigned long long c = ld_relaxed(&ctl->count_sh[lane][t - 1]);
     const unsigned long long tot = wave_sum_u64(c);
     if (lane == 0) L.PrevFront = tot;
   }
-  if (!lds_ready) load_graph_lds<W, ENUM>(g, L);
   __syncthreads();
   const int flags = L.Flags | L.FlagsH[0] | L.FlagsH[1];
   const unsigned long long cnt = L.Pre[CC_SHARDS];
@@ -1012,8 +1013,11 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
                              h1 = k1 ? L.PreH1[ENUM ? CC_SHARDS : 0] : 0ull;
     const long long cb0 = (long long)L.Cum[0], vb0 = (long long)L.Cum[1];
     const long long cb1 = cb0 + (long long)h0, vb1 = vb0 + (long long)h0 * k0;
+    // The decode counts blocks from the far end of the grid, the expansion
+    // below from the start: when either has little work, the two run on
+    // different blocks at the same time instead of one after the other.
     constexpr int NWB = CC_BLOCK / CC_WAVE;
-    const unsigned long long gw = (unsigned long long)vblk * NWB + wave;
+    const unsigned long long gw = (unsigned long long)(vgrid - 1 - vblk) * NWB + wave;
     const unsigned long long nwg = (unsigned long long)vgrid * NWB;
     decode_run<W, ENUM>(Nor, L.Dec[ENUM ? wave : 0], sd0, L.PreH0, h0, k0, cb0, vb0, out, gw, nwg);
     decode_run<W, ENUM>(Nor, L.Dec[ENUM ? wave : 0], sd1, L.PreH1, h1, k1, cb1, vb1, out, gw, nwg);
@@ -1313,18 +1317,19 @@ __device__ int step_body(const GraphDev &g, CcCtl *ctl, const LevelBufs &B, cons
 // depth-first kernel took over in enumerate mode, from its counting pass.
 // Count mode accumulates everything in the shards.  One block; sTot has
 // `slots` entries, at least n + 2 (all of CC_HSLOTS when the depth-first
-// kernel may have counted).
+// kernel may have counted).  bfs_only: the caller knows the depth-first
+// kernel did not take over.
 __device__ void length_totals(CcCtl *ctl, int n, bool enumerate, unsigned long long *sTot,
-                              int slots = CC_HSLOTS) {
+                              int slots = CC_HSLOTS, bool bfs_only = false) {
   const int tid = threadIdx.x;
   for (int k = tid; k < slots; k += blockDim.x) sTot[k] = 0ull;
   __syncthreads();
-  const bool dfs = ld_relaxed(&ctl->mode) != 0;
+  const bool dfs = !bfs_only && ld_relaxed(&ctl->mode) != 0;
   // a run on n vertices uses the columns 0..n+1 (the only ones zeroed)
   const int kmax = min((enumerate && dfs) ? ctl->bfs_max_len : CC_HSLOTS - 1, n + 1);
   // the shard counters of the used columns, several loads in flight per
   // thread before their sums go into LDS
-  constexpr int PER = 8;
+  constexpr int PER = 16;
   const int cols = max(kmax + 1, 0), total = CC_SHARDS * cols;
   for (int base = tid; base < total; base += blockDim.x * PER) {
     unsigned long long v[PER];
@@ -1355,8 +1360,8 @@ __device__ void length_totals(CcCtl *ctl, int n, bool enumerate, unsigned long l
 // enumerate mode also closes the offsets array with the total vertex count.
 // One block, sTot as for length_totals.
 __device__ void finalize_body(CcCtl *ctl, const OutDev &out, int n, bool enumerate,
-                              unsigned long long *sTot, int slots) {
-  length_totals(ctl, n, enumerate, sTot, slots);
+                              unsigned long long *sTot, int slots, bool bfs_only = false) {
+  length_totals(ctl, n, enumerate, sTot, slots, bfs_only);
   for (int k = threadIdx.x; k < slots; k += blockDim.x) ctl->hist[k] = sTot[k];
   if (enumerate && threadIdx.x == 0) {
     // the closing offset of the output window
@@ -1551,7 +1556,8 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
   extern __shared__ unsigned long long dyn[];
   const int tid = threadIdx.x;
   const int n = g.n;
-  if (host_done && tid == 0) st_system(host_done + 1, 1u);
+  if (host_done && tid == 0)
+    __hip_atomic_store(host_done + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   // the run's control block, as k_zero_ctl (the barrier below orders these
   // stores before this block's later use of it; later kernels follow in
   // stream order)
@@ -1836,13 +1842,18 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
                                                    unsigned int *host_done) {
   __shared__ LevelLds<W, ENUM> L;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-  if (host_done && lead) st_system(host_done + 1, (unsigned)launch + 1u);
-  // this launch's state, written by the launch before it (one load: the
-  // step index travels in the state)
+  // this launch's state, written by the launch before it (the step index
+  // travels in the state), and whether a launch before it handed over
   const StepState S = load_state(&ctl->ss[launch]);
+  const int mode = ctl->mode;
+  // the start mark for the host's pacing publishes nothing else, so it
+  // needs no release (block 0 does not wait for it)
+  if (host_done && lead)
+    __hip_atomic_store(host_done + 1, (unsigned)launch + 1u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
   const int step = S.step;
   StepState *next = &ctl->ss[launch + 1 < CC_HSLOTS ? launch + 1 : launch];
-  if (ld_relaxed(&ctl->mode) != 0 || S.done || step < 0 || step >= g.n - 2) {
+  if (mode != 0 || S.done || step < 0 || step >= g.n - 2) {
     // handed over, or queued after the loop ended: so is the next launch
     if (lead) {
       StepState D{};
@@ -1858,21 +1869,26 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
   // The step that finds the frontier empty ends the run: block 0 (r is the
   // same for all its threads) also writes the final histogram and closing
   // offset, and host_done[3] tells the host to launch no finalize kernel.
+  // (The levels ran to the end, so the depth-first kernel did not take over.)
   const bool fin = r == CC_LEVEL_EMPTY && blockIdx.x == 0 && host_done;
   if (fin) {
     __syncthreads();
-    finalize_body(ctl, out, g.n, ENUM, L.Tot, CC_ROWS(W) + 2);
+    finalize_body(ctl, out, g.n, ENUM, L.Tot, CC_ROWS(W) + 2, true);
   }
   if (lead) {
     if (launch + 1 < CC_HSLOTS) ctl->launch_step[launch + 1] = r == CC_LEVEL_NEXT ? step + 2 : 0;
     ctl->levels_run = step + 1;
     if (r != CC_LEVEL_NEXT && host_done) {
       // host_done[2]: the loop handed over to the depth-first kernel;
-      // host_done[3]: this launch finalized; both stored and released
-      // before host_done[0]
-      if (r == CC_LEVEL_SWITCH) st_system(host_done + 2, 1u);
-      if (fin) st_system(host_done + 3, 1u);
-      st_system(host_done, (unsigned)launch + 1u);
+      // host_done[3]: this launch finalized; both ordered before
+      // host_done[0] by one release fence
+      if (r == CC_LEVEL_SWITCH)
+        __hip_atomic_store(host_done + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if (fin)
+        __hip_atomic_store(host_done + 3, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      __hip_atomic_store(host_done, (unsigned)launch + 1u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }
@@ -1930,7 +1946,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_step(GraphDev g, CcCtl *ctl, Level
 // LDS per wavefront: the ring (X and E words, S words when enumerating, and
 // one meta word: v1|t|root in the low half, the graph id of a batch in the
 // high half) and, in batches, one graph's rows.  The ring holds 256 entries
-// when an entry has at most 24 bytes, else 128; a step pushes at most 128.
+// when an entry has at most 24 bytes, 128 up to 256 bytes, else 64 (graphs
+// of more than 512 vertices); a step pops at most half of it (64 at most)
+// and pushes at most twice what it popped.
 template <int W, bool ENUM, bool BATCH>
 struct DfsWaveLds {
   static constexpr int kEntry = 16 * W + (ENUM ? 8 * W : 0) + 8;
