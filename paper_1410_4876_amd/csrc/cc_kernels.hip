@@ -3188,51 +3188,57 @@ __global__ void k_sorted_lengths(const unsigned *idx, const long long *offs, lon
     len[j] = j < nc ? offs[(long long)idx[j] + 1] - offs[idx[j]] : 0;
 }
 
-// Runs of 64 cycles per wavefront: the lanes read the run's source and
-// destination offsets at once, then copy the cycles' ids, U cycles at a
-// time (U loads in flight before their stores).
+// Runs of 64 consecutive cycles of the new order per wavefront.  Their ids
+// form one contiguous destination range, which the lanes copy word by
+// word: lane l takes words l, l + 64, ..., and finds each word's cycle by
+// walking forward through the run's destination offsets (kept in LDS), so
+// every store is coalesced and every lane has work whatever the cycle
+// lengths.  U words per lane are loaded before they are stored.
 __global__ __launch_bounds__(CC_BLOCK) void k_gather_cycles(const unsigned *idx,
                                                             const long long *offs_old,
                                                             const int *verts_old,
                                                             const long long *offs_new,
                                                             int *verts_new, long long nc) {
-  constexpr int U = 16;
-  const int lane = lane_id();
-  const long long nw = (long long)gridDim.x * (CC_BLOCK / CC_WAVE);
-  for (long long j0 = ((long long)blockIdx.x * (CC_BLOCK / CC_WAVE) + threadIdx.x / CC_WAVE) *
-                      CC_WAVE;
-       j0 < nc; j0 += nw * CC_WAVE) {
-    const long long j = j0 + lane;
-    const long long src = j < nc ? offs_old[idx[j]] : 0;
-    const long long dst = j < nc ? offs_new[j] : 0;
-    const int k = j < nc ? (int)(offs_new[j + 1] - dst) : 0;
+  constexpr int U = 8;
+  constexpr int NW = CC_BLOCK / CC_WAVE;
+  __shared__ long long sSrc[NW][CC_WAVE];      // source offset of each cycle of the run
+  __shared__ long long sDst[NW][CC_WAVE + 1];  // destination offsets, from the run's start
+  const int lane = lane_id(), wave = threadIdx.x / CC_WAVE;
+  const long long nw = (long long)gridDim.x * NW;
+  for (long long j0 = ((long long)blockIdx.x * NW + wave) * CC_WAVE; j0 < nc;
+       j0 += nw * CC_WAVE) {
     const int cnt = (int)min((long long)CC_WAVE, nc - j0);
-    for (int c0 = 0; c0 < cnt; c0 += U) {
-      int val[U];
+    const long long j = j0 + lane;
+    const long long d0 = (long long)uni_u64((unsigned long long)offs_new[j0]);
+    if (lane < cnt) {
+      sSrc[wave][lane] = offs_old[idx[j]];
+      sDst[wave][lane] = offs_new[j] - d0;
+    }
+    if (lane == 0) sDst[wave][cnt] = offs_new[j0 + cnt] - d0;
+    wave_lds_sync();
+    const long long total = sDst[wave][cnt];
+    int c = 0;  // the cycle of this lane's current word
+    for (long long q0 = 0; q0 < total; q0 += (long long)U * CC_WAVE) {
+      long long sa[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int c = min(c0 + u, cnt - 1);
-        const long long s = lane_u64((unsigned long long)src, c);
-        const int kc = __builtin_amdgcn_readlane(k, c);
-        val[u] = (c0 + u < cnt && lane < kc) ? verts_old[s + lane] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = min(c0 + u, cnt - 1);
-        const long long d = lane_u64((unsigned long long)dst, c);
-        const int kc = __builtin_amdgcn_readlane(k, c);
-        if (c0 + u < cnt && lane < kc) verts_new[d + lane] = val[u];
-      }
-      // ids past the first 64 of a cycle (cycles of more than 64 vertices)
-      for (int u = 0; u < U && c0 + u < cnt; ++u) {
-        const int kc = __builtin_amdgcn_readlane(k, c0 + u);
-        if (kc > CC_WAVE) {
-          const long long d = lane_u64((unsigned long long)dst, c0 + u);
-          const long long s = lane_u64((unsigned long long)src, c0 + u);
-          for (int q = lane + CC_WAVE; q < kc; q += CC_WAVE) verts_new[d + q] = verts_old[s + q];
+        const long long q = q0 + (long long)u * CC_WAVE + lane;
+        sa[u] = -1;
+        if (q < total) {
+          while (c + 1 < cnt && sDst[wave][c + 1] <= q) ++c;
+          sa[u] = sSrc[wave][c] + (q - sDst[wave][c]);
         }
       }
+      int val[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) val[u] = sa[u] >= 0 ? verts_old[sa[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long q = q0 + (long long)u * CC_WAVE + lane;
+        if (q < total) verts_new[d0 + q] = val[u];
+      }
     }
+    wave_lds_sync();  // the next run rewrites the offsets
   }
 }
 
