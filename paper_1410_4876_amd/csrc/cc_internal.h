@@ -10,9 +10,9 @@
 #define CC_ROWS(W) (64 * (W))     // vertices a W-word bitset graph can hold
 #define CC_SLOTS(W) (CC_ROWS(W) + 2)  // per-length arrays of a W-word graph
 // Graphs of more than 256 vertices (8 and 16 words): adjacency rows stay in
-// device memory (their LDS copies would not fit), end vertices take 16 bits
-// (the frontier's end-vertex word is 32 bits wide), and the breadth-first
-// head kernel only runs stage one.
+// device memory (their LDS copies would not fit) and end vertices take 16
+// bits (the frontiers' end-vertex word is 32 bits wide); with 16 words the
+// breadth-first head kernel runs stage one only.
 #define CC_BIG(W) ((W) > 4)
 #define CC_BATCH_MAXN 256         // largest graph of a batch (1, 2 or 4 words)
 #define CC_WAVE 64

@@ -1394,8 +1394,8 @@ __device__ void finalize_body(CcCtl *ctl, const OutDev &out, int n, bool enumera
 // for host_done.
 template <int W, bool ENUM>
 struct HeadLds {
-  // rows in LDS up to 256 vertices (beyond, the head runs stage one only,
-  // on rows in device memory)
+  // rows in LDS up to 256 vertices (beyond, the head reads them from
+  // device memory)
   unsigned long long N[CC_BIG(W) ? 1 : CC_ROWS(W) * W];
   unsigned long long No[ENUM && !CC_BIG(W) ? CC_ROWS(W) * W : 1];
   int Perm[CC_ROWS(W)];
@@ -1417,17 +1417,29 @@ template <int W, bool ENUM>
 struct HeadBuf {
   unsigned long long *X;
   unsigned long long *S;
-  unsigned short *vv;
+  unsigned short *vv;  // end vertices v1 | vt << 8, up to 256 vertices
+  unsigned int *vw;    // v1 | vt << 16 beyond
 };
 template <int W, bool ENUM>
 __device__ __forceinline__ HeadBuf<W, ENUM> head_buf(unsigned long long *dyn, int cap, int b) {
   const int words = W * cap * (ENUM ? 2 : 1);
-  const int per = words + (cap * 2 + 7) / 8;  // 8-byte words per buffer
+  const int per = words + (cap * (CC_BIG(W) ? 4 : 2) + 7) / 8;  // 8-byte words per buffer
   HeadBuf<W, ENUM> h;
   h.X = dyn + b * per;
   h.S = h.X + W * cap;
   h.vv = (unsigned short *)(h.X + words);
+  h.vw = (unsigned int *)(h.X + words);
   return h;
+}
+template <int W, bool ENUM>
+__device__ __forceinline__ unsigned hb_get(const HeadBuf<W, ENUM> &h, unsigned i) {
+  if constexpr (CC_BIG(W)) return h.vw[i];
+  else return (unsigned)h.vv[i];
+}
+template <int W, bool ENUM>
+__device__ __forceinline__ void hb_put(const HeadBuf<W, ENUM> &h, unsigned i, int v1, int vt) {
+  if constexpr (CC_BIG(W)) h.vw[i] = (unsigned)v1 | ((unsigned)vt << 16);
+  else h.vv[i] = (unsigned short)(v1 | (vt << 8));
 }
 
 // Block-wide exclusive scan of two 32-bit counts packed in one 64-bit value
@@ -1466,7 +1478,8 @@ __device__ __forceinline__ unsigned long long block_scan2(unsigned long long v,
 // level here.  Updates t, cnt, b and the output cursors; returns
 // CC_HEAD_MORE, CC_HEAD_OVER or CC_HEAD_STOP.
 template <int W, bool ENUM>
-__device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, int cap,
+__device__ int head_wave_levels(HeadLds<W, ENUM> &L, const unsigned long long *Nh,
+                                const unsigned long long *Noh, unsigned long long *dyn, int cap,
                                 int forced_level, const OutDev &out, int &t, unsigned &cnt,
                                 int &b, long long &cum_c, long long &cum_v, int &odd) {
   const int lane = lane_id();
@@ -1486,12 +1499,12 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, in
 #pragma unroll
         for (int w = 0; w < W; ++w) Sv.w[w] = cur.S[w * cap + lane];
       }
-      vv = cur.vv[lane];
+      vv = hb_get<W, ENUM>(cur, lane);
     }
-    const int vt = vv >> 8, v1 = vv & 0xffu;
-    const Bits<W> nvt = row<W>(L.N, vt);
+    const int vt = vv_vt<W>(vv), v1 = vv_v1<W>(vv);
+    const Bits<W> nvt = row<W>(Nh, vt);
     const Bits<W> cand = mine ? bandnot(nvt, X) : bzero<W>();
-    const Bits<W> n1 = row<W>(L.N, v1);
+    const Bits<W> n1 = row<W>(Nh, v1);
     Bits<W> ext = bandnot(cand, n1);
     Bits<W> cl = band(cand, n1);
     const unsigned long long v = (unsigned long long)bpop(ext) |
@@ -1517,7 +1530,7 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, in
 #pragma unroll
         for (int w = 0; w < W; ++w) nxt.S[w * cap + oe] = Sn.w[w];
       }
-      nxt.vv[oe] = (unsigned short)(v1 | (u << 8));
+      hb_put<W, ENUM>(nxt, oe, v1, u);
       ++oe;
     }
     if (ENUM) {
@@ -1526,7 +1539,7 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, unsigned long long *dyn, in
         long long idx = cum_c + (long long)oc;
         long long pos = cum_v + (long long)oc * (t + 1);
         if (out_slot(out, t + 1, idx, pos)) {
-          write_cycle<W>(L.No, bor(Sv, bsingle<W>(L.Perm[u])), t + 1, out.verts + pos);
+          write_cycle<W>(Noh, bor(Sv, bsingle<W>(L.Perm[u])), t + 1, out.verts + pos);
           out.offs[idx] = pos;
         }
         ++oc;
@@ -1567,7 +1580,9 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
     if (ENUM)
       for (int i = tid; i < n * W; i += T) L.No[i] = g.adj_orig[i];
   }
+  // the rows: in LDS up to 256 vertices, in device memory beyond
   const unsigned long long *const Nh = CC_BIG(W) ? g.adj : L.N;
+  const unsigned long long *const Noh = CC_BIG(W) ? g.adj_orig : L.No;
   for (int i = tid; i < n; i += T) L.Perm[i] = g.perm[i];
   for (int k = tid; k < CC_SLOTS(W); k += T) {
     L.Front[k] = 0ull;
@@ -1604,12 +1619,11 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
   int t = 3;
   unsigned cnt = trip;
   bool over = false;
-  if constexpr (CC_BIG(W)) {
-    // beyond 256 vertices the step launches run every level from step 0
-    (void)cap;
+  if constexpr (W > 8) {
+    // Sixteen-word paths: a level here (rows from device memory, registers
+    // spilled at 1024 threads) costs more than a step launch, so the step
+    // launches run every level from step 0.
     (void)tri;
-    (void)t;
-    (void)cnt;
     (void)over;
     if (tid == 0) {
       ctl->launch_step[1] = 1;
@@ -1628,7 +1642,8 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
 #pragma unroll
         for (int w = 0; w < W; ++w) cur.S[w * cap + j] = f1.S[w * f1.cap + e];
       }
-      cur.vv[j] = f1.vv[e];
+      const unsigned x = vv_load<W>(f1, e);
+      hb_put<W, ENUM>(cur, j, vv_v1<W>(x), vv_vt<W>(x));
     }
     // the triangles, written to the output at once
     long long cum_c = 0, cum_v = 0;
@@ -1640,7 +1655,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         for (int w = 0; w < W; ++w) C.w[w] = st0.C[w * st0.cap + e];
         long long idx = j, pos = 3ll * j;
         if (out_slot(out, 3, idx, pos)) {
-          write_cycle<W>(L.No, C, 3, out.verts + pos);
+          write_cycle<W>(Noh, C, 3, out.verts + pos);
           out.offs[idx] = pos;
         }
       }
@@ -1660,7 +1675,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
       if (cnt <= CC_WAVE) {
         // small frontier: wavefront 0 alone, then tell the block
         if (tid < CC_WAVE) {
-          const int r = head_wave_levels<W, ENUM>(L, dyn, cap, forced_level, out, t, cnt, b,
+          const int r = head_wave_levels<W, ENUM>(L, Nh, Noh, dyn, cap, forced_level, out, t, cnt, b,
                                                   cum_c, cum_v, odd);
           if (tid == 0) {
             L.WState[0] = r;
@@ -1696,9 +1711,9 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
         Bits<W> X;
 #pragma unroll
         for (int w = 0; w < W; ++w) X.w[w] = cur.X[w * cap + i];
-        const unsigned vv = cur.vv[i];
-        const Bits<W> cand = bandnot(row<W>(L.N, vv >> 8), X);
-        const Bits<W> n1 = row<W>(L.N, vv & 0xffu);
+        const unsigned vv = hb_get<W, ENUM>(cur, i);
+        const Bits<W> cand = bandnot(row<W>(Nh, vv_vt<W>(vv)), X);
+        const Bits<W> n1 = row<W>(Nh, vv_v1<W>(vv));
         mine += (unsigned long long)bpop(bandnot(cand, n1)) |
                 ((unsigned long long)bpop(band(cand, n1)) << 32);
       }
@@ -1722,11 +1737,11 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
 #pragma unroll
           for (int w = 0; w < W; ++w) Sv.w[w] = cur.S[w * cap + i];
         }
-        const unsigned vv = cur.vv[i];
-        const int vt = vv >> 8, v1 = vv & 0xffu;
-        const Bits<W> nvt = row<W>(L.N, vt);
+        const unsigned vv = hb_get<W, ENUM>(cur, i);
+        const int vt = vv_vt<W>(vv), v1 = vv_v1<W>(vv);
+        const Bits<W> nvt = row<W>(Nh, vt);
         const Bits<W> cand = bandnot(nvt, X);
-        const Bits<W> n1 = row<W>(L.N, v1);
+        const Bits<W> n1 = row<W>(Nh, v1);
         Bits<W> ext = bandnot(cand, n1);
         const Bits<W> Xn = bor(X, nvt);
         while (bany(ext)) {
@@ -1738,7 +1753,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
 #pragma unroll
             for (int w = 0; w < W; ++w) nxt.S[w * cap + oe] = Sn.w[w];
           }
-          nxt.vv[oe] = (unsigned short)(v1 | (v << 8));
+          hb_put<W, ENUM>(nxt, oe, v1, v);
           ++oe;
         }
         if (ENUM) {
@@ -1748,7 +1763,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
             long long idx = cum_c + (long long)oc;
             long long pos = cum_v + (long long)oc * (t + 1);
             if (out_slot(out, t + 1, idx, pos)) {
-              write_cycle<W>(L.No, bor(Sv, bsingle<W>(L.Perm[v])), t + 1, out.verts + pos);
+              write_cycle<W>(Noh, bor(Sv, bsingle<W>(L.Perm[v])), t + 1, out.verts + pos);
               out.offs[idx] = pos;
             }
             ++oc;
@@ -1786,7 +1801,8 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
 #pragma unroll
           for (int w = 0; w < W; ++w) f0.S[w * f0.cap + e] = cur.S[w * cap + i];
         }
-        vv_store<W>(f0, e, vv_v1<W>(cur.vv[i]), vv_vt<W>(cur.vv[i]));
+        const unsigned x = hb_get<W, ENUM>(cur, i);
+        vv_store<W>(f0, e, vv_v1<W>(x), vv_vt<W>(x));
       }
       if (tid < CC_SHARDS)
         ctl->count_sh[tid][t] = cnt > (unsigned)tid ? (cnt - tid + CC_SHARDS - 1) / CC_SHARDS : 0u;
@@ -3397,7 +3413,7 @@ int cc_step_blocks_per_cu(int W, bool en) {
 // Paths the head's LDS frontier buffers hold with `lds_bytes` of dynamic
 // shared memory (two buffers).
 int cc_head_capacity(int W, bool en, size_t lds_bytes) {
-  const size_t per_path = (size_t)W * 8 * (en ? 2 : 1) + 2;
+  const size_t per_path = (size_t)W * 8 * (en ? 2 : 1) + (W > 4 ? 4 : 2);
   long long cap = (long long)(lds_bytes / 2 / per_path) - 8;
   return cap > 0 ? (int)std::min<long long>(cap, 1 << 20) : 0;
 }

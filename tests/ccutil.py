@@ -154,7 +154,7 @@ def groups_all_chordless(groups, n, row_ptr, col_idx) -> bool:
     """Every row of every group (k vertex ids) is a chordless cycle in the
     vertex order given: k distinct vertices, consecutive ones adjacent
     (cyclically), and exactly k edges among them (so no chord).  Vectorised
-    over the rows with per-vertex adjacency bitsets; n <= 256."""
+    over the rows with per-vertex adjacency bitsets."""
     words = max(1, (n + 63) // 64)
     adj = np.zeros((max(n, 1), words), dtype=np.uint64)
     for v in range(n):
