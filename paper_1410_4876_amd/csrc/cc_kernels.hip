@@ -347,15 +347,36 @@ __device__ void write_cycle(const unsigned long long *sNo, Bits<W> C, int k, int
   const int start = bpop_lowest(it);
   Bits<W> nb = band(row<W>(sNo, start), C);
   const int first = bany(nb) ? bpop_lowest(nb) : start;  // C is always a cycle here
-  int prev = start, cur = first;
   dst[0] = start;
   dst[1] = first;
-  for (int j = 2; j < k; ++j) {
-    Bits<W> nx = band(row<W>(sNo, cur), bandnot(C, bsingle<W>(prev)));
-    const int nxt = bany(nx) ? bpop_lowest(nx) : start;
-    dst[j] = nxt;
-    prev = cur;
-    cur = nxt;
+  if constexpr (CC_BIG(W)) {
+    // Rows in device memory: walk from both ends at once (positions 2, 3,
+    // ... from the smaller neighbour, k-2, k-3, ... from the other one), so
+    // the chain of dependent row loads is half as long.
+    const int last = bany(nb) ? bpop_lowest(nb) : start;
+    if (k > 2) dst[k - 1] = last;
+    int fp = start, fc = first, bp = start, bc = last;
+    for (int i = 2, j = k - 2; i <= j; ++i, --j) {
+      Bits<W> nf = band(row<W>(sNo, fc), bandnot(C, bsingle<W>(fp)));
+      Bits<W> nbk = band(row<W>(sNo, bc), bandnot(C, bsingle<W>(bp)));
+      const int fn = bany(nf) ? bpop_lowest(nf) : start;
+      const int bn = bany(nbk) ? bpop_lowest(nbk) : start;
+      dst[i] = fn;
+      if (j != i) dst[j] = bn;
+      fp = fc;
+      fc = fn;
+      bp = bc;
+      bc = bn;
+    }
+  } else {
+    int prev = start, cur = first;
+    for (int j = 2; j < k; ++j) {
+      Bits<W> nx = band(row<W>(sNo, cur), bandnot(C, bsingle<W>(prev)));
+      const int nxt = bany(nx) ? bpop_lowest(nx) : start;
+      dst[j] = nxt;
+      prev = cur;
+      cur = nxt;
+    }
   }
 }
 
@@ -616,10 +637,31 @@ __device__ void triplets_body(const GraphDev &g, CcCtl *ctl, const Frontier &f, 
   const int n = g.n;
   const int tid = threadIdx.x;
   const bool ranged = rr.lo > 0 || rr.hi < 0x7fffffffffffffffll;
-  for (int idx = tid; idx < n * n; idx += T) {
-    const int u = idx / n, x = idx - u * n;
-    const Bits<W> nu = row<W>(sN, u);
-    if (x <= u || !btest(nu, x)) continue;
+  // (u, x) pairs: all n^2 of them spread over the block when the rows are
+  // in LDS; beyond 256 vertices (rows in device memory) one thread per u,
+  // walking u's higher-labelled neighbours x
+  int u = 0, x = -1;
+  Bits<W> nu = bzero<W>(), xs = bzero<W>();
+  [[maybe_unused]] int idx = tid;
+  if (CC_BIG(W)) u = tid - T;  // the first call below moves to u = tid
+  while (true) {
+    if constexpr (CC_BIG(W)) {
+      while (!bany(xs)) {
+        u += T;
+        if (u >= n) break;
+        nu = row<W>(sN, u);
+        xs = bandnot(nu, low_through<W>(u));
+      }
+      if (u >= n) break;
+      x = bpop_lowest(xs);
+    } else {
+      if (idx >= n * n) break;
+      u = idx / n;
+      x = idx - u * n;
+      idx += T;
+      nu = row<W>(sN, u);
+      if (x <= u || !btest(nu, x)) continue;
+    }
     const Bits<W> nx = row<W>(sN, x);
     const Bits<W> ys0 = bandnot(nu, low_through<W>(x));
     long long base = 0;
