@@ -77,10 +77,12 @@ def test_big_graph_parity(cc, g):
 
 
 @pytest.mark.parametrize("case,level", [("c1024", 3), ("tree1024", 3), ("tree1024", 9),
-                                        ("union774", 4), ("union774", 40), ("wheel600", 3)])
+                                        ("union774", 4), ("union774", 40), ("wheel600", 3),
+                                        ("c512", 3), ("c512", 100), ("tree400", 4)])
 def test_big_graph_forced_depth_first(cc, case, level):
-    g = {"c1024": lambda: gg.cycle(1024),
+    g = {"c1024": lambda: gg.cycle(1024), "c512": lambda: gg.cycle(512),
          "tree1024": lambda: gg.permute_random(gg.tree_plus_edges(1024, 20, rng(3)), rng(33)),
+         "tree400": lambda: gg.permute_random(gg.tree_plus_edges(400, 18, rng(2)), rng(22)),
          "union774": union774, "wheel600": lambda: gg.wheel(600)}[case]()
     info = check(cc, g, force_dfs_level=level)
     assert info["switch_level"] == level
@@ -97,12 +99,14 @@ def test_big_graph_budget_switch(cc, budget):
         assert info["switch_level"] > 3
 
 
-@pytest.mark.parametrize("output_device", [True, False])
-def test_big_graph_sorted_output(cc, output_device):
-    """CC_SORTED with original ids up to 773: exactly the oracle's sorted
-    canonical list."""
+@pytest.mark.parametrize("case,output_device", [("union774", True), ("union774", False),
+                                                 ("tree400", True)])
+def test_big_graph_sorted_output(cc, case, output_device):
+    """CC_SORTED with original ids up to 773 (sixteen-word bitsets) and 399
+    (eight words): exactly the oracle's sorted canonical list."""
     import torch
-    g = union774()
+    g = union774() if case == "union774" else gg.permute_random(
+        gg.tree_plus_edges(400, 18, rng(2)), rng(22))
     with cc.prepare(g, sorted_output=True, output_device=output_device,
                     force_dfs_level=6) as h:
         v, o = h.enumerate()
