@@ -170,6 +170,13 @@ struct OutDev {
   int kmax = 1 << 30;
   long long cshift = 0;
   long long vshift = 0;
+  // Depth-first enumeration: the cycles the depth-first kernel finds (all
+  // longer than bfs_max_len) are staged here as bitsets of original ids,
+  // word w of the i-th of them (in output order) at dstage[w * dstage_cap +
+  // i], and decoded by k_dfs_decode afterwards; those past dstage_cap, or
+  // all of them when dstage is NULL, are written directly.
+  unsigned long long *dstage = nullptr;
+  long long dstage_cap = 0;
 };
 
 // Depth-first workspace: per-wavefront stacks, mailboxes and inboxes.  An
@@ -280,6 +287,8 @@ hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchD
                                int blocks, unsigned long long idle_timeout, hipStream_t s);
 // Zeroes wk's mailboxes and the claim and busy counters (always), and with
 // enum_bases computes the output base of each cycle length.
+hipError_t cc_launch_dfs_decode(int W, GraphDev g, const CcCtl *ctl, OutDev out, int blocks,
+                                hipStream_t s);
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s);
 hipError_t cc_launch_finalize(CcCtl *ctl, OutDev out, int n, bool enumerate, hipStream_t s);
 // After a complete enumerate run: the cycles of each length in out into

@@ -2087,6 +2087,9 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
   }
   __syncthreads();
   const unsigned long long nroots = BATCH ? bt.r1 - bt.r0 : sPre[CC_SHARDS];
+  // output index of the first cycle this kernel finds (the lengths above
+  // bfs_max_len), for the staging of out.dstage
+  const long long dfs_c0 = ENUM ? sCb[min(ctl->bfs_max_len + 1, CC_SLOTS(W) - 1)] : 0;
 
   const int wid = blockIdx.x * (CC_BLOCK / CC_WAVE) + wib;
   const int nwaves = gridDim.x * (CC_BLOCK / CC_WAVE);
@@ -2629,7 +2632,13 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
                 const int w = bpop_lowest(cl);
                 long long cyc = sCb[k] + (long long)(slot0 + j);
                 long long pos = sVb[k] + (long long)(slot0 + j) * k;
-                if (out_slot(out, k, cyc, pos)) {
+                const long long si = cyc - dfs_c0;
+                if (out.dstage && si >= 0 && si < out.dstage_cap) {
+                  // staged; k_dfs_decode writes it with every lane busy
+                  const Bits<W> Cy = bor(Sp, bsingle<W>(sPerm[w]));
+#pragma unroll
+                  for (int q = 0; q < W; ++q) out.dstage[q * out.dstage_cap + si] = Cy.w[q];
+                } else if (out_slot(out, k, cyc, pos)) {
                   write_cycle<W>(Nor, bor(Sp, bsingle<W>(sPerm[w])), k, out.verts + pos);
                   out.offs[cyc] = pos;
                 }
@@ -2819,6 +2828,47 @@ __global__ __launch_bounds__(CC_BLOCK) void k_dfs(GraphDev g, CcCtl *ctl, Fronti
 // workspace has memory of its own, so nothing else ever lives there); for
 // the writing pass of enumerate mode it also computes where each cycle
 // length starts in the output.
+// The cycles the depth-first kernel staged (out.dstage), decoded the way a
+// step decodes its staged cycles: per length above bfs_max_len, runs of
+// cycles per wavefront, each lane walking one cycle into LDS, then the
+// run's vertex range written by consecutive lanes.  Returns at once when
+// the levels finished without a hand-over.
+template <int W>
+__global__ __launch_bounds__(CC_BLOCK) void k_dfs_decode(GraphDev g, const CcCtl *ctl,
+                                                         OutDev out) {
+  constexpr int NWB = CC_BLOCK / CC_WAVE;
+  __shared__ unsigned long long sNo[CC_BIG(W) ? 1 : CC_ROWS(W) * W];
+  __shared__ int sDec[NWB][CC_DEC_WORDS];
+  __shared__ unsigned long long sPre[CC_SHARDS + 1];
+  if (ctl->mode == 0 || !out.dstage) return;
+  const int n = g.n, tid = threadIdx.x, wave = tid / CC_WAVE;
+  if (!CC_BIG(W))
+    for (int i = tid; i < n * W; i += CC_BLOCK) sNo[i] = g.adj_orig[i];
+  const unsigned long long *const No = CC_BIG(W) ? g.adj_orig : sNo;
+  const int L = ctl->bfs_max_len;
+  const long long c0 = (long long)ctl->len_cbase[L + 1];
+  const unsigned long long gw = (unsigned long long)blockIdx.x * NWB + wave;
+  const unsigned long long nwg = (unsigned long long)gridDim.x * NWB;
+  for (int k = L + 1; k <= n; ++k) {
+    const long long cb = (long long)ctl->len_cbase[k];
+    const long long si0 = cb - c0;
+    // the staged ones (the rest went straight to the output)
+    const long long h = min((long long)ctl->len_cbase[k + 1] - cb,
+                            max(0ll, out.dstage_cap - si0));
+    if (h <= 0) continue;
+    // one shard holding all h cycles
+    __syncthreads();  // the previous length's readers of sPre are done
+    if (tid <= CC_SHARDS) sPre[tid] = tid == 0 ? 0ull : (unsigned long long)h;
+    __syncthreads();
+    Stage st;
+    st.C = out.dstage + si0;
+    st.cap = (unsigned long long)out.dstage_cap;
+    st.cap_s = (unsigned long long)out.dstage_cap;
+    decode_run<W, true>(No, sDec[wave], st, sPre, (unsigned long long)h, k, cb,
+                        (long long)ctl->len_vbase[k], out, gw, nwg);
+  }
+}
+
 __global__ void k_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, int enum_bases) {
   __shared__ unsigned long long sTot[CC_HSLOTS];
   // the four words in use of every mailbox line (request, response, count,
@@ -3532,6 +3582,19 @@ int cc_dfs_blocks_per_cu(int W, bool en, bool batch) {
 hipError_t cc_launch_dfs_batch(int W, GraphDev g, CcCtl *ctl, DfsWork wk, BatchDev bt, int blocks,
                                unsigned long long idle_timeout, hipStream_t s) {
   return CC_BY_W(W, launch_dfs_batch, g, ctl, wk, bt, blocks, idle_timeout, s);
+}
+
+namespace {
+template <int W>
+hipError_t launch_dfs_decode(GraphDev g, const CcCtl *ctl, OutDev out, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_dfs_decode<W>, dim3(blocks), dim3(CC_BLOCK), 0, s, g, ctl, out);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t cc_launch_dfs_decode(int W, GraphDev g, const CcCtl *ctl, OutDev out, int blocks,
+                                hipStream_t s) {
+  return CC_BY_W(W, launch_dfs_decode, g, ctl, out, std::max(1, blocks), s);
 }
 
 hipError_t cc_launch_dfs_prepare(CcCtl *ctl, DfsWork wk, int n, bool enum_bases, hipStream_t s) {

@@ -431,6 +431,10 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
       lb.st[i].cap = cap;
       lb.st[i].cap_s = cap_s;
     }
+    // after a hand-over the four staging buffers are free: the depth-first
+    // kernel stages its cycles there, as one array of cycle bitsets
+    out.dstage = (unsigned long long *)(arena + 2 * buf_bytes);
+    out.dstage_cap = (long long)(4 * stage_bytes / (8 * (size_t)W));
   }
 
   const int maxc = std::max(1, g->max_deg - 1);
@@ -546,6 +550,7 @@ cc_status run_device(cc_graph *g, const RunOut &ro) {
     chk(cc_launch_dfs_prepare(ctl, we, n, true, s));
     chk(cc_launch_dfs(W, true, gd, ctl, f[0], f[1], we, out, nullptr, 0, false,
                       dfs_blocks_e, idle_timeout, s));
+    chk(cc_launch_dfs_decode(W, gd, ctl, out, g->dev.cus * 4, s));
   }
   mark(2 * n + 3);
   // the step that found the frontier empty has already finalized when it
