@@ -11,8 +11,7 @@
 #define CC_SLOTS(W) (CC_ROWS(W) + 2)  // per-length arrays of a W-word graph
 // Graphs of more than 256 vertices (8 and 16 words): adjacency rows stay in
 // device memory (their LDS copies would not fit) and end vertices take 16
-// bits (the frontiers' end-vertex word is 32 bits wide); with 16 words the
-// breadth-first head kernel runs stage one only.
+// bits (the frontiers' end-vertex word is 32 bits wide).
 #define CC_BIG(W) ((W) > 4)
 #define CC_BATCH_MAXN 256         // largest graph of a batch (1, 2 or 4 words)
 #define CC_WAVE 64
@@ -23,6 +22,8 @@
 #define CC_LEVEL_IPT_BIG 1        // and for eight and sixteen words (n > 256)
 #define CC_DEC_WORDS 1280         // per-wavefront LDS words for decoded cycles (enumerate steps)
 #define CC_HEAD_THREADS 1024      // threads of the one-block head kernel
+// (256 for sixteen-word bitsets, so that a path's bitsets fit registers)
+#define CC_HEAD_BLOCK(W) ((W) > 8 ? 256 : CC_HEAD_THREADS)
 #define CC_ROOT_CLAIM 1024        // handed-over paths a depth-first wavefront claims at once
 // Frontier and staged-cycle counters are split into CC_SHARDS shards, each
 // on its own cache lines: a block appends to shard blockIdx % CC_SHARDS, so

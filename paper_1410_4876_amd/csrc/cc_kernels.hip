@@ -1418,7 +1418,7 @@ __device__ void finalize_body(CcCtl *ctl, const OutDev &out, int n, bool enumera
 }
 
 // --------------------------------------------------------- one-block head
-// Stage one and the leading levels on one block of CC_HEAD_THREADS threads,
+// Stage one and the leading levels on one block of CC_HEAD_BLOCK(W) threads,
 // with the frontier in LDS: two buffers of `cap` paths in dynamic shared
 // memory (X words, S words when enumerating, then vv), used in turn.  Each
 // level takes one pass to count every path's extensions and closures, a
@@ -1602,11 +1602,11 @@ __device__ int head_wave_levels(HeadLds<W, ENUM> &L, const unsigned long long *N
 }
 
 template <int W, bool ENUM>
-__global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl, LevelBufs B,
+__global__ __launch_bounds__(CC_HEAD_BLOCK(W)) void k_head(GraphDev g, CcCtl *ctl, LevelBufs B,
                                                           OutDev out, int forced_level,
                                                           int cap_lds, unsigned int *host_done,
                                                           int zero_cols, RootRange rr) {
-  constexpr int T = CC_HEAD_THREADS;
+  constexpr int T = CC_HEAD_BLOCK(W);
   __shared__ HeadLds<W, ENUM> L;
   extern __shared__ unsigned long long dyn[];
   const int tid = threadIdx.x;
@@ -1661,18 +1661,7 @@ __global__ __launch_bounds__(CC_HEAD_THREADS) void k_head(GraphDev g, CcCtl *ctl
   int t = 3;
   unsigned cnt = trip;
   bool over = false;
-  if constexpr (W > 8) {
-    // Sixteen-word paths: a level here (rows from device memory, registers
-    // spilled at 1024 threads) costs more than a step launch, so the step
-    // launches run every level from step 0.
-    (void)tri;
-    (void)over;
-    if (tid == 0) {
-      ctl->launch_step[1] = 1;
-      ctl->levels_run = 0;
-      ctl->head_steps = 0;
-    }
-  } else if (trip <= (unsigned)cap && forced_level != 3 && trip / CC_SHARDS < f1.cap_s) {
+  if (trip <= (unsigned)cap && forced_level != 3 && trip / CC_SHARDS < f1.cap_s) {
     // the triplets into LDS buffer 0 (this block wrote them: its barrier
     // orders those stores before these loads)
     HeadBuf<W, ENUM> cur = head_buf<W, ENUM>(dyn, cap, 0);
@@ -3424,7 +3413,7 @@ template <int W>
 hipError_t launch_head(bool en, GraphDev g, CcCtl *ctl, const LevelBufs &b, OutDev out,
                        int forced_level, int cap, size_t lds_bytes, unsigned int *host_done,
                        int zero_cols, RootRange rr, hipStream_t s) {
-  dim3 gr(1), bl(CC_HEAD_THREADS);
+  dim3 gr(1), bl(CC_HEAD_BLOCK(W));
   if (en) hipLaunchKernelGGL((k_head<W, true>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols, rr);
   else hipLaunchKernelGGL((k_head<W, false>), gr, bl, lds_bytes, s, g, ctl, b, out, forced_level, cap, host_done, zero_cols, rr);
   return hipGetLastError();

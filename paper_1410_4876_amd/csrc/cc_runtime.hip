@@ -266,10 +266,8 @@ int words_for(int n) { return n <= 64 ? 1 : n <= 128 ? 2 : n <= 256 ? 4 : n <= 5
 size_t vv_bytes(int W) { return W > 4 ? 4 : 2; }
 
 // The head kernel's dynamic LDS for its in-LDS frontier: what a block may
-// hold, less the kernel's static part and a margin.  None for sixteen-word
-// bitsets, where the head runs stage one only.
+// hold, less the kernel's static part and a margin.
 size_t head_dyn_lds(int W, bool en, size_t lds_block) {
-  if (W > 8) return 0;
   const size_t stat = cc_head_static_lds(W, en) + 4096;
   return lds_block > stat ? lds_block - stat : 0;
 }
